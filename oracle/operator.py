@@ -1,0 +1,166 @@
+"""The standard-form IBQ operator A~' of the oracle: setup, Algorithm 1, dense assembly.
+
+Paper passages followed:
+  * Sec. 4.1, eq. (cholesky): Z = Z_d x ... x Z_1 = L L^T with L = L_d x ... x L_1, and
+    the standard form A' = L^{-1} A L^{-T}, v' = L^T v.
+  * Sec. 4.2: interpolation of G(xhat, xhat') = Gamma(F(xhat), F(xhat')) sqrt(det DF(xhat)
+    det DF(xhat')) (eq. integrand) at the Greville grid, Bt = Bt_d x ... x Bt_1,
+    G~ = Bt^{-1} G Bt^{-T}, d LU factorizations.
+  * Sec. 4.3, eq. (ApproxGalA_mat): A~ = M^T G~ M with M = M_d x ... x M_1.
+  * Sec. 4.4.1: A~' = L^{-1} M^T Bt^{-1} J Gamma J Bt^{-T} M L^{-T}.
+  * Sec. 4.4.2, Algorithm 1 (mf_eval): the nine stages of the matrix-free product.
+
+Reading of Algorithm 1's index notation (its subscripts are ambiguous): stages 1 and 9
+apply L^{-T} and L^{-1}, stages 3 and 7 apply Bt^{-T} and Bt^{-1}, which is the only
+order consistent with the operator of Sec. 4.4.1 and with "stages six to nine are
+equivalent to stages four to one".
+"""
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import covariance, geometry, kron, splines
+
+
+def _per_dir(v, d, default=None):
+    if v is None:
+        return [default] * d
+    v = list(v)
+    return (v + [v[-1]] * d)[:d]
+
+
+class Problem:
+    """All host data of one problem, built in FP64 from its description dict.
+
+    desc keys: dim, degree[d], nelem[d], optional interp_degree[d], interp_nelem[d]
+    (default: the trial space), map (geometry dict), cov (covariance dict).
+    """
+
+    def __init__(self, desc):
+        d = int(desc["dim"])
+        self.d = d
+        self.desc = desc
+        p = _per_dir(desc["degree"], d)
+        ne = _per_dir(desc["nelem"], d)
+        pt = _per_dir(desc.get("interp_degree"), d) if desc.get("interp_degree") else p
+        net = _per_dir(desc.get("interp_nelem"), d) if desc.get("interp_nelem") else ne
+        self.p, self.ne, self.pt, self.net = p, ne, pt, net
+        self.knots = [splines.open_uniform_knots(p[k], ne[k]) for k in range(d)]
+        self.knots_t = [splines.open_uniform_knots(pt[k], net[k]) for k in range(d)]
+        if "interp_knots" in desc:
+            self.knots_t = [np.asarray(t, dtype=np.float64) for t in desc["interp_knots"]]
+        self.n = [splines.dimension(self.knots[k], p[k]) for k in range(d)]
+        self.nt = [splines.dimension(self.knots_t[k], pt[k]) for k in range(d)]
+        self.N = int(np.prod(self.n))
+        self.Nt = int(np.prod(self.nt))
+        # univariate matrices (Sec. 3.5, 4.1-4.3)
+        self.Z = [splines.mass_matrix(self.knots[k], p[k]) for k in range(d)]
+        self.L = [np.linalg.cholesky(Zk) for Zk in self.Z]
+        self.Bt = [splines.collocation_matrix(self.knots_t[k], pt[k]) for k in range(d)]
+        self.Bt_lu = [sla.lu_factor(B) for B in self.Bt]
+        self.M = [splines.mixed_mass_matrix(self.knots_t[k], pt[k], self.knots[k], p[k])
+                  for k in range(d)]
+        # Greville grid in vec order (first index fastest), mapped points, J
+        g1 = [splines.greville(self.knots_t[k], pt[k]) for k in range(d)]
+        grids = np.meshgrid(*g1, indexing="ij")
+        self.xhat = np.stack([g.reshape(-1, order="F") for g in grids], axis=1)
+        self.X, det = geometry.map_points(desc["map"], self.xhat)
+        if np.any(det <= 0):
+            raise ValueError("det DF <= 0 at a Greville point")
+        self.J = np.sqrt(det)
+        self.cov = desc["cov"]
+
+    # ---- Algorithm 1, one stage at a time -------------------------------------------
+    def _modes(self, v, shape, fn_k):
+        T = kron.to_tensor(v, shape)
+        for k in range(self.d):
+            T = kron.mode_apply(T, k, lambda A, k=k: fn_k(k, A))
+        return kron.to_vec(T, self.d)
+
+    def stage1(self, v):
+        """V = L^{-T} v: back-substitution with the upper triangular L_k^T per direction."""
+        return self._modes(v, self.n, lambda k, A: sla.solve_triangular(
+            self.L[k], A, trans="T", lower=True))
+
+    def stage2(self, V):
+        """X = M V (mode products with M_k)."""
+        return self._modes(V, self.n, lambda k, A: self.M[k] @ A)
+
+    def stage3(self, X):
+        """Y = Bt^{-T} X using the LU factors of Bt_k."""
+        return self._modes(X, self.nt, lambda k, A: sla.lu_solve(self.Bt_lu[k], A, trans=1))
+
+    def stage4(self, Y):
+        """Y' = J (.) Y."""
+        return self.J[:, None] * Y if Y.ndim == 2 else self.J * Y
+
+    def stage5(self, Yp, rows_per_block=512):
+        """Z' = Gamma Y', Gamma evaluated on the fly a block of rows at a time."""
+        Z = np.zeros_like(Yp)
+        for r0 in range(0, self.Nt, rows_per_block):
+            r1 = min(self.Nt, r0 + rows_per_block)
+            G = covariance.gamma(self.cov, self.X[r0:r1], self.X)
+            Z[r0:r1] = G @ Yp
+        return Z
+
+    def stage6(self, Zp):
+        """Z = J (.) Z'."""
+        return self.stage4(Zp)
+
+    def stage7(self, Z):
+        """Y = Bt^{-1} Z using the LU factors of Bt_k."""
+        return self._modes(Z, self.nt, lambda k, A: sla.lu_solve(self.Bt_lu[k], A, trans=0))
+
+    def stage8(self, Y):
+        """V = M^T Y."""
+        return self._modes(Y, self.nt, lambda k, A: self.M[k].T @ A)
+
+    def stage9(self, V):
+        """v' = L^{-1} V: forward substitution with L_k per direction."""
+        return self._modes(V, self.n, lambda k, A: sla.solve_triangular(
+            self.L[k], A, trans="N", lower=True))
+
+    def forward(self, v):
+        """Stages 1-4: v' -> Y' (the input of stage 5)."""
+        return self.stage4(self.stage3(self.stage2(self.stage1(v))))
+
+    def backward(self, Zp):
+        """Stages 6-9: Z' -> A~' v'."""
+        return self.stage9(self.stage8(self.stage7(self.stage6(Zp))))
+
+    def apply(self, v, stage5=None):
+        """Algorithm 1: v' -> A~' v' for a vector (N,) or a block (N, b)."""
+        v = np.asarray(v, dtype=np.float64)
+        s5 = stage5 if stage5 is not None else self.stage5
+        return self.backward(s5(self.forward(v)))
+
+    # ---- dense forms (tiny and medium problems only) ----------------------------------
+    def gamma_matrix(self):
+        return covariance.gamma(self.cov, self.X, self.X)
+
+    def dense_operator(self):
+        """A~' = L^{-1} M^T Bt^{-1} J Gamma J Bt^{-T} M L^{-T} with explicit Kronecker
+        matrices (Sec. 4.4.1); no mode-wise contraction is used here."""
+        Lk = kron.kron_dense(self.L)
+        Mk = kron.kron_dense(self.M)
+        Bk = kron.kron_dense(self.Bt)
+        G = self.J[:, None] * self.gamma_matrix() * self.J[None, :]
+        Gt = np.linalg.solve(Bk, np.linalg.solve(Bk, G).T).T   # Bt^{-1} G Bt^{-T}
+        A = Mk.T @ Gt @ Mk                                      # eq. ApproxGalA_mat
+        Ap = np.linalg.solve(Lk, np.linalg.solve(Lk, A).T).T    # L^{-1} A L^{-T}
+        return 0.5 * (Ap + Ap.T)
+
+    def dense_A_tilde(self):
+        """A~ = M^T G~ M (eq. ApproxGalA_mat), before the standard-form transformation."""
+        Mk = kron.kron_dense(self.M)
+        Bk = kron.kron_dense(self.Bt)
+        G = self.J[:, None] * self.gamma_matrix() * self.J[None, :]
+        Gt = np.linalg.solve(Bk, np.linalg.solve(Bk, G).T).T
+        return Mk.T @ Gt @ Mk
+
+    def mass_dense(self):
+        return kron.kron_dense(self.Z)
+
+    def to_coefficients(self, vp):
+        """v = L^{-T} v' (Sec. 4.1): B-spline coefficients of phi_h = sum v_i B_i / sqrt(det DF)."""
+        return self.stage1(vp)
