@@ -1,0 +1,170 @@
+/* kl.h -- C ABI of the matrix-free isogeometric Galerkin Karhunen-Loeve library for
+ * one AMD MI355X (gfx950).
+ *
+ * Problem (Mika et al., "A matrix-free isogeometric Galerkin method for Karhunen-Loeve
+ * approximation of random fields ...", arXiv 2011.13861):
+ *   Sec. 3.4 eq. (weakform):   Galerkin discretisation of the Fredholm eigenproblem
+ *                              T phi = lambda phi in the trial space of eq. (basis).
+ *   Sec. 4.1 eq. (cholesky):   standard form  A' v' = lambda v',  v' = L^T v.
+ *   Sec. 4.2-4.4.1:            interpolation based quadrature gives
+ *                              A~' = L^{-1} M^T Bt^{-1} J Gamma J Bt^{-T} M L^{-T}.
+ *   Sec. 4.4.2, Algorithm 1:   the matrix-free product v' -> A~' v'.
+ *
+ * Conventions
+ *   - Every function returns kl_status (0 = KL_OK, negative = error).  Nothing aborts,
+ *     throws or exits across the ABI; kl_last_error() returns a thread-local message
+ *     describing the most recent failure on the calling thread.
+ *   - Vectors are in vec order (Sec. 2.2): the multi-index (i_1..i_d) maps to
+ *     i_1 + n_1 (i_2 + n_2 i_3), first index fastest.  Blocks of vectors are
+ *     column-major with a leading dimension >= N.
+ *   - "device" pointers are HIP device allocations owned by the caller; "host" pointers
+ *     are ordinary host memory owned by the caller.  The library owns the kl_problem
+ *     handle and all of its internal device buffers (points, weights, factors and
+ *     workspaces), allocated once by kl_setup and released by kl_destroy.
+ *   - Validation happens before any device work; on error, outputs and the handle are
+ *     left untouched, except where a function documents partial results.
+ *   - A handle is not thread-safe: use one handle per host thread / stream.
+ */
+#ifndef KL_H
+#define KL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kl_problem kl_problem;   /* opaque, library-owned */
+
+typedef enum {
+    KL_OK = 0,
+    KL_EINVAL = -1,      /* invalid argument or description */
+    KL_ENOMEM = -2,      /* device or host allocation failed */
+    KL_EHIP = -3,        /* a HIP runtime call failed */
+    KL_EDOMAIN = -4,     /* det DF <= 0 at a Greville point (Sec. 3.4 assumes det DF > 0) */
+    KL_ESINGULAR = -5,   /* univariate Gramian not SPD, or collocation matrix singular */
+    KL_ENUMERIC = -6,    /* NaN or Inf met in an input block or in the eigensolver */
+    KL_ENOCONV = -7      /* eigensolver hit max_applies; best pairs are still returned */
+} kl_status;
+
+/* Arithmetic of stage 5 (the covariance-times-block kernel).  The Kronecker stages
+ * always run in FP64. */
+typedef enum {
+    KL_F64 = 0,      /* FP64 kernel evaluation, FP64 MFMA contraction */
+    KL_F32 = 1,      /* FP32 kernel evaluation, FP32 MFMA contraction, FP32 accumulation */
+    KL_BF16 = 2,     /* FP32 kernel evaluation rounded to BF16, BF16 MFMA, FP32 accumulation */
+    KL_BF16X3 = 3    /* BF16 hi/lo split of both operands, three BF16 MFMAs, FP32 accumulation */
+} kl_precision;
+
+/* Covariance kernels (Sec. 3.1, eq. (kernel)); rho = ||diag(ell)^{-1}(x - x')||_2.
+ * EXP: sigma2 exp(-rho); SQEXP: sigma2 exp(-rho^2).  EXP_L1, CONST and LIN are test
+ * kernels: sigma2 exp(-sum |dx_k|/ell_k), sigma2, sigma2 (1 + x . x'). */
+typedef enum { KL_COV_EXP = 0, KL_COV_SQEXP = 1, KL_COV_EXP_L1 = 2, KL_COV_CONST = 3,
+               KL_COV_LIN = 4 } kl_cov_kind;
+
+/* Geometry maps F : [0,1]^d -> D (Sec. 2.4).  map_params:
+ *   BOX:            lo[0..d-1] in params[0..2], hi[0..d-1] in params[3..5]
+ *   ANNULUS_NURBS:  (2D) r0 = params[0], r1 = params[1]; exact rational quadratic arc
+ *   ANNULUS_POLAR:  (2D) r0, r1 as above; polar parametrisation of the same domain
+ *   SINE_CUBE:      F(u) = u + eps amp prod_k sin(pi u_k); eps = params[0],
+ *                   amp = params[1..3]                                            */
+typedef enum { KL_MAP_IDENTITY = 0, KL_MAP_BOX = 1, KL_MAP_ANNULUS_NURBS = 2,
+               KL_MAP_ANNULUS_POLAR = 3, KL_MAP_SINE_CUBE = 4 } kl_map_kind;
+
+typedef struct {
+    int32_t dim;                 /* spatial dimension d, 1..3 */
+    int32_t degree[3];           /* trial-space degree p_k >= 1 */
+    int32_t nelem[3];            /* trial-space elements per direction >= 1; open uniform
+                                    knots with C^{p-1} continuity, n_k = nelem_k + p_k */
+    int32_t interp_degree[3];    /* interpolation space (Sec. 4.2); 0 = same as trial */
+    int32_t interp_nelem[3];     /* 0 = same as trial */
+    int32_t map_kind;            /* kl_map_kind */
+    double  map_params[8];
+    int32_t cov_kind;            /* kl_cov_kind */
+    double  sigma2;              /* variance > 0 */
+    double  corr_len[3];         /* correlation length per physical direction > 0 */
+    int32_t max_block;           /* widest block per stage-5 pass; 0 = 32.  Wider
+                                    blocks given to kl_apply are processed in chunks. */
+} kl_desc;
+
+/* Builds the problem: knots, Greville points, Z_k and its Cholesky factor L_k, the
+ * collocation matrices Bt_k and their LU factors, the mixed mass matrices M_k, the
+ * composed factors C_k = Bt_k^{-T} M_k L_k^{-T}, mapped Greville points X = F(xhat)
+ * and J = sqrt(det DF(xhat)) (Sec. 3.5, 4.1-4.3), in FP64 on the host; then uploads
+ * them and allocates all workspaces.  Synchronous.  Errors: KL_EINVAL, KL_EDOMAIN,
+ * KL_ESINGULAR, KL_ENOMEM, KL_EHIP.  *out is written only on success. */
+kl_status kl_setup(const kl_desc *desc, kl_problem **out);
+
+/* Host part of kl_setup only (no device work, usable without a GPU): the handle
+ * supports kl_info, kl_get_points, kl_get_factor and kl_destroy; kl_apply, kl_stage5
+ * and kl_eigs reject it with KL_EINVAL.  Same errors as kl_setup otherwise. */
+kl_status kl_setup_host(const kl_desc *desc, kl_problem **out);
+
+/* Sizes: N = prod n_k trial dofs, Ntilde = prod nt_k interpolation dofs; n and nt
+ * (host arrays of 3) receive the per-direction sizes (1 beyond dim).  Any pointer may
+ * be NULL. */
+kl_status kl_info(const kl_problem *P, int64_t *N, int64_t *Ntilde, int32_t *n, int32_t *nt);
+
+/* y = A~' x for nvec columns (Algorithm 1): forward Kronecker stages 1-4 (composed
+ * into one factor per direction), stage 5 in the given kl_precision, backward stages
+ * 6-9.  x, y: device, FP64, column-major, ld >= N; x and y must not overlap.
+ * Asynchronous on `stream` (a hipStream_t, NULL = default stream); allocates nothing.
+ * Errors: KL_EINVAL (bad sizes/precision/pointers), KL_EHIP (launch failure). */
+kl_status kl_apply(kl_problem *P, int32_t precision, int32_t nvec,
+                   const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
+
+/* Stage 5 alone (Algorithm 1, stage 5): z = Gamma y on the Greville grid, for
+ * nvec columns of y (device, FP64, column-major, ld >= Ntilde).  z receives FP64.
+ * sigma2 is applied; J is not.  Used to test the kernel in isolation. */
+kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec,
+                    const double *y, int64_t ldy, double *z, int64_t ldz, void *stream);
+
+/* Copies of the setup data (host arrays, caller-owned):  X: Ntilde x dim row-major
+ * physical Greville points; J: Ntilde weights sqrt(det DF); C: the nt_k x n_k
+ * row-major composed factor of direction k (0-based).  Any output may be NULL. */
+kl_status kl_get_points(const kl_problem *P, double *X, double *J);
+kl_status kl_get_factor(const kl_problem *P, int32_t k, double *C);
+
+typedef struct {
+    int32_t k;              /* wanted eigenpairs (largest first), >= 1 */
+    int32_t block;          /* block size b of the block eigensolver; 0 = 32 */
+    int32_t max_applies;    /* cap on single-vector operator applications; 0 = default */
+    double  tol;            /* relative residual tolerance; 0 = 1e-6 */
+    double  abs_floor;      /* absolute floor relative to lambda_1; 0 = 1e-12 */
+    int32_t precision;      /* kl_precision of the inner applies */
+    int32_t refine_fp64;    /* 1: finish with FP64 applies so that the criterion below
+                               holds under the FP64 operator (forced for KL_F64) */
+    uint64_t seed;          /* seed of the random start block */
+    int32_t guard;          /* extra Ritz vectors kept beyond k; 0 = default */
+    int32_t max_basis;      /* largest search-space dimension; 0 = default */
+} kl_eigs_opts;
+
+typedef struct {
+    int32_t n_applies[4];   /* single-vector applications per kl_precision */
+    int32_t n_block_applies[4];
+    int32_t n_restarts;
+    int32_t converged;      /* number of leading pairs meeting the criterion */
+    double  t_solve;        /* seconds, wall clock */
+    double  max_rel_residual;   /* max_i ||A~' x_i - theta_i x_i|| / theta_i over i <= k */
+} kl_eigs_report;
+
+/* k leading eigenpairs of A~' (descending), block Krylov eigensolver with FP64
+ * Rayleigh-Ritz and FP64 reorthogonalisation.  Converged when for every i <= k
+ *   ||A~' x_i - theta_i x_i||_2 <= max(tol * theta_i, abs_floor * theta_1),  ||x_i|| = 1.
+ * x0: optional device FP64 start block (N x nvec0, ld N), or NULL for a seeded random
+ * start.  evals: host, k values.  evecs: device FP64, N x k, leading dimension ldv;
+ * unit 2-norm columns v' (so phi_h has unit L2 norm, Sec. 4.1).  rep may be NULL.
+ * Synchronous.  On KL_ENOCONV evals/evecs hold the best Ritz pairs found. */
+kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0, int32_t nvec0,
+                  double *evals, double *evecs, int64_t ldv, kl_eigs_report *rep);
+
+/* Releases the handle and every device buffer it owns.  NULL is accepted. */
+kl_status kl_destroy(kl_problem *P);
+
+/* Thread-local description of the last error ("" if none). */
+const char *kl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KL_H */

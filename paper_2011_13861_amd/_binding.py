@@ -1,0 +1,238 @@
+"""ctypes binding of the C ABI in include/kl.h (argument marshalling only).
+
+Every computation runs inside lib/libklmf.so; this module converts Python/PyTorch
+arguments to plain pointers and sizes.  Loading fails loudly if the library has not
+been built: there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libklmf.so")
+
+KL_OK, KL_EINVAL, KL_ENOMEM, KL_EHIP, KL_EDOMAIN, KL_ESINGULAR, KL_ENUMERIC, KL_ENOCONV = \
+    0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "KL_OK", -1: "KL_EINVAL", -2: "KL_ENOMEM", -3: "KL_EHIP", -4: "KL_EDOMAIN",
+                -5: "KL_ESINGULAR", -6: "KL_ENUMERIC", -7: "KL_ENOCONV"}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
+COV_KINDS = {"exp": 0, "sqexp": 1, "exp_l1": 2, "const": 3, "lin": 4}
+MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "sine_cube": 4}
+
+# exported symbols declared in include/kl.h
+EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
+           "kl_get_factor", "kl_eigs", "kl_destroy", "kl_last_error"]
+
+
+class KLError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class KLDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32 * 3), ("nelem", ctypes.c_int32 * 3),
+                ("interp_degree", ctypes.c_int32 * 3), ("interp_nelem", ctypes.c_int32 * 3),
+                ("map_kind", ctypes.c_int32), ("map_params", ctypes.c_double * 8),
+                ("cov_kind", ctypes.c_int32), ("sigma2", ctypes.c_double),
+                ("corr_len", ctypes.c_double * 3), ("max_block", ctypes.c_int32)]
+
+
+class KLEigsOpts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("block", ctypes.c_int32), ("max_applies", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("abs_floor", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("refine_fp64", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("guard", ctypes.c_int32), ("max_basis", ctypes.c_int32)]
+
+
+class KLEigsReport(ctypes.Structure):
+    _fields_ = [("n_applies", ctypes.c_int32 * 4), ("n_block_applies", ctypes.c_int32 * 4),
+                ("n_restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("t_solve", ctypes.c_double), ("max_rel_residual", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libklmf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.kl_setup.argtypes = [ctypes.POINTER(KLDesc), ctypes.POINTER(P)]
+        L.kl_setup_host.argtypes = [ctypes.POINTER(KLDesc), ctypes.POINTER(P)]
+        L.kl_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.kl_apply.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, P,
+                               ctypes.c_int64, P]
+        L.kl_stage5.argtypes = L.kl_apply.argtypes
+        L.kl_get_points.argtypes = [P, P, P]
+        L.kl_get_factor.argtypes = [P, ctypes.c_int32, P]
+        L.kl_eigs.argtypes = [P, ctypes.POINTER(KLEigsOpts), P, ctypes.c_int32, P, P,
+                              ctypes.c_int64, ctypes.POINTER(KLEigsReport)]
+        L.kl_destroy.argtypes = [P]
+        L.kl_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "kl_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != KL_OK:
+        raise KLError(status, lib().kl_last_error().decode())
+    return status
+
+
+def make_desc(desc, max_block=0):
+    """Marshals a workload description dict into the C kl_desc struct."""
+    d = int(desc["dim"])
+    c = KLDesc()
+    c.dim = d
+    deg = list(desc["degree"])
+    ne = list(desc["nelem"])
+    ideg = list(desc.get("interp_degree") or [0] * d)
+    ine = list(desc.get("interp_nelem") or [0] * d)
+    for k in range(min(d, 3, len(deg), len(ne))):
+        c.degree[k] = int(deg[k])
+        c.nelem[k] = int(ne[k])
+        c.interp_degree[k] = int(ideg[k]) if k < len(ideg) else 0
+        c.interp_nelem[k] = int(ine[k]) if k < len(ine) else 0
+    g = desc["map"]
+    c.map_kind = MAP_KINDS[g["kind"]]
+    if g["kind"] == "box":
+        for k in range(min(d, 3)):
+            c.map_params[k] = float(g["lo"][k])
+            c.map_params[3 + k] = float(g["hi"][k])
+    elif g["kind"] in ("annulus_nurbs", "annulus_polar"):
+        c.map_params[0] = float(g.get("r0", 1.0))
+        c.map_params[1] = float(g.get("r1", 2.0))
+    elif g["kind"] == "sine_cube":
+        c.map_params[0] = float(g.get("eps", 0.05))
+        amp = list(g.get("amp", [1.0, 0.5, 0.25]))
+        for k in range(3):
+            c.map_params[1 + k] = float(amp[k]) if k < len(amp) else 0.0
+    cov = desc["cov"]
+    c.cov_kind = COV_KINDS[cov["kind"]]
+    c.sigma2 = float(cov.get("sigma2", 1.0))
+    ell = list(cov.get("corr_len", [1.0] * d))
+    for k in range(min(d, 3, len(ell))):
+        c.corr_len[k] = float(ell[k])
+    c.max_block = int(max_block)
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Problem:
+    """Owns one kl_problem handle (kl_setup / kl_destroy)."""
+
+    def __init__(self, desc, host_only=False, max_block=0):
+        self._h = ctypes.c_void_p()
+        c = make_desc(desc, max_block)
+        fn = lib().kl_setup_host if host_only else lib().kl_setup
+        check(fn(ctypes.byref(c), ctypes.byref(self._h)))
+        N = ctypes.c_int64()
+        Nt = ctypes.c_int64()
+        n = (ctypes.c_int32 * 3)()
+        nt = (ctypes.c_int32 * 3)()
+        check(lib().kl_info(self._h, ctypes.byref(N), ctypes.byref(Nt), n, nt))
+        self.d = int(desc["dim"])
+        self.N, self.Nt = N.value, Nt.value
+        self.n = list(n)[:self.d]
+        self.nt = list(nt)[:self.d]
+
+    def close(self):
+        if self._h:
+            lib().kl_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, x, y, precision="f64", stream=None):
+        """y = A~' x for device FP64 tensors of shape (N, nvec), column-major storage
+        (a (nvec, N) contiguous tensor viewed transposed, i.e. x.T contiguous)."""
+        nvec, ldx, ldy = _colmajor(x, self.N), _ld(x), _ld(y)
+        check(lib().kl_apply(self._h, PRECISIONS[precision], nvec, _ptr(x), ldx, _ptr(y), ldy,
+                             _stream(stream)))
+
+    def stage5(self, yin, zout, precision="f64", stream=None):
+        nvec = _colmajor(yin, self.Nt)
+        check(lib().kl_stage5(self._h, PRECISIONS[precision], nvec, _ptr(yin), _ld(yin),
+                              _ptr(zout), _ld(zout), _stream(stream)))
+
+    def points(self):
+        X = np.zeros((self.Nt, self.d))
+        J = np.zeros(self.Nt)
+        check(lib().kl_get_points(self._h, ctypes.c_void_p(X.ctypes.data), ctypes.c_void_p(J.ctypes.data)))
+        return X, J
+
+    def factor(self, k):
+        C = np.zeros((self.nt[k], self.n[k]))
+        check(lib().kl_get_factor(self._h, k, ctypes.c_void_p(C.ctypes.data)))
+        return C
+
+    def eigs(self, k, precision="f64", block=32, tol=1e-6, abs_floor=1e-12, refine_fp64=True,
+             seed=0, x0=None, max_applies=0, guard=0, max_basis=0, ldv=None):
+        """k leading eigenpairs; returns (evals numpy, evecs device tensor (N, k) column-major,
+        report dict).  Raises KLError except for KL_ENOCONV, which is reported."""
+        import torch
+        o = KLEigsOpts(k=k, block=block, max_applies=max_applies, tol=tol, abs_floor=abs_floor,
+                       precision=PRECISIONS[precision], refine_fp64=int(bool(refine_fp64)),
+                       seed=seed, guard=guard, max_basis=max_basis)
+        ev = np.zeros(k)
+        V = torch.zeros((k, self.N), dtype=torch.float64, device="cuda").T
+        rep = KLEigsReport()
+        x0p, n0 = (ctypes.c_void_p(0), 0) if x0 is None else (_ptr(x0), _colmajor(x0, self.N))
+        st = lib().kl_eigs(self._h, ctypes.byref(o), x0p, n0, ctypes.c_void_p(ev.ctypes.data),
+                           _ptr(V), self.N, ctypes.byref(rep))
+        if st not in (KL_OK, KL_ENOCONV):
+            check(st)
+        return ev, V, report_dict(rep, st)
+
+
+def report_dict(rep, status=0):
+    return {"status": STATUS_NAMES.get(status, status), "n_applies": list(rep.n_applies),
+            "n_block_applies": list(rep.n_block_applies), "n_restarts": rep.n_restarts,
+            "converged": rep.converged, "t_solve": rep.t_solve,
+            "max_rel_residual": rep.max_rel_residual}
+
+
+def _colmajor(t, rows):
+    """Checks a device FP64 tensor laid out column-major (rows x nvec) and returns nvec."""
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise ValueError("expected a CUDA float64 tensor")
+    if t.dim() == 1:
+        t = t[:, None]
+    if t.shape[0] != rows or t.stride(0) != 1:
+        raise ValueError("expected a column-major (%d, nvec) tensor" % rows)
+    return int(t.shape[1])
+
+
+def _ld(t):
+    return int(t.stride(1)) if t.dim() == 2 and t.shape[1] > 1 else int(t.shape[0])

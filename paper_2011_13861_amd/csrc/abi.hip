@@ -1,0 +1,278 @@
+// C ABI: problem setup, the matrix-free apply (Algorithm 1) and accessors.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <sstream>
+
+#include "kl_internal.h"
+
+namespace kl {
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+namespace {
+
+kl_status hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return KL_OK;
+    std::ostringstream os;
+    os << what << ": " << hipGetErrorString(e);
+    set_error(os.str());
+    return e == hipErrorOutOfMemory ? KL_ENOMEM : KL_EHIP;
+}
+
+template <typename T>
+kl_status dev_alloc(T **p, size_t count, const char *what) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hip_check(hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)), what);
+}
+
+void free_problem(kl_problem *P) {
+    if (!P) return;
+    hipFree(P->dX64);
+    hipFree(P->dX32);
+    hipFree(P->dJ);
+    for (int k = 0; k < 3; ++k) {
+        hipFree(P->dC[k]);
+        hipFree(P->dCT[k]);
+    }
+    hipFree(P->ws.T0);
+    hipFree(P->ws.T1);
+    hipFree(P->ws.Y5);
+    hipFree(P->ws.Z5);
+    delete P;
+}
+
+// Coordinate scale for stage 5: the FP64 kernels evaluate exp(-rho) / exp(-rho^2) from
+// coordinates divided by ell; the FP32 kernels use exp2 and absorb log2(e).
+double coord_scale(int cov_kind, double ell, bool base2) {
+    const double log2e = 1.4426950408889634;
+    switch (cov_kind) {
+    case KL_COV_EXP:
+    case KL_COV_EXP_L1: return (base2 ? log2e : 1.0) / ell;
+    case KL_COV_SQEXP: return (base2 ? std::sqrt(log2e) : 1.0) / ell;
+    default: return 1.0;
+    }
+}
+
+int64_t max_intermediate(const HostSetup &hs) {
+    int64_t best = std::max(hs.N, hs.Nt);
+    for (int k = 0; k <= hs.d; ++k) {
+        int64_t f = 1, b = 1;
+        for (int j = 0; j < hs.d; ++j) {
+            f *= (j < k) ? hs.nt[j] : hs.n[j];
+            b *= (j < k) ? hs.n[j] : hs.nt[j];
+        }
+        best = std::max(best, std::max(f, b));
+    }
+    return best;
+}
+
+bool valid_precision(int precision) { return precision == KL_F64 || precision == KL_F32; }
+
+}  // namespace
+
+// One chunk (<= kBW columns) of Algorithm 1: x (N x nb, ld ldx) -> y (N x nb, ld ldy).
+kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx,
+                      double *y, int64_t ldy, hipStream_t s) {
+    const HostSetup &hs = P->hs;
+    double *T0 = P->ws.T0, *T1 = P->ws.T1;
+    const double *cur = x;
+    if (ldx != hs.N) {
+        launch_copy_cols(x, ldx, T0, hs.N, hs.N, nb, s);
+        cur = T0;
+    }
+    // stages 1-3 composed: C_k along each direction
+    int64_t A = 1;
+    for (int k = 0; k < hs.d; ++k) {
+        int64_t Cn = nb;
+        for (int j = k + 1; j < hs.d; ++j) Cn *= hs.n[j];
+        double *out = (cur == T0) ? T1 : T0;
+        launch_mode_contract(P->dC[k], cur, out, A, hs.n[k], hs.nt[k], Cn, s);
+        A *= hs.nt[k];
+        cur = out;
+    }
+    // stage 4 + layout change, stage 5, stage 6 (sigma^2 J) + split reduction
+    launch_to_stage5(precision, cur, hs.Nt, hs.Nt, nb, P->dJ, P->Ntpad, P->ws.Y5, s);
+    const int nsplit = launch_stage5(P, precision, P->ws.Y5, P->ws.Z5, s);
+    double *zbuf = (cur == T0) ? T1 : T0;
+    launch_from_stage5(precision, P->ws.Z5, nsplit, P->Ntpad, hs.Nt, nb, P->dJ, P->sigma2, zbuf,
+                       hs.Nt, s);
+    cur = zbuf;
+    // stages 7-9 composed: C_k^T along each direction
+    A = 1;
+    for (int k = 0; k < hs.d; ++k) {
+        int64_t Cn = nb;
+        for (int j = k + 1; j < hs.d; ++j) Cn *= hs.nt[j];
+        double *out = (k == hs.d - 1 && ldy == hs.N) ? y : ((cur == T0) ? T1 : T0);
+        launch_mode_contract(P->dCT[k], cur, out, A, hs.nt[k], hs.n[k], Cn, s);
+        A *= hs.n[k];
+        cur = out;
+    }
+    if (cur != y) launch_copy_cols(cur, hs.N, y, ldy, hs.N, nb, s);
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
+}  // namespace kl
+
+using namespace kl;
+
+extern "C" {
+
+kl_status kl_setup_host(const kl_desc *desc, kl_problem **out) {
+    if (!desc || !out) { set_error("kl_setup_host: NULL argument"); return KL_EINVAL; }
+    kl_problem *P = new (std::nothrow) kl_problem();
+    if (!P) { set_error("kl_setup_host: host allocation failed"); return KL_ENOMEM; }
+    kl_status st = build_host_setup(*desc, P->hs);
+    if (st != KL_OK) { delete P; return st; }
+    P->host_only = true;
+    *out = P;
+    return KL_OK;
+}
+
+kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
+    if (!desc || !out) { set_error("kl_setup: NULL argument"); return KL_EINVAL; }
+    kl_problem *P = new (std::nothrow) kl_problem();
+    if (!P) { set_error("kl_setup: host allocation failed"); return KL_ENOMEM; }
+    kl_status st = build_host_setup(*desc, P->hs);
+    if (st != KL_OK) { delete P; return st; }
+    const HostSetup &hs = P->hs;
+    P->cov_kind = desc->cov_kind;
+    P->sigma2 = desc->sigma2;
+    for (int k = 0; k < 3; ++k) P->ell[k] = k < hs.d ? desc->corr_len[k] : 1.0;
+    P->Ntpad = (hs.Nt + kPad - 1) / kPad * kPad;
+    int dev = 0;
+    if ((st = hip_check(hipGetDevice(&dev), "hipGetDevice")) != KL_OK) { delete P; return st; }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        P->n_cu = ncu;
+    const int64_t Np = P->Ntpad;
+    const int d = hs.d;
+    // host staging of the device arrays
+    std::vector<double> x64(size_t(d) * Np, 0.0), jpad(size_t(Np), 0.0);
+    std::vector<float> x32(size_t(d) * Np, 0.f);
+    for (int k = 0; k < d; ++k) {
+        const double s64 = coord_scale(P->cov_kind, P->ell[k], false);
+        const double s32 = coord_scale(P->cov_kind, P->ell[k], true);
+        for (int64_t p = 0; p < hs.Nt; ++p) {
+            const double v = hs.X[size_t(p) * d + k];
+            x64[size_t(k) * Np + p] = v * s64;
+            x32[size_t(k) * Np + p] = float(v * s32);
+        }
+    }
+    for (int64_t p = 0; p < hs.Nt; ++p) jpad[p] = hs.J[p];
+    int64_t lchunk;
+    P->ws.max_split = stage5_splits(Np, P->n_cu, &lchunk);
+    P->ws.t_elems = size_t(max_intermediate(hs)) * kBW;
+    P->ws.y5_bytes = size_t(Np) * kBW * sizeof(double);
+    P->ws.z5_bytes = size_t(P->ws.max_split) * Np * kBW * sizeof(double);
+#define KL_TRY(expr)                                   \
+    do {                                               \
+        if ((st = (expr)) != KL_OK) { free_problem(P); return st; } \
+    } while (0)
+    KL_TRY(dev_alloc(&P->dX64, x64.size(), "hipMalloc X64"));
+    KL_TRY(dev_alloc(&P->dX32, x32.size(), "hipMalloc X32"));
+    KL_TRY(dev_alloc(&P->dJ, jpad.size(), "hipMalloc J"));
+    KL_TRY(hip_check(hipMemcpy(P->dX64, x64.data(), x64.size() * 8, hipMemcpyHostToDevice), "copy X64"));
+    KL_TRY(hip_check(hipMemcpy(P->dX32, x32.data(), x32.size() * 4, hipMemcpyHostToDevice), "copy X32"));
+    KL_TRY(hip_check(hipMemcpy(P->dJ, jpad.data(), jpad.size() * 8, hipMemcpyHostToDevice), "copy J"));
+    for (int k = 0; k < d; ++k) {
+        const int n = hs.n[k], nt = hs.nt[k];
+        std::vector<double> CT(size_t(n) * nt);
+        for (int i = 0; i < nt; ++i)
+            for (int j = 0; j < n; ++j) CT[size_t(j) * nt + i] = hs.C[k][size_t(i) * n + j];
+        KL_TRY(dev_alloc(&P->dC[k], hs.C[k].size(), "hipMalloc C"));
+        KL_TRY(dev_alloc(&P->dCT[k], CT.size(), "hipMalloc CT"));
+        KL_TRY(hip_check(hipMemcpy(P->dC[k], hs.C[k].data(), CT.size() * 8, hipMemcpyHostToDevice), "copy C"));
+        KL_TRY(hip_check(hipMemcpy(P->dCT[k], CT.data(), CT.size() * 8, hipMemcpyHostToDevice), "copy CT"));
+    }
+    KL_TRY(dev_alloc(&P->ws.T0, P->ws.t_elems, "hipMalloc T0"));
+    KL_TRY(dev_alloc(&P->ws.T1, P->ws.t_elems, "hipMalloc T1"));
+    KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5), P->ws.y5_bytes, "hipMalloc Y5"));
+    KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Z5), P->ws.z5_bytes, "hipMalloc Z5"));
+#undef KL_TRY
+    *out = P;
+    return KL_OK;
+}
+
+kl_status kl_info(const kl_problem *P, int64_t *N, int64_t *Ntilde, int32_t *n, int32_t *nt) {
+    if (!P) { set_error("kl_info: NULL handle"); return KL_EINVAL; }
+    if (N) *N = P->hs.N;
+    if (Ntilde) *Ntilde = P->hs.Nt;
+    for (int k = 0; k < 3; ++k) {
+        if (n) n[k] = k < P->hs.d ? P->hs.n[k] : 1;
+        if (nt) nt[k] = k < P->hs.d ? P->hs.nt[k] : 1;
+    }
+    return KL_OK;
+}
+
+kl_status kl_apply(kl_problem *P, int32_t precision, int32_t nvec, const double *x, int64_t ldx,
+                   double *y, int64_t ldy, void *stream) {
+    if (!P || P->host_only) { set_error("kl_apply: NULL or host-only handle"); return KL_EINVAL; }
+    if (!valid_precision(precision)) { set_error("kl_apply: unsupported precision"); return KL_EINVAL; }
+    if (nvec < 0) { set_error("kl_apply: nvec < 0"); return KL_EINVAL; }
+    if (nvec == 0) return KL_OK;
+    if (!x || !y) { set_error("kl_apply: NULL vector"); return KL_EINVAL; }
+    if (ldx < P->hs.N || ldy < P->hs.N) { set_error("kl_apply: leading dimension < N"); return KL_EINVAL; }
+    const char *xb = reinterpret_cast<const char *>(x), *yb = reinterpret_cast<const char *>(y);
+    const size_t xbytes = size_t(ldx) * (nvec - 1) * 8 + size_t(P->hs.N) * 8;
+    const size_t ybytes = size_t(ldy) * (nvec - 1) * 8 + size_t(P->hs.N) * 8;
+    if (xb < yb + ybytes && yb < xb + xbytes) { set_error("kl_apply: x and y overlap"); return KL_EINVAL; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int c0 = 0; c0 < nvec; c0 += kBW) {
+        const int nb = std::min(kBW, nvec - c0);
+        kl_status st = apply_chunk(P, precision, nb, x + int64_t(c0) * ldx, ldx, y + int64_t(c0) * ldy,
+                                   ldy, s);
+        if (st != KL_OK) return st;
+    }
+    return KL_OK;
+}
+
+kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec, const double *y, int64_t ldy,
+                    double *z, int64_t ldz, void *stream) {
+    if (!P || P->host_only) { set_error("kl_stage5: NULL or host-only handle"); return KL_EINVAL; }
+    if (!valid_precision(precision)) { set_error("kl_stage5: unsupported precision"); return KL_EINVAL; }
+    if (nvec < 0) { set_error("kl_stage5: nvec < 0"); return KL_EINVAL; }
+    if (nvec == 0) return KL_OK;
+    if (!y || !z) { set_error("kl_stage5: NULL vector"); return KL_EINVAL; }
+    if (ldy < P->hs.Nt || ldz < P->hs.Nt) { set_error("kl_stage5: leading dimension < Ntilde"); return KL_EINVAL; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int c0 = 0; c0 < nvec; c0 += kBW) {
+        const int nb = std::min(kBW, nvec - c0);
+        launch_to_stage5(precision, y + int64_t(c0) * ldy, P->hs.Nt, ldy, nb, nullptr, P->Ntpad,
+                         P->ws.Y5, s);
+        const int nsplit = launch_stage5(P, precision, P->ws.Y5, P->ws.Z5, s);
+        launch_from_stage5(precision, P->ws.Z5, nsplit, P->Ntpad, P->hs.Nt, nb, nullptr, P->sigma2,
+                           z + int64_t(c0) * ldz, ldz, s);
+        kl_status st = hip_check(hipGetLastError(), "kernel launch");
+        if (st != KL_OK) return st;
+    }
+    return KL_OK;
+}
+
+kl_status kl_get_points(const kl_problem *P, double *X, double *J) {
+    if (!P) { set_error("kl_get_points: NULL handle"); return KL_EINVAL; }
+    if (X) std::memcpy(X, P->hs.X.data(), P->hs.X.size() * sizeof(double));
+    if (J) std::memcpy(J, P->hs.J.data(), P->hs.J.size() * sizeof(double));
+    return KL_OK;
+}
+
+kl_status kl_get_factor(const kl_problem *P, int32_t k, double *C) {
+    if (!P) { set_error("kl_get_factor: NULL handle"); return KL_EINVAL; }
+    if (k < 0 || k >= P->hs.d) { set_error("kl_get_factor: direction out of range"); return KL_EINVAL; }
+    if (C) std::memcpy(C, P->hs.C[k].data(), P->hs.C[k].size() * sizeof(double));
+    return KL_OK;
+}
+
+kl_status kl_destroy(kl_problem *P) {
+    free_problem(P);
+    return KL_OK;
+}
+
+const char *kl_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+"""GPU parity of the matrix-free apply (Algorithm 1) and of stage 5 against the oracle.
+
+All calls go through the C ABI (kl_setup / kl_apply / kl_stage5).  Tolerances:
+FP64 path: relative max-norm error <= 1e-12 (rounding of FP64 kernels and sums);
+FP32 path: relative Frobenius error <= 2e-6 (FP32 kernel evaluation, FP32 MFMA
+accumulation of up to ~2e4 terms).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2011_13861_amd as kl
+import workloads
+from oracle import cstage5, operator
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-6}
+
+
+def _rel_max(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def _rel_fro(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _gpu_apply(G, V, precision):
+    x = kl.to_device_block(V)
+    y = kl.new_block(G.N, V.shape[1])
+    G.apply(x, y, precision)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+SMALL = [
+    ("c1", workloads.config("c1")[0]),
+    ("annulus_ragged", workloads.quarter_annulus(13, 3, "sqexp", (0.5, 0.8))),
+    ("cube", workloads.sine_cube(6, 2, "exp", 0.5)),
+    ("interp_ne_trial", {"dim": 2, "degree": [2, 3], "nelem": [9, 5], "interp_degree": [3, 1],
+                         "interp_nelem": [12, 11], "map": {"kind": "annulus_polar", "r0": 1.0, "r1": 2.0},
+                         "cov": {"kind": "exp", "sigma2": 1.3, "corr_len": [0.4, 0.9]}}),
+    ("line", {"dim": 1, "degree": [3], "nelem": [300], "map": {"kind": "box", "lo": [0.0], "hi": [2.0]},
+              "cov": {"kind": "sqexp", "sigma2": 1.0, "corr_len": [0.2]}}),
+    ("exp_l1", {"dim": 2, "degree": [2, 2], "nelem": [10, 7], "map": {"kind": "identity"},
+                "cov": {"kind": "exp_l1", "sigma2": 1.0, "corr_len": [0.5, 0.3]}}),
+    ("const", {"dim": 2, "degree": [2, 2], "nelem": [6, 6], "map": {"kind": "box", "lo": [0, 0], "hi": [2, 1]},
+               "cov": {"kind": "const", "sigma2": 0.7, "corr_len": [1.0, 1.0]}}),
+    ("lin", {"dim": 3, "degree": [1, 2, 1], "nelem": [4, 3, 5], "map": {"kind": "identity"},
+             "cov": {"kind": "lin", "sigma2": 1.0, "corr_len": [1.0] * 3}}),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,desc", SMALL, ids=[s[0] for s in SMALL])
+def test_apply_matches_oracle(name, desc, precision):
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    V = workloads.random_block(P.N, 7, seed=3)
+    ref = P.apply(V)
+    out = _gpu_apply(G, V, precision)
+    err = _rel_max(out, ref) if precision == "f64" else _rel_fro(out, ref)
+    assert err <= TOL[precision], (name, precision, err)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_stage5_alone_matches_oracle(precision):
+    desc = workloads.quarter_annulus(20, 2, "exp", (0.3, 0.6))
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    Y = workloads.random_block(P.Nt, 32, seed=4)
+    ref = P.stage5(Y)
+    y = kl.to_device_block(Y)
+    z = kl.new_block(G.Nt, 32)
+    G.stage5(y, z, precision)
+    torch.cuda.synchronize()
+    out = z.cpu().numpy()
+    err = _rel_max(out, ref) if precision == "f64" else _rel_fro(out, ref)
+    assert err <= TOL[precision], err
+
+
+@pytest.mark.parametrize("nvec", [1, 31, 32, 33, 70])
+def test_block_widths_and_strides(nvec):
+    desc = workloads.quarter_annulus(11, 2, "sqexp", (0.5, 0.5))
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    V = workloads.random_block(P.N, nvec, seed=nvec)
+    ref = P.apply(V)
+    # strided input / output: leading dimension N + 5
+    xs = torch.zeros((nvec, P.N + 5), dtype=torch.float64, device="cuda")
+    xs[:, :P.N] = torch.from_numpy(np.ascontiguousarray(V.T)).cuda()
+    ys = torch.full((nvec, P.N + 5), 7.0, dtype=torch.float64, device="cuda")
+    x = xs.T[:P.N]
+    y = ys.T[:P.N]
+    G.apply(x, y, "f64")
+    torch.cuda.synchronize()
+    assert _rel_max(y.cpu().numpy(), ref) <= 1e-12
+    assert torch.all(ys[:, P.N:] == 7.0)          # padding of the output untouched
+
+
+def test_full_size_config2_apply():
+    """Config 2 (64x64 cubic quarter annulus, sqexp L = 0.5) at full size, 32 vectors."""
+    desc = workloads.config("c2")[0]
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    V = workloads.random_block(P.N, 32, seed=5)
+    ref = P.apply(V, stage5=lambda Y: cstage5.stage5(P, Y))
+    for prec in ("f64", "f32"):
+        out = _gpu_apply(G, V, prec)
+        err = _rel_max(out, ref) if prec == "f64" else _rel_fro(out, ref)
+        assert err <= TOL[prec], (prec, err)
+
+
+def test_full_size_config3_stage5_sampled_rows():
+    """Config 3 (24^3 perturbed cube, exp L = 0.5): stage 5 on 32 vectors, sampled rows
+    recomputed one by one by the oracle's kernel definition."""
+    from oracle import covariance
+    desc = workloads.config("c3")[0]
+    G = kl.Problem(desc)
+    X, _ = G.points()
+    Y = workloads.random_block(G.Nt, 32, seed=6)
+    y = kl.to_device_block(Y)
+    for prec in ("f64", "f32"):
+        z = kl.new_block(G.Nt, 32)
+        G.stage5(y, z, prec)
+        torch.cuda.synchronize()
+        out = z.cpu().numpy()
+        rows = np.random.default_rng(0).choice(G.Nt, 64, replace=False)
+        rows = np.concatenate([rows, [0, G.Nt - 1]])
+        ref = covariance.gamma(desc["cov"], X[rows], X) @ Y
+        err = _rel_max(out[rows], ref) if prec == "f64" else _rel_fro(out[rows], ref)
+        assert err <= TOL[prec], (prec, err)
+
+
+def test_apply_is_symmetric_on_gpu():
+    desc = workloads.config("c3")[0]
+    G = kl.Problem(desc)
+    rng = np.random.default_rng(7)
+    U = rng.standard_normal((G.N, 2))
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-6)):
+        AU = _gpu_apply(G, U, prec)
+        lhs = U[:, 0] @ AU[:, 1]
+        rhs = AU[:, 0] @ U[:, 1]
+        assert abs(lhs - rhs) <= tol * np.linalg.norm(AU[:, 0]) * np.linalg.norm(U[:, 1]), prec
+
+
+def test_apply_errors():
+    desc = workloads.unit_square(4, 2, "exp", 1.0)
+    G = kl.Problem(desc)
+    x = kl.new_block(G.N, 2)
+    with pytest.raises(kl.KLError):
+        G.apply(x, x, "f64")                        # aliasing input and output
+    with pytest.raises(KeyError):
+        G.apply(x, kl.new_block(G.N, 2), "f16")
+    import ctypes
+    st = kl.lib().kl_apply(G.handle, 9, 2, ctypes.c_void_p(x.data_ptr()), G.N,
+                           ctypes.c_void_p(kl.new_block(G.N, 2).data_ptr()), G.N, None)
+    assert st == -1
+    # nvec = 0 is a no-op
+    assert kl.lib().kl_apply(G.handle, 0, 0, None, G.N, None, G.N, None) == 0
