@@ -158,6 +158,13 @@ typedef struct {
 kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0, int32_t nvec0,
                   double *evals, double *evecs, int64_t ldv, kl_eigs_report *rep);
 
+/* Dense symmetric eigensolver used by the Rayleigh-Ritz step of kl_eigs (host, FP64):
+ * A is n x n row-major symmetric (host, read only); w receives the n eigenvalues in
+ * descending order, Z (host, n x n column-major) the orthonormal eigenvectors.
+ * Householder tridiagonalisation + implicit QR with Wilkinson shifts.
+ * Errors: KL_EINVAL, KL_ENUMERIC (non-finite input), KL_ENOCONV. */
+kl_status kl_symeig(int32_t n, const double *A, double *w, double *Z);
+
 /* Releases the handle and every device buffer it owns.  NULL is accepted. */
 kl_status kl_destroy(kl_problem *P);
 

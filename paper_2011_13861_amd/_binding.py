@@ -23,7 +23,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
-           "kl_get_factor", "kl_eigs", "kl_destroy", "kl_last_error"]
+           "kl_get_factor", "kl_eigs", "kl_symeig", "kl_destroy", "kl_last_error"]
 
 
 class KLError(RuntimeError):
@@ -74,6 +74,7 @@ def lib():
         L.kl_get_factor.argtypes = [P, ctypes.c_int32, P]
         L.kl_eigs.argtypes = [P, ctypes.POINTER(KLEigsOpts), P, ctypes.c_int32, P, P,
                               ctypes.c_int64, ctypes.POINTER(KLEigsReport)]
+        L.kl_symeig.argtypes = [ctypes.c_int32, P, P, P]
         L.kl_destroy.argtypes = [P]
         L.kl_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -213,6 +214,17 @@ class Problem:
         if st not in (KL_OK, KL_ENOCONV):
             check(st)
         return ev, V, report_dict(rep, st)
+
+
+def symeig(A):
+    """Host dense symmetric eigensolver of the library (w descending, Z columns)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    w = np.zeros(n)
+    Z = np.zeros((n, n))          # filled column-major -> read back transposed
+    check(lib().kl_symeig(n, ctypes.c_void_p(A.ctypes.data), ctypes.c_void_p(w.ctypes.data),
+                          ctypes.c_void_p(Z.ctypes.data)))
+    return w, Z.T.copy()
 
 
 def report_dict(rep, status=0):

@@ -29,6 +29,10 @@ struct HostSetup {
     std::vector<double> J;      // Nt, sqrt(det DF)
 };
 
+// Dense symmetric eigensolver (row-major A, descending w, column-major Z); false if the
+// QR iteration fails to converge.
+bool sym_eig(int n, const double *A, double *w, double *Z);
+
 // Fills `hs` from the description; returns KL_OK or an error (message set).
 kl_status build_host_setup(const kl_desc &desc, HostSetup &hs);
 
