@@ -1,0 +1,150 @@
+"""Benchmark of the covariance apply and of time-to-k eigenpairs on one MI355X.
+
+A step is one covariance apply (Algorithm 1) of a 32-vector block: forward Kronecker
+stages, the stage-5 covariance-times-block kernel in the workload's precision, backward
+Kronecker stages.  value = pair evaluations per second = Ntilde^2 per step / step time.
+The same run also times the eigensolve to k pairs at relative residual 1e-6 (FP32 form
+with FP64 refinement, and the plain FP64 form), reports the stage-5 kernel against its
+roofline (HIP events around every stage-5 launch in the timed region), and times the
+CPU oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5|c1]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+WORKLOADS = {
+    "c2": ("2D quarter annulus (r in [1,2], NURBS map) 64x64 cubic, Ntilde = N = 4489, "
+           "squared exponential L = 0.5, k = 40"),
+    "c3": ("3D sine-perturbed unit cube 24^3 quadratic, Ntilde = N = 17576, exponential L = 0.5, "
+           "k = 50"),
+    "c5": "2D quarter annulus 48x48 cubic, Ntilde = N = 2601, squared exponential L = 0.5, k = 16",
+    "c1": "2D unit square 16x16 quadratic, Ntilde = N = 324, exponential L = 1, k = 20",
+}
+
+
+def cpu_baseline(desc, b, budget_s=12.0):
+    """Oracle (literal Algorithm 1 with the C/OpenMP stage 5, FP64) applied to 32-vector
+    blocks of the same workload until about budget_s seconds have passed."""
+    import numpy as np
+
+    import workloads
+    from oracle import cstage5, operator
+    P = operator.Problem(desc)
+    V = workloads.random_block(P.N, b, seed=0)
+    s5 = lambda Y: cstage5.stage5(P, Y)   # noqa: E731
+    P.apply(V[:, :1], stage5=s5)          # load the shared object
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        P.apply(V, stage5=s5)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt > budget_s or n >= 50:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": P.Nt ** 2 * n / dt, "unit": "pair evals/s", "cores": threads, "kind": "oracle",
+            "sample": "%d oracle applies (FP64, %d-vector block) of the same workload in %.1f s"
+                      % (n, b, dt)}, float(np.float64(dt / n))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["f32", "f64"])
+    ap.add_argument("--solves", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2011_13861_amd as kl
+    import workloads
+
+    torch.cuda.set_device(0)
+    desc, k, b = workloads.config(args.workload)
+    prec = args.precision or "f32"
+    G = kl.Problem(desc)
+    x = kl.to_device_block(workloads.random_block(G.N, b, seed=1))
+    y = kl.new_block(G.N, b)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        G.apply(x, y, prec)
+    torch.cuda.synchronize()
+    G.profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        G.apply(x, y, prec)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = G.profile_read()
+    G.profile_enable(False)
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    pairs = float(G.Nt) ** 2
+    value = pairs / (ms_per_step * 1e-3)
+    cnt, kms = prof[prec]
+    k_avg_s = kms / max(cnt, 1) * 1e-3
+    flops = 2.0 * b * pairs                    # MFMA contraction flops per stage-5 launch
+    achieved = flops / k_avg_s / 1e12
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
+                "kernel": "stage5_%s_kernel" % prec, "kernel_avg_us": k_avg_s * 1e6,
+                "kernel_pairs_per_s": pairs / k_avg_s, "launches": cnt}
+
+    # time to k eigenpairs at relative residual 1e-6 (criterion under the FP64 operator)
+    def solve(p):
+        G.eigs(k, precision=p, tol=1e-6)          # warm (allocations, handles)
+        times, reps = [], []
+        for _ in range(args.solves):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            w, V, rep = G.eigs(k, precision=p, tol=1e-6)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            reps.append(rep)
+        i = int(np.argsort(times)[len(times) // 2])
+        return times[i], reps[i]
+    t_lo, rep_lo = solve("f32")
+    t_64, rep_64 = solve("f64")
+
+    out = {
+        "metric": "covariance-apply pair evals/s (% peak); time to k eigenpairs at 1e-6 err",
+        "value": value, "unit": "pair evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
+                   "block": b, "k": k, "stage5_precision": prec},
+        "roofline": roofline,
+        "time_to_k": {"f32_refined_fp64_ms": t_lo * 1e3, "f64_ms": t_64 * 1e3,
+                      "f32_report": rep_lo, "f64_report": rep_64},
+        "wall_s_timed_region": wall,
+    }
+    if not args.no_cpu:
+        cb, _ = cpu_baseline(desc, b)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -158,6 +158,16 @@ typedef struct {
 kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0, int32_t nvec0,
                   double *evals, double *evecs, int64_t ldv, kl_eigs_report *rep);
 
+/* Stage-5 kernel timing for measurement tools: while enabled, every stage-5 launch of
+ * this handle (from kl_apply, kl_stage5 and kl_eigs) is bracketed by two HIP events
+ * recorded on its launch stream (up to 8192 launches until the next read).
+ * kl_profile_enable(P, 1) creates the event pool (once) and resets the counters;
+ * kl_profile_enable(P, 0) stops recording.  kl_profile_read waits for the recorded
+ * events and returns, per kl_precision (host arrays of 4), the number of timed launches
+ * and their total duration in milliseconds accumulated since the last enable. */
+kl_status kl_profile_enable(kl_problem *P, int32_t enable);
+kl_status kl_profile_read(kl_problem *P, int64_t *count, double *ms);
+
 /* Dense symmetric eigensolver used by the Rayleigh-Ritz step of kl_eigs (host, FP64):
  * A is n x n row-major symmetric (host, read only); w receives the n eigenvalues in
  * descending order, Z (host, n x n column-major) the orthonormal eigenvectors.

@@ -23,7 +23,8 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
-           "kl_get_factor", "kl_eigs", "kl_symeig", "kl_destroy", "kl_last_error"]
+           "kl_get_factor", "kl_eigs", "kl_symeig", "kl_profile_enable", "kl_profile_read",
+           "kl_destroy", "kl_last_error"]
 
 
 class KLError(RuntimeError):
@@ -75,6 +76,8 @@ def lib():
         L.kl_eigs.argtypes = [P, ctypes.POINTER(KLEigsOpts), P, ctypes.c_int32, P, P,
                               ctypes.c_int64, ctypes.POINTER(KLEigsReport)]
         L.kl_symeig.argtypes = [ctypes.c_int32, P, P, P]
+        L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
+        L.kl_profile_read.argtypes = [P, P, P]
         L.kl_destroy.argtypes = [P]
         L.kl_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -196,6 +199,17 @@ class Problem:
         C = np.zeros((self.nt[k], self.n[k]))
         check(lib().kl_get_factor(self._h, k, ctypes.c_void_p(C.ctypes.data)))
         return C
+
+    def profile_enable(self, on=True):
+        check(lib().kl_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self):
+        """{precision: (timed stage-5 launches, total ms)} since the last enable."""
+        cnt = (ctypes.c_int64 * 4)()
+        ms = (ctypes.c_double * 4)()
+        check(lib().kl_profile_read(self._h, cnt, ms))
+        names = {v: k for k, v in PRECISIONS.items()}
+        return {names[p]: (int(cnt[p]), float(ms[p])) for p in range(4)}
 
     def eigs(self, k, precision="f64", block=32, tol=1e-6, abs_floor=1e-12, refine_fp64=True,
              seed=0, x0=None, max_applies=0, guard=0, max_basis=0, ldv=None):

@@ -33,6 +33,7 @@ kl_status dev_alloc(T **p, size_t count, const char *what) {
 
 void free_problem(kl_problem *P) {
     if (!P) return;
+    for (hipEvent_t e : P->prof_ev) hipEventDestroy(e);
     hipFree(P->dX64);
     hipFree(P->dX32);
     hipFree(P->dJ);
@@ -76,6 +77,19 @@ bool valid_precision(int precision) { return precision == KL_F64 || precision ==
 
 }  // namespace
 
+// Stage-5 launch, bracketed by HIP events on the launch stream while profiling is on.
+int timed_stage5(kl_problem *P, int precision, hipStream_t s) {
+    const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
+    if (rec) hipEventRecord(P->prof_ev[P->prof_used], s);
+    const int nsplit = launch_stage5(P, precision, P->ws.Y5, P->ws.Z5, s);
+    if (rec) {
+        hipEventRecord(P->prof_ev[P->prof_used + 1], s);
+        P->prof_prec.push_back(precision);
+        P->prof_used += 2;
+    }
+    return nsplit;
+}
+
 // One chunk (<= kBW columns) of Algorithm 1: x (N x nb, ld ldx) -> y (N x nb, ld ldy).
 kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx,
                       double *y, int64_t ldy, hipStream_t s) {
@@ -98,7 +112,7 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
     }
     // stage 4 + layout change, stage 5, stage 6 (sigma^2 J) + split reduction
     launch_to_stage5(precision, cur, hs.Nt, hs.Nt, nb, P->dJ, P->Ntpad, P->ws.Y5, s);
-    const int nsplit = launch_stage5(P, precision, P->ws.Y5, P->ws.Z5, s);
+    const int nsplit = timed_stage5(P, precision, s);
     double *zbuf = (cur == T0) ? T1 : T0;
     launch_from_stage5(precision, P->ws.Z5, nsplit, P->Ntpad, hs.Nt, nb, P->dJ, P->sigma2, zbuf,
                        hs.Nt, s);
@@ -245,7 +259,7 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec, const double
         const int nb = std::min(kBW, nvec - c0);
         launch_to_stage5(precision, y + int64_t(c0) * ldy, P->hs.Nt, ldy, nb, nullptr, P->Ntpad,
                          P->ws.Y5, s);
-        const int nsplit = launch_stage5(P, precision, P->ws.Y5, P->ws.Z5, s);
+        const int nsplit = timed_stage5(P, precision, s);
         launch_from_stage5(precision, P->ws.Z5, nsplit, P->Ntpad, P->hs.Nt, nb, nullptr, P->sigma2,
                            z + int64_t(c0) * ldz, ldz, s);
         kl_status st = hip_check(hipGetLastError(), "kernel launch");
@@ -265,6 +279,47 @@ kl_status kl_get_factor(const kl_problem *P, int32_t k, double *C) {
     if (!P) { set_error("kl_get_factor: NULL handle"); return KL_EINVAL; }
     if (k < 0 || k >= P->hs.d) { set_error("kl_get_factor: direction out of range"); return KL_EINVAL; }
     if (C) std::memcpy(C, P->hs.C[k].data(), P->hs.C[k].size() * sizeof(double));
+    return KL_OK;
+}
+
+kl_status kl_profile_enable(kl_problem *P, int32_t enable) {
+    if (!P || P->host_only) { set_error("kl_profile_enable: NULL or host-only handle"); return KL_EINVAL; }
+    const size_t pool = 2 * 8192;
+    if (enable && P->prof_ev.size() < pool) {
+        P->prof_ev.reserve(pool);
+        while (P->prof_ev.size() < pool) {
+            hipEvent_t e;
+            kl_status st = hip_check(hipEventCreate(&e), "hipEventCreate");
+            if (st != KL_OK) return st;
+            P->prof_ev.push_back(e);
+        }
+    }
+    P->prof_on = enable != 0;
+    P->prof_used = 0;
+    P->prof_prec.clear();
+    P->prof_prec.reserve(pool / 2);
+    for (int p = 0; p < 4; ++p) { P->prof_count[p] = 0; P->prof_ms[p] = 0.0; }
+    return KL_OK;
+}
+
+kl_status kl_profile_read(kl_problem *P, int64_t *count, double *ms) {
+    if (!P || P->host_only) { set_error("kl_profile_read: NULL or host-only handle"); return KL_EINVAL; }
+    for (size_t i = 0; i < P->prof_prec.size(); ++i) {
+        kl_status st = hip_check(hipEventSynchronize(P->prof_ev[2 * i + 1]), "hipEventSynchronize");
+        if (st != KL_OK) return st;
+        float t = 0.f;
+        if ((st = hip_check(hipEventElapsedTime(&t, P->prof_ev[2 * i], P->prof_ev[2 * i + 1]),
+                            "hipEventElapsedTime")) != KL_OK)
+            return st;
+        P->prof_count[P->prof_prec[i]] += 1;
+        P->prof_ms[P->prof_prec[i]] += t;
+    }
+    P->prof_prec.clear();
+    P->prof_used = 0;
+    for (int p = 0; p < 4; ++p) {
+        if (count) count[p] = P->prof_count[p];
+        if (ms) ms[p] = P->prof_ms[p];
+    }
     return KL_OK;
 }
 

@@ -1,10 +1,448 @@
-// Block eigensolver (placeholder until the solver lands).
+// Block eigensolver for the k leading eigenpairs of A~' (standard form, Sec. 4.1).
+//
+// The paper solves the standard eigenproblem with implicitly restarted Lanczos, one
+// vector at a time, calling Algorithm 1 once per iteration (Sec. 4.4.2).  Here the
+// Krylov space is grown a block of b vectors at a time, so that every stage-5 launch
+// contracts the covariance tile with b columns on the matrix cores:
+//   - basis V (N x m, orthonormal) and AV = A~' V are kept on the device in FP64;
+//   - expansion: the newest block of AV, orthogonalised against V twice (classical
+//     Gram-Schmidt, twice) and orthonormalised through the eigen-decomposition of its
+//     b x b Gram matrix;
+//   - Rayleigh-Ritz: H = V^T AV (FP64, symmetrised), dense symmetric eigensolve,
+//     Ritz vectors X = V S, residuals R = AV S - X Theta computed explicitly;
+//   - thick restart: keep the k + guard leading Ritz vectors; the next block spans the
+//     dominant directions of their residuals (the next Krylov block in exact arithmetic);
+//   - mixed precision: with a low-precision stage 5 the iteration runs until the
+//     residuals reach the level that precision can certify, then AV is recomputed
+//     with the FP64 apply and the same iteration finishes in FP64, so that the final
+//     criterion is met under the FP64 operator.
+// Converged when ||A~' x_i - theta_i x_i|| <= max(tol theta_i, abs_floor theta_1), i <= k.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <random>
+#include <sstream>
+
 #include "kl_internal.h"
+
+namespace kl {
+
+kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx,
+                      double *y, int64_t ldy, hipStream_t s);
+
+namespace {
+
+constexpr int kT = 256;
+
+// R[:, j] = AX[:, j] - theta_j X[:, j] for j < k; norms[j] = ||R[:, j]||_2.
+__global__ __launch_bounds__(kT) void residual_kernel(const double *__restrict__ X,
+                                                      const double *__restrict__ AX,
+                                                      const double *__restrict__ theta, int64_t N,
+                                                      int64_t ld, double *__restrict__ R,
+                                                      double *__restrict__ norms) {
+    const int j = blockIdx.x;
+    const double t = theta[j];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += kT) {
+        const double r = AX[i + ld * j] - t * X[i + ld * j];
+        if (R) R[i + ld * j] = r;
+        s += r * r;
+    }
+    __shared__ double red[kT];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) norms[j] = sqrt(red[0]);
+}
+
+// Checks a block for non-finite values: flag[0] = 1 if any.
+__global__ __launch_bounds__(kT) void finite_kernel(const double *__restrict__ X, int64_t n,
+                                                    int *__restrict__ flag) {
+    for (int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kT)
+        if (!isfinite(X[i])) flag[0] = 1;
+}
+
+struct Solver {
+    kl_problem *P;
+    rocblas_handle blas = nullptr;
+    hipStream_t s = nullptr;
+    int64_t N = 0;
+    int b = 32, k = 1, keep = 1, mmax = 1;
+    double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
+    double *C = nullptr, *dtheta = nullptr, *dnorm = nullptr;
+    int *dflag = nullptr;
+    std::vector<double> H;      // mmax x mmax, row-major, host
+    int m = 0;                  // current basis size
+    int last = 0;               // columns [m - last, m) are the newest block
+    int applies[4] = {0, 0, 0, 0}, block_applies[4] = {0, 0, 0, 0}, restarts = 0;
+
+    kl_status check(hipError_t e, const char *what) {
+        if (e == hipSuccess) return KL_OK;
+        std::ostringstream os;
+        os << "kl_eigs: " << what << ": " << hipGetErrorString(e);
+        set_error(os.str());
+        return e == hipErrorOutOfMemory ? KL_ENOMEM : KL_EHIP;
+    }
+    kl_status bcheck(rocblas_status st, const char *what) {
+        if (st == rocblas_status_success) return KL_OK;
+        std::ostringstream os;
+        os << "kl_eigs: rocBLAS " << what << " failed (" << int(st) << ")";
+        set_error(os.str());
+        return KL_EHIP;
+    }
+    // C = A^T B   (A: N x ma, B: N x nb, ld N) -> C (ma x nb, ld ma), device
+    kl_status gemm_tn(const double *A, int ma, const double *B, int nb, double *Cout) {
+        const double one = 1.0, zero = 0.0;
+        return bcheck(rocblas_dgemm(blas, rocblas_operation_transpose, rocblas_operation_none, ma, nb,
+                                    int(N), &one, A, int(N), B, int(N), &zero, Cout, ma), "dgemm TN");
+    }
+    // Out = alpha A S + beta Out   (A: N x ma, S: ma x nb with ld lds)
+    kl_status gemm_nn(const double *A, int ma, const double *S, int lds, int nb, double alpha,
+                      double beta, double *Out) {
+        return bcheck(rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, int(N), nb,
+                                    ma, &alpha, A, int(N), S, lds, &beta, Out, int(N)), "dgemm NN");
+    }
+
+    kl_status apply(int precision, const double *x, double *y, int ncols) {
+        for (int c0 = 0; c0 < ncols; c0 += kBW) {
+            const int nb = std::min(kBW, ncols - c0);
+            kl_status st = apply_chunk(P, precision, nb, x + int64_t(c0) * N, N, y + int64_t(c0) * N, N, s);
+            if (st != KL_OK) return st;
+            block_applies[precision] += 1;
+        }
+        applies[precision] += ncols;
+        return KL_OK;
+    }
+
+    // H[0:m, c0:c1] = V^T AV[:, c0:c1] (and the mirrored rows).
+    kl_status update_H(int c0, int c1) {
+        const int nc = c1 - c0;
+        kl_status st = gemm_tn(V, c1, AV + int64_t(c0) * N, nc, C);
+        if (st != KL_OK) return st;
+        std::vector<double> hc(size_t(c1) * nc);
+        if ((st = check(hipMemcpyAsync(hc.data(), C, hc.size() * 8, hipMemcpyDeviceToHost, s), "copy H")) != KL_OK)
+            return st;
+        if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+        for (int j = 0; j < nc; ++j)
+            for (int i = 0; i < c1; ++i) {
+                const double v = hc[size_t(j) * c1 + i];
+                const int col = c0 + j;
+                if (i < c0) {
+                    H[size_t(i) * mmax + col] = v;
+                    H[size_t(col) * mmax + i] = v;
+                } else {
+                    H[size_t(i) * mmax + col] = v;   // diagonal block, symmetrised below
+                }
+            }
+        for (int i = c0; i < c1; ++i)
+            for (int j = i + 1; j < c1; ++j) {
+                const double a = 0.5 * (H[size_t(i) * mmax + j] + H[size_t(j) * mmax + i]);
+                H[size_t(i) * mmax + j] = H[size_t(j) * mmax + i] = a;
+            }
+        return KL_OK;
+    }
+
+    // Orthonormalises the ncols columns of W against V[:, :m] and among themselves and
+    // writes `want` orthonormal columns to V[:, m:m+want], spanning the dominant
+    // directions of W; rank deficiency is filled with seeded random directions.
+    kl_status orth_into_basis(double *Wb, int ncols, int want, std::mt19937_64 &rng) {
+        kl_status st;
+        std::vector<double> G, w, Z;
+        double *dst = V + int64_t(m) * N;
+        // pass 0 selects the `want` dominant directions; later passes re-orthonormalise
+        // them (twice is enough unless a direction had to be replaced by a random one)
+        bool refilled = true;
+        for (int pass = 0; pass < 4 && (pass < 2 || refilled); ++pass) {
+            refilled = false;
+            for (int cgs = 0; cgs < 2; ++cgs) {
+                if (m == 0) break;
+                if ((st = gemm_tn(V, m, Wb, ncols, C)) != KL_OK) return st;
+                if ((st = gemm_nn(V, m, C, m, ncols, -1.0, 1.0, Wb)) != KL_OK) return st;
+            }
+            // Gram matrix of W and its eigen-decomposition
+            if ((st = gemm_tn(Wb, ncols, Wb, ncols, C)) != KL_OK) return st;
+            G.assign(size_t(ncols) * ncols, 0.0);
+            if ((st = check(hipMemcpyAsync(G.data(), C, G.size() * 8, hipMemcpyDeviceToHost, s), "copy G")) != KL_OK)
+                return st;
+            if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+            for (int i = 0; i < ncols; ++i)
+                for (int j = i + 1; j < ncols; ++j) {
+                    const double a = 0.5 * (G[size_t(i) * ncols + j] + G[size_t(j) * ncols + i]);
+                    G[size_t(i) * ncols + j] = G[size_t(j) * ncols + i] = a;
+                }
+            w.assign(ncols, 0.0);
+            Z.assign(size_t(ncols) * ncols, 0.0);
+            if (!sym_eig(ncols, G.data(), w.data(), Z.data())) {
+                set_error("kl_eigs: Gram eigen-decomposition failed");
+                return KL_ENUMERIC;
+            }
+            // pass 0 keeps the `want` dominant directions (fewer if W has fewer columns:
+            // the rest is filled at random); later passes keep every column
+            const int out_cols = pass == 0 ? want : ncols;
+            const double thresh = std::max(w[0], 1e-300) * 1e-26;
+            int good = 0;
+            while (good < std::min(out_cols, ncols) && w[good] > thresh) ++good;
+            // T = Z[:, :good] diag(1/sqrt w)  (ncols x good), new W = W T
+            std::vector<double> T(size_t(ncols) * good, 0.0);
+            for (int j = 0; j < good; ++j) {
+                const double sc = 1.0 / std::sqrt(w[j]);
+                for (int i = 0; i < ncols; ++i) T[size_t(j) * ncols + i] = Z[size_t(j) * ncols + i] * sc;
+            }
+            if ((st = check(hipMemcpyAsync(C, T.data(), T.size() * 8, hipMemcpyHostToDevice, s), "copy T")) != KL_OK)
+                return st;
+            if ((st = gemm_nn(Wb, ncols, C, ncols, good, 1.0, 0.0, dst)) != KL_OK) return st;
+            if (good < out_cols) {
+                // replace the missing directions by random vectors; the next pass
+                // orthonormalises them
+                refilled = true;
+                std::normal_distribution<double> nd;
+                std::vector<double> r(size_t(N) * (out_cols - good));
+                for (double &v : r) v = nd(rng);
+                if ((st = check(hipMemcpyAsync(dst + int64_t(good) * N, r.data(), r.size() * 8,
+                                               hipMemcpyHostToDevice, s), "copy random")) != KL_OK)
+                    return st;
+                if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+            }
+            ncols = out_cols;
+            if ((st = check(hipMemcpyAsync(Wb, dst, size_t(N) * ncols * 8, hipMemcpyDeviceToDevice, s),
+                            "copy W")) != KL_OK)
+                return st;
+        }
+        return KL_OK;
+    }
+};
+
+int default_guard(int k, int b) { return std::max(std::max(8, b / 4), (3 * k + 9) / 10); }
+
+}  // namespace
+
+}  // namespace kl
+
+using namespace kl;
 
 extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0,
                              int32_t nvec0, double *evals, double *evecs, int64_t ldv,
                              kl_eigs_report *rep) {
-    (void)P; (void)opts; (void)x0; (void)nvec0; (void)evals; (void)evecs; (void)ldv; (void)rep;
-    kl::set_error("kl_eigs: not available yet");
-    return KL_EINVAL;
+    using clock = std::chrono::steady_clock;
+    const auto t0 = clock::now();
+    if (!P || P->host_only) { set_error("kl_eigs: NULL or host-only handle"); return KL_EINVAL; }
+    if (!opts || !evals || !evecs) { set_error("kl_eigs: NULL argument"); return KL_EINVAL; }
+    const int64_t N = P->hs.N;
+    if (opts->k < 1 || opts->k > N) { set_error("kl_eigs: k must be in 1..N"); return KL_EINVAL; }
+    if (ldv < N) { set_error("kl_eigs: ldv < N"); return KL_EINVAL; }
+    if (opts->precision < KL_F64 || opts->precision > KL_F32) {
+        set_error("kl_eigs: unsupported precision");
+        return KL_EINVAL;
+    }
+    if (nvec0 < 0 || (nvec0 > 0 && !x0)) { set_error("kl_eigs: bad start block"); return KL_EINVAL; }
+    Solver S;
+    S.P = P;
+    S.N = N;
+    S.k = opts->k;
+    S.b = opts->block > 0 ? opts->block : 32;
+    if (S.b > kBW * 8) { set_error("kl_eigs: block too large"); return KL_EINVAL; }
+    const double tol = opts->tol > 0 ? opts->tol : 1e-6;
+    const double floor_rel = opts->abs_floor > 0 ? opts->abs_floor : 1e-12;
+    const int guard = opts->guard > 0 ? opts->guard : default_guard(S.k, S.b);
+    S.keep = S.k + guard;
+    S.mmax = opts->max_basis > 0 ? opts->max_basis : S.keep + 3 * S.b;
+    if (S.mmax < S.keep + S.b) S.mmax = S.keep + S.b;
+    if (S.mmax > N) S.mmax = int(N);
+    if (S.b > S.mmax) S.b = S.mmax;
+    if (S.keep > S.mmax - S.b) S.keep = std::max(S.k, S.mmax - S.b);
+    if (S.keep > S.mmax) S.keep = S.mmax;
+    const int max_applies = opts->max_applies > 0 ? opts->max_applies : int(std::min<int64_t>(
+        int64_t(400) * S.b + 20 * S.k, 4000000));
+    int precision = opts->precision;
+    const bool refine = precision != KL_F64 && opts->refine_fp64 != 0;
+    // low-precision floor: relative accuracy the low-precision apply can certify
+    const double lo_floor = precision == KL_F32 ? 2e-6 : 0.0;
+
+    kl_status st = KL_OK;
+    auto cleanup = [&]() {
+        hipFree(S.V); hipFree(S.AV); hipFree(S.Vt); hipFree(S.AVt); hipFree(S.W);
+        hipFree(S.C); hipFree(S.dtheta); hipFree(S.dnorm); hipFree(S.dflag);
+        if (S.blas) rocblas_destroy_handle(S.blas);
+        if (S.s) hipStreamDestroy(S.s);
+    };
+#define EIG_TRY(expr) do { if ((st = (expr)) != KL_OK) { cleanup(); return st; } } while (0)
+    EIG_TRY(S.check(hipStreamCreate(&S.s), "stream"));
+    EIG_TRY(S.bcheck(rocblas_create_handle(&S.blas), "create handle"));
+    EIG_TRY(S.bcheck(rocblas_set_stream(S.blas, S.s), "set stream"));
+    const size_t nb = size_t(N) * S.mmax * sizeof(double);
+    const int cmax = std::max(S.mmax, S.keep + S.b);
+    EIG_TRY(S.check(hipMalloc(&S.V, nb), "alloc V"));
+    EIG_TRY(S.check(hipMalloc(&S.AV, nb), "alloc AV"));
+    EIG_TRY(S.check(hipMalloc(&S.Vt, nb), "alloc Vt"));
+    EIG_TRY(S.check(hipMalloc(&S.AVt, nb), "alloc AVt"));
+    EIG_TRY(S.check(hipMalloc(&S.W, size_t(N) * cmax * sizeof(double)), "alloc W"));
+    EIG_TRY(S.check(hipMalloc(&S.C, size_t(cmax) * cmax * sizeof(double)), "alloc C"));
+    EIG_TRY(S.check(hipMalloc(&S.dtheta, size_t(S.mmax) * 8), "alloc theta"));
+    EIG_TRY(S.check(hipMalloc(&S.dnorm, size_t(S.mmax) * 8), "alloc norms"));
+    EIG_TRY(S.check(hipMalloc(&S.dflag, sizeof(int)), "alloc flag"));
+    S.H.assign(size_t(S.mmax) * S.mmax, 0.0);
+    std::mt19937_64 rng(opts->seed);
+
+    // ---- start block ------------------------------------------------------------------
+    {
+        const int b0 = S.b;
+        const int from_x0 = std::min<int>(nvec0, b0);
+        if (from_x0 > 0) {
+            EIG_TRY(S.check(hipMemcpy2DAsync(S.W, size_t(N) * 8, x0, size_t(N) * 8, size_t(N) * 8, from_x0,
+                                             hipMemcpyDeviceToDevice, S.s), "copy x0"));
+            EIG_TRY(S.check(hipMemsetAsync(S.dflag, 0, sizeof(int), S.s), "memset"));
+            hipLaunchKernelGGL(finite_kernel, dim3(256), dim3(kT), 0, S.s, S.W, int64_t(N) * from_x0, S.dflag);
+            int flag = 0;
+            EIG_TRY(S.check(hipMemcpyAsync(&flag, S.dflag, sizeof(int), hipMemcpyDeviceToHost, S.s), "flag"));
+            EIG_TRY(S.check(hipStreamSynchronize(S.s), "sync"));
+            if (flag) { cleanup(); set_error("kl_eigs: non-finite start block"); return KL_ENUMERIC; }
+        }
+        if (from_x0 < b0) {
+            std::normal_distribution<double> nd;
+            std::vector<double> r(size_t(N) * (b0 - from_x0));
+            for (double &v : r) v = nd(rng);
+            EIG_TRY(S.check(hipMemcpy(S.W + int64_t(from_x0) * N, r.data(), r.size() * 8, hipMemcpyHostToDevice),
+                            "copy random start"));
+        }
+        S.m = 0;
+        EIG_TRY(S.orth_into_basis(S.W, b0, b0, rng));
+        EIG_TRY(S.apply(precision, S.V, S.AV, b0));
+        S.m = b0;
+        S.last = b0;
+        EIG_TRY(S.update_H(0, b0));
+    }
+
+    std::vector<double> theta, Sm, norms;
+    double best_lo = INFINITY;
+    int stall = 0;
+    int converged = 0;
+    double max_rel = INFINITY;
+    bool done = false;
+    int total_applies = 0;
+    while (!done) {
+        total_applies = S.applies[0] + S.applies[1] + S.applies[2] + S.applies[3];
+        const bool must_restart = S.m + S.b > S.mmax;
+        // ---- Rayleigh-Ritz on the current basis --------------------------------------
+        const int m = S.m;
+        std::vector<double> Hm(size_t(m) * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) Hm[size_t(i) * m + j] = S.H[size_t(i) * S.mmax + j];
+        theta.assign(m, 0.0);
+        Sm.assign(size_t(m) * m, 0.0);
+        if (!sym_eig(m, Hm.data(), theta.data(), Sm.data())) {
+            cleanup();
+            set_error("kl_eigs: projected eigenproblem did not converge");
+            return KL_ENUMERIC;
+        }
+        for (double t : theta)
+            if (!std::isfinite(t)) { cleanup(); set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
+        const int kk = std::min(S.keep, m);
+        // X = V S[:, :kk] -> Vt,  AX = AV S[:, :kk] -> AVt
+        EIG_TRY(S.check(hipMemcpyAsync(S.C, Sm.data(), size_t(m) * kk * 8, hipMemcpyHostToDevice, S.s), "copy S"));
+        EIG_TRY(S.gemm_nn(S.V, m, S.C, m, kk, 1.0, 0.0, S.Vt));
+        EIG_TRY(S.gemm_nn(S.AV, m, S.C, m, kk, 1.0, 0.0, S.AVt));
+        EIG_TRY(S.check(hipMemcpyAsync(S.dtheta, theta.data(), size_t(kk) * 8, hipMemcpyHostToDevice, S.s), "copy theta"));
+        hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.Vt, S.AVt, S.dtheta, N, N, S.W, S.dnorm);
+        norms.assign(kk, 0.0);
+        EIG_TRY(S.check(hipMemcpyAsync(norms.data(), S.dnorm, size_t(kk) * 8, hipMemcpyDeviceToHost, S.s), "copy norms"));
+        EIG_TRY(S.check(hipStreamSynchronize(S.s), "sync"));
+        const double t1 = std::fabs(theta[0]);
+        converged = 0;
+        max_rel = 0.0;
+        bool lo_ok = true;
+        const int kc = std::min(S.k, kk);
+        for (int i = 0; i < kc; ++i) {
+            const double target = std::max(tol * std::fabs(theta[i]), floor_rel * t1);
+            if (norms[i] <= target) ++converged;
+            max_rel = std::max(max_rel, norms[i] / std::max(std::fabs(theta[i]), 1e-300));
+            if (norms[i] > std::max(target, lo_floor * t1)) lo_ok = false;
+        }
+        const bool all = converged == kc && kc == S.k;
+        // stagnation of the low-precision phase: no halving of the largest relative
+        // residual over three Rayleigh-Ritz steps
+        if (precision != KL_F64) {
+            if (max_rel < 0.5 * best_lo) { best_lo = max_rel; stall = 0; }
+            else if (++stall >= 3) lo_ok = true;
+        }
+        if (precision == KL_F64 || !refine) {
+            if (all || S.m >= N) { done = true; break; }
+        } else if (lo_ok || S.m >= N) {
+            // ---- switch to FP64: recompute AV of the kept Ritz basis ----------------
+            precision = KL_F64;
+            std::swap(S.V, S.Vt);
+            S.m = kk;
+            EIG_TRY(S.apply(KL_F64, S.V, S.AV, kk));
+            std::fill(S.H.begin(), S.H.end(), 0.0);
+            EIG_TRY(S.update_H(0, kk));
+            S.last = kk;
+            S.restarts += 1;
+            // expand from the residual directions of the FP64 operator
+            hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.V, S.AV, S.dtheta, N, N, S.W, S.dnorm);
+            const int add = std::min<int64_t>(S.b, N - S.m);
+            if (add > 0) {
+                EIG_TRY(S.orth_into_basis(S.W, kk, add, rng));
+                EIG_TRY(S.apply(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add));
+                EIG_TRY(S.update_H(S.m, S.m + add));
+                S.m += add;
+                S.last = add;
+            }
+            continue;
+        }
+        if (total_applies >= max_applies) break;
+        if (must_restart) {
+            // ---- thick restart -------------------------------------------------------
+            std::swap(S.V, S.Vt);
+            std::swap(S.AV, S.AVt);
+            S.m = kk;
+            std::fill(S.H.begin(), S.H.end(), 0.0);
+            for (int i = 0; i < kk; ++i) S.H[size_t(i) * S.mmax + i] = theta[i];
+            S.restarts += 1;
+            // residuals of the kept vectors are in W (residual_kernel above)
+            const int add = std::min<int64_t>(S.b, N - S.m);
+            if (add <= 0) { done = true; break; }
+            EIG_TRY(S.orth_into_basis(S.W, kk, add, rng));
+        } else {
+            // ---- block Krylov expansion from the newest block of AV --------------------
+            const int add = std::min<int64_t>(S.b, N - S.m);
+            if (add <= 0) { done = true; break; }
+            EIG_TRY(S.check(hipMemcpyAsync(S.W, S.AV + int64_t(S.m - S.last) * N, size_t(N) * S.last * 8,
+                                           hipMemcpyDeviceToDevice, S.s), "copy block"));
+            EIG_TRY(S.orth_into_basis(S.W, S.last, add, rng));
+        }
+        const int add = std::min<int64_t>(S.b, N - S.m);
+        EIG_TRY(S.apply(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add));
+        EIG_TRY(S.update_H(S.m, S.m + add));
+        S.m += add;
+        S.last = add;
+    }
+    // ---- outputs: Ritz pairs from the last Rayleigh-Ritz (held in Vt / theta) ------------
+    const int kout = std::min<int>(S.k, int(theta.size()));
+    for (int i = 0; i < S.k; ++i) evals[i] = i < kout ? theta[i] : 0.0;
+    launch_copy_cols(S.Vt, N, evecs, ldv, N, kout, S.s);
+    EIG_TRY(S.check(hipStreamSynchronize(S.s), "sync"));
+    if (rep) {
+        for (int p = 0; p < 4; ++p) {
+            rep->n_applies[p] = S.applies[p];
+            rep->n_block_applies[p] = S.block_applies[p];
+        }
+        rep->n_restarts = S.restarts;
+        rep->converged = converged;
+        rep->t_solve = std::chrono::duration<double>(clock::now() - t0).count();
+        rep->max_rel_residual = max_rel;
+    }
+    cleanup();
+#undef EIG_TRY
+    if (converged < S.k) {
+        std::ostringstream os;
+        os << "kl_eigs: " << converged << " of " << S.k << " pairs converged within " << max_applies
+           << " applies";
+        set_error(os.str());
+        return KL_ENOCONV;
+    }
+    return KL_OK;
 }

@@ -63,6 +63,13 @@ struct kl_problem {
     kl::Workspace ws;
     int n_cu = 256;
     bool host_only = false;   // built by kl_setup_host: no device data
+    // optional stage-5 timing with HIP events (kl_profile_enable / kl_profile_read)
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;      // pool: 2 events per timed launch
+    std::vector<int> prof_prec;           // precision of each recorded launch
+    size_t prof_used = 0;
+    int64_t prof_count[4] = {0, 0, 0, 0};
+    double prof_ms[4] = {0, 0, 0, 0};
 };
 
 namespace kl {
