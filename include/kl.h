@@ -145,6 +145,7 @@ typedef struct {
     int32_t n_restarts;
     int32_t converged;      /* number of leading pairs meeting the criterion */
     double  t_solve;        /* seconds, wall clock */
+    double  t_host_eig;     /* seconds spent in host dense eigensolves (Rayleigh-Ritz) */
     double  max_rel_residual;   /* max_i ||A~' x_i - theta_i x_i|| / theta_i over i <= k */
 } kl_eigs_report;
 

@@ -51,7 +51,8 @@ class KLEigsOpts(ctypes.Structure):
 class KLEigsReport(ctypes.Structure):
     _fields_ = [("n_applies", ctypes.c_int32 * 4), ("n_block_applies", ctypes.c_int32 * 4),
                 ("n_restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("t_solve", ctypes.c_double), ("max_rel_residual", ctypes.c_double)]
+                ("t_solve", ctypes.c_double), ("t_host_eig", ctypes.c_double),
+                ("max_rel_residual", ctypes.c_double)]
 
 
 _lib = None
@@ -244,7 +245,7 @@ def symeig(A):
 def report_dict(rep, status=0):
     return {"status": STATUS_NAMES.get(status, status), "n_applies": list(rep.n_applies),
             "n_block_applies": list(rep.n_block_applies), "n_restarts": rep.n_restarts,
-            "converged": rep.converged, "t_solve": rep.t_solve,
+            "converged": rep.converged, "t_solve": rep.t_solve, "t_host_eig": rep.t_host_eig,
             "max_rel_residual": rep.max_rel_residual}
 
 

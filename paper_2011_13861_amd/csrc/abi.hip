@@ -43,7 +43,9 @@ void free_problem(kl_problem *P) {
     }
     hipFree(P->ws.T0);
     hipFree(P->ws.T1);
-    hipFree(P->ws.Y5);
+    hipFree(P->ws.Y5d);
+    hipFree(P->ws.Y5f);
+    hipFree(P->ws.Y5b);
     hipFree(P->ws.Z5);
     delete P;
 }
@@ -73,15 +75,23 @@ int64_t max_intermediate(const HostSetup &hs) {
     return best;
 }
 
-bool valid_precision(int precision) { return precision == KL_F64 || precision == KL_F32; }
+bool valid_precision(int precision) { return precision >= KL_F64 && precision <= KL_BF16X3; }
+
+void *stage5_input(kl_problem *P, int precision) {
+    switch (precision) {
+    case KL_F64: return P->ws.Y5d;
+    case KL_F32: return P->ws.Y5f;
+    default: return P->ws.Y5b;
+    }
+}
 
 }  // namespace
 
 // Stage-5 launch, bracketed by HIP events on the launch stream while profiling is on.
-int timed_stage5(kl_problem *P, int precision, hipStream_t s) {
+int timed_stage5(kl_problem *P, int precision, const void *Y5, hipStream_t s) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
     if (rec) hipEventRecord(P->prof_ev[P->prof_used], s);
-    const int nsplit = launch_stage5(P, precision, P->ws.Y5, P->ws.Z5, s);
+    const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, s);
     if (rec) {
         hipEventRecord(P->prof_ev[P->prof_used + 1], s);
         P->prof_prec.push_back(precision);
@@ -91,43 +101,83 @@ int timed_stage5(kl_problem *P, int precision, hipStream_t s) {
 }
 
 // One chunk (<= kBW columns) of Algorithm 1: x (N x nb, ld ldx) -> y (N x nb, ld ldy).
+// 2d + 1 launches: d forward directions (the last one applies J and writes the stage-5
+// input), stage 5, d backward directions (the first one adds the split partials and
+// applies sigma^2 J).
 kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx,
                       double *y, int64_t ldy, hipStream_t s) {
     const HostSetup &hs = P->hs;
+    const int d = hs.d;
     double *T0 = P->ws.T0, *T1 = P->ws.T1;
-    const double *cur = x;
-    if (ldx != hs.N) {
-        launch_copy_cols(x, ldx, T0, hs.N, hs.N, nb, s);
-        cur = T0;
-    }
-    // stages 1-3 composed: C_k along each direction
+    const bool lo = precision != KL_F64;
+    void *Y5 = stage5_input(P, precision);
+    // ---- stages 1-4: C_k along each direction, J on the way out ----------------------
+    const void *cur = x;
+    int64_t cur_ld = ldx;
     int64_t A = 1;
-    for (int k = 0; k < hs.d; ++k) {
-        int64_t Cn = nb;
-        for (int j = k + 1; j < hs.d; ++j) Cn *= hs.n[j];
-        double *out = (cur == T0) ? T1 : T0;
-        launch_mode_contract(P->dC[k], cur, out, A, hs.n[k], hs.nt[k], Cn, s);
+    for (int k = 0; k < d; ++k) {
+        ModeSpec m;
+        m.D = P->dC[k];
+        m.in = cur;
+        m.in_ldj = cur_ld;
+        m.A = A;
+        m.nin = hs.n[k];
+        m.nout = hs.nt[k];
+        m.Clo = 1;
+        for (int j = k + 1; j < d; ++j) m.Clo *= hs.n[j];
+        m.nvec = nb;
+        if (k == d - 1) {
+            m.out = Y5;
+            m.out_ldj = P->Ntpad;
+            m.out_w = P->dJ;
+            m.out_f32 = precision == KL_F32;
+            m.out_bf16 = precision == KL_BF16 || precision == KL_BF16X3;
+            if (precision == KL_BF16X3) m.out_lo = static_cast<__bf16 *>(Y5) + P->Ntpad * kBW;
+        } else {
+            m.out = (cur == T0) ? T1 : T0;
+            m.out_ldj = A * hs.nt[k] * m.Clo;
+        }
+        launch_mode(m, s);
         A *= hs.nt[k];
-        cur = out;
+        cur = m.out;
+        cur_ld = m.out_ldj;
     }
-    // stage 4 + layout change, stage 5, stage 6 (sigma^2 J) + split reduction
-    launch_to_stage5(precision, cur, hs.Nt, hs.Nt, nb, P->dJ, P->Ntpad, P->ws.Y5, s);
-    const int nsplit = timed_stage5(P, precision, s);
-    double *zbuf = (cur == T0) ? T1 : T0;
-    launch_from_stage5(precision, P->ws.Z5, nsplit, P->Ntpad, hs.Nt, nb, P->dJ, P->sigma2, zbuf,
-                       hs.Nt, s);
-    cur = zbuf;
-    // stages 7-9 composed: C_k^T along each direction
+    // ---- stage 5 ----------------------------------------------------------------------
+    const int nsplit = timed_stage5(P, precision, Y5, s);
+    // ---- stages 6-9: sigma^2 J and the split sum on the way in, C_k^T per direction ----
+    cur = P->ws.Z5;
+    cur_ld = P->Ntpad;
     A = 1;
-    for (int k = 0; k < hs.d; ++k) {
-        int64_t Cn = nb;
-        for (int j = k + 1; j < hs.d; ++j) Cn *= hs.nt[j];
-        double *out = (k == hs.d - 1 && ldy == hs.N) ? y : ((cur == T0) ? T1 : T0);
-        launch_mode_contract(P->dCT[k], cur, out, A, hs.nt[k], hs.n[k], Cn, s);
+    for (int k = 0; k < d; ++k) {
+        ModeSpec m;
+        m.D = P->dCT[k];
+        m.in = cur;
+        m.in_ldj = cur_ld;
+        m.A = A;
+        m.nin = hs.nt[k];
+        m.nout = hs.n[k];
+        m.Clo = 1;
+        for (int j = k + 1; j < d; ++j) m.Clo *= hs.nt[j];
+        m.nvec = nb;
+        if (k == 0) {
+            m.nsplit = nsplit;
+            m.in_split = P->Ntpad * kBW;
+            m.in_w = P->dJ;
+            m.in_scale = P->sigma2;
+            m.in_f32 = lo;
+        }
+        if (k == d - 1) {
+            m.out = y;
+            m.out_ldj = ldy;
+        } else {
+            m.out = (cur == T0) ? T1 : T0;
+            m.out_ldj = A * hs.n[k] * m.Clo;
+        }
+        launch_mode(m, s);
         A *= hs.n[k];
-        cur = out;
+        cur = m.out;
+        cur_ld = m.out_ldj;
     }
-    if (cur != y) launch_copy_cols(cur, hs.N, y, ldy, hs.N, nb, s);
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
@@ -155,6 +205,12 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
     kl_status st = build_host_setup(*desc, P->hs);
     if (st != KL_OK) { delete P; return st; }
     const HostSetup &hs = P->hs;
+    for (int k = 0; k < hs.d; ++k)
+        if (!mode_fits(hs.n[k]) || !mode_fits(hs.nt[k])) {
+            delete P;
+            set_error("kl_setup: more than 199 basis functions in one direction are not supported");
+            return KL_EINVAL;
+        }
     P->cov_kind = desc->cov_kind;
     P->sigma2 = desc->sigma2;
     for (int k = 0; k < 3; ++k) P->ell[k] = k < hs.d ? desc->corr_len[k] : 1.0;
@@ -206,7 +262,13 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
     }
     KL_TRY(dev_alloc(&P->ws.T0, P->ws.t_elems, "hipMalloc T0"));
     KL_TRY(dev_alloc(&P->ws.T1, P->ws.t_elems, "hipMalloc T1"));
-    KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5), P->ws.y5_bytes, "hipMalloc Y5"));
+    KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5d), P->ws.y5_bytes, "hipMalloc Y5"));
+    KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5f), P->ws.y5_bytes / 2, "hipMalloc Y5"));
+    // the padding rows of the stage-5 input are never written and must stay zero
+    KL_TRY(hip_check(hipMemset(P->ws.Y5d, 0, P->ws.y5_bytes), "memset Y5"));
+    KL_TRY(hip_check(hipMemset(P->ws.Y5f, 0, P->ws.y5_bytes / 2), "memset Y5"));
+    KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5b), P->ws.y5_bytes / 2, "hipMalloc Y5"));
+    KL_TRY(hip_check(hipMemset(P->ws.Y5b, 0, P->ws.y5_bytes / 2), "memset Y5"));
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Z5), P->ws.z5_bytes, "hipMalloc Z5"));
 #undef KL_TRY
     *out = P;
@@ -257,11 +319,11 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec, const double
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int c0 = 0; c0 < nvec; c0 += kBW) {
         const int nb = std::min(kBW, nvec - c0);
-        launch_to_stage5(precision, y + int64_t(c0) * ldy, P->hs.Nt, ldy, nb, nullptr, P->Ntpad,
-                         P->ws.Y5, s);
-        const int nsplit = timed_stage5(P, precision, s);
-        launch_from_stage5(precision, P->ws.Z5, nsplit, P->Ntpad, P->hs.Nt, nb, nullptr, P->sigma2,
-                           z + int64_t(c0) * ldz, ldz, s);
+        void *Y5 = stage5_input(P, precision);
+        launch_pack_stage5(precision, y + int64_t(c0) * ldy, ldy, P->hs.Nt, nb, P->Ntpad, Y5, s);
+        const int nsplit = timed_stage5(P, precision, Y5, s);
+        launch_unpack_stage5(precision, P->ws.Z5, nsplit, P->Ntpad, P->hs.Nt, nb, P->sigma2,
+                             z + int64_t(c0) * ldz, ldz, s);
         kl_status st = hip_check(hipGetLastError(), "kernel launch");
         if (st != KL_OK) return st;
     }

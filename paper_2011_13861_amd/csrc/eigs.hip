@@ -74,7 +74,7 @@ struct Solver {
     int64_t N = 0;
     int b = 32, k = 1, keep = 1, mmax = 1;
     double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
-    double *C = nullptr, *dtheta = nullptr, *dnorm = nullptr;
+    double *C = nullptr, *dtheta = nullptr, *dnorm = nullptr, *part = nullptr;
     int *dflag = nullptr;
     std::vector<double> H;      // mmax x mmax, row-major, host
     int m = 0;                  // current basis size
@@ -95,11 +95,11 @@ struct Solver {
         set_error(os.str());
         return KL_EHIP;
     }
-    // C = A^T B   (A: N x ma, B: N x nb, ld N) -> C (ma x nb, ld ma), device
+    // C = A^T B   (A: N x ma, B: N x nb, ld N) -> C (ma x nb, ld ma), device; split-N
+    // Gram kernel (tall-skinny shapes)
     kl_status gemm_tn(const double *A, int ma, const double *B, int nb, double *Cout) {
-        const double one = 1.0, zero = 0.0;
-        return bcheck(rocblas_dgemm(blas, rocblas_operation_transpose, rocblas_operation_none, ma, nb,
-                                    int(N), &one, A, int(N), B, int(N), &zero, Cout, ma), "dgemm TN");
+        launch_gram(A, N, ma, B, N, nb, N, part, Cout, P->n_cu, s);
+        return check(hipGetLastError(), "gram kernel");
     }
     // Out = alpha A S + beta Out   (A: N x ma, S: ma x nb with ld lds)
     kl_status gemm_nn(const double *A, int ma, const double *S, int lds, int nb, double alpha,
@@ -235,7 +235,7 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
     const int64_t N = P->hs.N;
     if (opts->k < 1 || opts->k > N) { set_error("kl_eigs: k must be in 1..N"); return KL_EINVAL; }
     if (ldv < N) { set_error("kl_eigs: ldv < N"); return KL_EINVAL; }
-    if (opts->precision < KL_F64 || opts->precision > KL_F32) {
+    if (opts->precision < KL_F64 || opts->precision > KL_BF16X3) {
         set_error("kl_eigs: unsupported precision");
         return KL_EINVAL;
     }
@@ -261,12 +261,13 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
     int precision = opts->precision;
     const bool refine = precision != KL_F64 && opts->refine_fp64 != 0;
     // low-precision floor: relative accuracy the low-precision apply can certify
-    const double lo_floor = precision == KL_F32 ? 2e-6 : 0.0;
+    const double lo_floor = precision == KL_F32 ? 2e-6
+                            : precision == KL_BF16X3 ? 5e-5 : precision == KL_BF16 ? 5e-3 : 0.0;
 
     kl_status st = KL_OK;
     auto cleanup = [&]() {
         hipFree(S.V); hipFree(S.AV); hipFree(S.Vt); hipFree(S.AVt); hipFree(S.W);
-        hipFree(S.C); hipFree(S.dtheta); hipFree(S.dnorm); hipFree(S.dflag);
+        hipFree(S.C); hipFree(S.part); hipFree(S.dtheta); hipFree(S.dnorm); hipFree(S.dflag);
         if (S.blas) rocblas_destroy_handle(S.blas);
         if (S.s) hipStreamDestroy(S.s);
     };
@@ -282,6 +283,11 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
     EIG_TRY(S.check(hipMalloc(&S.AVt, nb), "alloc AVt"));
     EIG_TRY(S.check(hipMalloc(&S.W, size_t(N) * cmax * sizeof(double)), "alloc W"));
     EIG_TRY(S.check(hipMalloc(&S.C, size_t(cmax) * cmax * sizeof(double)), "alloc C"));
+    {
+        // split partials of the Gram kernel: 64 row ranges of a cmax x cmax product
+        const size_t need = size_t(64) * cmax * cmax;
+        EIG_TRY(S.check(hipMalloc(&S.part, need * sizeof(double)), "alloc gram partials"));
+    }
     EIG_TRY(S.check(hipMalloc(&S.dtheta, size_t(S.mmax) * 8), "alloc theta"));
     EIG_TRY(S.check(hipMalloc(&S.dnorm, size_t(S.mmax) * 8), "alloc norms"));
     EIG_TRY(S.check(hipMalloc(&S.dflag, sizeof(int)), "alloc flag"));
@@ -319,6 +325,7 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
 
     std::vector<double> theta, Sm, norms;
     double best_lo = INFINITY;
+    double t_host_eig = 0.0;
     int stall = 0;
     int converged = 0;
     double max_rel = INFINITY;
@@ -334,7 +341,10 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
             for (int j = 0; j < m; ++j) Hm[size_t(i) * m + j] = S.H[size_t(i) * S.mmax + j];
         theta.assign(m, 0.0);
         Sm.assign(size_t(m) * m, 0.0);
-        if (!sym_eig(m, Hm.data(), theta.data(), Sm.data())) {
+        const auto te0 = clock::now();
+        const bool eig_ok = sym_eig(m, Hm.data(), theta.data(), Sm.data());
+        t_host_eig += std::chrono::duration<double>(clock::now() - te0).count();
+        if (!eig_ok) {
             cleanup();
             set_error("kl_eigs: projected eigenproblem did not converge");
             return KL_ENUMERIC;
@@ -433,6 +443,7 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
         rep->n_restarts = S.restarts;
         rep->converged = converged;
         rep->t_solve = std::chrono::duration<double>(clock::now() - t0).count();
+        rep->t_host_eig = t_host_eig;
         rep->max_rel_residual = max_rel;
     }
     cleanup();

@@ -1,4 +1,5 @@
 // Stage 5 of Algorithm 1 on MFMA: Z'_k = sum_l Gamma(x_k, x_l) Y'_l.
+// Y and the split partials Z are column-major blocks of kBW columns, ld = padded grid.
 //
 // Sec. 4.4.2: the dense Ntilde x Ntilde covariance matrix is never stored; its entries
 // are evaluated on the fly and contracted with the block of vectors.  Here the
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
     const float *__restrict__ X, const float *__restrict__ Y, float *__restrict__ Z,
     int64_t Ntpad, int64_t lchunk) {
     __shared__ float sX[D][kTL32];
-    __shared__ float sY[kTL32][kBW];
+    __shared__ float sY[kTL32][kBW + 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 31, kh = lane >> 5;
     const int64_t row0 = int64_t(blockIdx.x) * (kWaves * 32 * RB) + int64_t(wave) * 32 * RB;
@@ -106,16 +107,16 @@ __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
 
     for (int64_t lt = l0; lt < l1; lt += kTL32) {
         __syncthreads();
-        {
-            const float4 *src = reinterpret_cast<const float4 *>(Y + lt * kBW);
-            float4 *dst = reinterpret_cast<float4 *>(&sY[0][0]);
+        // Y is column-major (ld Ntpad): coalesced along l, transposed into LDS
 #pragma unroll
-            for (int q = 0; q < (kTL32 * kBW / 4) / kThreads; ++q)
-                dst[threadIdx.x + q * kThreads] = src[threadIdx.x + q * kThreads];
-            if (threadIdx.x < D * kTL32) {
-                const int k = threadIdx.x / kTL32, l = threadIdx.x % kTL32;
-                sX[k][l] = X[k * Ntpad + lt + l];
-            }
+        for (int q = 0; q < (kTL32 * kBW) / kThreads; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int l = e % kTL32, j = e / kTL32;
+            sY[l][j] = Y[int64_t(j) * Ntpad + lt + l];
+        }
+        if (threadIdx.x < D * kTL32) {
+            const int k = threadIdx.x / kTL32, l = threadIdx.x % kTL32;
+            sX[k][l] = X[k * Ntpad + lt + l];
         }
         __syncthreads();
 #pragma unroll 8
@@ -131,13 +132,16 @@ __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
             }
         }
     }
-    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
+    // Z is column-major (ld Ntpad); accumulator registers 4m..4m+3 of a lane hold four
+    // consecutive rows of one column, stored as one 16-byte vector
+    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW + int64_t(i) * Ntpad;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t row = row0 + rb * 32 + (r & 3) + 4 * kh + 8 * (r >> 2);
-            Zs[row * kBW + i] = acc[rb][r];
+        for (int m = 0; m < 4; ++m) {
+            const int64_t row = row0 + rb * 32 + 4 * kh + 8 * m;
+            float4 v = {acc[rb][4 * m], acc[rb][4 * m + 1], acc[rb][4 * m + 2], acc[rb][4 * m + 3]};
+            *reinterpret_cast<float4 *>(Zs + row) = v;
         }
 }
 
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
     const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ Z,
     int64_t Ntpad, int64_t lchunk) {
     __shared__ double sX[D][kTL64];
-    __shared__ double sY[kTL64][kBW];
+    __shared__ double sY[kTL64][kBW + 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 15, kq = lane >> 4;
     const int64_t row0 = int64_t(blockIdx.x) * (kWaves * 16 * RB) + int64_t(wave) * 16 * RB;
@@ -171,16 +175,15 @@ __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
 
     for (int64_t lt = l0; lt < l1; lt += kTL64) {
         __syncthreads();
-        {
-            const double2 *src = reinterpret_cast<const double2 *>(Y + lt * kBW);
-            double2 *dst = reinterpret_cast<double2 *>(&sY[0][0]);
 #pragma unroll
-            for (int q = 0; q < (kTL64 * kBW / 2) / kThreads; ++q)
-                dst[threadIdx.x + q * kThreads] = src[threadIdx.x + q * kThreads];
-            if (threadIdx.x < D * kTL64) {
-                const int k = threadIdx.x / kTL64, l = threadIdx.x % kTL64;
-                sX[k][l] = X[k * Ntpad + lt + l];
-            }
+        for (int q = 0; q < (kTL64 * kBW) / kThreads; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int l = e % kTL64, j = e / kTL64;
+            sY[l][j] = Y[int64_t(j) * Ntpad + lt + l];
+        }
+        if (threadIdx.x < D * kTL64) {
+            const int k = threadIdx.x / kTL64, l = threadIdx.x % kTL64;
+            sX[k][l] = X[k * Ntpad + lt + l];
         }
         __syncthreads();
 #pragma unroll 2
@@ -198,14 +201,105 @@ __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
             }
         }
     }
+    // Z is column-major (ld Ntpad): for each register, lanes with the same column
+    // write four consecutive rows
     double *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t row = row0 + rb * 16 + kq + 4 * r;
-            Zs[row * kBW + i] = acc[rb][0][r];
-            Zs[row * kBW + 16 + i] = acc[rb][1][r];
+            Zs[int64_t(i) * Ntpad + row] = acc[rb][0][r];
+            Zs[int64_t(16 + i) * Ntpad + row] = acc[rb][1][r];
+        }
+}
+
+
+// ---- BF16: v_mfma_f32_32x32x16_bf16; A = Gamma[32 rows][16 l], B = Y[16 l][32 cols] ---
+// Lane layout (measured on gfx950): A[i][k] in lane i + 32 (k / 8), element k % 8;
+// B[k][j] in lane j + 32 (k / 8), element k % 8; accumulators as for the FP32 32x32x2.
+// The kernel is evaluated in FP32 and rounded to BF16 (round to nearest even).  With
+// X3 both operands are split into hi + lo BF16 parts and three products are
+// accumulated (hi hi + hi lo + lo hi), about 16 significant bits per operand.
+constexpr int kTLB = 64;   // l-points per LDS tile (4 MFMA k-steps)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int KIND, int D, int RB, bool X3>
+__global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
+    const float *__restrict__ X, const __bf16 *__restrict__ Yh, const __bf16 *__restrict__ Yl,
+    float *__restrict__ Z, int64_t Ntpad, int64_t lchunk) {
+    __shared__ float sX[D][kTLB];
+    __shared__ __attribute__((aligned(16))) __bf16 sYh[kBW][kTLB + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 sYl[X3 ? kBW : 1][kTLB + 8];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = lane & 31, kh = lane >> 5;
+    const int64_t row0 = int64_t(blockIdx.x) * (kWaves * 32 * RB) + int64_t(wave) * 32 * RB;
+    const int64_t l0 = int64_t(blockIdx.y) * lchunk;
+    const int64_t l1 = min(l0 + lchunk, Ntpad);
+    float xk[RB][D];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int k = 0; k < D; ++k) xk[rb][k] = X[k * Ntpad + row0 + rb * 32 + i];
+    floatx16 acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
+
+    for (int64_t lt = l0; lt < l1; lt += kTLB) {
+        __syncthreads();
+        // Y (column-major bf16, ld Ntpad): 8 consecutive l of one column per 16-byte load
+        {
+            const int j = threadIdx.x >> 3, seg = threadIdx.x & 7;   // 32 columns x 8 segments
+            const int4 vh = *reinterpret_cast<const int4 *>(Yh + int64_t(j) * Ntpad + lt + 8 * seg);
+            *reinterpret_cast<int4 *>(&sYh[j][8 * seg]) = vh;
+            if constexpr (X3) {
+                const int4 vl = *reinterpret_cast<const int4 *>(Yl + int64_t(j) * Ntpad + lt + 8 * seg);
+                *reinterpret_cast<int4 *>(&sYl[j][8 * seg]) = vl;
+            }
+        }
+        if (threadIdx.x < D * kTLB) {
+            const int k = threadIdx.x / kTLB, l = threadIdx.x % kTLB;
+            sX[k][l] = X[k * Ntpad + lt + l];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ll = 0; ll < kTLB; ll += 16) {
+            const int lb = ll + 8 * kh;
+            float xl[8][D];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+#pragma unroll
+                for (int k = 0; k < D; ++k) xl[e][k] = sX[k][lb + e];
+            const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sYh[i][lb]);
+            bf16x8 bl;
+            if constexpr (X3) bl = *reinterpret_cast<const bf16x8 *>(&sYl[i][lb]);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                bf16x8 ah, al;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float g = gamma_f32<KIND, D>(xk[rb], xl[e]);
+                    ah[e] = __bf16(g);
+                    if constexpr (X3) al[e] = __bf16(g - float(ah[e]));
+                }
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[rb], 0, 0, 0);
+                if constexpr (X3) {
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[rb], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW + int64_t(i) * Ntpad;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int64_t row = row0 + rb * 32 + 4 * kh + 8 * m;
+            float4 v = {acc[rb][4 * m], acc[rb][4 * m + 1], acc[rb][4 * m + 2], acc[rb][4 * m + 3]};
+            *reinterpret_cast<float4 *>(Zs + row) = v;
         }
 }
 
@@ -217,14 +311,25 @@ template <int KIND, int D>
 void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, int nsplit,
                  int64_t lchunk, hipStream_t s) {
     dim3 grid(unsigned(P->Ntpad / kRowsPerWG), unsigned(nsplit));
-    if (precision == KL_F64)
+    if (precision == KL_F64) {
         hipLaunchKernelGGL((stage5_f64_kernel<KIND, D, kRB64>), grid, dim3(kThreads), 0, s,
                            P->dX64, static_cast<const double *>(Y5), static_cast<double *>(Z5),
                            P->Ntpad, lchunk);
-    else
+    } else if (precision == KL_F32) {
         hipLaunchKernelGGL((stage5_f32_kernel<KIND, D, kRB32>), grid, dim3(kThreads), 0, s,
                            P->dX32, static_cast<const float *>(Y5), static_cast<float *>(Z5),
                            P->Ntpad, lchunk);
+    } else {
+        // BF16 operands: hi part at Y5, lo part right after it (Ntpad x kBW each)
+        const __bf16 *yh = static_cast<const __bf16 *>(Y5);
+        const __bf16 *yl = yh + P->Ntpad * kBW;
+        if (precision == KL_BF16)
+            hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, kRB32, false>), grid, dim3(kThreads), 0, s,
+                               P->dX32, yh, yl, static_cast<float *>(Z5), P->Ntpad, lchunk);
+        else
+            hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, kRB32, true>), grid, dim3(kThreads), 0, s,
+                               P->dX32, yh, yl, static_cast<float *>(Z5), P->Ntpad, lchunk);
+    }
 }
 
 template <int D>

@@ -39,7 +39,9 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs);
 struct Workspace {
     double *T0 = nullptr, *T1 = nullptr;   // FP64 Kronecker ping-pong buffers
     size_t t_elems = 0;                    // elements per buffer (max intermediate x kBW)
-    void *Y5 = nullptr;                    // stage-5 input block, kernel layout
+    void *Y5d = nullptr;                   // stage-5 input, FP64 (column-major, ld Ntpad)
+    void *Y5f = nullptr;                   // stage-5 input, FP32; padding rows stay zero
+    void *Y5b = nullptr;                   // stage-5 input, BF16 hi then lo part
     size_t y5_bytes = 0;
     void *Z5 = nullptr;                    // stage-5 split partial sums
     size_t z5_bytes = 0;
@@ -75,22 +77,43 @@ struct kl_problem {
 namespace kl {
 
 // ---- kernels (launch wrappers; all asynchronous on `s`) ---------------------------
-// Mode-k contraction on column-major FP64 tensors:
-//   out[a + A*(o + nout*c)] = sum_i D[o*nin + i] * in[a + A*(i + nin*c)],
-//   a < A, o < nout, c < Cn (Cn includes the column index).
-void launch_mode_contract(const double *D, const double *in, double *out, int64_t A, int nin,
-                          int nout, int64_t Cn, hipStream_t s);
-// Forward epilogue: Y5[p, j] = J[p] * T[p + ldt*j] in stage-5 precision and layout
-// (J may be NULL: no scaling), zero for p >= Nt or j >= nvec.
-void launch_to_stage5(int precision, const double *T, int64_t Nt, int64_t ldt, int nvec,
-                      const double *J, int64_t Ntpad, void *Y5, hipStream_t s);
-// Backward prologue: T[p + Nt*j] = scale * w[p] * sum_s Z5[s][p][j].
-void launch_from_stage5(int precision, const void *Z5, int nsplit, int64_t Ntpad, int64_t Nt,
-                        int nvec, const double *w, double scale, double *T, int64_t ldt,
-                        hipStream_t s);
-// Copies a strided column block (FP64) into / out of a packed one.
+// One direction of a Kronecker product (see kernels_kron.hip for the index layout):
+//   OUT[a + A(o + nout c) + out_ldj j] = out_w[p] * sum_i D[o][i] IN'[a + A(i + nin c)]
+//   IN'[q] = in_scale * in_w[q] * sum_{s < nsplit} in[q + in_ldj j + s in_split]
+struct ModeSpec {
+    const double *D = nullptr;      // nout x nin, row-major, FP64
+    const void *in = nullptr;
+    void *out = nullptr;
+    int64_t A = 1;
+    int nin = 1, nout = 1;
+    int64_t Clo = 1;
+    int nvec = 1;
+    int64_t in_ldj = 0, out_ldj = 0;
+    int nsplit = 1;
+    int64_t in_split = 0;
+    const double *in_w = nullptr;
+    double in_scale = 1.0;
+    const double *out_w = nullptr;
+    void *out_lo = nullptr;         // BF16 output: low parts (hi/lo split), or NULL
+    bool in_f32 = false, out_f32 = false, out_bf16 = false;
+};
+// true if a factor with nin columns fits the LDS-staged kernel
+bool mode_fits(int nin);
+void launch_mode(const ModeSpec &m, hipStream_t s);
+// Copies a strided column block (FP64).
 void launch_copy_cols(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
                       int cols, hipStream_t s);
+// Stage-5 input from an FP64 block (no scaling): Y5[j*Ntpad + p] = y[p + ldy j], p < Nt.
+void launch_pack_stage5(int precision, const double *y, int64_t ldy, int64_t Nt, int nvec,
+                        int64_t Ntpad, void *Y5, hipStream_t s);
+// Stage-5 output to FP64: z[p + ldz j] = scale * sum_s Z5[s][j*Ntpad + p].
+void launch_unpack_stage5(int precision, const void *Z5, int nsplit, int64_t Ntpad, int64_t Nt,
+                          int nvec, double scale, double *z, int64_t ldz, hipStream_t s);
+// C (m x c, column-major, ld m) = A^T B for tall-skinny FP64 blocks; `part` holds
+// 64 * m * c doubles of row-range partials.
+int gram_splits(int64_t N, int m, int c, int n_cu);
+void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int c,
+                 int64_t N, double *part, double *C, int n_cu, hipStream_t s);
 
 // Number of l-splits of stage 5 for a padded grid; *lchunk receives the l-range length.
 int stage5_splits(int64_t Ntpad, int n_cu, int64_t *lchunk);

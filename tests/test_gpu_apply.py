@@ -3,7 +3,9 @@
 All calls go through the C ABI (kl_setup / kl_apply / kl_stage5).  Tolerances:
 FP64 path: relative max-norm error <= 1e-12 (rounding of FP64 kernels and sums);
 FP32 path: relative Frobenius error <= 2e-6 (FP32 kernel evaluation, FP32 MFMA
-accumulation of up to ~2e4 terms).
+accumulation of up to ~2e4 terms);
+BF16x3 path: <= 5e-5 (hi + lo BF16 split keeps about 16 bits of each operand);
+BF16 path: <= 5e-3 (8-bit significands of the kernel values and of the block).
 """
 
 import numpy as np
@@ -16,7 +18,8 @@ from oracle import cstage5, operator
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 2e-6}
+TOL = {"f64": 1e-12, "f32": 2e-6, "bf16x3": 5e-5, "bf16": 5e-3}
+PRECS = ["f64", "f32", "bf16x3", "bf16"]
 
 
 def _rel_max(a, b):
@@ -53,7 +56,7 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precision", PRECS)
 @pytest.mark.parametrize("name,desc", SMALL, ids=[s[0] for s in SMALL])
 def test_apply_matches_oracle(name, desc, precision):
     P = operator.Problem(desc)
@@ -65,7 +68,7 @@ def test_apply_matches_oracle(name, desc, precision):
     assert err <= TOL[precision], (name, precision, err)
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precision", PRECS)
 def test_stage5_alone_matches_oracle(precision):
     desc = workloads.quarter_annulus(20, 2, "exp", (0.3, 0.6))
     P = operator.Problem(desc)
@@ -107,7 +110,7 @@ def test_full_size_config2_apply():
     G = kl.Problem(desc)
     V = workloads.random_block(P.N, 32, seed=5)
     ref = P.apply(V, stage5=lambda Y: cstage5.stage5(P, Y))
-    for prec in ("f64", "f32"):
+    for prec in PRECS:
         out = _gpu_apply(G, V, prec)
         err = _rel_max(out, ref) if prec == "f64" else _rel_fro(out, ref)
         assert err <= TOL[prec], (prec, err)
@@ -122,7 +125,7 @@ def test_full_size_config3_stage5_sampled_rows():
     X, _ = G.points()
     Y = workloads.random_block(G.Nt, 32, seed=6)
     y = kl.to_device_block(Y)
-    for prec in ("f64", "f32"):
+    for prec in PRECS:
         z = kl.new_block(G.Nt, 32)
         G.stage5(y, z, prec)
         torch.cuda.synchronize()
