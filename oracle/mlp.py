@@ -1,0 +1,73 @@
+"""FP64 reference multilayer perceptron for the learned warm start (oracle).
+
+TEST INFRASTRUCTURE ONLY.  Not a paper construct: the warm-start network is an addition
+to the method (the paper starts its Lanczos iteration from a generic vector, Sec. 4.4.2).
+This module is the gradient oracle for the GPU training kernels:
+  forward   h_0 = x,  z_l = h_{l-1} W_l + b_l,  h_l = tanh(z_l) (hidden), output z_L
+  loss      0.5 / B * sum (z_L - T)^2    (mean over the batch, summed over outputs)
+  backward  the chain rule written out layer by layer
+  adam      Kingma and Ba (2015) with bias correction.
+Pinned by central differences (tests/test_oracle_mlp.py), which do not use the backward code.
+Weights W_l are (fan_in, fan_out) row-major, matching the library.
+"""
+
+import numpy as np
+
+
+def init_params(sizes, seed=0):
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and zero biases."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        bound = 1.0 / np.sqrt(fi)
+        params.append([rng.uniform(-bound, bound, size=(fi, fo)), np.zeros(fo)])
+    return params
+
+
+def forward(params, x):
+    """Returns the output and the list of layer activations needed by backward."""
+    hs = [np.asarray(x, dtype=np.float64)]
+    L = len(params)
+    for l, (W, b) in enumerate(params):
+        z = hs[-1] @ W + b
+        hs.append(np.tanh(z) if l < L - 1 else z)
+    return hs[-1], hs
+
+
+def loss(params, x, T):
+    y, _ = forward(params, x)
+    return 0.5 * np.sum((y - T) ** 2) / x.shape[0]
+
+
+def backward(params, x, T):
+    """Gradients [(dW_l, db_l)] of `loss` by the chain rule."""
+    y, hs = forward(params, x)
+    B = x.shape[0]
+    L = len(params)
+    grads = [None] * L
+    delta = (y - T) / B                          # dloss / dz_L
+    for l in range(L - 1, -1, -1):
+        W, _ = params[l]
+        grads[l] = [hs[l].T @ delta, delta.sum(axis=0)]
+        if l > 0:
+            delta = (delta @ W.T) * (1.0 - hs[l] ** 2)   # through tanh of layer l
+    return grads
+
+
+def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update in place; state = {"t": int, "m": [...], "v": [...]}."""
+    if not state:
+        state["t"] = 0
+        state["m"] = [[np.zeros_like(p) for p in layer] for layer in params]
+        state["v"] = [[np.zeros_like(p) for p in layer] for layer in params]
+    state["t"] += 1
+    t = state["t"]
+    for l, layer in enumerate(params):
+        for q in range(2):
+            g = grads[l][q]
+            m = state["m"][l][q] = beta1 * state["m"][l][q] + (1 - beta1) * g
+            v = state["v"][l][q] = beta2 * state["v"][l][q] + (1 - beta2) * g * g
+            mh = m / (1 - beta1 ** t)
+            vh = v / (1 - beta2 ** t)
+            layer[q] -= lr * mh / (np.sqrt(vh) + eps)
+    return params
