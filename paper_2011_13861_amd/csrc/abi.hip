@@ -118,6 +118,7 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
     for (int k = 0; k < d; ++k) {
         ModeSpec m;
         m.D = P->dC[k];
+        m.DT = P->dCT[k];
         m.in = cur;
         m.in_ldj = cur_ld;
         m.A = A;
@@ -151,6 +152,7 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
     for (int k = 0; k < d; ++k) {
         ModeSpec m;
         m.D = P->dCT[k];
+        m.DT = P->dC[k];
         m.in = cur;
         m.in_ldj = cur_ld;
         m.A = A;
@@ -206,9 +208,9 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
     if (st != KL_OK) { delete P; return st; }
     const HostSetup &hs = P->hs;
     for (int k = 0; k < hs.d; ++k)
-        if (!mode_fits(hs.n[k]) || !mode_fits(hs.nt[k])) {
+        if (!mode_fits(hs.n[k], hs.nt[k]) || !mode_fits(hs.nt[k], hs.n[k])) {
             delete P;
-            set_error("kl_setup: more than 199 basis functions in one direction are not supported");
+            set_error("kl_setup: more than 128 basis functions in one direction are not supported");
             return KL_EINVAL;
         }
     P->cov_kind = desc->cov_kind;

@@ -14,9 +14,9 @@
 //     sigma^2 J[p], in FP64.
 // The point index of an entry is its address without the vector term, p = a + A (i + nin c).
 //
-// A workgroup owns 32 consecutive rows and a range of o: it stages the 32 x nin input
-// slice and the factor rows D[o0:o0+oc][:] in LDS (loads coalesced along the contiguous
-// index) and each thread accumulates up to R outputs for one row.
+// A workgroup owns 32 consecutive rows and every o: it stages the 32 x nin input slice
+// and D^T in LDS (loads coalesced along the contiguous index), runs the contraction on
+// FP64 matrix cores and writes through LDS so that stores are coalesced too.
 #include <algorithm>
 #include <type_traits>
 
@@ -27,10 +27,11 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kRT = 32;                 // rows per workgroup
-constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kLdsBudget = 160 * 1024;   // gfx950: up to 160 KB per workgroup
 
 struct ModeArgs {
     const double *D;          // nout x nin row-major
+    const double *DT;         // nin x nout row-major (D transposed)
     const void *in;           // TIN
     void *out;                // TOUT
     int64_t A;                // product of the sizes before the direction (1 = first)
@@ -44,7 +45,6 @@ struct ModeArgs {
     double in_scale;
     const double *out_w;      // optional per-point output scale
     void *out_lo;             // BF16 output only: low part v - bf16(v), or NULL
-    int oc;                   // o-range per workgroup
 };
 
 template <typename TOUT>
@@ -59,98 +59,151 @@ __device__ __forceinline__ void store_out(TOUT *out, void *out_lo, int64_t addr,
     }
 }
 
-template <bool FIRST, int R, typename TIN, typename TOUT>
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// MFMA form: v_mfma_f64_16x16x4_f64 with A = IN[16 rows][4 i], B = D^T[4 i][16 o];
+// A[i][k] / B[k][j] sit in lane (i or j) + 16 k; accumulator r of lane L holds
+// C[(L >> 4) + 4 r][L & 15].  The 32-row input slice and D^T are staged in LDS with the
+// contraction index padded to a multiple of 4 by zeros; the (2 row tiles) x (o tiles)
+// products are spread over the 4 waves.
+template <bool FIRST, typename TIN, typename TOUT>
 __global__ __launch_bounds__(kThreads) void mode_kernel(ModeArgs g) {
     extern __shared__ double smem[];
-    const int nin = g.nin;
-    double *sIN = smem;                                   // [nin][kRT + 1]
-    double *sD = smem + size_t(nin) * (kRT + 1);          // [oc][nin]
+    const int nin = g.nin, nout = g.nout;
+    const int Kp = (nin + 3) & ~3;
+    const int NOp = (nout + 15) & ~15;
+    const int ldi = kRT + 1;                              // sIN[i][row]
+    const int ldo = NOp + 1;                              // sDT[i][o], sOUT[row][o]
+    // per-row address bases first, so that the output staging below (which reuses the
+    // tile region) can never overwrite them
+    int64_t *rin = reinterpret_cast<int64_t *>(smem);     // input base per row
+    int64_t *rout = rin + kRT;                            // output base per row
+    int64_t *pin = rout + kRT;                            // input point base per row
+    int64_t *pout = pin + kRT;                            // output point base per row
+    double *tiles = smem + 4 * kRT;
+    double *sIN = tiles;                                  // Kp * ldi
+    double *sDT = sIN + size_t(Kp) * ldi;                 // Kp * ldo
     const int64_t nrows = g.A * g.Clo * g.nvec;
     const int64_t r0 = int64_t(blockIdx.x) * kRT;
     const int rows = int(min<int64_t>(kRT, nrows - r0));
-    const int o0 = blockIdx.y * g.oc;
-    const int oc = min(g.oc, g.nout - o0);
     const int tid = threadIdx.x;
-    const TIN *in = static_cast<const TIN *>(g.in);
-    // ---- stage the input rows (with the stage-6 split sum and scale) -----------------
-    const int tile = kRT * nin;
-    for (int e = tid; e < tile; e += kThreads) {
-        int rr, i;
-        if (FIRST) { rr = e / nin; i = e % nin; }          // contiguous along i
-        else { rr = e % kRT; i = e / kRT; }                // contiguous along a
-        double v = 0.0;
-        if (rr < rows) {
-            const int64_t r = r0 + rr;
+    // ---- per-row address bases (the only divisions) ----------------------------------
+    if (tid < kRT) {
+        int64_t bi = 0, bo = 0, qi = 0, qo = 0;
+        if (tid < rows) {
+            const int64_t r = r0 + tid;
             const int64_t a = r % g.A, t = r / g.A;
             const int64_t c = t % g.Clo, j = t / g.Clo;
-            const int64_t p = a + g.A * (i + int64_t(nin) * c);
-            const int64_t addr = p + g.in_ldj * j;
-            for (int q = 0; q < g.nsplit; ++q) v += double(in[addr + q * g.in_split]);
-            if (g.in_w) v *= g.in_scale * g.in_w[p];
+            qi = a + g.A * int64_t(nin) * c;
+            qo = a + g.A * int64_t(nout) * c;
+            bi = qi + g.in_ldj * j;
+            bo = qo + g.out_ldj * j;
         }
-        sIN[i * (kRT + 1) + rr] = v;
+        rin[tid] = bi; rout[tid] = bo; pin[tid] = qi; pout[tid] = qo;
     }
-    for (int e = tid; e < oc * nin; e += kThreads) sD[e] = g.D[int64_t(o0) * nin + e];
     __syncthreads();
-    // ---- compute: 32 lanes = 32 rows, 8 groups take o = grp + 8 q ----------------------
-    const int row = tid & 31;
-    const int grp = tid >> 5;
-    double acc[R];
+    // ---- stage IN (with the split sum and the scale) and D^T ---------------------------
+    const TIN *in = static_cast<const TIN *>(g.in);
+    const int tile = kRT * Kp;
+    // batches of 8 elements per thread: the loads of a batch are issued before any of
+    // its LDS stores, so that their latencies overlap
+    for (int e0 = 0; e0 < tile; e0 += 8 * kThreads) {
+        double vb[8];
+        int64_t off[8], pidx[8];
+        bool ok[8];
 #pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = 0.0;
-    for (int i = 0; i < nin; ++i) {
-        const double v = sIN[i * (kRT + 1) + row];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int o = grp + 8 * q;
-            if (o < oc) acc[q] = fma(sD[o * nin + i], v, acc[q]);
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kThreads + tid;
+            int rr, i;
+            if (FIRST) { rr = e / Kp; i = e % Kp; }        // contiguous along i
+            else { rr = e % kRT; i = e / kRT; }            // contiguous along a
+            ok[u] = e < tile && rr < rows && i < nin;
+            off[u] = ok[u] ? rin[rr] + g.A * i : 0;
+            pidx[u] = ok[u] ? pin[rr] + g.A * i : 0;
+            vb[u] = 0.0;
         }
-    }
-    // ---- write -------------------------------------------------------------------------
-    TOUT *out = static_cast<TOUT *>(g.out);
-    if (FIRST) {
-        // through LDS so that consecutive threads write consecutive o
-        __syncthreads();
-        double *sOUT = smem;                               // [kRT][oc + 1]
+        // split partial sums: 8 independent loads per split
+        for (int q = 0; q < g.nsplit; ++q) {
+            const TIN *src = in + q * g.in_split;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int o = grp + 8 * q;
-            if (o < oc) sOUT[row * (oc + 1) + o] = acc[q];
+            for (int u = 0; u < 8; ++u)
+                if (ok[u]) vb[u] += double(src[off[u]]);
         }
-        __syncthreads();
-        for (int e = tid; e < rows * oc; e += kThreads) {
-            const int rr = e / oc, ol = e % oc;
-            const int64_t r = r0 + rr;
-            const int64_t c = r % g.Clo, j = r / g.Clo;
-            const int64_t p = (o0 + ol) + int64_t(g.nout) * c;
-            double v = sOUT[rr * (oc + 1) + ol];
-            if (g.out_w) v *= g.out_w[p];
-            store_out<TOUT>(out, g.out_lo, p + g.out_ldj * j, v);
-        }
-    } else if (row < rows) {
-        const int64_t r = r0 + row;
-        const int64_t a = r % g.A, t = r / g.A;
-        const int64_t c = t % g.Clo, j = t / g.Clo;
+        if (g.in_w) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int o = grp + 8 * q;
-            if (o < oc) {
-                const int64_t p = a + g.A * ((o0 + o) + int64_t(g.nout) * c);
-                double v = acc[q];
-                if (g.out_w) v *= g.out_w[p];
-                store_out<TOUT>(out, g.out_lo, p + g.out_ldj * j, v);
+            for (int u = 0; u < 8; ++u)
+                if (ok[u]) vb[u] *= g.in_scale * g.in_w[pidx[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kThreads + tid;
+            if (e < tile) {
+                int rr, i;
+                if (FIRST) { rr = e / Kp; i = e % Kp; }
+                else { rr = e % kRT; i = e / kRT; }
+                sIN[i * ldi + rr] = vb[u];
             }
         }
     }
-}
-
-template <bool FIRST, typename TIN, typename TOUT>
-void launch_r(const ModeArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    const int R = (a.oc + 7) / 8;
-    if (R <= 4) hipLaunchKernelGGL((mode_kernel<FIRST, 4, TIN, TOUT>), grid, dim3(kThreads), lds, s, a);
-    else if (R <= 8) hipLaunchKernelGGL((mode_kernel<FIRST, 8, TIN, TOUT>), grid, dim3(kThreads), lds, s, a);
-    else if (R <= 12) hipLaunchKernelGGL((mode_kernel<FIRST, 12, TIN, TOUT>), grid, dim3(kThreads), lds, s, a);
-    else hipLaunchKernelGGL((mode_kernel<FIRST, 16, TIN, TOUT>), grid, dim3(kThreads), lds, s, a);
+    for (int e0 = 0; e0 < Kp * NOp; e0 += 8 * kThreads) {
+        double vb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kThreads + tid;
+            const int i = e / NOp, o = e % NOp;           // D^T row-major: contiguous in o
+            vb[u] = (e < Kp * NOp && i < nin && o < nout) ? g.DT[int64_t(i) * nout + o] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kThreads + tid;
+            if (e < Kp * NOp) sDT[(e / NOp) * ldo + e % NOp] = vb[u];
+        }
+    }
+    __syncthreads();
+    // ---- MFMA over the (2 row tiles) x (NOp / 16 o tiles), 4 waves --------------------
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ntiles = 2 * (NOp / 16);                    // <= 16 for nout <= 128
+    doublex4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < Kp; k0 += 4) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int tt = wave + 4 * t;
+            if (tt < ntiles) {
+                const int rt = tt & 1, ot = tt >> 1;
+                const double a = sIN[(k0 + lk) * ldi + rt * 16 + li];
+                const double b = sDT[(k0 + lk) * ldo + ot * 16 + li];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // ---- results through LDS (the IN region is reused: kRT x (NOp + 1)) ---------------
+    __syncthreads();
+    double *sOUT = tiles;                                 // kRT * ldo, within the tile region
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int tt = wave + 4 * t;
+        if (tt < ntiles) {
+            const int rt = tt & 1, ot = tt >> 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sOUT[(rt * 16 + lk + 4 * r) * ldo + ot * 16 + li] = acc[t][r];
+        }
+    }
+    __syncthreads();
+    TOUT *out = static_cast<TOUT *>(g.out);
+    const int outs = kRT * nout;
+    for (int e = tid; e < outs; e += kThreads) {
+        int rr, o;
+        if (FIRST) { rr = e / nout; o = e % nout; }        // contiguous along o
+        else { rr = e % kRT; o = e / kRT; }                // contiguous along a
+        if (rr < rows) {
+            double v = sOUT[rr * ldo + o];
+            if (g.out_w) v *= g.out_w[pout[rr] + g.A * o];
+            store_out<TOUT>(out, g.out_lo, rout[rr] + g.A * o, v);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void copy_cols_kernel(
@@ -201,38 +254,51 @@ unsigned grid_for(int64_t total) {
 
 }  // namespace
 
-bool mode_fits(int nin) {
-    // at least 8 factor rows must fit next to the 32 x nin input slice
-    return nin >= 1 && size_t(nin) * (kRT + 1) * 8 + size_t(8) * nin * 8 <= kLdsBudget;
+// LDS: 4 x kRT row bases, then max(staged tiles, output staging)
+size_t mode_lds_bytes(int nin, int nout) {
+    const size_t Kp = (size_t(nin) + 3) & ~size_t(3), NOp = (size_t(nout) + 15) & ~size_t(15);
+    const size_t tiles = Kp * (kRT + 1) * 8 + Kp * (NOp + 1) * 8;
+    const size_t outs = size_t(kRT) * (NOp + 1) * 8;
+    return 4 * kRT * 8 + std::max(tiles, outs);
+}
+
+bool mode_fits(int nin, int nout) {
+    return nin >= 1 && nout >= 1 && nout <= 128 && mode_lds_bytes(nin, nout) <= kLdsBudget;
+}
+
+template <bool FIRST, typename TIN, typename TOUT>
+void launch_mode_t(const ModeArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    static bool attr_set = false;       // opt in to more than 64 KB of LDS, once
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&mode_kernel<FIRST, TIN, TOUT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsBudget));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((mode_kernel<FIRST, TIN, TOUT>), grid, dim3(kThreads), lds, s, a);
 }
 
 void launch_mode(const ModeSpec &m, hipStream_t s) {
     ModeArgs a;
-    a.D = m.D; a.in = m.in; a.out = m.out; a.A = m.A; a.nin = m.nin; a.nout = m.nout;
+    a.D = m.D; a.DT = m.DT; a.in = m.in; a.out = m.out; a.A = m.A; a.nin = m.nin; a.nout = m.nout;
     a.Clo = m.Clo; a.nvec = m.nvec; a.in_ldj = m.in_ldj; a.out_ldj = m.out_ldj;
     a.nsplit = m.nsplit > 0 ? m.nsplit : 1; a.in_split = m.in_split;
     a.in_w = m.in_w; a.in_scale = m.in_scale; a.out_w = m.out_w; a.out_lo = m.out_lo;
-    // o-range: as many factor rows as fit next to the input slice, at most 128
-    const size_t in_bytes = size_t(m.nin) * (kRT + 1) * 8;
-    int oc = int(std::min<size_t>(128, (kLdsBudget - in_bytes) / (size_t(m.nin) * 8)));
-    oc = std::min(oc, m.nout);
-    a.oc = oc;
-    const size_t lds = std::max(in_bytes + size_t(oc) * m.nin * 8, size_t(kRT) * (oc + 1) * 8);
+    const size_t lds = mode_lds_bytes(m.nin, m.nout);
     const int64_t nrows = m.A * m.Clo * m.nvec;
-    const dim3 grid(unsigned((nrows + kRT - 1) / kRT), unsigned((m.nout + oc - 1) / oc));
+    const dim3 grid(unsigned((nrows + kRT - 1) / kRT));
     const bool first = m.A == 1;
     if (m.in_f32) {
-        if (first) launch_r<true, float, double>(a, grid, lds, s);
-        else launch_r<false, float, double>(a, grid, lds, s);
+        if (first) launch_mode_t<true, float, double>(a, grid, lds, s);
+        else launch_mode_t<false, float, double>(a, grid, lds, s);
     } else if (m.out_f32) {
-        if (first) launch_r<true, double, float>(a, grid, lds, s);
-        else launch_r<false, double, float>(a, grid, lds, s);
+        if (first) launch_mode_t<true, double, float>(a, grid, lds, s);
+        else launch_mode_t<false, double, float>(a, grid, lds, s);
     } else if (m.out_bf16) {
-        if (first) launch_r<true, double, __bf16>(a, grid, lds, s);
-        else launch_r<false, double, __bf16>(a, grid, lds, s);
+        if (first) launch_mode_t<true, double, __bf16>(a, grid, lds, s);
+        else launch_mode_t<false, double, __bf16>(a, grid, lds, s);
     } else {
-        if (first) launch_r<true, double, double>(a, grid, lds, s);
-        else launch_r<false, double, double>(a, grid, lds, s);
+        if (first) launch_mode_t<true, double, double>(a, grid, lds, s);
+        else launch_mode_t<false, double, double>(a, grid, lds, s);
     }
 }
 

@@ -13,6 +13,8 @@
 // exp(-rho) or exp(-rho^2)) and by log2(e)/ell or sqrt(log2 e)/ell for the FP32 kernels,
 // which then use the hardware base-2 exponential.  sigma^2 is applied after the split
 // reduction.  Grids are padded with zero points and zero vectors, which add nothing.
+#include <algorithm>
+
 #include "kl_internal.h"
 
 namespace kl {
@@ -77,246 +79,327 @@ __device__ __forceinline__ double gamma_f64(const double *xk, const double *xl) 
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
+constexpr int kRows = 64;                  // rows per workgroup (shared by its 4 waves)
+constexpr int kSub = 64;                   // l-points per wave per step
+constexpr int kStep = kWaves * kSub;       // l-points per workgroup step
 
-// ---- FP32: v_mfma_f32_32x32x2_f32; A = Gamma[32 rows][2 l], B = Y[2 l][32 cols] -----
-// Lane layout: A[i][k] and B[k][j] sit in lane (i or j) + 32 k; accumulator element r of
-// lane L holds C[(r & 3) + 4 (L >> 5) + 8 (r >> 2)][L & 31].
-constexpr int kTL32 = 64;   // l-points per LDS tile
-
-template <int KIND, int D, int RB>
+// Skeleton shared by all precisions.  The workgroup owns rows [row0, row0 + 64) and the
+// l-range [l0, l1) of its split; each step stages 256 points (and the matching rows of
+// the stage-5 input block) in LDS and wave w contracts the 64-point sub-tile w.  At the
+// end the four waves' 64 x 32 accumulator tiles are added in LDS and the workgroup writes
+// one partial tile, column-major.
+//
+// FP32: v_mfma_f32_32x32x2_f32, A = Gamma[32 rows][2 l], B = Y[2 l][32 cols]; A[i][k] and
+// B[k][j] sit in lane (i or j) + 32 k; accumulator r of lane L holds
+// C[(r & 3) + 4 (L >> 5) + 8 (r >> 2)][L & 31].
+template <int KIND, int D>
 __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
     const float *__restrict__ X, const float *__restrict__ Y, float *__restrict__ Z,
     int64_t Ntpad, int64_t lchunk) {
-    __shared__ float sX[D][kTL32];
-    __shared__ float sY[kTL32][kBW + 1];
+    __shared__ float sX[D][kStep];
+    __shared__ float sY[kStep * (kBW + 1)];      // [l][j], reused for the reduction
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 31, kh = lane >> 5;
-    const int64_t row0 = int64_t(blockIdx.x) * (kWaves * 32 * RB) + int64_t(wave) * 32 * RB;
+    const int64_t row0 = int64_t(blockIdx.x) * kRows;
     const int64_t l0 = int64_t(blockIdx.y) * lchunk;
     const int64_t l1 = min(l0 + lchunk, Ntpad);
-    float xk[RB][D];
+    float xk[2][D];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int k = 0; k < D; ++k) xk[rb][k] = X[k * Ntpad + row0 + rb * 32 + i];
-    floatx16 acc[RB];
+    floatx16 acc[2];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
-
-    for (int64_t lt = l0; lt < l1; lt += kTL32) {
+    for (int64_t lt = l0; lt < l1; lt += kStep) {
         __syncthreads();
-        // Y is column-major (ld Ntpad): coalesced along l, transposed into LDS
+        {
+            // 16-byte loads (4 consecutive l of one column), all issued before the stores
+            float4 v[(kStep * kBW / 4) / kThreads];
 #pragma unroll
-        for (int q = 0; q < (kTL32 * kBW) / kThreads; ++q) {
-            const int e = threadIdx.x + q * kThreads;
-            const int l = e % kTL32, j = e / kTL32;
-            sY[l][j] = Y[int64_t(j) * Ntpad + lt + l];
+            for (int q = 0; q < (kStep * kBW / 4) / kThreads; ++q) {
+                const int e = threadIdx.x + q * kThreads;
+                const int l4 = e % (kStep / 4), j = e / (kStep / 4);
+                const int64_t lg = lt + 4 * l4;
+                v[q] = lg < l1 ? *reinterpret_cast<const float4 *>(Y + int64_t(j) * Ntpad + lg)
+                               : float4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int q = 0; q < (kStep * kBW / 4) / kThreads; ++q) {
+                const int e = threadIdx.x + q * kThreads;
+                const int l4 = e % (kStep / 4), j = e / (kStep / 4);
+                sY[(4 * l4 + 0) * (kBW + 1) + j] = v[q].x;
+                sY[(4 * l4 + 1) * (kBW + 1) + j] = v[q].y;
+                sY[(4 * l4 + 2) * (kBW + 1) + j] = v[q].z;
+                sY[(4 * l4 + 3) * (kBW + 1) + j] = v[q].w;
+            }
         }
-        if (threadIdx.x < D * kTL32) {
-            const int k = threadIdx.x / kTL32, l = threadIdx.x % kTL32;
-            sX[k][l] = X[k * Ntpad + lt + l];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int64_t lg = lt + threadIdx.x;
+            sX[k][threadIdx.x] = lg < l1 ? X[k * Ntpad + lg] : 0.f;
         }
         __syncthreads();
+        if (lt + wave * kSub < l1) {
+            const int base = wave * kSub;
 #pragma unroll 8
-        for (int ll = 0; ll < kTL32; ll += 2) {
-            float xl[D];
+            for (int ll = 0; ll < kSub; ll += 2) {
+                float xl[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) xl[k] = sX[k][ll + kh];
-            const float b = sY[ll + kh][i];
+                for (int k = 0; k < D; ++k) xl[k] = sX[k][base + ll + kh];
+                const float b = sY[(base + ll + kh) * (kBW + 1) + i];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const float g = gamma_f32<KIND, D>(xk[rb], xl);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, b, acc[rb], 0, 0, 0);
+                for (int rb = 0; rb < 2; ++rb) {
+                    const float g = gamma_f32<KIND, D>(xk[rb], xl);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, b, acc[rb], 0, 0, 0);
+                }
             }
         }
     }
-    // Z is column-major (ld Ntpad); accumulator registers 4m..4m+3 of a lane hold four
-    // consecutive rows of one column, stored as one 16-byte vector
-    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW + int64_t(i) * Ntpad;
+    // ---- reduce the four waves in LDS and write the partial tile -----------------------
+    __syncthreads();
+    float *red = sY;                             // [wave][row][kBW + 1]
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int64_t row = row0 + rb * 32 + 4 * kh + 8 * m;
-            float4 v = {acc[rb][4 * m], acc[rb][4 * m + 1], acc[rb][4 * m + 2], acc[rb][4 * m + 3]};
-            *reinterpret_cast<float4 *>(Zs + row) = v;
+        for (int r = 0; r < 16; ++r) {
+            const int row = rb * 32 + (r & 3) + 4 * kh + 8 * (r >> 2);
+            red[(wave * kRows + row) * (kBW + 1) + i] = acc[rb][r];
         }
+    __syncthreads();
+    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
+#pragma unroll
+    for (int q = 0; q < (kRows * kBW) / kThreads; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        const int row = e % kRows, j = e / kRows;
+        float v = 0.f;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) v += red[(w * kRows + row) * (kBW + 1) + j];
+        Zs[int64_t(j) * Ntpad + row0 + row] = v;
+    }
 }
 
-// ---- FP64: v_mfma_f64_16x16x4_f64; A = Gamma[16 rows][4 l], B = Y[4 l][16 cols] -----
-// Lane layout: A[i][k] and B[k][j] sit in lane (i or j) + 16 k; accumulator element r of
-// lane L holds C[(L >> 4) + 4 r][L & 15] (measured on gfx950; this differs from the
-// FP32 16x16x4 layout).  Two MFMAs cover the 32 columns.
-constexpr int kTL64 = 32;
-
-template <int KIND, int D, int RB>
+// FP64: v_mfma_f64_16x16x4_f64, A = Gamma[16 rows][4 l], B = Y[4 l][16 cols]; A[i][k] and
+// B[k][j] sit in lane (i or j) + 16 k; accumulator r of lane L holds C[(L >> 4) + 4 r][L & 15]
+// (measured on gfx950; differs from the FP32 16x16x4 layout).  Four 16-row tiles x two
+// 16-column halves per wave.
+template <int KIND, int D>
 __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
     const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ Z,
     int64_t Ntpad, int64_t lchunk) {
-    __shared__ double sX[D][kTL64];
-    __shared__ double sY[kTL64][kBW + 1];
+    extern __shared__ double sm64[];
+    double *sX = sm64;                           // [D][kStep]
+    double *sY = sm64 + D * kStep;               // [l][kBW + 1]; reduction reuses it all
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 15, kq = lane >> 4;
-    const int64_t row0 = int64_t(blockIdx.x) * (kWaves * 16 * RB) + int64_t(wave) * 16 * RB;
+    const int64_t row0 = int64_t(blockIdx.x) * kRows;
     const int64_t l0 = int64_t(blockIdx.y) * lchunk;
     const int64_t l1 = min(l0 + lchunk, Ntpad);
-    double xk[RB][D];
+    double xk[4][D];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int k = 0; k < D; ++k) xk[rb][k] = X[k * Ntpad + row0 + rb * 16 + i];
-    doublex4 acc[RB][2];
+    doublex4 acc[4][2];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) { acc[rb][0][r] = 0.0; acc[rb][1][r] = 0.0; }
-
-    for (int64_t lt = l0; lt < l1; lt += kTL64) {
+    for (int64_t lt = l0; lt < l1; lt += kStep) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < (kTL64 * kBW) / kThreads; ++q) {
-            const int e = threadIdx.x + q * kThreads;
-            const int l = e % kTL64, j = e / kTL64;
-            sY[l][j] = Y[int64_t(j) * Ntpad + lt + l];
+        for (int h = 0; h < 2; ++h) {
+            // 16-byte loads (2 consecutive l of one column), 8 in flight per thread
+            double2 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = threadIdx.x + (h * 8 + q) * kThreads;
+                const int l2 = e % (kStep / 2), j = e / (kStep / 2);
+                const int64_t lg = lt + 2 * l2;
+                v[q] = lg < l1 ? *reinterpret_cast<const double2 *>(Y + int64_t(j) * Ntpad + lg)
+                               : double2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = threadIdx.x + (h * 8 + q) * kThreads;
+                const int l2 = e % (kStep / 2), j = e / (kStep / 2);
+                sY[(2 * l2 + 0) * (kBW + 1) + j] = v[q].x;
+                sY[(2 * l2 + 1) * (kBW + 1) + j] = v[q].y;
+            }
         }
-        if (threadIdx.x < D * kTL64) {
-            const int k = threadIdx.x / kTL64, l = threadIdx.x % kTL64;
-            sX[k][l] = X[k * Ntpad + lt + l];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int64_t lg = lt + threadIdx.x;
+            sX[k * kStep + threadIdx.x] = lg < l1 ? X[k * Ntpad + lg] : 0.0;
         }
         __syncthreads();
+        if (lt + wave * kSub < l1) {
+            const int base = wave * kSub;
 #pragma unroll 2
-        for (int ll = 0; ll < kTL64; ll += 4) {
-            double xl[D];
+            for (int ll = 0; ll < kSub; ll += 4) {
+                double xl[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) xl[k] = sX[k][ll + kq];
-            const double b0 = sY[ll + kq][i];
-            const double b1 = sY[ll + kq][16 + i];
+                for (int k = 0; k < D; ++k) xl[k] = sX[k * kStep + base + ll + kq];
+                const double b0 = sY[(base + ll + kq) * (kBW + 1) + i];
+                const double b1 = sY[(base + ll + kq) * (kBW + 1) + 16 + i];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const double g = gamma_f64<KIND, D>(xk[rb], xl);
-                acc[rb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, b0, acc[rb][0], 0, 0, 0);
-                acc[rb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, b1, acc[rb][1], 0, 0, 0);
+                for (int rb = 0; rb < 4; ++rb) {
+                    const double g = gamma_f64<KIND, D>(xk[rb], xl);
+                    acc[rb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, b0, acc[rb][0], 0, 0, 0);
+                    acc[rb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, b1, acc[rb][1], 0, 0, 0);
+                }
             }
         }
     }
-    // Z is column-major (ld Ntpad): for each register, lanes with the same column
-    // write four consecutive rows
-    double *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
+    __syncthreads();
+    double *red = sm64;                          // [wave][row][kBW + 1]
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t row = row0 + rb * 16 + kq + 4 * r;
-            Zs[int64_t(i) * Ntpad + row] = acc[rb][0][r];
-            Zs[int64_t(16 + i) * Ntpad + row] = acc[rb][1][r];
+            const int row = rb * 16 + kq + 4 * r;
+            red[(wave * kRows + row) * (kBW + 1) + i] = acc[rb][0][r];
+            red[(wave * kRows + row) * (kBW + 1) + 16 + i] = acc[rb][1][r];
         }
+    __syncthreads();
+    double *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
+#pragma unroll
+    for (int q = 0; q < (kRows * kBW) / kThreads; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        const int row = e % kRows, j = e / kRows;
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) v += red[(w * kRows + row) * (kBW + 1) + j];
+        Zs[int64_t(j) * Ntpad + row0 + row] = v;
+    }
 }
+// staged tiles (points for up to 3 dimensions + the Y rows) and, afterwards, the reduction
+constexpr size_t kLds64 = std::max(size_t(3 * kStep + kStep * (kBW + 1)),
+                                   size_t(kWaves) * kRows * (kBW + 1)) * sizeof(double);
 
-
-// ---- BF16: v_mfma_f32_32x32x16_bf16; A = Gamma[32 rows][16 l], B = Y[16 l][32 cols] ---
-// Lane layout (measured on gfx950): A[i][k] in lane i + 32 (k / 8), element k % 8;
-// B[k][j] in lane j + 32 (k / 8), element k % 8; accumulators as for the FP32 32x32x2.
-// The kernel is evaluated in FP32 and rounded to BF16 (round to nearest even).  With
-// X3 both operands are split into hi + lo BF16 parts and three products are
-// accumulated (hi hi + hi lo + lo hi), about 16 significant bits per operand.
-constexpr int kTLB = 64;   // l-points per LDS tile (4 MFMA k-steps)
+// BF16: v_mfma_f32_32x32x16_bf16, A = Gamma[32 rows][16 l], B = Y[16 l][32 cols];
+// A[i][k] in lane i + 32 (k / 8), element k % 8; B[k][j] in lane j + 32 (k / 8), element
+// k % 8; accumulators as for the FP32 32x32x2 (measured on gfx950).  The kernel value is
+// evaluated in FP32 and rounded to BF16 (nearest even).  With X3 both operands are split
+// into hi + lo BF16 parts and hi hi + hi lo + lo hi are accumulated.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <int KIND, int D, int RB, bool X3>
+template <int KIND, int D, bool X3>
 __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
     const float *__restrict__ X, const __bf16 *__restrict__ Yh, const __bf16 *__restrict__ Yl,
     float *__restrict__ Z, int64_t Ntpad, int64_t lchunk) {
-    __shared__ float sX[D][kTLB];
-    __shared__ __attribute__((aligned(16))) __bf16 sYh[kBW][kTLB + 8];
-    __shared__ __attribute__((aligned(16))) __bf16 sYl[X3 ? kBW : 1][kTLB + 8];
+    constexpr int ldb = kStep + 8;               // bf16 row of one column (16-byte aligned)
+    __shared__ float sX[D][kStep];
+    __shared__ __attribute__((aligned(16))) __bf16 sYh[kBW * ldb];
+    __shared__ __attribute__((aligned(16))) __bf16 sYl[X3 ? kBW * ldb : 8];
+    __shared__ float red[kWaves * kRows * (kBW + 1)];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 31, kh = lane >> 5;
-    const int64_t row0 = int64_t(blockIdx.x) * (kWaves * 32 * RB) + int64_t(wave) * 32 * RB;
+    const int64_t row0 = int64_t(blockIdx.x) * kRows;
     const int64_t l0 = int64_t(blockIdx.y) * lchunk;
     const int64_t l1 = min(l0 + lchunk, Ntpad);
-    float xk[RB][D];
+    float xk[2][D];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int k = 0; k < D; ++k) xk[rb][k] = X[k * Ntpad + row0 + rb * 32 + i];
-    floatx16 acc[RB];
+    floatx16 acc[2];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
-
-    for (int64_t lt = l0; lt < l1; lt += kTLB) {
+    for (int64_t lt = l0; lt < l1; lt += kStep) {
         __syncthreads();
-        // Y (column-major bf16, ld Ntpad): 8 consecutive l of one column per 16-byte load
-        {
-            const int j = threadIdx.x >> 3, seg = threadIdx.x & 7;   // 32 columns x 8 segments
-            const int4 vh = *reinterpret_cast<const int4 *>(Yh + int64_t(j) * Ntpad + lt + 8 * seg);
-            *reinterpret_cast<int4 *>(&sYh[j][8 * seg]) = vh;
-            if constexpr (X3) {
-                const int4 vl = *reinterpret_cast<const int4 *>(Yl + int64_t(j) * Ntpad + lt + 8 * seg);
-                *reinterpret_cast<int4 *>(&sYl[j][8 * seg]) = vl;
+        // 32 columns x 32 segments of 8 consecutive l (16 bytes)
+#pragma unroll
+        for (int q = 0; q < (kBW * kStep / 8) / kThreads; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int j = e / (kStep / 8), seg = e % (kStep / 8);
+            const int64_t lg = lt + 8 * seg;
+            int4 vh = {0, 0, 0, 0}, vl = {0, 0, 0, 0};
+            if (lg < l1) {
+                vh = *reinterpret_cast<const int4 *>(Yh + int64_t(j) * Ntpad + lg);
+                if constexpr (X3) vl = *reinterpret_cast<const int4 *>(Yl + int64_t(j) * Ntpad + lg);
             }
+            *reinterpret_cast<int4 *>(&sYh[j * ldb + 8 * seg]) = vh;
+            if constexpr (X3) *reinterpret_cast<int4 *>(&sYl[j * ldb + 8 * seg]) = vl;
         }
-        if (threadIdx.x < D * kTLB) {
-            const int k = threadIdx.x / kTLB, l = threadIdx.x % kTLB;
-            sX[k][l] = X[k * Ntpad + lt + l];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int64_t lg = lt + threadIdx.x;
+            sX[k][threadIdx.x] = lg < l1 ? X[k * Ntpad + lg] : 0.f;
         }
         __syncthreads();
+        if (lt + wave * kSub < l1) {
+            const int base = wave * kSub;
 #pragma unroll
-        for (int ll = 0; ll < kTLB; ll += 16) {
-            const int lb = ll + 8 * kh;
-            float xl[8][D];
+            for (int ll = 0; ll < kSub; ll += 16) {
+                const int lb = base + ll + 8 * kh;
+                float xl[8][D];
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
+                for (int e = 0; e < 8; ++e)
 #pragma unroll
-                for (int k = 0; k < D; ++k) xl[e][k] = sX[k][lb + e];
-            const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sYh[i][lb]);
-            bf16x8 bl;
-            if constexpr (X3) bl = *reinterpret_cast<const bf16x8 *>(&sYl[i][lb]);
+                    for (int k = 0; k < D; ++k) xl[e][k] = sX[k][lb + e];
+                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sYh[i * ldb + lb]);
+                bf16x8 bl;
+                if constexpr (X3) bl = *reinterpret_cast<const bf16x8 *>(&sYl[i * ldb + lb]);
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                bf16x8 ah, al;
+                for (int rb = 0; rb < 2; ++rb) {
+                    bf16x8 ah, al;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const float g = gamma_f32<KIND, D>(xk[rb], xl[e]);
-                    ah[e] = __bf16(g);
-                    if constexpr (X3) al[e] = __bf16(g - float(ah[e]));
-                }
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[rb], 0, 0, 0);
-                if constexpr (X3) {
-                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[rb], 0, 0, 0);
-                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[rb], 0, 0, 0);
+                    for (int e = 0; e < 8; ++e) {
+                        const float g = gamma_f32<KIND, D>(xk[rb], xl[e]);
+                        ah[e] = __bf16(g);
+                        if constexpr (X3) al[e] = __bf16(g - float(ah[e]));
+                    }
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[rb], 0, 0, 0);
+                    if constexpr (X3) {
+                        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[rb], 0, 0, 0);
+                        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[rb], 0, 0, 0);
+                    }
                 }
             }
         }
     }
-    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW + int64_t(i) * Ntpad;
+    __syncthreads();
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int64_t row = row0 + rb * 32 + 4 * kh + 8 * m;
-            float4 v = {acc[rb][4 * m], acc[rb][4 * m + 1], acc[rb][4 * m + 2], acc[rb][4 * m + 3]};
-            *reinterpret_cast<float4 *>(Zs + row) = v;
+        for (int r = 0; r < 16; ++r) {
+            const int row = rb * 32 + (r & 3) + 4 * kh + 8 * (r >> 2);
+            red[(wave * kRows + row) * (kBW + 1) + i] = acc[rb][r];
         }
+    __syncthreads();
+    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
+#pragma unroll
+    for (int q = 0; q < (kRows * kBW) / kThreads; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        const int row = e % kRows, j = e / kRows;
+        float v = 0.f;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) v += red[(w * kRows + row) * (kBW + 1) + j];
+        Zs[int64_t(j) * Ntpad + row0 + row] = v;
+    }
 }
-
-constexpr int kRB32 = 2;   // rows per FP32 workgroup: 4 waves x 2 x 32 = 256
-constexpr int kRB64 = 4;   // rows per FP64 workgroup: 4 waves x 4 x 16 = 256
-constexpr int kRowsPerWG = 256;
 
 template <int KIND, int D>
 void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, int nsplit,
                  int64_t lchunk, hipStream_t s) {
-    dim3 grid(unsigned(P->Ntpad / kRowsPerWG), unsigned(nsplit));
+    dim3 grid(unsigned(P->Ntpad / kRows), unsigned(nsplit));
     if (precision == KL_F64) {
-        hipLaunchKernelGGL((stage5_f64_kernel<KIND, D, kRB64>), grid, dim3(kThreads), 0, s,
+        static bool attr_set = false;
+        if (!attr_set) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&stage5_f64_kernel<KIND, D>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(kLds64));
+            attr_set = true;
+        }
+        hipLaunchKernelGGL((stage5_f64_kernel<KIND, D>), grid, dim3(kThreads), kLds64, s,
                            P->dX64, static_cast<const double *>(Y5), static_cast<double *>(Z5),
                            P->Ntpad, lchunk);
     } else if (precision == KL_F32) {
-        hipLaunchKernelGGL((stage5_f32_kernel<KIND, D, kRB32>), grid, dim3(kThreads), 0, s,
+        hipLaunchKernelGGL((stage5_f32_kernel<KIND, D>), grid, dim3(kThreads), 0, s,
                            P->dX32, static_cast<const float *>(Y5), static_cast<float *>(Z5),
                            P->Ntpad, lchunk);
     } else {
@@ -324,10 +407,10 @@ void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, i
         const __bf16 *yh = static_cast<const __bf16 *>(Y5);
         const __bf16 *yl = yh + P->Ntpad * kBW;
         if (precision == KL_BF16)
-            hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, kRB32, false>), grid, dim3(kThreads), 0, s,
+            hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, false>), grid, dim3(kThreads), 0, s,
                                P->dX32, yh, yl, static_cast<float *>(Z5), P->Ntpad, lchunk);
         else
-            hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, kRB32, true>), grid, dim3(kThreads), 0, s,
+            hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, true>), grid, dim3(kThreads), 0, s,
                                P->dX32, yh, yl, static_cast<float *>(Z5), P->Ntpad, lchunk);
     }
 }
@@ -346,18 +429,26 @@ void launch_dim(int precision, const kl_problem *P, const void *Y5, void *Z5, in
 
 }  // namespace
 
-// Number of l-splits: enough workgroups to fill the chip twice over, each split a
-// whole number of LDS tiles.
+// Number of l-splits.  Each workgroup has 4 waves; a split count S gives 4 R S waves
+// (R = row tiles) over the 4 SIMDs of every CU.  S minimises the busiest SIMD's share,
+// ceil(4 R S / SIMDs) / S, plus a small charge per split for the partial sums, among the
+// counts that put at least 1.5 waves on every SIMD when that is possible.
 int stage5_splits(int64_t Ntpad, int n_cu, int64_t *lchunk_out) {
-    const int64_t row_tiles = Ntpad / kRowsPerWG;
-    const int64_t tile = 64;   // common multiple of both LDS tile lengths
-    int64_t want = (2 * int64_t(n_cu) + row_tiles - 1) / row_tiles;
-    const int64_t max_split = Ntpad / tile;
-    if (want > max_split) want = max_split;
-    if (want > 64) want = 64;
-    if (want < 1) want = 1;
-    int64_t lchunk = ((Ntpad + want - 1) / want + tile - 1) / tile * tile;
-    int64_t nsplit = (Ntpad + lchunk - 1) / lchunk;
+    const int64_t R = Ntpad / kRows;
+    const int64_t simds = 4 * int64_t(n_cu);
+    const int64_t max_split = std::min<int64_t>(64, Ntpad / kSub);
+    int64_t best = 1;
+    double best_cost = 1e300;
+    bool any_full = false;
+    for (int64_t S = 1; S <= max_split; ++S) if (4 * R * S * 2 >= 3 * simds) { any_full = true; break; }
+    for (int64_t S = 1; S <= max_split; ++S) {
+        const int64_t waves = 4 * R * S;
+        if (any_full && waves * 2 < 3 * simds) continue;
+        const double cost = double((waves + simds - 1) / simds) / double(S) + 0.01 * double(S);
+        if (cost < best_cost - 1e-12) { best_cost = cost; best = S; }
+    }
+    int64_t lchunk = ((Ntpad + best - 1) / best + kSub - 1) / kSub * kSub;
+    const int64_t nsplit = (Ntpad + lchunk - 1) / lchunk;
     if (lchunk_out) *lchunk_out = lchunk;
     return int(nsplit);
 }

@@ -82,6 +82,7 @@ namespace kl {
 //   IN'[q] = in_scale * in_w[q] * sum_{s < nsplit} in[q + in_ldj j + s in_split]
 struct ModeSpec {
     const double *D = nullptr;      // nout x nin, row-major, FP64
+    const double *DT = nullptr;     // the same factor transposed (nin x nout)
     const void *in = nullptr;
     void *out = nullptr;
     int64_t A = 1;
@@ -97,8 +98,8 @@ struct ModeSpec {
     void *out_lo = nullptr;         // BF16 output: low parts (hi/lo split), or NULL
     bool in_f32 = false, out_f32 = false, out_bf16 = false;
 };
-// true if a factor with nin columns fits the LDS-staged kernel
-bool mode_fits(int nin);
+// true if a factor (nout x nin) fits the LDS-staged MFMA kernel
+bool mode_fits(int nin, int nout);
 void launch_mode(const ModeSpec &m, hipStream_t s);
 // Copies a strided column block (FP64).
 void launch_copy_cols(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,

@@ -45,7 +45,7 @@ SMALL = [
     ("interp_ne_trial", {"dim": 2, "degree": [2, 3], "nelem": [9, 5], "interp_degree": [3, 1],
                          "interp_nelem": [12, 11], "map": {"kind": "annulus_polar", "r0": 1.0, "r1": 2.0},
                          "cov": {"kind": "exp", "sigma2": 1.3, "corr_len": [0.4, 0.9]}}),
-    ("line", {"dim": 1, "degree": [3], "nelem": [300], "map": {"kind": "box", "lo": [0.0], "hi": [2.0]},
+    ("line", {"dim": 1, "degree": [3], "nelem": [120], "map": {"kind": "box", "lo": [0.0], "hi": [2.0]},
               "cov": {"kind": "sqexp", "sigma2": 1.0, "corr_len": [0.2]}}),
     ("exp_l1", {"dim": 2, "degree": [2, 2], "nelem": [10, 7], "map": {"kind": "identity"},
                 "cov": {"kind": "exp_l1", "sigma2": 1.0, "corr_len": [0.5, 0.3]}}),
@@ -163,3 +163,8 @@ def test_apply_errors():
     assert st == -1
     # nvec = 0 is a no-op
     assert kl.lib().kl_apply(G.handle, 0, 0, None, G.N, None, G.N, None) == 0
+    # more than 128 functions in one direction: rejected at setup with KL_EINVAL
+    with pytest.raises(kl.KLError) as e:
+        kl.Problem({"dim": 1, "degree": [2], "nelem": [200], "map": {"kind": "identity"},
+                    "cov": {"kind": "exp", "corr_len": [0.3]}})
+    assert e.value.status == -1
