@@ -125,8 +125,12 @@ def main():
             reps.append(rep)
         i = int(np.argsort(times)[len(times) // 2])
         return times[i], reps[i]
-    t_lo, rep_lo = solve("f32")
-    t_64, rep_64 = solve("f64")
+    if args.solves > 0:
+        t_lo, rep_lo = solve("f32")
+        t_64, rep_64 = solve("f64")
+    else:
+        t_lo = t_64 = float("nan")
+        rep_lo = rep_64 = None
 
     out = {
         "metric": "covariance-apply pair evals/s (% peak); time to k eigenpairs at 1e-6 err",

@@ -47,6 +47,7 @@ void free_problem(kl_problem *P) {
     hipFree(P->ws.Y5f);
     hipFree(P->ws.Y5b);
     hipFree(P->ws.Z5);
+    hipFree(P->ws.Zf);
     delete P;
 }
 
@@ -91,7 +92,7 @@ void *stage5_input(kl_problem *P, int precision) {
 int timed_stage5(kl_problem *P, int precision, const void *Y5, hipStream_t s) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
     if (rec) hipEventRecord(P->prof_ev[P->prof_used], s);
-    const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, s);
+    const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, P->ws.Zf, s);
     if (rec) {
         hipEventRecord(P->prof_ev[P->prof_used + 1], s);
         P->prof_prec.push_back(precision);
@@ -146,7 +147,8 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
     // ---- stage 5 ----------------------------------------------------------------------
     const int nsplit = timed_stage5(P, precision, Y5, s);
     // ---- stages 6-9: sigma^2 J and the split sum on the way in, C_k^T per direction ----
-    cur = P->ws.Z5;
+    (void)nsplit;
+    cur = P->ws.Zf;
     cur_ld = P->Ntpad;
     A = 1;
     for (int k = 0; k < d; ++k) {
@@ -162,8 +164,6 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
         for (int j = k + 1; j < d; ++j) m.Clo *= hs.nt[j];
         m.nvec = nb;
         if (k == 0) {
-            m.nsplit = nsplit;
-            m.in_split = P->Ntpad * kBW;
             m.in_w = P->dJ;
             m.in_scale = P->sigma2;
             m.in_f32 = lo;
@@ -272,6 +272,7 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5b), P->ws.y5_bytes / 2, "hipMalloc Y5"));
     KL_TRY(hip_check(hipMemset(P->ws.Y5b, 0, P->ws.y5_bytes / 2), "memset Y5"));
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Z5), P->ws.z5_bytes, "hipMalloc Z5"));
+    KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Zf), size_t(Np) * kBW * sizeof(double), "hipMalloc Zf"));
 #undef KL_TRY
     *out = P;
     return KL_OK;
@@ -324,7 +325,8 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec, const double
         void *Y5 = stage5_input(P, precision);
         launch_pack_stage5(precision, y + int64_t(c0) * ldy, ldy, P->hs.Nt, nb, P->Ntpad, Y5, s);
         const int nsplit = timed_stage5(P, precision, Y5, s);
-        launch_unpack_stage5(precision, P->ws.Z5, nsplit, P->Ntpad, P->hs.Nt, nb, P->sigma2,
+        (void)nsplit;
+        launch_unpack_stage5(precision, P->ws.Zf, 1, P->Ntpad, P->hs.Nt, nb, P->sigma2,
                              z + int64_t(c0) * ldz, ldz, s);
         kl_status st = hip_check(hipGetLastError(), "kernel launch");
         if (st != KL_OK) return st;

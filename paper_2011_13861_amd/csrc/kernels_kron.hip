@@ -14,9 +14,7 @@
 //     sigma^2 J[p], in FP64.
 // The point index of an entry is its address without the vector term, p = a + A (i + nin c).
 //
-// A workgroup owns 32 consecutive rows and every o: it stages the 32 x nin input slice
-// and D^T in LDS (loads coalesced along the contiguous index), runs the contraction on
-// FP64 matrix cores and writes through LDS so that stores are coalesced too.
+// Each wave computes one 16 x 16 tile of OUT on the FP64 matrix cores (see below).
 #include <algorithm>
 #include <type_traits>
 
@@ -26,8 +24,6 @@ namespace kl {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRT = 32;                 // rows per workgroup
-constexpr size_t kLdsBudget = 160 * 1024;   // gfx950: up to 160 KB per workgroup
 
 struct ModeArgs {
     const double *D;          // nout x nin row-major
@@ -61,147 +57,80 @@ __device__ __forceinline__ void store_out(TOUT *out, void *out_lo, int64_t addr,
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// MFMA form: v_mfma_f64_16x16x4_f64 with A = IN[16 rows][4 i], B = D^T[4 i][16 o];
-// A[i][k] / B[k][j] sit in lane (i or j) + 16 k; accumulator r of lane L holds
-// C[(L >> 4) + 4 r][L & 15].  The 32-row input slice and D^T are staged in LDS with the
-// contraction index padded to a multiple of 4 by zeros; the (2 row tiles) x (o tiles)
-// products are spread over the 4 waves.
+// One wave per 16 x 16 output tile on v_mfma_f64_16x16x4_f64, operands loaded straight
+// from memory into registers (all loads of a wave are issued before the first MFMA), no
+// LDS and no barriers.  Lane layout: A[i][k] and B[k][j] sit in lane (i or j) + 16 k;
+// accumulator r of lane L holds C[(L >> 4) + 4 r][L & 15].
+//  * First direction (A == 1): C = IN D^T  (16 rows x 16 o): A = IN[row][i], B = D^T[i][o];
+//    a lane of the result holds 16 consecutive o of one row -> coalesced stores.
+//  * Later directions: C = D IN^T (16 o x 16 rows): A = D[o][i], B = IN[row][i]; a lane
+//    holds 16 consecutive rows (consecutive a) of one o -> coalesced stores.
+// The contraction index is processed in chunks of 64 (16 MFMA steps).
+constexpr int kChunk = 16;                 // MFMA steps per operand batch (64 indices)
+
 template <bool FIRST, typename TIN, typename TOUT>
 __global__ __launch_bounds__(kThreads) void mode_kernel(ModeArgs g) {
-    extern __shared__ double smem[];
-    const int nin = g.nin, nout = g.nout;
-    const int Kp = (nin + 3) & ~3;
-    const int NOp = (nout + 15) & ~15;
-    const int ldi = kRT + 1;                              // sIN[i][row]
-    const int ldo = NOp + 1;                              // sDT[i][o], sOUT[row][o]
-    // per-row address bases first, so that the output staging below (which reuses the
-    // tile region) can never overwrite them
-    int64_t *rin = reinterpret_cast<int64_t *>(smem);     // input base per row
-    int64_t *rout = rin + kRT;                            // output base per row
-    int64_t *pin = rout + kRT;                            // input point base per row
-    int64_t *pout = pin + kRT;                            // output point base per row
-    double *tiles = smem + 4 * kRT;
-    double *sIN = tiles;                                  // Kp * ldi
-    double *sDT = sIN + size_t(Kp) * ldi;                 // Kp * ldo
-    const int64_t nrows = g.A * g.Clo * g.nvec;
-    const int64_t r0 = int64_t(blockIdx.x) * kRT;
-    const int rows = int(min<int64_t>(kRT, nrows - r0));
-    const int tid = threadIdx.x;
-    // ---- per-row address bases (the only divisions) ----------------------------------
-    if (tid < kRT) {
-        int64_t bi = 0, bo = 0, qi = 0, qo = 0;
-        if (tid < rows) {
-            const int64_t r = r0 + tid;
-            const int64_t a = r % g.A, t = r / g.A;
-            const int64_t c = t % g.Clo, j = t / g.Clo;
-            qi = a + g.A * int64_t(nin) * c;
-            qo = a + g.A * int64_t(nout) * c;
-            bi = qi + g.in_ldj * j;
-            bo = qo + g.out_ldj * j;
-        }
-        rin[tid] = bi; rout[tid] = bo; pin[tid] = qi; pout[tid] = qo;
-    }
-    __syncthreads();
-    // ---- stage IN (with the split sum and the scale) and D^T ---------------------------
-    const TIN *in = static_cast<const TIN *>(g.in);
-    const int tile = kRT * Kp;
-    // batches of 8 elements per thread: the loads of a batch are issued before any of
-    // its LDS stores, so that their latencies overlap
-    for (int e0 = 0; e0 < tile; e0 += 8 * kThreads) {
-        double vb[8];
-        int64_t off[8], pidx[8];
-        bool ok[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kThreads + tid;
-            int rr, i;
-            if (FIRST) { rr = e / Kp; i = e % Kp; }        // contiguous along i
-            else { rr = e % kRT; i = e / kRT; }            // contiguous along a
-            ok[u] = e < tile && rr < rows && i < nin;
-            off[u] = ok[u] ? rin[rr] + g.A * i : 0;
-            pidx[u] = ok[u] ? pin[rr] + g.A * i : 0;
-            vb[u] = 0.0;
-        }
-        // split partial sums: 8 independent loads per split
-        for (int q = 0; q < g.nsplit; ++q) {
-            const TIN *src = in + q * g.in_split;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (ok[u]) vb[u] += double(src[off[u]]);
-        }
-        if (g.in_w) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (ok[u]) vb[u] *= g.in_scale * g.in_w[pidx[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kThreads + tid;
-            if (e < tile) {
-                int rr, i;
-                if (FIRST) { rr = e / Kp; i = e % Kp; }
-                else { rr = e % kRT; i = e / kRT; }
-                sIN[i * ldi + rr] = vb[u];
-            }
-        }
-    }
-    for (int e0 = 0; e0 < Kp * NOp; e0 += 8 * kThreads) {
-        double vb[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kThreads + tid;
-            const int i = e / NOp, o = e % NOp;           // D^T row-major: contiguous in o
-            vb[u] = (e < Kp * NOp && i < nin && o < nout) ? g.DT[int64_t(i) * nout + o] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kThreads + tid;
-            if (e < Kp * NOp) sDT[(e / NOp) * ldo + e % NOp] = vb[u];
-        }
-    }
-    __syncthreads();
-    // ---- MFMA over the (2 row tiles) x (NOp / 16 o tiles), 4 waves --------------------
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int ntiles = 2 * (NOp / 16);                    // <= 16 for nout <= 128
-    doublex4 acc[4];
+    const int nin = g.nin, nout = g.nout;
+    const int64_t nrows = g.A * g.Clo * g.nvec;
+    const int64_t rtiles = (nrows + 15) / 16;
+    const int otiles = (nout + 15) / 16;
+    const int64_t tile = int64_t(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6);
+    if (tile >= rtiles * otiles) return;           // whole wave leaves together
+    const int64_t rt = tile / otiles;
+    const int ot = int(tile % otiles);
+    // this lane's row (operand index li) and its address bases
+    const int64_t r = rt * 16 + li;
+    const bool rok = r < nrows;
+    int64_t bin = 0, pin = 0;
+    if (rok) {
+        const int64_t a = r % g.A, t = r / g.A;
+        const int64_t c = t % g.Clo, j = t / g.Clo;
+        pin = a + g.A * int64_t(nin) * c;
+        bin = pin + g.in_ldj * j;
+    }
+    const int o_l = ot * 16 + li;                  // this lane's o (operand index li)
+    const bool ook = o_l < nout;
+    const TIN *in = static_cast<const TIN *>(g.in);
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < nin; kc += 4 * kChunk) {
+        double xa[kChunk], xb[kChunk];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < Kp; k0 += 4) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int tt = wave + 4 * t;
-            if (tt < ntiles) {
-                const int rt = tt & 1, ot = tt >> 1;
-                const double a = sIN[(k0 + lk) * ldi + rt * 16 + li];
-                const double b = sDT[(k0 + lk) * ldo + ot * 16 + li];
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        for (int s = 0; s < kChunk; ++s) {
+            const int i = kc + 4 * s + lk;
+            double vin = 0.0, vd = 0.0;
+            if (i < nin) {
+                if (rok) {
+                    vin = double(in[bin + g.A * i]);
+                    if (g.in_w) vin *= g.in_scale * g.in_w[pin + g.A * i];
+                }
+                if (ook) vd = g.D[int64_t(o_l) * nin + i];
             }
+            if (FIRST) { xa[s] = vin; xb[s] = vd; }
+            else { xa[s] = vd; xb[s] = vin; }
         }
-    }
-    // ---- results through LDS (the IN region is reused: kRT x (NOp + 1)) ---------------
-    __syncthreads();
-    double *sOUT = tiles;                                 // kRT * ldo, within the tile region
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int tt = wave + 4 * t;
-        if (tt < ntiles) {
-            const int rt = tt & 1, ot = tt >> 1;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) sOUT[(rt * 16 + lk + 4 * r) * ldo + ot * 16 + li] = acc[t][r];
-        }
+        for (int s = 0; s < kChunk; ++s)
+            if (kc + 4 * s < nin)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], xb[s], acc, 0, 0, 0);
     }
-    __syncthreads();
+    // ---- store: C[(lane >> 4) + 4 q][lane & 15] --------------------------------------
     TOUT *out = static_cast<TOUT *>(g.out);
-    const int outs = kRT * nout;
-    for (int e = tid; e < outs; e += kThreads) {
-        int rr, o;
-        if (FIRST) { rr = e / nout; o = e % nout; }        // contiguous along o
-        else { rr = e % kRT; o = e / kRT; }                // contiguous along a
-        if (rr < rows) {
-            double v = sOUT[rr * ldo + o];
-            if (g.out_w) v *= g.out_w[pout[rr] + g.A * o];
-            store_out<TOUT>(out, g.out_lo, rout[rr] + g.A * o, v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int m = lk + 4 * q;                  // C row index
+        int64_t rr;
+        int o;
+        if (FIRST) { rr = rt * 16 + m; o = ot * 16 + li; }
+        else { rr = rt * 16 + li; o = ot * 16 + m; }
+        if (rr < nrows && o < nout) {
+            const int64_t a = rr % g.A, t = rr / g.A;
+            const int64_t c = t % g.Clo, j = t / g.Clo;
+            const int64_t p = a + g.A * (o + int64_t(nout) * c);
+            double v = acc[q];
+            if (g.out_w) v *= g.out_w[p];
+            store_out<TOUT>(out, g.out_lo, p + g.out_ldj * j, v);
         }
     }
 }
@@ -254,52 +183,29 @@ unsigned grid_for(int64_t total) {
 
 }  // namespace
 
-// LDS: 4 x kRT row bases, then max(staged tiles, output staging)
-size_t mode_lds_bytes(int nin, int nout) {
-    const size_t Kp = (size_t(nin) + 3) & ~size_t(3), NOp = (size_t(nout) + 15) & ~size_t(15);
-    const size_t tiles = Kp * (kRT + 1) * 8 + Kp * (NOp + 1) * 8;
-    const size_t outs = size_t(kRT) * (NOp + 1) * 8;
-    return 4 * kRT * 8 + std::max(tiles, outs);
-}
-
-bool mode_fits(int nin, int nout) {
-    return nin >= 1 && nout >= 1 && nout <= 128 && mode_lds_bytes(nin, nout) <= kLdsBudget;
-}
-
-template <bool FIRST, typename TIN, typename TOUT>
-void launch_mode_t(const ModeArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    static bool attr_set = false;       // opt in to more than 64 KB of LDS, once
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&mode_kernel<FIRST, TIN, TOUT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsBudget));
-        attr_set = true;
-    }
-    hipLaunchKernelGGL((mode_kernel<FIRST, TIN, TOUT>), grid, dim3(kThreads), lds, s, a);
-}
+bool mode_fits(int nin, int nout) { return nin >= 1 && nout >= 1 && nin <= 4096 && nout <= 4096; }
 
 void launch_mode(const ModeSpec &m, hipStream_t s) {
     ModeArgs a;
     a.D = m.D; a.DT = m.DT; a.in = m.in; a.out = m.out; a.A = m.A; a.nin = m.nin; a.nout = m.nout;
     a.Clo = m.Clo; a.nvec = m.nvec; a.in_ldj = m.in_ldj; a.out_ldj = m.out_ldj;
-    a.nsplit = m.nsplit > 0 ? m.nsplit : 1; a.in_split = m.in_split;
+    a.nsplit = 1; a.in_split = 0;
     a.in_w = m.in_w; a.in_scale = m.in_scale; a.out_w = m.out_w; a.out_lo = m.out_lo;
-    const size_t lds = mode_lds_bytes(m.nin, m.nout);
     const int64_t nrows = m.A * m.Clo * m.nvec;
-    const dim3 grid(unsigned((nrows + kRT - 1) / kRT));
+    const int64_t tiles = (nrows + 15) / 16 * ((m.nout + 15) / 16);
+    const dim3 grid(unsigned((tiles + 3) / 4));
     const bool first = m.A == 1;
+#define KL_MODE(F, TI, TO) hipLaunchKernelGGL((mode_kernel<F, TI, TO>), grid, dim3(kThreads), 0, s, a)
     if (m.in_f32) {
-        if (first) launch_mode_t<true, float, double>(a, grid, lds, s);
-        else launch_mode_t<false, float, double>(a, grid, lds, s);
+        if (first) KL_MODE(true, float, double); else KL_MODE(false, float, double);
     } else if (m.out_f32) {
-        if (first) launch_mode_t<true, double, float>(a, grid, lds, s);
-        else launch_mode_t<false, double, float>(a, grid, lds, s);
+        if (first) KL_MODE(true, double, float); else KL_MODE(false, double, float);
     } else if (m.out_bf16) {
-        if (first) launch_mode_t<true, double, __bf16>(a, grid, lds, s);
-        else launch_mode_t<false, double, __bf16>(a, grid, lds, s);
+        if (first) KL_MODE(true, double, __bf16); else KL_MODE(false, double, __bf16);
     } else {
-        if (first) launch_mode_t<true, double, double>(a, grid, lds, s);
-        else launch_mode_t<false, double, double>(a, grid, lds, s);
+        if (first) KL_MODE(true, double, double); else KL_MODE(false, double, double);
     }
+#undef KL_MODE
 }
 
 void launch_pack_stage5(int precision, const double *y, int64_t ldy, int64_t Nt, int nvec,

@@ -83,6 +83,54 @@ constexpr int kRows = 64;                  // rows per workgroup (shared by its 
 constexpr int kSub = 64;                   // l-points per wave per step
 constexpr int kStep = kWaves * kSub;       // l-points per workgroup step
 
+
+// End of a workgroup: add the four waves' tiles (LDS `red`, [wave][row][kBW + 1]) and
+// store the workgroup's tile: the final result with one split, otherwise the split's
+// partial tile (added by split_reduce_kernel in split order).
+template <typename T>
+__device__ __forceinline__ void finish_tile(const T *red, T *__restrict__ Zpart, T *__restrict__ Zf,
+                                            int nsplit, int64_t Ntpad, int64_t row0) {
+    constexpr int kPer = (kRows * kBW) / kThreads;        // 8 entries per thread
+    T *dst = nsplit == 1 ? Zf : Zpart + int64_t(blockIdx.y) * Ntpad * kBW;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        const int row = e % kRows, j = e / kRows;
+        T acc = T(0);
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) acc += red[(w * kRows + row) * (kBW + 1) + j];
+        dst[int64_t(j) * Ntpad + row0 + row] = acc;
+    }
+}
+
+// Zf[e] = sum_{s < nsplit} Zpart[s][e] in split order; each thread owns 4 consecutive
+// entries and issues up to 8 splits' 16-byte loads before adding.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void split_reduce_kernel(const T *__restrict__ Zpart,
+                                                                T *__restrict__ Zf, int nsplit,
+                                                                int64_t n4, int64_t stride) {
+    const int64_t e4 = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (e4 >= n4) return;
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    for (int s0 = 0; s0 < nsplit; s0 += 8) {
+        T v[8][4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (s0 + u < nsplit) {
+                const T *src = Zpart + int64_t(s0 + u) * stride + 4 * e4;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v[u][t] = src[t];
+            }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (s0 + u < nsplit)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] += v[u][t];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Zf[4 * e4 + t] = acc[t];
+}
+
 // Skeleton shared by all precisions.  The workgroup owns rows [row0, row0 + 64) and the
 // l-range [l0, l1) of its split; each step stages 256 points (and the matching rows of
 // the stage-5 input block) in LDS and wave w contracts the 64-point sub-tile w.  At the
@@ -95,7 +143,7 @@ constexpr int kStep = kWaves * kSub;       // l-points per workgroup step
 template <int KIND, int D>
 __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
     const float *__restrict__ X, const float *__restrict__ Y, float *__restrict__ Z,
-    int64_t Ntpad, int64_t lchunk) {
+    float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
     __shared__ float sX[D][kStep];
     __shared__ float sY[kStep * (kBW + 1)];      // [l][j], reused for the reduction
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -169,16 +217,7 @@ __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
             red[(wave * kRows + row) * (kBW + 1) + i] = acc[rb][r];
         }
     __syncthreads();
-    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
-#pragma unroll
-    for (int q = 0; q < (kRows * kBW) / kThreads; ++q) {
-        const int e = threadIdx.x + q * kThreads;
-        const int row = e % kRows, j = e / kRows;
-        float v = 0.f;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) v += red[(w * kRows + row) * (kBW + 1) + j];
-        Zs[int64_t(j) * Ntpad + row0 + row] = v;
-    }
+    finish_tile<float>(red, Z, Zf, int(gridDim.y), Ntpad, row0);
 }
 
 // FP64: v_mfma_f64_16x16x4_f64, A = Gamma[16 rows][4 l], B = Y[4 l][16 cols]; A[i][k] and
@@ -188,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
 template <int KIND, int D>
 __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
     const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ Z,
-    int64_t Ntpad, int64_t lchunk) {
+    double *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
     extern __shared__ double sm64[];
     double *sX = sm64;                           // [D][kStep]
     double *sY = sm64 + D * kStep;               // [l][kBW + 1]; reduction reuses it all
@@ -264,16 +303,7 @@ __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
             red[(wave * kRows + row) * (kBW + 1) + 16 + i] = acc[rb][1][r];
         }
     __syncthreads();
-    double *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
-#pragma unroll
-    for (int q = 0; q < (kRows * kBW) / kThreads; ++q) {
-        const int e = threadIdx.x + q * kThreads;
-        const int row = e % kRows, j = e / kRows;
-        double v = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) v += red[(w * kRows + row) * (kBW + 1) + j];
-        Zs[int64_t(j) * Ntpad + row0 + row] = v;
-    }
+    finish_tile<double>(red, Z, Zf, int(gridDim.y), Ntpad, row0);
 }
 // staged tiles (points for up to 3 dimensions + the Y rows) and, afterwards, the reduction
 constexpr size_t kLds64 = std::max(size_t(3 * kStep + kStep * (kBW + 1)),
@@ -289,7 +319,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 template <int KIND, int D, bool X3>
 __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
     const float *__restrict__ X, const __bf16 *__restrict__ Yh, const __bf16 *__restrict__ Yl,
-    float *__restrict__ Z, int64_t Ntpad, int64_t lchunk) {
+    float *__restrict__ Z, float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
     constexpr int ldb = kStep + 8;               // bf16 row of one column (16-byte aligned)
     __shared__ float sX[D][kStep];
     __shared__ __attribute__((aligned(16))) __bf16 sYh[kBW * ldb];
@@ -372,21 +402,12 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
             red[(wave * kRows + row) * (kBW + 1) + i] = acc[rb][r];
         }
     __syncthreads();
-    float *Zs = Z + int64_t(blockIdx.y) * Ntpad * kBW;
-#pragma unroll
-    for (int q = 0; q < (kRows * kBW) / kThreads; ++q) {
-        const int e = threadIdx.x + q * kThreads;
-        const int row = e % kRows, j = e / kRows;
-        float v = 0.f;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) v += red[(w * kRows + row) * (kBW + 1) + j];
-        Zs[int64_t(j) * Ntpad + row0 + row] = v;
-    }
+    finish_tile<float>(red, Z, Zf, int(gridDim.y), Ntpad, row0);
 }
 
 template <int KIND, int D>
-void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, int nsplit,
-                 int64_t lchunk, hipStream_t s) {
+void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, void *Zf,
+                 int nsplit, int64_t lchunk, hipStream_t s) {
     dim3 grid(unsigned(P->Ntpad / kRows), unsigned(nsplit));
     if (precision == KL_F64) {
         static bool attr_set = false;
@@ -397,33 +418,35 @@ void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, i
         }
         hipLaunchKernelGGL((stage5_f64_kernel<KIND, D>), grid, dim3(kThreads), kLds64, s,
                            P->dX64, static_cast<const double *>(Y5), static_cast<double *>(Z5),
-                           P->Ntpad, lchunk);
+                           static_cast<double *>(Zf), P->Ntpad, lchunk);
     } else if (precision == KL_F32) {
         hipLaunchKernelGGL((stage5_f32_kernel<KIND, D>), grid, dim3(kThreads), 0, s,
                            P->dX32, static_cast<const float *>(Y5), static_cast<float *>(Z5),
-                           P->Ntpad, lchunk);
+                           static_cast<float *>(Zf), P->Ntpad, lchunk);
     } else {
         // BF16 operands: hi part at Y5, lo part right after it (Ntpad x kBW each)
         const __bf16 *yh = static_cast<const __bf16 *>(Y5);
         const __bf16 *yl = yh + P->Ntpad * kBW;
         if (precision == KL_BF16)
             hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, false>), grid, dim3(kThreads), 0, s,
-                               P->dX32, yh, yl, static_cast<float *>(Z5), P->Ntpad, lchunk);
+                               P->dX32, yh, yl, static_cast<float *>(Z5), static_cast<float *>(Zf),
+                               P->Ntpad, lchunk);
         else
             hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, true>), grid, dim3(kThreads), 0, s,
-                               P->dX32, yh, yl, static_cast<float *>(Z5), P->Ntpad, lchunk);
+                               P->dX32, yh, yl, static_cast<float *>(Z5), static_cast<float *>(Zf),
+                               P->Ntpad, lchunk);
     }
 }
 
 template <int D>
-void launch_dim(int precision, const kl_problem *P, const void *Y5, void *Z5, int nsplit,
-                int64_t lchunk, hipStream_t s) {
+void launch_dim(int precision, const kl_problem *P, const void *Y5, void *Z5, void *Zf,
+                int nsplit, int64_t lchunk, hipStream_t s) {
     switch (P->cov_kind) {
-    case KL_COV_EXP: launch_kind<KL_COV_EXP, D>(precision, P, Y5, Z5, nsplit, lchunk, s); break;
-    case KL_COV_SQEXP: launch_kind<KL_COV_SQEXP, D>(precision, P, Y5, Z5, nsplit, lchunk, s); break;
-    case KL_COV_EXP_L1: launch_kind<KL_COV_EXP_L1, D>(precision, P, Y5, Z5, nsplit, lchunk, s); break;
-    case KL_COV_CONST: launch_kind<KL_COV_CONST, D>(precision, P, Y5, Z5, nsplit, lchunk, s); break;
-    default: launch_kind<KL_COV_LIN, D>(precision, P, Y5, Z5, nsplit, lchunk, s); break;
+    case KL_COV_EXP: launch_kind<KL_COV_EXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    case KL_COV_SQEXP: launch_kind<KL_COV_SQEXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    case KL_COV_EXP_L1: launch_kind<KL_COV_EXP_L1, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    case KL_COV_CONST: launch_kind<KL_COV_CONST, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    default: launch_kind<KL_COV_LIN, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
     }
 }
 
@@ -453,13 +476,26 @@ int stage5_splits(int64_t Ntpad, int n_cu, int64_t *lchunk_out) {
     return int(nsplit);
 }
 
-int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, hipStream_t s) {
+int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
+                  hipStream_t s) {
     int64_t lchunk;
     const int nsplit = stage5_splits(P->Ntpad, P->n_cu, &lchunk);
     switch (P->hs.d) {
-    case 1: launch_dim<1>(precision, P, Y5, Z5, nsplit, lchunk, s); break;
-    case 2: launch_dim<2>(precision, P, Y5, Z5, nsplit, lchunk, s); break;
-    default: launch_dim<3>(precision, P, Y5, Z5, nsplit, lchunk, s); break;
+    case 1: launch_dim<1>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    case 2: launch_dim<2>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    default: launch_dim<3>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    }
+    if (nsplit > 1) {
+        const int64_t n4 = P->Ntpad * kBW / 4;
+        const dim3 g(unsigned((n4 + kThreads - 1) / kThreads));
+        if (precision == KL_F64)
+            hipLaunchKernelGGL(split_reduce_kernel<double>, g, dim3(kThreads), 0, s,
+                               static_cast<const double *>(Z5), static_cast<double *>(Zf), nsplit, n4,
+                               P->Ntpad * kBW);
+        else
+            hipLaunchKernelGGL(split_reduce_kernel<float>, g, dim3(kThreads), 0, s,
+                               static_cast<const float *>(Z5), static_cast<float *>(Zf), nsplit, n4,
+                               P->Ntpad * kBW);
     }
     return nsplit;
 }

@@ -43,8 +43,9 @@ struct Workspace {
     void *Y5f = nullptr;                   // stage-5 input, FP32; padding rows stay zero
     void *Y5b = nullptr;                   // stage-5 input, BF16 hi then lo part
     size_t y5_bytes = 0;
-    void *Z5 = nullptr;                    // stage-5 split partial sums
+    void *Z5 = nullptr;                    // stage-5 split partial sums (scratch)
     size_t z5_bytes = 0;
+    void *Zf = nullptr;                    // stage-5 output (column-major, ld Ntpad)
     int max_split = 1;
 };
 
@@ -120,6 +121,8 @@ void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t l
 int stage5_splits(int64_t Ntpad, int n_cu, int64_t *lchunk);
 // Stage 5: Z5[s][k][j] = sum_{l in split s} Gamma(x_k, x_l) Y5[l][j] for all k < Ntpad.
 // Returns the number of splits used.
-int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, hipStream_t s);
+// Stage 5: Zf[j][k] = sum_l Gamma(x_k, x_l) Y5[j][l]; Z5 holds split partials (scratch).
+int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
+                  hipStream_t s);
 
 }  // namespace kl

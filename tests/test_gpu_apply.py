@@ -163,8 +163,15 @@ def test_apply_errors():
     assert st == -1
     # nvec = 0 is a no-op
     assert kl.lib().kl_apply(G.handle, 0, 0, None, G.N, None, G.N, None) == 0
-    # more than 128 functions in one direction: rejected at setup with KL_EINVAL
-    with pytest.raises(kl.KLError) as e:
-        kl.Problem({"dim": 1, "degree": [2], "nelem": [200], "map": {"kind": "identity"},
-                    "cov": {"kind": "exp", "corr_len": [0.3]}})
-    assert e.value.status == -1
+
+
+
+def test_long_direction():
+    """A direction with several hundred basis functions (several MFMA chunks of the
+    contraction index) against the oracle."""
+    desc = {"dim": 1, "degree": [2], "nelem": [400], "map": {"kind": "identity"},
+            "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.3]}}
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    V = workloads.random_block(P.N, 3, seed=9)
+    assert _rel_max(_gpu_apply(G, V, "f64"), P.apply(V)) <= 1e-12
