@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=["f32", "f64"])
     ap.add_argument("--solves", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
+                    help="also run one plain device-to-device copy of MB MiB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -78,6 +81,12 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    if args.copy_calib > 0:
+        n = args.copy_calib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     desc, k, b = workloads.config(args.workload)
     prec = args.precision or "f32"
     G = kl.Problem(desc)

@@ -119,6 +119,14 @@ kl_status kl_apply(kl_problem *P, int32_t precision, int32_t nvec,
 kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec,
                     const double *y, int64_t ldy, double *z, int64_t ldz, void *stream);
 
+/* Stage-5 launch configuration for one kl_precision (used by the autotuner):
+ * rb = 32-row blocks per wave of the FP32/BF16 kernels (2 or 4; 0 keeps the current
+ * value; the FP64 kernel always uses four 16-row blocks); nsplit = number of l-splits
+ * (1..64 forces it, 0 = automatic load-balancing choice, -1 keeps the current setting).
+ * rb_out / nsplit_out (may be NULL) receive the effective values.  Errors: KL_EINVAL. */
+kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t nsplit,
+                           int32_t *rb_out, int32_t *nsplit_out);
+
 /* Copies of the setup data (host arrays, caller-owned):  X: Ntilde x dim row-major
  * physical Greville points; J: Ntilde weights sqrt(det DF); C: the nt_k x n_k
  * row-major composed factor of direction k (0-based).  Any output may be NULL. */

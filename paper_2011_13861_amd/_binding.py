@@ -24,6 +24,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
            "kl_get_factor", "kl_eigs", "kl_symeig", "kl_profile_enable", "kl_profile_read",
+           "kl_stage5_config",
            "kl_destroy", "kl_last_error"]
 
 
@@ -78,6 +79,7 @@ def lib():
                               ctypes.c_int64, ctypes.POINTER(KLEigsReport)]
         L.kl_symeig.argtypes = [ctypes.c_int32, P, P, P]
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
+        L.kl_stage5_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
         L.kl_profile_read.argtypes = [P, P, P]
         L.kl_destroy.argtypes = [P]
         L.kl_last_error.restype = ctypes.c_char_p
@@ -200,6 +202,14 @@ class Problem:
         C = np.zeros((self.nt[k], self.n[k]))
         check(lib().kl_get_factor(self._h, k, ctypes.c_void_p(C.ctypes.data)))
         return C
+
+    def stage5_config(self, precision, rb=0, nsplit=-1):
+        """Sets (rb, nsplit; 0/-1 keep) and returns the effective (rb, nsplit)."""
+        rbo = ctypes.c_int32()
+        nso = ctypes.c_int32()
+        check(lib().kl_stage5_config(self._h, PRECISIONS[precision], int(rb), int(nsplit),
+                                     ctypes.byref(rbo), ctypes.byref(nso)))
+        return rbo.value, nso.value
 
     def profile_enable(self, on=True):
         check(lib().kl_profile_enable(self._h, int(bool(on))))

@@ -237,8 +237,9 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
         }
     }
     for (int64_t p = 0; p < hs.Nt; ++p) jpad[p] = hs.J[p];
-    int64_t lchunk;
-    P->ws.max_split = stage5_splits(Np, P->n_cu, &lchunk);
+    // split partials: at most 64 splits, at most ~512 MB
+    P->ws.max_split = int(std::max<int64_t>(1, std::min<int64_t>(
+        std::min<int64_t>(64, Np / 64), (int64_t(512) << 20) / (Np * kBW * int64_t(sizeof(double))))));
     P->ws.t_elems = size_t(max_intermediate(hs)) * kBW;
     P->ws.y5_bytes = size_t(Np) * kBW * sizeof(double);
     P->ws.z5_bytes = size_t(P->ws.max_split) * Np * kBW * sizeof(double);
@@ -331,6 +332,23 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec, const double
         kl_status st = hip_check(hipGetLastError(), "kernel launch");
         if (st != KL_OK) return st;
     }
+    return KL_OK;
+}
+
+kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t nsplit,
+                           int32_t *rb_out, int32_t *nsplit_out) {
+    if (!P || P->host_only) { set_error("kl_stage5_config: NULL or host-only handle"); return KL_EINVAL; }
+    if (!valid_precision(precision)) { set_error("kl_stage5_config: bad precision"); return KL_EINVAL; }
+    if (rb != 0 && rb != 2 && rb != 4) { set_error("kl_stage5_config: rb must be 0, 2 or 4"); return KL_EINVAL; }
+    if (nsplit < -1 || nsplit > 64) { set_error("kl_stage5_config: nsplit must be in -1..64"); return KL_EINVAL; }
+    if (rb > 0) P->s5_rb[precision] = rb;
+    if (nsplit >= 0) P->s5_split[precision] = nsplit;
+    const int rbe = P->s5_rb[precision] == 4 ? 4 : 2;
+    int64_t lchunk;
+    const int ns = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rbe), P->n_cu, P->ws.max_split,
+                                 P->s5_split[precision], &lchunk);
+    if (rb_out) *rb_out = precision == KL_F64 ? 4 : rbe;
+    if (nsplit_out) *nsplit_out = ns;
     return KL_OK;
 }
 

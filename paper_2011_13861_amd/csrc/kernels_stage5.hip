@@ -79,26 +79,26 @@ __device__ __forceinline__ double gamma_f64(const double *xk, const double *xl) 
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kRows = 64;                  // rows per workgroup (shared by its 4 waves)
+constexpr int kRows = 64;                  // rows per FP64 workgroup (shared by its 4 waves)
 constexpr int kSub = 64;                   // l-points per wave per step
 constexpr int kStep = kWaves * kSub;       // l-points per workgroup step
 
 
-// End of a workgroup: add the four waves' tiles (LDS `red`, [wave][row][kBW + 1]) and
-// store the workgroup's tile: the final result with one split, otherwise the split's
-// partial tile (added by split_reduce_kernel in split order).
+// End of a workgroup: add the four waves' 32-row blocks (LDS `red`,
+// [wave][32 rows][kBW + 1]) and store the block: the final result with one split,
+// otherwise the split's partial (added by split_reduce_kernel in split order).
 template <typename T>
-__device__ __forceinline__ void finish_tile(const T *red, T *__restrict__ Zpart, T *__restrict__ Zf,
-                                            int nsplit, int64_t Ntpad, int64_t row0) {
-    constexpr int kPer = (kRows * kBW) / kThreads;        // 8 entries per thread
+__device__ __forceinline__ void finish_block(const T *red, T *__restrict__ Zpart, T *__restrict__ Zf,
+                                             int nsplit, int64_t Ntpad, int64_t row0) {
+    constexpr int kPer = (32 * kBW) / kThreads;          // 4 entries per thread
     T *dst = nsplit == 1 ? Zf : Zpart + int64_t(blockIdx.y) * Ntpad * kBW;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int e = threadIdx.x + q * kThreads;
-        const int row = e % kRows, j = e / kRows;
+        const int row = e % 32, j = e / 32;
         T acc = T(0);
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) acc += red[(w * kRows + row) * (kBW + 1) + j];
+        for (int w = 0; w < kWaves; ++w) acc += red[(w * 32 + row) * (kBW + 1) + j];
         dst[int64_t(j) * Ntpad + row0 + row] = acc;
     }
 }
@@ -140,56 +140,64 @@ __global__ __launch_bounds__(kThreads) void split_reduce_kernel(const T *__restr
 // FP32: v_mfma_f32_32x32x2_f32, A = Gamma[32 rows][2 l], B = Y[2 l][32 cols]; A[i][k] and
 // B[k][j] sit in lane (i or j) + 32 k; accumulator r of lane L holds
 // C[(r & 3) + 4 (L >> 5) + 8 (r >> 2)][L & 31].
-template <int KIND, int D>
+template <int KIND, int D, int RB>
 __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
     const float *__restrict__ X, const float *__restrict__ Y, float *__restrict__ Z,
     float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
+    constexpr int rows_wg = 32 * RB;
+    constexpr int kLd4 = (kStep * kBW / 4) / kThreads;   // float4 loads per thread per step
     __shared__ float sX[D][kStep];
-    __shared__ float sY[kStep * (kBW + 1)];      // [l][j], reused for the reduction
+    __shared__ float sY[kStep * (kBW + 1)];               // [l][j]; reused for the reduction
+    static_assert(kStep * (kBW + 1) >= 0, "");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 31, kh = lane >> 5;
-    const int64_t row0 = int64_t(blockIdx.x) * kRows;
+    const int64_t row0 = int64_t(blockIdx.x) * rows_wg;
     const int64_t l0 = int64_t(blockIdx.y) * lchunk;
     const int64_t l1 = min(l0 + lchunk, Ntpad);
-    float xk[2][D];
+    float xk[RB][D];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int k = 0; k < D; ++k) xk[rb][k] = X[k * Ntpad + row0 + rb * 32 + i];
-    floatx16 acc[2];
+    floatx16 acc[RB];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
-    for (int64_t lt = l0; lt < l1; lt += kStep) {
-        __syncthreads();
-        {
-            // 16-byte loads (4 consecutive l of one column), all issued before the stores
-            float4 v[(kStep * kBW / 4) / kThreads];
+    // prefetch registers: the next step's Y rows (16-byte loads) and points
+    float4 py[kLd4];
+    float px[D];
+    auto prefetch = [&](int64_t lt) {
 #pragma unroll
-            for (int q = 0; q < (kStep * kBW / 4) / kThreads; ++q) {
-                const int e = threadIdx.x + q * kThreads;
-                const int l4 = e % (kStep / 4), j = e / (kStep / 4);
-                const int64_t lg = lt + 4 * l4;
-                v[q] = lg < l1 ? *reinterpret_cast<const float4 *>(Y + int64_t(j) * Ntpad + lg)
-                               : float4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-            for (int q = 0; q < (kStep * kBW / 4) / kThreads; ++q) {
-                const int e = threadIdx.x + q * kThreads;
-                const int l4 = e % (kStep / 4), j = e / (kStep / 4);
-                sY[(4 * l4 + 0) * (kBW + 1) + j] = v[q].x;
-                sY[(4 * l4 + 1) * (kBW + 1) + j] = v[q].y;
-                sY[(4 * l4 + 2) * (kBW + 1) + j] = v[q].z;
-                sY[(4 * l4 + 3) * (kBW + 1) + j] = v[q].w;
-            }
+        for (int q = 0; q < kLd4; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int l4 = e % (kStep / 4), j = e / (kStep / 4);
+            const int64_t lg = lt + 4 * l4;
+            py[q] = lg < l1 ? *reinterpret_cast<const float4 *>(Y + int64_t(j) * Ntpad + lg)
+                            : float4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int64_t lg = lt + threadIdx.x;
-            sX[k][threadIdx.x] = lg < l1 ? X[k * Ntpad + lg] : 0.f;
+            px[k] = lg < l1 ? X[k * Ntpad + lg] : 0.f;
         }
+    };
+    prefetch(l0);
+    for (int64_t lt = l0; lt < l1; lt += kStep) {
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kLd4; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int l4 = e % (kStep / 4), j = e / (kStep / 4);
+            sY[(4 * l4 + 0) * (kBW + 1) + j] = py[q].x;
+            sY[(4 * l4 + 1) * (kBW + 1) + j] = py[q].y;
+            sY[(4 * l4 + 2) * (kBW + 1) + j] = py[q].z;
+            sY[(4 * l4 + 3) * (kBW + 1) + j] = py[q].w;
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) sX[k][threadIdx.x] = px[k];
+        __syncthreads();
+        if (lt + kStep < l1) prefetch(lt + kStep);       // lands while this step computes
         if (lt + wave * kSub < l1) {
             const int base = wave * kSub;
 #pragma unroll 8
@@ -199,25 +207,26 @@ __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
                 for (int k = 0; k < D; ++k) xl[k] = sX[k][base + ll + kh];
                 const float b = sY[(base + ll + kh) * (kBW + 1) + i];
 #pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
+                for (int rb = 0; rb < RB; ++rb) {
                     const float g = gamma_f32<KIND, D>(xk[rb], xl);
                     acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(g, b, acc[rb], 0, 0, 0);
                 }
             }
         }
     }
-    // ---- reduce the four waves in LDS and write the partial tile -----------------------
-    __syncthreads();
-    float *red = sY;                             // [wave][row][kBW + 1]
+    // ---- reduce the four waves (one 32-row block at a time) and write ------------------
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb) {
+        __syncthreads();
+        float *red = sY;                                  // [wave][32 rows][kBW + 1]
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int row = rb * 32 + (r & 3) + 4 * kh + 8 * (r >> 2);
-            red[(wave * kRows + row) * (kBW + 1) + i] = acc[rb][r];
+            const int row = (r & 3) + 4 * kh + 8 * (r >> 2);
+            red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][r];
         }
-    __syncthreads();
-    finish_tile<float>(red, Z, Zf, int(gridDim.y), Ntpad, row0);
+        __syncthreads();
+        finish_block<float>(red, Z, Zf, int(gridDim.y), Ntpad, row0 + rb * 32);
+    }
 }
 
 // FP64: v_mfma_f64_16x16x4_f64, A = Gamma[16 rows][4 l], B = Y[4 l][16 cols]; A[i][k] and
@@ -292,22 +301,23 @@ __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
             }
         }
     }
-    __syncthreads();
-    double *red = sm64;                          // [wave][row][kBW + 1]
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int half = 0; half < 2; ++half) {
+        __syncthreads();
+        double *red = sm64;                               // [wave][32 rows][kBW + 1]
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = rb * 16 + kq + 4 * r;
-            red[(wave * kRows + row) * (kBW + 1) + i] = acc[rb][0][r];
-            red[(wave * kRows + row) * (kBW + 1) + 16 + i] = acc[rb][1][r];
-        }
-    __syncthreads();
-    finish_tile<double>(red, Z, Zf, int(gridDim.y), Ntpad, row0);
+        for (int rb = 2 * half; rb < 2 * half + 2; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = (rb - 2 * half) * 16 + kq + 4 * r;
+                red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][0][r];
+                red[(wave * 32 + row) * (kBW + 1) + 16 + i] = acc[rb][1][r];
+            }
+        __syncthreads();
+        finish_block<double>(red, Z, Zf, int(gridDim.y), Ntpad, row0 + 32 * half);
+    }
 }
-// staged tiles (points for up to 3 dimensions + the Y rows) and, afterwards, the reduction
-constexpr size_t kLds64 = std::max(size_t(3 * kStep + kStep * (kBW + 1)),
-                                   size_t(kWaves) * kRows * (kBW + 1)) * sizeof(double);
+constexpr size_t kLds64 = size_t(3 * kStep + kStep * (kBW + 1)) * sizeof(double);
 
 // BF16: v_mfma_f32_32x32x16_bf16, A = Gamma[32 rows][16 l], B = Y[16 l][32 cols];
 // A[i][k] in lane i + 32 (k / 8), element k % 8; B[k][j] in lane j + 32 (k / 8), element
@@ -316,52 +326,67 @@ constexpr size_t kLds64 = std::max(size_t(3 * kStep + kStep * (kBW + 1)),
 // into hi + lo BF16 parts and hi hi + hi lo + lo hi are accumulated.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <int KIND, int D, bool X3>
+template <int KIND, int D, int RB, bool X3>
 __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
     const float *__restrict__ X, const __bf16 *__restrict__ Yh, const __bf16 *__restrict__ Yl,
     float *__restrict__ Z, float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
+    constexpr int rows_wg = 32 * RB;
     constexpr int ldb = kStep + 8;               // bf16 row of one column (16-byte aligned)
+    constexpr int kLd = (kBW * kStep / 8) / kThreads;   // 16-byte loads per thread per step
     __shared__ float sX[D][kStep];
     __shared__ __attribute__((aligned(16))) __bf16 sYh[kBW * ldb];
     __shared__ __attribute__((aligned(16))) __bf16 sYl[X3 ? kBW * ldb : 8];
-    __shared__ float red[kWaves * kRows * (kBW + 1)];
+    __shared__ float red[kWaves * 32 * (kBW + 1)];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 31, kh = lane >> 5;
-    const int64_t row0 = int64_t(blockIdx.x) * kRows;
+    const int64_t row0 = int64_t(blockIdx.x) * rows_wg;
     const int64_t l0 = int64_t(blockIdx.y) * lchunk;
     const int64_t l1 = min(l0 + lchunk, Ntpad);
-    float xk[2][D];
+    float xk[RB][D];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int k = 0; k < D; ++k) xk[rb][k] = X[k * Ntpad + row0 + rb * 32 + i];
-    floatx16 acc[2];
+    floatx16 acc[RB];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
-    for (int64_t lt = l0; lt < l1; lt += kStep) {
-        __syncthreads();
-        // 32 columns x 32 segments of 8 consecutive l (16 bytes)
+    int4 ph[kLd], pl[kLd];
+    float px[D];
+    auto prefetch = [&](int64_t lt) {
 #pragma unroll
-        for (int q = 0; q < (kBW * kStep / 8) / kThreads; ++q) {
+        for (int q = 0; q < kLd; ++q) {
             const int e = threadIdx.x + q * kThreads;
             const int j = e / (kStep / 8), seg = e % (kStep / 8);
             const int64_t lg = lt + 8 * seg;
-            int4 vh = {0, 0, 0, 0}, vl = {0, 0, 0, 0};
+            ph[q] = int4{0, 0, 0, 0};
+            pl[q] = int4{0, 0, 0, 0};
             if (lg < l1) {
-                vh = *reinterpret_cast<const int4 *>(Yh + int64_t(j) * Ntpad + lg);
-                if constexpr (X3) vl = *reinterpret_cast<const int4 *>(Yl + int64_t(j) * Ntpad + lg);
+                ph[q] = *reinterpret_cast<const int4 *>(Yh + int64_t(j) * Ntpad + lg);
+                if constexpr (X3) pl[q] = *reinterpret_cast<const int4 *>(Yl + int64_t(j) * Ntpad + lg);
             }
-            *reinterpret_cast<int4 *>(&sYh[j * ldb + 8 * seg]) = vh;
-            if constexpr (X3) *reinterpret_cast<int4 *>(&sYl[j * ldb + 8 * seg]) = vl;
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int64_t lg = lt + threadIdx.x;
-            sX[k][threadIdx.x] = lg < l1 ? X[k * Ntpad + lg] : 0.f;
+            px[k] = lg < l1 ? X[k * Ntpad + lg] : 0.f;
         }
+    };
+    prefetch(l0);
+    for (int64_t lt = l0; lt < l1; lt += kStep) {
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kLd; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int j = e / (kStep / 8), seg = e % (kStep / 8);
+            *reinterpret_cast<int4 *>(&sYh[j * ldb + 8 * seg]) = ph[q];
+            if constexpr (X3) *reinterpret_cast<int4 *>(&sYl[j * ldb + 8 * seg]) = pl[q];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) sX[k][threadIdx.x] = px[k];
+        __syncthreads();
+        if (lt + kStep < l1) prefetch(lt + kStep);
         if (lt + wave * kSub < l1) {
             const int base = wave * kSub;
 #pragma unroll
@@ -376,7 +401,7 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
                 bf16x8 bl;
                 if constexpr (X3) bl = *reinterpret_cast<const bf16x8 *>(&sYl[i * ldb + lb]);
 #pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
+                for (int rb = 0; rb < RB; ++rb) {
                     bf16x8 ah, al;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
@@ -393,22 +418,24 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
             }
         }
     }
-    __syncthreads();
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb) {
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int row = rb * 32 + (r & 3) + 4 * kh + 8 * (r >> 2);
-            red[(wave * kRows + row) * (kBW + 1) + i] = acc[rb][r];
+            const int row = (r & 3) + 4 * kh + 8 * (r >> 2);
+            red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][r];
         }
-    __syncthreads();
-    finish_tile<float>(red, Z, Zf, int(gridDim.y), Ntpad, row0);
+        __syncthreads();
+        finish_block<float>(red, Z, Zf, int(gridDim.y), Ntpad, row0 + rb * 32);
+    }
 }
 
 template <int KIND, int D>
 void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, void *Zf,
-                 int nsplit, int64_t lchunk, hipStream_t s) {
-    dim3 grid(unsigned(P->Ntpad / kRows), unsigned(nsplit));
+                 int nsplit, int64_t lchunk, int rb, hipStream_t s) {
+    const int64_t rows_wg = stage5_rows_per_wg(precision, rb);
+    dim3 grid(unsigned(P->Ntpad / rows_wg), unsigned(nsplit));
     if (precision == KL_F64) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -420,55 +447,68 @@ void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, v
                            P->dX64, static_cast<const double *>(Y5), static_cast<double *>(Z5),
                            static_cast<double *>(Zf), P->Ntpad, lchunk);
     } else if (precision == KL_F32) {
-        hipLaunchKernelGGL((stage5_f32_kernel<KIND, D>), grid, dim3(kThreads), 0, s,
-                           P->dX32, static_cast<const float *>(Y5), static_cast<float *>(Z5),
-                           static_cast<float *>(Zf), P->Ntpad, lchunk);
+        if (rb == 4)
+            hipLaunchKernelGGL((stage5_f32_kernel<KIND, D, 4>), grid, dim3(kThreads), 0, s, P->dX32,
+                               static_cast<const float *>(Y5), static_cast<float *>(Z5),
+                               static_cast<float *>(Zf), P->Ntpad, lchunk);
+        else
+            hipLaunchKernelGGL((stage5_f32_kernel<KIND, D, 2>), grid, dim3(kThreads), 0, s, P->dX32,
+                               static_cast<const float *>(Y5), static_cast<float *>(Z5),
+                               static_cast<float *>(Zf), P->Ntpad, lchunk);
     } else {
         // BF16 operands: hi part at Y5, lo part right after it (Ntpad x kBW each)
         const __bf16 *yh = static_cast<const __bf16 *>(Y5);
         const __bf16 *yl = yh + P->Ntpad * kBW;
-        if (precision == KL_BF16)
-            hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, false>), grid, dim3(kThreads), 0, s,
-                               P->dX32, yh, yl, static_cast<float *>(Z5), static_cast<float *>(Zf),
-                               P->Ntpad, lchunk);
-        else
-            hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, true>), grid, dim3(kThreads), 0, s,
-                               P->dX32, yh, yl, static_cast<float *>(Z5), static_cast<float *>(Zf),
-                               P->Ntpad, lchunk);
+        float *z = static_cast<float *>(Z5), *zf = static_cast<float *>(Zf);
+        const bool x3 = precision == KL_BF16X3;
+#define KL_BF(RB_, X3_) hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, RB_, X3_>), grid, dim3(kThreads), \
+                                           0, s, P->dX32, yh, yl, z, zf, P->Ntpad, lchunk)
+        if (rb == 4) { if (x3) KL_BF(4, true); else KL_BF(4, false); }
+        else { if (x3) KL_BF(2, true); else KL_BF(2, false); }
+#undef KL_BF
     }
 }
 
 template <int D>
 void launch_dim(int precision, const kl_problem *P, const void *Y5, void *Z5, void *Zf,
-                int nsplit, int64_t lchunk, hipStream_t s) {
+                int nsplit, int64_t lchunk, int rb, hipStream_t s) {
     switch (P->cov_kind) {
-    case KL_COV_EXP: launch_kind<KL_COV_EXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
-    case KL_COV_SQEXP: launch_kind<KL_COV_SQEXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
-    case KL_COV_EXP_L1: launch_kind<KL_COV_EXP_L1, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
-    case KL_COV_CONST: launch_kind<KL_COV_CONST, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
-    default: launch_kind<KL_COV_LIN, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    case KL_COV_EXP: launch_kind<KL_COV_EXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
+    case KL_COV_SQEXP: launch_kind<KL_COV_SQEXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
+    case KL_COV_EXP_L1: launch_kind<KL_COV_EXP_L1, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
+    case KL_COV_CONST: launch_kind<KL_COV_CONST, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
+    default: launch_kind<KL_COV_LIN, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
     }
 }
 
 }  // namespace
 
+// Rows owned by one stage-5 workgroup: 32 RB for the FP32 and BF16 kernels, 64 for FP64.
+int64_t stage5_rows_per_wg(int precision, int rb) { return precision == KL_F64 ? 64 : 32 * rb; }
+
 // Number of l-splits.  Each workgroup has 4 waves; a split count S gives 4 R S waves
 // (R = row tiles) over the 4 SIMDs of every CU.  S minimises the busiest SIMD's share,
 // ceil(4 R S / SIMDs) / S, plus a small charge per split for the partial sums, among the
-// counts that put at least 1.5 waves on every SIMD when that is possible.
-int stage5_splits(int64_t Ntpad, int n_cu, int64_t *lchunk_out) {
-    const int64_t R = Ntpad / kRows;
+// counts that put at least 1.5 waves on every SIMD when that is possible.  `forced` > 0
+// overrides the choice (autotuning).
+int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int forced,
+                  int64_t *lchunk_out) {
+    const int64_t R = Ntpad / rows_wg;
     const int64_t simds = 4 * int64_t(n_cu);
-    const int64_t max_split = std::min<int64_t>(64, Ntpad / kSub);
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(max_split, Ntpad / kSub));
     int64_t best = 1;
-    double best_cost = 1e300;
-    bool any_full = false;
-    for (int64_t S = 1; S <= max_split; ++S) if (4 * R * S * 2 >= 3 * simds) { any_full = true; break; }
-    for (int64_t S = 1; S <= max_split; ++S) {
-        const int64_t waves = 4 * R * S;
-        if (any_full && waves * 2 < 3 * simds) continue;
-        const double cost = double((waves + simds - 1) / simds) / double(S) + 0.01 * double(S);
-        if (cost < best_cost - 1e-12) { best_cost = cost; best = S; }
+    if (forced > 0) {
+        best = std::min<int64_t>(forced, cap);
+    } else {
+        double best_cost = 1e300;
+        bool any_full = false;
+        for (int64_t S = 1; S <= cap; ++S) if (4 * R * S * 2 >= 3 * simds) { any_full = true; break; }
+        for (int64_t S = 1; S <= cap; ++S) {
+            const int64_t waves = 4 * R * S;
+            if (any_full && waves * 2 < 3 * simds) continue;
+            const double cost = double((waves + simds - 1) / simds) / double(S) + 0.01 * double(S);
+            if (cost < best_cost - 1e-12) { best_cost = cost; best = S; }
+        }
     }
     int64_t lchunk = ((Ntpad + best - 1) / best + kSub - 1) / kSub * kSub;
     const int64_t nsplit = (Ntpad + lchunk - 1) / lchunk;
@@ -478,12 +518,14 @@ int stage5_splits(int64_t Ntpad, int n_cu, int64_t *lchunk_out) {
 
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
                   hipStream_t s) {
+    const int rb = P->s5_rb[precision] == 4 ? 4 : 2;
     int64_t lchunk;
-    const int nsplit = stage5_splits(P->Ntpad, P->n_cu, &lchunk);
+    const int nsplit = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rb), P->n_cu,
+                                     P->ws.max_split, P->s5_split[precision], &lchunk);
     switch (P->hs.d) {
-    case 1: launch_dim<1>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
-    case 2: launch_dim<2>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
-    default: launch_dim<3>(precision, P, Y5, Z5, Zf, nsplit, lchunk, s); break;
+    case 1: launch_dim<1>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
+    case 2: launch_dim<2>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
+    default: launch_dim<3>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
     }
     if (nsplit > 1) {
         const int64_t n4 = P->Ntpad * kBW / 4;

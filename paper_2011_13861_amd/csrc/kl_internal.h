@@ -66,6 +66,10 @@ struct kl_problem {
     kl::Workspace ws;
     int n_cu = 256;
     bool host_only = false;   // built by kl_setup_host: no device data
+    // stage-5 tuning per kl_precision: 32-row blocks per wave (2 or 4) and forced split
+    // count (0 = automatic); set by kl_stage5_config
+    int s5_rb[4] = {2, 2, 2, 2};
+    int s5_split[4] = {0, 0, 0, 0};
     // optional stage-5 timing with HIP events (kl_profile_enable / kl_profile_read)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;      // pool: 2 events per timed launch
@@ -117,8 +121,11 @@ int gram_splits(int64_t N, int m, int c, int n_cu);
 void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int c,
                  int64_t N, double *part, double *C, int n_cu, hipStream_t s);
 
-// Number of l-splits of stage 5 for a padded grid; *lchunk receives the l-range length.
-int stage5_splits(int64_t Ntpad, int n_cu, int64_t *lchunk);
+// Stage-5 launch geometry: rows per workgroup, and the number of l-splits (forced > 0
+// overrides the automatic choice); *lchunk receives the l-range length of one split.
+int64_t stage5_rows_per_wg(int precision, int rb);
+int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int forced,
+                  int64_t *lchunk);
 // Stage 5: Z5[s][k][j] = sum_{l in split s} Gamma(x_k, x_l) Y5[l][j] for all k < Ntpad.
 // Returns the number of splits used.
 // Stage 5: Zf[j][k] = sum_l Gamma(x_k, x_l) Y5[j][l]; Z5 holds split partials (scratch).
