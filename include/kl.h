@@ -105,6 +105,13 @@ kl_status kl_setup_host(const kl_desc *desc, kl_problem **out);
  * be NULL. */
 kl_status kl_info(const kl_problem *P, int64_t *N, int64_t *Ntilde, int32_t *n, int32_t *nt);
 
+/* Replaces the covariance of an existing problem (Sec. 4.3: the kernel enters only
+ * through stage 5): kind, variance sigma2 > 0 and correlation lengths corr_len[0..dim-1]
+ * > 0 (host array).  Mesh, map and the Kronecker factors are kept, so a sweep over
+ * covariance parameters costs one small upload per value.  Waits for outstanding device
+ * work before it replaces the scaled points.  Errors: KL_EINVAL, KL_EHIP. */
+kl_status kl_set_cov(kl_problem *P, int32_t cov_kind, double sigma2, const double *corr_len);
+
 /* y = A~' x for nvec columns (Algorithm 1): forward Kronecker stages 1-4 (composed
  * into one factor per direction), stage 5 in the given kl_precision, backward stages
  * 6-9.  x, y: device, FP64, column-major, ld >= N; x and y must not overlap.
@@ -163,7 +170,10 @@ typedef struct {
  * x0: optional device FP64 start block (N x nvec0, ld N), or NULL for a seeded random
  * start.  evals: host, k values.  evecs: device FP64, N x k, leading dimension ldv;
  * unit 2-norm columns v' (so phi_h has unit L2 norm, Sec. 4.1).  rep may be NULL.
- * Synchronous.  On KL_ENOCONV evals/evecs hold the best Ritz pairs found. */
+ * Synchronous.  On KL_ENOCONV evals/evecs hold the best Ritz pairs found.
+ * The solver's device buffers, stream and rocBLAS handle are created on the first call
+ * and kept with the handle (grown when a later call needs more) until kl_destroy, so
+ * calls on one handle must not overlap. */
 kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0, int32_t nvec0,
                   double *evals, double *evecs, int64_t ldv, kl_eigs_report *rep);
 
@@ -183,6 +193,51 @@ kl_status kl_profile_read(kl_problem *P, int64_t *count, double *ms);
  * Householder tridiagonalisation + implicit QR with Wilkinson shifts.
  * Errors: KL_EINVAL, KL_ENUMERIC (non-finite input), KL_ENOCONV. */
 kl_status kl_symeig(int32_t n, const double *A, double *w, double *Z);
+
+/* ---- Warm-start network -----------------------------------------------------------
+ * A multilayer perceptron that maps covariance parameters to a block of leading
+ * eigenvector coefficients, used as the start block of kl_eigs.  It is an addition to
+ * the method (the paper starts its Lanczos iteration from a generic vector, Sec. 4.4.2).
+ * Layers l = 0..n_layers-1 map sizes[l] -> sizes[l+1]; hidden layers apply tanh, the
+ * output layer is linear.  Parameters (device, FP32, flat): per layer W_l (sizes[l] x
+ * sizes[l+1], row-major) then b_l (sizes[l+1]).  Inputs and outputs are row-major FP32
+ * device arrays, one row per sample.  Calls on one handle must not overlap. */
+typedef struct kl_mlp kl_mlp;
+
+/* Creates the network: W_l ~ U(-1/sqrt(sizes[l]), 1/sqrt(sizes[l])) drawn from
+ * splitmix64(seed), b_l = 0, Adam moments zero.  sizes: host array of n_layers + 1
+ * widths (1..2^24), 1 <= n_layers <= 16.  Errors: KL_EINVAL, KL_ENOMEM, KL_EHIP. */
+kl_status kl_mlp_create(int32_t n_layers, const int32_t *sizes, uint64_t seed, kl_mlp **out);
+kl_status kl_mlp_num_params(const kl_mlp *M, int64_t *n);
+/* Host copies of the flat parameter vector; set also clears the Adam state. */
+kl_status kl_mlp_set_params(kl_mlp *M, const float *params);
+kl_status kl_mlp_get_params(const kl_mlp *M, float *params);
+
+/* y (batch x sizes[n_layers]) = network(x (batch x sizes[0])).  Asynchronous on
+ * stream; grows internal activation buffers on first use of a larger batch. */
+kl_status kl_mlp_forward(kl_mlp *M, int32_t batch, const float *x, float *y, void *stream);
+
+/* Loss and gradients for one batch (no update).  group = 0: loss = 0.5/B sum (y - t)^2;
+ * group = g > 0 (g divides the output width): every output row is split into groups of
+ * g values (one eigenvector each) and loss = 0.5/B sum_groups min_{s=+-1} ||y_g - s t_g||^2,
+ * s = +1 when <y_g, t_g> >= 0 (eigenvectors are defined up to sign).  The gradients are
+ * kept for kl_mlp_adam and, if grads != NULL, copied there (device, flat layout).
+ * loss (host, may be NULL) receives the batch loss; then the call waits for the stream. */
+kl_status kl_mlp_gradients(kl_mlp *M, int32_t batch, const float *x, const float *t, int32_t group,
+                           double *loss, float *grads, void *stream);
+
+/* One Adam step (Kingma and Ba, with bias correction) with the last gradients. */
+kl_status kl_mlp_adam(kl_mlp *M, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Minibatch training on n samples x (n x sizes[0]) and targets t (n x sizes[L]), both
+ * device: per epoch a splitmix64(seed) shuffle, batches of `batch` rows (the last may be
+ * smaller), loss as in kl_mlp_gradients, Adam (0.9, 0.999, 1e-8) with a learning rate
+ * going geometrically from lr0 (first epoch) to lr1 (last).  epoch_loss (host, epochs
+ * values, may be NULL) receives the mean per-sample loss of each epoch.  Synchronous.
+ * Errors: KL_EINVAL, KL_ENOMEM, KL_EHIP, KL_ENUMERIC (non-finite loss). */
+kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int32_t group, int32_t epochs,
+                       int32_t batch, float lr0, float lr1, uint64_t seed, double *epoch_loss, void *stream);
+kl_status kl_mlp_destroy(kl_mlp *M);
 
 /* Releases the handle and every device buffer it owns.  NULL is accepted. */
 kl_status kl_destroy(kl_problem *P);

@@ -4,7 +4,11 @@ TEST INFRASTRUCTURE ONLY.  Not a paper construct: the warm-start network is an a
 to the method (the paper starts its Lanczos iteration from a generic vector, Sec. 4.4.2).
 This module is the gradient oracle for the GPU training kernels:
   forward   h_0 = x,  z_l = h_{l-1} W_l + b_l,  h_l = tanh(z_l) (hidden), output z_L
-  loss      0.5 / B * sum (z_L - T)^2    (mean over the batch, summed over outputs)
+  loss      0.5 / B * sum (z_L - T)^2    (mean over the batch, summed over outputs);
+            with `group` = g, each output row is split into consecutive groups of g values
+            (one eigenvector each) and every group is compared with the sign of its target
+            that fits best: 0.5 / B * sum_groups min_{s = +-1} ||y_g - s t_g||^2, where
+            s = +1 when <y_g, t_g> >= 0 (eigenvectors are defined up to sign)
   backward  the chain rule written out layer by layer
   adam      Kingma and Ba (2015) with bias correction.
 Pinned by central differences (tests/test_oracle_mlp.py), which do not use the backward code.
@@ -34,18 +38,35 @@ def forward(params, x):
     return hs[-1], hs
 
 
-def loss(params, x, T):
+def group_signs(y, T, group):
+    """Per-row, per-group sign s = +1 if <y_g, t_g> >= 0 else -1 (shape B x n_groups)."""
+    B, n = y.shape
+    dots = np.einsum("bgi,bgi->bg", y.reshape(B, n // group, group), T.reshape(B, n // group, group))
+    return np.where(dots >= 0.0, 1.0, -1.0)
+
+
+def signed_target(y, T, group):
+    """The target with every group's sign aligned to the output (T itself if group is None)."""
+    if group is None:
+        return T
+    B, n = y.shape
+    s = group_signs(y, T, group)
+    return (T.reshape(B, n // group, group) * s[:, :, None]).reshape(B, n)
+
+
+def loss(params, x, T, group=None):
     y, _ = forward(params, x)
-    return 0.5 * np.sum((y - T) ** 2) / x.shape[0]
+    return 0.5 * np.sum((y - signed_target(y, T, group)) ** 2) / x.shape[0]
 
 
-def backward(params, x, T):
-    """Gradients [(dW_l, db_l)] of `loss` by the chain rule."""
+def backward(params, x, T, group=None):
+    """Gradients [(dW_l, db_l)] of `loss` by the chain rule (the group signs are
+    piecewise constant, so they are held fixed in the derivative)."""
     y, hs = forward(params, x)
     B = x.shape[0]
     L = len(params)
     grads = [None] * L
-    delta = (y - T) / B                          # dloss / dz_L
+    delta = (y - signed_target(y, T, group)) / B      # dloss / dz_L
     for l in range(L - 1, -1, -1):
         W, _ = params[l]
         grads[l] = [hs[l].T @ delta, delta.sum(axis=0)]

@@ -24,7 +24,9 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
            "kl_get_factor", "kl_eigs", "kl_symeig", "kl_profile_enable", "kl_profile_read",
-           "kl_stage5_config",
+           "kl_stage5_config", "kl_set_cov",
+           "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
+           "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_destroy",
            "kl_destroy", "kl_last_error"]
 
 
@@ -81,6 +83,18 @@ def lib():
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
         L.kl_stage5_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
         L.kl_profile_read.argtypes = [P, P, P]
+        L.kl_set_cov.argtypes = [P, ctypes.c_int32, ctypes.c_double, P]
+        L.kl_mlp_create.argtypes = [ctypes.c_int32, P, ctypes.c_uint64, ctypes.POINTER(P)]
+        L.kl_mlp_num_params.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+        L.kl_mlp_set_params.argtypes = [P, P]
+        L.kl_mlp_get_params.argtypes = [P, P]
+        L.kl_mlp_forward.argtypes = [P, ctypes.c_int32, P, P, P]
+        L.kl_mlp_gradients.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), P, P]
+        L.kl_mlp_adam.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
+        L.kl_mlp_train.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P, P]
+        L.kl_mlp_destroy.argtypes = [P]
         L.kl_destroy.argtypes = [P]
         L.kl_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -203,6 +217,11 @@ class Problem:
         check(lib().kl_get_factor(self._h, k, ctypes.c_void_p(C.ctypes.data)))
         return C
 
+    def set_cov(self, kind, sigma2, corr_len):
+        """Replaces the covariance (kind name, variance, per-direction lengths)."""
+        ell = (ctypes.c_double * 3)(*([float(v) for v in corr_len] + [1.0] * 3)[:3])
+        check(lib().kl_set_cov(self._h, COV_KINDS[kind], float(sigma2), ell))
+
     def stage5_config(self, precision, rb=0, nsplit=-1):
         """Sets (rb, nsplit; 0/-1 keep) and returns the effective (rb, nsplit)."""
         rbo = ctypes.c_int32()
@@ -239,6 +258,82 @@ class Problem:
         if st not in (KL_OK, KL_ENOCONV):
             check(st)
         return ev, V, report_dict(rep, st)
+
+
+class MLP:
+    """Owns one kl_mlp handle: a tanh network sizes[0] -> ... -> sizes[-1] trained on the
+    GPU (kl_mlp_*).  Inputs and outputs are row-major FP32 CUDA tensors."""
+
+    def __init__(self, sizes, seed=0):
+        self._h = ctypes.c_void_p()
+        self.sizes = [int(v) for v in sizes]
+        arr = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
+        check(lib().kl_mlp_create(len(self.sizes) - 1, arr, int(seed), ctypes.byref(self._h)))
+        n = ctypes.c_int64()
+        check(lib().kl_mlp_num_params(self._h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if self._h:
+            lib().kl_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        if flat.size != self.n_params:
+            raise ValueError("expected %d parameters" % self.n_params)
+        check(lib().kl_mlp_set_params(self._h, ctypes.c_void_p(flat.ctypes.data)))
+
+    def get_params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        check(lib().kl_mlp_get_params(self._h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def forward(self, x, stream=None):
+        import torch
+        x = _rows_f32(x, self.sizes[0])
+        y = torch.empty((x.shape[0], self.sizes[-1]), dtype=torch.float32, device=x.device)
+        check(lib().kl_mlp_forward(self._h, x.shape[0], _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def gradients(self, x, t, group=0, stream=None):
+        """(batch loss, flat device gradients)."""
+        import torch
+        x = _rows_f32(x, self.sizes[0])
+        t = _rows_f32(t, self.sizes[-1])
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_double()
+        check(lib().kl_mlp_gradients(self._h, x.shape[0], _ptr(x), _ptr(t), int(group), ctypes.byref(loss),
+                                     _ptr(g), _stream(stream)))
+        return loss.value, g
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        check(lib().kl_mlp_adam(self._h, lr, beta1, beta2, eps, _stream(stream)))
+
+    def train(self, x, t, group=0, epochs=100, batch=64, lr0=1e-3, lr1=1e-4, seed=0, stream=None):
+        """Minibatch Adam training; returns the per-epoch mean loss (numpy)."""
+        x = _rows_f32(x, self.sizes[0])
+        t = _rows_f32(t, self.sizes[-1])
+        if x.shape[0] != t.shape[0]:
+            raise ValueError("x and t need the same number of rows")
+        losses = np.zeros(int(epochs))
+        check(lib().kl_mlp_train(self._h, x.shape[0], _ptr(x), _ptr(t), int(group), int(epochs), int(batch),
+                                 float(lr0), float(lr1), int(seed), ctypes.c_void_p(losses.ctypes.data),
+                                 _stream(stream)))
+        return losses
+
+
+def _rows_f32(t, width):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or t.dim() != 2 or t.shape[1] != width or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA float32 tensor of shape (rows, %d)" % width)
+    return t
 
 
 def symeig(A):

@@ -33,6 +33,7 @@ kl_status dev_alloc(T **p, size_t count, const char *what) {
 
 void free_problem(kl_problem *P) {
     if (!P) return;
+    free_solver_cache(P->solver);
     for (hipEvent_t e : P->prof_ev) hipEventDestroy(e);
     hipFree(P->dX64);
     hipFree(P->dX32);
@@ -77,6 +78,29 @@ int64_t max_intermediate(const HostSetup &hs) {
 }
 
 bool valid_precision(int precision) { return precision >= KL_F64 && precision <= KL_BF16X3; }
+
+// Scaled Greville points for the stage-5 kernels (Sec. 4.3): X / ell per direction for
+// the FP64 kernel, with log2(e) absorbed for the exp2-based FP32 / BF16 kernels.  The
+// padding points stay zero (their rows and columns carry zero weight).
+kl_status upload_points(kl_problem *P) {
+    const HostSetup &hs = P->hs;
+    const int d = hs.d;
+    const int64_t Np = P->Ntpad;
+    std::vector<double> x64(size_t(d) * Np, 0.0);
+    std::vector<float> x32(size_t(d) * Np, 0.f);
+    for (int k = 0; k < d; ++k) {
+        const double s64 = coord_scale(P->cov_kind, P->ell[k], false);
+        const double s32 = coord_scale(P->cov_kind, P->ell[k], true);
+        for (int64_t p = 0; p < hs.Nt; ++p) {
+            const double v = hs.X[size_t(p) * d + k];
+            x64[size_t(k) * Np + p] = v * s64;
+            x32[size_t(k) * Np + p] = float(v * s32);
+        }
+    }
+    kl_status st = hip_check(hipMemcpy(P->dX64, x64.data(), x64.size() * 8, hipMemcpyHostToDevice), "copy X64");
+    if (st != KL_OK) return st;
+    return hip_check(hipMemcpy(P->dX32, x32.data(), x32.size() * 4, hipMemcpyHostToDevice), "copy X32");
+}
 
 void *stage5_input(kl_problem *P, int precision) {
     switch (precision) {
@@ -224,19 +248,6 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
         P->n_cu = ncu;
     const int64_t Np = P->Ntpad;
     const int d = hs.d;
-    // host staging of the device arrays
-    std::vector<double> x64(size_t(d) * Np, 0.0), jpad(size_t(Np), 0.0);
-    std::vector<float> x32(size_t(d) * Np, 0.f);
-    for (int k = 0; k < d; ++k) {
-        const double s64 = coord_scale(P->cov_kind, P->ell[k], false);
-        const double s32 = coord_scale(P->cov_kind, P->ell[k], true);
-        for (int64_t p = 0; p < hs.Nt; ++p) {
-            const double v = hs.X[size_t(p) * d + k];
-            x64[size_t(k) * Np + p] = v * s64;
-            x32[size_t(k) * Np + p] = float(v * s32);
-        }
-    }
-    for (int64_t p = 0; p < hs.Nt; ++p) jpad[p] = hs.J[p];
     // split partials: at most 64 splits, at most ~512 MB
     P->ws.max_split = int(std::max<int64_t>(1, std::min<int64_t>(
         std::min<int64_t>(64, Np / 64), (int64_t(512) << 20) / (Np * kBW * int64_t(sizeof(double))))));
@@ -247,12 +258,15 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
     do {                                               \
         if ((st = (expr)) != KL_OK) { free_problem(P); return st; } \
     } while (0)
-    KL_TRY(dev_alloc(&P->dX64, x64.size(), "hipMalloc X64"));
-    KL_TRY(dev_alloc(&P->dX32, x32.size(), "hipMalloc X32"));
-    KL_TRY(dev_alloc(&P->dJ, jpad.size(), "hipMalloc J"));
-    KL_TRY(hip_check(hipMemcpy(P->dX64, x64.data(), x64.size() * 8, hipMemcpyHostToDevice), "copy X64"));
-    KL_TRY(hip_check(hipMemcpy(P->dX32, x32.data(), x32.size() * 4, hipMemcpyHostToDevice), "copy X32"));
-    KL_TRY(hip_check(hipMemcpy(P->dJ, jpad.data(), jpad.size() * 8, hipMemcpyHostToDevice), "copy J"));
+    {
+        std::vector<double> jpad(size_t(Np), 0.0);
+        for (int64_t p = 0; p < hs.Nt; ++p) jpad[p] = hs.J[p];
+        KL_TRY(dev_alloc(&P->dX64, size_t(d) * Np, "hipMalloc X64"));
+        KL_TRY(dev_alloc(&P->dX32, size_t(d) * Np, "hipMalloc X32"));
+        KL_TRY(dev_alloc(&P->dJ, jpad.size(), "hipMalloc J"));
+        KL_TRY(upload_points(P));
+        KL_TRY(hip_check(hipMemcpy(P->dJ, jpad.data(), jpad.size() * 8, hipMemcpyHostToDevice), "copy J"));
+    }
     for (int k = 0; k < d; ++k) {
         const int n = hs.n[k], nt = hs.nt[k];
         std::vector<double> CT(size_t(n) * nt);
@@ -288,6 +302,25 @@ kl_status kl_info(const kl_problem *P, int64_t *N, int64_t *Ntilde, int32_t *n, 
         if (nt) nt[k] = k < P->hs.d ? P->hs.nt[k] : 1;
     }
     return KL_OK;
+}
+
+kl_status kl_set_cov(kl_problem *P, int32_t cov_kind, double sigma2, const double *corr_len) {
+    if (!P || P->host_only) { set_error("kl_set_cov: NULL or host-only handle"); return KL_EINVAL; }
+    if (!corr_len) { set_error("kl_set_cov: NULL corr_len"); return KL_EINVAL; }
+    if (cov_kind < KL_COV_EXP || cov_kind > KL_COV_LIN) { set_error("kl_set_cov: unknown covariance kind"); return KL_EINVAL; }
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) { set_error("kl_set_cov: sigma2 must be positive"); return KL_EINVAL; }
+    for (int k = 0; k < P->hs.d; ++k)
+        if (!(corr_len[k] > 0.0) || !std::isfinite(corr_len[k])) {
+            set_error("kl_set_cov: correlation lengths must be positive");
+            return KL_EINVAL;
+        }
+    // the device may still read the old points: wait for outstanding work first
+    kl_status st = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (st != KL_OK) return st;
+    P->cov_kind = cov_kind;
+    P->sigma2 = sigma2;
+    for (int k = 0; k < 3; ++k) P->ell[k] = k < P->hs.d ? corr_len[k] : 1.0;
+    return upload_points(P);
 }
 
 kl_status kl_apply(kl_problem *P, int32_t precision, int32_t nvec, const double *x, int64_t ldx,

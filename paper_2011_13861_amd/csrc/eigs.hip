@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <new>
 #include <random>
 #include <sstream>
 
@@ -65,6 +66,29 @@ __global__ __launch_bounds__(kT) void finite_kernel(const double *__restrict__ X
                                                     int *__restrict__ flag) {
     for (int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kT)
         if (!isfinite(X[i])) flag[0] = 1;
+}
+
+}  // namespace
+
+struct SolverCache {
+    hipStream_t s = nullptr;
+    rocblas_handle blas = nullptr;
+    int64_t N = 0;
+    int mcap = 0, ccap = 0;
+    double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
+    double *C = nullptr, *part = nullptr, *dtheta = nullptr, *dnorm = nullptr;
+    int *dflag = nullptr;
+};
+
+namespace {
+
+void release_buffers(SolverCache &c) {
+    hipFree(c.V); hipFree(c.AV); hipFree(c.Vt); hipFree(c.AVt); hipFree(c.W);
+    hipFree(c.C); hipFree(c.part); hipFree(c.dtheta); hipFree(c.dnorm); hipFree(c.dflag);
+    c.V = c.AV = c.Vt = c.AVt = c.W = c.C = c.part = c.dtheta = c.dnorm = nullptr;
+    c.dflag = nullptr;
+    c.N = 0;
+    c.mcap = c.ccap = 0;
 }
 
 struct Solver {
@@ -217,9 +241,63 @@ struct Solver {
     }
 };
 
+// Grows the problem's solver cache to hold an N x mmax basis (and N x cmax work block).
+kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
+    if (!P->solver) {
+        P->solver = new (std::nothrow) SolverCache();
+        if (!P->solver) { set_error("kl_eigs: host allocation failed"); return KL_ENOMEM; }
+    }
+    SolverCache &c = *P->solver;
+    auto hip = [](hipError_t e, const char *what) -> kl_status {
+        if (e == hipSuccess) return KL_OK;
+        set_error(std::string("kl_eigs: ") + what + ": " + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? KL_ENOMEM : KL_EHIP;
+    };
+    kl_status st;
+    if (!c.s && (st = hip(hipStreamCreate(&c.s), "stream")) != KL_OK) return st;
+    if (!c.blas) {
+        if (rocblas_create_handle(&c.blas) != rocblas_status_success ||
+            rocblas_set_stream(c.blas, c.s) != rocblas_status_success) {
+            set_error("kl_eigs: rocBLAS handle");
+            return KL_EHIP;
+        }
+    }
+    if (c.N == N && c.mcap >= mmax && c.ccap >= cmax) return KL_OK;
+    release_buffers(c);
+    const int mc = std::max(mmax, c.N == N ? c.mcap : 0), cc = std::max(cmax, c.N == N ? c.ccap : 0);
+    const size_t nb = size_t(N) * mc * sizeof(double);
+    if ((st = hip(hipMalloc(&c.V, nb), "alloc V")) != KL_OK ||
+        (st = hip(hipMalloc(&c.AV, nb), "alloc AV")) != KL_OK ||
+        (st = hip(hipMalloc(&c.Vt, nb), "alloc Vt")) != KL_OK ||
+        (st = hip(hipMalloc(&c.AVt, nb), "alloc AVt")) != KL_OK ||
+        (st = hip(hipMalloc(&c.W, size_t(N) * cc * sizeof(double)), "alloc W")) != KL_OK ||
+        (st = hip(hipMalloc(&c.C, size_t(cc) * cc * sizeof(double)), "alloc C")) != KL_OK ||
+        // split partials of the Gram kernel: 64 row ranges of a cmax x cmax product
+        (st = hip(hipMalloc(&c.part, size_t(64) * cc * cc * sizeof(double)), "alloc gram partials")) != KL_OK ||
+        (st = hip(hipMalloc(&c.dtheta, size_t(mc) * 8), "alloc theta")) != KL_OK ||
+        (st = hip(hipMalloc(&c.dnorm, size_t(mc) * 8), "alloc norms")) != KL_OK ||
+        (st = hip(hipMalloc(&c.dflag, sizeof(int)), "alloc flag")) != KL_OK) {
+        release_buffers(c);
+        return st;
+    }
+    c.N = N;
+    c.mcap = mc;
+    c.ccap = cc;
+    return KL_OK;
+}
+
 int default_guard(int k, int b) { return std::max(std::max(8, b / 4), (3 * k + 9) / 10); }
 
 }  // namespace
+
+void free_solver_cache(SolverCache *c) {
+    if (!c) return;
+    if (c->s) hipStreamSynchronize(c->s);
+    release_buffers(*c);
+    if (c->blas) rocblas_destroy_handle(c->blas);
+    if (c->s) hipStreamDestroy(c->s);
+    delete c;
+}
 
 }  // namespace kl
 
@@ -265,32 +343,16 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
                             : precision == KL_BF16X3 ? 5e-5 : precision == KL_BF16 ? 5e-3 : 0.0;
 
     kl_status st = KL_OK;
-    auto cleanup = [&]() {
-        hipFree(S.V); hipFree(S.AV); hipFree(S.Vt); hipFree(S.AVt); hipFree(S.W);
-        hipFree(S.C); hipFree(S.part); hipFree(S.dtheta); hipFree(S.dnorm); hipFree(S.dflag);
-        if (S.blas) rocblas_destroy_handle(S.blas);
-        if (S.s) hipStreamDestroy(S.s);
-    };
-#define EIG_TRY(expr) do { if ((st = (expr)) != KL_OK) { cleanup(); return st; } } while (0)
-    EIG_TRY(S.check(hipStreamCreate(&S.s), "stream"));
-    EIG_TRY(S.bcheck(rocblas_create_handle(&S.blas), "create handle"));
-    EIG_TRY(S.bcheck(rocblas_set_stream(S.blas, S.s), "set stream"));
-    const size_t nb = size_t(N) * S.mmax * sizeof(double);
+#define EIG_TRY(expr) do { if ((st = (expr)) != KL_OK) return st; } while (0)
     const int cmax = std::max(S.mmax, S.keep + S.b);
-    EIG_TRY(S.check(hipMalloc(&S.V, nb), "alloc V"));
-    EIG_TRY(S.check(hipMalloc(&S.AV, nb), "alloc AV"));
-    EIG_TRY(S.check(hipMalloc(&S.Vt, nb), "alloc Vt"));
-    EIG_TRY(S.check(hipMalloc(&S.AVt, nb), "alloc AVt"));
-    EIG_TRY(S.check(hipMalloc(&S.W, size_t(N) * cmax * sizeof(double)), "alloc W"));
-    EIG_TRY(S.check(hipMalloc(&S.C, size_t(cmax) * cmax * sizeof(double)), "alloc C"));
+    EIG_TRY(acquire_cache(P, N, S.mmax, cmax));
     {
-        // split partials of the Gram kernel: 64 row ranges of a cmax x cmax product
-        const size_t need = size_t(64) * cmax * cmax;
-        EIG_TRY(S.check(hipMalloc(&S.part, need * sizeof(double)), "alloc gram partials"));
+        SolverCache &c = *P->solver;
+        S.s = c.s;
+        S.blas = c.blas;
+        S.V = c.V; S.AV = c.AV; S.Vt = c.Vt; S.AVt = c.AVt; S.W = c.W;
+        S.C = c.C; S.part = c.part; S.dtheta = c.dtheta; S.dnorm = c.dnorm; S.dflag = c.dflag;
     }
-    EIG_TRY(S.check(hipMalloc(&S.dtheta, size_t(S.mmax) * 8), "alloc theta"));
-    EIG_TRY(S.check(hipMalloc(&S.dnorm, size_t(S.mmax) * 8), "alloc norms"));
-    EIG_TRY(S.check(hipMalloc(&S.dflag, sizeof(int)), "alloc flag"));
     S.H.assign(size_t(S.mmax) * S.mmax, 0.0);
     std::mt19937_64 rng(opts->seed);
 
@@ -306,7 +368,7 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
             int flag = 0;
             EIG_TRY(S.check(hipMemcpyAsync(&flag, S.dflag, sizeof(int), hipMemcpyDeviceToHost, S.s), "flag"));
             EIG_TRY(S.check(hipStreamSynchronize(S.s), "sync"));
-            if (flag) { cleanup(); set_error("kl_eigs: non-finite start block"); return KL_ENUMERIC; }
+            if (flag) { set_error("kl_eigs: non-finite start block"); return KL_ENUMERIC; }
         }
         if (from_x0 < b0) {
             std::normal_distribution<double> nd;
@@ -345,12 +407,11 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
         const bool eig_ok = sym_eig(m, Hm.data(), theta.data(), Sm.data());
         t_host_eig += std::chrono::duration<double>(clock::now() - te0).count();
         if (!eig_ok) {
-            cleanup();
             set_error("kl_eigs: projected eigenproblem did not converge");
             return KL_ENUMERIC;
         }
         for (double t : theta)
-            if (!std::isfinite(t)) { cleanup(); set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
+            if (!std::isfinite(t)) { set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
         const int kk = std::min(S.keep, m);
         // X = V S[:, :kk] -> Vt,  AX = AV S[:, :kk] -> AVt
         EIG_TRY(S.check(hipMemcpyAsync(S.C, Sm.data(), size_t(m) * kk * 8, hipMemcpyHostToDevice, S.s), "copy S"));
@@ -446,7 +507,6 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
         rep->t_host_eig = t_host_eig;
         rep->max_rel_residual = max_rel;
     }
-    cleanup();
 #undef EIG_TRY
     if (converged < S.k) {
         std::ostringstream os;

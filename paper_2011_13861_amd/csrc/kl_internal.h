@@ -49,6 +49,11 @@ struct Workspace {
     int max_split = 1;
 };
 
+// Device buffers, stream and rocBLAS handle of the block eigensolver, kept with the
+// problem between kl_eigs calls (grown on demand, freed by kl_destroy).
+struct SolverCache;
+void free_solver_cache(SolverCache *c);
+
 }  // namespace kl
 
 struct kl_problem {
@@ -64,6 +69,7 @@ struct kl_problem {
     double *dC[3] = {nullptr, nullptr, nullptr};    // C_k, nt_k x n_k row-major
     double *dCT[3] = {nullptr, nullptr, nullptr};   // C_k^T, n_k x nt_k row-major
     kl::Workspace ws;
+    kl::SolverCache *solver = nullptr;
     int n_cu = 256;
     bool host_only = false;   // built by kl_setup_host: no device data
     // stage-5 tuning per kl_precision: 32-row blocks per wave (2 or 4) and forced split

@@ -1,0 +1,51 @@
+// Internal declarations of the warm-start network kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+namespace kl {
+namespace mlp {
+
+enum Epilogue { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_TANH = 2, EPI_DTANH = 3 };
+
+// C = op(A) op(B) with an epilogue; logical A is M x K, logical B is K x N:
+//   A(i, k) = TA ? A[k lda + i] : A[i lda + k],  B(k, j) = TB ? B[j ldb + k] : B[k ldb + j].
+// Epilogues: EPI_BIAS  C = AB + bias[j];  EPI_BIAS_TANH  C = tanh(AB + bias[j]);
+// EPI_DTANH  C = AB * (1 - aux[i][j]^2).
+struct GemmArgs {
+    const float *A = nullptr;
+    int64_t lda = 0;
+    const float *B = nullptr;
+    int64_t ldb = 0;
+    float *C = nullptr;
+    int64_t ldc = 0;
+    int M = 0, N = 0, K = 0;
+    int kchunk = 0;                 // K range of one split (multiple of 32)
+    const float *bias = nullptr;
+    const float *aux = nullptr;
+    int64_t ldaux = 0;
+    int epi = EPI_NONE;
+    float *part = nullptr;          // splits x M x N partials when split over K
+};
+
+struct AdamArgs {
+    float lr, b1, b2, eps, c1, c2;
+};
+
+// Number of K splits for a launch (partials limited to part_cap floats); *kchunk
+// receives the K range of one split.
+int gemm_splits(int M, int N, int K, int n_cu, int64_t part_cap, int *kchunk);
+void launch_gemm(bool ta, bool tb, GemmArgs g, int splits, hipStream_t s);
+void launch_loss(const float *y, int64_t ldy, const float *t, int64_t ldt, const int *rows, int batch,
+                 int n_out, int group, int signed_, float *dy, int64_t lddy, double *loss_part,
+                 hipStream_t s);
+void launch_colsum(const float *D, int64_t ldd, int M, int N, float *out, hipStream_t s);
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, const AdamArgs &a, hipStream_t s);
+void launch_gather(const float *src, int64_t lds, const int *rows, int nrows, int ncols, float *dst,
+                   hipStream_t s);
+
+}  // namespace mlp
+}  // namespace kl

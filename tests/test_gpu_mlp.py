@@ -1,0 +1,126 @@
+"""GPU parity of the warm-start network kernels (kl_mlp_*) against the FP64 oracle MLP.
+
+The oracle's backpropagation is pinned by central differences (test_oracle_mlp.py).
+Here the GPU forward pass, gradients and Adam step are compared with it on the same
+FP32 parameters (converted exactly to FP64).  Tolerance: 1e-4 relative for FP32 GEMMs
+with FP32 accumulation over at most a few thousand terms (forward outputs 1e-5).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2011_13861_amd as kl
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _flat(params):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params])
+
+
+def _unflat(flat, sizes):
+    out, off = [], 0
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        W = flat[off:off + fi * fo].reshape(fi, fo)
+        off += fi * fo
+        b = flat[off:off + fo]
+        off += fo
+        out.append([W.astype(np.float64).copy(), b.astype(np.float64).copy()])
+    return out
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _setup(sizes, B, seed, group):
+    rng = np.random.default_rng(seed)
+    flat = _flat(mlp.init_params(sizes, seed=seed)).astype(np.float32)
+    # non-zero biases so that the bias paths are exercised
+    params = _unflat(flat, sizes)
+    for W, b in params:
+        b[:] = rng.uniform(-0.2, 0.2, size=b.shape).astype(np.float32)
+    flat = _flat(params).astype(np.float32)
+    params = _unflat(flat, sizes)
+    x = rng.standard_normal((B, sizes[0])).astype(np.float32)
+    y, _ = mlp.forward(params, x.astype(np.float64))
+    if group:
+        # targets near +-output per group, so the sign choice is unambiguous
+        ng = sizes[-1] // group
+        s = rng.choice([-1.0, 1.0], size=(B, ng))
+        t = (y + 0.3 * np.abs(y).mean() * rng.standard_normal(y.shape)).reshape(B, ng, group) * s[:, :, None]
+        t = t.reshape(B, -1)
+    else:
+        t = y + rng.standard_normal(y.shape)
+    return flat, params, x, t.astype(np.float32)
+
+
+CASES = [([3, 16, 16, 10], 7, 0), ([3, 16, 16, 10], 7, 5), ([5, 70, 33, 130], 67, 13),
+         ([3, 256, 256, 41616], 8, 2601)]
+
+
+@pytest.mark.parametrize("sizes,B,group", CASES, ids=["small_mse", "small_signed", "ragged", "warmstart_size"])
+def test_forward_and_gradients_match_oracle(sizes, B, group):
+    flat, params, x, t = _setup(sizes, B, 11, group)
+    net = kl.MLP(sizes)
+    net.set_params(flat)
+    assert np.array_equal(net.get_params(), flat)
+    xd = torch.from_numpy(x).cuda()
+    td = torch.from_numpy(t).cuda()
+    y = net.forward(xd).cpu().numpy()
+    y_ref, _ = mlp.forward(params, x.astype(np.float64))
+    assert _rel(y, y_ref) <= 1e-5
+    loss, g = net.gradients(xd, td, group=group)
+    loss_ref = mlp.loss(params, x.astype(np.float64), t.astype(np.float64), group=group or None)
+    assert abs(loss - loss_ref) <= 1e-4 * loss_ref
+    g_ref = mlp.backward(params, x.astype(np.float64), t.astype(np.float64), group=group or None)
+    gl = _unflat(g.cpu().numpy(), sizes)
+    for l, ((dW, db), (rW, rb)) in enumerate(zip(gl, g_ref)):
+        assert _rel(dW, rW) <= 1e-4, (l, "W", _rel(dW, rW))
+        assert _rel(db, rb) <= 1e-4, (l, "b", _rel(db, rb))
+
+
+def test_adam_step_matches_oracle():
+    """Three Adam steps on the GPU gradients, against the oracle's Adam fed the same
+    gradients (the update rule alone, FP32 against FP64)."""
+    sizes = [3, 20, 9]
+    flat, params, x, t = _setup(sizes, 6, 5, 0)
+    net = kl.MLP(sizes)
+    net.set_params(flat)
+    state = {}
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    for _ in range(3):
+        _, g = net.gradients(xd, td)
+        net.adam(1e-2)
+        mlp.adam_step(params, _unflat(g.cpu().numpy(), sizes), state, lr=1e-2)
+    got = net.get_params()
+    ref = _flat(params)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_training_reduces_loss():
+    """kl_mlp_train on a smooth synthetic regression: the epoch loss falls by 20x."""
+    rng = np.random.default_rng(2)
+    n = 512
+    x = rng.uniform(-1, 1, size=(n, 3)).astype(np.float32)
+    freq = rng.standard_normal((3, 24))
+    t = np.sin(x @ freq).astype(np.float32)
+    net = kl.MLP([3, 64, 64, 24], seed=3)
+    losses = net.train(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), epochs=150, batch=64,
+                       lr0=3e-3, lr1=3e-4, seed=4)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < losses[0] / 20, (losses[0], losses[-1])
+
+
+def test_mlp_errors():
+    with pytest.raises(kl.KLError):
+        kl.MLP([3])
+    net = kl.MLP([3, 4, 6])
+    x = torch.zeros((2, 3), dtype=torch.float32, device="cuda")
+    t = torch.zeros((2, 6), dtype=torch.float32, device="cuda")
+    with pytest.raises(kl.KLError):
+        net.gradients(x, t, group=4)           # 4 does not divide 6
+    with pytest.raises(ValueError):
+        net.forward(torch.zeros((2, 5), dtype=torch.float32, device="cuda"))
