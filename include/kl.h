@@ -194,6 +194,46 @@ kl_status kl_profile_read(kl_problem *P, int64_t *count, double *ms);
  * Errors: KL_EINVAL, KL_ENUMERIC (non-finite input), KL_ENOCONV. */
 kl_status kl_symeig(int32_t n, const double *A, double *w, double *Z);
 
+/* ---- Batches of problems -------------------------------------------------------------
+ * Many problems of uneven size (same dimension) solved together: one apply of the whole
+ * batch is one replay of a captured HIP graph of 2 dim + 3 launches (batched Kronecker
+ * directions, a persistent stage-5 kernel that takes (problem, row tile, l-split) items
+ * longest first, split sums).  Block arenas: problem i's block of nvec columns starts
+ * at element nvec * row_offset_i of the arena and has leading dimension N_i
+ * (row_offset_i = N_0 + ... + N_{i-1}, see kl_batch_info).  Calls on one batch must be
+ * ordered (one stream); the batched path supports KL_F64 and KL_F32. */
+typedef struct kl_batch kl_batch;
+
+/* Sets up n problems (host setup as kl_setup for each; all with the same dim).  Errors
+ * as kl_setup (the message names the failing problem). */
+kl_status kl_setup_batch(int32_t n, const kl_desc *descs, kl_batch **out);
+kl_status kl_batch_info(const kl_batch *B, int32_t i, int64_t *N, int64_t *Ntilde, int64_t *row_offset);
+
+/* y_i = A~'_i x_i for every problem i with active[i] != 0 (active: host array of n flags,
+ * NULL = all); y_i of inactive problems is left untouched.  x, y: device FP64 arenas as
+ * above, 1 <= nvec <= 32, x and y must not overlap.  Asynchronous on stream.  The first
+ * call per precision builds and captures the graph (synchronous).  Errors: KL_EINVAL,
+ * KL_ENOMEM, KL_EHIP. */
+kl_status kl_apply_batch(kl_batch *B, int32_t precision, int32_t nvec, const double *x, double *y,
+                         const int32_t *active, void *stream);
+
+/* Tile configuration of the batched stage-5 kernel (for the autotuner): rb = 32-row
+ * blocks per wave of the FP32 kernel (2 or 4, 0 keeps), lchunk = l-points per split
+ * (0 = automatic: the largest power of two >= 512 that leaves >= 4 queue items per
+ * resident workgroup).  Rebuilds the graph if the setting changed (waits for the device).
+ * grid_out / items_out (may be NULL): resident workgroups and queue length. */
+kl_status kl_batch_config(kl_batch *B, int32_t precision, int32_t rb, int64_t lchunk, int32_t *grid_out,
+                          int32_t *items_out);
+
+/* kl_eigs for every problem of the batch with the same options, in lockstep: each
+ * iteration applies the operators of all unfinished problems in one graph replay
+ * (finished ones masked off).  evals: host, n x k (row i = problem i).  evecs: device
+ * arena, problem i's N_i x k block at element k * row_offset_i, leading dimension N_i.
+ * reps: host array of n reports, or NULL.  Returns KL_ENOCONV if any problem did not
+ * converge (its report says how far it got), or the first error. */
+kl_status kl_eigs_batch(kl_batch *B, const kl_eigs_opts *opts, double *evals, double *evecs, kl_eigs_report *reps);
+kl_status kl_batch_destroy(kl_batch *B);
+
 /* ---- Warm-start network -----------------------------------------------------------
  * A multilayer perceptron that maps covariance parameters to a block of leading
  * eigenvector coefficients, used as the start block of kl_eigs.  It is an addition to

@@ -5,7 +5,7 @@ this package is its thin Python binding.  Build the library with
 `python -m paper_2011_13861_amd.build` (or __graft_entry__.build()).
 """
 
-from ._binding import (KLError, MLP, Problem, PRECISIONS, EXPORTS, LIB_PATH, lib,  # noqa: F401
+from ._binding import (Batch, KLError, MLP, Problem, PRECISIONS, EXPORTS, LIB_PATH, lib,  # noqa: F401
                        make_desc)
 
 

@@ -27,6 +27,8 @@ EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_
            "kl_stage5_config", "kl_set_cov",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
            "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_destroy",
+           "kl_setup_batch", "kl_batch_info", "kl_apply_batch", "kl_batch_config", "kl_eigs_batch",
+           "kl_batch_destroy",
            "kl_destroy", "kl_last_error"]
 
 
@@ -95,6 +97,14 @@ def lib():
         L.kl_mlp_train.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P, P]
         L.kl_mlp_destroy.argtypes = [P]
+        L.kl_setup_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(KLDesc), ctypes.POINTER(P)]
+        L.kl_batch_info.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.kl_apply_batch.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
+        L.kl_batch_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.kl_eigs_batch.argtypes = [P, ctypes.POINTER(KLEigsOpts), P, P, P]
+        L.kl_batch_destroy.argtypes = [P]
         L.kl_destroy.argtypes = [P]
         L.kl_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -258,6 +268,71 @@ class Problem:
         if st not in (KL_OK, KL_ENOCONV):
             check(st)
         return ev, V, report_dict(rep, st)
+
+
+class Batch:
+    """Owns one kl_batch handle: problems of uneven size applied and solved together.
+    Block arenas are CUDA float64 tensors of Ntot * nvec elements; problem i's block is
+    the (N_i, nvec) column-major view returned by `block(arena, i, nvec)`."""
+
+    def __init__(self, descs):
+        self._h = ctypes.c_void_p()
+        arr = (KLDesc * len(descs))(*[make_desc(d) for d in descs])
+        check(lib().kl_setup_batch(len(descs), arr, ctypes.byref(self._h)))
+        self.n = len(descs)
+        self.N, self.Nt, self.rowoff = [], [], []
+        for i in range(self.n):
+            a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            check(lib().kl_batch_info(self._h, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+            self.N.append(a.value)
+            self.Nt.append(b.value)
+            self.rowoff.append(c.value)
+        self.Ntot = sum(self.N)
+
+    def close(self):
+        if self._h:
+            lib().kl_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def arena(self, nvec):
+        import torch
+        return torch.zeros(self.Ntot * nvec, dtype=torch.float64, device="cuda")
+
+    def block(self, arena, i, nvec):
+        o = nvec * self.rowoff[i]
+        return arena[o:o + nvec * self.N[i]].view(nvec, self.N[i]).T
+
+    def apply(self, x, y, nvec, precision="f64", active=None, stream=None):
+        act = None if active is None else (ctypes.c_int32 * self.n)(*[int(bool(a)) for a in active])
+        check(lib().kl_apply_batch(self._h, PRECISIONS[precision], int(nvec), _ptr(x), _ptr(y),
+                                   act, _stream(stream)))
+
+    def config(self, precision, rb=0, lchunk=0):
+        """Sets the batched stage-5 tiles; returns (resident workgroups, queue items)."""
+        g, it = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().kl_batch_config(self._h, PRECISIONS[precision], int(rb), int(lchunk),
+                                    ctypes.byref(g), ctypes.byref(it)))
+        return g.value, it.value
+
+    def eigs(self, k, precision="f64", block=32, tol=1e-6, abs_floor=1e-12, refine_fp64=True, seed=0,
+             max_applies=0, guard=0, max_basis=0):
+        """Returns (evals (n, k) numpy, evecs arena (device), [report dict per problem])."""
+        o = KLEigsOpts(k=k, block=block, max_applies=max_applies, tol=tol, abs_floor=abs_floor,
+                       precision=PRECISIONS[precision], refine_fp64=int(bool(refine_fp64)),
+                       seed=seed, guard=guard, max_basis=max_basis)
+        ev = np.zeros((self.n, k))
+        V = self.arena(k)
+        reps = (KLEigsReport * self.n)()
+        st = lib().kl_eigs_batch(self._h, ctypes.byref(o), ctypes.c_void_p(ev.ctypes.data), _ptr(V), reps)
+        if st not in (KL_OK, KL_ENOCONV):
+            check(st)
+        return ev, V, [report_dict(reps[i], st) for i in range(self.n)]
 
 
 class MLP:

@@ -64,18 +64,6 @@ double coord_scale(int cov_kind, double ell, bool base2) {
     }
 }
 
-int64_t max_intermediate(const HostSetup &hs) {
-    int64_t best = std::max(hs.N, hs.Nt);
-    for (int k = 0; k <= hs.d; ++k) {
-        int64_t f = 1, b = 1;
-        for (int j = 0; j < hs.d; ++j) {
-            f *= (j < k) ? hs.nt[j] : hs.n[j];
-            b *= (j < k) ? hs.n[j] : hs.nt[j];
-        }
-        best = std::max(best, std::max(f, b));
-    }
-    return best;
-}
 
 bool valid_precision(int precision) { return precision >= KL_F64 && precision <= KL_BF16X3; }
 
@@ -111,6 +99,19 @@ void *stage5_input(kl_problem *P, int precision) {
 }
 
 }  // namespace
+
+int64_t max_intermediate(const HostSetup &hs) {
+    int64_t best = std::max(hs.N, hs.Nt);
+    for (int k = 0; k <= hs.d; ++k) {
+        int64_t f = 1, b = 1;
+        for (int j = 0; j < hs.d; ++j) {
+            f *= (j < k) ? hs.nt[j] : hs.n[j];
+            b *= (j < k) ? hs.n[j] : hs.nt[j];
+        }
+        best = std::max(best, std::max(f, b));
+    }
+    return best;
+}
 
 // Stage-5 launch, bracketed by HIP events on the launch stream while profiling is on.
 int timed_stage5(kl_problem *P, int precision, const void *Y5, hipStream_t s) {
@@ -224,7 +225,13 @@ kl_status kl_setup_host(const kl_desc *desc, kl_problem **out) {
     return KL_OK;
 }
 
-kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
+kl_status kl_setup(const kl_desc *desc, kl_problem **out) { return kl::setup_problem(desc, true, out); }
+
+}  // extern "C"
+
+namespace kl {
+
+kl_status setup_problem(const kl_desc *desc, bool workspace, kl_problem **out) {
     if (!desc || !out) { set_error("kl_setup: NULL argument"); return KL_EINVAL; }
     kl_problem *P = new (std::nothrow) kl_problem();
     if (!P) { set_error("kl_setup: host allocation failed"); return KL_ENOMEM; }
@@ -277,6 +284,10 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
         KL_TRY(hip_check(hipMemcpy(P->dC[k], hs.C[k].data(), CT.size() * 8, hipMemcpyHostToDevice), "copy C"));
         KL_TRY(hip_check(hipMemcpy(P->dCT[k], CT.data(), CT.size() * 8, hipMemcpyHostToDevice), "copy CT"));
     }
+    if (!workspace) {
+        *out = P;
+        return KL_OK;
+    }
     KL_TRY(dev_alloc(&P->ws.T0, P->ws.t_elems, "hipMalloc T0"));
     KL_TRY(dev_alloc(&P->ws.T1, P->ws.t_elems, "hipMalloc T1"));
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5d), P->ws.y5_bytes, "hipMalloc Y5"));
@@ -292,6 +303,12 @@ kl_status kl_setup(const kl_desc *desc, kl_problem **out) {
     *out = P;
     return KL_OK;
 }
+
+void destroy_problem(kl_problem *P) { free_problem(P); }
+
+}  // namespace kl
+
+extern "C" {
 
 kl_status kl_info(const kl_problem *P, int64_t *N, int64_t *Ntilde, int32_t *n, int32_t *nt) {
     if (!P) { set_error("kl_info: NULL handle"); return KL_EINVAL; }

@@ -20,11 +20,14 @@
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <new>
 #include <random>
 #include <sstream>
+#include <string>
+#include <thread>
 
 #include "kl_internal.h"
 
@@ -288,6 +291,35 @@ kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
 
 int default_guard(int k, int b) { return std::max(std::max(8, b / 4), (3 * k + 9) / 10); }
 
+enum { AFTER_NONE = 0, AFTER_START, AFTER_SWITCH, AFTER_EXPAND };
+
+struct EigRun {
+    kl_problem *P = nullptr;
+    Solver S;
+    double tol = 1e-6, floor_rel = 1e-12, lo_floor = 0.0;
+    bool refine = false;
+    int max_applies = 0;
+    int precision = KL_F64;                 // precision of the current phase
+    std::mt19937_64 rng;
+    std::vector<double> theta, Sm, norms;
+    double best_lo = INFINITY, t_host_eig = 0.0, max_rel = INFINITY;
+    int stall = 0, converged = 0;
+    bool done = false;
+    // the operator application the run waits for
+    int pending_prec = KL_F64, pending_cols = 0, after = AFTER_NONE, last_add = 0;
+    double *pending_x = nullptr, *pending_y = nullptr;
+
+    kl_status configure(kl_problem *P_, const kl_eigs_opts *opts);
+    kl_status begin(const double *x0, int nvec0);
+    kl_status after_apply();
+    kl_status finish(double *evals, double *evecs, int64_t ldv, kl_eigs_report *rep, double t_solve);
+    void count_apply(int prec, int cols);
+
+  private:
+    kl_status rr_step();
+    void set_pending(int prec, double *x, double *y, int cols, int after_);
+};
+
 }  // namespace
 
 void free_solver_cache(SolverCache *c) {
@@ -297,6 +329,253 @@ void free_solver_cache(SolverCache *c) {
     if (c->blas) rocblas_destroy_handle(c->blas);
     if (c->s) hipStreamDestroy(c->s);
     delete c;
+}
+
+// ---- one eigensolve as a resumable run ----------------------------------------------
+// The run stops at every operator application (pending_*); the caller applies A~' in
+// the pending precision to the pending columns (alone, or together with other runs in
+// one batched launch) and resumes with after_apply().
+
+kl_status EigRun::configure(kl_problem *P_, const kl_eigs_opts *opts) {
+    P = P_;
+    if (!opts) { set_error("kl_eigs: NULL argument"); return KL_EINVAL; }
+    const int64_t N = P->hs.N;
+    if (opts->k < 1 || opts->k > N) { set_error("kl_eigs: k must be in 1..N"); return KL_EINVAL; }
+    if (opts->precision < KL_F64 || opts->precision > KL_BF16X3) {
+        set_error("kl_eigs: unsupported precision");
+        return KL_EINVAL;
+    }
+    S.P = P;
+    S.N = N;
+    S.k = opts->k;
+    S.b = opts->block > 0 ? opts->block : 32;
+    if (S.b > kBW * 8) { set_error("kl_eigs: block too large"); return KL_EINVAL; }
+    tol = opts->tol > 0 ? opts->tol : 1e-6;
+    floor_rel = opts->abs_floor > 0 ? opts->abs_floor : 1e-12;
+    const int guard = opts->guard > 0 ? opts->guard : default_guard(S.k, S.b);
+    S.keep = S.k + guard;
+    S.mmax = opts->max_basis > 0 ? opts->max_basis : S.keep + 3 * S.b;
+    if (S.mmax < S.keep + S.b) S.mmax = S.keep + S.b;
+    if (S.mmax > N) S.mmax = int(N);
+    if (S.b > S.mmax) S.b = S.mmax;
+    if (S.keep > S.mmax - S.b) S.keep = std::max(S.k, S.mmax - S.b);
+    if (S.keep > S.mmax) S.keep = S.mmax;
+    max_applies = opts->max_applies > 0 ? opts->max_applies : int(std::min<int64_t>(
+        int64_t(400) * S.b + 20 * S.k, 4000000));
+    precision = opts->precision;
+    refine = precision != KL_F64 && opts->refine_fp64 != 0;
+    // low-precision floor: relative accuracy the low-precision apply can certify
+    lo_floor = precision == KL_F32 ? 2e-6 : precision == KL_BF16X3 ? 5e-5 : precision == KL_BF16 ? 5e-3 : 0.0;
+    rng.seed(opts->seed);
+    return KL_OK;
+}
+
+kl_status EigRun::begin(const double *x0, int nvec0) {
+    kl_status st;
+    const int64_t N = S.N;
+    const int cmax = std::max(S.mmax, S.keep + S.b);
+    if ((st = acquire_cache(P, N, S.mmax, cmax)) != KL_OK) return st;
+    {
+        SolverCache &c = *P->solver;
+        S.s = c.s;
+        S.blas = c.blas;
+        S.V = c.V; S.AV = c.AV; S.Vt = c.Vt; S.AVt = c.AVt; S.W = c.W;
+        S.C = c.C; S.part = c.part; S.dtheta = c.dtheta; S.dnorm = c.dnorm; S.dflag = c.dflag;
+    }
+    S.H.assign(size_t(S.mmax) * S.mmax, 0.0);
+    const int b0 = S.b;
+    const int from_x0 = std::min<int>(nvec0, b0);
+    if (from_x0 > 0) {
+        if ((st = S.check(hipMemcpy2DAsync(S.W, size_t(N) * 8, x0, size_t(N) * 8, size_t(N) * 8, from_x0,
+                                           hipMemcpyDeviceToDevice, S.s), "copy x0")) != KL_OK)
+            return st;
+        if ((st = S.check(hipMemsetAsync(S.dflag, 0, sizeof(int), S.s), "memset")) != KL_OK) return st;
+        hipLaunchKernelGGL(finite_kernel, dim3(256), dim3(kT), 0, S.s, S.W, int64_t(N) * from_x0, S.dflag);
+        int flag = 0;
+        if ((st = S.check(hipMemcpyAsync(&flag, S.dflag, sizeof(int), hipMemcpyDeviceToHost, S.s), "flag")) != KL_OK)
+            return st;
+        if ((st = S.check(hipStreamSynchronize(S.s), "sync")) != KL_OK) return st;
+        if (flag) { set_error("kl_eigs: non-finite start block"); return KL_ENUMERIC; }
+    }
+    if (from_x0 < b0) {
+        std::normal_distribution<double> nd;
+        std::vector<double> r(size_t(N) * (b0 - from_x0));
+        for (double &v : r) v = nd(rng);
+        if ((st = S.check(hipMemcpyAsync(S.W + int64_t(from_x0) * N, r.data(), r.size() * 8, hipMemcpyHostToDevice,
+                                         S.s), "copy random start")) != KL_OK)
+            return st;
+        if ((st = S.check(hipStreamSynchronize(S.s), "sync")) != KL_OK) return st;
+    }
+    S.m = 0;
+    if ((st = S.orth_into_basis(S.W, b0, b0, rng)) != KL_OK) return st;
+    set_pending(precision, S.V, S.AV, b0, AFTER_START);
+    return KL_OK;
+}
+
+void EigRun::set_pending(int prec, double *x, double *y, int cols, int after_) {
+    pending_prec = prec;
+    pending_x = x;
+    pending_y = y;
+    pending_cols = cols;
+    after = after_;
+}
+
+void EigRun::count_apply(int prec, int cols) {
+    S.applies[prec] += cols;
+    S.block_applies[prec] += (cols + kBW - 1) / kBW;
+}
+
+kl_status EigRun::after_apply() {
+    kl_status st;
+    const int64_t N = S.N;
+    pending_cols = 0;
+    switch (after) {
+    case AFTER_START:
+        S.m = S.b;
+        S.last = S.b;
+        if ((st = S.update_H(0, S.b)) != KL_OK) return st;
+        return rr_step();
+    case AFTER_SWITCH: {
+        const int kk = S.m;
+        std::fill(S.H.begin(), S.H.end(), 0.0);
+        if ((st = S.update_H(0, kk)) != KL_OK) return st;
+        S.last = kk;
+        // expand from the residual directions of the FP64 operator
+        hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.V, S.AV, S.dtheta, N, N, S.W, S.dnorm);
+        const int add = int(std::min<int64_t>(S.b, N - S.m));
+        if (add > 0) {
+            if ((st = S.orth_into_basis(S.W, kk, add, rng)) != KL_OK) return st;
+            set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add, AFTER_EXPAND);
+            return KL_OK;
+        }
+        return rr_step();
+    }
+    case AFTER_EXPAND: {
+        const int add = last_add;
+        if ((st = S.update_H(S.m, S.m + add)) != KL_OK) return st;
+        S.m += add;
+        S.last = add;
+        return rr_step();
+    }
+    default:
+        return KL_OK;
+    }
+}
+
+kl_status EigRun::rr_step() {
+    using clock = std::chrono::steady_clock;
+    kl_status st;
+    const int64_t N = S.N;
+    const int total_applies = S.applies[0] + S.applies[1] + S.applies[2] + S.applies[3];
+    const bool must_restart = S.m + S.b > S.mmax;
+    // ---- Rayleigh-Ritz on the current basis ------------------------------------------
+    const int m = S.m;
+    std::vector<double> Hm(size_t(m) * m);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) Hm[size_t(i) * m + j] = S.H[size_t(i) * S.mmax + j];
+    theta.assign(m, 0.0);
+    Sm.assign(size_t(m) * m, 0.0);
+    const auto te0 = clock::now();
+    const bool eig_ok = sym_eig(m, Hm.data(), theta.data(), Sm.data());
+    t_host_eig += std::chrono::duration<double>(clock::now() - te0).count();
+    if (!eig_ok) { set_error("kl_eigs: projected eigenproblem did not converge"); return KL_ENUMERIC; }
+    for (double t : theta)
+        if (!std::isfinite(t)) { set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
+    const int kk = std::min(S.keep, m);
+    // X = V S[:, :kk] -> Vt,  AX = AV S[:, :kk] -> AVt
+    if ((st = S.check(hipMemcpyAsync(S.C, Sm.data(), size_t(m) * kk * 8, hipMemcpyHostToDevice, S.s), "copy S")) != KL_OK)
+        return st;
+    if ((st = S.gemm_nn(S.V, m, S.C, m, kk, 1.0, 0.0, S.Vt)) != KL_OK) return st;
+    if ((st = S.gemm_nn(S.AV, m, S.C, m, kk, 1.0, 0.0, S.AVt)) != KL_OK) return st;
+    if ((st = S.check(hipMemcpyAsync(S.dtheta, theta.data(), size_t(kk) * 8, hipMemcpyHostToDevice, S.s),
+                      "copy theta")) != KL_OK)
+        return st;
+    hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.Vt, S.AVt, S.dtheta, N, N, S.W, S.dnorm);
+    norms.assign(kk, 0.0);
+    if ((st = S.check(hipMemcpyAsync(norms.data(), S.dnorm, size_t(kk) * 8, hipMemcpyDeviceToHost, S.s),
+                      "copy norms")) != KL_OK)
+        return st;
+    if ((st = S.check(hipStreamSynchronize(S.s), "sync")) != KL_OK) return st;
+    const double t1 = std::fabs(theta[0]);
+    converged = 0;
+    max_rel = 0.0;
+    bool lo_ok = true;
+    const int kc = std::min(S.k, kk);
+    for (int i = 0; i < kc; ++i) {
+        const double target = std::max(tol * std::fabs(theta[i]), floor_rel * t1);
+        if (norms[i] <= target) ++converged;
+        max_rel = std::max(max_rel, norms[i] / std::max(std::fabs(theta[i]), 1e-300));
+        if (norms[i] > std::max(target, lo_floor * t1)) lo_ok = false;
+    }
+    const bool all = converged == kc && kc == S.k;
+    // stagnation of the low-precision phase: no halving of the largest relative
+    // residual over three Rayleigh-Ritz steps
+    if (precision != KL_F64) {
+        if (max_rel < 0.5 * best_lo) { best_lo = max_rel; stall = 0; }
+        else if (++stall >= 3) lo_ok = true;
+    }
+    if (precision == KL_F64 || !refine) {
+        if (all || S.m >= N) { done = true; return KL_OK; }
+    } else if (lo_ok || S.m >= N) {
+        // ---- switch to FP64: recompute AV of the kept Ritz basis --------------------
+        precision = KL_F64;
+        std::swap(S.V, S.Vt);
+        S.m = kk;
+        S.restarts += 1;
+        set_pending(KL_F64, S.V, S.AV, kk, AFTER_SWITCH);
+        return KL_OK;
+    }
+    if (total_applies >= max_applies) { done = true; return KL_OK; }
+    const int add = int(std::min<int64_t>(S.b, N - (must_restart ? kk : S.m)));
+    if (must_restart) {
+        // ---- thick restart -------------------------------------------------------
+        std::swap(S.V, S.Vt);
+        std::swap(S.AV, S.AVt);
+        S.m = kk;
+        std::fill(S.H.begin(), S.H.end(), 0.0);
+        for (int i = 0; i < kk; ++i) S.H[size_t(i) * S.mmax + i] = theta[i];
+        S.restarts += 1;
+        // residuals of the kept vectors are in W (residual_kernel above)
+        if (add <= 0) { done = true; return KL_OK; }
+        if ((st = S.orth_into_basis(S.W, kk, add, rng)) != KL_OK) return st;
+    } else {
+        // ---- block Krylov expansion from the newest block of AV --------------------
+        if (add <= 0) { done = true; return KL_OK; }
+        if ((st = S.check(hipMemcpyAsync(S.W, S.AV + int64_t(S.m - S.last) * N, size_t(N) * S.last * 8,
+                                         hipMemcpyDeviceToDevice, S.s), "copy block")) != KL_OK)
+            return st;
+        if ((st = S.orth_into_basis(S.W, S.last, add, rng)) != KL_OK) return st;
+    }
+    last_add = add;
+    set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add, AFTER_EXPAND);
+    return KL_OK;
+}
+
+kl_status EigRun::finish(double *evals, double *evecs, int64_t ldv, kl_eigs_report *rep, double t_solve) {
+    const int64_t N = S.N;
+    const int kout = std::min<int>(S.k, int(theta.size()));
+    for (int i = 0; i < S.k; ++i) evals[i] = i < kout ? theta[i] : 0.0;
+    launch_copy_cols(S.Vt, N, evecs, ldv, N, kout, S.s);
+    kl_status st = S.check(hipStreamSynchronize(S.s), "sync");
+    if (st != KL_OK) return st;
+    if (rep) {
+        for (int p = 0; p < 4; ++p) {
+            rep->n_applies[p] = S.applies[p];
+            rep->n_block_applies[p] = S.block_applies[p];
+        }
+        rep->n_restarts = S.restarts;
+        rep->converged = converged;
+        rep->t_solve = t_solve;
+        rep->t_host_eig = t_host_eig;
+        rep->max_rel_residual = max_rel;
+    }
+    if (converged < S.k) {
+        std::ostringstream os;
+        os << "kl_eigs: " << converged << " of " << S.k << " pairs converged within " << max_applies << " applies";
+        set_error(os.str());
+        return KL_ENOCONV;
+    }
+    return KL_OK;
 }
 
 }  // namespace kl
@@ -310,210 +589,157 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
     const auto t0 = clock::now();
     if (!P || P->host_only) { set_error("kl_eigs: NULL or host-only handle"); return KL_EINVAL; }
     if (!opts || !evals || !evecs) { set_error("kl_eigs: NULL argument"); return KL_EINVAL; }
-    const int64_t N = P->hs.N;
-    if (opts->k < 1 || opts->k > N) { set_error("kl_eigs: k must be in 1..N"); return KL_EINVAL; }
-    if (ldv < N) { set_error("kl_eigs: ldv < N"); return KL_EINVAL; }
-    if (opts->precision < KL_F64 || opts->precision > KL_BF16X3) {
-        set_error("kl_eigs: unsupported precision");
+    if (ldv < P->hs.N) { set_error("kl_eigs: ldv < N"); return KL_EINVAL; }
+    if (nvec0 < 0 || (nvec0 > 0 && !x0)) { set_error("kl_eigs: bad start block"); return KL_EINVAL; }
+    EigRun run;
+    kl_status st = run.configure(P, opts);
+    if (st != KL_OK) return st;
+    if ((st = run.begin(x0, nvec0)) != KL_OK) return st;
+    while (!run.done) {
+        if ((st = run.S.apply(run.pending_prec, run.pending_x, run.pending_y, run.pending_cols)) != KL_OK) return st;
+        if ((st = run.after_apply()) != KL_OK) return st;
+    }
+    return run.finish(evals, evecs, ldv, rep, std::chrono::duration<double>(clock::now() - t0).count());
+}
+
+namespace kl {
+namespace {
+
+// Runs fn(i) for i < n on up to 16 host threads.
+template <typename F>
+void parallel_for(int n, F fn) {
+    const int hw = int(std::max(1u, std::thread::hardware_concurrency()));
+    const int T = std::min(n, std::min(16, hw));
+    if (T <= 1) {
+        for (int i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::atomic<int> next(0);
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 0; t < T; ++t)
+        th.emplace_back([&]() {
+            for (;;) {
+                const int i = next.fetch_add(1);
+                if (i >= n) break;
+                fn(i);
+            }
+        });
+    for (auto &t : th) t.join();
+}
+
+}  // namespace
+}  // namespace kl
+
+// Every problem of the batch runs the same block eigensolver as kl_eigs, in lockstep:
+// the operator applications of all runs that wait for one are made by one replay of the
+// batch's apply graph (runs that converged are masked off), and the rest of each run's
+// step (orthogonalisation, Rayleigh-Ritz, restarts) proceeds on host threads, each run
+// on its own stream.
+extern "C" kl_status kl_eigs_batch(kl_batch *B, const kl_eigs_opts *opts, double *evals, double *evecs,
+                                   kl_eigs_report *reps) {
+    using clock = std::chrono::steady_clock;
+    const auto t0 = clock::now();
+    if (!B || !opts || !evals || !evecs) { set_error("kl_eigs_batch: NULL argument"); return KL_EINVAL; }
+    if (opts->precision != KL_F64 && opts->precision != KL_F32) {
+        set_error("kl_eigs_batch: the batched path supports KL_F64 and KL_F32");
         return KL_EINVAL;
     }
-    if (nvec0 < 0 || (nvec0 > 0 && !x0)) { set_error("kl_eigs: bad start block"); return KL_EINVAL; }
-    Solver S;
-    S.P = P;
-    S.N = N;
-    S.k = opts->k;
-    S.b = opts->block > 0 ? opts->block : 32;
-    if (S.b > kBW * 8) { set_error("kl_eigs: block too large"); return KL_EINVAL; }
-    const double tol = opts->tol > 0 ? opts->tol : 1e-6;
-    const double floor_rel = opts->abs_floor > 0 ? opts->abs_floor : 1e-12;
-    const int guard = opts->guard > 0 ? opts->guard : default_guard(S.k, S.b);
-    S.keep = S.k + guard;
-    S.mmax = opts->max_basis > 0 ? opts->max_basis : S.keep + 3 * S.b;
-    if (S.mmax < S.keep + S.b) S.mmax = S.keep + S.b;
-    if (S.mmax > N) S.mmax = int(N);
-    if (S.b > S.mmax) S.b = S.mmax;
-    if (S.keep > S.mmax - S.b) S.keep = std::max(S.k, S.mmax - S.b);
-    if (S.keep > S.mmax) S.keep = S.mmax;
-    const int max_applies = opts->max_applies > 0 ? opts->max_applies : int(std::min<int64_t>(
-        int64_t(400) * S.b + 20 * S.k, 4000000));
-    int precision = opts->precision;
-    const bool refine = precision != KL_F64 && opts->refine_fp64 != 0;
-    // low-precision floor: relative accuracy the low-precision apply can certify
-    const double lo_floor = precision == KL_F32 ? 2e-6
-                            : precision == KL_BF16X3 ? 5e-5 : precision == KL_BF16 ? 5e-3 : 0.0;
-
-    kl_status st = KL_OK;
-#define EIG_TRY(expr) do { if ((st = (expr)) != KL_OK) return st; } while (0)
-    const int cmax = std::max(S.mmax, S.keep + S.b);
-    EIG_TRY(acquire_cache(P, N, S.mmax, cmax));
-    {
-        SolverCache &c = *P->solver;
-        S.s = c.s;
-        S.blas = c.blas;
-        S.V = c.V; S.AV = c.AV; S.Vt = c.Vt; S.AVt = c.AVt; S.W = c.W;
-        S.C = c.C; S.part = c.part; S.dtheta = c.dtheta; S.dnorm = c.dnorm; S.dflag = c.dflag;
+    const int n = batch_size(B);
+    std::vector<EigRun> runs(n);
+    std::vector<kl_status> stv(n, KL_OK);
+    std::vector<std::string> msg(n);
+    std::vector<int64_t> N(n), off(n);
+    for (int i = 0; i < n; ++i) {
+        kl_status st = kl_batch_info(B, i, &N[i], nullptr, &off[i]);
+        if (st == KL_OK) st = runs[i].configure(batch_problem(B, i), opts);
+        if (st != KL_OK) return st;
     }
-    S.H.assign(size_t(S.mmax) * S.mmax, 0.0);
-    std::mt19937_64 rng(opts->seed);
-
-    // ---- start block ------------------------------------------------------------------
-    {
-        const int b0 = S.b;
-        const int from_x0 = std::min<int>(nvec0, b0);
-        if (from_x0 > 0) {
-            EIG_TRY(S.check(hipMemcpy2DAsync(S.W, size_t(N) * 8, x0, size_t(N) * 8, size_t(N) * 8, from_x0,
-                                             hipMemcpyDeviceToDevice, S.s), "copy x0"));
-            EIG_TRY(S.check(hipMemsetAsync(S.dflag, 0, sizeof(int), S.s), "memset"));
-            hipLaunchKernelGGL(finite_kernel, dim3(256), dim3(kT), 0, S.s, S.W, int64_t(N) * from_x0, S.dflag);
-            int flag = 0;
-            EIG_TRY(S.check(hipMemcpyAsync(&flag, S.dflag, sizeof(int), hipMemcpyDeviceToHost, S.s), "flag"));
-            EIG_TRY(S.check(hipStreamSynchronize(S.s), "sync"));
-            if (flag) { set_error("kl_eigs: non-finite start block"); return KL_ENUMERIC; }
-        }
-        if (from_x0 < b0) {
-            std::normal_distribution<double> nd;
-            std::vector<double> r(size_t(N) * (b0 - from_x0));
-            for (double &v : r) v = nd(rng);
-            EIG_TRY(S.check(hipMemcpy(S.W + int64_t(from_x0) * N, r.data(), r.size() * 8, hipMemcpyHostToDevice),
-                            "copy random start"));
-        }
-        S.m = 0;
-        EIG_TRY(S.orth_into_basis(S.W, b0, b0, rng));
-        EIG_TRY(S.apply(precision, S.V, S.AV, b0));
-        S.m = b0;
-        S.last = b0;
-        EIG_TRY(S.update_H(0, b0));
-    }
-
-    std::vector<double> theta, Sm, norms;
-    double best_lo = INFINITY;
-    double t_host_eig = 0.0;
-    int stall = 0;
-    int converged = 0;
-    double max_rel = INFINITY;
-    bool done = false;
-    int total_applies = 0;
-    while (!done) {
-        total_applies = S.applies[0] + S.applies[1] + S.applies[2] + S.applies[3];
-        const bool must_restart = S.m + S.b > S.mmax;
-        // ---- Rayleigh-Ritz on the current basis --------------------------------------
-        const int m = S.m;
-        std::vector<double> Hm(size_t(m) * m);
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) Hm[size_t(i) * m + j] = S.H[size_t(i) * S.mmax + j];
-        theta.assign(m, 0.0);
-        Sm.assign(size_t(m) * m, 0.0);
-        const auto te0 = clock::now();
-        const bool eig_ok = sym_eig(m, Hm.data(), theta.data(), Sm.data());
-        t_host_eig += std::chrono::duration<double>(clock::now() - te0).count();
-        if (!eig_ok) {
-            set_error("kl_eigs: projected eigenproblem did not converge");
-            return KL_ENUMERIC;
-        }
-        for (double t : theta)
-            if (!std::isfinite(t)) { set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
-        const int kk = std::min(S.keep, m);
-        // X = V S[:, :kk] -> Vt,  AX = AV S[:, :kk] -> AVt
-        EIG_TRY(S.check(hipMemcpyAsync(S.C, Sm.data(), size_t(m) * kk * 8, hipMemcpyHostToDevice, S.s), "copy S"));
-        EIG_TRY(S.gemm_nn(S.V, m, S.C, m, kk, 1.0, 0.0, S.Vt));
-        EIG_TRY(S.gemm_nn(S.AV, m, S.C, m, kk, 1.0, 0.0, S.AVt));
-        EIG_TRY(S.check(hipMemcpyAsync(S.dtheta, theta.data(), size_t(kk) * 8, hipMemcpyHostToDevice, S.s), "copy theta"));
-        hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.Vt, S.AVt, S.dtheta, N, N, S.W, S.dnorm);
-        norms.assign(kk, 0.0);
-        EIG_TRY(S.check(hipMemcpyAsync(norms.data(), S.dnorm, size_t(kk) * 8, hipMemcpyDeviceToHost, S.s), "copy norms"));
-        EIG_TRY(S.check(hipStreamSynchronize(S.s), "sync"));
-        const double t1 = std::fabs(theta[0]);
-        converged = 0;
-        max_rel = 0.0;
-        bool lo_ok = true;
-        const int kc = std::min(S.k, kk);
-        for (int i = 0; i < kc; ++i) {
-            const double target = std::max(tol * std::fabs(theta[i]), floor_rel * t1);
-            if (norms[i] <= target) ++converged;
-            max_rel = std::max(max_rel, norms[i] / std::max(std::fabs(theta[i]), 1e-300));
-            if (norms[i] > std::max(target, lo_floor * t1)) lo_ok = false;
-        }
-        const bool all = converged == kc && kc == S.k;
-        // stagnation of the low-precision phase: no halving of the largest relative
-        // residual over three Rayleigh-Ritz steps
-        if (precision != KL_F64) {
-            if (max_rel < 0.5 * best_lo) { best_lo = max_rel; stall = 0; }
-            else if (++stall >= 3) lo_ok = true;
-        }
-        if (precision == KL_F64 || !refine) {
-            if (all || S.m >= N) { done = true; break; }
-        } else if (lo_ok || S.m >= N) {
-            // ---- switch to FP64: recompute AV of the kept Ritz basis ----------------
-            precision = KL_F64;
-            std::swap(S.V, S.Vt);
-            S.m = kk;
-            EIG_TRY(S.apply(KL_F64, S.V, S.AV, kk));
-            std::fill(S.H.begin(), S.H.end(), 0.0);
-            EIG_TRY(S.update_H(0, kk));
-            S.last = kk;
-            S.restarts += 1;
-            // expand from the residual directions of the FP64 operator
-            hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.V, S.AV, S.dtheta, N, N, S.W, S.dnorm);
-            const int add = std::min<int64_t>(S.b, N - S.m);
-            if (add > 0) {
-                EIG_TRY(S.orth_into_basis(S.W, kk, add, rng));
-                EIG_TRY(S.apply(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add));
-                EIG_TRY(S.update_H(S.m, S.m + add));
-                S.m += add;
-                S.last = add;
+    auto first_error = [&]() -> kl_status {
+        for (int i = 0; i < n; ++i)
+            if (stv[i] != KL_OK && stv[i] != KL_ENOCONV) {
+                std::ostringstream os;
+                os << "kl_eigs_batch: problem " << i << ": " << msg[i];
+                set_error(os.str());
+                return stv[i];
             }
-            continue;
+        return KL_OK;
+    };
+    auto record = [&](int i, kl_status st) {
+        stv[i] = st;
+        if (st != KL_OK) msg[i] = kl_last_error();
+    };
+    parallel_for(n, [&](int i) { record(i, runs[i].begin(nullptr, 0)); });
+    kl_status st = first_error();
+    if (st != KL_OK) return st;
+    hipStream_t bs = batch_stream(B);
+    std::vector<hipEvent_t> ev(n, nullptr);
+    hipEvent_t evb = nullptr;
+    auto release = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (evb) (void)hipEventDestroy(evb);
+    };
+    for (int i = 0; i < n && st == KL_OK; ++i)
+        if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) st = KL_EHIP;
+    if (st == KL_OK && hipEventCreateWithFlags(&evb, hipEventDisableTiming) != hipSuccess) st = KL_EHIP;
+    if (st != KL_OK) { release(); set_error("kl_eigs_batch: event creation failed"); return st; }
+    std::vector<int> nv(n);
+    std::vector<const double *> xs(n);
+    std::vector<double *> ys(n);
+    for (;;) {
+        bool any = false;
+        for (int i = 0; i < n; ++i) any = any || !runs[i].done;
+        if (!any) break;
+        const int precs[2] = {int(opts->precision), opts->precision == KL_F64 ? -1 : int(KL_F64)};
+        for (int prec : precs) {
+            if (prec < 0) continue;
+            int maxcols = 0;
+            for (int i = 0; i < n; ++i)
+                if (!runs[i].done && runs[i].pending_cols > 0 && runs[i].pending_prec == prec)
+                    maxcols = std::max(maxcols, runs[i].pending_cols);
+            if (maxcols == 0) continue;
+            for (int i = 0; i < n; ++i)
+                if (!runs[i].done && runs[i].pending_cols > 0 && runs[i].pending_prec == prec) {
+                    (void)hipEventRecord(ev[i], runs[i].S.s);
+                    (void)hipStreamWaitEvent(bs, ev[i], 0);
+                }
+            for (int c0 = 0; c0 < maxcols && st == KL_OK; c0 += kBW) {
+                for (int i = 0; i < n; ++i) {
+                    const bool part = !runs[i].done && runs[i].pending_prec == prec && runs[i].pending_cols > c0;
+                    nv[i] = part ? std::min(kBW, runs[i].pending_cols - c0) : 0;
+                    xs[i] = part ? runs[i].pending_x + int64_t(c0) * N[i] : nullptr;
+                    ys[i] = part ? runs[i].pending_y + int64_t(c0) * N[i] : nullptr;
+                }
+                st = batch_apply(B, prec, nv.data(), xs.data(), N.data(), ys.data(), N.data(), bs);
+            }
+            if (st != KL_OK) { release(); return st; }
+            (void)hipEventRecord(evb, bs);
+            for (int i = 0; i < n; ++i)
+                if (!runs[i].done && runs[i].pending_cols > 0 && runs[i].pending_prec == prec) {
+                    (void)hipStreamWaitEvent(runs[i].S.s, evb, 0);
+                    runs[i].count_apply(prec, runs[i].pending_cols);
+                }
         }
-        if (total_applies >= max_applies) break;
-        if (must_restart) {
-            // ---- thick restart -------------------------------------------------------
-            std::swap(S.V, S.Vt);
-            std::swap(S.AV, S.AVt);
-            S.m = kk;
-            std::fill(S.H.begin(), S.H.end(), 0.0);
-            for (int i = 0; i < kk; ++i) S.H[size_t(i) * S.mmax + i] = theta[i];
-            S.restarts += 1;
-            // residuals of the kept vectors are in W (residual_kernel above)
-            const int add = std::min<int64_t>(S.b, N - S.m);
-            if (add <= 0) { done = true; break; }
-            EIG_TRY(S.orth_into_basis(S.W, kk, add, rng));
-        } else {
-            // ---- block Krylov expansion from the newest block of AV --------------------
-            const int add = std::min<int64_t>(S.b, N - S.m);
-            if (add <= 0) { done = true; break; }
-            EIG_TRY(S.check(hipMemcpyAsync(S.W, S.AV + int64_t(S.m - S.last) * N, size_t(N) * S.last * 8,
-                                           hipMemcpyDeviceToDevice, S.s), "copy block"));
-            EIG_TRY(S.orth_into_basis(S.W, S.last, add, rng));
+        parallel_for(n, [&](int i) {
+            if (!runs[i].done) record(i, runs[i].after_apply());
+        });
+        if ((st = first_error()) != KL_OK) { release(); return st; }
+    }
+    const double t_solve = std::chrono::duration<double>(clock::now() - t0).count();
+    parallel_for(n, [&](int i) {
+        const int k = runs[i].S.k;
+        record(i, runs[i].finish(evals + int64_t(i) * k, evecs + int64_t(k) * off[i], N[i], reps ? reps + i : nullptr,
+                                 t_solve));
+    });
+    release();
+    if ((st = first_error()) != KL_OK) return st;
+    for (int i = 0; i < n; ++i)
+        if (stv[i] == KL_ENOCONV) {
+            std::ostringstream os;
+            os << "kl_eigs_batch: problem " << i << ": " << msg[i];
+            set_error(os.str());
+            return KL_ENOCONV;
         }
-        const int add = std::min<int64_t>(S.b, N - S.m);
-        EIG_TRY(S.apply(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add));
-        EIG_TRY(S.update_H(S.m, S.m + add));
-        S.m += add;
-        S.last = add;
-    }
-    // ---- outputs: Ritz pairs from the last Rayleigh-Ritz (held in Vt / theta) ------------
-    const int kout = std::min<int>(S.k, int(theta.size()));
-    for (int i = 0; i < S.k; ++i) evals[i] = i < kout ? theta[i] : 0.0;
-    launch_copy_cols(S.Vt, N, evecs, ldv, N, kout, S.s);
-    EIG_TRY(S.check(hipStreamSynchronize(S.s), "sync"));
-    if (rep) {
-        for (int p = 0; p < 4; ++p) {
-            rep->n_applies[p] = S.applies[p];
-            rep->n_block_applies[p] = S.block_applies[p];
-        }
-        rep->n_restarts = S.restarts;
-        rep->converged = converged;
-        rep->t_solve = std::chrono::duration<double>(clock::now() - t0).count();
-        rep->t_host_eig = t_host_eig;
-        rep->max_rel_residual = max_rel;
-    }
-#undef EIG_TRY
-    if (converged < S.k) {
-        std::ostringstream os;
-        os << "kl_eigs: " << converged << " of " << S.k << " pairs converged within " << max_applies
-           << " applies";
-        set_error(os.str());
-        return KL_ENOCONV;
-    }
     return KL_OK;
 }

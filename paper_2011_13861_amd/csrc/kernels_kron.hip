@@ -25,24 +25,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-struct ModeArgs {
-    const double *D;          // nout x nin row-major
-    const double *DT;         // nin x nout row-major (D transposed)
-    const void *in;           // TIN
-    void *out;                // TOUT
-    int64_t A;                // product of the sizes before the direction (1 = first)
-    int nin, nout;
-    int64_t Clo;              // product of the sizes after the direction
-    int nvec;
-    int64_t in_ldj, out_ldj;  // distance between vectors
-    int nsplit;               // input partial sums to add (stage-5 splits)
-    int64_t in_split;         // distance between splits
-    const double *in_w;       // optional per-point input scale (times in_scale)
-    double in_scale;
-    const double *out_w;      // optional per-point output scale
-    void *out_lo;             // BF16 output only: low part v - bf16(v), or NULL
-};
-
 template <typename TOUT>
 __device__ __forceinline__ void store_out(TOUT *out, void *out_lo, int64_t addr, double v) {
     if constexpr (std::is_same<TOUT, __bf16>::value) {
@@ -69,14 +51,13 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int kChunk = 16;                 // MFMA steps per operand batch (64 indices)
 
 template <bool FIRST, typename TIN, typename TOUT>
-__global__ __launch_bounds__(kThreads) void mode_kernel(ModeArgs g) {
+__device__ __forceinline__ void mode_tile(const ModeArgs &g, int64_t tile) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nin = g.nin, nout = g.nout;
     const int64_t nrows = g.A * g.Clo * g.nvec;
     const int64_t rtiles = (nrows + 15) / 16;
     const int otiles = (nout + 15) / 16;
-    const int64_t tile = int64_t(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6);
     if (tile >= rtiles * otiles) return;           // whole wave leaves together
     const int64_t rt = tile / otiles;
     const int ot = int(tile % otiles);
@@ -135,6 +116,29 @@ __global__ __launch_bounds__(kThreads) void mode_kernel(ModeArgs g) {
     }
 }
 
+template <bool FIRST, typename TIN, typename TOUT>
+__global__ __launch_bounds__(kThreads) void mode_kernel(ModeArgs g) {
+    mode_tile<FIRST, TIN, TOUT>(g, int64_t(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6));
+}
+
+// One direction for every problem of a batch: workgroup b belongs to the problem p with
+// wg_prefix[p] <= b < wg_prefix[p + 1] (binary search over nprob + 1 entries) and
+// computes that problem's tiles 4 (b - wg_prefix[p]) + wave.
+template <bool FIRST, typename TIN, typename TOUT>
+__global__ __launch_bounds__(kThreads) void mode_batch_kernel(const ModeArgs *__restrict__ args,
+                                                              const int64_t *__restrict__ wg_prefix, int nprob,
+                                                              const int *__restrict__ active) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nprob;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (wg_prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    if (active && active[lo] == 0) return;
+    const ModeArgs g = args[lo];
+    mode_tile<FIRST, TIN, TOUT>(g, (b - wg_prefix[lo]) * (kThreads / 64) + (threadIdx.x >> 6));
+}
+
 __global__ __launch_bounds__(kThreads) void copy_cols_kernel(
     const double *__restrict__ src, int64_t lds, double *__restrict__ dst, int64_t ldd,
     int64_t rows, int cols) {
@@ -185,15 +189,43 @@ unsigned grid_for(int64_t total) {
 
 bool mode_fits(int nin, int nout) { return nin >= 1 && nout >= 1 && nin <= 4096 && nout <= 4096; }
 
-void launch_mode(const ModeSpec &m, hipStream_t s) {
+ModeArgs mode_args(const ModeSpec &m) {
     ModeArgs a;
     a.D = m.D; a.DT = m.DT; a.in = m.in; a.out = m.out; a.A = m.A; a.nin = m.nin; a.nout = m.nout;
     a.Clo = m.Clo; a.nvec = m.nvec; a.in_ldj = m.in_ldj; a.out_ldj = m.out_ldj;
     a.nsplit = 1; a.in_split = 0;
     a.in_w = m.in_w; a.in_scale = m.in_scale; a.out_w = m.out_w; a.out_lo = m.out_lo;
+    return a;
+}
+
+int64_t mode_workgroups(const ModeSpec &m) {
     const int64_t nrows = m.A * m.Clo * m.nvec;
     const int64_t tiles = (nrows + 15) / 16 * ((m.nout + 15) / 16);
-    const dim3 grid(unsigned((tiles + 3) / 4));
+    return (tiles + 3) / 4;
+}
+
+void launch_mode_batch(const ModeSpec &kind, const ModeArgs *args, const int64_t *wg_prefix, int nprob,
+                       int64_t total_wgs, const int *active, hipStream_t s) {
+    if (total_wgs < 1) return;
+    const dim3 grid(static_cast<unsigned>(total_wgs));
+    const bool first = kind.A == 1;
+#define KL_MODEB(F, TI, TO) hipLaunchKernelGGL((mode_batch_kernel<F, TI, TO>), grid, dim3(kThreads), 0, s, \
+                                               args, wg_prefix, nprob, active)
+    if (kind.in_f32) {
+        if (first) KL_MODEB(true, float, double); else KL_MODEB(false, float, double);
+    } else if (kind.out_f32) {
+        if (first) KL_MODEB(true, double, float); else KL_MODEB(false, double, float);
+    } else if (kind.out_bf16) {
+        if (first) KL_MODEB(true, double, __bf16); else KL_MODEB(false, double, __bf16);
+    } else {
+        if (first) KL_MODEB(true, double, double); else KL_MODEB(false, double, double);
+    }
+#undef KL_MODEB
+}
+
+void launch_mode(const ModeSpec &m, hipStream_t s) {
+    const ModeArgs a = mode_args(m);
+    const dim3 grid(unsigned(mode_workgroups(m)));
     const bool first = m.A == 1;
 #define KL_MODE(F, TI, TO) hipLaunchKernelGGL((mode_kernel<F, TI, TO>), grid, dim3(kThreads), 0, s, a)
     if (m.in_f32) {

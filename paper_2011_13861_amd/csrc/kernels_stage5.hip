@@ -89,9 +89,9 @@ constexpr int kStep = kWaves * kSub;       // l-points per workgroup step
 // otherwise the split's partial (added by split_reduce_kernel in split order).
 template <typename T>
 __device__ __forceinline__ void finish_block(const T *red, T *__restrict__ Zpart, T *__restrict__ Zf,
-                                             int nsplit, int64_t Ntpad, int64_t row0) {
+                                             int split, int nsplit, int64_t Ntpad, int64_t row0) {
     constexpr int kPer = (32 * kBW) / kThreads;          // 4 entries per thread
-    T *dst = nsplit == 1 ? Zf : Zpart + int64_t(blockIdx.y) * Ntpad * kBW;
+    T *dst = nsplit == 1 ? Zf : Zpart + int64_t(split) * Ntpad * kBW;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int e = threadIdx.x + q * kThreads;
@@ -131,6 +131,24 @@ __global__ __launch_bounds__(kThreads) void split_reduce_kernel(const T *__restr
     for (int t = 0; t < 4; ++t) Zf[4 * e4 + t] = acc[t];
 }
 
+// Work of one workgroup: rows [row0, row0 + rows_wg) against the l-range [l0, l1) of
+// split `split` (of nsplit) of a problem with Ntpad padded points.
+struct S5Tile {
+    int64_t Ntpad, row0, l0, l1;
+    int split, nsplit;
+};
+
+__device__ __forceinline__ S5Tile grid_tile(int64_t rows_wg, int64_t Ntpad, int64_t lchunk) {
+    S5Tile t;
+    t.Ntpad = Ntpad;
+    t.row0 = int64_t(blockIdx.x) * rows_wg;
+    t.l0 = int64_t(blockIdx.y) * lchunk;
+    t.l1 = min(t.l0 + lchunk, Ntpad);
+    t.split = int(blockIdx.y);
+    t.nsplit = int(gridDim.y);
+    return t;
+}
+
 // Skeleton shared by all precisions.  The workgroup owns rows [row0, row0 + 64) and the
 // l-range [l0, l1) of its split; each step stages 256 points (and the matching rows of
 // the stage-5 input block) in LDS and wave w contracts the 64-point sub-tile w.  At the
@@ -140,20 +158,18 @@ __global__ __launch_bounds__(kThreads) void split_reduce_kernel(const T *__restr
 // FP32: v_mfma_f32_32x32x2_f32, A = Gamma[32 rows][2 l], B = Y[2 l][32 cols]; A[i][k] and
 // B[k][j] sit in lane (i or j) + 32 k; accumulator r of lane L holds
 // C[(r & 3) + 4 (L >> 5) + 8 (r >> 2)][L & 31].
+// LDS of the FP32 skeleton: points [D][kStep] and the block tile [l][kBW + 1] (reused
+// for the reduction).
+constexpr int kLdsF32Y = kStep * (kBW + 1);
+
 template <int KIND, int D, int RB>
-__global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
-    const float *__restrict__ X, const float *__restrict__ Y, float *__restrict__ Z,
-    float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
-    constexpr int rows_wg = 32 * RB;
+__device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, const float *__restrict__ Y,
+                                                float *__restrict__ Z, float *__restrict__ Zf, const S5Tile &t,
+                                                float (*sX)[kStep], float *sY) {
     constexpr int kLd4 = (kStep * kBW / 4) / kThreads;   // float4 loads per thread per step
-    __shared__ float sX[D][kStep];
-    __shared__ float sY[kStep * (kBW + 1)];               // [l][j]; reused for the reduction
-    static_assert(kStep * (kBW + 1) >= 0, "");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 31, kh = lane >> 5;
-    const int64_t row0 = int64_t(blockIdx.x) * rows_wg;
-    const int64_t l0 = int64_t(blockIdx.y) * lchunk;
-    const int64_t l1 = min(l0 + lchunk, Ntpad);
+    const int64_t Ntpad = t.Ntpad, row0 = t.row0, l0 = t.l0, l1 = t.l1;
     float xk[RB][D];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -225,8 +241,17 @@ __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
             red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][r];
         }
         __syncthreads();
-        finish_block<float>(red, Z, Zf, int(gridDim.y), Ntpad, row0 + rb * 32);
+        finish_block<float>(red, Z, Zf, t.split, t.nsplit, Ntpad, row0 + rb * 32);
     }
+}
+
+template <int KIND, int D, int RB>
+__global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
+    const float *__restrict__ X, const float *__restrict__ Y, float *__restrict__ Z,
+    float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
+    __shared__ float sX[D][kStep];
+    __shared__ float sY[kLdsF32Y];
+    stage5_f32_body<KIND, D, RB>(X, Y, Z, Zf, grid_tile(32 * RB, Ntpad, lchunk), sX, sY);
 }
 
 // FP64: v_mfma_f64_16x16x4_f64, A = Gamma[16 rows][4 l], B = Y[4 l][16 cols]; A[i][k] and
@@ -234,17 +259,14 @@ __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
 // (measured on gfx950; differs from the FP32 16x16x4 layout).  Four 16-row tiles x two
 // 16-column halves per wave.
 template <int KIND, int D>
-__global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
-    const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ Z,
-    double *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
-    extern __shared__ double sm64[];
+__device__ __forceinline__ void stage5_f64_body(const double *__restrict__ X, const double *__restrict__ Y,
+                                                double *__restrict__ Z, double *__restrict__ Zf,
+                                                const S5Tile &t, double *sm64) {
     double *sX = sm64;                           // [D][kStep]
     double *sY = sm64 + D * kStep;               // [l][kBW + 1]; reduction reuses it all
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 15, kq = lane >> 4;
-    const int64_t row0 = int64_t(blockIdx.x) * kRows;
-    const int64_t l0 = int64_t(blockIdx.y) * lchunk;
-    const int64_t l1 = min(l0 + lchunk, Ntpad);
+    const int64_t Ntpad = t.Ntpad, row0 = t.row0, l0 = t.l0, l1 = t.l1;
     double xk[4][D];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
@@ -314,10 +336,18 @@ __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
                 red[(wave * 32 + row) * (kBW + 1) + 16 + i] = acc[rb][1][r];
             }
         __syncthreads();
-        finish_block<double>(red, Z, Zf, int(gridDim.y), Ntpad, row0 + 32 * half);
+        finish_block<double>(red, Z, Zf, t.split, t.nsplit, Ntpad, row0 + 32 * half);
     }
 }
 constexpr size_t kLds64 = size_t(3 * kStep + kStep * (kBW + 1)) * sizeof(double);
+
+template <int KIND, int D>
+__global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
+    const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ Z,
+    double *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
+    extern __shared__ double sm64[];
+    stage5_f64_body<KIND, D>(X, Y, Z, Zf, grid_tile(kRows, Ntpad, lchunk), sm64);
+}
 
 // BF16: v_mfma_f32_32x32x16_bf16, A = Gamma[32 rows][16 l], B = Y[16 l][32 cols];
 // A[i][k] in lane i + 32 (k / 8), element k % 8; B[k][j] in lane j + 32 (k / 8), element
@@ -427,8 +457,116 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
             red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][r];
         }
         __syncthreads();
-        finish_block<float>(red, Z, Zf, int(gridDim.y), Ntpad, row0 + rb * 32);
+        finish_block<float>(red, Z, Zf, int(blockIdx.y), int(gridDim.y), Ntpad, row0 + rb * 32);
     }
+}
+
+
+// ---- batched form: many problems, one persistent launch ------------------------------
+// The grid holds as many workgroups as fit on the chip at once; each repeatedly takes
+// the next (problem, row tile, split) item from a queue (a device counter) and runs the
+// same skeleton on it.  Items are ordered longest first on the host, so the tail of the
+// launch is made of short items.  Problems whose active flag is 0 are skipped.
+__device__ __forceinline__ int next_item(int *counter, int *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*slot);
+}
+
+__device__ __forceinline__ S5Tile item_tile(const S5Prob &P, const S5Item &I, int64_t rows_wg) {
+    S5Tile t;
+    t.Ntpad = P.Ntpad;
+    t.row0 = int64_t(I.rowtile) * rows_wg;
+    t.l0 = int64_t(I.split) * P.lchunk;
+    t.l1 = min(t.l0 + P.lchunk, P.Ntpad);
+    t.split = I.split;
+    t.nsplit = P.nsplit;
+    return t;
+}
+
+template <int D, int RB>
+__global__ __launch_bounds__(kThreads) void stage5_f32_batch_kernel(const S5Prob *__restrict__ probs,
+                                                                    const S5Item *__restrict__ items, int n_items,
+                                                                    int *__restrict__ counter,
+                                                                    const int *__restrict__ active) {
+    __shared__ float sX[D][kStep];
+    __shared__ float sY[kLdsF32Y];
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(counter, &slot);
+        if (it >= n_items) break;
+        const S5Item I = items[it];
+        if (active && active[I.prob] == 0) continue;
+        const S5Prob P = probs[I.prob];
+        const S5Tile t = item_tile(P, I, 32 * RB);
+        const float *Y = static_cast<const float *>(P.Y5);
+        float *Z = static_cast<float *>(P.Z5), *Zf = static_cast<float *>(P.Zf);
+        switch (P.kind) {
+        case KL_COV_EXP: stage5_f32_body<KL_COV_EXP, D, RB>(P.X32, Y, Z, Zf, t, sX, sY); break;
+        case KL_COV_SQEXP: stage5_f32_body<KL_COV_SQEXP, D, RB>(P.X32, Y, Z, Zf, t, sX, sY); break;
+        case KL_COV_EXP_L1: stage5_f32_body<KL_COV_EXP_L1, D, RB>(P.X32, Y, Z, Zf, t, sX, sY); break;
+        case KL_COV_CONST: stage5_f32_body<KL_COV_CONST, D, RB>(P.X32, Y, Z, Zf, t, sX, sY); break;
+        default: stage5_f32_body<KL_COV_LIN, D, RB>(P.X32, Y, Z, Zf, t, sX, sY); break;
+        }
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void stage5_f64_batch_kernel(const S5Prob *__restrict__ probs,
+                                                                    const S5Item *__restrict__ items, int n_items,
+                                                                    int *__restrict__ counter,
+                                                                    const int *__restrict__ active) {
+    extern __shared__ double sm64[];
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(counter, &slot);
+        if (it >= n_items) break;
+        const S5Item I = items[it];
+        if (active && active[I.prob] == 0) continue;
+        const S5Prob P = probs[I.prob];
+        const S5Tile t = item_tile(P, I, kRows);
+        const double *Y = static_cast<const double *>(P.Y5);
+        double *Z = static_cast<double *>(P.Z5), *Zf = static_cast<double *>(P.Zf);
+        switch (P.kind) {
+        case KL_COV_EXP: stage5_f64_body<KL_COV_EXP, D>(P.X64, Y, Z, Zf, t, sm64); break;
+        case KL_COV_SQEXP: stage5_f64_body<KL_COV_SQEXP, D>(P.X64, Y, Z, Zf, t, sm64); break;
+        case KL_COV_EXP_L1: stage5_f64_body<KL_COV_EXP_L1, D>(P.X64, Y, Z, Zf, t, sm64); break;
+        case KL_COV_CONST: stage5_f64_body<KL_COV_CONST, D>(P.X64, Y, Z, Zf, t, sm64); break;
+        default: stage5_f64_body<KL_COV_LIN, D>(P.X64, Y, Z, Zf, t, sm64); break;
+        }
+    }
+}
+
+__global__ void reset_counter_kernel(int *counter) {
+    if (threadIdx.x == 0) counter[0] = 0;
+}
+
+// Split sums of all problems of a batch: global 4-entry index -> problem by binary search
+// over the prefix `base4` (nprob + 1 entries), then as split_reduce_kernel.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void split_reduce_batch_kernel(const RedProb *__restrict__ probs, int nprob,
+                                                                      int64_t total4, const int *__restrict__ active) {
+    const int64_t g4 = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g4 >= total4) return;
+    int lo = 0, hi = nprob;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (probs[mid].base4 <= g4) lo = mid; else hi = mid;
+    }
+    const RedProb P = probs[lo];
+    if (active && active[P.prob] == 0) return;
+    const int64_t e4 = g4 - P.base4;
+    const T *Zpart = static_cast<const T *>(P.Zpart);
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    for (int sp = 0; sp < P.nsplit; ++sp) {
+        const T *src = Zpart + int64_t(sp) * P.stride + 4 * e4;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] += src[t];
+    }
+    T *Zf = static_cast<T *>(P.Zf);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Zf[4 * e4 + t] = acc[t];
 }
 
 template <int KIND, int D>
@@ -540,6 +678,60 @@ int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, 
                                P->Ntpad * kBW);
     }
     return nsplit;
+}
+
+int stage5_batch_grid(int precision, int d, int rb, int n_cu) {
+    int per_cu = 1;
+    hipError_t e;
+    const void *fn;
+    size_t lds = 0;
+    if (precision == KL_F64) {
+        fn = d == 1 ? reinterpret_cast<const void *>(&stage5_f64_batch_kernel<1>)
+           : d == 2 ? reinterpret_cast<const void *>(&stage5_f64_batch_kernel<2>)
+                    : reinterpret_cast<const void *>(&stage5_f64_batch_kernel<3>);
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(kLds64));
+        lds = kLds64;
+    } else if (rb == 4) {
+        fn = d == 1 ? reinterpret_cast<const void *>(&stage5_f32_batch_kernel<1, 4>)
+           : d == 2 ? reinterpret_cast<const void *>(&stage5_f32_batch_kernel<2, 4>)
+                    : reinterpret_cast<const void *>(&stage5_f32_batch_kernel<3, 4>);
+    } else {
+        fn = d == 1 ? reinterpret_cast<const void *>(&stage5_f32_batch_kernel<1, 2>)
+           : d == 2 ? reinterpret_cast<const void *>(&stage5_f32_batch_kernel<2, 2>)
+                    : reinterpret_cast<const void *>(&stage5_f32_batch_kernel<3, 2>);
+    }
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * n_cu;
+}
+
+void launch_stage5_batch(int precision, int d, int rb, const S5Prob *probs, const S5Item *items, int n_items,
+                         int *counter, const int *active, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+    const dim3 g(unsigned(std::max(grid, 1)));
+    if (precision == KL_F64) {
+        if (d == 1) hipLaunchKernelGGL(stage5_f64_batch_kernel<1>, g, dim3(kThreads), kLds64, s, probs, items, n_items, counter, active);
+        else if (d == 2) hipLaunchKernelGGL(stage5_f64_batch_kernel<2>, g, dim3(kThreads), kLds64, s, probs, items, n_items, counter, active);
+        else hipLaunchKernelGGL(stage5_f64_batch_kernel<3>, g, dim3(kThreads), kLds64, s, probs, items, n_items, counter, active);
+    } else if (rb == 4) {
+        if (d == 1) hipLaunchKernelGGL((stage5_f32_batch_kernel<1, 4>), g, dim3(kThreads), 0, s, probs, items, n_items, counter, active);
+        else if (d == 2) hipLaunchKernelGGL((stage5_f32_batch_kernel<2, 4>), g, dim3(kThreads), 0, s, probs, items, n_items, counter, active);
+        else hipLaunchKernelGGL((stage5_f32_batch_kernel<3, 4>), g, dim3(kThreads), 0, s, probs, items, n_items, counter, active);
+    } else {
+        if (d == 1) hipLaunchKernelGGL((stage5_f32_batch_kernel<1, 2>), g, dim3(kThreads), 0, s, probs, items, n_items, counter, active);
+        else if (d == 2) hipLaunchKernelGGL((stage5_f32_batch_kernel<2, 2>), g, dim3(kThreads), 0, s, probs, items, n_items, counter, active);
+        else hipLaunchKernelGGL((stage5_f32_batch_kernel<3, 2>), g, dim3(kThreads), 0, s, probs, items, n_items, counter, active);
+    }
+}
+
+void launch_split_reduce_batch(int precision, const RedProb *probs, int nprob, int64_t total4, const int *active,
+                               hipStream_t s) {
+    if (nprob < 1 || total4 < 1) return;
+    const dim3 g(unsigned((total4 + kThreads - 1) / kThreads));
+    if (precision == KL_F64)
+        hipLaunchKernelGGL(split_reduce_batch_kernel<double>, g, dim3(kThreads), 0, s, probs, nprob, total4, active);
+    else
+        hipLaunchKernelGGL(split_reduce_batch_kernel<float>, g, dim3(kThreads), 0, s, probs, nprob, total4, active);
 }
 
 }  // namespace kl

@@ -56,6 +56,8 @@ void free_solver_cache(SolverCache *c);
 
 }  // namespace kl
 
+struct kl_batch;
+
 struct kl_problem {
     kl::HostSetup hs;
     int cov_kind = 0;
@@ -109,6 +111,32 @@ struct ModeSpec {
     void *out_lo = nullptr;         // BF16 output: low parts (hi/lo split), or NULL
     bool in_f32 = false, out_f32 = false, out_bf16 = false;
 };
+// Kernel-side form of a ModeSpec (kernels_kron.hip).
+struct ModeArgs {
+    const double *D;          // nout x nin row-major
+    const double *DT;         // nin x nout row-major (D transposed)
+    const void *in;           // TIN
+    void *out;                // TOUT
+    int64_t A;                // product of the sizes before the direction (1 = first)
+    int nin, nout;
+    int64_t Clo;              // product of the sizes after the direction
+    int nvec;
+    int64_t in_ldj, out_ldj;  // distance between vectors
+    int nsplit;               // unused (1)
+    int64_t in_split;
+    const double *in_w;       // optional per-point input scale (times in_scale)
+    double in_scale;
+    const double *out_w;      // optional per-point output scale
+    void *out_lo;             // BF16 output only: low part v - bf16(v), or NULL
+};
+ModeArgs mode_args(const ModeSpec &m);
+// Workgroups of one launch_mode (4 waves of one 16 x 16 tile each).
+int64_t mode_workgroups(const ModeSpec &m);
+// One direction for all problems of a batch: args[p] per problem (device), wg_prefix
+// (device, nprob + 1 entries) the prefix sums of mode_workgroups; `kind` selects the
+// kernel variant (first direction, FP32 input, FP32 / BF16 output) shared by all.
+void launch_mode_batch(const ModeSpec &kind, const ModeArgs *args, const int64_t *wg_prefix, int nprob,
+                       int64_t total_wgs, const int *active, hipStream_t s);
 // true if a factor (nout x nin) fits the LDS-staged MFMA kernel
 bool mode_fits(int nin, int nout);
 void launch_mode(const ModeSpec &m, hipStream_t s);
@@ -137,5 +165,56 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 // Stage 5: Zf[j][k] = sum_l Gamma(x_k, x_l) Y5[j][l]; Z5 holds split partials (scratch).
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
                   hipStream_t s);
+
+// kl_setup with or without the single-problem apply workspace (T0/T1, stage-5 buffers);
+// problems of a batch use the batch's arenas instead.
+kl_status setup_problem(const kl_desc *desc, bool workspace, kl_problem **out);
+void destroy_problem(kl_problem *P);
+int64_t max_intermediate(const HostSetup &hs);
+// One chunk (<= kBW columns) of the single-problem apply.
+kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx, double *y,
+                      int64_t ldy, hipStream_t s);
+
+// ---- batches of problems (batch.hip) ---------------------------------------------------
+int batch_size(const kl_batch *B);
+kl_problem *batch_problem(kl_batch *B, int i);
+hipStream_t batch_stream(kl_batch *B);
+// A~'_i applied to nvec[i] <= kBW columns of each problem i (0 = skip), one graph replay.
+kl_status batch_apply(kl_batch *B, int precision, const int *nvec, const double *const *x, const int64_t *ldx,
+                      double *const *y, const int64_t *ldy, hipStream_t s);
+
+// ---- batched stage 5 (kernels_stage5.hip) -------------------------------------------
+// One problem of a batch: points (FP32 and FP64 scaled copies, [d][Ntpad]), its
+// stage-5 input, split partials and output (layouts as for one problem), l-range per
+// split and the covariance kind.
+struct S5Prob {
+    const float *X32;
+    const double *X64;
+    const void *Y5;
+    void *Z5;
+    void *Zf;
+    int64_t Ntpad, lchunk;
+    int nsplit, kind;
+};
+// One work item: the workgroup-sized row tile `rowtile` of problem `prob` against split
+// `split` of its l-range.
+struct S5Item {
+    int prob, rowtile, split, pad;
+};
+// Split sum of one problem: Zf[4 e4 + t] = sum_s Zpart[s stride + 4 e4 + t], e4 < n4;
+// base4 = sum of n4 over the preceding entries.
+struct RedProb {
+    const void *Zpart;
+    void *Zf;
+    int64_t n4, stride, base4;
+    int nsplit, prob;
+};
+// Persistent grid size (workgroups resident at once) of the batched stage-5 kernel.
+int stage5_batch_grid(int precision, int d, int rb, int n_cu);
+// Resets `counter` and launches the persistent kernel over n_items queue entries.
+void launch_stage5_batch(int precision, int d, int rb, const S5Prob *probs, const S5Item *items, int n_items,
+                         int *counter, const int *active, int grid, hipStream_t s);
+void launch_split_reduce_batch(int precision, const RedProb *probs, int nprob, int64_t total4, const int *active,
+                               hipStream_t s);
 
 }  // namespace kl
