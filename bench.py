@@ -56,6 +56,136 @@ def cpu_baseline(desc, b, budget_s=12.0):
                       % (n, b, dt)}, float(np.float64(dt / n))
 
 
+def warm_start_section(n_train, epochs, n_eval, solves=3):
+    """Config 5: the network is trained on n_train method-generated FP64 solves (tol 1e-10)
+    of the 48x48 cubic quarter annulus (training draws seed 2000), then the held-out draws
+    (seed 2001) are solved to 1e-6 three ways: plain FP64 from a random block, FP32 with
+    FP64 refinement from a random block, and the same from the predicted block (network
+    inference included in the timed solve).  Times are medians over the held-out draws."""
+    import numpy as np
+    import torch
+
+    import paper_2011_13861_amd as kl
+    import workloads
+    from paper_2011_13861_amd import warmstart
+    K = 16
+
+    def covs(L, a, flag):
+        out = []
+        for Li, ai, fi in zip(L, a, flag):
+            d = workloads.mlp_problem(Li, ai, fi)
+            out.append((d["cov"]["kind"], d["cov"]["sigma2"], d["cov"]["corr_len"]))
+        return out
+
+    G = kl.Problem(workloads.mlp_problem(1.0, 1.0, 0))
+    L, a, flag = workloads.mlp_parameters(2000, n_train)
+    t = time.perf_counter()
+    T, _, _ = warmstart.generate(G, covs(L, a, flag), K, block=16, tol=1e-10)
+    gen_s = time.perf_counter() - t
+    ws = warmstart.WarmStart(G.N, K, seed=0)
+    t = time.perf_counter()
+    losses = ws.fit(warmstart.features(L, a, flag), T, epochs=epochs, batch=64, lr0=1e-3, lr1=3e-5)
+    train_s = time.perf_counter() - t
+    del T
+    Le, ae, fe = workloads.mlp_parameters(2001, n_eval)
+    rec = {"f64": [], "f32_random": [], "f32_warm": []}
+    app = {k: [] for k in rec}
+    for i, cov in enumerate(covs(Le, ae, fe)):
+        G.set_cov(*cov)
+        f = warmstart.features(Le[i], ae[i], fe[i])[0]
+        runs = {"f64": lambda: G.eigs(K, precision="f64", block=16, tol=1e-6),
+                "f32_random": lambda: G.eigs(K, precision="f32", block=16, tol=1e-6),
+                "f32_warm": lambda: warmstart.solve(G, K, ws, f, precision="f32", block=16, tol=1e-6)}
+        for name, fn in runs.items():
+            best = None
+            for _ in range(solves):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, _, rep = fn()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                best = dt if best is None else min(best, dt)
+            rec[name].append(best)
+            app[name].append(sum(rep["n_applies"]))
+    med = {k: float(np.median(v)) * 1e3 for k, v in rec.items()}
+    return {"workload": "c5: 2D quarter annulus 48x48 cubic, N = 2601, k = 16, block 16; "
+                        "L ~ logU[0.1,2], a ~ logU[0.5,2], flag ~ B(1/2)",
+            "n_train": n_train, "epochs": epochs, "generate_s": gen_s, "train_s": train_s,
+            "loss_first_last": [float(losses[0]), float(losses[-1])], "n_eval": n_eval,
+            "median_ms": med, "mean_applies": {k: float(np.mean(v)) for k, v in app.items()},
+            "f32_warm_speedup_vs_f64": med["f64"] / med["f32_warm"]}
+
+
+def batch_section(reps=20):
+    """Config 4: 64 uneven 2D problems (seed 1127).  The batched apply (one graph replay
+    of 32 columns per problem, autotuned tiles) against the same 64 applies issued one
+    problem after the other; then 20 eigenpairs of every problem at 1e-6, batched
+    (FP32 with FP64 refinement) against 64 sequential kl_eigs calls."""
+    import numpy as np
+    import torch
+
+    import paper_2011_13861_amd as kl
+    import workloads
+    from paper_2011_13861_amd import autotune
+    descs = workloads.batch_problems(1127)
+    kinds = [d["cov"]["kind"] for d in descs]
+    B = kl.Batch(descs)
+    pairs = float(sum(nt * nt for nt in B.Nt))
+    out = {"workload": "c4: 64 unit-square problems, nelem ~ U{16..96}^2, p ~ U{2,3,4}, exp/sqexp, "
+                       "L ~ logU[0.1,2] (seed 1127), 32 vectors each",
+           "pairs_per_apply": pairs}
+    x = torch.randn(B.Ntot * 32, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    singles = [kl.Problem(d) for d in descs]
+    for prec in ("f32", "f64"):
+        rb, lc, _ = autotune.tune_batch(B, kinds, prec, reps=5)
+        for _ in range(3):
+            B.apply(x, y, 32, prec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            B.apply(x, y, 32, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        t_b = e0.elapsed_time(e1) / reps * 1e-3
+        xs = [B.block(x, i, 32) for i in range(B.n)]
+        ys = [kl.new_block(G.N, 32) for G in singles]
+        for G, xi, yi in zip(singles, xs, ys):
+            G.apply(xi, yi, prec)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(max(1, reps // 4)):
+            for G, xi, yi in zip(singles, xs, ys):
+                G.apply(xi, yi, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        t_s = e0.elapsed_time(e1) / max(1, reps // 4) * 1e-3
+        out["apply_" + prec] = {"batched_ms": t_b * 1e3, "pair_evals_per_s": pairs / t_b, "rb": rb, "lchunk": lc,
+                                "sequential_ms": t_s * 1e3, "speedup": t_s / t_b}
+    B.eigs(20, precision="f32", block=32, tol=1e-6)          # warm (solver buffers, handles)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ev, _, reps_b = B.eigs(20, precision="f32", block=32, tol=1e-6)
+    torch.cuda.synchronize()
+    t_eb = time.perf_counter() - t
+    seq = {}
+    for prec in ("f32", "f64"):
+        for G in singles[:2]:
+            G.eigs(20, precision=prec, block=32, tol=1e-6)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for G in singles:
+            G.eigs(20, precision=prec, block=32, tol=1e-6)
+        torch.cuda.synchronize()
+        seq[prec] = (time.perf_counter() - t) * 1e3
+    out["eigs_k20"] = {"batched_f32_refined_ms": t_eb * 1e3,
+                       "all_converged": all(r["converged"] == 20 for r in reps_b),
+                       "sequential_f32_refined_ms": seq["f32"], "sequential_f64_ms": seq["f64"],
+                       "speedup_vs_sequential_f64": seq["f64"] / (t_eb * 1e3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +195,12 @@ def main():
     ap.add_argument("--precision", default=None, choices=["f32", "f64"])
     ap.add_argument("--solves", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mlp-train", type=int, default=2000,
+                    help="training solves for the warm-start section (0 = skip the section)")
+    ap.add_argument("--mlp-epochs", type=int, default=200)
+    ap.add_argument("--mlp-eval", type=int, default=20)
+    ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batch section")
+    ap.add_argument("--no-tune", action="store_true", help="keep the automatic stage-5 split")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="also run one plain device-to-device copy of MB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -90,6 +226,10 @@ def main():
     desc, k, b = workloads.config(args.workload)
     prec = args.precision or "f32"
     G = kl.Problem(desc)
+    tuned = None
+    if not args.no_tune:
+        from paper_2011_13861_amd import autotune
+        tuned = autotune.tune_problem(G, desc["cov"]["kind"], precisions=(prec,), reps=10)[prec]
     x = kl.to_device_block(workloads.random_block(G.N, b, seed=1))
     y = kl.new_block(G.N, b)
     stream = torch.cuda.current_stream()
@@ -119,7 +259,8 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
                 "kernel": "stage5_%s_kernel" % prec, "kernel_avg_us": k_avg_s * 1e6,
-                "kernel_pairs_per_s": pairs / k_avg_s, "launches": cnt}
+                "kernel_pairs_per_s": pairs / k_avg_s, "launches": cnt,
+                "stage5_tiles": None if tuned is None else {"rb": tuned[0], "nsplit": tuned[1]}}
 
     # time to k eigenpairs at relative residual 1e-6 (criterion under the FP64 operator)
     def solve(p):
@@ -153,6 +294,10 @@ def main():
                       "f32_report": rep_lo, "f64_report": rep_64},
         "wall_s_timed_region": wall,
     }
+    if not args.no_batch:
+        out["batch"] = batch_section()
+    if args.mlp_train > 0:
+        out["warm_start"] = warm_start_section(args.mlp_train, args.mlp_epochs, args.mlp_eval)
     if not args.no_cpu:
         cb, _ = cpu_baseline(desc, b)
         out["cpu_baseline"] = cb

@@ -1,0 +1,151 @@
+"""Autotuner for the stage-5 tiles (argument marshalling and timing over the C ABI).
+
+The stage-5 kernels have two launch parameters that the best choice of depends on the
+problem size and on the chip: the rows per workgroup (rb 32-row blocks per wave, FP32 and
+BF16 kernels) and how the l-range is split across workgroups (split count for one
+problem, l-points per split for a batch).  The tuner times every candidate with HIP
+events on the device (kl_profile_* for one problem, events around the graph replay for a
+batch), keeps the fastest, and caches it in a JSON file keyed by
+
+    (GPU architecture, dimension, covariance kind, precision, padded grid size)
+
+for single problems, and by (architecture, dimension, precision, batch signature) for
+batches.  Cached settings are applied with `apply_cached`.  The cache file is
+$KL_TUNE_CACHE, else ~/.cache/paper_2011_13861_amd/stage5_tune.json.
+"""
+
+import hashlib
+import json
+import os
+
+
+def cache_path():
+    return os.environ.get("KL_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_2011_13861_amd", "stage5_tune.json")
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def arch():
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def _padded(nt):
+    return (nt + 255) // 256 * 256
+
+
+def problem_key(G, kind, precision):
+    return "|".join([arch(), "d%d" % G.d, kind, precision, "Np%d" % _padded(G.Nt)])
+
+
+def batch_key(B, kinds, precision):
+    sig = hashlib.sha1(json.dumps([[_padded(nt), k] for nt, k in zip(B.Nt, kinds)]).encode()).hexdigest()[:16]
+    return "|".join([arch(), "batch", precision, "n%d" % B.n, sig])
+
+
+def _time_problem(G, precision, reps, nvec=32):
+    import torch
+    yin = torch.randn((nvec, G.Nt), dtype=torch.float64, device="cuda").T
+    z = torch.empty((nvec, G.Nt), dtype=torch.float64, device="cuda").T
+    for _ in range(3):
+        G.stage5(yin, z, precision)
+    torch.cuda.synchronize()
+    G.profile_enable(True)
+    for _ in range(reps):
+        G.stage5(yin, z, precision)
+    torch.cuda.synchronize()
+    cnt, ms = G.profile_read()[precision]
+    G.profile_enable(False)
+    return ms / max(cnt, 1) * 1e3
+
+
+def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None, verbose=False):
+    """Searches (rb, nsplit) for each precision on problem G (covariance `kind`), sets
+    the best, records it in the cache and returns {precision: (rb, nsplit, us)}."""
+    path = path or cache_path()
+    data = _load(path)
+    out = {}
+    for prec in precisions:
+        rbs = [2] if prec == "f64" else [2, 4]
+        best = None
+        for rb in rbs:
+            _, auto = G.stage5_config(prec, rb=rb, nsplit=0)
+            cands = sorted({auto, 1} | set(range(2, max_split + 1, 1 if max_split <= 24 else 2)))
+            for ns in cands:
+                rbe, nse = G.stage5_config(prec, rb=rb, nsplit=ns)
+                if nse != ns and ns != auto:
+                    continue                      # capped: same as a smaller candidate
+                us = _time_problem(G, prec, reps)
+                if verbose:
+                    print("tune", prec, rbe, nse, "%.1f us" % us)
+                if best is None or us < best[2]:
+                    best = (rbe, nse, us)
+        G.stage5_config(prec, rb=best[0], nsplit=best[1])
+        data[problem_key(G, kind, prec)] = {"rb": best[0], "nsplit": best[1], "us": best[2]}
+        out[prec] = best
+    _store(path, data)
+    return out
+
+
+def tune_batch(B, kinds, precision="f32", reps=10, path=None, verbose=False):
+    """Searches (rb, l-points per split) of the batched stage-5 kernel by timing whole
+    graph replays (32 columns per problem); sets and records the best."""
+    import torch
+    path = path or cache_path()
+    data = _load(path)
+    x = torch.randn(B.Ntot * 32, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    rbs = [2] if precision == "f64" else [2, 4]
+    best = None
+    for rb in rbs:
+        for lc in (0, 512, 1024, 2048, 4096, 8192, 16384):
+            B.config(precision, rb=rb, lchunk=lc)
+            for _ in range(2):
+                B.apply(x, y, 32, precision)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                B.apply(x, y, 32, precision)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            if verbose:
+                print("tune batch", precision, rb, lc, "%.1f us" % us)
+            if best is None or us < best[2]:
+                best = (rb, lc, us)
+    B.config(precision, rb=best[0], lchunk=best[1])
+    data[batch_key(B, kinds, precision)] = {"rb": best[0], "lchunk": best[1], "us": best[2]}
+    _store(path, data)
+    return best
+
+
+def apply_cached(G, kind, precision, path=None):
+    """Sets the cached setting for G, if any; returns it (or None)."""
+    e = _load(path or cache_path()).get(problem_key(G, kind, precision))
+    if e:
+        G.stage5_config(precision, rb=e["rb"], nsplit=e["nsplit"])
+    return e
+
+
+def apply_cached_batch(B, kinds, precision, path=None):
+    e = _load(path or cache_path()).get(batch_key(B, kinds, precision))
+    if e:
+        B.config(precision, rb=e["rb"], lchunk=e["lchunk"])
+    return e

@@ -116,10 +116,10 @@ int64_t max_intermediate(const HostSetup &hs) {
 // Stage-5 launch, bracketed by HIP events on the launch stream while profiling is on.
 int timed_stage5(kl_problem *P, int precision, const void *Y5, hipStream_t s) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
-    if (rec) hipEventRecord(P->prof_ev[P->prof_used], s);
-    const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, P->ws.Zf, s);
+    if (rec) (void)hipEventRecord(P->prof_ev[P->prof_used], s);
+    const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, P->ws.Zf, s,
+                                     rec ? P->prof_ev[P->prof_used + 1] : nullptr);
     if (rec) {
-        hipEventRecord(P->prof_ev[P->prof_used + 1], s);
         P->prof_prec.push_back(precision);
         P->prof_used += 2;
     }

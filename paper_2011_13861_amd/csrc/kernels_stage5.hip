@@ -655,7 +655,7 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 }
 
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
-                  hipStream_t s) {
+                  hipStream_t s, hipEvent_t after_main) {
     const int rb = P->s5_rb[precision] == 4 ? 4 : 2;
     int64_t lchunk;
     const int nsplit = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rb), P->n_cu,
@@ -665,6 +665,7 @@ int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, 
     case 2: launch_dim<2>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
     default: launch_dim<3>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
     }
+    if (after_main) (void)hipEventRecord(after_main, s);
     if (nsplit > 1) {
         const int64_t n4 = P->Ntpad * kBW / 4;
         const dim3 g(unsigned((n4 + kThreads - 1) / kThreads));
