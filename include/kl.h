@@ -171,7 +171,7 @@ typedef struct {
  * start.  evals: host, k values.  evecs: device FP64, N x k, leading dimension ldv;
  * unit 2-norm columns v' (so phi_h has unit L2 norm, Sec. 4.1).  rep may be NULL.
  * Synchronous.  On KL_ENOCONV evals/evecs hold the best Ritz pairs found.
- * The solver's device buffers, stream and rocBLAS handle are created on the first call
+ * The solver's device buffers and stream are created on the first call
  * and kept with the handle (grown when a later call needs more) until kl_destroy, so
  * calls on one handle must not overlap. */
 kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0, int32_t nvec0,
@@ -194,6 +194,14 @@ kl_status kl_profile_read(kl_problem *P, int64_t *count, double *ms);
  * Householder tridiagonalisation + implicit QR with Wilkinson shifts.
  * Errors: KL_EINVAL, KL_ENUMERIC (non-finite input), KL_ENOCONV. */
 kl_status kl_symeig(int32_t n, const double *A, double *w, double *Z);
+
+/* As kl_symeig, but only the eigenvectors of the nv largest eigenvalues (Z: host, n x nv
+ * column-major; all n eigenvalues in w): eigenvalues by QR on the tridiagonal form
+ * without vectors, eigenvectors by inverse iteration on the tridiagonal form (vectors
+ * of eigenvalues closer than 1e-3 ||T|| orthogonalised against each other), then the
+ * Householder back-transformation.  Used by the Rayleigh-Ritz step of kl_eigs, which
+ * needs only the kept Ritz vectors.  Errors: KL_EINVAL, KL_ENUMERIC, KL_ENOCONV. */
+kl_status kl_symeig_partial(int32_t n, const double *A, double *w, double *Z, int32_t nv);
 
 /* ---- Batches of problems -------------------------------------------------------------
  * Many problems of uneven size (same dimension) solved together: one apply of the whole

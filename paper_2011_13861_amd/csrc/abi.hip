@@ -241,9 +241,15 @@ kl_status setup_problem(const kl_desc *desc, bool workspace, kl_problem **out) {
     for (int k = 0; k < hs.d; ++k)
         if (!mode_fits(hs.n[k], hs.nt[k]) || !mode_fits(hs.nt[k], hs.n[k])) {
             delete P;
-            set_error("kl_setup: more than 128 basis functions in one direction are not supported");
+            set_error("kl_setup: more than 4096 basis functions in one direction are not supported");
             return KL_EINVAL;
         }
+    // the Kronecker kernels index the rows of a 32-vector chunk with 32-bit integers
+    if (max_intermediate(hs) * kBW >= (int64_t(1) << 31)) {
+        delete P;
+        set_error("kl_setup: grid too large (intermediate size x 32 must stay below 2^31)");
+        return KL_EINVAL;
+    }
     P->cov_kind = desc->cov_kind;
     P->sigma2 = desc->sigma2;
     for (int k = 0; k < 3; ++k) P->ell[k] = k < hs.d ? desc->corr_len[k] : 1.0;

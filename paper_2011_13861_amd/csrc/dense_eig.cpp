@@ -14,16 +14,19 @@
 
 namespace kl {
 
-// A: n x n symmetric, row-major (read only).  w: eigenvalues, descending.
-// Z: column-major n x n, column j = unit eigenvector of w[j].  Returns false if the QR
-// iteration does not converge.
-bool sym_eig(int n, const double *A, double *w, double *Z) {
-    if (n <= 0) return true;
+namespace {
+
+// Householder reduction a <- H a H to tridiagonal form (d diagonal, e sub-diagonal);
+// reflector k is I - beta[k] v_k v_k^T acting on rows / columns k+1..n-1, with v_k stored
+// in row k of V.
+void tridiagonalise(int n, const double *A, std::vector<double> &d, std::vector<double> &e,
+                    std::vector<double> &V, std::vector<double> &beta) {
     std::vector<double> a(A, A + size_t(n) * n);     // working copy, row-major
-    std::vector<double> d(n, 0.0), e(n, 0.0);
-    std::vector<double> V(size_t(n) * n, 0.0);        // Householder vectors, row k = v_k
-    std::vector<double> beta(n, 0.0), p(n), q(n);
-    // ---- tridiagonalisation: a <- H a H, column by column -----------------------------
+    d.assign(n, 0.0);
+    e.assign(n, 0.0);
+    V.assign(size_t(n) * n, 0.0);
+    beta.assign(n, 0.0);
+    std::vector<double> p(n), q(n);
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;
         double *v = &V[size_t(k) * n];
@@ -65,6 +68,17 @@ bool sym_eig(int n, const double *A, double *w, double *Z) {
     }
     d[n - 1] = a[size_t(n - 1) * n + (n - 1)];
     e[n - 1] = 0.0;
+}
+
+}  // namespace
+
+// A: n x n symmetric, row-major (read only).  w: eigenvalues, descending.
+// Z: column-major n x n, column j = unit eigenvector of w[j].  Returns false if the QR
+// iteration does not converge.
+bool sym_eig(int n, const double *A, double *w, double *Z) {
+    if (n <= 0) return true;
+    std::vector<double> d, e, V, beta;
+    tridiagonalise(n, A, d, e, V, beta);
     // ---- accumulate Q = H_0 H_1 ... H_{n-3}, column-major in Z ------------------------
     for (size_t i = 0; i < size_t(n) * n; ++i) Z[i] = 0.0;
     for (int i = 0; i < n; ++i) Z[size_t(i) * n + i] = 1.0;
@@ -134,7 +148,192 @@ bool sym_eig(int n, const double *A, double *w, double *Z) {
     return true;
 }
 
+namespace {
+
+// Eigenvalues of the symmetric tridiagonal (d, e) by implicit QR with the Wilkinson shift,
+// without vectors; w receives them in descending order.
+bool tridiagonal_eigenvalues(int n, std::vector<double> d, std::vector<double> e, double *w) {
+    const double eps = std::numeric_limits<double>::epsilon();
+    int h = n - 1, iter = 0;
+    while (h > 0) {
+        if (std::fabs(e[h - 1]) <= eps * (std::fabs(d[h - 1]) + std::fabs(d[h]))) {
+            e[h - 1] = 0.0;
+            --h;
+            iter = 0;
+            continue;
+        }
+        if (++iter > 60) return false;
+        int l = h - 1;
+        while (l > 0 && std::fabs(e[l - 1]) > eps * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
+        const double delta = 0.5 * (d[h - 1] - d[h]);
+        const double eh = e[h - 1];
+        const double sg = delta >= 0 ? 1.0 : -1.0;
+        const double mu = d[h] - eh * eh / (delta + sg * std::hypot(delta, eh));
+        double x = d[l] - mu, z = e[l];
+        for (int k = l; k < h; ++k) {
+            const double r = std::hypot(x, z);
+            const double c = r > 0 ? x / r : 1.0;
+            const double s = r > 0 ? -z / r : 0.0;
+            if (k > l) e[k - 1] = r;
+            const double ak = d[k], bk = e[k], ck = d[k + 1];
+            d[k] = ak * c * c - 2.0 * bk * c * s + ck * s * s;
+            d[k + 1] = ak * s * s + 2.0 * bk * c * s + ck * c * c;
+            e[k] = (ak - ck) * c * s + bk * (c * c - s * s);
+            if (k + 1 < h) {
+                z = -s * e[k + 1];
+                e[k + 1] = c * e[k + 1];
+                x = e[k];
+            }
+        }
+    }
+    std::sort(d.begin(), d.end(), [](double a, double b) { return a > b; });
+    std::copy(d.begin(), d.end(), w);
+    return true;
+}
+
+// LU factorisation with partial pivoting of the tridiagonal T - lambda I (diagonal dd,
+// sub-diagonal dl, super-diagonals du, du2 after row interchanges; piv[i] marks an
+// interchange of rows i and i + 1).  Zero pivots are replaced by `tiny`.
+struct TriLU {
+    std::vector<double> dd, dl, du, du2;
+    std::vector<char> piv;
+
+    void factor(int n, const std::vector<double> &d, const std::vector<double> &e, double lambda, double tiny) {
+        dd.resize(n); dl.assign(n, 0.0); du.assign(n, 0.0); du2.assign(n, 0.0); piv.assign(n, 0);
+        for (int i = 0; i < n; ++i) dd[i] = d[i] - lambda;
+        for (int i = 0; i + 1 < n; ++i) { dl[i] = e[i]; du[i] = e[i]; }
+        for (int i = 0; i + 1 < n; ++i) {
+            if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
+                if (dd[i] == 0.0) dd[i] = tiny;
+                const double f = dl[i] / dd[i];
+                dl[i] = f;
+                dd[i + 1] -= f * du[i];
+            } else {
+                const double f = dd[i] / dl[i];
+                dd[i] = dl[i];
+                dl[i] = f;
+                const double t = du[i];
+                du[i] = dd[i + 1];
+                dd[i + 1] = t - f * dd[i + 1];
+                if (i + 2 < n) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
+                piv[i] = 1;
+            }
+        }
+        if (dd[n - 1] == 0.0) dd[n - 1] = tiny;
+    }
+
+    // x <- (T - lambda I)^{-1} x
+    void solve(int n, double *x) const {
+        for (int i = 0; i + 1 < n; ++i) {
+            if (piv[i]) {
+                const double t = x[i];
+                x[i] = x[i + 1];
+                x[i + 1] = t - dl[i] * x[i];
+            } else {
+                x[i + 1] -= dl[i] * x[i];
+            }
+        }
+        x[n - 1] /= dd[n - 1];
+        if (n > 1) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dd[n - 2];
+        for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
+    }
+};
+
+}  // namespace
+
+// All n eigenvalues (descending, w) and the eigenvectors of the nv largest (Z, n x nv
+// column-major): tridiagonalisation, eigenvalues by QR without vectors, eigenvectors of
+// the tridiagonal by inverse iteration (three steps from a seeded random vector;
+// eigenvalues closer than 1e-3 ||T|| form a cluster whose vectors are orthogonalised
+// against each other at every step, and equal ones are separated by a tiny shift), then
+// the Householder reflectors applied to them.
+bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv) {
+    if (n <= 0) return true;
+    if (nv >= n || n <= 2) {
+        std::vector<double> Zf(size_t(n) * n);
+        if (!sym_eig(n, A, w, Zf.data())) return false;
+        std::copy(Zf.begin(), Zf.begin() + size_t(n) * std::min(nv, n), Z);
+        return true;
+    }
+    std::vector<double> d, e, V, beta;
+    tridiagonalise(n, A, d, e, V, beta);
+    if (!tridiagonal_eigenvalues(n, d, e, w)) return false;
+    const double eps = std::numeric_limits<double>::epsilon();
+    double tnorm = 0.0;
+    for (int i = 0; i < n; ++i)
+        tnorm = std::max(tnorm, std::fabs(d[i]) + (i + 1 < n ? std::fabs(e[i]) : 0.0) + (i > 0 ? std::fabs(e[i - 1]) : 0.0));
+    if (tnorm == 0.0) tnorm = 1.0;
+    const double ortol = 1e-3 * tnorm, pertol = 10.0 * eps * tnorm, tiny = eps * tnorm;
+    std::vector<double> X(size_t(n) * nv);
+    TriLU lu;
+    uint64_t state = 0x2545F4914F6CDD1Dull;
+    auto uniform = [&state]() {
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return 2.0 * (double(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+    };
+    int cs = 0;                  // first index of the current cluster
+    double lam_prev = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        double lam = w[j];
+        if (j > 0 && w[j - 1] - w[j] > ortol) cs = j;
+        if (j > cs && lam_prev - lam < pertol) lam = lam_prev - pertol;
+        lam_prev = lam;
+        lu.factor(n, d, e, lam, tiny);
+        double *x = &X[size_t(j) * n];
+        for (int i = 0; i < n; ++i) x[i] = uniform();
+        for (int it = 0; it < 3; ++it) {
+            lu.solve(n, x);
+            for (int c = cs; c < j; ++c) {
+                const double *y = &X[size_t(c) * n];
+                double s = 0.0;
+                for (int i = 0; i < n; ++i) s += x[i] * y[i];
+                for (int i = 0; i < n; ++i) x[i] -= s * y[i];
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < n; ++i) nrm += x[i] * x[i];
+            nrm = std::sqrt(nrm);
+            if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+            for (int i = 0; i < n; ++i) x[i] /= nrm;
+        }
+    }
+    // back-transformation: X <- H_0 H_1 ... H_{n-3} X
+    for (int k = n - 3; k >= 0; --k) {
+        if (beta[k] == 0.0) continue;
+        const int m = n - k - 1;
+        const double *v = &V[size_t(k) * n];
+        for (int j = 0; j < nv; ++j) {
+            double *col = &X[size_t(j) * n + k + 1];
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s += v[i] * col[i];
+            s *= beta[k];
+            for (int i = 0; i < m; ++i) col[i] -= s * v[i];
+        }
+    }
+    std::copy(X.begin(), X.end(), Z);
+    return true;
+}
+
 }  // namespace kl
+
+extern "C" kl_status kl_symeig_partial(int32_t n, const double *A, double *w, double *Z, int32_t nv) {
+    if (n < 0 || nv < 0 || nv > n || (n > 0 && (!A || !w || (nv > 0 && !Z)))) {
+        kl::set_error("kl_symeig_partial: invalid arguments");
+        return KL_EINVAL;
+    }
+    for (int64_t i = 0; i < int64_t(n) * n; ++i)
+        if (!std::isfinite(A[i])) { kl::set_error("kl_symeig_partial: non-finite input"); return KL_ENUMERIC; }
+    if (!kl::sym_eig_partial(n, A, w, Z, nv)) {
+        kl::set_error("kl_symeig_partial: iteration did not converge");
+        return KL_ENOCONV;
+    }
+    return KL_OK;
+}
 
 extern "C" kl_status kl_symeig(int32_t n, const double *A, double *w, double *Z) {
     if (n < 0 || (n > 0 && (!A || !w || !Z))) {

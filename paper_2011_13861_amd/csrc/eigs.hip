@@ -17,8 +17,6 @@
 //     with the FP64 apply and the same iteration finishes in FP64, so that the final
 //     criterion is met under the FP64 operator.
 // Converged when ||A~' x_i - theta_i x_i|| <= max(tol theta_i, abs_floor theta_1), i <= k.
-#include <rocblas/rocblas.h>
-
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -75,7 +73,6 @@ __global__ __launch_bounds__(kT) void finite_kernel(const double *__restrict__ X
 
 struct SolverCache {
     hipStream_t s = nullptr;
-    rocblas_handle blas = nullptr;
     int64_t N = 0;
     int mcap = 0, ccap = 0;
     double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
@@ -96,7 +93,6 @@ void release_buffers(SolverCache &c) {
 
 struct Solver {
     kl_problem *P;
-    rocblas_handle blas = nullptr;
     hipStream_t s = nullptr;
     int64_t N = 0;
     int b = 32, k = 1, keep = 1, mmax = 1;
@@ -115,13 +111,6 @@ struct Solver {
         set_error(os.str());
         return e == hipErrorOutOfMemory ? KL_ENOMEM : KL_EHIP;
     }
-    kl_status bcheck(rocblas_status st, const char *what) {
-        if (st == rocblas_status_success) return KL_OK;
-        std::ostringstream os;
-        os << "kl_eigs: rocBLAS " << what << " failed (" << int(st) << ")";
-        set_error(os.str());
-        return KL_EHIP;
-    }
     // C = A^T B   (A: N x ma, B: N x nb, ld N) -> C (ma x nb, ld ma), device; split-N
     // Gram kernel (tall-skinny shapes)
     kl_status gemm_tn(const double *A, int ma, const double *B, int nb, double *Cout) {
@@ -131,8 +120,8 @@ struct Solver {
     // Out = alpha A S + beta Out   (A: N x ma, S: ma x nb with ld lds)
     kl_status gemm_nn(const double *A, int ma, const double *S, int lds, int nb, double alpha,
                       double beta, double *Out) {
-        return bcheck(rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, int(N), nb,
-                                    ma, &alpha, A, int(N), S, lds, &beta, Out, int(N)), "dgemm NN");
+        launch_gemm_nn(A, N, ma, S, lds, nb, N, alpha, beta, Out, N, s);
+        return check(hipGetLastError(), "gemm kernel");
     }
 
     kl_status apply(int precision, const double *x, double *y, int ncols) {
@@ -258,13 +247,6 @@ kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
     };
     kl_status st;
     if (!c.s && (st = hip(hipStreamCreate(&c.s), "stream")) != KL_OK) return st;
-    if (!c.blas) {
-        if (rocblas_create_handle(&c.blas) != rocblas_status_success ||
-            rocblas_set_stream(c.blas, c.s) != rocblas_status_success) {
-            set_error("kl_eigs: rocBLAS handle");
-            return KL_EHIP;
-        }
-    }
     if (c.N == N && c.mcap >= mmax && c.ccap >= cmax) return KL_OK;
     release_buffers(c);
     const int mc = std::max(mmax, c.N == N ? c.mcap : 0), cc = std::max(cmax, c.N == N ? c.ccap : 0);
@@ -275,8 +257,9 @@ kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
         (st = hip(hipMalloc(&c.AVt, nb), "alloc AVt")) != KL_OK ||
         (st = hip(hipMalloc(&c.W, size_t(N) * cc * sizeof(double)), "alloc W")) != KL_OK ||
         (st = hip(hipMalloc(&c.C, size_t(cc) * cc * sizeof(double)), "alloc C")) != KL_OK ||
-        // split partials of the Gram kernel: 64 row ranges of a cmax x cmax product
-        (st = hip(hipMalloc(&c.part, size_t(64) * cc * cc * sizeof(double)), "alloc gram partials")) != KL_OK ||
+        // split partials of the Gram kernel: its row ranges times a cmax x cmax product
+        (st = hip(hipMalloc(&c.part, size_t(gram_splits(N, cc, cc, 0)) * cc * cc * sizeof(double)),
+                  "alloc gram partials")) != KL_OK ||
         (st = hip(hipMalloc(&c.dtheta, size_t(mc) * 8), "alloc theta")) != KL_OK ||
         (st = hip(hipMalloc(&c.dnorm, size_t(mc) * 8), "alloc norms")) != KL_OK ||
         (st = hip(hipMalloc(&c.dflag, sizeof(int)), "alloc flag")) != KL_OK) {
@@ -326,7 +309,6 @@ void free_solver_cache(SolverCache *c) {
     if (!c) return;
     if (c->s) hipStreamSynchronize(c->s);
     release_buffers(*c);
-    if (c->blas) rocblas_destroy_handle(c->blas);
     if (c->s) hipStreamDestroy(c->s);
     delete c;
 }
@@ -378,7 +360,6 @@ kl_status EigRun::begin(const double *x0, int nvec0) {
     {
         SolverCache &c = *P->solver;
         S.s = c.s;
-        S.blas = c.blas;
         S.V = c.V; S.AV = c.AV; S.Vt = c.Vt; S.AVt = c.AVt; S.W = c.W;
         S.C = c.C; S.part = c.part; S.dtheta = c.dtheta; S.dnorm = c.dnorm; S.dflag = c.dflag;
     }
@@ -473,15 +454,16 @@ kl_status EigRun::rr_step() {
     std::vector<double> Hm(size_t(m) * m);
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < m; ++j) Hm[size_t(i) * m + j] = S.H[size_t(i) * S.mmax + j];
+    // all Ritz values, and the Ritz vectors of the kk kept ones (m x kk, column-major)
+    const int kk = std::min(S.keep, m);
     theta.assign(m, 0.0);
-    Sm.assign(size_t(m) * m, 0.0);
+    Sm.assign(size_t(m) * kk, 0.0);
     const auto te0 = clock::now();
-    const bool eig_ok = sym_eig(m, Hm.data(), theta.data(), Sm.data());
+    const bool eig_ok = sym_eig_partial(m, Hm.data(), theta.data(), Sm.data(), kk);
     t_host_eig += std::chrono::duration<double>(clock::now() - te0).count();
     if (!eig_ok) { set_error("kl_eigs: projected eigenproblem did not converge"); return KL_ENUMERIC; }
     for (double t : theta)
         if (!std::isfinite(t)) { set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
-    const int kk = std::min(S.keep, m);
     // X = V S[:, :kk] -> Vt,  AX = AV S[:, :kk] -> AVt
     if ((st = S.check(hipMemcpyAsync(S.C, Sm.data(), size_t(m) * kk * 8, hipMemcpyHostToDevice, S.s), "copy S")) != KL_OK)
         return st;

@@ -1,12 +1,15 @@
 // FP64 block kernels of the eigensolver: C = A^T B for tall-skinny A (N x m) and
 // B (N x c), N >> m, c (the Gram matrices of the Rayleigh-Ritz projection and of the
-// Gram-Schmidt reorthogonalisation).
+// Gram-Schmidt reorthogonalisation), and Out = alpha A S + beta Out for a tall-skinny A
+// and a small S (Ritz vectors, projections).
 //
-// The N rows are split into G ranges.  A workgroup owns one (64 x 64 tile of C, row
+// The N rows are split into G <= 256 ranges of at least two slabs, so that short
+// products still spread over the chip.  A workgroup owns one (64 x 64 tile of C, row
 // range) pair: it stages 32-row slabs of the 64 columns of A and of B in LDS (loads
-// coalesced along the rows) and accumulates 16 entries per thread with FP64 FMAs.  The
-// partials are stored output-major, part[e][g], so that the reduction is one wave per
-// output entry: 64 coalesced loads and a cross-lane sum, in a fixed order.
+// coalesced along the rows, the next slab prefetched into registers while the current
+// one is used) and accumulates 16 entries per thread with FP64 FMAs.  The partials are
+// stored output-major, part[e][g], so that the reduction is one wave per output entry:
+// coalesced loads of G values and a cross-lane sum, in a fixed order.
 #include "kl_internal.h"
 
 namespace kl {
@@ -15,7 +18,7 @@ namespace {
 constexpr int kT = 64;         // C tile edge
 constexpr int kSlab = 32;      // rows per LDS slab
 constexpr int kThreads = 256;  // 16 x 16 threads, 4 x 4 entries each
-constexpr int kG = 64;         // maximum number of row ranges
+constexpr int kG = 256;        // maximum number of row ranges
 
 __global__ __launch_bounds__(kThreads) void gram_partial_kernel(
     const double *__restrict__ A, int64_t lda, int m, const double *__restrict__ B, int64_t ldb,
@@ -32,16 +35,30 @@ __global__ __launch_bounds__(kThreads) void gram_partial_kernel(
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-    for (int64_t ns = n0; ns < n1; ns += kSlab) {
+    constexpr int kPer = (kSlab * kT) / kThreads;       // 8 elements of A and of B per thread
+    double pa[kPer], pb[kPer];
+    auto load = [&](int64_t ns) {
 #pragma unroll
-        for (int q = 0; q < (kSlab * kT) / kThreads; ++q) {
+        for (int q = 0; q < kPer; ++q) {
             const int e = threadIdx.x + q * kThreads;
             const int r = e % kSlab, col = e / kSlab;
             const int64_t n = ns + r;
-            sA[r][col] = (n < n1 && i0 + col < m) ? A[(i0 + col) * lda + n] : 0.0;
-            sB[r][col] = (n < n1 && j0 + col < c) ? B[(j0 + col) * ldb + n] : 0.0;
+            pa[q] = (n < n1 && i0 + col < m) ? A[(i0 + col) * lda + n] : 0.0;
+            pb[q] = (n < n1 && j0 + col < c) ? B[(j0 + col) * ldb + n] : 0.0;
+        }
+    };
+    if (n0 < n1) load(n0);
+    for (int64_t ns = n0; ns < n1; ns += kSlab) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int r = e % kSlab, col = e / kSlab;
+            sA[r][col] = pa[q];
+            sB[r][col] = pb[q];
         }
         __syncthreads();
+        if (ns + kSlab < n1) load(ns + kSlab);
 #pragma unroll 4
         for (int r = 0; r < kSlab; ++r) {
             double a[4], b[4];
@@ -54,14 +71,13 @@ __global__ __launch_bounds__(kThreads) void gram_partial_kernel(
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = i0 + ti + 16 * u, j = j0 + tj + 16 * v;
-            if (i < m && j < c) part[(int64_t(j) * m + i) * kG + g] = acc[u][v];
+            if (i < m && j < c) part[(int64_t(j) * m + i) * gridDim.z + g] = acc[u][v];
         }
 }
 
@@ -72,10 +88,70 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__r
     const int lane = threadIdx.x & 63;
     const int64_t e = int64_t(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6);
     if (e >= mc) return;
-    double v = lane < G ? part[e * kG + lane] : 0.0;
+    double v = 0.0;
+    for (int g = lane; g < G; g += 64) v += part[e * G + g];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) C[e] = v;
+}
+
+// Out (N x c) = alpha A (N x m) S (m x c) + beta Out, column-major.  Computed as
+// Out^T = S^T A^T on v_mfma_f64_16x16x4_f64 so that a lane's accumulators are 16
+// consecutive rows of one output column (coalesced stores) and a lane's B operand is
+// one row of A (coalesced loads): A-operand S^T[j][k] in lane j + 16 k, B-operand
+// A^T[k][i] in lane i + 16 k, accumulator r of lane L = Out^T[(L >> 4) + 4 r][L & 15].
+// A workgroup covers 64 rows x 64 columns: wave w owns rows 16 w.. of the tile and four
+// 16-column MFMA tiles.  Operands go straight from memory to registers, 8 MFMA steps
+// (32 values of k) per batch of loads.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kNNSteps = 8;
+
+__global__ __launch_bounds__(kThreads) void gemm_nn_kernel(const double *__restrict__ A, int64_t lda, int m,
+                                                           const double *__restrict__ S, int64_t lds, int c,
+                                                           int64_t N, double alpha, double beta,
+                                                           double *__restrict__ Out, int64_t ldo) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t row = int64_t(blockIdx.x) * 64 + 16 * w + li;   // this lane's A row
+    const int j0 = blockIdx.y * 64;
+    const bool rok = row < N;
+    doublex4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < m; k0 += 4 * kNNSteps) {
+        double a[kNNSteps], b[4][kNNSteps];
+#pragma unroll
+        for (int s = 0; s < kNNSteps; ++s) {
+            const int k = k0 + 4 * s + lk;
+            const bool kok = k < m;
+            a[s] = (kok && rok) ? A[row + lda * k] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = j0 + 16 * t + li;
+                b[t][s] = (kok && j < c) ? S[k + lds * j] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kNNSteps; ++s)
+            if (k0 + 4 * s < m)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t][s], a[s], acc[t], 0, 0, 0);
+    }
+    // lane L holds Out[row0 + (L & 15)][j0 + 16 t + (L >> 4) + 4 r]
+    const int64_t orow = int64_t(blockIdx.x) * 64 + 16 * w + li;
+    if (orow >= N) return;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = j0 + 16 * t + lk + 4 * r;
+            if (j < c) {
+                double *o = Out + orow + ldo * j;
+                const double v = alpha * acc[t][r];
+                *o = beta == 0.0 ? v : v + beta * *o;
+            }
+        }
 }
 
 }  // namespace
@@ -89,7 +165,7 @@ int gram_splits(int64_t N, int m, int c, int n_cu) {
 }
 
 // C (m x c, column-major, ld m) = A^T B with A: N x m (ld lda), B: N x c (ld ldb).
-// `part` needs 64 * m * c doubles.
+// `part` needs gram_splits(N, ...) * m * c doubles (at most 256 m c).
 void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int c,
                  int64_t N, double *part, double *C, int n_cu, hipStream_t s) {
     const int G0 = gram_splits(N, m, c, n_cu);
@@ -102,6 +178,13 @@ void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t l
     const int64_t mc = int64_t(m) * c;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(unsigned((mc + 3) / 4)), dim3(kThreads), 0, s, part,
                        G, mc, C);
+}
+
+void launch_gemm_nn(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
+                    double alpha, double beta, double *Out, int64_t ldo, hipStream_t s) {
+    if (N < 1 || c < 1) return;
+    const dim3 grid(unsigned((N + 63) / 64), unsigned((c + 63) / 64));
+    hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(kThreads), 0, s, A, lda, m, S, lds, c, N, alpha, beta, Out, ldo);
 }
 
 }  // namespace kl

@@ -55,22 +55,27 @@ __device__ __forceinline__ void mode_tile(const ModeArgs &g, int64_t tile) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nin = g.nin, nout = g.nout;
-    const int64_t nrows = g.A * g.Clo * g.nvec;
-    const int64_t rtiles = (nrows + 15) / 16;
-    const int otiles = (nout + 15) / 16;
-    if (tile >= rtiles * otiles) return;           // whole wave leaves together
-    const int64_t rt = tile / otiles;
-    const int ot = int(tile % otiles);
+    // row counts fit in 32 bits (checked on the host), so the row -> (a, c, j) split uses
+    // 32-bit division (64-bit division is a long software sequence on the GPU)
+    const uint32_t A = uint32_t(g.A), Clo = uint32_t(g.Clo);
+    const uint32_t nrows = A * Clo * uint32_t(g.nvec);
+    const uint32_t rtiles = (nrows + 15) / 16;
+    const uint32_t otiles = uint32_t(nout + 15) / 16;
+    if (tile >= int64_t(rtiles) * otiles) return;  // whole wave leaves together
+    const uint32_t rt = uint32_t(tile / otiles);
+    const int ot = int(tile - int64_t(rt) * otiles);
     // this lane's row (operand index li) and its address bases
-    const int64_t r = rt * 16 + li;
+    const uint32_t r = rt * 16 + li;
     const bool rok = r < nrows;
-    int64_t bin = 0, pin = 0;
+    uint32_t ra = 0, rc = 0, rj = 0;
     if (rok) {
-        const int64_t a = r % g.A, t = r / g.A;
-        const int64_t c = t % g.Clo, j = t / g.Clo;
-        pin = a + g.A * int64_t(nin) * c;
-        bin = pin + g.in_ldj * j;
+        const uint32_t t = FIRST ? r : r / A;
+        ra = FIRST ? 0 : r - t * A;
+        rj = t / Clo;
+        rc = t - rj * Clo;
     }
+    const int64_t pin = int64_t(ra) + g.A * int64_t(nin) * rc;
+    const int64_t bin = pin + g.in_ldj * int64_t(rj);
     const int o_l = ot * 16 + li;                  // this lane's o (operand index li)
     const bool ook = o_l < nout;
     const TIN *in = static_cast<const TIN *>(g.in);
@@ -98,20 +103,34 @@ __device__ __forceinline__ void mode_tile(const ModeArgs &g, int64_t tile) {
     }
     // ---- store: C[(lane >> 4) + 4 q][lane & 15] --------------------------------------
     TOUT *out = static_cast<TOUT *>(g.out);
+    if (FIRST) {
+        // rows rt 16 + lk + 4 q (A == 1): split the first one, then step by 4
+        uint32_t rr = rt * 16 + lk;
+        uint32_t j = rr / Clo, c = rr - j * Clo;
+        const int o = ot * 16 + li;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int m = lk + 4 * q;                  // C row index
-        int64_t rr;
-        int o;
-        if (FIRST) { rr = rt * 16 + m; o = ot * 16 + li; }
-        else { rr = rt * 16 + li; o = ot * 16 + m; }
-        if (rr < nrows && o < nout) {
-            const int64_t a = rr % g.A, t = rr / g.A;
-            const int64_t c = t % g.Clo, j = t / g.Clo;
-            const int64_t p = a + g.A * (o + int64_t(nout) * c);
-            double v = acc[q];
-            if (g.out_w) v *= g.out_w[p];
-            store_out<TOUT>(out, g.out_lo, p + g.out_ldj * j, v);
+        for (int q = 0; q < 4; ++q) {
+            if (rr < nrows && o < nout) {
+                const int64_t p = int64_t(o) + int64_t(nout) * c;
+                double v = acc[q];
+                if (g.out_w) v *= g.out_w[p];
+                store_out<TOUT>(out, g.out_lo, p + g.out_ldj * int64_t(j), v);
+            }
+            rr += 4;
+            c += 4;
+            while (c >= Clo) { c -= Clo; ++j; }
+        }
+    } else if (rok) {
+        // row r (this lane's), outputs o = ot 16 + lk + 4 q
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = ot * 16 + lk + 4 * q;
+            if (o < nout) {
+                const int64_t p = int64_t(ra) + g.A * (int64_t(o) + int64_t(nout) * rc);
+                double v = acc[q];
+                if (g.out_w) v *= g.out_w[p];
+                store_out<TOUT>(out, g.out_lo, p + g.out_ldj * int64_t(rj), v);
+            }
         }
     }
 }

@@ -32,6 +32,8 @@ struct HostSetup {
 // Dense symmetric eigensolver (row-major A, descending w, column-major Z); false if the
 // QR iteration fails to converge.
 bool sym_eig(int n, const double *A, double *w, double *Z);
+// All eigenvalues (descending) and the eigenvectors of the nv largest (Z: n x nv).
+bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv);
 
 // Fills `hs` from the description; returns KL_OK or an error (message set).
 kl_status build_host_setup(const kl_desc &desc, HostSetup &hs);
@@ -49,7 +51,7 @@ struct Workspace {
     int max_split = 1;
 };
 
-// Device buffers, stream and rocBLAS handle of the block eigensolver, kept with the
+// Device buffers and stream of the block eigensolver, kept with the
 // problem between kl_eigs calls (grown on demand, freed by kl_destroy).
 struct SolverCache;
 void free_solver_cache(SolverCache *c);
@@ -150,10 +152,15 @@ void launch_pack_stage5(int precision, const double *y, int64_t ldy, int64_t Nt,
 void launch_unpack_stage5(int precision, const void *Z5, int nsplit, int64_t Ntpad, int64_t Nt,
                           int nvec, double scale, double *z, int64_t ldz, hipStream_t s);
 // C (m x c, column-major, ld m) = A^T B for tall-skinny FP64 blocks; `part` holds
-// 64 * m * c doubles of row-range partials.
+// gram_splits(N, m, c) * m * c doubles of row-range partials (at most 256 m c).
 int gram_splits(int64_t N, int m, int c, int n_cu);
 void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int c,
                  int64_t N, double *part, double *C, int n_cu, hipStream_t s);
+
+// Out (N x c) = alpha A (N x m) S (m x c) + beta Out, FP64 column-major (beta = 0: Out is
+// not read).
+void launch_gemm_nn(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
+                    double alpha, double beta, double *Out, int64_t ldo, hipStream_t s);
 
 // Stage-5 launch geometry: rows per workgroup, and the number of l-splits (forced > 0
 // overrides the automatic choice); *lchunk receives the l-range length of one split.

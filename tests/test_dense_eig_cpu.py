@@ -1,0 +1,64 @@
+"""Host dense symmetric eigensolvers of the library (kl_symeig, kl_symeig_partial), used by
+the Rayleigh-Ritz step of the eigensolver, against numpy.linalg.eigh: eigenvalues,
+residuals ||A z - w z||, orthonormality, on random matrices, matrices with exactly
+repeated eigenvalues (the spectra of symmetric domains), graded spectra and tiny sizes."""
+
+import numpy as np
+import pytest
+
+from paper_2011_13861_amd import _binding as B
+
+
+def _cases():
+    rng = np.random.default_rng(0)
+    out = []
+    for n in (1, 2, 3, 7, 40, 161):
+        M = rng.standard_normal((n, n))
+        out.append(("random%d" % n, (M + M.T) / 2))
+    # exact multiplicities: Q diag(...) Q^T with repeated values
+    n = 60
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    w = np.concatenate([[3.0, 2.0, 2.0, 2.0, 1.5, 1.5], np.geomspace(1.0, 1e-9, n - 6)])
+    out.append(("degenerate", (Q * w) @ Q.T))
+    # diagonal (already tridiagonal, zero off-diagonals)
+    out.append(("diagonal", np.diag(np.linspace(2.0, -1.0, 25))))
+    # graded spectrum as in the Rayleigh-Ritz matrices (eigenvalues over 10 decades)
+    Q, _ = np.linalg.qr(rng.standard_normal((120, 120)))
+    out.append(("graded", (Q * np.geomspace(1.0, 1e-10, 120)) @ Q.T))
+    return out
+
+
+CASES = _cases()
+
+
+def _check(A, w, Z, nv):
+    n = A.shape[0]
+    ref = np.sort(np.linalg.eigvalsh(A))[::-1]
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    assert np.all(np.abs(w - ref) <= 1e-12 * scale * max(1.0, np.sqrt(n)))
+    assert np.all(np.diff(w) <= 0)
+    if nv:
+        R = A @ Z - Z * w[:nv]
+        assert np.max(np.linalg.norm(R, axis=0)) <= 1e-11 * scale
+        assert np.max(np.abs(Z.T @ Z - np.eye(nv))) <= 1e-11
+
+
+@pytest.mark.parametrize("name,A", CASES, ids=[c[0] for c in CASES])
+def test_symeig_full(name, A):
+    w, Z = B.symeig(A)
+    _check(A, w, Z, A.shape[0])
+
+
+@pytest.mark.parametrize("name,A", CASES, ids=[c[0] for c in CASES])
+def test_symeig_partial(name, A):
+    n = A.shape[0]
+    for nv in sorted({0, 1, max(1, n // 3), n}):
+        w, Z = B.symeig_partial(A, nv)
+        _check(A, w, Z, nv)
+
+
+def test_symeig_errors():
+    with pytest.raises(B.KLError):
+        B.symeig(np.array([[np.nan]]))
+    with pytest.raises(B.KLError):
+        B.symeig_partial(np.eye(3), 4)
