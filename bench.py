@@ -21,6 +21,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+# HBM bytes per stage-5 launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a
+# plain 256 MiB copy), keyed by (workload, precision, rb, nsplit); see
+# profiles/stage5_f32_c2_hbm_traffic.md.  Only reported for the setting it was measured on.
+MEASURED_TRAFFIC = {("c2", "f32", 2, 6): 8445 * 1024}
 WORKLOADS = {
     "c2": ("2D quarter annulus (r in [1,2], NURBS map) 64x64 cubic, Ntilde = N = 4489, "
            "squared exponential L = 0.5, k = 40"),
@@ -201,6 +205,8 @@ def main():
     ap.add_argument("--mlp-eval", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batch section")
     ap.add_argument("--no-tune", action="store_true", help="keep the automatic stage-5 split")
+    ap.add_argument("--tiles", default=None, metavar="RB,NSPLIT",
+                    help="force the stage-5 tiles instead of tuning (e.g. 2,6), for profiler runs")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="also run one plain device-to-device copy of MB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -226,10 +232,12 @@ def main():
     desc, k, b = workloads.config(args.workload)
     prec = args.precision or "f32"
     G = kl.Problem(desc)
-    tuned = None
-    if not args.no_tune:
+    if args.tiles:
+        rb_, ns_ = (int(v) for v in args.tiles.split(","))
+        G.stage5_config(prec, rb=rb_, nsplit=ns_)
+    elif not args.no_tune:
         from paper_2011_13861_amd import autotune
-        tuned = autotune.tune_problem(G, desc["cov"]["kind"], precisions=(prec,), reps=10)[prec]
+        autotune.tune_problem(G, desc["cov"]["kind"], precisions=(prec,), reps=10)
     x = kl.to_device_block(workloads.random_block(G.N, b, seed=1))
     y = kl.new_block(G.N, b)
     stream = torch.cuda.current_stream()
@@ -256,11 +264,13 @@ def main():
     k_avg_s = kms / max(cnt, 1) * 1e-3
     flops = 2.0 * b * pairs                    # MFMA contraction flops per stage-5 launch
     achieved = flops / k_avg_s / 1e12
+    tiles = G.stage5_config(prec)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
+                "frac": achieved / PEAK_TFLOPS[prec],
+                "traffic": MEASURED_TRAFFIC.get((args.workload, prec) + tuple(tiles)),
                 "kernel": "stage5_%s_kernel" % prec, "kernel_avg_us": k_avg_s * 1e6,
                 "kernel_pairs_per_s": pairs / k_avg_s, "launches": cnt,
-                "stage5_tiles": None if tuned is None else {"rb": tuned[0], "nsplit": tuned[1]}}
+                "stage5_tiles": {"rb": tiles[0], "nsplit": tiles[1]}}
 
     # time to k eigenpairs at relative residual 1e-6 (criterion under the FP64 operator)
     def solve(p):

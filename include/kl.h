@@ -179,8 +179,9 @@ kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0, int
 
 /* Stage-5 kernel timing for measurement tools: while enabled, every stage-5 launch of
  * this handle (from kl_apply, kl_stage5 and kl_eigs) is bracketed by two HIP events
- * recorded on its launch stream around the covariance kernel alone (the split sums that
- * follow it are not included), up to 8192 launches until the next read.
+ * recorded on its stream right before and after the covariance kernel (the split sums
+ * that follow it are outside), created without the system-scope fence so that the
+ * interval holds no cache writeback; up to 8192 launches until the next read.
  * kl_profile_enable(P, 1) creates the event pool (once) and resets the counters;
  * kl_profile_enable(P, 0) stops recording.  kl_profile_read waits for the recorded
  * events and returns, per kl_precision (host arrays of 4), the number of timed launches

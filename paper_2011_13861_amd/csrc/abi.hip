@@ -113,11 +113,12 @@ int64_t max_intermediate(const HostSetup &hs) {
     return best;
 }
 
-// Stage-5 launch, bracketed by HIP events on the launch stream while profiling is on.
+// Stage-5 launch; while profiling is on, a pair of HIP events (without the system-scope
+// fence, which would add a cache writeback to the interval) brackets the covariance kernel.
 int timed_stage5(kl_problem *P, int precision, const void *Y5, hipStream_t s) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
-    if (rec) (void)hipEventRecord(P->prof_ev[P->prof_used], s);
     const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, P->ws.Zf, s,
+                                     rec ? P->prof_ev[P->prof_used] : nullptr,
                                      rec ? P->prof_ev[P->prof_used + 1] : nullptr);
     if (rec) {
         P->prof_prec.push_back(precision);
@@ -429,7 +430,7 @@ kl_status kl_profile_enable(kl_problem *P, int32_t enable) {
         P->prof_ev.reserve(pool);
         while (P->prof_ev.size() < pool) {
             hipEvent_t e;
-            kl_status st = hip_check(hipEventCreate(&e), "hipEventCreate");
+            kl_status st = hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
             if (st != KL_OK) return st;
             P->prof_ev.push_back(e);
         }

@@ -655,17 +655,18 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 }
 
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
-                  hipStream_t s, hipEvent_t after_main) {
+                  hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
     const int rb = P->s5_rb[precision] == 4 ? 4 : 2;
     int64_t lchunk;
     const int nsplit = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rb), P->n_cu,
                                      P->ws.max_split, P->s5_split[precision], &lchunk);
+    if (ev_start) (void)hipEventRecord(ev_start, s);
     switch (P->hs.d) {
     case 1: launch_dim<1>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
     case 2: launch_dim<2>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
     default: launch_dim<3>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
     }
-    if (after_main) (void)hipEventRecord(after_main, s);
+    if (ev_stop) (void)hipEventRecord(ev_stop, s);
     if (nsplit > 1) {
         const int64_t n4 = P->Ntpad * kBW / 4;
         const dim3 g(unsigned((n4 + kThreads - 1) / kThreads));

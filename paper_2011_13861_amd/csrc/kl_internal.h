@@ -168,10 +168,10 @@ int64_t stage5_rows_per_wg(int precision, int rb);
 int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int forced,
                   int64_t *lchunk);
 // Stage 5: Zf[j][k] = sum_l Gamma(x_k, x_l) Y5[j][l]; Z5 holds split partials (scratch).
-// Returns the number of splits used.  If after_main is not NULL it is recorded right after
-// the covariance kernel (before the split sums).
+// Returns the number of splits used.  Non-NULL ev_start / ev_stop are recorded right
+// before and right after the covariance kernel (the split sums that follow are outside).
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
-                  hipStream_t s, hipEvent_t after_main = nullptr);
+                  hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // kl_setup with or without the single-problem apply workspace (T0/T1, stage-5 buffers);
 // problems of a batch use the batch's arenas instead.
