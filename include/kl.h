@@ -127,7 +127,7 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec,
                     const double *y, int64_t ldy, double *z, int64_t ldz, void *stream);
 
 /* Stage-5 launch configuration for one kl_precision (used by the autotuner):
- * rb = 32-row blocks per wave of the FP32/BF16 kernels (2 or 4; 0 keeps the current
+ * rb = 32-row blocks per wave of the FP32/BF16 kernels (1, 2 or 4; 0 keeps the current
  * value; the FP64 kernel always uses four 16-row blocks); nsplit = number of l-splits
  * (1..64 forces it, 0 = automatic load-balancing choice, -1 keeps the current setting).
  * rb_out / nsplit_out (may be NULL) receive the effective values.  Errors: KL_EINVAL. */

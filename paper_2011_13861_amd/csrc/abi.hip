@@ -115,9 +115,10 @@ int64_t max_intermediate(const HostSetup &hs) {
 
 // Stage-5 launch; while profiling is on, a pair of HIP events (without the system-scope
 // fence, which would add a cache writeback to the interval) brackets the covariance kernel.
-int timed_stage5(kl_problem *P, int precision, const void *Y5, hipStream_t s) {
+int timed_stage5(kl_problem *P, int precision, const void *Y5, const double *wrow, double scale,
+                 hipStream_t s) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
-    const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, P->ws.Zf, s,
+    const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, P->ws.Zf, wrow, scale, s,
                                      rec ? P->prof_ev[P->prof_used] : nullptr,
                                      rec ? P->prof_ev[P->prof_used + 1] : nullptr);
     if (rec) {
@@ -128,9 +129,9 @@ int timed_stage5(kl_problem *P, int precision, const void *Y5, hipStream_t s) {
 }
 
 // One chunk (<= kBW columns) of Algorithm 1: x (N x nb, ld ldx) -> y (N x nb, ld ldy).
-// 2d + 1 launches: d forward directions (the last one applies J and writes the stage-5
-// input), stage 5, d backward directions (the first one adds the split partials and
-// applies sigma^2 J).
+// 2d + 1 launches (+1 for the split sums): d forward directions (the last one applies J
+// and writes the stage-5 input), stage 5 (its output rows scaled by sigma^2 J), d
+// backward directions.
 kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx,
                       double *y, int64_t ldy, hipStream_t s) {
     const HostSetup &hs = P->hs;
@@ -170,9 +171,9 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
         cur = m.out;
         cur_ld = m.out_ldj;
     }
-    // ---- stage 5 ----------------------------------------------------------------------
-    const int nsplit = timed_stage5(P, precision, Y5, s);
-    // ---- stages 6-9: sigma^2 J and the split sum on the way in, C_k^T per direction ----
+    // ---- stage 5, its output scaled by sigma^2 J --------------------------------------
+    const int nsplit = timed_stage5(P, precision, Y5, P->dJ, P->sigma2, s);
+    // ---- stages 6-9: C_k^T per direction -----------------------------------------------
     (void)nsplit;
     cur = P->ws.Zf;
     cur_ld = P->Ntpad;
@@ -189,11 +190,7 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
         m.Clo = 1;
         for (int j = k + 1; j < d; ++j) m.Clo *= hs.nt[j];
         m.nvec = nb;
-        if (k == 0) {
-            m.in_w = P->dJ;
-            m.in_scale = P->sigma2;
-            m.in_f32 = lo;
-        }
+        if (k == 0) m.in_f32 = lo;
         if (k == d - 1) {
             m.out = y;
             m.out_ldj = ldy;
@@ -382,7 +379,7 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec, const double
         const int nb = std::min(kBW, nvec - c0);
         void *Y5 = stage5_input(P, precision);
         launch_pack_stage5(precision, y + int64_t(c0) * ldy, ldy, P->hs.Nt, nb, P->Ntpad, Y5, s);
-        const int nsplit = timed_stage5(P, precision, Y5, s);
+        const int nsplit = timed_stage5(P, precision, Y5, nullptr, 1.0, s);
         (void)nsplit;
         launch_unpack_stage5(precision, P->ws.Zf, 1, P->Ntpad, P->hs.Nt, nb, P->sigma2,
                              z + int64_t(c0) * ldz, ldz, s);
@@ -396,11 +393,11 @@ kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t
                            int32_t *rb_out, int32_t *nsplit_out) {
     if (!P || P->host_only) { set_error("kl_stage5_config: NULL or host-only handle"); return KL_EINVAL; }
     if (!valid_precision(precision)) { set_error("kl_stage5_config: bad precision"); return KL_EINVAL; }
-    if (rb != 0 && rb != 2 && rb != 4) { set_error("kl_stage5_config: rb must be 0, 2 or 4"); return KL_EINVAL; }
+    if (rb != 0 && rb != 1 && rb != 2 && rb != 4) { set_error("kl_stage5_config: rb must be 0, 1, 2 or 4"); return KL_EINVAL; }
     if (nsplit < -1 || nsplit > 64) { set_error("kl_stage5_config: nsplit must be in -1..64"); return KL_EINVAL; }
     if (rb > 0) P->s5_rb[precision] = rb;
     if (nsplit >= 0) P->s5_split[precision] = nsplit;
-    const int rbe = P->s5_rb[precision] == 4 ? 4 : 2;
+    const int rbe = P->s5_rb[precision] == 4 ? 4 : P->s5_rb[precision] == 1 ? 1 : 2;
     int64_t lchunk;
     const int ns = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rbe), P->n_cu, P->ws.max_split,
                                  P->s5_split[precision], &lchunk);

@@ -195,7 +195,7 @@ kl_status build_plan(kl_batch *B, int precision) {
             cur = m.out;
             cur_ld = m.out_ldj;
         }
-        // backward: Zf (sigma^2 J on the way in) -> T -> ... -> y
+        // backward: Zf (already scaled by sigma^2 J) -> T -> ... -> y
         cur = zf;
         cur_ld = P->Ntpad;
         A = 1;
@@ -211,11 +211,7 @@ kl_status build_plan(kl_batch *B, int precision) {
             m.Clo = 1;
             for (int j = k + 1; j < d; ++j) m.Clo *= hs.nt[j];
             m.nvec = kBW;
-            if (k == 0) {
-                m.in_w = P->dJ;
-                m.in_scale = P->sigma2;
-                m.in_f32 = lo;
-            }
+            if (k == 0) m.in_f32 = lo;
             if (k == d - 1) {
                 m.out = nullptr;            // the caller's y, set per call
                 m.out_ldj = 0;
@@ -270,6 +266,8 @@ kl_status build_plan(kl_batch *B, int precision) {
         q.lchunk = lc;
         q.nsplit = ns;
         q.kind = P->cov_kind;
+        q.wrow = P->dJ;
+        q.scale = P->sigma2;
         for (int64_t r = 0; r < Np / rows_wg; ++r)
             for (int sp = 0; sp < ns; ++sp) items.push_back(S5Item{i, int(r), sp, 0});
     }
@@ -287,6 +285,9 @@ kl_status build_plan(kl_batch *B, int precision) {
         r.base4 = base4;
         r.nsplit = pl.nsplit[i];
         r.prob = i;
+        r.Ntpad = s5[i].Ntpad;
+        r.wrow = s5[i].wrow;
+        r.scale = s5[i].scale;
         base4 += r.n4;
         red.push_back(r);
     }

@@ -7,11 +7,12 @@
 // index.  IN/OUT addresses:  a + A (i + nin c) + ldj j  (and nout for OUT), i.e. the
 // column-major tensor of each vector, with a free leading dimension ldj between vectors.
 //
-// Fusions (one launch per direction, 2d + 1 launches per apply):
+// Fusions (one launch per direction):
 //   * last forward direction (stage 4): multiplies by J[p] and writes the stage-5 input
 //     in its precision (column-major, ld = padded grid);
-//   * first backward direction (stage 6): sums the stage-5 split partials, multiplies by
-//     sigma^2 J[p], in FP64.
+//   * first backward direction (stage 6): reads the stage-5 output (FP32 or FP64), which
+//     stage 5 has already multiplied by sigma^2 J[p]; an optional per-point input weight
+//     (in_w, in_scale) remains available.
 // The point index of an entry is its address without the vector term, p = a + A (i + nin c).
 //
 // Each wave computes one 16 x 16 tile of OUT on the FP64 matrix cores (see below).

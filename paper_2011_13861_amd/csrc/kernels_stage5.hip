@@ -89,7 +89,8 @@ constexpr int kStep = kWaves * kSub;       // l-points per workgroup step
 // otherwise the split's partial (added by split_reduce_kernel in split order).
 template <typename T>
 __device__ __forceinline__ void finish_block(const T *red, T *__restrict__ Zpart, T *__restrict__ Zf,
-                                             int split, int nsplit, int64_t Ntpad, int64_t row0) {
+                                             int split, int nsplit, int64_t Ntpad, int64_t row0,
+                                             const double *__restrict__ wrow, double scale) {
     constexpr int kPer = (32 * kBW) / kThreads;          // 4 entries per thread
     T *dst = nsplit == 1 ? Zf : Zpart + int64_t(split) * Ntpad * kBW;
 #pragma unroll
@@ -99,16 +100,19 @@ __device__ __forceinline__ void finish_block(const T *red, T *__restrict__ Zpart
         T acc = T(0);
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) acc += red[(w * 32 + row) * (kBW + 1) + j];
+        if (nsplit == 1 && wrow) acc = T(double(acc) * scale * wrow[row0 + row]);
         dst[int64_t(j) * Ntpad + row0 + row] = acc;
     }
 }
 
-// Zf[e] = sum_{s < nsplit} Zpart[s][e] in split order; each thread owns 4 consecutive
-// entries and issues up to 8 splits' 16-byte loads before adding.
+// Zf[e] = w(row) sum_{s < nsplit} Zpart[s][e] in split order (w = scale wrow[row], or 1
+// without wrow; row = e mod Ntpad); each thread owns 4 consecutive entries (one column)
+// and issues up to 8 splits' 16-byte loads before adding.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void split_reduce_kernel(const T *__restrict__ Zpart,
                                                                 T *__restrict__ Zf, int nsplit,
-                                                                int64_t n4, int64_t stride) {
+                                                                int64_t n4, int64_t stride, int64_t Ntpad,
+                                                                const double *__restrict__ wrow, double scale) {
     const int64_t e4 = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (e4 >= n4) return;
     T acc[4] = {T(0), T(0), T(0), T(0)};
@@ -127,8 +131,9 @@ __global__ __launch_bounds__(kThreads) void split_reduce_kernel(const T *__restr
 #pragma unroll
                 for (int t = 0; t < 4; ++t) acc[t] += v[u][t];
     }
+    const int64_t row = (4 * e4) % Ntpad;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) Zf[4 * e4 + t] = acc[t];
+    for (int t = 0; t < 4; ++t) Zf[4 * e4 + t] = wrow ? T(double(acc[t]) * scale * wrow[row + t]) : acc[t];
 }
 
 // Work of one workgroup: rows [row0, row0 + rows_wg) against the l-range [l0, l1) of
@@ -136,10 +141,15 @@ __global__ __launch_bounds__(kThreads) void split_reduce_kernel(const T *__restr
 struct S5Tile {
     int64_t Ntpad, row0, l0, l1;
     int split, nsplit;
+    const double *wrow;     // final rows scaled by scale * wrow[row] (NULL: unscaled)
+    double scale;
 };
 
-__device__ __forceinline__ S5Tile grid_tile(int64_t rows_wg, int64_t Ntpad, int64_t lchunk) {
+__device__ __forceinline__ S5Tile grid_tile(int64_t rows_wg, int64_t Ntpad, int64_t lchunk,
+                                             const double *wrow, double scale) {
     S5Tile t;
+    t.wrow = wrow;
+    t.scale = scale;
     t.Ntpad = Ntpad;
     t.row0 = int64_t(blockIdx.x) * rows_wg;
     t.l0 = int64_t(blockIdx.y) * lchunk;
@@ -241,17 +251,17 @@ __device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, con
             red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][r];
         }
         __syncthreads();
-        finish_block<float>(red, Z, Zf, t.split, t.nsplit, Ntpad, row0 + rb * 32);
+        finish_block<float>(red, Z, Zf, t.split, t.nsplit, Ntpad, row0 + rb * 32, t.wrow, t.scale);
     }
 }
 
 template <int KIND, int D, int RB>
 __global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
     const float *__restrict__ X, const float *__restrict__ Y, float *__restrict__ Z,
-    float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
+    float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk, const double *__restrict__ wrow, double scale) {
     __shared__ float sX[D][kStep];
     __shared__ float sY[kLdsF32Y];
-    stage5_f32_body<KIND, D, RB>(X, Y, Z, Zf, grid_tile(32 * RB, Ntpad, lchunk), sX, sY);
+    stage5_f32_body<KIND, D, RB>(X, Y, Z, Zf, grid_tile(32 * RB, Ntpad, lchunk, wrow, scale), sX, sY);
 }
 
 // FP64: v_mfma_f64_16x16x4_f64, A = Gamma[16 rows][4 l], B = Y[4 l][16 cols]; A[i][k] and
@@ -336,7 +346,7 @@ __device__ __forceinline__ void stage5_f64_body(const double *__restrict__ X, co
                 red[(wave * 32 + row) * (kBW + 1) + 16 + i] = acc[rb][1][r];
             }
         __syncthreads();
-        finish_block<double>(red, Z, Zf, t.split, t.nsplit, Ntpad, row0 + 32 * half);
+        finish_block<double>(red, Z, Zf, t.split, t.nsplit, Ntpad, row0 + 32 * half, t.wrow, t.scale);
     }
 }
 constexpr size_t kLds64 = size_t(3 * kStep + kStep * (kBW + 1)) * sizeof(double);
@@ -344,9 +354,9 @@ constexpr size_t kLds64 = size_t(3 * kStep + kStep * (kBW + 1)) * sizeof(double)
 template <int KIND, int D>
 __global__ __launch_bounds__(kThreads) void stage5_f64_kernel(
     const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ Z,
-    double *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
+    double *__restrict__ Zf, int64_t Ntpad, int64_t lchunk, const double *__restrict__ wrow, double scale) {
     extern __shared__ double sm64[];
-    stage5_f64_body<KIND, D>(X, Y, Z, Zf, grid_tile(kRows, Ntpad, lchunk), sm64);
+    stage5_f64_body<KIND, D>(X, Y, Z, Zf, grid_tile(kRows, Ntpad, lchunk, wrow, scale), sm64);
 }
 
 // BF16: v_mfma_f32_32x32x16_bf16, A = Gamma[32 rows][16 l], B = Y[16 l][32 cols];
@@ -359,7 +369,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 template <int KIND, int D, int RB, bool X3>
 __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
     const float *__restrict__ X, const __bf16 *__restrict__ Yh, const __bf16 *__restrict__ Yl,
-    float *__restrict__ Z, float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk) {
+    float *__restrict__ Z, float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk,
+    const double *__restrict__ wrow, double scale) {
     constexpr int rows_wg = 32 * RB;
     constexpr int ldb = kStep + 8;               // bf16 row of one column (16-byte aligned)
     constexpr int kLd = (kBW * kStep / 8) / kThreads;   // 16-byte loads per thread per step
@@ -457,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
             red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][r];
         }
         __syncthreads();
-        finish_block<float>(red, Z, Zf, int(blockIdx.y), int(gridDim.y), Ntpad, row0 + rb * 32);
+        finish_block<float>(red, Z, Zf, int(blockIdx.y), int(gridDim.y), Ntpad, row0 + rb * 32, wrow, scale);
     }
 }
 
@@ -482,6 +493,8 @@ __device__ __forceinline__ S5Tile item_tile(const S5Prob &P, const S5Item &I, in
     t.l1 = min(t.l0 + P.lchunk, P.Ntpad);
     t.split = I.split;
     t.nsplit = P.nsplit;
+    t.wrow = P.wrow;
+    t.scale = P.scale;
     return t;
 }
 
@@ -565,13 +578,14 @@ __global__ __launch_bounds__(kThreads) void split_reduce_batch_kernel(const RedP
         for (int t = 0; t < 4; ++t) acc[t] += src[t];
     }
     T *Zf = static_cast<T *>(P.Zf);
+    const int64_t row = (4 * e4) % P.Ntpad;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) Zf[4 * e4 + t] = acc[t];
+    for (int t = 0; t < 4; ++t) Zf[4 * e4 + t] = P.wrow ? T(double(acc[t]) * P.scale * P.wrow[row + t]) : acc[t];
 }
 
 template <int KIND, int D>
 void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, void *Zf,
-                 int nsplit, int64_t lchunk, int rb, hipStream_t s) {
+                 int nsplit, int64_t lchunk, int rb, const double *wrow, double scale, hipStream_t s) {
     const int64_t rows_wg = stage5_rows_per_wg(precision, rb);
     dim3 grid(unsigned(P->Ntpad / rows_wg), unsigned(nsplit));
     if (precision == KL_F64) {
@@ -583,16 +597,15 @@ void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, v
         }
         hipLaunchKernelGGL((stage5_f64_kernel<KIND, D>), grid, dim3(kThreads), kLds64, s,
                            P->dX64, static_cast<const double *>(Y5), static_cast<double *>(Z5),
-                           static_cast<double *>(Zf), P->Ntpad, lchunk);
+                           static_cast<double *>(Zf), P->Ntpad, lchunk, wrow, scale);
     } else if (precision == KL_F32) {
-        if (rb == 4)
-            hipLaunchKernelGGL((stage5_f32_kernel<KIND, D, 4>), grid, dim3(kThreads), 0, s, P->dX32,
-                               static_cast<const float *>(Y5), static_cast<float *>(Z5),
-                               static_cast<float *>(Zf), P->Ntpad, lchunk);
-        else
-            hipLaunchKernelGGL((stage5_f32_kernel<KIND, D, 2>), grid, dim3(kThreads), 0, s, P->dX32,
-                               static_cast<const float *>(Y5), static_cast<float *>(Z5),
-                               static_cast<float *>(Zf), P->Ntpad, lchunk);
+#define KL_F32L(RB_) hipLaunchKernelGGL((stage5_f32_kernel<KIND, D, RB_>), grid, dim3(kThreads), 0, s, P->dX32, \
+                                        static_cast<const float *>(Y5), static_cast<float *>(Z5),                 \
+                                        static_cast<float *>(Zf), P->Ntpad, lchunk, wrow, scale)
+        if (rb == 4) KL_F32L(4);
+        else if (rb == 1) KL_F32L(1);
+        else KL_F32L(2);
+#undef KL_F32L
     } else {
         // BF16 operands: hi part at Y5, lo part right after it (Ntpad x kBW each)
         const __bf16 *yh = static_cast<const __bf16 *>(Y5);
@@ -600,8 +613,9 @@ void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, v
         float *z = static_cast<float *>(Z5), *zf = static_cast<float *>(Zf);
         const bool x3 = precision == KL_BF16X3;
 #define KL_BF(RB_, X3_) hipLaunchKernelGGL((stage5_bf16_kernel<KIND, D, RB_, X3_>), grid, dim3(kThreads), \
-                                           0, s, P->dX32, yh, yl, z, zf, P->Ntpad, lchunk)
+                                           0, s, P->dX32, yh, yl, z, zf, P->Ntpad, lchunk, wrow, scale)
         if (rb == 4) { if (x3) KL_BF(4, true); else KL_BF(4, false); }
+        else if (rb == 1) { if (x3) KL_BF(1, true); else KL_BF(1, false); }
         else { if (x3) KL_BF(2, true); else KL_BF(2, false); }
 #undef KL_BF
     }
@@ -609,13 +623,13 @@ void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, v
 
 template <int D>
 void launch_dim(int precision, const kl_problem *P, const void *Y5, void *Z5, void *Zf,
-                int nsplit, int64_t lchunk, int rb, hipStream_t s) {
+                int nsplit, int64_t lchunk, int rb, const double *wrow, double scale, hipStream_t s) {
     switch (P->cov_kind) {
-    case KL_COV_EXP: launch_kind<KL_COV_EXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
-    case KL_COV_SQEXP: launch_kind<KL_COV_SQEXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
-    case KL_COV_EXP_L1: launch_kind<KL_COV_EXP_L1, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
-    case KL_COV_CONST: launch_kind<KL_COV_CONST, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
-    default: launch_kind<KL_COV_LIN, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
+    case KL_COV_EXP: launch_kind<KL_COV_EXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
+    case KL_COV_SQEXP: launch_kind<KL_COV_SQEXP, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
+    case KL_COV_EXP_L1: launch_kind<KL_COV_EXP_L1, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
+    case KL_COV_CONST: launch_kind<KL_COV_CONST, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
+    default: launch_kind<KL_COV_LIN, D>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
     }
 }
 
@@ -655,16 +669,16 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 }
 
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
-                  hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-    const int rb = P->s5_rb[precision] == 4 ? 4 : 2;
+                  const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+    const int rb = P->s5_rb[precision] == 4 ? 4 : P->s5_rb[precision] == 1 ? 1 : 2;
     int64_t lchunk;
     const int nsplit = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rb), P->n_cu,
                                      P->ws.max_split, P->s5_split[precision], &lchunk);
     if (ev_start) (void)hipEventRecord(ev_start, s);
     switch (P->hs.d) {
-    case 1: launch_dim<1>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
-    case 2: launch_dim<2>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
-    default: launch_dim<3>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, s); break;
+    case 1: launch_dim<1>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
+    case 2: launch_dim<2>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
+    default: launch_dim<3>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
     }
     if (ev_stop) (void)hipEventRecord(ev_stop, s);
     if (nsplit > 1) {
@@ -673,11 +687,11 @@ int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, 
         if (precision == KL_F64)
             hipLaunchKernelGGL(split_reduce_kernel<double>, g, dim3(kThreads), 0, s,
                                static_cast<const double *>(Z5), static_cast<double *>(Zf), nsplit, n4,
-                               P->Ntpad * kBW);
+                               P->Ntpad * kBW, P->Ntpad, wrow, scale);
         else
             hipLaunchKernelGGL(split_reduce_kernel<float>, g, dim3(kThreads), 0, s,
                                static_cast<const float *>(Z5), static_cast<float *>(Zf), nsplit, n4,
-                               P->Ntpad * kBW);
+                               P->Ntpad * kBW, P->Ntpad, wrow, scale);
     }
     return nsplit;
 }

@@ -167,11 +167,13 @@ void launch_gemm_nn(const double *A, int64_t lda, int m, const double *S, int64_
 int64_t stage5_rows_per_wg(int precision, int rb);
 int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int forced,
                   int64_t *lchunk);
-// Stage 5: Zf[j][k] = sum_l Gamma(x_k, x_l) Y5[j][l]; Z5 holds split partials (scratch).
-// Returns the number of splits used.  Non-NULL ev_start / ev_stop are recorded right
-// before and right after the covariance kernel (the split sums that follow are outside).
+// Stage 5: Zf[j][k] = w_k sum_l Gamma(x_k, x_l) Y5[j][l] with w_k = scale wrow[k] (1 if
+// wrow is NULL); Z5 holds split partials (scratch).  Returns the number of splits used.
+// Non-NULL ev_start / ev_stop are recorded right before and right after the covariance
+// kernel (the split sums that follow are outside).
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
-                  hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                  const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start = nullptr,
+                  hipEvent_t ev_stop = nullptr);
 
 // kl_setup with or without the single-problem apply workspace (T0/T1, stage-5 buffers);
 // problems of a batch use the batch's arenas instead.
@@ -202,19 +204,23 @@ struct S5Prob {
     void *Zf;
     int64_t Ntpad, lchunk;
     int nsplit, kind;
+    const double *wrow;      // output rows scaled by scale * wrow[row] (sigma^2 J)
+    double scale;
 };
 // One work item: the workgroup-sized row tile `rowtile` of problem `prob` against split
 // `split` of its l-range.
 struct S5Item {
     int prob, rowtile, split, pad;
 };
-// Split sum of one problem: Zf[4 e4 + t] = sum_s Zpart[s stride + 4 e4 + t], e4 < n4;
-// base4 = sum of n4 over the preceding entries.
+// Split sum of one problem: Zf[4 e4 + t] = w sum_s Zpart[s stride + 4 e4 + t], e4 < n4,
+// w = scale wrow[(4 e4 + t) mod Ntpad]; base4 = sum of n4 over the preceding entries.
 struct RedProb {
     const void *Zpart;
     void *Zf;
-    int64_t n4, stride, base4;
+    int64_t n4, stride, base4, Ntpad;
     int nsplit, prob;
+    const double *wrow;
+    double scale;
 };
 // Persistent grid size (workgroups resident at once) of the batched stage-5 kernel.
 int stage5_batch_grid(int precision, int d, int rb, int n_cu);
