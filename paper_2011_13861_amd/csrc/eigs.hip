@@ -91,6 +91,29 @@ void release_buffers(SolverCache &c) {
     c.mcap = c.ccap = 0;
 }
 
+// Standard normal values for a random block: element i uses two 53-bit uniforms from
+// splitmix64 of (seed, 2i) and (seed, 2i + 1) and the Box-Muller transform.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kT) void normal_fill_kernel(double *__restrict__ X, int64_t n, uint64_t seed) {
+    for (int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kT) {
+        const uint64_t a = mix64(seed ^ mix64(2 * uint64_t(i))), b = mix64(seed ^ mix64(2 * uint64_t(i) + 1));
+        const double u1 = (double(a >> 11) + 1.0) * (1.0 / 9007199254740992.0);   // (0, 1]
+        const double u2 = double(b >> 11) * (1.0 / 9007199254740992.0);
+        X[i] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+    }
+}
+
+void launch_normal_fill(double *X, int64_t n, uint64_t seed, hipStream_t s) {
+    const int64_t g = std::min<int64_t>(1024, (n + kT - 1) / kT);
+    hipLaunchKernelGGL(normal_fill_kernel, dim3(unsigned(std::max<int64_t>(g, 1))), dim3(kT), 0, s, X, n, seed);
+}
+
 struct Solver {
     kl_problem *P;
     hipStream_t s = nullptr;
@@ -216,13 +239,7 @@ struct Solver {
                 // replace the missing directions by random vectors; the next pass
                 // orthonormalises them
                 refilled = true;
-                std::normal_distribution<double> nd;
-                std::vector<double> r(size_t(N) * (out_cols - good));
-                for (double &v : r) v = nd(rng);
-                if ((st = check(hipMemcpyAsync(dst + int64_t(good) * N, r.data(), r.size() * 8,
-                                               hipMemcpyHostToDevice, s), "copy random")) != KL_OK)
-                    return st;
-                if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+                launch_normal_fill(dst + int64_t(good) * N, int64_t(N) * (out_cols - good), rng(), s);
             }
             ncols = out_cols;
             if ((st = check(hipMemcpyAsync(Wb, dst, size_t(N) * ncols * 8, hipMemcpyDeviceToDevice, s),
@@ -288,6 +305,7 @@ struct EigRun {
     double best_lo = INFINITY, t_host_eig = 0.0, max_rel = INFINITY;
     int stall = 0, converged = 0;
     bool done = false;
+    bool overlap = true;                    // host Rayleigh-Ritz overlapped with the next expansion
     // the operator application the run waits for
     int pending_prec = KL_F64, pending_cols = 0, after = AFTER_NONE, last_add = 0;
     double *pending_x = nullptr, *pending_y = nullptr;
@@ -378,15 +396,7 @@ kl_status EigRun::begin(const double *x0, int nvec0) {
         if ((st = S.check(hipStreamSynchronize(S.s), "sync")) != KL_OK) return st;
         if (flag) { set_error("kl_eigs: non-finite start block"); return KL_ENUMERIC; }
     }
-    if (from_x0 < b0) {
-        std::normal_distribution<double> nd;
-        std::vector<double> r(size_t(N) * (b0 - from_x0));
-        for (double &v : r) v = nd(rng);
-        if ((st = S.check(hipMemcpyAsync(S.W + int64_t(from_x0) * N, r.data(), r.size() * 8, hipMemcpyHostToDevice,
-                                         S.s), "copy random start")) != KL_OK)
-            return st;
-        if ((st = S.check(hipStreamSynchronize(S.s), "sync")) != KL_OK) return st;
-    }
+    if (from_x0 < b0) launch_normal_fill(S.W + int64_t(from_x0) * N, int64_t(N) * (b0 - from_x0), rng(), S.s);
     S.m = 0;
     if ((st = S.orth_into_basis(S.W, b0, b0, rng)) != KL_OK) return st;
     set_pending(precision, S.V, S.AV, b0, AFTER_START);
@@ -449,7 +459,7 @@ kl_status EigRun::rr_step() {
     const int64_t N = S.N;
     const int total_applies = S.applies[0] + S.applies[1] + S.applies[2] + S.applies[3];
     const bool must_restart = S.m + S.b > S.mmax;
-    // ---- Rayleigh-Ritz on the current basis ------------------------------------------
+    // ---- Rayleigh-Ritz on the current basis --------------------------------------------
     const int m = S.m;
     std::vector<double> Hm(size_t(m) * m);
     for (int i = 0; i < m; ++i)
@@ -458,9 +468,30 @@ kl_status EigRun::rr_step() {
     const int kk = std::min(S.keep, m);
     theta.assign(m, 0.0);
     Sm.assign(size_t(m) * kk, 0.0);
-    const auto te0 = clock::now();
-    const bool eig_ok = sym_eig_partial(m, Hm.data(), theta.data(), Sm.data(), kk);
-    t_host_eig += std::chrono::duration<double>(clock::now() - te0).count();
+    // Without a restart, the next Krylov block (the newest block of AV orthonormalised
+    // against the basis) does not depend on the Ritz pairs: it is formed on the GPU while
+    // the host solves the projected problem, and discarded if the check below stops or
+    // restarts the iteration.
+    const int add_next = int(std::min<int64_t>(S.b, N - S.m));
+    const bool speculate = overlap && !must_restart && add_next > 0;
+    bool eig_ok = false;
+    double eig_s = 0.0;
+    auto solve_projected = [&]() {
+        const auto te0 = clock::now();
+        eig_ok = sym_eig_partial(m, Hm.data(), theta.data(), Sm.data(), kk);
+        eig_s = std::chrono::duration<double>(clock::now() - te0).count();
+    };
+    if (speculate) {
+        std::thread worker(solve_projected);
+        st = S.check(hipMemcpyAsync(S.W, S.AV + int64_t(S.m - S.last) * N, size_t(N) * S.last * 8,
+                                    hipMemcpyDeviceToDevice, S.s), "copy block");
+        if (st == KL_OK) st = S.orth_into_basis(S.W, S.last, add_next, rng);
+        worker.join();
+        if (st != KL_OK) return st;
+    } else {
+        solve_projected();
+    }
+    t_host_eig += eig_s;
     if (!eig_ok) { set_error("kl_eigs: projected eigenproblem did not converge"); return KL_ENUMERIC; }
     for (double t : theta)
         if (!std::isfinite(t)) { set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
@@ -508,6 +539,12 @@ kl_status EigRun::rr_step() {
         return KL_OK;
     }
     if (total_applies >= max_applies) { done = true; return KL_OK; }
+    if (speculate) {
+        // the next block was formed above
+        last_add = add_next;
+        set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add_next, AFTER_EXPAND);
+        return KL_OK;
+    }
     const int add = int(std::min<int64_t>(S.b, N - (must_restart ? kk : S.m)));
     if (must_restart) {
         // ---- thick restart -------------------------------------------------------
@@ -636,6 +673,7 @@ extern "C" kl_status kl_eigs_batch(kl_batch *B, const kl_eigs_opts *opts, double
         kl_status st = kl_batch_info(B, i, &N[i], nullptr, &off[i]);
         if (st == KL_OK) st = runs[i].configure(batch_problem(B, i), opts);
         if (st != KL_OK) return st;
+        runs[i].overlap = false;      // the runs already proceed in parallel on host threads
     }
     auto first_error = [&]() -> kl_status {
         for (int i = 0; i < n; ++i)
