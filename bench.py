@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mlp-train", type=int, default=2000,
                     help="training solves for the warm-start section (0 = skip the section)")
-    ap.add_argument("--mlp-epochs", type=int, default=200)
+    ap.add_argument("--mlp-epochs", type=int, default=1000)
     ap.add_argument("--mlp-eval", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batch section")
     ap.add_argument("--no-tune", action="store_true", help="keep the automatic stage-5 split")

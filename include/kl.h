@@ -152,6 +152,9 @@ typedef struct {
     uint64_t seed;          /* seed of the random start block */
     int32_t guard;          /* extra Ritz vectors kept beyond k; 0 = default */
     int32_t max_basis;      /* largest search-space dimension; 0 = default */
+    double  lo_floor;       /* low-precision phase: relative residual (times theta_1) it
+                               runs down to before the FP64 phase; 0 = default (FP32 2e-6,
+                               BF16x3 5e-5, BF16 5e-3) */
 } kl_eigs_opts;
 
 typedef struct {

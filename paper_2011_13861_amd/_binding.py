@@ -50,7 +50,8 @@ class KLEigsOpts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("block", ctypes.c_int32), ("max_applies", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("abs_floor", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("refine_fp64", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("guard", ctypes.c_int32), ("max_basis", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("guard", ctypes.c_int32), ("max_basis", ctypes.c_int32),
+                ("lo_floor", ctypes.c_double)]
 
 
 class KLEigsReport(ctypes.Structure):
@@ -253,13 +254,13 @@ class Problem:
         return {names[p]: (int(cnt[p]), float(ms[p])) for p in range(4)}
 
     def eigs(self, k, precision="f64", block=32, tol=1e-6, abs_floor=1e-12, refine_fp64=True,
-             seed=0, x0=None, max_applies=0, guard=0, max_basis=0, ldv=None):
+             seed=0, x0=None, max_applies=0, guard=0, max_basis=0, lo_floor=0.0, ldv=None):
         """k leading eigenpairs; returns (evals numpy, evecs device tensor (N, k) column-major,
         report dict).  Raises KLError except for KL_ENOCONV, which is reported."""
         import torch
         o = KLEigsOpts(k=k, block=block, max_applies=max_applies, tol=tol, abs_floor=abs_floor,
                        precision=PRECISIONS[precision], refine_fp64=int(bool(refine_fp64)),
-                       seed=seed, guard=guard, max_basis=max_basis)
+                       seed=seed, guard=guard, max_basis=max_basis, lo_floor=lo_floor)
         ev = np.zeros(k)
         V = torch.zeros((k, self.N), dtype=torch.float64, device="cuda").T
         rep = KLEigsReport()
@@ -322,11 +323,11 @@ class Batch:
         return g.value, it.value
 
     def eigs(self, k, precision="f64", block=32, tol=1e-6, abs_floor=1e-12, refine_fp64=True, seed=0,
-             max_applies=0, guard=0, max_basis=0):
+             max_applies=0, guard=0, max_basis=0, lo_floor=0.0):
         """Returns (evals (n, k) numpy, evecs arena (device), [report dict per problem])."""
         o = KLEigsOpts(k=k, block=block, max_applies=max_applies, tol=tol, abs_floor=abs_floor,
                        precision=PRECISIONS[precision], refine_fp64=int(bool(refine_fp64)),
-                       seed=seed, guard=guard, max_basis=max_basis)
+                       seed=seed, guard=guard, max_basis=max_basis, lo_floor=lo_floor)
         ev = np.zeros((self.n, k))
         V = self.arena(k)
         reps = (KLEigsReport * self.n)()

@@ -365,7 +365,8 @@ kl_status EigRun::configure(kl_problem *P_, const kl_eigs_opts *opts) {
     precision = opts->precision;
     refine = precision != KL_F64 && opts->refine_fp64 != 0;
     // low-precision floor: relative accuracy the low-precision apply can certify
-    lo_floor = precision == KL_F32 ? 2e-6 : precision == KL_BF16X3 ? 5e-5 : precision == KL_BF16 ? 5e-3 : 0.0;
+    lo_floor = opts->lo_floor > 0 ? opts->lo_floor
+               : precision == KL_F32 ? 2e-6 : precision == KL_BF16X3 ? 5e-5 : precision == KL_BF16 ? 5e-3 : 0.0;
     rng.seed(opts->seed);
     return KL_OK;
 }
