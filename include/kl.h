@@ -127,8 +127,9 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec,
                     const double *y, int64_t ldy, double *z, int64_t ldz, void *stream);
 
 /* Stage-5 launch configuration for one kl_precision (used by the autotuner):
- * rb = 32-row blocks per wave of the FP32/BF16 kernels (1, 2 or 4; 0 keeps the current
- * value; the FP64 kernel always uses four 16-row blocks); nsplit = number of l-splits
+ * rb = 32-row blocks per wave of the FP32/BF16 kernels (1, 2 or 4; 8 selects the FP32
+ * form with two blocks per wave and 8 waves per workgroup; 0 keeps the current value;
+ * the FP64 kernel always uses four 16-row blocks); nsplit = number of l-splits
  * (1..64 forces it, 0 = automatic load-balancing choice, -1 keeps the current setting).
  * rb_out / nsplit_out (may be NULL) receive the effective values.  Errors: KL_EINVAL. */
 kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t nsplit,

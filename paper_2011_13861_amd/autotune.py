@@ -82,7 +82,7 @@ def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None,
     data = _load(path)
     out = {}
     for prec in precisions:
-        rbs = [2] if prec == "f64" else [1, 2, 4]
+        rbs = [2] if prec == "f64" else ([1, 2, 4, 8] if prec == "f32" else [1, 2, 4])
         best = None
         for rb in rbs:
             _, auto = G.stage5_config(prec, rb=rb, nsplit=0)

@@ -393,11 +393,15 @@ kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t
                            int32_t *rb_out, int32_t *nsplit_out) {
     if (!P || P->host_only) { set_error("kl_stage5_config: NULL or host-only handle"); return KL_EINVAL; }
     if (!valid_precision(precision)) { set_error("kl_stage5_config: bad precision"); return KL_EINVAL; }
-    if (rb != 0 && rb != 1 && rb != 2 && rb != 4) { set_error("kl_stage5_config: rb must be 0, 1, 2 or 4"); return KL_EINVAL; }
+    if (rb != 0 && rb != 1 && rb != 2 && rb != 4 && rb != 8) {
+        set_error("kl_stage5_config: rb must be 0, 1, 2, 4 or 8");
+        return KL_EINVAL;
+    }
     if (nsplit < -1 || nsplit > 64) { set_error("kl_stage5_config: nsplit must be in -1..64"); return KL_EINVAL; }
     if (rb > 0) P->s5_rb[precision] = rb;
     if (nsplit >= 0) P->s5_split[precision] = nsplit;
-    const int rbe = P->s5_rb[precision] == 4 ? 4 : P->s5_rb[precision] == 1 ? 1 : 2;
+    const int rbs = P->s5_rb[precision];
+    const int rbe = (rbs == 1 || rbs == 4 || (rbs == 8 && precision == KL_F32)) ? rbs : 2;
     int64_t lchunk;
     const int ns = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rbe), P->n_cu, P->ws.max_split,
                                  P->s5_split[precision], &lchunk);

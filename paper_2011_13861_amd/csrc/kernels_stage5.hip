@@ -87,19 +87,19 @@ constexpr int kStep = kWaves * kSub;       // l-points per workgroup step
 // End of a workgroup: add the four waves' 32-row blocks (LDS `red`,
 // [wave][32 rows][kBW + 1]) and store the block: the final result with one split,
 // otherwise the split's partial (added by split_reduce_kernel in split order).
-template <typename T>
+template <typename T, int W = kWaves>
 __device__ __forceinline__ void finish_block(const T *red, T *__restrict__ Zpart, T *__restrict__ Zf,
                                              int split, int nsplit, int64_t Ntpad, int64_t row0,
                                              const double *__restrict__ wrow, double scale) {
-    constexpr int kPer = (32 * kBW) / kThreads;          // 4 entries per thread
+    constexpr int kPer = (32 * kBW) / (64 * W);          // entries per thread
     T *dst = nsplit == 1 ? Zf : Zpart + int64_t(split) * Ntpad * kBW;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int e = threadIdx.x + q * kThreads;
+        const int e = threadIdx.x + q * (64 * W);
         const int row = e % 32, j = e / 32;
         T acc = T(0);
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) acc += red[(w * 32 + row) * (kBW + 1) + j];
+        for (int w = 0; w < W; ++w) acc += red[(w * 32 + row) * (kBW + 1) + j];
         if (nsplit == 1 && wrow) acc = T(double(acc) * scale * wrow[row0 + row]);
         dst[int64_t(j) * Ntpad + row0 + row] = acc;
     }
@@ -172,11 +172,13 @@ __device__ __forceinline__ S5Tile grid_tile(int64_t rows_wg, int64_t Ntpad, int6
 // for the reduction).
 constexpr int kLdsF32Y = kStep * (kBW + 1);
 
-template <int KIND, int D, int RB>
+template <int KIND, int D, int RB, int W = kWaves>
 __device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, const float *__restrict__ Y,
                                                 float *__restrict__ Z, float *__restrict__ Zf, const S5Tile &t,
                                                 float (*sX)[kStep], float *sY) {
-    constexpr int kLd4 = (kStep * kBW / 4) / kThreads;   // float4 loads per thread per step
+    // W waves share the 256-point step: wave w contracts the sub-tile of kStep / W points
+    constexpr int kNT = 64 * W, kSubW = kStep / W;
+    constexpr int kLd4 = (kStep * kBW / 4) / kNT;        // float4 loads per thread per step
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 31, kh = lane >> 5;
     const int64_t Ntpad = t.Ntpad, row0 = t.row0, l0 = t.l0, l1 = t.l1;
@@ -196,7 +198,7 @@ __device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, con
     auto prefetch = [&](int64_t lt) {
 #pragma unroll
         for (int q = 0; q < kLd4; ++q) {
-            const int e = threadIdx.x + q * kThreads;
+            const int e = threadIdx.x + q * kNT;
             const int l4 = e % (kStep / 4), j = e / (kStep / 4);
             const int64_t lg = lt + 4 * l4;
             py[q] = lg < l1 ? *reinterpret_cast<const float4 *>(Y + int64_t(j) * Ntpad + lg)
@@ -205,7 +207,7 @@ __device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, con
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int64_t lg = lt + threadIdx.x;
-            px[k] = lg < l1 ? X[k * Ntpad + lg] : 0.f;
+            px[k] = (threadIdx.x < kStep && lg < l1) ? X[k * Ntpad + lg] : 0.f;
         }
     };
     prefetch(l0);
@@ -213,21 +215,22 @@ __device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, con
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kLd4; ++q) {
-            const int e = threadIdx.x + q * kThreads;
+            const int e = threadIdx.x + q * kNT;
             const int l4 = e % (kStep / 4), j = e / (kStep / 4);
             sY[(4 * l4 + 0) * (kBW + 1) + j] = py[q].x;
             sY[(4 * l4 + 1) * (kBW + 1) + j] = py[q].y;
             sY[(4 * l4 + 2) * (kBW + 1) + j] = py[q].z;
             sY[(4 * l4 + 3) * (kBW + 1) + j] = py[q].w;
         }
+        if (threadIdx.x < kStep)
 #pragma unroll
-        for (int k = 0; k < D; ++k) sX[k][threadIdx.x] = px[k];
+            for (int k = 0; k < D; ++k) sX[k][threadIdx.x] = px[k];
         __syncthreads();
         if (lt + kStep < l1) prefetch(lt + kStep);       // lands while this step computes
-        if (lt + wave * kSub < l1) {
-            const int base = wave * kSub;
+        if (lt + wave * kSubW < l1) {
+            const int base = wave * kSubW;
 #pragma unroll 8
-            for (int ll = 0; ll < kSub; ll += 2) {
+            for (int ll = 0; ll < kSubW; ll += 2) {
                 float xl[D];
 #pragma unroll
                 for (int k = 0; k < D; ++k) xl[k] = sX[k][base + ll + kh];
@@ -251,17 +254,17 @@ __device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, con
             red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][r];
         }
         __syncthreads();
-        finish_block<float>(red, Z, Zf, t.split, t.nsplit, Ntpad, row0 + rb * 32, t.wrow, t.scale);
+        finish_block<float, W>(red, Z, Zf, t.split, t.nsplit, Ntpad, row0 + rb * 32, t.wrow, t.scale);
     }
 }
 
-template <int KIND, int D, int RB>
-__global__ __launch_bounds__(kThreads) void stage5_f32_kernel(
+template <int KIND, int D, int RB, int W = kWaves>
+__global__ __launch_bounds__(64 * W) void stage5_f32_kernel(
     const float *__restrict__ X, const float *__restrict__ Y, float *__restrict__ Z,
     float *__restrict__ Zf, int64_t Ntpad, int64_t lchunk, const double *__restrict__ wrow, double scale) {
     __shared__ float sX[D][kStep];
     __shared__ float sY[kLdsF32Y];
-    stage5_f32_body<KIND, D, RB>(X, Y, Z, Zf, grid_tile(32 * RB, Ntpad, lchunk, wrow, scale), sX, sY);
+    stage5_f32_body<KIND, D, RB, W>(X, Y, Z, Zf, grid_tile(32 * RB, Ntpad, lchunk, wrow, scale), sX, sY);
 }
 
 // FP64: v_mfma_f64_16x16x4_f64, A = Gamma[16 rows][4 l], B = Y[4 l][16 cols]; A[i][k] and
@@ -604,6 +607,10 @@ void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, v
                                         static_cast<float *>(Zf), P->Ntpad, lchunk, wrow, scale)
         if (rb == 4) KL_F32L(4);
         else if (rb == 1) KL_F32L(1);
+        else if (rb == 8)
+            hipLaunchKernelGGL((stage5_f32_kernel<KIND, D, 2, 8>), grid, dim3(512), 0, s, P->dX32,
+                               static_cast<const float *>(Y5), static_cast<float *>(Z5),
+                               static_cast<float *>(Zf), P->Ntpad, lchunk, wrow, scale);
         else KL_F32L(2);
 #undef KL_F32L
     } else {
@@ -635,8 +642,13 @@ void launch_dim(int precision, const kl_problem *P, const void *Y5, void *Z5, vo
 
 }  // namespace
 
-// Rows owned by one stage-5 workgroup: 32 RB for the FP32 and BF16 kernels, 64 for FP64.
-int64_t stage5_rows_per_wg(int precision, int rb) { return precision == KL_F64 ? 64 : 32 * rb; }
+// Rows owned by one stage-5 workgroup: 32 rb for the FP32 and BF16 kernels (rb = 8 is the
+// FP32 form with two 32-row blocks per wave and 8 waves: 64 rows; BF16 treats it as 2),
+// 64 for FP64.
+int64_t stage5_rows_per_wg(int precision, int rb) {
+    if (precision == KL_F64 || rb == 8) return 64;
+    return 32 * rb;
+}
 
 // Number of l-splits.  Each workgroup has 4 waves; a split count S gives 4 R S waves
 // (R = row tiles) over the 4 SIMDs of every CU.  S minimises the busiest SIMD's share,
@@ -670,7 +682,8 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
                   const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-    const int rb = P->s5_rb[precision] == 4 ? 4 : P->s5_rb[precision] == 1 ? 1 : 2;
+    const int rbs = P->s5_rb[precision];
+    const int rb = (rbs == 1 || rbs == 4 || (rbs == 8 && precision == KL_F32)) ? rbs : 2;
     int64_t lchunk;
     const int nsplit = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rb), P->n_cu,
                                      P->ws.max_split, P->s5_split[precision], &lchunk);

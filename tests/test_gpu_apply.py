@@ -175,3 +175,19 @@ def test_long_direction():
     G = kl.Problem(desc)
     V = workloads.random_block(P.N, 3, seed=9)
     assert _rel_max(_gpu_apply(G, V, "f64"), P.apply(V)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,rb,ns", [("f32", 1, 0), ("f32", 2, 5), ("f32", 4, 0), ("f32", 8, 0), ("f32", 8, 9),
+                                        ("bf16x3", 1, 0), ("bf16x3", 4, 3), ("f64", 0, 7)])
+def test_stage5_tile_settings(prec, rb, ns):
+    """Every stage-5 tile setting (32-row blocks per wave, waves per workgroup, l-splits)
+    against the oracle on a problem with several row tiles and splits."""
+    desc = workloads.quarter_annulus(20, 2, "sqexp", (0.4, 0.7))
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    G.stage5_config(prec, rb=rb, nsplit=ns)
+    V = workloads.random_block(P.N, 11, seed=12)
+    out = _gpu_apply(G, V, prec)
+    ref = P.apply(V)
+    err = _rel_max(out, ref) if prec == "f64" else _rel_fro(out, ref)
+    assert err <= TOL[prec], (prec, rb, ns, err)
