@@ -432,11 +432,14 @@ kl_status EigRun::after_apply() {
         std::fill(S.H.begin(), S.H.end(), 0.0);
         if ((st = S.update_H(0, kk)) != KL_OK) return st;
         S.last = kk;
-        // expand from the residual directions of the FP64 operator
+        // expand with every residual direction of the FP64 operator: the kept vectors are
+        // Ritz vectors of the low-precision operator, so (unlike after a restart within
+        // one precision) their residuals are not confined to one block
         hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.V, S.AV, S.dtheta, N, N, S.W, S.dnorm);
-        const int add = int(std::min<int64_t>(S.b, N - S.m));
+        const int add = int(std::min<int64_t>(std::min(kk, S.mmax - S.m), N - S.m));
         if (add > 0) {
             if ((st = S.orth_into_basis(S.W, kk, add, rng)) != KL_OK) return st;
+            last_add = add;
             set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add, AFTER_EXPAND);
             return KL_OK;
         }
