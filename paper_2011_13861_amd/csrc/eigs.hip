@@ -308,6 +308,7 @@ struct EigRun {
     bool overlap = true;                    // host Rayleigh-Ritz overlapped with the next expansion
     // the operator application the run waits for
     int pending_prec = KL_F64, pending_cols = 0, after = AFTER_NONE, last_add = 0;
+    bool pending_done = false;              // the pending application was already made
     double *pending_x = nullptr, *pending_y = nullptr;
 
     kl_status configure(kl_problem *P_, const kl_eigs_opts *opts);
@@ -405,6 +406,7 @@ kl_status EigRun::begin(const double *x0, int nvec0) {
 }
 
 void EigRun::set_pending(int prec, double *x, double *y, int cols, int after_) {
+    pending_done = false;
     pending_prec = prec;
     pending_x = x;
     pending_y = y;
@@ -478,6 +480,7 @@ kl_status EigRun::rr_step() {
     // restarts the iteration.
     const int add_next = int(std::min<int64_t>(S.b, N - S.m));
     const bool speculate = overlap && !must_restart && add_next > 0;
+    const bool spec_apply = speculate && max_rel > 10.0 * tol;
     bool eig_ok = false;
     double eig_s = 0.0;
     auto solve_projected = [&]() {
@@ -490,6 +493,11 @@ kl_status EigRun::rr_step() {
         st = S.check(hipMemcpyAsync(S.W, S.AV + int64_t(S.m - S.last) * N, size_t(N) * S.last * 8,
                                     hipMemcpyDeviceToDevice, S.s), "copy block");
         if (st == KL_OK) st = S.orth_into_basis(S.W, S.last, add_next, rng);
+        // while the previous check was far from the criterion, the operator application
+        // of the next block is queued as well, so that it runs on the GPU while the host
+        // still solves the projected problem (near convergence it would be wasted)
+        if (st == KL_OK && spec_apply)
+            st = S.apply(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add_next);
         worker.join();
         if (st != KL_OK) return st;
     } else {
@@ -544,9 +552,10 @@ kl_status EigRun::rr_step() {
     }
     if (total_applies >= max_applies) { done = true; return KL_OK; }
     if (speculate) {
-        // the next block was formed above
+        // the next block was formed and applied above
         last_add = add_next;
         set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add_next, AFTER_EXPAND);
+        pending_done = spec_apply;
         return KL_OK;
     }
     const int add = int(std::min<int64_t>(S.b, N - (must_restart ? kk : S.m)));
@@ -619,7 +628,9 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
     if (st != KL_OK) return st;
     if ((st = run.begin(x0, nvec0)) != KL_OK) return st;
     while (!run.done) {
-        if ((st = run.S.apply(run.pending_prec, run.pending_x, run.pending_y, run.pending_cols)) != KL_OK) return st;
+        if (!run.pending_done &&
+            (st = run.S.apply(run.pending_prec, run.pending_x, run.pending_y, run.pending_cols)) != KL_OK)
+            return st;
         if ((st = run.after_apply()) != KL_OK) return st;
     }
     return run.finish(evals, evecs, ldv, rep, std::chrono::duration<double>(clock::now() - t0).count());
