@@ -24,7 +24,8 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 # HBM bytes per stage-5 launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a
 # plain 256 MiB copy), keyed by (workload, precision, rb, nsplit); see
 # profiles/stage5_f32_c2_hbm_traffic.md.  Only reported for the setting it was measured on.
-MEASURED_TRAFFIC = {("c2", "f32", 2, 6): 8445 * 1024}
+MEASURED_TRAFFIC = {("c2", "f32", 2, 6): 8453 * 1024, ("c2", "f32", 2, 7): 9029 * 1024,
+                    ("c2", "f32", 8, 6): 8428 * 1024, ("c2", "f32", 8, 7): 9003 * 1024}
 WORKLOADS = {
     "c2": ("2D quarter annulus (r in [1,2], NURBS map) 64x64 cubic, Ntilde = N = 4489, "
            "squared exponential L = 0.5, k = 40"),
