@@ -1,7 +1,8 @@
 """Compiles the HIP/C++ sources under csrc/ into lib/libklmf.so for gfx950.
 
-Every source is compiled by hipcc (device code for gfx950 only) with packed FP32
-instructions disabled, then linked into one shared library exposing the C ABI of
+Every source with device code is compiled by hipcc (device code for gfx950 only) with
+packed FP32 instructions disabled; the host-only sources (setup, dense eigensolver) are
+compiled as plain C++; everything is linked into one shared library exposing the C ABI of
 include/kl.h.
 """
 
@@ -24,9 +25,19 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-I" + os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 
 
+# host-only sources (no device code): plain C++ through the same compiler, so that they may
+# carry x86 function multiversioning; `omp simd` reductions are honoured (no OpenMP runtime)
+CLANG = os.environ.get("KL_HOST_CXX", "/opt/rocm/lib/llvm/bin/clang++")
+HOST_ONLY = ("dense_eig.cpp", "setup.cpp")
+
+
 def _compile(src):
     obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", src, "-o", obj]
+    if os.path.basename(src) in HOST_ONLY:
+        cmd = [CLANG, "-O3", "-std=c++17", "-fPIC", "-fopenmp-simd", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
+               "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-6000:]))

@@ -16,20 +16,20 @@ namespace kl {
 
 namespace {
 
+// Host kernels are built for the baseline x86-64 target and for x86-64-v3 (AVX2, FMA); the
+// loader picks the clone the CPU supports.
+#define KL_HOST_CLONES __attribute__((target_clones("arch=x86-64-v3", "default")))
+
 // Householder reduction a <- H a H to tridiagonal form (d diagonal, e sub-diagonal);
 // reflector k is I - beta[k] v_k v_k^T acting on rows / columns k+1..n-1, with v_k stored
-// in row k of V.
-void tridiagonalise(int n, const double *A, std::vector<double> &d, std::vector<double> &e,
-                    std::vector<double> &V, std::vector<double> &beta) {
-    std::vector<double> a(A, A + size_t(n) * n);     // working copy, row-major
-    d.assign(n, 0.0);
-    e.assign(n, 0.0);
-    V.assign(size_t(n) * n, 0.0);
-    beta.assign(n, 0.0);
-    std::vector<double> p(n), q(n);
+// in row k of V.  Only the lower triangle of the working copy is read and updated: the
+// symmetric product p = A22 v takes each off-diagonal entry twice (a dot product and an
+// axpy along its row) and the rank-2 update touches j <= i only.
+KL_HOST_CLONES
+void tridiagonalise_raw(int n, double *a, double *d, double *e, double *V, double *beta, double *p, double *q) {
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;
-        double *v = &V[size_t(k) * n];
+        double *v = V + size_t(k) * n;
         double nrm2 = 0.0;
         for (int i = 0; i < m; ++i) {
             v[i] = a[size_t(k + 1 + i) * n + k];
@@ -41,25 +41,37 @@ void tridiagonalise(int n, const double *A, std::vector<double> &d, std::vector<
         const double alpha = v[0] > 0 ? -nrm : nrm;
         v[0] -= alpha;
         double vv = 0.0;
+#pragma omp simd reduction(+ : vv)
         for (int i = 0; i < m; ++i) vv += v[i] * v[i];
         const double b = 2.0 / vv;
         beta[k] = b;
         e[k] = alpha;
-        // p = b * A22 v,  q = p - (b/2)(p.v) v,  A22 -= v q^T + q v^T
+        // p = A22 v from the lower triangle (row i of A22 is a + (k+1+i) n + k+1, entries j <= i)
+        for (int i = 0; i < m; ++i) p[i] = 0.0;
         for (int i = 0; i < m; ++i) {
-            const double *row = &a[size_t(k + 1 + i) * n + k + 1];
-            double s = 0.0;
-            for (int j = 0; j < m; ++j) s += row[j] * v[j];
-            p[i] = b * s;
+            const double *row = a + size_t(k + 1 + i) * n + k + 1;
+            const double vi = v[i];
+            double s = row[i] * vi;
+#pragma omp simd reduction(+ : s)
+            for (int j = 0; j < i; ++j) {
+                s += row[j] * v[j];
+                p[j] += row[j] * vi;
+            }
+            p[i] += s;
         }
         double pv = 0.0;
-        for (int i = 0; i < m; ++i) pv += p[i] * v[i];
+#pragma omp simd reduction(+ : pv)
+        for (int i = 0; i < m; ++i) {
+            p[i] *= b;
+            pv += p[i] * v[i];
+        }
+        // q = p - (b/2)(p.v) v,  A22 -= v q^T + q v^T  (lower triangle)
         const double K = 0.5 * b * pv;
         for (int i = 0; i < m; ++i) q[i] = p[i] - K * v[i];
         for (int i = 0; i < m; ++i) {
-            double *row = &a[size_t(k + 1 + i) * n + k + 1];
+            double *row = a + size_t(k + 1 + i) * n + k + 1;
             const double vi = v[i], qi = q[i];
-            for (int j = 0; j < m; ++j) row[j] -= vi * q[j] + qi * v[j];
+            for (int j = 0; j <= i; ++j) row[j] -= vi * q[j] + qi * v[j];
         }
     }
     if (n >= 2) {
@@ -70,6 +82,40 @@ void tridiagonalise(int n, const double *A, std::vector<double> &d, std::vector<
     e[n - 1] = 0.0;
 }
 
+void tridiagonalise(int n, const double *A, std::vector<double> &d, std::vector<double> &e,
+                    std::vector<double> &V, std::vector<double> &beta) {
+    std::vector<double> a(A, A + size_t(n) * n);     // working copy, row-major (lower triangle used)
+    d.assign(n, 0.0);
+    e.assign(n, 0.0);
+    V.assign(size_t(n) * n, 0.0);
+    beta.assign(n, 0.0);
+    std::vector<double> p(n), q(n);
+    tridiagonalise_raw(n, a.data(), d.data(), e.data(), V.data(), beta.data(), p.data(), q.data());
+}
+
+// X (n x nv, column-major) <- H_0 H_1 ... H_{n-3} X.  With from_identity, X starts as the
+// identity, whose columns j <= k are untouched by reflector k and are skipped.
+KL_HOST_CLONES
+void apply_reflectors_raw(int n, int nv, const double *V, const double *beta, double *X, bool from_identity) {
+    for (int k = n - 3; k >= 0; --k) {
+        if (beta[k] == 0.0) continue;
+        const int m = n - k - 1;
+        const double *v = V + size_t(k) * n;
+        for (int j = from_identity ? k + 1 : 0; j < nv; ++j) {
+            double *col = X + size_t(j) * n + k + 1;
+            double s = 0.0;
+#pragma omp simd reduction(+ : s)
+            for (int i = 0; i < m; ++i) s += v[i] * col[i];
+            s *= beta[k];
+            for (int i = 0; i < m; ++i) col[i] -= s * v[i];
+        }
+    }
+}
+
+void apply_reflectors(int n, int nv, const std::vector<double> &V, const std::vector<double> &beta, double *X,
+                      bool from_identity) {
+    apply_reflectors_raw(n, nv, V.data(), beta.data(), X, from_identity);
+}
 }  // namespace
 
 // A: n x n symmetric, row-major (read only).  w: eigenvalues, descending.
@@ -82,19 +128,7 @@ bool sym_eig(int n, const double *A, double *w, double *Z) {
     // ---- accumulate Q = H_0 H_1 ... H_{n-3}, column-major in Z ------------------------
     for (size_t i = 0; i < size_t(n) * n; ++i) Z[i] = 0.0;
     for (int i = 0; i < n; ++i) Z[size_t(i) * n + i] = 1.0;
-    for (int k = n - 3; k >= 0; --k) {
-        if (beta[k] == 0.0) continue;
-        const int m = n - k - 1;
-        const double *v = &V[size_t(k) * n];
-        // Q[k+1:, k+1:] <- (I - b v v^T) Q[k+1:, k+1:]; columns are contiguous
-        for (int c = k + 1; c < n; ++c) {
-            double *col = &Z[size_t(c) * n + k + 1];
-            double s = 0.0;
-            for (int i = 0; i < m; ++i) s += v[i] * col[i];
-            s *= beta[k];
-            for (int i = 0; i < m; ++i) col[i] -= s * v[i];
-        }
-    }
+    apply_reflectors(n, n, V, beta, Z, true);
     // ---- implicit symmetric QR with Wilkinson shift -------------------------------------
     const double eps = std::numeric_limits<double>::epsilon();
     int h = n - 1, iter = 0;
@@ -114,7 +148,7 @@ bool sym_eig(int n, const double *A, double *w, double *Z) {
         const double mu = d[h] - eh * eh / (delta + sg * std::hypot(delta, eh));
         double x = d[l] - mu, z = e[l];
         for (int k = l; k < h; ++k) {
-            const double r = std::hypot(x, z);
+            const double r = std::sqrt(x * x + z * z);      // |x|, |z| ~ ||T||: no overflow
             const double c = r > 0 ? x / r : 1.0;
             const double s = r > 0 ? -z / r : 0.0;
             if (k > l) e[k - 1] = r;
@@ -171,7 +205,7 @@ bool tridiagonal_eigenvalues(int n, std::vector<double> d, std::vector<double> e
         const double mu = d[h] - eh * eh / (delta + sg * std::hypot(delta, eh));
         double x = d[l] - mu, z = e[l];
         for (int k = l; k < h; ++k) {
-            const double r = std::hypot(x, z);
+            const double r = std::sqrt(x * x + z * z);      // |x|, |z| ~ ||T||: no overflow
             const double c = r > 0 ? x / r : 1.0;
             const double s = r > 0 ? -z / r : 0.0;
             if (k > l) e[k - 1] = r;
@@ -191,65 +225,116 @@ bool tridiagonal_eigenvalues(int n, std::vector<double> d, std::vector<double> e
     return true;
 }
 
-// LU factorisation with partial pivoting of the tridiagonal T - lambda I (diagonal dd,
-// sub-diagonal dl, super-diagonals du, du2 after row interchanges; piv[i] marks an
-// interchange of rows i and i + 1).  Zero pivots are replaced by `tiny`.
-struct TriLU {
-    std::vector<double> dd, dl, du, du2;
-    std::vector<char> piv;
-
-    void factor(int n, const std::vector<double> &d, const std::vector<double> &e, double lambda, double tiny) {
-        dd.resize(n); dl.assign(n, 0.0); du.assign(n, 0.0); du2.assign(n, 0.0); piv.assign(n, 0);
-        for (int i = 0; i < n; ++i) dd[i] = d[i] - lambda;
-        for (int i = 0; i + 1 < n; ++i) { dl[i] = e[i]; du[i] = e[i]; }
-        for (int i = 0; i + 1 < n; ++i) {
-            if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
-                if (dd[i] == 0.0) dd[i] = tiny;
-                const double f = dl[i] / dd[i];
-                dl[i] = f;
-                dd[i + 1] -= f * du[i];
-            } else {
-                const double f = dd[i] / dl[i];
-                dd[i] = dl[i];
-                dl[i] = f;
-                const double t = du[i];
-                du[i] = dd[i + 1];
-                dd[i + 1] = t - f * dd[i + 1];
-                if (i + 2 < n) {
-                    du2[i] = du[i + 1];
-                    du[i + 1] = -f * du[i + 1];
-                }
-                piv[i] = 1;
+// LU factorisation with partial pivoting of the tridiagonal T - lambda I (reciprocal
+// pivots rdd, multipliers dl, super-diagonals du, du2 after row interchanges; piv[i] marks
+// an interchange of rows i and i + 1).  Zero pivots are replaced by `tiny`.
+inline void tri_lu_factor(int n, const double *d, const double *e, double lambda, double tiny, double *rdd, double *dl,
+                   double *du, double *du2, char *piv) {
+    // rdd holds the pivots themselves until the end of the sweep
+    for (int i = 0; i < n; ++i) { rdd[i] = d[i] - lambda; du2[i] = 0.0; piv[i] = 0; }
+    for (int i = 0; i + 1 < n; ++i) { dl[i] = e[i]; du[i] = e[i]; }
+    dl[n - 1] = du[n - 1] = 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+        if (std::fabs(rdd[i]) >= std::fabs(dl[i])) {
+            if (rdd[i] == 0.0) rdd[i] = tiny;
+            const double f = dl[i] / rdd[i];
+            dl[i] = f;
+            rdd[i + 1] -= f * du[i];
+        } else {
+            const double f = rdd[i] / dl[i];
+            rdd[i] = dl[i];
+            dl[i] = f;
+            const double t = du[i];
+            du[i] = rdd[i + 1];
+            rdd[i + 1] = t - f * rdd[i + 1];
+            if (i + 2 < n) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du[i + 1];
             }
+            piv[i] = 1;
         }
-        if (dd[n - 1] == 0.0) dd[n - 1] = tiny;
     }
+    if (rdd[n - 1] == 0.0) rdd[n - 1] = tiny;
+    for (int i = 0; i < n; ++i) rdd[i] = 1.0 / rdd[i];
+}
 
-    // x <- (T - lambda I)^{-1} x
-    void solve(int n, double *x) const {
-        for (int i = 0; i + 1 < n; ++i) {
-            if (piv[i]) {
-                const double t = x[i];
-                x[i] = x[i + 1];
-                x[i + 1] = t - dl[i] * x[i];
-            } else {
-                x[i + 1] -= dl[i] * x[i];
-            }
+// x <- (T - lambda I)^{-1} x from the factors above
+inline void tri_lu_solve(int n, const double *rdd, const double *dl, const double *du, const double *du2,
+                         const char *piv, double *x) {
+    for (int i = 0; i + 1 < n; ++i) {
+        if (piv[i]) {
+            const double t = x[i];
+            x[i] = x[i + 1];
+            x[i + 1] = t - dl[i] * x[i];
+        } else {
+            x[i + 1] -= dl[i] * x[i];
         }
-        x[n - 1] /= dd[n - 1];
-        if (n > 1) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dd[n - 2];
-        for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
     }
-};
+    x[n - 1] *= rdd[n - 1];
+    if (n > 1) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) * rdd[n - 2];
+    for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) * rdd[i];
+}
+
+// Eigenvectors of the tridiagonal (d, e) for its nv largest eigenvalues w[0..nv-1]
+// (descending) by inverse iteration: three steps from a seeded random vector; eigenvalues
+// closer than 1e-3 ||T|| form a cluster whose vectors are orthogonalised against each
+// other at every step, and equal ones are separated by a tiny shift.  X: n x nv,
+// column-major.  work: 5 n doubles, piv: n chars.  Returns false on a breakdown.
+KL_HOST_CLONES
+bool tridiagonal_vectors_raw(int n, const double *d, const double *e, const double *w, int nv, double *X,
+                             double *work, char *piv) {
+    const double eps = std::numeric_limits<double>::epsilon();
+    double tnorm = 0.0;
+    for (int i = 0; i < n; ++i)
+        tnorm = std::max(tnorm, std::fabs(d[i]) + (i + 1 < n ? std::fabs(e[i]) : 0.0) + (i > 0 ? std::fabs(e[i - 1]) : 0.0));
+    if (tnorm == 0.0) tnorm = 1.0;
+    const double ortol = 1e-3 * tnorm, pertol = 10.0 * eps * tnorm, tiny = eps * tnorm;
+    double *rdd = work, *dl = work + n, *du = work + 2 * n, *du2 = work + 3 * n;
+    uint64_t state = 0x2545F4914F6CDD1Dull;
+    int cs = 0;                  // first index of the current cluster
+    double lam_prev = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        double lam = w[j];
+        if (j > 0 && w[j - 1] - w[j] > ortol) cs = j;
+        if (j > cs && lam_prev - lam < pertol) lam = lam_prev - pertol;
+        lam_prev = lam;
+        tri_lu_factor(n, d, e, lam, tiny, rdd, dl, du, du2, piv);
+        double *x = X + size_t(j) * n;
+        for (int i = 0; i < n; ++i) {     // splitmix64 uniform on [-1, 1)
+            uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            x[i] = 2.0 * (double(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+        }
+        for (int it = 0; it < 3; ++it) {
+            tri_lu_solve(n, rdd, dl, du, du2, piv, x);
+            for (int c = cs; c < j; ++c) {
+                const double *y = X + size_t(c) * n;
+                double s = 0.0;
+#pragma omp simd reduction(+ : s)
+                for (int i = 0; i < n; ++i) s += x[i] * y[i];
+#pragma omp simd
+                for (int i = 0; i < n; ++i) x[i] -= s * y[i];
+            }
+            double nrm = 0.0;
+#pragma omp simd reduction(+ : nrm)
+            for (int i = 0; i < n; ++i) nrm += x[i] * x[i];
+            nrm = std::sqrt(nrm);
+            if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+            const double r = 1.0 / nrm;
+#pragma omp simd
+            for (int i = 0; i < n; ++i) x[i] *= r;
+        }
+    }
+    return true;
+}
 
 }  // namespace
 
 // All n eigenvalues (descending, w) and the eigenvectors of the nv largest (Z, n x nv
 // column-major): tridiagonalisation, eigenvalues by QR without vectors, eigenvectors of
-// the tridiagonal by inverse iteration (three steps from a seeded random vector;
-// eigenvalues closer than 1e-3 ||T|| form a cluster whose vectors are orthogonalised
-// against each other at every step, and equal ones are separated by a tiny shift), then
-// the Householder reflectors applied to them.
+// the tridiagonal by inverse iteration, then the Householder reflectors applied to them.
 bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv) {
     if (n <= 0) return true;
     if (nv >= n || n <= 2) {
@@ -261,60 +346,11 @@ bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv) {
     std::vector<double> d, e, V, beta;
     tridiagonalise(n, A, d, e, V, beta);
     if (!tridiagonal_eigenvalues(n, d, e, w)) return false;
-    const double eps = std::numeric_limits<double>::epsilon();
-    double tnorm = 0.0;
-    for (int i = 0; i < n; ++i)
-        tnorm = std::max(tnorm, std::fabs(d[i]) + (i + 1 < n ? std::fabs(e[i]) : 0.0) + (i > 0 ? std::fabs(e[i - 1]) : 0.0));
-    if (tnorm == 0.0) tnorm = 1.0;
-    const double ortol = 1e-3 * tnorm, pertol = 10.0 * eps * tnorm, tiny = eps * tnorm;
-    std::vector<double> X(size_t(n) * nv);
-    TriLU lu;
-    uint64_t state = 0x2545F4914F6CDD1Dull;
-    auto uniform = [&state]() {
-        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        z ^= z >> 31;
-        return 2.0 * (double(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
-    };
-    int cs = 0;                  // first index of the current cluster
-    double lam_prev = 0.0;
-    for (int j = 0; j < nv; ++j) {
-        double lam = w[j];
-        if (j > 0 && w[j - 1] - w[j] > ortol) cs = j;
-        if (j > cs && lam_prev - lam < pertol) lam = lam_prev - pertol;
-        lam_prev = lam;
-        lu.factor(n, d, e, lam, tiny);
-        double *x = &X[size_t(j) * n];
-        for (int i = 0; i < n; ++i) x[i] = uniform();
-        for (int it = 0; it < 3; ++it) {
-            lu.solve(n, x);
-            for (int c = cs; c < j; ++c) {
-                const double *y = &X[size_t(c) * n];
-                double s = 0.0;
-                for (int i = 0; i < n; ++i) s += x[i] * y[i];
-                for (int i = 0; i < n; ++i) x[i] -= s * y[i];
-            }
-            double nrm = 0.0;
-            for (int i = 0; i < n; ++i) nrm += x[i] * x[i];
-            nrm = std::sqrt(nrm);
-            if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
-            for (int i = 0; i < n; ++i) x[i] /= nrm;
-        }
-    }
+    std::vector<double> X(size_t(n) * nv), work(size_t(5) * n);
+    std::vector<char> piv(n);
+    if (!tridiagonal_vectors_raw(n, d.data(), e.data(), w, nv, X.data(), work.data(), piv.data())) return false;
     // back-transformation: X <- H_0 H_1 ... H_{n-3} X
-    for (int k = n - 3; k >= 0; --k) {
-        if (beta[k] == 0.0) continue;
-        const int m = n - k - 1;
-        const double *v = &V[size_t(k) * n];
-        for (int j = 0; j < nv; ++j) {
-            double *col = &X[size_t(j) * n + k + 1];
-            double s = 0.0;
-            for (int i = 0; i < m; ++i) s += v[i] * col[i];
-            s *= beta[k];
-            for (int i = 0; i < m; ++i) col[i] -= s * v[i];
-        }
-    }
+    apply_reflectors(n, nv, V, beta, X.data(), false);
     std::copy(X.begin(), X.end(), Z);
     return true;
 }
