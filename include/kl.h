@@ -126,6 +126,16 @@ kl_status kl_apply(kl_problem *P, int32_t precision, int32_t nvec,
 kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec,
                     const double *y, int64_t ldy, double *z, int64_t ldz, void *stream);
 
+/* Launch structure of kl_apply (Sec. 2.2, the d mode products of each side): with
+ * fuse_directions = 1 (the default) and d >= 2, the first two directions of the forward
+ * side run as one launch over 2-D slabs, and so do those of the backward side, which
+ * also adds the stage-5 split partials and applies sigma^2 J (2d - 1 launches per
+ * 32-column block); with 0, one launch per direction plus the split sums.  Sizes whose
+ * slab does not fit the fused kernel's LDS take the per-direction form either way.
+ * fused_out (may be NULL) receives whether a 32-column apply would be fused.
+ * Errors: KL_EINVAL. */
+kl_status kl_apply_config(kl_problem *P, int32_t fuse_directions, int32_t *fused_out);
+
 /* Stage-5 launch configuration for one kl_precision (used by the autotuner):
  * rb = 32-row blocks per wave of the FP32/BF16 kernels (1, 2 or 4; 8 selects the FP32
  * form with two blocks per wave and 8 waves per workgroup; 0 keeps the current value;

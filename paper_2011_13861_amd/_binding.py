@@ -24,7 +24,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
            "kl_get_factor", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_profile_enable", "kl_profile_read",
-           "kl_stage5_config", "kl_set_cov",
+           "kl_stage5_config", "kl_apply_config", "kl_set_cov",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
            "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_destroy",
            "kl_setup_batch", "kl_batch_info", "kl_apply_batch", "kl_batch_config", "kl_eigs_batch",
@@ -86,6 +86,7 @@ def lib():
         L.kl_symeig_partial.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
         L.kl_stage5_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
+        L.kl_apply_config.argtypes = [P, ctypes.c_int32, P]
         L.kl_profile_read.argtypes = [P, P, P]
         L.kl_set_cov.argtypes = [P, ctypes.c_int32, ctypes.c_double, P]
         L.kl_mlp_create.argtypes = [ctypes.c_int32, P, ctypes.c_uint64, ctypes.POINTER(P)]
@@ -241,6 +242,13 @@ class Problem:
         check(lib().kl_stage5_config(self._h, PRECISIONS[precision], int(rb), int(nsplit),
                                      ctypes.byref(rbo), ctypes.byref(nso)))
         return rbo.value, nso.value
+
+    def apply_config(self, fuse_directions=True):
+        """Fused (True) or per-direction (False) Kronecker launches; returns whether a
+        32-column apply of this problem is fused."""
+        out = ctypes.c_int32()
+        check(lib().kl_apply_config(self._h, int(bool(fuse_directions)), ctypes.byref(out)))
+        return bool(out.value)
 
     def profile_enable(self, on=True):
         check(lib().kl_profile_enable(self._h, int(bool(on))))

@@ -116,11 +116,11 @@ int64_t max_intermediate(const HostSetup &hs) {
 // Stage-5 launch; while profiling is on, a pair of HIP events (without the system-scope
 // fence, which would add a cache writeback to the interval) brackets the covariance kernel.
 int timed_stage5(kl_problem *P, int precision, const void *Y5, const double *wrow, double scale,
-                 hipStream_t s) {
+                 hipStream_t s, bool defer_reduce = false) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
     const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, P->ws.Zf, wrow, scale, s,
                                      rec ? P->prof_ev[P->prof_used] : nullptr,
-                                     rec ? P->prof_ev[P->prof_used + 1] : nullptr);
+                                     rec ? P->prof_ev[P->prof_used + 1] : nullptr, defer_reduce);
     if (rec) {
         P->prof_prec.push_back(precision);
         P->prof_used += 2;
@@ -128,10 +128,22 @@ int timed_stage5(kl_problem *P, int precision, const void *Y5, const double *wro
     return nsplit;
 }
 
+// Whether the first two directions of each side run as one fused launch (mode2_kernel).
+bool fused_directions(const kl_problem *P, int nb) {
+    const HostSetup &hs = P->hs;
+    if (!P->fuse_dirs || hs.d < 2) return false;
+    int64_t clo_f = nb, clo_b = nb;
+    for (int k = 2; k < hs.d; ++k) { clo_f *= hs.n[k]; clo_b *= hs.nt[k]; }
+    return mode2_fits(hs.n[0], hs.n[1], hs.nt[0], hs.nt[1], clo_f) &&
+           mode2_fits(hs.nt[0], hs.nt[1], hs.n[0], hs.n[1], clo_b);
+}
+
 // One chunk (<= kBW columns) of Algorithm 1: x (N x nb, ld ldx) -> y (N x nb, ld ldy).
-// 2d + 1 launches (+1 for the split sums): d forward directions (the last one applies J
-// and writes the stage-5 input), stage 5 (its output rows scaled by sigma^2 J), d
-// backward directions.
+// Forward stages 1-4: C_k along each direction, J on the way out of the last one;
+// stage 5 (its output rows scaled by sigma^2 J); backward stages 6-9: C_k^T per
+// direction.  For d >= 2 the first two directions of each side are one launch (the
+// backward one also adds the stage-5 split partials and applies sigma^2 J): 2d - 1
+// launches for d >= 2, otherwise one per direction, stage 5 and its split sums.
 kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx,
                       double *y, int64_t ldy, hipStream_t s) {
     const HostSetup &hs = P->hs;
@@ -139,11 +151,36 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
     double *T0 = P->ws.T0, *T1 = P->ws.T1;
     const bool lo = precision != KL_F64;
     void *Y5 = stage5_input(P, precision);
-    // ---- stages 1-4: C_k along each direction, J on the way out ----------------------
+    void *Y5lo = precision == KL_BF16X3 ? static_cast<void *>(static_cast<__bf16 *>(Y5) + P->Ntpad * kBW) : nullptr;
+    const int y5_kind = precision == KL_F32 ? 1 : (precision == KL_BF16 || precision == KL_BF16X3) ? 2 : 0;
+    const bool fuse = fused_directions(P, nb);
+    // ---- stages 1-4 ---------------------------------------------------------------------
     const void *cur = x;
     int64_t cur_ld = ldx;
     int64_t A = 1;
-    for (int k = 0; k < d; ++k) {
+    int k0 = 0;
+    if (fuse) {
+        Mode2Args a{};
+        a.D1 = P->dC[0]; a.D2 = P->dC[1]; a.D1T = P->dCT[0]; a.D2T = P->dCT[1];
+        a.in = x; a.in_ldj = ldx;
+        a.nin1 = hs.n[0]; a.nin2 = hs.n[1]; a.nout1 = hs.nt[0]; a.nout2 = hs.nt[1];
+        a.Clo = 1;
+        for (int j = 2; j < d; ++j) a.Clo *= hs.n[j];
+        a.nvec = nb;
+        a.nsplit = 1; a.in_split = 0; a.in_w = nullptr; a.in_scale = 1.0;
+        if (d == 2) {
+            a.out = Y5; a.out_lo = Y5lo; a.out_ldj = P->Ntpad; a.out_w = P->dJ;
+            launch_mode2(a, false, y5_kind, s);
+        } else {
+            a.out = T0; a.out_lo = nullptr; a.out_ldj = int64_t(hs.nt[0]) * hs.nt[1] * a.Clo; a.out_w = nullptr;
+            launch_mode2(a, false, 0, s);
+        }
+        cur = T0;
+        cur_ld = int64_t(hs.nt[0]) * hs.nt[1] * a.Clo;
+        A = int64_t(hs.nt[0]) * hs.nt[1];
+        k0 = 2;
+    }
+    for (int k = k0; k < d; ++k) {
         ModeSpec m;
         m.D = P->dC[k];
         m.DT = P->dCT[k];
@@ -161,7 +198,7 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
             m.out_w = P->dJ;
             m.out_f32 = precision == KL_F32;
             m.out_bf16 = precision == KL_BF16 || precision == KL_BF16X3;
-            if (precision == KL_BF16X3) m.out_lo = static_cast<__bf16 *>(Y5) + P->Ntpad * kBW;
+            m.out_lo = Y5lo;
         } else {
             m.out = (cur == T0) ? T1 : T0;
             m.out_ldj = A * hs.nt[k] * m.Clo;
@@ -171,14 +208,40 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
         cur = m.out;
         cur_ld = m.out_ldj;
     }
-    // ---- stage 5, its output scaled by sigma^2 J --------------------------------------
-    const int nsplit = timed_stage5(P, precision, Y5, P->dJ, P->sigma2, s);
-    // ---- stages 6-9: C_k^T per direction -----------------------------------------------
-    (void)nsplit;
+    // ---- stage 5, its output scaled by sigma^2 J (or left as split partials) ------------
+    const int nsplit = timed_stage5(P, precision, Y5, P->dJ, P->sigma2, s, fuse);
+    // ---- stages 6-9 ---------------------------------------------------------------------
     cur = P->ws.Zf;
     cur_ld = P->Ntpad;
     A = 1;
-    for (int k = 0; k < d; ++k) {
+    k0 = 0;
+    if (fuse) {
+        Mode2Args a{};
+        a.D1 = P->dCT[0]; a.D2 = P->dCT[1]; a.D1T = P->dC[0]; a.D2T = P->dC[1];
+        a.nin1 = hs.nt[0]; a.nin2 = hs.nt[1]; a.nout1 = hs.n[0]; a.nout2 = hs.n[1];
+        a.Clo = 1;
+        for (int j = 2; j < d; ++j) a.Clo *= hs.nt[j];
+        a.nvec = nb;
+        a.in_ldj = P->Ntpad;
+        if (nsplit > 1) {
+            a.in = P->ws.Z5; a.nsplit = nsplit; a.in_split = P->Ntpad * kBW;
+            a.in_w = P->dJ; a.in_scale = P->sigma2;
+        } else {
+            a.in = P->ws.Zf; a.nsplit = 1; a.in_split = 0; a.in_w = nullptr; a.in_scale = 1.0;
+        }
+        a.out_lo = nullptr; a.out_w = nullptr;
+        if (d == 2) {
+            a.out = y; a.out_ldj = ldy;
+        } else {
+            a.out = T0; a.out_ldj = int64_t(hs.n[0]) * hs.n[1] * a.Clo;
+        }
+        launch_mode2(a, lo, 0, s);
+        cur = T0;
+        cur_ld = int64_t(hs.n[0]) * hs.n[1] * a.Clo;
+        A = int64_t(hs.n[0]) * hs.n[1];
+        k0 = 2;
+    }
+    for (int k = k0; k < d; ++k) {
         ModeSpec m;
         m.D = P->dCT[k];
         m.DT = P->dC[k];
@@ -386,6 +449,17 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec, const double
         kl_status st = hip_check(hipGetLastError(), "kernel launch");
         if (st != KL_OK) return st;
     }
+    return KL_OK;
+}
+
+kl_status kl_apply_config(kl_problem *P, int32_t fuse_directions, int32_t *fused_out) {
+    if (!P || P->host_only) { set_error("kl_apply_config: NULL or host-only handle"); return KL_EINVAL; }
+    if (fuse_directions != 0 && fuse_directions != 1) {
+        set_error("kl_apply_config: fuse_directions must be 0 or 1");
+        return KL_EINVAL;
+    }
+    P->fuse_dirs = fuse_directions != 0;
+    if (fused_out) *fused_out = fused_directions(P, kBW) ? 1 : 0;
     return KL_OK;
 }
 

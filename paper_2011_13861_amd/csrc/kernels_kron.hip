@@ -159,6 +159,169 @@ __global__ __launch_bounds__(kThreads) void mode_batch_kernel(const ModeArgs *__
     mode_tile<FIRST, TIN, TOUT>(g, (b - wg_prefix[lo]) * (kThreads / 64) + (threadIdx.x >> 6));
 }
 
+// Directions 1 and 2 of one 2-D slab per workgroup (both Kronecker factors of a 2-D
+// problem, or the first two of a 3-D one), Sec. 2.2 applied twice without a trip through
+// memory:
+//     U[o1][i2]     = sum_i1 D1[o1][i1] IN_s[i1][i2]       (phase 1, kept in LDS)
+//     OUT_s[o1][o2] = sum_i2 D2[o2][i2] U[o1][i2]          (phase 2)
+// for the slab s = c + Clo j (c < Clo: the index of the directions after the second,
+// j: the vector), IN_s[i1][i2] at in + i1 + nin1 (i2 + nin2 c) + in_ldj j and OUT_s at
+// out + o1 + nout1 (o2 + nout2 c) + out_ldj j.  Workgroup (s, b) owns the 16 values
+// o1 = 16 b.. and all of o2, so that no output value is computed twice; the workgroups
+// of one slab are nslab apart in launch order, which keeps them on one XCD (one L2)
+// when nslab is a multiple of 8.
+//  * Each wave first issues the loads of its matrix-core A operands: the 16 rows of D1
+//    of its block (the same for all of its phase-1 tiles) and the D2 rows of its first
+//    phase-2 tile, so that they arrive while the slab is staged.  They are read from the
+//    transposed factors, where the 16 lanes of one contraction index are 16 consecutive
+//    values (4 cache lines per load instead of 16).
+//  * Phase 0 stages the whole input slab in LDS with coalesced loads, 8 entries and up
+//    to 8 partial inputs per thread in flight: the `nsplit` partials (stride in_split)
+//    are added in split order and the sum scaled by in_scale in_w[p] when in_w is set
+//    (the stage-5 split sums and sigma^2 J taken on the way in).
+//  * Phase 1: 16 x 16 tiles of U on v_mfma_f64_16x16x4_f64, B = the slab from LDS;
+//    tile t of i2 per wave, round robin.
+//  * Phase 2: tiles of OUT^T (16 o2 x 16 o1), B = U from LDS; a lane's accumulators are
+//    16 consecutive o1 of one o2 (coalesced stores), times out_w[p] when set, converted
+//    to TOUT (BF16 with an optional low part).
+// NS: MFMA steps per contraction (4 NS >= nin1, nin2; chosen on the host in multiples of
+// 4, at most kMode2Steps): all loops have fixed trip counts and every load reads a
+// clamped, valid address whose value is then masked, so that the kernel has no
+// divergent branches.
+constexpr int kMode2Steps = 20;                            // largest NS (no spills)
+
+template <typename TIN, typename TOUT, int NS>
+__global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
+    extern __shared__ double lds2[];
+    const int n1 = g.nin1, n2 = g.nin2, m1 = g.nout1, m2 = g.nout2;
+    const int ldx = n1 | 1;                               // odd strides: conflict-free columns
+    const int t2 = (n2 + 15) / 16;
+    const int ldu = 16 * t2 + 1;
+    double *sX = lds2;                                    // [i2][ldx]
+    double *sU = lds2 + n2 * ldx;                         // [16 o1][ldu]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const uint32_t slab = blockIdx.x;
+    const int ob = blockIdx.y;                            // block of 16 o1
+    const uint32_t j = slab / uint32_t(g.Clo), c = slab - j * uint32_t(g.Clo);
+    const int t2o = (m2 + 15) / 16;
+    // ---- A operands in flight while the slab is staged: the D1 rows of the block and
+    //      the D2 rows of this wave's first phase-2 tile ---------------------------------
+    double a1[NS], a2[NS];
+    {
+        // from the transposed factors: the 16 lanes of one index i read 16 consecutive o
+        const int o1 = ob * 16 + li, o2 = w * 16 + li;
+        const int o1c = min(o1, m1 - 1), o2c = min(o2, m2 - 1);
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int i = 4 * u + lk;
+            const double v1 = g.D1T[int64_t(min(i, n1 - 1)) * m1 + o1c];
+            const double v2 = g.D2T[int64_t(min(i, n2 - 1)) * m2 + o2c];
+            a1[u] = (i < n1 && o1 < m1) ? v1 : 0.0;
+            a2[u] = (i < n2 && o2 < m2) ? v2 : 0.0;
+        }
+    }
+    // ---- phase 0: the input slab, split partials summed, into LDS ---------------------
+    {
+        const int64_t pbase = int64_t(n1) * n2 * c;        // point index of the slab's first entry
+        const TIN *in = static_cast<const TIN *>(g.in) + pbase + g.in_ldj * int64_t(j);
+        const int ne = n1 * n2, nt = blockDim.x;
+        const float rn1 = 1.0f / float(n1);
+        auto put = [&](int e, double x) {                  // e < ne
+            if (g.in_w) x *= g.in_scale * g.in_w[pbase + e];
+            int i2 = int(float(e) * rn1);                  // e / n1 (e < 2^20: off by at most one)
+            if (i2 * n1 > e) --i2;
+            if ((i2 + 1) * n1 <= e) ++i2;
+            sX[i2 * ldx + (e - i2 * n1)] = x;
+        };
+        if (g.nsplit == 1) {
+            constexpr int kE = 12;
+            for (int e0 = threadIdx.x; e0 < ne; e0 += kE * nt) {
+                TIN t[kE];
+#pragma unroll
+                for (int u = 0; u < kE; ++u) t[u] = in[min(e0 + u * nt, ne - 1)];
+#pragma unroll
+                for (int u = 0; u < kE; ++u)
+                    if (e0 + u * nt < ne) put(e0 + u * nt, double(t[u]));
+            }
+        } else {
+            constexpr int kE = 9, kQ = sizeof(TIN) == 4 ? 8 : 4;
+            const uint32_t split = uint32_t(g.in_split);   // < 2^31 (checked on the host)
+            for (int e0 = threadIdx.x; e0 < ne; e0 += kE * nt) {
+                double v[kE];
+#pragma unroll
+                for (int u = 0; u < kE; ++u) v[u] = 0.0;
+                for (int q0 = 0; q0 < g.nsplit; q0 += kQ) {
+                    TIN t[kQ][kE];
+#pragma unroll
+                    for (int q = 0; q < kQ; ++q)
+#pragma unroll
+                        for (int u = 0; u < kE; ++u)
+                            t[q][u] = in[uint32_t(min(q0 + q, g.nsplit - 1)) * split + uint32_t(min(e0 + u * nt, ne - 1))];
+#pragma unroll
+                    for (int q = 0; q < kQ; ++q)
+#pragma unroll
+                        for (int u = 0; u < kE; ++u) v[u] += (q0 + q < g.nsplit) ? double(t[q][u]) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kE; ++u)
+                    if (e0 + u * nt < ne) put(e0 + u * nt, v[u]);
+            }
+        }
+    }
+    __syncthreads();
+    // ---- phase 1: U = D1[block] IN_s ----------------------------------------------------
+    // B operands are read unmasked from clamped addresses: past nin1 the A operand is
+    // zero, and columns i2 >= nin2 of U (finite, from clamped reads) meet zero A
+    // operands in phase 2.
+    for (int t = w; t < t2; t += nw) {
+        const int i2 = t * 16 + li;                        // B operand column of this lane
+        const double *col = sX + min(i2, n2 - 1) * ldx;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], col[min(4 * u + lk, n1 - 1)], acc, 0, 0, 0);
+        // acc[r] = U[o1 local lk + 4 r][i2 = t 16 + li]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sU[(lk + 4 * r) * ldu + t * 16 + li] = acc[r];
+    }
+    __syncthreads();
+    // ---- phase 2: OUT_s^T[o2][o1] = D2[o2][:] U[o1][:]^T --------------------------------
+    const int o1 = ob * 16 + li;                           // this lane's output o1 (and B column)
+    TOUT *out = static_cast<TOUT *>(g.out);
+    const int64_t pslab = int64_t(m1) * m2 * c;
+    const int64_t obase = pslab + g.out_ldj * int64_t(j);
+    const double *urow = sU + li * ldu;
+    for (int t = w; t < t2o; t += nw) {
+        if (t != w) {                                      // later tiles: their D2 rows
+            const int o2 = t * 16 + li, o2c = min(o2, m2 - 1);
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                const int i2 = 4 * u + lk;
+                const double v = g.D2T[int64_t(min(i2, n2 - 1)) * m2 + o2c];
+                a2[u] = (i2 < n2 && o2 < m2) ? v : 0.0;
+            }
+        }
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[u], urow[min(4 * u + lk, ldu - 1)], acc, 0, 0, 0);
+        // acc[r] = OUT^T[o2 = t 16 + lk + 4 r][o1]
+        if (o1 < m1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o2 = t * 16 + lk + 4 * r;
+                if (o2 < m2) {
+                    const int64_t pl = int64_t(o1) + int64_t(m1) * o2;
+                    double v = acc[r];
+                    if (g.out_w) v *= g.out_w[pslab + pl];
+                    store_out<TOUT>(out, g.out_lo, obase + pl, v);
+                }
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void copy_cols_kernel(
     const double *__restrict__ src, int64_t lds, double *__restrict__ dst, int64_t ldd,
     int64_t rows, int cols) {
@@ -258,6 +421,54 @@ void launch_mode(const ModeSpec &m, hipStream_t s) {
         if (first) KL_MODE(true, double, double); else KL_MODE(false, double, double);
     }
 #undef KL_MODE
+}
+
+// LDS bytes of mode2_kernel: the slab (nin2 rows of nin1 | 1) and U (16 rows of
+// 16 ceil(nin2 / 16) + 1), FP64.
+static size_t mode2_lds(int nin1, int nin2) {
+    return size_t(8) * (size_t(nin2) * size_t(nin1 | 1) + size_t(16) * size_t(16 * ((nin2 + 15) / 16) + 1));
+}
+
+bool mode2_fits(int nin1, int nin2, int nout1, int nout2, int64_t slabs) {
+    return nin1 >= 1 && nin2 >= 1 && nout1 >= 1 && nout2 >= 1 && slabs >= 1 && slabs < (int64_t(1) << 31) &&
+           nin1 <= 4 * kMode2Steps && nin2 <= 4 * kMode2Steps && (nout1 + 15) / 16 <= 65535 &&
+           mode2_lds(nin1, nin2) <= size_t(kMode2MaxLds);
+}
+
+template <typename TI, typename TO, int NS>
+static void launch_mode2_ns(const Mode2Args &a, dim3 grid, int threads, size_t lds, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&mode2_kernel<TI, TO, NS>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kMode2MaxLds);
+        attr = true;
+    }
+    hipLaunchKernelGGL((mode2_kernel<TI, TO, NS>), grid, dim3(threads), lds, s, a);
+}
+
+template <typename TI, typename TO>
+static void launch_mode2_t(const Mode2Args &a, dim3 grid, int threads, size_t lds, hipStream_t s) {
+    const int steps = (std::max(a.nin1, a.nin2) + 3) / 4;
+    switch ((steps + 3) / 4) {
+    case 1: launch_mode2_ns<TI, TO, 4>(a, grid, threads, lds, s); break;
+    case 2: launch_mode2_ns<TI, TO, 8>(a, grid, threads, lds, s); break;
+    case 3: launch_mode2_ns<TI, TO, 12>(a, grid, threads, lds, s); break;
+    case 4: launch_mode2_ns<TI, TO, 16>(a, grid, threads, lds, s); break;
+    default: launch_mode2_ns<TI, TO, 20>(a, grid, threads, lds, s); break;
+    }
+}
+
+void launch_mode2(const Mode2Args &a, bool in_f32, int out_kind, hipStream_t s) {
+    // 8 waves for slabs of more than 1024 values (one pass of the staging loads); small
+    // slabs take one wave per 16-wide tile of the larger phase
+    const int tiles = std::max((a.nin2 + 15) / 16, (a.nout2 + 15) / 16);
+    const int waves = a.nin1 * a.nin2 > 1024 ? 8 : std::min(8, std::max(2, tiles));
+    const dim3 grid(unsigned(int64_t(a.Clo) * a.nvec), unsigned((a.nout1 + 15) / 16));
+    const size_t lds = mode2_lds(a.nin1, a.nin2);
+    if (in_f32) launch_mode2_t<float, double>(a, grid, 64 * waves, lds, s);
+    else if (out_kind == 1) launch_mode2_t<double, float>(a, grid, 64 * waves, lds, s);
+    else if (out_kind == 2) launch_mode2_t<double, __bf16>(a, grid, 64 * waves, lds, s);
+    else launch_mode2_t<double, double>(a, grid, 64 * waves, lds, s);
 }
 
 void launch_pack_stage5(int precision, const double *y, int64_t ldy, int64_t Nt, int nvec,

@@ -681,7 +681,8 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 }
 
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
-                  const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                  const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop,
+                  bool defer_reduce) {
     const int rbs = P->s5_rb[precision];
     const int rb = (rbs == 1 || rbs == 4 || (rbs == 8 && precision == KL_F32)) ? rbs : 2;
     int64_t lchunk;
@@ -694,7 +695,7 @@ int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, 
     default: launch_dim<3>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;
     }
     if (ev_stop) (void)hipEventRecord(ev_stop, s);
-    if (nsplit > 1) {
+    if (nsplit > 1 && !defer_reduce) {
         const int64_t n4 = P->Ntpad * kBW / 4;
         const dim3 g(unsigned((n4 + kThreads - 1) / kThreads));
         if (precision == KL_F64)

@@ -79,6 +79,7 @@ struct kl_problem {
     // stage-5 tuning per kl_precision: 32-row blocks per wave (2 or 4) and forced split
     // count (0 = automatic); set by kl_stage5_config
     int s5_rb[4] = {2, 2, 2, 2};
+    bool fuse_dirs = true;                 // first two directions of each side in one launch
     int s5_split[4] = {0, 0, 0, 0};
     // optional stage-5 timing with HIP events (kl_profile_enable / kl_profile_read)
     bool prof_on = false;
@@ -131,6 +132,30 @@ struct ModeArgs {
     const double *out_w;      // optional per-point output scale
     void *out_lo;             // BF16 output only: low part v - bf16(v), or NULL
 };
+// Kernel arguments of the fused pair of directions 1 and 2 over 2-D slabs
+// (kernels_kron.hip): D1 nout1 x nin1 and D2 nout2 x nin2 row-major FP64; slabs
+// s = c + Clo j (c < Clo, j < nvec); input = sum of nsplit partials (stride in_split),
+// optionally scaled by in_scale in_w[point]; output optionally scaled by out_w[point].
+struct Mode2Args {
+    const double *D1, *D2;
+    const double *D1T, *D2T;  // the same factors transposed (nin x nout row-major)
+    const void *in;
+    void *out;
+    void *out_lo;             // BF16 output only: low part v - bf16(v), or NULL
+    int nin1, nin2, nout1, nout2;
+    int Clo, nvec;
+    int64_t in_ldj, out_ldj;
+    int nsplit;
+    int64_t in_split;
+    const double *in_w;
+    double in_scale;
+    const double *out_w;
+};
+constexpr int kMode2MaxLds = 96 * 1024;
+// Whether the fused kernel takes these sizes (LDS, grid limits).
+bool mode2_fits(int nin1, int nin2, int nout1, int nout2, int64_t slabs);
+// out_kind: 0 FP64, 1 FP32, 2 BF16 output (FP64 input); in_f32: FP32 input, FP64 output.
+void launch_mode2(const Mode2Args &a, bool in_f32, int out_kind, hipStream_t s);
 ModeArgs mode_args(const ModeSpec &m);
 // Workgroups of one launch_mode (4 waves of one 16 x 16 tile each).
 int64_t mode_workgroups(const ModeSpec &m);
@@ -170,10 +195,12 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 // Stage 5: Zf[j][k] = w_k sum_l Gamma(x_k, x_l) Y5[j][l] with w_k = scale wrow[k] (1 if
 // wrow is NULL); Z5 holds split partials (scratch).  Returns the number of splits used.
 // Non-NULL ev_start / ev_stop are recorded right before and right after the covariance
-// kernel (the split sums that follow are outside).
+// kernel (the split sums that follow are outside).  With defer_reduce and more than one
+// split, the split sums are left to the consumer: Z5 then holds the unscaled partials
+// (split q of column j at Z5 + (q kBW + j) Ntpad) and Zf is not written.
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
                   const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start = nullptr,
-                  hipEvent_t ev_stop = nullptr);
+                  hipEvent_t ev_stop = nullptr, bool defer_reduce = false);
 
 // kl_setup with or without the single-problem apply workspace (T0/T1, stage-5 buffers);
 // problems of a batch use the batch's arenas instead.

@@ -191,3 +191,48 @@ def test_stage5_tile_settings(prec, rb, ns):
     ref = P.apply(V)
     err = _rel_max(out, ref) if prec == "f64" else _rel_fro(out, ref)
     assert err <= TOL[prec], (prec, rb, ns, err)
+
+
+FUSE_CASES = [s for s in SMALL if s[1]["dim"] >= 2] + [
+    ("wide_2d", {"dim": 2, "degree": [3, 2], "nelem": [70, 17], "map": {"kind": "identity"},
+                 "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.3, 0.6]}}),
+]
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("name,desc", FUSE_CASES, ids=[s[0] for s in FUSE_CASES])
+def test_fused_directions_match_oracle_and_per_direction_form(name, desc, precision):
+    """The fused pair of directions (one launch per side, the backward one adding the
+    stage-5 split partials) against the oracle and against the per-direction launches,
+    with the split count forced to 1 (stage 5 writes the scaled output) and to 3."""
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    assert G.apply_config(True), name
+    V = workloads.random_block(P.N, 33, seed=21)       # a full 32-column block and a ragged one
+    ref = P.apply(V)
+    tol = TOL[precision]
+    for ns in (1, 3):
+        G.stage5_config(precision, nsplit=ns)
+        G.apply_config(True)
+        fused = _gpu_apply(G, V, precision)
+        G.apply_config(False)
+        per_dir = _gpu_apply(G, V, precision)
+        for out in (fused, per_dir):
+            err = _rel_max(out, ref) if precision == "f64" else _rel_fro(out, ref)
+            assert err <= tol, (name, precision, ns, err)
+        assert _rel_max(fused, per_dir) <= (1e-12 if precision == "f64" else 10 * tol), (name, precision, ns)
+    G.apply_config(True)
+    G.stage5_config(precision, nsplit=0)
+
+
+def test_fused_directions_fallback_for_large_slabs():
+    """A 2-D problem whose slab does not fit the fused kernel's LDS keeps the
+    per-direction form (and stays correct)."""
+    desc = {"dim": 2, "degree": [2, 2], "nelem": [120, 100], "map": {"kind": "identity"},
+            "cov": {"kind": "sqexp", "sigma2": 1.0, "corr_len": [0.3, 0.3]}}
+    G = kl.Problem(desc)
+    assert not G.apply_config(True)
+    P = operator.Problem(desc)
+    V = workloads.random_block(P.N, 2, seed=22)
+    ref = P.apply(V, stage5=lambda Y: cstage5.stage5(P, Y))
+    assert _rel_max(_gpu_apply(G, V, "f64"), ref) <= 1e-12
