@@ -78,6 +78,12 @@ struct SolverCache {
     double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
     double *C = nullptr, *part = nullptr, *dtheta = nullptr, *dnorm = nullptr;
     int *dflag = nullptr;
+    // pinned host staging of the small transfers (hipHostMalloc): a device-to-host
+    // region (Gram matrices, blocks of H, residual norms) and one host-to-device region
+    // per source (orthonormalising transform, Ritz vectors, Ritz values); every region
+    // is reused only after a stream synchronisation that follows its last transfer
+    double *pin = nullptr;
+    size_t pin_region = 0;      // doubles per region (4 regions)
 };
 
 namespace {
@@ -85,7 +91,10 @@ namespace {
 void release_buffers(SolverCache &c) {
     hipFree(c.V); hipFree(c.AV); hipFree(c.Vt); hipFree(c.AVt); hipFree(c.W);
     hipFree(c.C); hipFree(c.part); hipFree(c.dtheta); hipFree(c.dnorm); hipFree(c.dflag);
+    if (c.pin) hipHostFree(c.pin);
     c.V = c.AV = c.Vt = c.AVt = c.W = c.C = c.part = c.dtheta = c.dnorm = nullptr;
+    c.pin = nullptr;
+    c.pin_region = 0;
     c.dflag = nullptr;
     c.N = 0;
     c.mcap = c.ccap = 0;
@@ -122,6 +131,8 @@ struct Solver {
     double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
     double *C = nullptr, *dtheta = nullptr, *dnorm = nullptr, *part = nullptr;
     int *dflag = nullptr;
+    // pinned staging regions (see SolverCache)
+    double *pin_d2h = nullptr, *pin_T = nullptr, *pin_S = nullptr, *pin_theta = nullptr;
     std::vector<double> H;      // mmax x mmax, row-major, host
     int m = 0;                  // current basis size
     int last = 0;               // columns [m - last, m) are the newest block
@@ -163,8 +174,8 @@ struct Solver {
         const int nc = c1 - c0;
         kl_status st = gemm_tn(V, c1, AV + int64_t(c0) * N, nc, C);
         if (st != KL_OK) return st;
-        std::vector<double> hc(size_t(c1) * nc);
-        if ((st = check(hipMemcpyAsync(hc.data(), C, hc.size() * 8, hipMemcpyDeviceToHost, s), "copy H")) != KL_OK)
+        const double *hc = pin_d2h;
+        if ((st = check(hipMemcpyAsync(pin_d2h, C, size_t(c1) * nc * 8, hipMemcpyDeviceToHost, s), "copy H")) != KL_OK)
             return st;
         if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
         for (int j = 0; j < nc; ++j)
@@ -205,10 +216,11 @@ struct Solver {
             }
             // Gram matrix of W and its eigen-decomposition
             if ((st = gemm_tn(Wb, ncols, Wb, ncols, C)) != KL_OK) return st;
-            G.assign(size_t(ncols) * ncols, 0.0);
-            if ((st = check(hipMemcpyAsync(G.data(), C, G.size() * 8, hipMemcpyDeviceToHost, s), "copy G")) != KL_OK)
+            if ((st = check(hipMemcpyAsync(pin_d2h, C, size_t(ncols) * ncols * 8, hipMemcpyDeviceToHost, s),
+                            "copy G")) != KL_OK)
                 return st;
             if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+            G.assign(pin_d2h, pin_d2h + size_t(ncols) * ncols);
             for (int i = 0; i < ncols; ++i)
                 for (int j = i + 1; j < ncols; ++j) {
                     const double a = 0.5 * (G[size_t(i) * ncols + j] + G[size_t(j) * ncols + i]);
@@ -227,12 +239,13 @@ struct Solver {
             int good = 0;
             while (good < std::min(out_cols, ncols) && w[good] > thresh) ++good;
             // T = Z[:, :good] diag(1/sqrt w)  (ncols x good), new W = W T
-            std::vector<double> T(size_t(ncols) * good, 0.0);
+            double *T = pin_T;
             for (int j = 0; j < good; ++j) {
                 const double sc = 1.0 / std::sqrt(w[j]);
                 for (int i = 0; i < ncols; ++i) T[size_t(j) * ncols + i] = Z[size_t(j) * ncols + i] * sc;
             }
-            if ((st = check(hipMemcpyAsync(C, T.data(), T.size() * 8, hipMemcpyHostToDevice, s), "copy T")) != KL_OK)
+            if (good > 0 &&
+                (st = check(hipMemcpyAsync(C, T, size_t(ncols) * good * 8, hipMemcpyHostToDevice, s), "copy T")) != KL_OK)
                 return st;
             if ((st = gemm_nn(Wb, ncols, C, ncols, good, 1.0, 0.0, dst)) != KL_OK) return st;
             if (good < out_cols) {
@@ -280,6 +293,13 @@ kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
         (st = hip(hipMalloc(&c.dtheta, size_t(mc) * 8), "alloc theta")) != KL_OK ||
         (st = hip(hipMalloc(&c.dnorm, size_t(mc) * 8), "alloc norms")) != KL_OK ||
         (st = hip(hipMalloc(&c.dflag, sizeof(int)), "alloc flag")) != KL_OK) {
+        release_buffers(c);
+        return st;
+    }
+    c.pin_region = size_t(std::max(mc, cc)) * size_t(std::max(mc, cc));
+    if ((st = hip(hipHostMalloc(reinterpret_cast<void **>(&c.pin), 4 * c.pin_region * sizeof(double),
+                                hipHostMallocDefault), "alloc pinned staging")) != KL_OK) {
+        c.pin = nullptr;
         release_buffers(c);
         return st;
     }
@@ -382,6 +402,10 @@ kl_status EigRun::begin(const double *x0, int nvec0) {
         S.s = c.s;
         S.V = c.V; S.AV = c.AV; S.Vt = c.Vt; S.AVt = c.AVt; S.W = c.W;
         S.C = c.C; S.part = c.part; S.dtheta = c.dtheta; S.dnorm = c.dnorm; S.dflag = c.dflag;
+        S.pin_d2h = c.pin;
+        S.pin_T = c.pin + c.pin_region;
+        S.pin_S = c.pin + 2 * c.pin_region;
+        S.pin_theta = c.pin + 3 * c.pin_region;
     }
     S.H.assign(size_t(S.mmax) * S.mmax, 0.0);
     const int b0 = S.b;
@@ -508,19 +532,21 @@ kl_status EigRun::rr_step() {
     for (double t : theta)
         if (!std::isfinite(t)) { set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
     // X = V S[:, :kk] -> Vt,  AX = AV S[:, :kk] -> AVt
-    if ((st = S.check(hipMemcpyAsync(S.C, Sm.data(), size_t(m) * kk * 8, hipMemcpyHostToDevice, S.s), "copy S")) != KL_OK)
+    std::copy(Sm.begin(), Sm.begin() + size_t(m) * kk, S.pin_S);
+    if ((st = S.check(hipMemcpyAsync(S.C, S.pin_S, size_t(m) * kk * 8, hipMemcpyHostToDevice, S.s), "copy S")) != KL_OK)
         return st;
     if ((st = S.gemm_nn(S.V, m, S.C, m, kk, 1.0, 0.0, S.Vt)) != KL_OK) return st;
     if ((st = S.gemm_nn(S.AV, m, S.C, m, kk, 1.0, 0.0, S.AVt)) != KL_OK) return st;
-    if ((st = S.check(hipMemcpyAsync(S.dtheta, theta.data(), size_t(kk) * 8, hipMemcpyHostToDevice, S.s),
+    std::copy(theta.begin(), theta.begin() + kk, S.pin_theta);
+    if ((st = S.check(hipMemcpyAsync(S.dtheta, S.pin_theta, size_t(kk) * 8, hipMemcpyHostToDevice, S.s),
                       "copy theta")) != KL_OK)
         return st;
     hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.Vt, S.AVt, S.dtheta, N, N, S.W, S.dnorm);
-    norms.assign(kk, 0.0);
-    if ((st = S.check(hipMemcpyAsync(norms.data(), S.dnorm, size_t(kk) * 8, hipMemcpyDeviceToHost, S.s),
+    if ((st = S.check(hipMemcpyAsync(S.pin_d2h, S.dnorm, size_t(kk) * 8, hipMemcpyDeviceToHost, S.s),
                       "copy norms")) != KL_OK)
         return st;
     if ((st = S.check(hipStreamSynchronize(S.s), "sync")) != KL_OK) return st;
+    norms.assign(S.pin_d2h, S.pin_d2h + kk);
     const double t1 = std::fabs(theta[0]);
     converged = 0;
     max_rel = 0.0;

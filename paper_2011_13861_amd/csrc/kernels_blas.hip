@@ -3,13 +3,15 @@
 // Gram-Schmidt reorthogonalisation), and Out = alpha A S + beta Out for a tall-skinny A
 // and a small S (Ritz vectors, projections).
 //
-// The N rows are split into G <= 256 ranges of at least two slabs, so that short
+// Gram products: the N rows are split into G <= 256 ranges of at least two slabs, so that short
 // products still spread over the chip.  A workgroup owns one (64 x 64 tile of C, row
 // range) pair: it stages 32-row slabs of the 64 columns of A and of B in LDS (loads
 // coalesced along the rows, the next slab prefetched into registers while the current
 // one is used) and accumulates 16 entries per thread with FP64 FMAs.  The partials are
 // stored output-major, part[e][g], so that the reduction is one wave per output entry:
 // coalesced loads of G values and a cross-lane sum, in a fixed order.
+#include <algorithm>
+
 #include "kl_internal.h"
 
 namespace kl {
@@ -95,63 +97,101 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__r
     if (lane == 0) C[e] = v;
 }
 
-// Out (N x c) = alpha A (N x m) S (m x c) + beta Out, column-major.  Computed as
-// Out^T = S^T A^T on v_mfma_f64_16x16x4_f64 so that a lane's accumulators are 16
-// consecutive rows of one output column (coalesced stores) and a lane's B operand is
-// one row of A (coalesced loads): A-operand S^T[j][k] in lane j + 16 k, B-operand
-// A^T[k][i] in lane i + 16 k, accumulator r of lane L = Out^T[(L >> 4) + 4 r][L & 15].
-// A workgroup covers 64 rows x 64 columns: wave w owns rows 16 w.. of the tile and four
-// 16-column MFMA tiles.  Operands go straight from memory to registers, 8 MFMA steps
-// (32 values of k) per batch of loads.
+// Out (N x c) = alpha A (N x m) S (m x c) + beta Out, column-major, on
+// v_mfma_f64_16x16x4_f64 in the transposed form Out^T = S^T A^T: A operand S^T[j][k] in
+// lane j + 16 k, B operand A^T[k][i] = A[i + lda k] in lane i + 16 k (16 consecutive
+// rows of one column: coalesced), accumulator r of lane L = Out^T[(L >> 4) + 4 r][L & 15].
+// A workgroup owns 16 rows of Out and NT tiles of 16 columns (all of c up to 128, so
+// that A is read once); its 4 waves split the contraction (wave w takes the 4-wide
+// k-steps s = w mod 4), with the operands of the next batch of steps in flight while the
+// current one runs on the matrix cores.  The four partial tiles are added in LDS in
+// wave order and stored with alpha and beta (beta = 0 does not read Out).
 typedef double doublex4 __attribute__((ext_vector_type(4)));
-constexpr int kNNSteps = 8;
+constexpr int kNNBatch = 4;      // k-steps per wave per batch of loads
+constexpr int kNNMaxTiles = 8;   // column tiles per workgroup
 
+template <int NT>
 __global__ __launch_bounds__(kThreads) void gemm_nn_kernel(const double *__restrict__ A, int64_t lda, int m,
                                                            const double *__restrict__ S, int64_t lds, int c,
                                                            int64_t N, double alpha, double beta,
                                                            double *__restrict__ Out, int64_t ldo) {
+    extern __shared__ double red_nn[];                     // [4][16][16 NT + 1]
+    constexpr int ldr = 16 * NT + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t row = int64_t(blockIdx.x) * 64 + 16 * w + li;   // this lane's A row
-    const int j0 = blockIdx.y * 64;
-    const bool rok = row < N;
-    doublex4 acc[4];
+    const int64_t row0 = int64_t(blockIdx.x) * 16;
+    const int j0 = blockIdx.y * 16 * NT;
+    const int64_t rowc = min(row0 + li, N - 1);            // clamped: rows past N are not stored
+    const int steps = (m + 3) / 4;
+    doublex4 acc[NT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < m; k0 += 4 * kNNSteps) {
-        double a[kNNSteps], b[4][kNNSteps];
+    for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    // batch q of this wave: steps w + 4 (kNNBatch q + u), u < kNNBatch
+    auto load = [&](int q, double (&a)[kNNBatch], double (&b)[kNNBatch][NT]) {
 #pragma unroll
-        for (int s = 0; s < kNNSteps; ++s) {
-            const int k = k0 + 4 * s + lk;
+        for (int u = 0; u < kNNBatch; ++u) {
+            const int k = 4 * (w + 4 * (kNNBatch * q + u)) + lk;
             const bool kok = k < m;
-            a[s] = (kok && rok) ? A[row + lda * k] : 0.0;
+            const int kc = kok ? k : m - 1;
+            const double va = A[rowc + lda * kc];
+            a[u] = kok ? va : 0.0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < NT; ++t) {
                 const int j = j0 + 16 * t + li;
-                b[t][s] = (kok && j < c) ? S[k + lds * j] : 0.0;
+                const double vs = S[kc + lds * min(j, c - 1)];
+                b[u][t] = (kok && j < c) ? vs : 0.0;
             }
         }
+    };
+    auto mma = [&](const double (&a)[kNNBatch], const double (&b)[kNNBatch][NT]) {
 #pragma unroll
-        for (int s = 0; s < kNNSteps; ++s)
-            if (k0 + 4 * s < m)
+        for (int u = 0; u < kNNBatch; ++u)
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t][s], a[s], acc[t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[u][t], a[u], acc[t], 0, 0, 0);
+    };
+    const int nbatch = (steps + 4 * kNNBatch - 1) / (4 * kNNBatch);
+    double a0[kNNBatch], b0[kNNBatch][NT], a1[kNNBatch], b1[kNNBatch][NT];
+    if (nbatch > 0) load(0, a0, b0);                       // m = 0: no loads, Out = beta Out
+    for (int q = 0; q < nbatch; q += 2) {
+        if (q + 1 < nbatch) load(q + 1, a1, b1);
+        mma(a0, b0);
+        if (q + 1 >= nbatch) break;
+        if (q + 2 < nbatch) load(q + 2, a0, b0);
+        mma(a1, b1);
     }
-    // lane L holds Out[row0 + (L & 15)][j0 + 16 t + (L >> 4) + 4 r]
-    const int64_t orow = int64_t(blockIdx.x) * 64 + 16 * w + li;
-    if (orow >= N) return;
+    // partial tiles -> LDS: acc[t][r] of lane L = Out[row0 + (L & 15)][j0 + 16 t + (L >> 4) + 4 r]
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = j0 + 16 * t + lk + 4 * r;
-            if (j < c) {
-                double *o = Out + orow + ldo * j;
-                const double v = alpha * acc[t][r];
-                *o = beta == 0.0 ? v : v + beta * *o;
-            }
+        for (int r = 0; r < 4; ++r) red_nn[(w * 16 + li) * ldr + 16 * t + lk + 4 * r] = acc[t][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * 16 * NT; e += kThreads) {
+        const int i = e & 15, jj = e >> 4;
+        const int64_t row = row0 + i;
+        const int j = j0 + jj;
+        if (row < N && j < c) {
+            double v = red_nn[i * ldr + jj];
+#pragma unroll
+            for (int ww = 1; ww < 4; ++ww) v += red_nn[(ww * 16 + i) * ldr + jj];
+            double *o = Out + row + ldo * j;
+            *o = beta == 0.0 ? alpha * v : alpha * v + beta * *o;
         }
+    }
+}
+
+template <int NT>
+void launch_gemm_nn_t(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
+                      double alpha, double beta, double *Out, int64_t ldo, hipStream_t s) {
+    const size_t lds_bytes = size_t(4) * 16 * (16 * NT + 1) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nn_kernel<NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+        attr = true;
+    }
+    const dim3 grid(unsigned((N + 15) / 16), unsigned((c + 16 * NT - 1) / (16 * NT)));
+    hipLaunchKernelGGL((gemm_nn_kernel<NT>), grid, dim3(kThreads), lds_bytes, s, A, lda, m, S, lds, c, N, alpha,
+                       beta, Out, ldo);
 }
 
 }  // namespace
@@ -183,8 +223,20 @@ void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t l
 void launch_gemm_nn(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
                     double alpha, double beta, double *Out, int64_t ldo, hipStream_t s) {
     if (N < 1 || c < 1) return;
-    const dim3 grid(unsigned((N + 63) / 64), unsigned((c + 63) / 64));
-    hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(kThreads), 0, s, A, lda, m, S, lds, c, N, alpha, beta, Out, ldo);
+    if (m < 1) {                        // empty contraction: Out = beta Out
+        if (beta != 1.0) launch_gemm_nn_t<1>(A, lda, 0, S, lds, c, N, alpha, beta, Out, ldo, s);
+        return;
+    }
+    switch (std::min(kNNMaxTiles, (c + 15) / 16)) {
+    case 1: launch_gemm_nn_t<1>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
+    case 2: launch_gemm_nn_t<2>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
+    case 3: launch_gemm_nn_t<3>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
+    case 4: launch_gemm_nn_t<4>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
+    case 5: launch_gemm_nn_t<5>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
+    case 6: launch_gemm_nn_t<6>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
+    case 7: launch_gemm_nn_t<7>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
+    default: launch_gemm_nn_t<8>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
+    }
 }
 
 }  // namespace kl
