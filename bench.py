@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--mlp-eval", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batch section")
     ap.add_argument("--no-tune", action="store_true", help="keep the automatic stage-5 split")
+    ap.add_argument("--tune-objective", default="apply", choices=["apply", "stage5"],
+                    help="what the stage-5 tile search minimises: the whole apply (default) or the kernel alone")
     ap.add_argument("--tiles", default=None, metavar="RB,NSPLIT",
                     help="force the stage-5 tiles instead of tuning (e.g. 2,6), for profiler runs")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
@@ -238,7 +240,7 @@ def main():
         G.stage5_config(prec, rb=rb_, nsplit=ns_)
     elif not args.no_tune:
         from paper_2011_13861_amd import autotune
-        autotune.tune_problem(G, desc["cov"]["kind"], precisions=(prec,), reps=10)
+        autotune.tune_problem(G, desc["cov"]["kind"], precisions=(prec,), reps=10, objective=args.tune_objective)
     x = kl.to_device_block(workloads.random_block(G.N, b, seed=1))
     y = kl.new_block(G.N, b)
     stream = torch.cuda.current_stream()

@@ -9,8 +9,12 @@ batch), keeps the fastest, and caches it in a JSON file keyed by
 
     (GPU architecture, dimension, covariance kind, precision, padded grid size)
 
-for single problems, and by (architecture, dimension, precision, batch signature) for
-batches.  Cached settings are applied with `apply_cached`.  The cache file is
+for single problems (plus the objective when it is the whole apply), and by
+(architecture, dimension, precision, batch signature) for batches.  The objective of a
+single problem is the stage-5 kernel alone (`objective="stage5"`, the default) or the whole
+apply of a 32-column block (`objective="apply"`): the fused backward Kronecker launch adds
+the stage-5 split partials, so fewer splits can make the apply faster even when the kernel
+alone is not.  Cached settings are applied with `apply_cached`.  The cache file is
 $KL_TUNE_CACHE, else ~/.cache/paper_2011_13861_amd/stage5_tune.json.
 """
 
@@ -50,8 +54,11 @@ def _padded(nt):
     return (nt + 255) // 256 * 256
 
 
-def problem_key(G, kind, precision):
-    return "|".join([arch(), "d%d" % G.d, kind, precision, "Np%d" % _padded(G.Nt)])
+def problem_key(G, kind, precision, objective="stage5"):
+    parts = [arch(), "d%d" % G.d, kind, precision, "Np%d" % _padded(G.Nt)]
+    if objective != "stage5":
+        parts.append(objective)
+    return "|".join(parts)
 
 
 def batch_key(B, kinds, precision):
@@ -75,9 +82,30 @@ def _time_problem(G, precision, reps, nvec=32):
     return ms / max(cnt, 1) * 1e3
 
 
-def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None, verbose=False):
+def _time_apply(G, precision, reps, nvec=32):
+    import torch
+    x = torch.randn((nvec, G.N), dtype=torch.float64, device="cuda").T
+    y = torch.empty((nvec, G.N), dtype=torch.float64, device="cuda").T
+    for _ in range(3):
+        G.apply(x, y, precision)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        G.apply(x, y, precision)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e3
+
+
+def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None, verbose=False,
+                 objective="stage5"):
     """Searches (rb, nsplit) for each precision on problem G (covariance `kind`), sets
-    the best, records it in the cache and returns {precision: (rb, nsplit, us)}."""
+    the best for the objective ("stage5": the kernel alone; "apply": the whole apply of
+    a 32-column block), records it in the cache and returns {precision: (rb, nsplit, us)}."""
+    if objective not in ("stage5", "apply"):
+        raise ValueError("objective must be 'stage5' or 'apply'")
+    timer = _time_problem if objective == "stage5" else _time_apply
     path = path or cache_path()
     data = _load(path)
     out = {}
@@ -91,13 +119,13 @@ def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None,
                 rbe, nse = G.stage5_config(prec, rb=rb, nsplit=ns)
                 if nse != ns and ns != auto:
                     continue                      # capped: same as a smaller candidate
-                us = _time_problem(G, prec, reps)
+                us = timer(G, prec, reps)
                 if verbose:
                     print("tune", prec, rbe, nse, "%.1f us" % us)
                 if best is None or us < best[2]:
                     best = (rbe, nse, us)
         G.stage5_config(prec, rb=best[0], nsplit=best[1])
-        data[problem_key(G, kind, prec)] = {"rb": best[0], "nsplit": best[1], "us": best[2]}
+        data[problem_key(G, kind, prec, objective)] = {"rb": best[0], "nsplit": best[1], "us": best[2]}
         out[prec] = best
     _store(path, data)
     return out
@@ -136,9 +164,9 @@ def tune_batch(B, kinds, precision="f32", reps=10, path=None, verbose=False):
     return best
 
 
-def apply_cached(G, kind, precision, path=None):
+def apply_cached(G, kind, precision, path=None, objective="stage5"):
     """Sets the cached setting for G, if any; returns it (or None)."""
-    e = _load(path or cache_path()).get(problem_key(G, kind, precision))
+    e = _load(path or cache_path()).get(problem_key(G, kind, precision, objective))
     if e:
         G.stage5_config(precision, rb=e["rb"], nsplit=e["nsplit"])
     return e

@@ -302,10 +302,12 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
                 a2[u] = (i2 < n2 && o2 < m2) ? v : 0.0;
             }
         }
+        // U columns past 16 t2 were not written: clamp to the last written one (the A
+        // operand is zero past nin2)
         doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < NS; ++u)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[u], urow[min(4 * u + lk, ldu - 1)], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[u], urow[min(4 * u + lk, 16 * t2 - 1)], acc, 0, 0, 0);
         // acc[r] = OUT^T[o2 = t 16 + lk + 4 r][o1]
         if (o1 < m1) {
 #pragma unroll

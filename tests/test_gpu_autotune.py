@@ -41,6 +41,34 @@ def test_tune_problem_records_and_reapplies(tmp_path):
     assert np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref) <= 2e-6
 
 
+def test_tune_problem_apply_objective(tmp_path):
+    """Tuning on the whole apply records its own cache entry (apart from the
+    kernel-alone one) and the setting it picks keeps the apply correct."""
+    path = str(tmp_path / "tune.json")
+    desc = workloads.quarter_annulus(24, 3, "sqexp", (0.5, 0.5))
+    G = kl.Problem(desc)
+    rb, ns, us = autotune.tune_problem(G, "sqexp", precisions=("f32",), reps=5, max_split=12, path=path,
+                                       objective="apply")["f32"]
+    data = json.load(open(path))
+    assert autotune.problem_key(G, "sqexp", "f32") not in data
+    e = data[autotune.problem_key(G, "sqexp", "f32", "apply")]
+    assert (e["rb"], e["nsplit"]) == (rb, ns) and us > 0
+    F = kl.Problem(desc)
+    assert autotune.apply_cached(F, "sqexp", "f32", path=path) is None
+    assert autotune.apply_cached(F, "sqexp", "f32", path=path, objective="apply") is not None
+    assert F.stage5_config("f32") == (rb, ns)
+    P = operator.Problem(desc)
+    V = workloads.random_block(P.N, 32, seed=3)
+    x = kl.to_device_block(V)
+    y = kl.new_block(F.N, 32)
+    F.apply(x, y, "f32")
+    torch.cuda.synchronize()
+    ref = P.apply(V)
+    assert np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref) <= 2e-6
+    with pytest.raises(ValueError):
+        autotune.tune_problem(G, "sqexp", objective="wall")
+
+
 def test_tune_batch_records_and_stays_correct(tmp_path):
     path = str(tmp_path / "tune.json")
     descs = workloads.batch_problems(7, count=6)
