@@ -197,6 +197,52 @@ struct Solver {
         return KL_OK;
     }
 
+    // Re-orthonormalises W = V[:, m:m+ncols], already orthonormal and orthogonal to
+    // V[:, :m] up to rounding, with one Gram product: [C1; G] = [V | W]^T W (V and W are
+    // adjacent columns), G = Z diag(w) Z^T on the host, then W <- (W - V C1) T with
+    // T = Z diag(w)^(-1/2).  The Gram matrix of W - V C1 is G - C1^T C1, which differs
+    // from G by the square of rounding-size terms, so G is used.  On a numerically rank
+    // deficient G nothing is changed and ok stays false.  Wb receives a copy of the result.
+    kl_status reorth_short(double *Wb, int ncols, bool &ok) {
+        kl_status st;
+        ok = false;
+        double *dst = V + int64_t(m) * N;
+        const int mt = m + ncols;
+        if ((st = gemm_tn(V, mt, dst, ncols, C)) != KL_OK) return st;
+        if ((st = check(hipMemcpyAsync(pin_d2h, C, size_t(mt) * ncols * 8, hipMemcpyDeviceToHost, s),
+                        "copy Gram")) != KL_OK)
+            return st;
+        if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+        std::vector<double> G(size_t(ncols) * ncols), w(ncols), Z(size_t(ncols) * ncols);
+        for (int j = 0; j < ncols; ++j)
+            for (int i = 0; i < ncols; ++i) G[size_t(i) * ncols + j] = pin_d2h[size_t(j) * mt + m + i];
+        for (int i = 0; i < ncols; ++i)
+            for (int j = i + 1; j < ncols; ++j) {
+                const double a = 0.5 * (G[size_t(i) * ncols + j] + G[size_t(j) * ncols + i]);
+                G[size_t(i) * ncols + j] = G[size_t(j) * ncols + i] = a;
+            }
+        if (!sym_eig(ncols, G.data(), w.data(), Z.data())) {
+            set_error("kl_eigs: Gram eigen-decomposition failed");
+            return KL_ENUMERIC;
+        }
+        if (!(w[ncols - 1] > std::max(w[0], 1e-300) * 1e-26)) return KL_OK;
+        // W -= V C1 (C1: the first m rows of the device Gram result, ld mt)
+        if (m > 0 && (st = gemm_nn(V, m, C, mt, ncols, -1.0, 1.0, dst)) != KL_OK) return st;
+        double *T = pin_T;
+        for (int j = 0; j < ncols; ++j) {
+            const double sc = 1.0 / std::sqrt(w[j]);
+            for (int i = 0; i < ncols; ++i) T[size_t(j) * ncols + i] = Z[size_t(j) * ncols + i] * sc;
+        }
+        // the upload follows the product that reads C1 on the stream
+        if ((st = check(hipMemcpyAsync(C, T, size_t(ncols) * ncols * 8, hipMemcpyHostToDevice, s), "copy T")) != KL_OK)
+            return st;
+        if ((st = gemm_nn(dst, ncols, C, ncols, ncols, 1.0, 0.0, Wb)) != KL_OK) return st;
+        if ((st = check(hipMemcpyAsync(dst, Wb, size_t(N) * ncols * 8, hipMemcpyDeviceToDevice, s), "copy W")) != KL_OK)
+            return st;
+        ok = true;
+        return KL_OK;
+    }
+
     // Orthonormalises the ncols columns of W against V[:, :m] and among themselves and
     // writes `want` orthonormal columns to V[:, m:m+want], spanning the dominant
     // directions of W; rank deficiency is filled with seeded random directions.
@@ -208,6 +254,13 @@ struct Solver {
         // them (twice is enough unless a direction had to be replaced by a random one)
         bool refilled = true;
         for (int pass = 0; pass < 4 && (pass < 2 || refilled); ++pass) {
+            if (pass > 0 && !refilled) {
+                // the block is orthonormal and orthogonal to V up to rounding: one pass of
+                // the short form (falls through to the full one if it meets rank deficiency)
+                bool ok = false;
+                if ((st = reorth_short(Wb, ncols, ok)) != KL_OK) return st;
+                if (ok) break;
+            }
             refilled = false;
             for (int cgs = 0; cgs < 2; ++cgs) {
                 if (m == 0) break;
