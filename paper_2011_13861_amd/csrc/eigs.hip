@@ -245,8 +245,10 @@ struct Solver {
 
     // Orthonormalises the ncols columns of W against V[:, :m] and among themselves and
     // writes `want` orthonormal columns to V[:, m:m+want], spanning the dominant
-    // directions of W; rank deficiency is filled with seeded random directions.
-    kl_status orth_into_basis(double *Wb, int ncols, int want, std::mt19937_64 &rng) {
+    // directions of W; rank deficiency is filled with seeded random directions.  With
+    // c_holds_vtw the device buffer C already holds V[:, :m]^T W (m x ncols, as the
+    // last update_H left it) and the first Gram product is not recomputed.
+    kl_status orth_into_basis(double *Wb, int ncols, int want, std::mt19937_64 &rng, bool c_holds_vtw = false) {
         kl_status st;
         std::vector<double> G, w, Z;
         double *dst = V + int64_t(m) * N;
@@ -264,7 +266,8 @@ struct Solver {
             refilled = false;
             for (int cgs = 0; cgs < 2; ++cgs) {
                 if (m == 0) break;
-                if ((st = gemm_tn(V, m, Wb, ncols, C)) != KL_OK) return st;
+                if (!(pass == 0 && cgs == 0 && c_holds_vtw) && (st = gemm_tn(V, m, Wb, ncols, C)) != KL_OK)
+                    return st;
                 if ((st = gemm_nn(V, m, C, m, ncols, -1.0, 1.0, Wb)) != KL_OK) return st;
             }
             // Gram matrix of W and its eigen-decomposition
@@ -569,7 +572,9 @@ kl_status EigRun::rr_step() {
         std::thread worker(solve_projected);
         st = S.check(hipMemcpyAsync(S.W, S.AV + int64_t(S.m - S.last) * N, size_t(N) * S.last * 8,
                                     hipMemcpyDeviceToDevice, S.s), "copy block");
-        if (st == KL_OK) st = S.orth_into_basis(S.W, S.last, add_next, rng);
+        // C still holds V^T AV[:, m - last:m] from update_H, the first product of the
+        // orthonormalisation of this block
+        if (st == KL_OK) st = S.orth_into_basis(S.W, S.last, add_next, rng, true);
         // while the previous check was far from the criterion, the operator application
         // of the next block is queued as well, so that it runs on the GPU while the host
         // still solves the projected problem (near convergence it would be wasted)
