@@ -451,8 +451,10 @@ kl_status EigRun::configure(kl_problem *P_, const kl_eigs_opts *opts) {
 kl_status EigRun::begin(const double *x0, int nvec0) {
     kl_status st;
     const int64_t N = S.N;
-    const int cmax = std::max(S.mmax, S.keep + S.b);
-    if ((st = acquire_cache(P, N, S.mmax, cmax)) != KL_OK) return st;
+    // b spare basis columns hold the speculative block of a restart step (see rr_step);
+    // C and the Gram partials hold the (mmax + b) x b products of its orthonormalisation
+    const int cmax = std::max(S.mmax + S.b, S.keep + S.b);
+    if ((st = acquire_cache(P, N, S.mmax + S.b, cmax)) != KL_OK) return st;
     {
         SolverCache &c = *P->solver;
         S.s = c.s;
@@ -554,12 +556,15 @@ kl_status EigRun::rr_step() {
     const int kk = std::min(S.keep, m);
     theta.assign(m, 0.0);
     Sm.assign(size_t(m) * kk, 0.0);
-    // Without a restart, the next Krylov block (the newest block of AV orthonormalised
-    // against the basis) does not depend on the Ritz pairs: it is formed on the GPU while
-    // the host solves the projected problem, and discarded if the check below stops or
-    // restarts the iteration.
+    // The next Krylov block (the newest block of AV orthonormalised against the basis)
+    // does not depend on the Ritz pairs: it is formed on the GPU while the host solves
+    // the projected problem, and discarded if the check below stops the iteration or
+    // switches precision.  On a restart step it goes to the b spare columns past mmax
+    // and continues the restarted basis: the residuals of the Ritz vectors of a block
+    // Krylov space lie in the span of that block, so it is the same continuation as the
+    // orthonormalised residuals.
     const int add_next = int(std::min<int64_t>(S.b, N - S.m));
-    const bool speculate = overlap && !must_restart && add_next > 0;
+    const bool speculate = overlap && add_next > 0;
     const bool spec_apply = speculate && max_rel > 10.0 * tol;
     bool eig_ok = false;
     double eig_s = 0.0;
@@ -635,10 +640,32 @@ kl_status EigRun::rr_step() {
         return KL_OK;
     }
     if (total_applies >= max_applies) { done = true; return KL_OK; }
-    if (speculate) {
+    if (speculate && !must_restart) {
         // the next block was formed and applied above
         last_add = add_next;
         set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add_next, AFTER_EXPAND);
+        pending_done = spec_apply;
+        return KL_OK;
+    }
+    if (speculate) {
+        // ---- thick restart continued by the speculative block ------------------------
+        // kept Ritz vectors X (and AX) are in Vt[:, :kk] (AVt); the block formed above is
+        // orthonormal to the old basis, hence to X: it moves next to them
+        if ((st = S.check(hipMemcpyAsync(S.Vt + int64_t(kk) * N, S.V + int64_t(m) * N, size_t(N) * add_next * 8,
+                                         hipMemcpyDeviceToDevice, S.s), "copy block")) != KL_OK)
+            return st;
+        if (spec_apply &&
+            (st = S.check(hipMemcpyAsync(S.AVt + int64_t(kk) * N, S.AV + int64_t(m) * N, size_t(N) * add_next * 8,
+                                         hipMemcpyDeviceToDevice, S.s), "copy block")) != KL_OK)
+            return st;
+        std::swap(S.V, S.Vt);
+        std::swap(S.AV, S.AVt);
+        S.m = kk;
+        std::fill(S.H.begin(), S.H.end(), 0.0);
+        for (int i = 0; i < kk; ++i) S.H[size_t(i) * S.mmax + i] = theta[i];
+        S.restarts += 1;
+        last_add = add_next;
+        set_pending(precision, S.V + int64_t(kk) * N, S.AV + int64_t(kk) * N, add_next, AFTER_EXPAND);
         pending_done = spec_apply;
         return KL_OK;
     }
