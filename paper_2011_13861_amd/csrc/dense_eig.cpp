@@ -355,6 +355,46 @@ bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv) {
     return true;
 }
 
+// Orthonormalising transform of a Gram matrix G = W^T W (n x n, row-major, symmetric):
+// the Cholesky factor G = R^T R (R upper triangular) and T = R^{-1}, so that W T has
+// orthonormal columns spanning the columns of W.  T: column-major n x n (upper
+// triangular).  Returns false, leaving T unspecified, when a pivot r_jj^2 falls to
+// rel_tol max_i G_ii or below (numerical rank deficiency: the caller uses the
+// eigen-decomposition instead).
+bool chol_orth_transform(int n, const double *G, double *T, double rel_tol) {
+    if (n <= 0) return true;
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = std::max(dmax, G[size_t(i) * n + i]);
+    if (!(dmax > 0.0) || !std::isfinite(dmax)) return false;
+    const double floor_ = rel_tol * dmax;
+    std::vector<double> R(size_t(n) * n, 0.0);     // row-major upper triangle
+    for (int j = 0; j < n; ++j) {
+        double d = G[size_t(j) * n + j];
+        for (int k = 0; k < j; ++k) d -= R[size_t(k) * n + j] * R[size_t(k) * n + j];
+        if (!(d > floor_)) return false;
+        const double rjj = std::sqrt(d);
+        R[size_t(j) * n + j] = rjj;
+        const double inv = 1.0 / rjj;
+        for (int c = j + 1; c < n; ++c) {
+            double v = G[size_t(j) * n + c];
+            for (int k = 0; k < j; ++k) v -= R[size_t(k) * n + j] * R[size_t(k) * n + c];
+            R[size_t(j) * n + c] = v * inv;
+        }
+    }
+    // T = R^{-1}: back substitution column by column (T upper triangular)
+    for (size_t e = 0; e < size_t(n) * n; ++e) T[e] = 0.0;
+    for (int c = 0; c < n; ++c) {
+        double *t = T + size_t(c) * n;                // column c of T
+        t[c] = 1.0 / R[size_t(c) * n + c];
+        for (int i = c - 1; i >= 0; --i) {
+            double v = 0.0;
+            for (int k = i + 1; k <= c; ++k) v += R[size_t(i) * n + k] * t[k];
+            t[i] = -v / R[size_t(i) * n + i];
+        }
+    }
+    return true;
+}
+
 }  // namespace kl
 
 extern "C" kl_status kl_symeig_partial(int32_t n, const double *A, double *w, double *Z, int32_t nv) {

@@ -213,7 +213,7 @@ struct Solver {
                         "copy Gram")) != KL_OK)
             return st;
         if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
-        std::vector<double> G(size_t(ncols) * ncols), w(ncols), Z(size_t(ncols) * ncols);
+        std::vector<double> G(size_t(ncols) * ncols);
         for (int j = 0; j < ncols; ++j)
             for (int i = 0; i < ncols; ++i) G[size_t(i) * ncols + j] = pin_d2h[size_t(j) * mt + m + i];
         for (int i = 0; i < ncols; ++i)
@@ -221,18 +221,22 @@ struct Solver {
                 const double a = 0.5 * (G[size_t(i) * ncols + j] + G[size_t(j) * ncols + i]);
                 G[size_t(i) * ncols + j] = G[size_t(j) * ncols + i] = a;
             }
-        if (!sym_eig(ncols, G.data(), w.data(), Z.data())) {
-            set_error("kl_eigs: Gram eigen-decomposition failed");
-            return KL_ENUMERIC;
+        // T = R^{-1} (G = R^T R); on a small pivot, T = Z diag(w)^(-1/2) from G = Z diag(w) Z^T
+        double *T = pin_T;
+        if (!chol_orth_transform(ncols, G.data(), T, 1e-24)) {
+            std::vector<double> w(ncols), Z(size_t(ncols) * ncols);
+            if (!sym_eig(ncols, G.data(), w.data(), Z.data())) {
+                set_error("kl_eigs: Gram eigen-decomposition failed");
+                return KL_ENUMERIC;
+            }
+            if (!(w[ncols - 1] > std::max(w[0], 1e-300) * 1e-26)) return KL_OK;
+            for (int j = 0; j < ncols; ++j) {
+                const double sc = 1.0 / std::sqrt(w[j]);
+                for (int i = 0; i < ncols; ++i) T[size_t(j) * ncols + i] = Z[size_t(j) * ncols + i] * sc;
+            }
         }
-        if (!(w[ncols - 1] > std::max(w[0], 1e-300) * 1e-26)) return KL_OK;
         // W -= V C1 (C1: the first m rows of the device Gram result, ld mt)
         if (m > 0 && (st = gemm_nn(V, m, C, mt, ncols, -1.0, 1.0, dst)) != KL_OK) return st;
-        double *T = pin_T;
-        for (int j = 0; j < ncols; ++j) {
-            const double sc = 1.0 / std::sqrt(w[j]);
-            for (int i = 0; i < ncols; ++i) T[size_t(j) * ncols + i] = Z[size_t(j) * ncols + i] * sc;
-        }
         // the upload follows the product that reads C1 on the stream
         if ((st = check(hipMemcpyAsync(C, T, size_t(ncols) * ncols * 8, hipMemcpyHostToDevice, s), "copy T")) != KL_OK)
             return st;
@@ -282,23 +286,29 @@ struct Solver {
                     const double a = 0.5 * (G[size_t(i) * ncols + j] + G[size_t(j) * ncols + i]);
                     G[size_t(i) * ncols + j] = G[size_t(j) * ncols + i] = a;
                 }
-            w.assign(ncols, 0.0);
-            Z.assign(size_t(ncols) * ncols, 0.0);
-            if (!sym_eig(ncols, G.data(), w.data(), Z.data())) {
-                set_error("kl_eigs: Gram eigen-decomposition failed");
-                return KL_ENUMERIC;
-            }
             // pass 0 keeps the `want` dominant directions (fewer if W has fewer columns:
-            // the rest is filled at random); later passes keep every column
+            // the rest is filled at random); later passes keep every column.  When every
+            // column is kept, the Cholesky factor of G gives the transform (T = R^{-1});
+            // otherwise, or on a small pivot, the eigen-decomposition G = Z diag(w) Z^T
+            // (T = Z[:, :good] diag(w)^(-1/2), the dominant directions first)
             const int out_cols = pass == 0 ? want : ncols;
-            const double thresh = std::max(w[0], 1e-300) * 1e-26;
-            int good = 0;
-            while (good < std::min(out_cols, ncols) && w[good] > thresh) ++good;
-            // T = Z[:, :good] diag(1/sqrt w)  (ncols x good), new W = W T
             double *T = pin_T;
-            for (int j = 0; j < good; ++j) {
-                const double sc = 1.0 / std::sqrt(w[j]);
-                for (int i = 0; i < ncols; ++i) T[size_t(j) * ncols + i] = Z[size_t(j) * ncols + i] * sc;
+            int good = 0;
+            if (out_cols == ncols && chol_orth_transform(ncols, G.data(), T, 1e-24)) {
+                good = ncols;
+            } else {
+                w.assign(ncols, 0.0);
+                Z.assign(size_t(ncols) * ncols, 0.0);
+                if (!sym_eig(ncols, G.data(), w.data(), Z.data())) {
+                    set_error("kl_eigs: Gram eigen-decomposition failed");
+                    return KL_ENUMERIC;
+                }
+                const double thresh = std::max(w[0], 1e-300) * 1e-26;
+                while (good < std::min(out_cols, ncols) && w[good] > thresh) ++good;
+                for (int j = 0; j < good; ++j) {
+                    const double sc = 1.0 / std::sqrt(w[j]);
+                    for (int i = 0; i < ncols; ++i) T[size_t(j) * ncols + i] = Z[size_t(j) * ncols + i] * sc;
+                }
             }
             if (good > 0 &&
                 (st = check(hipMemcpyAsync(C, T, size_t(ncols) * good * 8, hipMemcpyHostToDevice, s), "copy T")) != KL_OK)
