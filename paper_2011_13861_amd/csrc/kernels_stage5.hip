@@ -86,7 +86,8 @@ constexpr int kStep = kWaves * kSub;       // l-points per workgroup step
 
 // End of a workgroup: add the four waves' 32-row blocks (LDS `red`,
 // [wave][32 rows][kBW + 1]) and store the block: the final result with one split,
-// otherwise the split's partial (added by split_reduce_kernel in split order).
+// otherwise the split's partial (added in split order by split_reduce_kernel or by the
+// consumer: the fused backward Kronecker launch).
 template <typename T, int W = kWaves>
 __device__ __forceinline__ void finish_block(const T *red, T *__restrict__ Zpart, T *__restrict__ Zf,
                                              int split, int nsplit, int64_t Ntpad, int64_t row0,
