@@ -64,9 +64,10 @@ def cpu_baseline(desc, b, budget_s=12.0):
 def warm_start_section(n_train, epochs, n_eval, solves=3):
     """Config 5: the network is trained on n_train method-generated FP64 solves (tol 1e-10)
     of the 48x48 cubic quarter annulus (training draws seed 2000), then the held-out draws
-    (seed 2001) are solved to 1e-6 three ways: plain FP64 from a random block, FP32 with
-    FP64 refinement from a random block, and the same from the predicted block (network
-    inference included in the timed solve).  Times are medians over the held-out draws."""
+    (seed 2001) are solved to 1e-6 four ways: plain FP64 from a random block, FP32 with
+    FP64 refinement from a random block, the same from the predicted block, and plain FP64
+    from the predicted block (network inference included in the timed warm solves).  Times
+    are medians over the held-out draws."""
     import numpy as np
     import torch
 
@@ -93,14 +94,15 @@ def warm_start_section(n_train, epochs, n_eval, solves=3):
     train_s = time.perf_counter() - t
     del T
     Le, ae, fe = workloads.mlp_parameters(2001, n_eval)
-    rec = {"f64": [], "f32_random": [], "f32_warm": []}
+    rec = {"f64": [], "f32_random": [], "f32_warm": [], "f64_warm": []}
     app = {k: [] for k in rec}
     for i, cov in enumerate(covs(Le, ae, fe)):
         G.set_cov(*cov)
         f = warmstart.features(Le[i], ae[i], fe[i])[0]
         runs = {"f64": lambda: G.eigs(K, precision="f64", block=16, tol=1e-6),
                 "f32_random": lambda: G.eigs(K, precision="f32", block=16, tol=1e-6),
-                "f32_warm": lambda: warmstart.solve(G, K, ws, f, precision="f32", block=16, tol=1e-6)}
+                "f32_warm": lambda: warmstart.solve(G, K, ws, f, precision="f32", block=16, tol=1e-6),
+                "f64_warm": lambda: warmstart.solve(G, K, ws, f, precision="f64", block=16, tol=1e-6)}
         for name, fn in runs.items():
             best = None
             for _ in range(solves):
@@ -118,7 +120,8 @@ def warm_start_section(n_train, epochs, n_eval, solves=3):
             "n_train": n_train, "epochs": epochs, "generate_s": gen_s, "train_s": train_s,
             "loss_first_last": [float(losses[0]), float(losses[-1])], "n_eval": n_eval,
             "median_ms": med, "mean_applies": {k: float(np.mean(v)) for k, v in app.items()},
-            "f32_warm_speedup_vs_f64": med["f64"] / med["f32_warm"]}
+            "f32_warm_speedup_vs_f64": med["f64"] / med["f32_warm"],
+            "f64_warm_speedup_vs_f64": med["f64"] / med["f64_warm"]}
 
 
 def batch_section(reps=20):

@@ -135,3 +135,24 @@ def test_eigs_errors():
     with pytest.raises(kl.KLError) as e:
         H.eigs(4)
     assert e.value.status == -1
+
+
+def test_config3_residuals_under_fp64_apply():
+    """Config 3 (3-D, 24^3 quadratic, k = 50): both forms meet the criterion at 1e-6 under
+    the FP64 apply (itself checked against the oracle elsewhere), the basis is
+    orthonormal, and the two forms agree on the eigenvalues."""
+    desc, k, b = workloads.config("c3")
+    G = kl.Problem(desc)
+    ws = {}
+    for prec in ("f64", "f32"):
+        w, V, rep = G.eigs(k, precision=prec, block=b, tol=1e-6)
+        assert rep["status"] == "KL_OK" and rep["converged"] == k, (prec, rep)
+        Y = kl.new_block(G.N, k)
+        G.apply(V, Y, "f64")
+        torch.cuda.synchronize()
+        Vh, Yh = V.cpu().numpy(), Y.cpu().numpy()
+        r = np.linalg.norm(Yh - Vh * w[None, :], axis=0)
+        assert np.all(r <= np.maximum(1e-6 * w, 1e-12 * w[0]) * 1.01), (prec, np.max(r / w))
+        assert np.max(np.abs(Vh.T @ Vh - np.eye(k))) < 1e-8, prec
+        ws[prec] = w
+    assert np.all(np.abs(ws["f32"] - ws["f64"]) <= 2e-6 * np.abs(ws["f64"])), np.max(np.abs(ws["f32"] / ws["f64"] - 1))
