@@ -183,12 +183,13 @@ template <int NT>
 void launch_gemm_nn_t(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
                       double alpha, double beta, double *Out, int64_t ldo, hipStream_t s) {
     const size_t lds_bytes = size_t(4) * 16 * (16 * NT + 1) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
+    // once per process (thread-safe initialisation of a function-local static)
+    static const bool attr = [lds_bytes] {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nn_kernel<NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
-        attr = true;
-    }
+        return true;
+    }();
+    (void)attr;
     const dim3 grid(unsigned((N + 15) / 16), unsigned((c + 16 * NT - 1) / (16 * NT)));
     hipLaunchKernelGGL((gemm_nn_kernel<NT>), grid, dim3(kThreads), lds_bytes, s, A, lda, m, S, lds, c, N, alpha,
                        beta, Out, ldo);

@@ -439,12 +439,13 @@ bool mode2_fits(int nin1, int nin2, int nout1, int nout2, int64_t slabs) {
 
 template <typename TI, typename TO, int NS>
 static void launch_mode2_ns(const Mode2Args &a, dim3 grid, int threads, size_t lds, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
+    // once per process (thread-safe initialisation of a function-local static)
+    static const bool attr = [] {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&mode2_kernel<TI, TO, NS>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kMode2MaxLds);
-        attr = true;
-    }
+        return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL((mode2_kernel<TI, TO, NS>), grid, dim3(threads), lds, s, a);
 }
 

@@ -593,12 +593,13 @@ void launch_kind(int precision, const kl_problem *P, const void *Y5, void *Z5, v
     const int64_t rows_wg = stage5_rows_per_wg(precision, rb);
     dim3 grid(unsigned(P->Ntpad / rows_wg), unsigned(nsplit));
     if (precision == KL_F64) {
-        static bool attr_set = false;
-        if (!attr_set) {
+        // once per process (thread-safe initialisation of a function-local static)
+        static const bool attr_set = [] {
             (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&stage5_f64_kernel<KIND, D>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kLds64));
-            attr_set = true;
-        }
+            return true;
+        }();
+        (void)attr_set;
         hipLaunchKernelGGL((stage5_f64_kernel<KIND, D>), grid, dim3(kThreads), kLds64, s,
                            P->dX64, static_cast<const double *>(Y5), static_cast<double *>(Z5),
                            static_cast<double *>(Zf), P->Ntpad, lchunk, wrow, scale);
