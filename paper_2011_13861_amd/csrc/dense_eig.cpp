@@ -276,7 +276,8 @@ inline void tri_lu_solve(int n, const double *rdd, const double *dl, const doubl
 }
 
 // Eigenvectors of the tridiagonal (d, e) for its nv largest eigenvalues w[0..nv-1]
-// (descending) by inverse iteration: three steps from a seeded random vector; eigenvalues
+// (descending) by inverse iteration: two steps from a seeded random vector (the shifts are
+// eigenvalues accurate to rounding, so the second step already converges); eigenvalues
 // closer than 1e-3 ||T|| form a cluster whose vectors are orthogonalised against each
 // other at every step, and equal ones are separated by a tiny shift.  X: n x nv,
 // column-major.  work: 5 n doubles, piv: n chars.  Returns false on a breakdown.
@@ -307,7 +308,7 @@ bool tridiagonal_vectors_raw(int n, const double *d, const double *e, const doub
             z ^= z >> 31;
             x[i] = 2.0 * (double(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
         }
-        for (int it = 0; it < 3; ++it) {
+        for (int it = 0; it < 2; ++it) {
             tri_lu_solve(n, rdd, dl, du, du2, piv, x);
             for (int c = cs; c < j; ++c) {
                 const double *y = X + size_t(c) * n;
