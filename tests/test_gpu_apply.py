@@ -116,6 +116,22 @@ def test_full_size_config2_apply():
         assert err <= TOL[prec], (prec, err)
 
 
+def test_full_size_config3_apply_two_columns():
+    """Config 3 (24^3 perturbed cube, exp L = 0.5) at full size: the whole apply (fused
+    first two directions, third direction, stage 5, backward) on two columns against the
+    oracle's Algorithm 1 with its C stage 5."""
+    desc = workloads.config("c3")[0]
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    assert G.apply_config(True)
+    V = workloads.random_block(P.N, 2, seed=13)
+    ref = P.apply(V, stage5=lambda Y: cstage5.stage5(P, Y))
+    for prec in PRECS:
+        out = _gpu_apply(G, V, prec)
+        err = _rel_max(out, ref) if prec == "f64" else _rel_fro(out, ref)
+        assert err <= TOL[prec], (prec, err)
+
+
 def test_full_size_config3_stage5_sampled_rows():
     """Config 3 (24^3 perturbed cube, exp L = 0.5): stage 5 on 32 vectors, sampled rows
     recomputed one by one by the oracle's kernel definition."""
