@@ -136,6 +136,7 @@ struct Solver {
     std::vector<double> H;      // mmax x mmax, row-major, host
     int m = 0;                  // current basis size
     int last = 0;               // columns [m - last, m) are the newest block
+    bool last_refilled = false; // the last orth_into_basis replaced directions by random ones
     int applies[4] = {0, 0, 0, 0}, block_applies[4] = {0, 0, 0, 0}, restarts = 0;
 
     kl_status check(hipError_t e, const char *what) {
@@ -256,6 +257,7 @@ struct Solver {
         kl_status st;
         std::vector<double> G, w, Z;
         double *dst = V + int64_t(m) * N;
+        last_refilled = false;
         // pass 0 selects the `want` dominant directions; later passes re-orthonormalise
         // them (twice is enough unless a direction had to be replaced by a random one)
         bool refilled = true;
@@ -318,6 +320,7 @@ struct Solver {
                 // replace the missing directions by random vectors; the next pass
                 // orthonormalises them
                 refilled = true;
+                last_refilled = true;
                 launch_normal_fill(dst + int64_t(good) * N, int64_t(N) * (out_cols - good), rng(), s);
             }
             ncols = out_cols;
@@ -394,6 +397,12 @@ struct EigRun {
     bool overlap = true;                    // host Rayleigh-Ritz overlapped with the next expansion
     // the operator application the run waits for
     int pending_prec = KL_F64, pending_cols = 0, after = AFTER_NONE, last_add = 0;
+    // the basis satisfies the block Arnoldi relation A V[:, :m - last] in span V[:, :m]:
+    // every expansion so far kept all directions of the operator image of the newest
+    // block (no truncation, no random refill); only then is the next Krylov block a
+    // valid continuation of a thick restart (it spans the residuals of the Ritz vectors)
+    bool krylov_ok = true;
+    bool pending_keeps_krylov = true;       // the pending expansion keeps the relation
     bool pending_done = false;              // the pending application was already made
     double *pending_x = nullptr, *pending_y = nullptr;
 
@@ -492,6 +501,8 @@ kl_status EigRun::begin(const double *x0, int nvec0) {
     }
     if (from_x0 < b0) launch_normal_fill(S.W + int64_t(from_x0) * N, int64_t(N) * (b0 - from_x0), rng(), S.s);
     S.m = 0;
+    krylov_ok = true;
+    pending_keeps_krylov = true;
     if ((st = S.orth_into_basis(S.W, b0, b0, rng)) != KL_OK) return st;
     set_pending(precision, S.V, S.AV, b0, AFTER_START);
     return KL_OK;
@@ -531,8 +542,11 @@ kl_status EigRun::after_apply() {
         // one precision) their residuals are not confined to one block
         hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.V, S.AV, S.dtheta, N, N, S.W, S.dnorm);
         const int add = int(std::min<int64_t>(std::min(kk, S.mmax - S.m), N - S.m));
+        krylov_ok = false;                  // low-precision Ritz vectors under the FP64 operator
         if (add > 0) {
             if ((st = S.orth_into_basis(S.W, kk, add, rng)) != KL_OK) return st;
+            krylov_ok = add == kk && !S.last_refilled;
+            pending_keeps_krylov = true;
             last_add = add;
             set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add, AFTER_EXPAND);
             return KL_OK;
@@ -544,6 +558,7 @@ kl_status EigRun::after_apply() {
         if ((st = S.update_H(S.m, S.m + add)) != KL_OK) return st;
         S.m += add;
         S.last = add;
+        krylov_ok = krylov_ok && pending_keeps_krylov;
         return rr_step();
     }
     default:
@@ -570,12 +585,14 @@ kl_status EigRun::rr_step() {
     // does not depend on the Ritz pairs: it is formed on the GPU while the host solves
     // the projected problem, and discarded if the check below stops the iteration or
     // switches precision.  On a restart step it goes to the b spare columns past mmax
-    // and continues the restarted basis: the residuals of the Ritz vectors of a block
-    // Krylov space lie in the span of that block, so it is the same continuation as the
-    // orthonormalised residuals.
+    // and continues the restarted basis when the basis satisfies the block Arnoldi
+    // relation and the block kept every direction: the residuals of the Ritz vectors
+    // then lie in the span of that block, so it is the same continuation as the
+    // orthonormalised residuals (otherwise the residuals are used).
     const int add_next = int(std::min<int64_t>(S.b, N - S.m));
     const bool speculate = overlap && add_next > 0;
     const bool spec_apply = speculate && max_rel > 10.0 * tol;
+    bool blk_full = false;                  // the speculative block kept every direction
     bool eig_ok = false;
     double eig_s = 0.0;
     auto solve_projected = [&]() {
@@ -590,6 +607,7 @@ kl_status EigRun::rr_step() {
         // C still holds V^T AV[:, m - last:m] from update_H, the first product of the
         // orthonormalisation of this block
         if (st == KL_OK) st = S.orth_into_basis(S.W, S.last, add_next, rng, true);
+        blk_full = add_next == S.last && !S.last_refilled;
         // while the previous check was far from the criterion, the operator application
         // of the next block is queued as well, so that it runs on the GPU while the host
         // still solves the projected problem (near convergence it would be wasted)
@@ -653,11 +671,12 @@ kl_status EigRun::rr_step() {
     if (speculate && !must_restart) {
         // the next block was formed and applied above
         last_add = add_next;
+        pending_keeps_krylov = blk_full;
         set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add_next, AFTER_EXPAND);
         pending_done = spec_apply;
         return KL_OK;
     }
-    if (speculate) {
+    if (speculate && krylov_ok && blk_full) {
         // ---- thick restart continued by the speculative block ------------------------
         // kept Ritz vectors X (and AX) are in Vt[:, :kk] (AVt); the block formed above is
         // orthonormal to the old basis, hence to X: it moves next to them
@@ -675,6 +694,7 @@ kl_status EigRun::rr_step() {
         for (int i = 0; i < kk; ++i) S.H[size_t(i) * S.mmax + i] = theta[i];
         S.restarts += 1;
         last_add = add_next;
+        pending_keeps_krylov = true;
         set_pending(precision, S.V + int64_t(kk) * N, S.AV + int64_t(kk) * N, add_next, AFTER_EXPAND);
         pending_done = spec_apply;
         return KL_OK;
@@ -688,9 +708,12 @@ kl_status EigRun::rr_step() {
         std::fill(S.H.begin(), S.H.end(), 0.0);
         for (int i = 0; i < kk; ++i) S.H[size_t(i) * S.mmax + i] = theta[i];
         S.restarts += 1;
-        // residuals of the kept vectors are in W (residual_kernel above)
+        // residuals of the kept vectors are in W (residual_kernel above); the restarted
+        // basis keeps the Arnoldi relation if the old one had it (the residuals then
+        // span at most one block)
         if (add <= 0) { done = true; return KL_OK; }
         if ((st = S.orth_into_basis(S.W, kk, add, rng)) != KL_OK) return st;
+        pending_keeps_krylov = true;
     } else {
         // ---- block Krylov expansion from the newest block of AV --------------------
         if (add <= 0) { done = true; return KL_OK; }
@@ -698,6 +721,7 @@ kl_status EigRun::rr_step() {
                                          hipMemcpyDeviceToDevice, S.s), "copy block")) != KL_OK)
             return st;
         if ((st = S.orth_into_basis(S.W, S.last, add, rng)) != KL_OK) return st;
+        pending_keeps_krylov = add == S.last && !S.last_refilled;
     }
     last_add = add;
     set_pending(precision, S.V + int64_t(S.m) * N, S.AV + int64_t(S.m) * N, add, AFTER_EXPAND);
