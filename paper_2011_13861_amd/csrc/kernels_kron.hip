@@ -170,24 +170,27 @@ __global__ __launch_bounds__(kThreads) void mode_batch_kernel(const ModeArgs *__
 // o1 = 16 b.. and all of o2, so that no output value is computed twice; the workgroups
 // of one slab are nslab apart in launch order, which keeps them on one XCD (one L2)
 // when nslab is a multiple of 8.
-//  * Each wave first issues the loads of its matrix-core A operands: the 16 rows of D1
-//    of its block (the same for all of its phase-1 tiles) and the D2 rows of its first
-//    phase-2 tile, so that they arrive while the slab is staged.  They are read from the
-//    transposed factors, where the 16 lanes of one contraction index are 16 consecutive
-//    values (4 cache lines per load instead of 16).
+//  * The D1 rows of the block (the A operand of every phase-1 tile, the same for all
+//    waves) are staged once in LDS, read from the transposed factor where the 16 values
+//    of one contraction index are consecutive; each wave loads the D2 rows of its first
+//    phase-2 tile into registers.  Both are issued before the slab, so that they arrive
+//    while it is staged.
 //  * Phase 0 stages the whole input slab in LDS with coalesced loads, 8 entries and up
 //    to 8 partial inputs per thread in flight: the `nsplit` partials (stride in_split)
 //    are added in split order and the sum scaled by in_scale in_w[p] when in_w is set
-//    (the stage-5 split sums and sigma^2 J taken on the way in).
+//    (the stage-5 split sums and sigma^2 J taken on the way in; the weights are loaded
+//    with the first partials, not after the sum).
 //  * Phase 1: 16 x 16 tiles of U on v_mfma_f64_16x16x4_f64, B = the slab from LDS;
 //    tile t of i2 per wave, round robin.
 //  * Phase 2: tiles of OUT^T (16 o2 x 16 o1), B = U from LDS; a lane's accumulators are
-//    16 consecutive o1 of one o2 (coalesced stores), times out_w[p] when set, converted
-//    to TOUT (BF16 with an optional low part).
-// NS: MFMA steps per contraction (4 NS >= nin1, nin2; chosen on the host in multiples of
-// 4, at most kMode2Steps): all loops have fixed trip counts and every load reads a
-// clamped, valid address whose value is then masked, so that the kernel has no
-// divergent branches.
+//    16 consecutive o1 of one o2 (coalesced stores), times out_w[p] when set (the weights
+//    of the first tile loaded at the start), converted to TOUT (BF16 with an optional low
+//    part).
+// NS: MFMA steps per contraction, ceil(max(nin1, nin2) / 4) <= kMode2Steps.  Every load
+// reads a clamped, valid address (a weight that is not given reads entry 0 of D1T) and
+// its value is masked where it is used, not where it is loaded: the kernel has no
+// branches around loads, which would make each load wait for its value before the next
+// one is issued.
 constexpr int kMode2Steps = 20;                            // largest NS (no spills)
 
 template <typename TIN, typename TOUT, int NS>
@@ -198,37 +201,62 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
     const int t2 = (n2 + 15) / 16;
     const int ldu = 16 * t2 + 1;
     double *sX = lds2;                                    // [i2][ldx]
-    double *sU = lds2 + n2 * ldx;                         // [16 o1][ldu]
+    double *sU = sX + n2 * ldx;                           // [16 o1][ldu]
+    double *sA = sU + 16 * ldu;                           // [i1 < 4 NS][16 o1]: D1 rows of the block
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
+    const int nt = blockDim.x;
     const uint32_t slab = blockIdx.x;
     const int ob = blockIdx.y;                            // block of 16 o1
     const uint32_t j = slab / uint32_t(g.Clo), c = slab - j * uint32_t(g.Clo);
     const int t2o = (m2 + 15) / 16;
-    // ---- A operands in flight while the slab is staged: the D1 rows of the block and
-    //      the D2 rows of this wave's first phase-2 tile ---------------------------------
-    double a1[NS], a2[NS];
-    {
-        // from the transposed factors: the 16 lanes of one index i read 16 consecutive o
-        const int o1 = ob * 16 + li, o2 = w * 16 + li;
-        const int o1c = min(o1, m1 - 1), o2c = min(o2, m2 - 1);
+    const int o1 = ob * 16 + li;                          // this lane's phase-2 o1 (and B column)
+    const int o1c = min(o1, m1 - 1);
+    const int64_t pslab = int64_t(m1) * m2 * c;
+    // ---- loads in flight while the slab is staged ----------------------------------------
+    // D1 rows of the block: entry q = 16 i + o of sA (i < 4 NS; rows past nin1 are zero)
+    constexpr int kA = 4;
+    constexpr int na = 64 * NS;
+    double av[kA];
 #pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            const int i = 4 * u + lk;
-            const double v1 = g.D1T[int64_t(min(i, n1 - 1)) * m1 + o1c];
-            const double v2 = g.D2T[int64_t(min(i, n2 - 1)) * m2 + o2c];
-            a1[u] = (i < n1 && o1 < m1) ? v1 : 0.0;
-            a2[u] = (i < n2 && o2 < m2) ? v2 : 0.0;
+    for (int u = 0; u < kA; ++u) {
+        const int q = threadIdx.x + u * nt, i = q >> 4, o = ob * 16 + (q & 15);
+        av[u] = g.D1T[int64_t(min(i, n1 - 1)) * m1 + min(o, m1 - 1)];
+    }
+    // D2 rows and output weights of this wave's first phase-2 tile (masked in phase 2).
+    // Loads that a wave does not need sit behind wave-uniform branches whose blocks do
+    // not use the values, so that nothing waits for them there.
+    const bool has_ow = g.out_w != nullptr;
+    const double *owp = has_ow ? g.out_w + pslab : g.D1T;
+    double a2[NS], ow[4];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) a2[u] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ow[r] = 1.0;
+    if (w < t2o) {
+        const int o2c = min(w * 16 + li, m2 - 1);
+#pragma unroll
+        for (int u = 0; u < NS; ++u) a2[u] = g.D2T[int64_t(min(4 * u + lk, n2 - 1)) * m2 + o2c];
+        if (has_ow) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                ow[r] = owp[int64_t(o1c) + int64_t(m1) * min(w * 16 + lk + 4 * r, m2 - 1)];
         }
     }
     // ---- phase 0: the input slab, split partials summed, into LDS ---------------------
+    // Lanes past the end of the slab read and write its last entry (the same value as
+    // the lane that owns it), so that no load or store sits behind a branch; one pass
+    // covers the slab in the common case and is then straight-line code.  The forms with
+    // and without input weights are separate branches (HW below), each with its own
+    // loads and uses.
     {
         const int64_t pbase = int64_t(n1) * n2 * c;        // point index of the slab's first entry
         const TIN *in = static_cast<const TIN *>(g.in) + pbase + g.in_ldj * int64_t(j);
-        const int ne = n1 * n2, nt = blockDim.x;
+        const double *inw = g.in_w + pbase;                // dereferenced only when in_w is set
+        const double wscale = g.in_scale;
+        const int ne = n1 * n2;
         const float rn1 = 1.0f / float(n1);
-        auto put = [&](int e, double x) {                  // e < ne
-            if (g.in_w) x *= g.in_scale * g.in_w[pbase + e];
+        auto put = [&](int e, double x) __attribute__((always_inline)) {                  // e < ne
             int i2 = int(float(e) * rn1);                  // e / n1 (e < 2^20: off by at most one)
             if (i2 * n1 > e) --i2;
             if ((i2 + 1) * n1 <= e) ++i2;
@@ -236,22 +264,41 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
         };
         if (g.nsplit == 1) {
             constexpr int kE = 12;
-            for (int e0 = threadIdx.x; e0 < ne; e0 += kE * nt) {
+            auto pass = [&](int e0, auto hw) __attribute__((always_inline)) {
+                constexpr bool HW = decltype(hw)::value;
+                double wv[kE];
                 TIN t[kE];
+                if constexpr (HW) {
+#pragma unroll
+                    for (int u = 0; u < kE; ++u) wv[u] = inw[min(e0 + u * nt, ne - 1)];
+                }
 #pragma unroll
                 for (int u = 0; u < kE; ++u) t[u] = in[min(e0 + u * nt, ne - 1)];
 #pragma unroll
-                for (int u = 0; u < kE; ++u)
-                    if (e0 + u * nt < ne) put(e0 + u * nt, double(t[u]));
-            }
+                for (int u = 0; u < kE; ++u) {
+                    double x = double(t[u]);
+                    if constexpr (HW) x *= wscale * wv[u];
+                    put(min(e0 + u * nt, ne - 1), x);
+                }
+            };
+            auto run = [&](auto hw) __attribute__((always_inline)) {
+                if (ne <= kE * nt) pass(int(threadIdx.x), hw);
+                else for (int e0 = threadIdx.x; e0 < ne; e0 += kE * nt) pass(e0, hw);
+            };
+            if (g.in_w) run(std::true_type{}); else run(std::false_type{});
         } else {
             constexpr int kE = 9, kQ = sizeof(TIN) == 4 ? 8 : 4;
             const uint32_t split = uint32_t(g.in_split);   // < 2^31 (checked on the host)
-            for (int e0 = threadIdx.x; e0 < ne; e0 += kE * nt) {
-                double v[kE];
+            auto pass = [&](int e0, bool one_group, auto hw) __attribute__((always_inline)) {
+                constexpr bool HW = decltype(hw)::value;
+                double wv[kE], v[kE];
+                if constexpr (HW) {
+#pragma unroll
+                    for (int u = 0; u < kE; ++u) wv[u] = inw[min(e0 + u * nt, ne - 1)];
+                }
 #pragma unroll
                 for (int u = 0; u < kE; ++u) v[u] = 0.0;
-                for (int q0 = 0; q0 < g.nsplit; q0 += kQ) {
+                auto group = [&](int q0) __attribute__((always_inline)) {
                     TIN t[kQ][kE];
 #pragma unroll
                     for (int q = 0; q < kQ; ++q)
@@ -262,12 +309,32 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
                     for (int q = 0; q < kQ; ++q)
 #pragma unroll
                         for (int u = 0; u < kE; ++u) v[u] += (q0 + q < g.nsplit) ? double(t[q][u]) : 0.0;
-                }
+                };
+                if (one_group) group(0);
+                else for (int q0 = 0; q0 < g.nsplit; q0 += kQ) group(q0);
 #pragma unroll
-                for (int u = 0; u < kE; ++u)
-                    if (e0 + u * nt < ne) put(e0 + u * nt, v[u]);
-            }
+                for (int u = 0; u < kE; ++u) {
+                    double x = v[u];
+                    if constexpr (HW) x *= wscale * wv[u];
+                    put(min(e0 + u * nt, ne - 1), x);
+                }
+            };
+            auto run = [&](auto hw) __attribute__((always_inline)) {
+                if (ne <= kE * nt && g.nsplit <= kQ) pass(int(threadIdx.x), true, hw);
+                else for (int e0 = threadIdx.x; e0 < ne; e0 += kE * nt) pass(e0, false, hw);
+            };
+            if (g.in_w) run(std::true_type{}); else run(std::false_type{});
         }
+    }
+#pragma unroll
+    for (int u = 0; u < kA; ++u) {
+        const int q = threadIdx.x + u * nt;
+        if (q < na) sA[q] = ((q >> 4) < n1 && ob * 16 + (q & 15) < m1) ? av[u] : 0.0;
+    }
+    for (int q = threadIdx.x + kA * nt; q < na; q += nt) {   // blocks of fewer than 8 waves
+        const int i = q >> 4, o = ob * 16 + (q & 15);
+        const double v = g.D1T[int64_t(min(i, n1 - 1)) * m1 + min(o, m1 - 1)];
+        sA[q] = (i < n1 && o < m1) ? v : 0.0;
     }
     __syncthreads();
     // ---- phase 1: U = D1[block] IN_s ----------------------------------------------------
@@ -280,34 +347,36 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
         doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < NS; ++u)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], col[min(4 * u + lk, n1 - 1)], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(4 * u + lk) * 16 + li], col[min(4 * u + lk, n1 - 1)],
+                                                      acc, 0, 0, 0);
         // acc[r] = U[o1 local lk + 4 r][i2 = t 16 + li]
 #pragma unroll
         for (int r = 0; r < 4; ++r) sU[(lk + 4 * r) * ldu + t * 16 + li] = acc[r];
     }
     __syncthreads();
     // ---- phase 2: OUT_s^T[o2][o1] = D2[o2][:] U[o1][:]^T --------------------------------
-    const int o1 = ob * 16 + li;                           // this lane's output o1 (and B column)
     TOUT *out = static_cast<TOUT *>(g.out);
-    const int64_t pslab = int64_t(m1) * m2 * c;
     const int64_t obase = pslab + g.out_ldj * int64_t(j);
     const double *urow = sU + li * ldu;
     for (int t = w; t < t2o; t += nw) {
-        if (t != w) {                                      // later tiles: their D2 rows
-            const int o2 = t * 16 + li, o2c = min(o2, m2 - 1);
+        if (t != w) {                                      // later tiles: their D2 rows and weights
+            const int o2c = min(t * 16 + li, m2 - 1);
 #pragma unroll
-            for (int u = 0; u < NS; ++u) {
-                const int i2 = 4 * u + lk;
-                const double v = g.D2T[int64_t(min(i2, n2 - 1)) * m2 + o2c];
-                a2[u] = (i2 < n2 && o2 < m2) ? v : 0.0;
+            for (int u = 0; u < NS; ++u) a2[u] = g.D2T[int64_t(min(4 * u + lk, n2 - 1)) * m2 + o2c];
+            if (has_ow) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    ow[r] = owp[int64_t(o1c) + int64_t(m1) * min(t * 16 + lk + 4 * r, m2 - 1)];
             }
         }
         // U columns past 16 t2 were not written: clamp to the last written one (the A
         // operand is zero past nin2)
+        const bool row_ok = t * 16 + li < m2;
         doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < NS; ++u)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[u], urow[min(4 * u + lk, 16 * t2 - 1)], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((row_ok && 4 * u + lk < n2) ? a2[u] : 0.0,
+                                                      urow[min(4 * u + lk, 16 * t2 - 1)], acc, 0, 0, 0);
         // acc[r] = OUT^T[o2 = t 16 + lk + 4 r][o1]
         if (o1 < m1) {
 #pragma unroll
@@ -315,9 +384,7 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
                 const int o2 = t * 16 + lk + 4 * r;
                 if (o2 < m2) {
                     const int64_t pl = int64_t(o1) + int64_t(m1) * o2;
-                    double v = acc[r];
-                    if (g.out_w) v *= g.out_w[pslab + pl];
-                    store_out<TOUT>(out, g.out_lo, obase + pl, v);
+                    store_out<TOUT>(out, g.out_lo, obase + pl, has_ow ? acc[r] * ow[r] : acc[r]);
                 }
             }
         }
@@ -425,10 +492,14 @@ void launch_mode(const ModeSpec &m, hipStream_t s) {
 #undef KL_MODE
 }
 
-// LDS bytes of mode2_kernel: the slab (nin2 rows of nin1 | 1) and U (16 rows of
-// 16 ceil(nin2 / 16) + 1), FP64.
+// MFMA steps of mode2_kernel: ceil(max(nin1, nin2) / 4)
+static int mode2_steps(int nin1, int nin2) { return (std::max(nin1, nin2) + 3) / 4; }
+
+// LDS bytes of mode2_kernel: the slab (nin2 rows of nin1 | 1), U (16 rows of
+// 16 ceil(nin2 / 16) + 1) and the D1 rows of the block (4 NS x 16), FP64.
 static size_t mode2_lds(int nin1, int nin2) {
-    return size_t(8) * (size_t(nin2) * size_t(nin1 | 1) + size_t(16) * size_t(16 * ((nin2 + 15) / 16) + 1));
+    return size_t(8) * (size_t(nin2) * size_t(nin1 | 1) + size_t(16) * size_t(16 * ((nin2 + 15) / 16) + 1) +
+                        size_t(64) * size_t(mode2_steps(nin1, nin2)));
 }
 
 bool mode2_fits(int nin1, int nin2, int nout1, int nout2, int64_t slabs) {
@@ -449,16 +520,17 @@ static void launch_mode2_ns(const Mode2Args &a, dim3 grid, int threads, size_t l
     hipLaunchKernelGGL((mode2_kernel<TI, TO, NS>), grid, dim3(threads), lds, s, a);
 }
 
+template <typename TI, typename TO, int NS>
+static void launch_mode2_steps(int steps, const Mode2Args &a, dim3 grid, int threads, size_t lds, hipStream_t s) {
+    if constexpr (NS < kMode2Steps) {
+        if (steps > NS) return launch_mode2_steps<TI, TO, NS + 1>(steps, a, grid, threads, lds, s);
+    }
+    launch_mode2_ns<TI, TO, NS>(a, grid, threads, lds, s);
+}
+
 template <typename TI, typename TO>
 static void launch_mode2_t(const Mode2Args &a, dim3 grid, int threads, size_t lds, hipStream_t s) {
-    const int steps = (std::max(a.nin1, a.nin2) + 3) / 4;
-    switch ((steps + 3) / 4) {
-    case 1: launch_mode2_ns<TI, TO, 4>(a, grid, threads, lds, s); break;
-    case 2: launch_mode2_ns<TI, TO, 8>(a, grid, threads, lds, s); break;
-    case 3: launch_mode2_ns<TI, TO, 12>(a, grid, threads, lds, s); break;
-    case 4: launch_mode2_ns<TI, TO, 16>(a, grid, threads, lds, s); break;
-    default: launch_mode2_ns<TI, TO, 20>(a, grid, threads, lds, s); break;
-    }
+    launch_mode2_steps<TI, TO, 1>(mode2_steps(a.nin1, a.nin2), a, grid, threads, lds, s);
 }
 
 void launch_mode2(const Mode2Args &a, bool in_f32, int out_kind, hipStream_t s) {
