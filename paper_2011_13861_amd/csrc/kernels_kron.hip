@@ -180,12 +180,15 @@ __global__ __launch_bounds__(kThreads) void mode_batch_kernel(const ModeArgs *__
 //    are added in split order and the sum scaled by in_scale in_w[p] when in_w is set
 //    (the stage-5 split sums and sigma^2 J taken on the way in; the weights are loaded
 //    with the first partials, not after the sum).
-//  * Phase 1: 16 x 16 tiles of U on v_mfma_f64_16x16x4_f64, B = the slab from LDS;
-//    tile t of i2 per wave, round robin.
+//  * Phase 1: 16 x 16 tiles of U on v_mfma_f64_16x16x4_f64, B = the slab from LDS.
 //  * Phase 2: tiles of OUT^T (16 o2 x 16 o1), B = U from LDS; a lane's accumulators are
 //    16 consecutive o1 of one o2 (coalesced stores), times out_w[p] when set (the weights
 //    of the first tile loaded at the start), converted to TOUT (BF16 with an optional low
 //    part).
+//  * Tiles go to waves round robin.  With 8 waves (two per SIMD) the T mod 4 tiles left
+//    after the largest multiple of 4 are cut into four quarters of the contraction on
+//    waves of four different SIMDs, so that every SIMD carries the same number of MFMA
+//    steps; the quarters' partial tiles meet in LDS and are added in quarter order.
 // NS: MFMA steps per contraction, ceil(max(nin1, nin2) / 4) <= kMode2Steps.  Every load
 // reads a clamped, valid address (a weight that is not given reads entry 0 of D1T) and
 // its value is masked where it is used, not where it is loaded: the kernel has no
@@ -202,7 +205,9 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
     const int ldu = 16 * t2 + 1;
     double *sX = lds2;                                    // [i2][ldx]
     double *sU = sX + n2 * ldx;                           // [16 o1][ldu]
-    double *sA = sU + 16 * ldu;                           // [i1 < 4 NS][16 o1]: D1 rows of the block
+    constexpr int NQ = (NS + 3) / 4;                      // MFMA steps of a quarter
+    double *sA = sU + 16 * ldu;                           // [i1 < 16 NQ][16 o1]: D1 rows of the block
+    double *sP = sA + 256 * NQ;                           // [4 R][256]: partial tiles of quarters
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int nt = blockDim.x;
@@ -210,13 +215,19 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
     const int ob = blockIdx.y;                            // block of 16 o1
     const uint32_t j = slab / uint32_t(g.Clo), c = slab - j * uint32_t(g.Clo);
     const int t2o = (m2 + 15) / 16;
+    // tiles of the two phases done whole (F) and in quarters (R = T mod 4, 8 waves only);
+    // quarter unit k < 4 R is quarter k mod 4 of tile F + k / 4, on wave (F + k) mod 8
+    const bool quarters = nw == 8;
+    const int R1 = quarters ? t2 % 4 : 0, F1 = t2 - R1;
+    const int R2 = quarters ? t2o % 4 : 0, F2 = t2o - R2;
+    const int kq1 = ((w - F1) % 8 + 8) % 8, kq2 = ((w - F2) % 8 + 8) % 8;   // first quarter units
     const int o1 = ob * 16 + li;                          // this lane's phase-2 o1 (and B column)
     const int o1c = min(o1, m1 - 1);
     const int64_t pslab = int64_t(m1) * m2 * c;
     // ---- loads in flight while the slab is staged ----------------------------------------
-    // D1 rows of the block: entry q = 16 i + o of sA (i < 4 NS; rows past nin1 are zero)
+    // D1 rows of the block: entry q = 16 i + o of sA (i < 16 NQ; rows past nin1 are zero)
     constexpr int kA = 4;
-    constexpr int na = 64 * NS;
+    constexpr int na = 256 * NQ;
     double av[kA];
 #pragma unroll
     for (int u = 0; u < kA; ++u) {
@@ -228,12 +239,15 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
     // not use the values, so that nothing waits for them there.
     const bool has_ow = g.out_w != nullptr;
     const double *owp = has_ow ? g.out_w + pslab : g.D1T;
-    double a2[NS], ow[4];
+    double a2[NS], ow[4], a2q[NQ], owr[2];
 #pragma unroll
     for (int u = 0; u < NS; ++u) a2[u] = 0.0;
 #pragma unroll
+    for (int u = 0; u < NQ; ++u) a2q[u] = 0.0;
+#pragma unroll
     for (int r = 0; r < 4; ++r) ow[r] = 1.0;
-    if (w < t2o) {
+    owr[0] = owr[1] = 1.0;
+    if (w < F2) {                                         // first whole tile
         const int o2c = min(w * 16 + li, m2 - 1);
 #pragma unroll
         for (int u = 0; u < NS; ++u) a2[u] = g.D2T[int64_t(min(4 * u + lk, n2 - 1)) * m2 + o2c];
@@ -241,6 +255,19 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 ow[r] = owp[int64_t(o1c) + int64_t(m1) * min(w * 16 + lk + 4 * r, m2 - 1)];
+        }
+    }
+    if (kq2 < 4 * R2) {                                   // first quarter unit
+        const int o2c = min((F2 + kq2 / 4) * 16 + li, m2 - 1), u0 = (kq2 % 4) * NQ;
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) a2q[u] = g.D2T[int64_t(min(4 * (u0 + u) + lk, n2 - 1)) * m2 + o2c];
+    }
+    if (has_ow && R2 > 0) {                               // weights of the quartered outputs this thread adds
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int idx = int(threadIdx.x) + m * nt, e = idx & 255;
+            const int o1r = min(ob * 16 + (e & 15), m1 - 1), o2r = min((F2 + (idx >> 8)) * 16 + (e >> 4), m2 - 1);
+            owr[m] = owp[int64_t(o1r) + int64_t(m1) * o2r];
         }
     }
     // ---- phase 0: the input slab, split partials summed, into LDS ---------------------
@@ -341,9 +368,8 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
     // B operands are read unmasked from clamped addresses: past nin1 the A operand is
     // zero, and columns i2 >= nin2 of U (finite, from clamped reads) meet zero A
     // operands in phase 2.
-    for (int t = w; t < t2; t += nw) {
-        const int i2 = t * 16 + li;                        // B operand column of this lane
-        const double *col = sX + min(i2, n2 - 1) * ldx;
+    for (int t = w; t < F1; t += nw) {
+        const double *col = sX + min(t * 16 + li, n2 - 1) * ldx;   // B operand column i2 of this lane
         doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < NS; ++u)
@@ -353,12 +379,34 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) sU[(lk + 4 * r) * ldu + t * 16 + li] = acc[r];
     }
+    for (int k = kq1; k < 4 * R1; k += 8) {
+        const int t = F1 + k / 4, u0 = (k % 4) * NQ;
+        const double *col = sX + min(t * 16 + li, n2 - 1) * ldx;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int i = 4 * (u0 + u) + lk;                 // < 16 NQ: rows of sA past nin1 are zero
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[i * 16 + li], col[min(i, n1 - 1)], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sP[k * 256 + lane * 4 + r] = acc[r];
+    }
     __syncthreads();
+    if (R1 > 0) {
+        for (int idx = threadIdx.x; idx < R1 * 256; idx += nt) {
+            const int rt = idx >> 8, e = idx & 255, ol = e >> 4, il = e & 15;
+            const double *p = sP + rt * 1024 + (il + 16 * (ol & 3)) * 4 + (ol >> 2);
+            sU[ol * ldu + (F1 + rt) * 16 + il] = ((p[0] + p[256]) + p[512]) + p[768];
+        }
+        __syncthreads();
+    }
     // ---- phase 2: OUT_s^T[o2][o1] = D2[o2][:] U[o1][:]^T --------------------------------
     TOUT *out = static_cast<TOUT *>(g.out);
     const int64_t obase = pslab + g.out_ldj * int64_t(j);
     const double *urow = sU + li * ldu;
-    for (int t = w; t < t2o; t += nw) {
+    // U columns past 16 t2 were not written: B reads clamp to the last written one (the A
+    // operand is zero past nin2)
+    for (int t = w; t < F2; t += nw) {
         if (t != w) {                                      // later tiles: their D2 rows and weights
             const int o2c = min(t * 16 + li, m2 - 1);
 #pragma unroll
@@ -369,8 +417,6 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
                     ow[r] = owp[int64_t(o1c) + int64_t(m1) * min(t * 16 + lk + 4 * r, m2 - 1)];
             }
         }
-        // U columns past 16 t2 were not written: clamp to the last written one (the A
-        // operand is zero past nin2)
         const bool row_ok = t * 16 + li < m2;
         doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -386,6 +432,40 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
                     const int64_t pl = int64_t(o1) + int64_t(m1) * o2;
                     store_out<TOUT>(out, g.out_lo, obase + pl, has_ow ? acc[r] * ow[r] : acc[r]);
                 }
+            }
+        }
+    }
+    for (int k = kq2; k < 4 * R2; k += 8) {
+        const int t = F2 + k / 4, u0 = (k % 4) * NQ;
+        if (k != kq2) {                                    // later quarter units: their D2 rows
+            const int o2c = min(t * 16 + li, m2 - 1);
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) a2q[u] = g.D2T[int64_t(min(4 * (u0 + u) + lk, n2 - 1)) * m2 + o2c];
+        }
+        const bool row_ok = t * 16 + li < m2;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int i = 4 * (u0 + u) + lk;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((row_ok && i < n2) ? a2q[u] : 0.0,
+                                                      urow[min(i, 16 * t2 - 1)], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sP[k * 256 + lane * 4 + r] = acc[r];
+    }
+    if (R2 > 0) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int idx = int(threadIdx.x) + m * nt;
+            if (idx < R2 * 256) {
+                // entry e: o2 = 16 (F2 + rt) + (e >> 4), o1 = 16 ob + (e & 15)
+                const int rt = idx >> 8, e = idx & 255, ol = e >> 4, il = e & 15;
+                const double *p = sP + rt * 1024 + (il + 16 * (ol & 3)) * 4 + (ol >> 2);
+                const double v = ((p[0] + p[256]) + p[512]) + p[768];
+                const int o1e = ob * 16 + il, o2e = (F2 + rt) * 16 + ol;
+                if (o1e < m1 && o2e < m2)
+                    store_out<TOUT>(out, g.out_lo, obase + int64_t(o1e) + int64_t(m1) * o2e, has_ow ? v * owr[m] : v);
             }
         }
     }
@@ -495,17 +575,27 @@ void launch_mode(const ModeSpec &m, hipStream_t s) {
 // MFMA steps of mode2_kernel: ceil(max(nin1, nin2) / 4)
 static int mode2_steps(int nin1, int nin2) { return (std::max(nin1, nin2) + 3) / 4; }
 
+// Waves of a mode2_kernel block: 8 for slabs of more than 1024 values (one pass of the
+// staging loads); small slabs take one wave per 16-wide tile of the larger phase.
+static int mode2_waves(int nin1, int nin2, int nout2) {
+    const int tiles = std::max((nin2 + 15) / 16, (nout2 + 15) / 16);
+    return nin1 * nin2 > 1024 ? 8 : std::min(8, std::max(2, tiles));
+}
+
 // LDS bytes of mode2_kernel: the slab (nin2 rows of nin1 | 1), U (16 rows of
-// 16 ceil(nin2 / 16) + 1) and the D1 rows of the block (4 NS x 16), FP64.
-static size_t mode2_lds(int nin1, int nin2) {
+// 16 ceil(nin2 / 16) + 1), the D1 rows of the block (16 NQ x 16, NQ = ceil(NS / 4)) and,
+// with 8 waves, the partial tiles of up to 3 quartered tiles (12 x 256), FP64.
+static size_t mode2_lds(int nin1, int nin2, int nout2) {
+    const size_t nq = size_t((mode2_steps(nin1, nin2) + 3) / 4);
+    const size_t parts = mode2_waves(nin1, nin2, nout2) == 8 ? size_t(12 * 256) : 0;
     return size_t(8) * (size_t(nin2) * size_t(nin1 | 1) + size_t(16) * size_t(16 * ((nin2 + 15) / 16) + 1) +
-                        size_t(64) * size_t(mode2_steps(nin1, nin2)));
+                        size_t(256) * nq + parts);
 }
 
 bool mode2_fits(int nin1, int nin2, int nout1, int nout2, int64_t slabs) {
     return nin1 >= 1 && nin2 >= 1 && nout1 >= 1 && nout2 >= 1 && slabs >= 1 && slabs < (int64_t(1) << 31) &&
            nin1 <= 4 * kMode2Steps && nin2 <= 4 * kMode2Steps && (nout1 + 15) / 16 <= 65535 &&
-           mode2_lds(nin1, nin2) <= size_t(kMode2MaxLds);
+           mode2_lds(nin1, nin2, nout2) <= size_t(kMode2MaxLds);
 }
 
 template <typename TI, typename TO, int NS>
@@ -534,12 +624,9 @@ static void launch_mode2_t(const Mode2Args &a, dim3 grid, int threads, size_t ld
 }
 
 void launch_mode2(const Mode2Args &a, bool in_f32, int out_kind, hipStream_t s) {
-    // 8 waves for slabs of more than 1024 values (one pass of the staging loads); small
-    // slabs take one wave per 16-wide tile of the larger phase
-    const int tiles = std::max((a.nin2 + 15) / 16, (a.nout2 + 15) / 16);
-    const int waves = a.nin1 * a.nin2 > 1024 ? 8 : std::min(8, std::max(2, tiles));
+    const int waves = mode2_waves(a.nin1, a.nin2, a.nout2);
     const dim3 grid(unsigned(int64_t(a.Clo) * a.nvec), unsigned((a.nout1 + 15) / 16));
-    const size_t lds = mode2_lds(a.nin1, a.nin2);
+    const size_t lds = mode2_lds(a.nin1, a.nin2, a.nout2);
     if (in_f32) launch_mode2_t<float, double>(a, grid, 64 * waves, lds, s);
     else if (out_kind == 1) launch_mode2_t<double, float>(a, grid, 64 * waves, lds, s);
     else if (out_kind == 2) launch_mode2_t<double, __bf16>(a, grid, 64 * waves, lds, s);
