@@ -370,11 +370,17 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
     // operands in phase 2.
     for (int t = w; t < F1; t += nw) {
         const double *col = sX + min(t * 16 + li, n2 - 1) * ldx;   // B operand column i2 of this lane
+        // all operands of the chain are read first, so that LDS latency is paid once
+        double opa[NS], opb[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            opa[u] = sA[(4 * u + lk) * 16 + li];
+            opb[u] = col[min(4 * u + lk, n1 - 1)];
+        }
+        __builtin_amdgcn_sched_barrier(0);
         doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int u = 0; u < NS; ++u)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(4 * u + lk) * 16 + li], col[min(4 * u + lk, n1 - 1)],
-                                                      acc, 0, 0, 0);
+        for (int u = 0; u < NS; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(opa[u], opb[u], acc, 0, 0, 0);
         // acc[r] = U[o1 local lk + 4 r][i2 = t 16 + li]
 #pragma unroll
         for (int r = 0; r < 4; ++r) sU[(lk + 4 * r) * ldu + t * 16 + li] = acc[r];
@@ -418,11 +424,14 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
             }
         }
         const bool row_ok = t * 16 + li < m2;
+        double opb[NS];                                    // B operands read first (see phase 1)
+#pragma unroll
+        for (int u = 0; u < NS; ++u) opb[u] = urow[min(4 * u + lk, 16 * t2 - 1)];
+        __builtin_amdgcn_sched_barrier(0);
         doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < NS; ++u)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((row_ok && 4 * u + lk < n2) ? a2[u] : 0.0,
-                                                      urow[min(4 * u + lk, 16 * t2 - 1)], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((row_ok && 4 * u + lk < n2) ? a2[u] : 0.0, opb[u], acc, 0, 0, 0);
         // acc[r] = OUT^T[o2 = t 16 + lk + 4 r][o1]
         if (o1 < m1) {
 #pragma unroll
