@@ -128,7 +128,8 @@ def batch_section(reps=20):
     """Config 4: 64 uneven 2D problems (seed 1127).  The batched apply (one graph replay
     of 32 columns per problem, autotuned tiles) against the same 64 applies issued one
     problem after the other; then 20 eigenpairs of every problem at 1e-6, batched
-    (FP32 with FP64 refinement) against 64 sequential kl_eigs calls."""
+    (FP32 with FP64 refinement, median of three runs: the solve is bound by host threads
+    and varies from run to run) against 64 sequential kl_eigs calls."""
     import numpy as np
     import torch
 
@@ -172,11 +173,14 @@ def batch_section(reps=20):
         out["apply_" + prec] = {"batched_ms": t_b * 1e3, "pair_evals_per_s": pairs / t_b, "rb": rb, "lchunk": lc,
                                 "sequential_ms": t_s * 1e3, "speedup": t_s / t_b}
     B.eigs(20, precision="f32", block=32, tol=1e-6)          # warm (solver buffers, handles)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    ev, _, reps_b = B.eigs(20, precision="f32", block=32, tol=1e-6)
-    torch.cuda.synchronize()
-    t_eb = time.perf_counter() - t
+    t_ebs = []                                               # host-thread bound: median of three
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ev, _, reps_b = B.eigs(20, precision="f32", block=32, tol=1e-6)
+        torch.cuda.synchronize()
+        t_ebs.append(time.perf_counter() - t)
+    t_eb = float(np.median(t_ebs))
     seq = {}
     for prec in ("f32", "f64"):
         for G in singles[:2]:
@@ -187,7 +191,7 @@ def batch_section(reps=20):
             G.eigs(20, precision=prec, block=32, tol=1e-6)
         torch.cuda.synchronize()
         seq[prec] = (time.perf_counter() - t) * 1e3
-    out["eigs_k20"] = {"batched_f32_refined_ms": t_eb * 1e3,
+    out["eigs_k20"] = {"batched_f32_refined_ms": t_eb * 1e3, "batched_runs_ms": [t * 1e3 for t in t_ebs],
                        "all_converged": all(r["converged"] == 20 for r in reps_b),
                        "sequential_f32_refined_ms": seq["f32"], "sequential_f64_ms": seq["f64"],
                        "speedup_vs_sequential_f64": seq["f64"] / (t_eb * 1e3)}
