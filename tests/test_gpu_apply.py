@@ -210,9 +210,18 @@ def test_stage5_tile_settings(prec, rb, ns):
 
 
 FUSE_CASES = [s for s in SMALL if s[1]["dim"] >= 2] + [
+    # 73 x 19 slab: 8 waves, two leftover tiles of 16 in each phase cut into quarters
     ("wide_2d", {"dim": 2, "degree": [3, 2], "nelem": [70, 17], "map": {"kind": "identity"},
                  "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.3, 0.6]}}),
+    # 40 x 40: three leftover tiles per phase (12 quarters, two on some waves)
+    ("quarters_r3", {"dim": 2, "degree": [2, 2], "nelem": [38, 38], "map": {"kind": "identity"},
+                     "cov": {"kind": "sqexp", "sigma2": 1.0, "corr_len": [0.4, 0.4]}}),
+    # 77 x 80: the longest contraction (20 MFMA steps), four whole tiles and one in
+    # quarters, slab staged in more than one pass with and without split partials
+    ("big_slab", {"dim": 2, "degree": [3, 3], "nelem": [74, 77], "map": {"kind": "annulus_polar", "r0": 1.0, "r1": 2.0},
+                  "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.5, 0.5]}}),
 ]
+_FUSE_REF = {}
 
 
 @pytest.mark.parametrize("precision", PRECS)
@@ -220,14 +229,17 @@ FUSE_CASES = [s for s in SMALL if s[1]["dim"] >= 2] + [
 def test_fused_directions_match_oracle_and_per_direction_form(name, desc, precision):
     """The fused pair of directions (one launch per side, the backward one adding the
     stage-5 split partials) against the oracle and against the per-direction launches,
-    with the split count forced to 1 (stage 5 writes the scaled output) and to 3."""
-    P = operator.Problem(desc)
+    with the split count forced to 1 (stage 5 writes the scaled output), 3 and 9 (more
+    partials than the backward launch loads in one group)."""
     G = kl.Problem(desc)
     assert G.apply_config(True), name
-    V = workloads.random_block(P.N, 33, seed=21)       # a full 32-column block and a ragged one
-    ref = P.apply(V)
+    if name not in _FUSE_REF:
+        P = operator.Problem(desc)
+        V = workloads.random_block(P.N, 33, seed=21)   # a full 32-column block and a ragged one
+        _FUSE_REF[name] = (V, P.apply(V))
+    V, ref = _FUSE_REF[name]
     tol = TOL[precision]
-    for ns in (1, 3):
+    for ns in (1, 3, 9):
         G.stage5_config(precision, nsplit=ns)
         G.apply_config(True)
         fused = _gpu_apply(G, V, precision)
