@@ -50,23 +50,72 @@ __device__ __forceinline__ float gamma_f32(const float *xk, const float *xl) {
     }
 }
 
+// FP64 exponential and square root for the arguments of the covariance kernels only
+// (exp of a finite x <= 0, sqrt of a finite a >= 0 that is zero or a normal number),
+// without the range and special-value handling of the general library functions.
+//  * exp: Cody-Waite reduction x = n ln2 + r, |r| <= ln2 / 2, with ln2 split into a high
+//    part of 32 significant bits (n ln2_hi is exact for |n| < 2^21; below that the result
+//    underflows to zero anyway) and the rounded remainder; e^r by a polynomial of degree
+//    11 (below); scaling by 2^n.
+//  * sqrt: Goldschmidt iteration from the hardware reciprocal square root (two coupled
+//    steps for s -> sqrt(a), h -> 1 / (2 sqrt(a))), then one Newton correction of s;
+//    sqrt(0) = 0 is selected explicitly (the reciprocal square root of 0 is infinite).
+__device__ __forceinline__ double exp_nonpos(double x) {
+    constexpr double kLog2e = 1.4426950408889634;
+    constexpr double kLn2Hi = 0x1.62e42fee00000p-1, kLn2Lo = 0x1.a39ef35793c76p-33;
+    const double n = __builtin_rint(x * kLog2e);
+    double r = fma(-n, kLn2Hi, x);
+    r = fma(-n, kLn2Lo, r);
+    // degree-11 interpolant of e^r at the 12 Chebyshev nodes of [-ln2/2, ln2/2]
+    // (coefficients solved in exact rational arithmetic from 80-digit values of e^r, then
+    // rounded; interpolation error below 5e-18, Horner evaluation below one ulp);
+    // exp_poly.py beside this file regenerates them and the ln2 split
+    double p = 2.5110037721946562e-08;
+    p = fma(p, r, 2.7632639789868395e-07);
+    p = fma(p, r, 2.7557240918265525e-06);
+    p = fma(p, r, 2.480148548192088e-05);
+    p = fma(p, r, 0.00019841269890047406);
+    p = fma(p, r, 0.0013888888952315155);
+    p = fma(p, r, 0.008333333333319601);
+    p = fma(p, r, 0.04166666666648809);
+    p = fma(p, r, 0.1666666666666668);
+    p = fma(p, r, 0.5000000000000019);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return __builtin_ldexp(p, int(n));
+}
+
+__device__ __forceinline__ double sqrt_nonneg(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double s = a * y, h = 0.5 * y;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-s, h, 0.5);
+        s = fma(s, e, s);
+        h = fma(h, e, h);
+    }
+    const double d = fma(-s, s, a);
+    s = fma(d, h, s);
+    return a == 0.0 ? 0.0 : s;
+}
+
 template <int KIND, int D>
 __device__ __forceinline__ double gamma_f64(const double *xk, const double *xl) {
     if constexpr (KIND == KL_COV_EXP) {
         double r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) { double t = xk[k] - xl[k]; r2 = fma(t, t, r2); }
-        return exp(-sqrt(r2));
+        return exp_nonpos(-sqrt_nonneg(r2));
     } else if constexpr (KIND == KL_COV_SQEXP) {
         double r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) { double t = xk[k] - xl[k]; r2 = fma(t, t, r2); }
-        return exp(-r2);
+        return exp_nonpos(-r2);
     } else if constexpr (KIND == KL_COV_EXP_L1) {
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s += fabs(xk[k] - xl[k]);
-        return exp(-s);
+        return exp_nonpos(-s);
     } else if constexpr (KIND == KL_COV_CONST) {
         return 1.0;
     } else {
