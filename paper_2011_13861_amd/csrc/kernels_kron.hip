@@ -316,8 +316,11 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
         } else {
             constexpr int kE = 9, kQ = sizeof(TIN) == 4 ? 8 : 4;
             const uint32_t split = uint32_t(g.in_split);   // < 2^31 (checked on the host)
-            auto pass = [&](int e0, bool one_group, auto hw) __attribute__((always_inline)) {
+            // NQ > 0: exactly NQ partials in one group (no clamped duplicate loads);
+            // NQ = 0: groups of kQ, the last one clamped and masked
+            auto pass = [&](int e0, auto nq, auto hw) __attribute__((always_inline)) {
                 constexpr bool HW = decltype(hw)::value;
+                constexpr int NQ = decltype(nq)::value;
                 double wv[kE], v[kE];
                 if constexpr (HW) {
 #pragma unroll
@@ -325,20 +328,30 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
                 }
 #pragma unroll
                 for (int u = 0; u < kE; ++u) v[u] = 0.0;
-                auto group = [&](int q0) __attribute__((always_inline)) {
-                    TIN t[kQ][kE];
+                if constexpr (NQ > 0) {
+                    TIN t[NQ][kE];
 #pragma unroll
-                    for (int q = 0; q < kQ; ++q)
+                    for (int q = 0; q < NQ; ++q)
 #pragma unroll
-                        for (int u = 0; u < kE; ++u)
-                            t[q][u] = in[uint32_t(min(q0 + q, g.nsplit - 1)) * split + uint32_t(min(e0 + u * nt, ne - 1))];
+                        for (int u = 0; u < kE; ++u) t[q][u] = in[uint32_t(q) * split + uint32_t(min(e0 + u * nt, ne - 1))];
 #pragma unroll
-                    for (int q = 0; q < kQ; ++q)
+                    for (int q = 0; q < NQ; ++q)
 #pragma unroll
-                        for (int u = 0; u < kE; ++u) v[u] += (q0 + q < g.nsplit) ? double(t[q][u]) : 0.0;
-                };
-                if (one_group) group(0);
-                else for (int q0 = 0; q0 < g.nsplit; q0 += kQ) group(q0);
+                        for (int u = 0; u < kE; ++u) v[u] += double(t[q][u]);
+                } else {
+                    for (int q0 = 0; q0 < g.nsplit; q0 += kQ) {
+                        TIN t[kQ][kE];
+#pragma unroll
+                        for (int q = 0; q < kQ; ++q)
+#pragma unroll
+                            for (int u = 0; u < kE; ++u)
+                                t[q][u] = in[uint32_t(min(q0 + q, g.nsplit - 1)) * split + uint32_t(min(e0 + u * nt, ne - 1))];
+#pragma unroll
+                        for (int q = 0; q < kQ; ++q)
+#pragma unroll
+                            for (int u = 0; u < kE; ++u) v[u] += (q0 + q < g.nsplit) ? double(t[q][u]) : 0.0;
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < kE; ++u) {
                     double x = v[u];
@@ -346,9 +359,28 @@ __global__ __launch_bounds__(512) void mode2_kernel(Mode2Args g) {
                     put(min(e0 + u * nt, ne - 1), x);
                 }
             };
+            auto one = [&](auto nq, auto hw) __attribute__((always_inline)) { pass(int(threadIdx.x), nq, hw); };
             auto run = [&](auto hw) __attribute__((always_inline)) {
-                if (ne <= kE * nt && g.nsplit <= kQ) pass(int(threadIdx.x), true, hw);
-                else for (int e0 = threadIdx.x; e0 < ne; e0 += kE * nt) pass(e0, false, hw);
+                using std::integral_constant;
+                if (ne <= kE * nt && g.nsplit <= kQ) {
+                    switch (g.nsplit) {                        // 2..kQ (nsplit 1 takes the branch above)
+                    case 2: one(integral_constant<int, 2>{}, hw); break;
+                    case 3: one(integral_constant<int, 3>{}, hw); break;
+                    case 4: one(integral_constant<int, 4>{}, hw); break;
+                    default:
+                        if constexpr (kQ > 4) {
+                            switch (g.nsplit) {
+                            case 5: one(integral_constant<int, 5>{}, hw); break;
+                            case 6: one(integral_constant<int, 6>{}, hw); break;
+                            case 7: one(integral_constant<int, 7>{}, hw); break;
+                            default: one(integral_constant<int, kQ>{}, hw); break;
+                            }
+                        }
+                        break;
+                    }
+                } else {
+                    for (int e0 = threadIdx.x; e0 < ne; e0 += kE * nt) pass(e0, integral_constant<int, 0>{}, hw);
+                }
             };
             if (g.in_w) run(std::true_type{}); else run(std::false_type{});
         }
