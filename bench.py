@@ -222,7 +222,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+        print("bench.py: the library runs on one GPU (it has no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -2,7 +2,7 @@
 against the plain random start, on the 48 x 48 cubic quarter annulus with parameters
 drawn as L ~ logU[0.1, 2], a ~ logU[0.5, 2], flag ~ B(1/2).
 
-The judge of the prediction's error is the oracle: residuals of the Rayleigh-Ritz
+The prediction's error is measured by the oracle: residuals of the Rayleigh-Ritz
 vectors of the predicted block under the oracle operator.  The gain test trains on a
 reduced set (300 draws of the training seed) to keep the test short.
 """
