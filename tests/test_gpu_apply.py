@@ -116,6 +116,47 @@ def test_full_size_config2_apply():
         assert err <= TOL[prec], (prec, err)
 
 
+def test_full_size_config5_apply():
+    """Config 5 (48x48 cubic quarter annulus, sqexp L = 0.5, the warm-start workload) at
+    full size, 32 vectors, every precision."""
+    desc = workloads.config("c5")[0]
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    V = workloads.random_block(P.N, 32, seed=6)
+    ref = P.apply(V)
+    for prec in PRECS:
+        out = _gpu_apply(G, V, prec)
+        err = _rel_max(out, ref) if prec == "f64" else _rel_fro(out, ref)
+        assert err <= TOL[prec], (prec, err)
+
+
+# Correlation lengths far below the point spacing (all but the nearest kernel entries
+# underflow: exponents down to about -10^5) and far above the domain (entries within 1e-4
+# of 1): both ends of the argument range of the FP64 exponential of the stage-5 kernels.
+EXTREME = [
+    ("tiny_ell_sqexp", {"dim": 2, "degree": [2, 2], "nelem": [20, 14],
+                        "map": {"kind": "annulus_polar", "r0": 1.0, "r1": 2.0},
+                        "cov": {"kind": "sqexp", "sigma2": 1.0, "corr_len": [0.01, 0.01]}}),
+    ("tiny_ell_exp3d", {"dim": 3, "degree": [1, 1, 1], "nelem": [8, 7, 6], "map": {"kind": "identity"},
+                        "cov": {"kind": "exp", "sigma2": 2.0, "corr_len": [0.002, 0.003, 0.002]}}),
+    ("huge_ell_exp", {"dim": 2, "degree": [2, 3], "nelem": [11, 9], "map": {"kind": "identity"},
+                      "cov": {"kind": "exp", "sigma2": 0.5, "corr_len": [300.0, 150.0]}}),
+]
+
+
+@pytest.mark.parametrize("name,desc", EXTREME, ids=[e[0] for e in EXTREME])
+def test_extreme_correlation_lengths(name, desc):
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    V = workloads.random_block(P.N, 32, seed=8)
+    ref = P.apply(V)
+    for prec in PRECS:
+        out = _gpu_apply(G, V, prec)
+        assert np.all(np.isfinite(out)), (name, prec)
+        err = _rel_max(out, ref) if prec == "f64" else _rel_fro(out, ref)
+        assert err <= TOL[prec], (name, prec, err)
+
+
 def test_full_size_config3_apply_two_columns():
     """Config 3 (24^3 perturbed cube, exp L = 0.5) at full size: the whole apply (fused
     first two directions, third direction, stage 5, backward) on two columns against the
