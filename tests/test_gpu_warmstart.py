@@ -62,7 +62,7 @@ def test_training_converges(trained):
     assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
 
 
-def test_prediction_error_judged_by_oracle(trained):
+def test_prediction_error_measured_by_oracle(trained):
     """Rayleigh-Ritz on the predicted block under the oracle operator: relative
     residuals of the leading Ritz pairs are far below those of a random block."""
     G, ws, _ = trained
