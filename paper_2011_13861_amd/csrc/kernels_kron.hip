@@ -40,16 +40,26 @@ __device__ __forceinline__ void store_out(TOUT *out, void *out_lo, int64_t addr,
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+// The batched kernels read their pointers from a device table, so the compiler cannot tell
+// that they point to global memory and would use flat loads, which also count against the
+// counter that scalar loads wait on (a scalar argument load then waits for every load in
+// flight).  Loads through these views are global loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *global_view(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
 // One wave per 16 x 16 output tile on v_mfma_f64_16x16x4_f64, operands loaded straight
-// from memory into registers (all loads of a wave are issued before the first MFMA), no
-// LDS and no barriers.  Lane layout: A[i][k] and B[k][j] sit in lane (i or j) + 16 k;
+// from memory into registers (all loads of a chunk are issued before the first of its
+// MFMAs), no LDS and no barriers.  Lane layout: A[i][k] and B[k][j] sit in lane (i or j) + 16 k;
 // accumulator r of lane L holds C[(L >> 4) + 4 r][L & 15].
 //  * First direction (A == 1): C = IN D^T  (16 rows x 16 o): A = IN[row][i], B = D^T[i][o];
 //    a lane of the result holds 16 consecutive o of one row -> coalesced stores.
 //  * Later directions: C = D IN^T (16 o x 16 rows): A = D[o][i], B = IN[row][i]; a lane
 //    holds 16 consecutive rows (consecutive a) of one o -> coalesced stores.
-// The contraction index is processed in chunks of 64 (16 MFMA steps).
-constexpr int kChunk = 16;                 // MFMA steps per operand batch (64 indices)
+// The contraction index is processed in chunks of 32 (8 MFMA steps: operand registers
+// small enough for four waves per SIMD, which these latency-bound tiles need).
+constexpr int kChunk = 8;                  // MFMA steps per operand batch (32 indices)
 
 template <bool FIRST, typename TIN, typename TOUT>
 __device__ __forceinline__ void mode_tile(const ModeArgs &g, int64_t tile) {
@@ -79,59 +89,93 @@ __device__ __forceinline__ void mode_tile(const ModeArgs &g, int64_t tile) {
     const int64_t bin = pin + g.in_ldj * int64_t(rj);
     const int o_l = ot * 16 + li;                  // this lane's o (operand index li)
     const bool ook = o_l < nout;
+    const int o_lc = min(o_l, nout - 1);
     const TIN *in = static_cast<const TIN *>(g.in);
-    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int kc = 0; kc < nin; kc += 4 * kChunk) {
-        double xa[kChunk], xb[kChunk];
-#pragma unroll
-        for (int s = 0; s < kChunk; ++s) {
-            const int i = kc + 4 * s + lk;
-            double vin = 0.0, vd = 0.0;
-            if (i < nin) {
-                if (rok) {
-                    vin = double(in[bin + g.A * i]);
-                    if (g.in_w) vin *= g.in_scale * g.in_w[pin + g.A * i];
-                }
-                if (ook) vd = g.D[int64_t(o_l) * nin + i];
-            }
-            if (FIRST) { xa[s] = vin; xb[s] = vd; }
-            else { xa[s] = vd; xb[s] = vin; }
-        }
-#pragma unroll
-        for (int s = 0; s < kChunk; ++s)
-            if (kc + 4 * s < nin)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], xb[s], acc, 0, 0, 0);
-    }
-    // ---- store: C[(lane >> 4) + 4 q][lane & 15] --------------------------------------
-    TOUT *out = static_cast<TOUT *>(g.out);
+    const bool has_w = g.in_w != nullptr, has_ow = g.out_w != nullptr;
+    // output positions of this lane's four accumulators, and their weights (loaded here,
+    // with the operands, not at the stores)
+    int64_t pq[4], jq[4];
+    bool okq[4];
     if (FIRST) {
         // rows rt 16 + lk + 4 q (A == 1): split the first one, then step by 4
         uint32_t rr = rt * 16 + lk;
         uint32_t j = rr / Clo, c = rr - j * Clo;
-        const int o = ot * 16 + li;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (rr < nrows && o < nout) {
-                const int64_t p = int64_t(o) + int64_t(nout) * c;
-                double v = acc[q];
-                if (g.out_w) v *= g.out_w[p];
-                store_out<TOUT>(out, g.out_lo, p + g.out_ldj * int64_t(j), v);
-            }
+            okq[q] = rr < nrows && o_l < nout;
+            pq[q] = int64_t(o_lc) + int64_t(nout) * (okq[q] ? c : 0);
+            jq[q] = okq[q] ? j : 0;
             rr += 4;
             c += 4;
             while (c >= Clo) { c -= Clo; ++j; }
         }
-    } else if (rok) {
+    } else {
         // row r (this lane's), outputs o = ot 16 + lk + 4 q
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int o = ot * 16 + lk + 4 * q;
-            if (o < nout) {
-                const int64_t p = int64_t(ra) + g.A * (int64_t(o) + int64_t(nout) * rc);
-                double v = acc[q];
-                if (g.out_w) v *= g.out_w[p];
-                store_out<TOUT>(out, g.out_lo, p + g.out_ldj * int64_t(rj), v);
+            okq[q] = rok && o < nout;
+            pq[q] = int64_t(ra) + g.A * (int64_t(min(o, nout - 1)) + int64_t(nout) * rc);
+            jq[q] = rj;
+        }
+    }
+    double ow[4];                                           // read only when has_ow
+    if (has_ow) {
+        const auto wo = global_view(g.out_w);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ow[q] = wo[pq[q]];
+    }
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    // Every load reads a clamped, valid address (rows past the end use row 0, indices past
+    // nin the last one) and is issued before any value is used; the values are masked
+    // afterwards and pinned in registers ahead of the MFMA steps.  (Loads behind branches
+    // that use them made each load wait for its value before the next was issued.)  The
+    // factor is read transposed, D^T[i][o]: the 16 lanes of one i read 16 consecutive o.
+    for (int kc = 0; kc < nin; kc += 4 * kChunk) {
+        const int nst = min(kChunk, (nin - kc + 3) / 4);     // MFMA steps of this chunk
+        TIN tin[kChunk];
+        double td[kChunk], tw[kChunk];                      // tw read only when has_w
+        const auto gin = global_view(in);
+        const auto gdt = global_view(g.DT);
+        // steps past nst load nothing (uniform guards; the blocks only load)
+#pragma unroll
+        for (int s = 0; s < kChunk; ++s) {
+            if (s < nst) {
+                const int ic = min(kc + 4 * s + lk, nin - 1);
+                tin[s] = gin[bin + g.A * ic];
+                td[s] = gdt[int64_t(ic) * nout + o_lc];
             }
+        }
+        if (has_w) {
+            const auto gw = global_view(g.in_w);
+#pragma unroll
+            for (int s = 0; s < kChunk; ++s)
+                if (s < nst) tw[s] = gw[pin + g.A * min(kc + 4 * s + lk, nin - 1)];
+        }
+        double xa[kChunk], xb[kChunk];
+#pragma unroll
+        for (int s = 0; s < kChunk; ++s) {
+            const bool iok = kc + 4 * s + lk < nin;
+            double vin = (rok && iok) ? double(tin[s]) : 0.0;
+            vin *= has_w ? g.in_scale * tw[s] : 1.0;
+            const double vd = (ook && iok) ? td[s] : 0.0;
+            if (FIRST) { xa[s] = vin; xb[s] = vd; }
+            else { xa[s] = vd; xb[s] = vin; }
+            asm volatile("" : "+v"(xa[s]), "+v"(xb[s]));   // materialise before the steps
+        }
+#pragma unroll
+        for (int s = 0; s < kChunk; ++s)
+            if (s < nst) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], xb[s], acc, 0, 0, 0);
+    }
+    // ---- store: C[(lane >> 4) + 4 q][lane & 15] --------------------------------------
+    // (first direction: a lane holds 16 consecutive o of one row; later directions: 16
+    // consecutive rows of one o; both coalesced)
+    TOUT *out = static_cast<TOUT *>(g.out);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (okq[q]) {
+            const double v = has_ow ? acc[q] * ow[q] : acc[q];
+            store_out<TOUT>(out, g.out_lo, pq[q] + g.out_ldj * jq[q], v);
         }
     }
 }
