@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__r
 // current one runs on the matrix cores.  The four partial tiles are added in LDS in
 // wave order and stored with alpha and beta (beta = 0 does not read Out).
 typedef double doublex4 __attribute__((ext_vector_type(4)));
-constexpr int kNNBatch = 4;      // k-steps per wave per batch of loads
+constexpr int kNNBatch = 2;      // k-steps per wave per batch of loads
 constexpr int kNNMaxTiles = 8;   // column tiles per workgroup
 
 template <int NT>
