@@ -85,6 +85,13 @@ typedef struct {
     double  corr_len[3];         /* correlation length per physical direction > 0 */
     int32_t max_block;           /* widest block per stage-5 pass; 0 = 32.  Wider
                                     blocks given to kl_apply are processed in chunks. */
+    int32_t interp_mult[3];      /* multiplicity m of every interior breakpoint of the
+                                    interpolation knot vector, 1 <= m <= interp degree pt:
+                                    continuity C^{pt-m}, nt_k = pt + 1 + (net_k - 1) m;
+                                    m = pt gives the C^0 interpolation spaces that Sec. 4.2
+                                    and Sec. 6 prefer for the exponential kernel.  0 = 1
+                                    (C^{pt-1}).  m > pt (a discontinuous space, whose
+                                    Greville points coincide) is KL_EINVAL. */
 } kl_desc;
 
 /* Builds the problem: knots, Greville points, Z_k and its Cholesky factor L_k, the

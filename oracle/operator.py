@@ -33,7 +33,9 @@ class Problem:
     """All host data of one problem, built in FP64 from its description dict.
 
     desc keys: dim, degree[d], nelem[d], optional interp_degree[d], interp_nelem[d]
-    (default: the trial space), map (geometry dict), cov (covariance dict).
+    (default: the trial space) and interp_mult[d] (multiplicity of the interpolation
+    space's interior breakpoints, default (or 0) 1; interp_mult = interp_degree gives the C^0
+    interpolation of Sec. 4.2), map (geometry dict), cov (covariance dict).
     """
 
     def __init__(self, desc):
@@ -46,7 +48,12 @@ class Problem:
         net = _per_dir(desc.get("interp_nelem"), d) if desc.get("interp_nelem") else ne
         self.p, self.ne, self.pt, self.net = p, ne, pt, net
         self.knots = [splines.open_uniform_knots(p[k], ne[k]) for k in range(d)]
-        self.knots_t = [splines.open_uniform_knots(pt[k], net[k]) for k in range(d)]
+        mult = _per_dir(desc.get("interp_mult"), d) if desc.get("interp_mult") else [1] * d
+        mult = [1 if m == 0 else int(m) for m in mult]              # 0 means the default, 1
+        if any(m < 1 or m > pt[k] for k, m in enumerate(mult)):
+            raise ValueError("interp_mult must lie in 1..interp degree")
+        self.knots_t = [splines.knots_with_multiplicity(pt[k], [j / net[k] for j in range(1, net[k])], mult[k])
+                        for k in range(d)]
         if "interp_knots" in desc:
             self.knots_t = [np.asarray(t, dtype=np.float64) for t in desc["interp_knots"]]
         self.n = [splines.dimension(self.knots[k], p[k]) for k in range(d)]

@@ -43,7 +43,8 @@ class KLDesc(ctypes.Structure):
                 ("interp_degree", ctypes.c_int32 * 3), ("interp_nelem", ctypes.c_int32 * 3),
                 ("map_kind", ctypes.c_int32), ("map_params", ctypes.c_double * 8),
                 ("cov_kind", ctypes.c_int32), ("sigma2", ctypes.c_double),
-                ("corr_len", ctypes.c_double * 3), ("max_block", ctypes.c_int32)]
+                ("corr_len", ctypes.c_double * 3), ("max_block", ctypes.c_int32),
+                ("interp_mult", ctypes.c_int32 * 3)]
 
 
 class KLEigsOpts(ctypes.Structure):
@@ -132,11 +133,13 @@ def make_desc(desc, max_block=0):
     ne = list(desc["nelem"])
     ideg = list(desc.get("interp_degree") or [0] * d)
     ine = list(desc.get("interp_nelem") or [0] * d)
+    imu = list(desc.get("interp_mult") or [0] * d)
     for k in range(min(d, 3, len(deg), len(ne))):
         c.degree[k] = int(deg[k])
         c.nelem[k] = int(ne[k])
         c.interp_degree[k] = int(ideg[k]) if k < len(ideg) else 0
         c.interp_nelem[k] = int(ine[k]) if k < len(ine) else 0
+        c.interp_mult[k] = int(imu[k]) if k < len(imu) else 0
     g = desc["map"]
     c.map_kind = MAP_KINDS[g["kind"]]
     if g["kind"] == "box":

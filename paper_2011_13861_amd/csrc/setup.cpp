@@ -19,10 +19,13 @@
 namespace kl {
 namespace {
 
-std::vector<double> uniform_knots(int p, int ne) {
+// Open knot vector on [0, 1] with ne uniform elements, each interior breakpoint repeated
+// `mult` times (continuity C^{p-mult} there); n = p + 1 + (ne - 1) mult functions.
+std::vector<double> uniform_knots(int p, int ne, int mult = 1) {
     std::vector<double> t;
     for (int i = 0; i <= p; ++i) t.push_back(0.0);
-    for (int j = 1; j < ne; ++j) t.push_back(double(j) / ne);
+    for (int j = 1; j < ne; ++j)
+        for (int m = 0; m < mult; ++m) t.push_back(double(j) / ne);
     for (int i = 0; i <= p; ++i) t.push_back(1.0);
     return t;
 }
@@ -363,10 +366,16 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
             r.ne > 100000 || r.net > 100000) {
             set_error("degrees must be in 1..20 and element counts >= 1"); return KL_EINVAL;
         }
+        const int mult = desc.interp_mult[k] > 0 ? desc.interp_mult[k] : 1;
+        if (desc.interp_mult[k] < 0 || mult > r.pt) {
+            set_error("interp_mult must be in 1..interp degree (0 = 1); discontinuous "
+                      "interpolation spaces are not supported");
+            return KL_EINVAL;
+        }
         r.n = r.ne + r.p;
-        r.nt = r.net + r.pt;
+        r.nt = r.pt + 1 + (r.net - 1) * mult;
         r.t = uniform_knots(r.p, r.ne);
-        r.tt = uniform_knots(r.pt, r.net);
+        r.tt = uniform_knots(r.pt, r.net, mult);
         hs.p[k] = r.p; hs.ne[k] = r.ne; hs.pt[k] = r.pt; hs.net[k] = r.net;
         hs.n[k] = r.n; hs.nt[k] = r.nt;
         N *= r.n;

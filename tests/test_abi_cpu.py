@@ -52,6 +52,13 @@ CASES = [
      "map": {"kind": "box", "lo": [0.5], "hi": [2.0]}, "cov": {"kind": "sqexp", "corr_len": [0.3]}},
     {"dim": 2, "degree": [2, 3], "nelem": [6, 4], "interp_degree": [3, 1], "interp_nelem": [9, 7],
      "map": {"kind": "annulus_polar", "r0": 1.0, "r1": 2.0}, "cov": {"kind": "exp", "corr_len": [0.4, 0.9]}},
+    # C^0 interpolation in both directions, and C^1 cubic interpolation next to the default
+    {"dim": 2, "degree": [3, 2], "nelem": [8, 6], "interp_degree": [2, 3], "interp_nelem": [7, 5],
+     "interp_mult": [2, 3], "map": {"kind": "annulus_nurbs", "r0": 1.0, "r1": 2.0},
+     "cov": {"kind": "exp", "corr_len": [0.5, 0.5]}},
+    {"dim": 3, "degree": [2, 2, 1], "nelem": [4, 3, 5], "interp_degree": [3, 2, 1], "interp_nelem": [4, 3, 5],
+     "interp_mult": [2, 0, 1], "map": {"kind": "sine_cube", "eps": 0.05, "amp": [1.0, 0.5, 0.3]},
+     "cov": {"kind": "exp", "corr_len": [0.6, 0.6, 0.6]}},
 ]
 
 
@@ -89,6 +96,10 @@ def test_error_codes():
     assert _status_of(bad_ell) == -1
     bad_s2 = dict(good, cov={"kind": "exp", "sigma2": -1.0, "corr_len": [1.0, 1.0]})
     assert _status_of(bad_s2) == -1
+    # interpolation breakpoint multiplicity beyond the degree (discontinuous) or negative
+    assert _status_of(dict(good, interp_degree=[2, 2], interp_mult=[3, 1])) == -1
+    assert _status_of(dict(good, interp_mult=[-1, 1])) == -1
+    assert _status_of(dict(good, interp_mult=[2, 2])) == 0
     annulus_3d = {"dim": 3, "degree": [2] * 3, "nelem": [2] * 3, "map": {"kind": "annulus_nurbs"},
                   "cov": {"kind": "exp", "corr_len": [1.0] * 3}}
     assert _status_of(annulus_3d) == -1

@@ -45,6 +45,10 @@ SMALL = [
     ("interp_ne_trial", {"dim": 2, "degree": [2, 3], "nelem": [9, 5], "interp_degree": [3, 1],
                          "interp_nelem": [12, 11], "map": {"kind": "annulus_polar", "r0": 1.0, "r1": 2.0},
                          "cov": {"kind": "exp", "sigma2": 1.3, "corr_len": [0.4, 0.9]}}),
+    ("interp_c0", {"dim": 2, "degree": [3, 2], "nelem": [10, 7], "interp_degree": [2, 3],
+                   "interp_nelem": [9, 6], "interp_mult": [2, 3],
+                   "map": {"kind": "annulus_nurbs", "r0": 1.0, "r1": 2.0},
+                   "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.5, 0.5]}}),
     ("line", {"dim": 1, "degree": [3], "nelem": [120], "map": {"kind": "box", "lo": [0.0], "hi": [2.0]},
               "cov": {"kind": "sqexp", "sigma2": 1.0, "corr_len": [0.2]}}),
     ("exp_l1", {"dim": 2, "degree": [2, 2], "nelem": [10, 7], "map": {"kind": "identity"},

@@ -134,6 +134,19 @@ def test_linear_kernel_exact_1d():
         assert np.max(np.abs(w[2:])) < 1e-13
 
 
+@pytest.mark.parametrize("p,pt,ne,net", [(2, 2, 4, 3), (3, 3, 5, 4), (1, 4, 3, 2)])
+def test_linear_kernel_exact_1d_c0_interpolation(p, pt, ne, net):
+    """The same closed form through C^0 interpolation spaces (interior breakpoints repeated
+    pt times, Sec. 4.2): 1 + x x' still lies in the interpolation space."""
+    desc = _desc(1, p, ne, "lin", 1.0, {"kind": "identity"}, pt=pt, net=net)
+    desc["interp_mult"] = [pt]
+    P = operator.Problem(desc)
+    assert P.nt == [net * pt + 1]
+    w = np.linalg.eigvalsh(P.dense_operator())[::-1]
+    assert np.allclose(w[:2], [(4 + math.sqrt(13)) / 6, (4 - math.sqrt(13)) / 6], rtol=0, atol=1e-13)
+    assert np.max(np.abs(w[2:])) < 1e-13
+
+
 def test_linear_kernel_exact_2d():
     """Gamma = 1 + x . x' on the unit square: lambda = (19 +- sqrt 313)/24 and 1/12."""
     P = operator.Problem(_desc(2, 2, 3, "lin", 1.0, {"kind": "identity"}))

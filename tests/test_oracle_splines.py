@@ -135,3 +135,25 @@ def test_kron_contraction_equals_dense_kron():
     # vec ordering: first index fastest
     T = kron.to_tensor(np.arange(30.0), shape)
     assert T[1, 0, 0] == 1 and T[0, 1, 0] == 3 and T[0, 0, 1] == 15
+
+
+@pytest.mark.parametrize("pt", [2, 3, 4])
+def test_c0_interpolation_reproduces_kinked_function(pt):
+    """Reduced-continuity interpolation (Sec. 4.2): with every interior breakpoint repeated
+    pt times the space holds all continuous piecewise polynomials of degree pt, so
+    collocation at the Greville points reproduces |x - 1/2| (kink at a breakpoint) exactly;
+    the maximally smooth space of the same mesh cannot."""
+    net = 4
+    kn = splines.knots_with_multiplicity(pt, [j / net for j in range(1, net)], pt)
+    n = splines.dimension(kn, pt)
+    assert n == pt + 1 + (net - 1) * pt == net * pt + 1
+    g = splines.greville(kn, pt)
+    # C^0 Greville points of a uniform mesh: the pt + 1 equispaced points of every element
+    assert np.max(np.abs(g - np.arange(n) / (n - 1))) < 1e-15
+    f = lambda x: np.abs(x - 0.5)
+    xs = np.random.default_rng(pt).random(300)
+    c = np.linalg.solve(splines.collocation_matrix(kn, pt), f(g))
+    assert np.max(np.abs(splines.basis_matrix(kn, pt, xs) @ c - f(xs))) < 1e-13
+    ks = splines.open_uniform_knots(pt, net)
+    cs = np.linalg.solve(splines.collocation_matrix(ks, pt), f(splines.greville(ks, pt)))
+    assert np.max(np.abs(splines.basis_matrix(ks, pt, xs) @ cs - f(xs))) > 1e-3

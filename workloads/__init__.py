@@ -9,6 +9,8 @@ Description dict:
   degree, nelem  trial space: degree p_k and element count per direction (open uniform
                  knots with C^{p-1} continuity, n_k = nelem_k + p_k)
   interp_degree, interp_nelem   optional interpolation space (default: trial space)
+  interp_mult    optional multiplicity of the interpolation space's interior breakpoints
+                 (default 1; interp_mult = interp_degree gives a C^0 space)
   map            {"kind": identity | box | annulus_nurbs | annulus_polar | sine_cube, ...}
   cov            {"kind": exp | sqexp | exp_l1 | const | lin, "sigma2": s2, "corr_len": [...]}
 
