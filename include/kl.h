@@ -156,6 +156,22 @@ kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t
  * physical Greville points; J: Ntilde weights sqrt(det DF); C: the nt_k x n_k
  * row-major composed factor of direction k (0-based).  Any output may be NULL. */
 kl_status kl_get_points(const kl_problem *P, double *X, double *J);
+
+/* Truncated KL expansion (Sec. 3.2) at the Ntilde mapped Greville points of kl_get_points:
+ *   F[:, s] = sum_{i<M} sqrt(lam_i) phi_i(x) xi[i, s]   zero-mean field samples, s < m
+ *   var     = sum_{i<M} lam_i phi_i(x)^2                the truncated variance
+ * with phi_i = (sum_j v_j B_j) / sqrt(det DF) in the trial basis of Sec. 3.4 and v = L^{-T} v'
+ * for the standard-form eigenvector v' (Sec. 4.1; column i of evecs, as kl_eigs returns it).
+ * lam: host, M eigenvalues (finite, >= 0).  evecs: device, N x M column-major, ld ldv >= N.
+ * xi: device, M x m column-major, ld ldxi >= M (read only when F is requested).  F: device,
+ * Ntilde x m column-major, ld ldf >= Ntilde, or NULL.  var: device, Ntilde, or NULL (not
+ * both NULL).  Inputs and outputs must not overlap.  Asynchronous on `stream`; uses the
+ * problem's workspaces, so calls on one problem must not run concurrently with each other or
+ * with kl_apply.  Errors: KL_EINVAL (sizes, pointers, eigenvalues, host-only handle),
+ * KL_EHIP. */
+kl_status kl_kle_field(kl_problem *P, int32_t M, const double *lam, const double *evecs, int64_t ldv,
+                       int32_t m, const double *xi, int64_t ldxi, double *F, int64_t ldf, double *var,
+                       void *stream);
 kl_status kl_get_factor(const kl_problem *P, int32_t k, double *C);
 
 typedef struct {

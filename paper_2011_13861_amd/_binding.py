@@ -23,7 +23,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
-           "kl_get_factor", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_profile_enable", "kl_profile_read",
+           "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_profile_enable", "kl_profile_read",
            "kl_stage5_config", "kl_apply_config", "kl_set_cov",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
            "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_destroy",
@@ -81,6 +81,8 @@ def lib():
         L.kl_stage5.argtypes = L.kl_apply.argtypes
         L.kl_get_points.argtypes = [P, P, P]
         L.kl_get_factor.argtypes = [P, ctypes.c_int32, P]
+        L.kl_kle_field.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, P,
+                                   ctypes.c_int64, P, ctypes.c_int64, P, P]
         L.kl_eigs.argtypes = [P, ctypes.POINTER(KLEigsOpts), P, ctypes.c_int32, P, P,
                               ctypes.c_int64, ctypes.POINTER(KLEigsReport)]
         L.kl_symeig.argtypes = [ctypes.c_int32, P, P, P]
@@ -227,6 +229,29 @@ class Problem:
         J = np.zeros(self.Nt)
         check(lib().kl_get_points(self._h, ctypes.c_void_p(X.ctypes.data), ctypes.c_void_p(J.ctypes.data)))
         return X, J
+
+    def kle_field(self, lam, evecs, xi=None, variance=True, stream=None):
+        """Truncated KL expansion at the Greville points (kl_kle_field).  lam: M host
+        eigenvalues; evecs: device (N, M) column-major block (as eigs returns it); xi: device
+        (M, m) column-major block of standard-normal draws, or None.  Returns (F, var): device
+        tensors of shape (Ntilde, m) (column-major) and (Ntilde,), or None where not asked."""
+        import torch
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        M = _colmajor(evecs, self.N)
+        if lam.shape != (M,):
+            raise ValueError("need one eigenvalue per eigenvector column")
+        F = var = None
+        m = 0
+        if xi is not None:
+            m = _colmajor(xi, M)
+            F = torch.empty((m, self.Nt), dtype=torch.float64, device=evecs.device).T
+        if variance:
+            var = torch.empty(self.Nt, dtype=torch.float64, device=evecs.device)
+        check(lib().kl_kle_field(self._h, M, ctypes.c_void_p(lam.ctypes.data), _ptr(evecs), _ld(evecs), m,
+                                 _ptr(xi) if xi is not None else None, _ld(xi) if xi is not None else 0,
+                                 _ptr(F) if F is not None else None, _ld(F) if F is not None else 0,
+                                 _ptr(var) if var is not None else None, _stream(stream)))
+        return F, var
 
     def factor(self, k):
         C = np.zeros((self.nt[k], self.n[k]))

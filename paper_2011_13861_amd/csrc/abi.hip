@@ -41,6 +41,8 @@ void free_problem(kl_problem *P) {
     for (int k = 0; k < 3; ++k) {
         hipFree(P->dC[k]);
         hipFree(P->dCT[k]);
+        hipFree(P->dE[k]);
+        hipFree(P->dET[k]);
     }
     hipFree(P->ws.T0);
     hipFree(P->ws.T1);
@@ -350,6 +352,14 @@ kl_status setup_problem(const kl_desc *desc, bool workspace, kl_problem **out) {
         KL_TRY(dev_alloc(&P->dCT[k], CT.size(), "hipMalloc CT"));
         KL_TRY(hip_check(hipMemcpy(P->dC[k], hs.C[k].data(), CT.size() * 8, hipMemcpyHostToDevice), "copy C"));
         KL_TRY(hip_check(hipMemcpy(P->dCT[k], CT.data(), CT.size() * 8, hipMemcpyHostToDevice), "copy CT"));
+        // evaluation factor of the truncated expansion (kl_kle_field)
+        std::vector<double> ET(size_t(n) * nt);
+        for (int i = 0; i < nt; ++i)
+            for (int j = 0; j < n; ++j) ET[size_t(j) * nt + i] = hs.E[k][size_t(i) * n + j];
+        KL_TRY(dev_alloc(&P->dE[k], hs.E[k].size(), "hipMalloc E"));
+        KL_TRY(dev_alloc(&P->dET[k], ET.size(), "hipMalloc ET"));
+        KL_TRY(hip_check(hipMemcpy(P->dE[k], hs.E[k].data(), ET.size() * 8, hipMemcpyHostToDevice), "copy E"));
+        KL_TRY(hip_check(hipMemcpy(P->dET[k], ET.data(), ET.size() * 8, hipMemcpyHostToDevice), "copy ET"));
     }
     if (!workspace) {
         *out = P;

@@ -25,6 +25,7 @@ struct HostSetup {
     int n[3] = {1, 1, 1}, nt[3] = {1, 1, 1};
     int64_t N = 0, Nt = 0;
     std::vector<double> C[3];   // composed factor C_k (nt_k x n_k, row-major)
+    std::vector<double> E[3];   // B_k(Greville points of the interpolation space) L_k^{-T} (nt_k x n_k)
     std::vector<double> X;      // Nt x d, physical Greville points, vec order
     std::vector<double> J;      // Nt, sqrt(det DF)
 };
@@ -74,6 +75,8 @@ struct kl_problem {
     double *dJ = nullptr;     // [Ntpad], sqrt(det DF); zero in the padding
     double *dC[3] = {nullptr, nullptr, nullptr};    // C_k, nt_k x n_k row-major
     double *dCT[3] = {nullptr, nullptr, nullptr};   // C_k^T, n_k x nt_k row-major
+    double *dE[3] = {nullptr, nullptr, nullptr};    // E_k, nt_k x n_k row-major (kl_kle_field)
+    double *dET[3] = {nullptr, nullptr, nullptr};   // E_k^T
     kl::Workspace ws;
     kl::SolverCache *solver = nullptr;
     int n_cu = 256;

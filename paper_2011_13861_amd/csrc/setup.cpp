@@ -181,8 +181,10 @@ struct Dir {
     std::vector<double> t, tt;
 };
 
-// C_k = Bt^{-T} M L^{-T} for one direction.
-kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &g) {
+// C_k = Bt^{-T} M L^{-T} for one direction; also E_k = B(g) L^{-T}, the trial B-splines at
+// the interpolation Greville abscissae g applied to standard-form coefficients (Sec. 3.4,
+// 4.1), which evaluates eigenfunctions there.
+kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &E, std::vector<double> &g) {
     const int n = D.n, nt = D.nt;
     // Z_k by Gauss-Legendre with p+1 points per element
     std::vector<double> xs, ws;
@@ -244,6 +246,19 @@ kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &g
             double s = M[size_t(r) * n + i];
             for (int k = 0; k < i; ++k) s -= Z[size_t(i) * n + k] * W[size_t(r) * n + k];
             W[size_t(r) * n + i] = s / Z[size_t(i) * n + i];
+        }
+    }
+    // E = B(g) L^{-T}: row r solves L e^T = b(g_r)^T (forward substitution)
+    E.assign(size_t(nt) * n, 0.0);
+    for (int r = 0; r < nt; ++r) {
+        const int s0 = find_span(D.t, D.p, n, g[r]);
+        nonzero_basis(D.t, D.p, s0, g[r], B);
+        double *e = &E[size_t(r) * n];
+        for (int a = 0; a <= D.p; ++a) e[s0 - D.p + a] = B[a];
+        for (int i = 0; i < n; ++i) {
+            double s = e[i];
+            for (int k = 0; k < i; ++k) s -= Z[size_t(i) * n + k] * e[k];
+            e[i] = s / Z[size_t(i) * n + i];
         }
     }
     // C = Bt^{-T} W, column by column
@@ -386,7 +401,7 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
     hs.Nt = Nt;
     std::vector<double> g[3];
     for (int k = 0; k < d; ++k) {
-        kl_status st = build_direction(D[k], hs.C[k], g[k]);
+        kl_status st = build_direction(D[k], hs.C[k], hs.E[k], g[k]);
         if (st != KL_OK) return st;
     }
     hs.X.assign(size_t(Nt) * d, 0.0);
