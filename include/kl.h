@@ -163,7 +163,8 @@ kl_status kl_get_points(const kl_problem *P, double *X, double *J);
  * with phi_i = (sum_j v_j B_j) / sqrt(det DF) in the trial basis of Sec. 3.4 and v = L^{-T} v'
  * for the standard-form eigenvector v' (Sec. 4.1; column i of evecs, as kl_eigs returns it).
  * lam: host, M eigenvalues (finite, >= 0).  evecs: device, N x M column-major, ld ldv >= N.
- * xi: device, M x m column-major, ld ldxi >= M (read only when F is requested).  F: device,
+ * xi: device, M x m column-major, ld ldxi >= M, m <= 1048560 (read only when F is
+ * requested).  F: device,
  * Ntilde x m column-major, ld ldf >= Ntilde, or NULL.  var: device, Ntilde, or NULL (not
  * both NULL).  Inputs and outputs must not overlap.  Asynchronous on `stream`; uses the
  * problem's workspaces, so calls on one problem must not run concurrently with each other or

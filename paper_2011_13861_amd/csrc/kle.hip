@@ -4,10 +4,10 @@
 //
 // Per chunk of up to 32 eigenvectors: the Kronecker product of the factors E_k = B_k(g) L_k^{-T}
 // (one per-direction launch each, the forward-stage kernel with E_k in place of C_k) gives
-// the unscaled values in the stage-5 output buffer; one pass scales row x by 1 / J(x) and
-// column i by sqrt(lambda_i) and adds the squares to the variance; the samples are then one
-// tall-skinny product with the chunk's rows of xi (the eigensolver's FP64 matrix-core GEMM),
-// accumulated over chunks.
+// the unscaled values in the stage-5 output buffer; one more launch scales row x by 1 / J(x)
+// and column i by sqrt(lambda_i), adds the squares to the variance and accumulates the
+// chunk's part of the samples (a contraction of at most 32 terms per output: FP64 FMAs in
+// registers, bound by writing F).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,21 +22,56 @@ struct ColScale {
     double v[kBW];
 };
 
-// Phi[row][i] *= sqrt(lambda_i) / J[row]; var[row] (+)= sum_i Phi[row][i]^2.  One thread per
-// row; the columns are read row-contiguously (coalesced).
-__global__ __launch_bounds__(256) void kle_scale_kernel(double *__restrict__ Phi, int64_t ldp, int64_t Nt,
+// One chunk of nb <= 32 eigenfunctions, Phi[row][i] unscaled (column-major, ld ldp).  The
+// thread of row x runs over i, forming phi_i(x) sqrt(lambda_i) = Phi[x][i] sqrt(lambda_i) / J[x]
+// one at a time: the workgroups of column group 0 add its square to the variance, and with
+// WITH_F every workgroup adds its products with xi[i][j] to kCols columns of F (F[x][j] (+)=
+// sum_i phi_i(x) sqrt(lambda_i) xi[i][j]), which stay in registers.  Rows run along the
+// threads, so the Phi reads and the F accesses are coalesced; sqrt(lambda_i) and the group's
+// xi entries sit in LDS (every lane reads the same word: a broadcast).
+constexpr int kCols = 16;
+
+template <bool WITH_F>
+__global__ __launch_bounds__(256) void kle_field_kernel(const double *__restrict__ Phi, int64_t ldp, int64_t Nt,
                                                          int nb, const double *__restrict__ J, ColScale cs,
+                                                         const double *__restrict__ xi, int64_t ldxi, int m,
+                                                         double *__restrict__ F, int64_t ldf,
                                                          double *__restrict__ var, int first) {
+    __shared__ double ssl[kBW];
+    __shared__ double sxi[kBW][kCols];
     const int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (row >= Nt) return;
-    const double inv = 1.0 / J[row];
-    double acc = 0.0;
-    for (int i = 0; i < nb; ++i) {
-        const double v = Phi[int64_t(i) * ldp + row] * inv * cs.v[i];
-        Phi[int64_t(i) * ldp + row] = v;
-        acc = fma(v, v, acc);
+    const bool live = row < Nt;
+    const int64_t r = live ? row : Nt - 1;                  // clamped: dead rows store nothing
+    const int j0 = int(blockIdx.y) * kCols;
+    if (threadIdx.x < kBW) ssl[threadIdx.x] = cs.v[threadIdx.x];
+    if constexpr (WITH_F) {
+        for (int e = threadIdx.x; e < kCols * kBW; e += 256) {
+            const int c = e % kCols, i = e / kCols;
+            sxi[i][c] = (j0 + c < m && i < nb) ? xi[int64_t(j0 + c) * ldxi + i] : 0.0;
+        }
     }
-    if (var) var[row] = first ? acc : var[row] + acc;
+    const int nc = min(kCols, m - j0);
+    double acc[kCols];
+#pragma unroll
+    for (int c = 0; c < kCols; ++c)
+        acc[c] = (WITH_F && !first && live && c < nc) ? F[int64_t(j0 + c) * ldf + row] : 0.0;
+    const double inv = 1.0 / J[r];
+    __syncthreads();
+    double vs = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < nb; ++i) {
+        const double v = Phi[int64_t(i) * ldp + r] * inv * ssl[i];
+        vs = fma(v, v, vs);
+        if constexpr (WITH_F)
+#pragma unroll
+            for (int c = 0; c < kCols; ++c) acc[c] = fma(v, sxi[i][c], acc[c]);
+    }
+    if (!live) return;
+    if (var && blockIdx.y == 0) var[row] = first ? vs : var[row] + vs;
+    if constexpr (WITH_F)
+#pragma unroll
+        for (int c = 0; c < kCols; ++c)
+            if (c < nc) F[int64_t(j0 + c) * ldf + row] = acc[c];
 }
 
 }  // namespace
@@ -55,6 +90,9 @@ extern "C" kl_status kl_kle_field(kl_problem *P, int32_t M, const double *lam, c
     if (!want_f && !var) { set_error("kl_kle_field: neither F nor var requested"); return KL_EINVAL; }
     if (want_f && (!xi || ldxi < M || ldf < hs.Nt)) {
         set_error("kl_kle_field: NULL xi, ldxi < M or ldf < Ntilde"); return KL_EINVAL;
+    }
+    if (want_f && (int64_t(m) + kCols - 1) / kCols > 65535) {
+        set_error("kl_kle_field: more than 1048560 samples per call"); return KL_EINVAL;
     }
     for (int i = 0; i < M; ++i)
         if (!(lam[i] >= 0.0) || !std::isfinite(lam[i])) {
@@ -93,10 +131,14 @@ extern "C" kl_status kl_kle_field(kl_problem *P, int32_t M, const double *lam, c
         }
         ColScale cs{};
         for (int i = 0; i < nb; ++i) cs.v[i] = std::sqrt(lam[c0 + i]);
-        hipLaunchKernelGGL(kle_scale_kernel, dim3(unsigned((hs.Nt + 255) / 256)), dim3(256), 0, s, Phi,
-                           P->Ntpad, hs.Nt, nb, P->dJ, cs, var, c0 == 0 ? 1 : 0);
+        const unsigned groups = want_f ? unsigned((m + kCols - 1) / kCols) : 1u;
+        const dim3 grid(unsigned((hs.Nt + 255) / 256), groups);
         if (want_f)
-            launch_gemm_nn(Phi, P->Ntpad, nb, xi + c0, ldxi, m, hs.Nt, 1.0, c0 == 0 ? 0.0 : 1.0, F, ldf, s);
+            hipLaunchKernelGGL(kle_field_kernel<true>, grid, dim3(256), 0, s, Phi, P->Ntpad, hs.Nt, nb, P->dJ, cs,
+                               xi + c0, ldxi, m, F, ldf, var, c0 == 0 ? 1 : 0);
+        else
+            hipLaunchKernelGGL(kle_field_kernel<false>, grid, dim3(256), 0, s, Phi, P->Ntpad, hs.Nt, nb, P->dJ, cs,
+                               nullptr, ldxi, 0, nullptr, ldf, var, c0 == 0 ? 1 : 0);
     }
     if (hipGetLastError() != hipSuccess) { set_error("kl_kle_field: kernel launch failed"); return KL_EHIP; }
     return KL_OK;
