@@ -92,3 +92,21 @@ def test_linear_kernel_variance_through_gpu_eigensolver():
     _, var = G.kle_field(w, V)
     X, _ = G.points()
     assert np.max(np.abs(var.cpu().numpy() - (1.0 + np.sum(X ** 2, axis=1)))) < 1e-8
+
+
+def test_kle_field_many_chunks_same_problem():
+    """Same problem twice: 45 modes (two chunks), then 300 modes (ten chunks of 32, the last
+    ragged, each accumulating into F and var)."""
+    desc = {"dim": 2, "degree": [2, 2], "nelem": [20, 19], "map": {"kind": "annulus_polar", "r0": 1.0, "r1": 2.0},
+            "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.3, 0.3]}}
+    P = operator.Problem(desc)
+    lam_all, V_all = oeigs.dense_eigs(P, 300)
+    lam_all = np.maximum(lam_all, 0.0)
+    G = kl.Problem(desc)
+    for M, m in [(45, 20), (300, 37)]:
+        lam, V = lam_all[:M], V_all[:, :M]
+        xi = np.random.default_rng(M).standard_normal((M, m))
+        F, var = G.kle_field(lam, kl.to_device_block(V), kl.to_device_block(xi))
+        torch.cuda.synchronize()
+        assert _rel(F.cpu().numpy(), kle.sample_field(P, lam, V, xi)) < 1e-12, M
+        assert _rel(var.cpu().numpy(), kle.variance_field(P, lam, V)) < 1e-12, M
