@@ -118,4 +118,9 @@ def test_host_only_handle_rejects_device_calls():
     st = kl.lib().kl_apply(H.handle, 0, 1, ctypes.c_void_p(1), H.N, ctypes.c_void_p(2), H.N, None)
     assert st == -1
     assert b"host-only" in kl.lib().kl_last_error()
+    lam = (ctypes.c_double * 1)(1.0)
+    st = kl.lib().kl_kle_field(H.handle, 1, lam, ctypes.c_void_p(1), H.N, 0, None, 0, None, 0,
+                               ctypes.c_void_p(2), None)
+    assert st == -1
+    assert b"host-only" in kl.lib().kl_last_error()
     H.close()
