@@ -104,10 +104,31 @@ def test_symmetric_positive_semidefinite(desc):
     assert w.min() >= -1e-12 * w.max()
 
 
-def test_c_stage5_equals_numpy_stage5():
-    P = operator.Problem(CASES[4])
+@pytest.mark.parametrize("kind", ["exp", "sqexp", "exp_l1", "const", "lin"])
+@pytest.mark.parametrize("case", [0, 3, 4])
+def test_c_stage5_equals_numpy_stage5(kind, case):
+    """The C/OpenMP stage 5 and the NumPy one (pinned by the spectral tests) agree for every
+    kernel kind, in 1D, 2D and 3D, with unequal correlation lengths per direction."""
+    desc = dict(CASES[case])
+    d = desc["dim"]
+    desc["cov"] = {"kind": kind, "sigma2": 1.3, "corr_len": [0.35, 0.8, 0.55][:d]}
+    P = operator.Problem(desc)
     Y = workloads.random_block(P.Nt, 3, seed=2)
-    assert np.max(np.abs(cstage5.stage5(P, Y) - P.stage5(Y))) < 1e-12 * np.abs(P.stage5(Y)).max()
+    ref = P.stage5(Y)
+    assert np.max(np.abs(cstage5.stage5(P, Y) - ref)) < 1e-12 * np.abs(ref).max()
+
+
+def test_clusters_on_hand_built_spectrum():
+    """Runs of consecutive eigenvalues with relative gap below the threshold are grouped;
+    the gap is relative to the larger of the two neighbours."""
+    w = np.array([1.0, 0.5, 0.4999, 0.49985, 0.3, 0.2999999, 0.1, 0.05, 0.04996])
+    assert eigs.clusters(w, rel_gap=1e-3) == [[0], [1, 2, 3], [4, 5], [6], [7, 8]]
+    assert eigs.clusters(w, rel_gap=1e-9) == [[i] for i in range(len(w))]
+    assert eigs.clusters(w, rel_gap=0.6) == [[0, 1, 2, 3, 4, 5], [6, 7, 8]]
+    assert eigs.clusters(w, rel_gap=0.7) == [list(range(len(w)))]
+    # exactly repeated and a gap just above the threshold
+    assert eigs.clusters(np.array([2.0, 2.0, 2.0 * (1 - 1.001e-3)]), rel_gap=1e-3) == [[0, 1], [2]]
+    assert eigs.clusters(np.array([3.0])) == [[0]]
 
 
 @pytest.mark.parametrize("geom,d,measure", [
