@@ -16,6 +16,10 @@ Map kinds (dicts with a "kind" key):
   annulus_polar   (r0 + (r1 - r0) u) (cos(pi v / 2), sin(pi v / 2)), a cross-check with
                   the same physical domain
   sine_cube       F(u) = u + eps * amp * prod_k sin(pi u_k): identity on the boundary
+  tensor_nurbs    a general d-variate NURBS map (Sec. 2.3-2.4): "degree" [d], "knots" [d]
+                  open knot vectors on [0, 1], "ctrl" (m_1, ..., m_d, d) control points,
+                  optional "weights" (m_1, ..., m_d); F = sum_a w_a P_a N_a / sum_a w_a N_a
+                  with N_a the tensor-product B-splines, derivatives by the quotient rule
   any of the above may carry "rotation" (d x d orthogonal) and "shift" (d) applied after
   F; det DF is unchanged by them.
 
@@ -93,6 +97,34 @@ def _quarter_annulus_nurbs(r0, r1):
     return ku, 1, kv, 2, ctrl, weights
 
 
+def tensor_nurbs(degree, knots, ctrl, weights, u):
+    """F(u) and DF(u) (shape (npts, d, d), D[r, i, j] = dF_i / du_j) of a d-variate NURBS map.
+    Sums over the control net are written as tensor contractions of the per-direction basis
+    matrices N_k (npts x m_k) and their derivatives, with the weights folded into the
+    homogeneous control points (w P, w)."""
+    u = np.atleast_2d(np.asarray(u, dtype=np.float64))
+    npts, d = u.shape
+    ctrl = np.asarray(ctrl, dtype=np.float64)
+    w = np.ones(ctrl.shape[:d]) if weights is None else np.asarray(weights, dtype=np.float64)
+    Pw = np.concatenate([ctrl * w[..., None], w[..., None]], axis=-1)   # homogeneous (m_1..m_d, d + 1)
+    N = [splines.basis_matrix(np.asarray(knots[k], dtype=np.float64), degree[k], u[:, k]) for k in range(d)]
+    dN = [_bspline_derivative_matrix(np.asarray(knots[k], dtype=np.float64), degree[k], u[:, k])
+          for k in range(d)]
+    letters = "abc"[:d]
+    spec = ",".join("r" + letters[k] for k in range(d)) + "," + letters + "h->rh"
+
+    def contract(mats):
+        return np.einsum(spec, *mats, Pw)
+
+    H = contract(N)                                   # (npts, d + 1): A and W
+    X = H[:, :d] / H[:, d:]
+    D = np.zeros((npts, d, d))
+    for j in range(d):
+        Hj = contract([dN[k] if k == j else N[k] for k in range(d)])
+        D[:, :, j] = (Hj[:, :d] - X * Hj[:, d:]) / H[:, d:]
+    return X, D
+
+
 def map_points(geom, u):
     """Physical points F(u) and det DF(u) for parametric points u of shape (npts, d)."""
     u = np.atleast_2d(np.asarray(u, dtype=np.float64))
@@ -139,6 +171,8 @@ def map_points(geom, u):
         X = u + eps * s[:, None] * amp[None, :]
         D = np.broadcast_to(np.eye(d), (npts, d, d)).copy()
         D += eps * amp[None, :, None] * grad[:, None, :]
+    elif kind == "tensor_nurbs":
+        X, D = tensor_nurbs(geom["degree"], geom["knots"], geom["ctrl"], geom.get("weights"), u)
     else:
         raise ValueError("unknown map kind %r" % kind)
     if "rotation" in geom:

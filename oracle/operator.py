@@ -32,10 +32,12 @@ def _per_dir(v, d, default=None):
 class Problem:
     """All host data of one problem, built in FP64 from its description dict.
 
-    desc keys: dim, degree[d], nelem[d], optional interp_degree[d], interp_nelem[d]
-    (default: the trial space) and interp_mult[d] (multiplicity of the interpolation
-    space's interior breakpoints, default (or 0) 1; interp_mult = interp_degree gives the C^0
-    interpolation of Sec. 4.2), map (geometry dict), cov (covariance dict).
+    desc keys: dim, degree[d], nelem[d] (open uniform knots) or knots[d] (explicit open knot
+    vectors on [0, 1]; None entries fall back to nelem), optional interp_degree[d],
+    interp_nelem[d] (default: the trial space) and interp_mult[d] (multiplicity of the
+    interpolation space's interior breakpoints, default (or 0) 1; interp_mult =
+    interp_degree gives the C^0 interpolation of Sec. 4.2) or interp_knots[d], map
+    (geometry dict), cov (covariance dict).
     """
 
     def __init__(self, desc):
@@ -43,19 +45,31 @@ class Problem:
         self.d = d
         self.desc = desc
         p = _per_dir(desc["degree"], d)
-        ne = _per_dir(desc["nelem"], d)
         pt = _per_dir(desc.get("interp_degree"), d) if desc.get("interp_degree") else p
-        net = _per_dir(desc.get("interp_nelem"), d) if desc.get("interp_nelem") else ne
+        pt = [p[k] if pt[k] in (0, None) else pt[k] for k in range(d)]
+        # trial knots: explicit (Sec. 2.3, any open knot vector on [0, 1]) or open uniform
+        given = list(desc.get("knots") or [None] * d) + [None] * d
+        ne = _per_dir(desc.get("nelem"), d) if desc.get("nelem") else [None] * d
+        self.knots = [np.asarray(given[k], dtype=np.float64) if given[k] is not None
+                      else splines.open_uniform_knots(p[k], ne[k]) for k in range(d)]
+        ne = [len(np.unique(self.knots[k])) - 1 for k in range(d)]
+        net = _per_dir(desc.get("interp_nelem"), d) if desc.get("interp_nelem") else [0] * d
+        mult = _per_dir(desc.get("interp_mult"), d) if desc.get("interp_mult") else [0] * d
+        gt = list(desc.get("interp_knots") or [None] * d) + [None] * d
+        self.knots_t = []
+        for k in range(d):
+            if gt[k] is not None:
+                self.knots_t.append(np.asarray(gt[k], dtype=np.float64))
+            elif given[k] is not None and pt[k] == p[k] and not net[k] and not mult[k]:
+                self.knots_t.append(self.knots[k])            # the trial space itself
+            else:
+                nek = net[k] or ne[k]
+                mk = int(mult[k]) or 1                            # 0 means the default, 1
+                if mk < 1 or mk > pt[k]:
+                    raise ValueError("interp_mult must lie in 1..interp degree")
+                self.knots_t.append(splines.knots_with_multiplicity(pt[k], [j / nek for j in range(1, nek)], mk))
+        net = [len(np.unique(self.knots_t[k])) - 1 for k in range(d)]
         self.p, self.ne, self.pt, self.net = p, ne, pt, net
-        self.knots = [splines.open_uniform_knots(p[k], ne[k]) for k in range(d)]
-        mult = _per_dir(desc.get("interp_mult"), d) if desc.get("interp_mult") else [1] * d
-        mult = [1 if m == 0 else int(m) for m in mult]              # 0 means the default, 1
-        if any(m < 1 or m > pt[k] for k, m in enumerate(mult)):
-            raise ValueError("interp_mult must lie in 1..interp degree")
-        self.knots_t = [splines.knots_with_multiplicity(pt[k], [j / net[k] for j in range(1, net[k])], mult[k])
-                        for k in range(d)]
-        if "interp_knots" in desc:
-            self.knots_t = [np.asarray(t, dtype=np.float64) for t in desc["interp_knots"]]
         self.n = [splines.dimension(self.knots[k], p[k]) for k in range(d)]
         self.nt = [splines.dimension(self.knots_t[k], pt[k]) for k in range(d)]
         self.N = int(np.prod(self.n))
