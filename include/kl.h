@@ -67,24 +67,29 @@ typedef enum { KL_COV_EXP = 0, KL_COV_SQEXP = 1, KL_COV_EXP_L1 = 2, KL_COV_CONST
  *   ANNULUS_NURBS:  (2D) r0 = params[0], r1 = params[1]; exact rational quadratic arc
  *   ANNULUS_POLAR:  (2D) r0, r1 as above; polar parametrisation of the same domain
  *   SINE_CUBE:      F(u) = u + eps amp prod_k sin(pi u_k); eps = params[0],
- *                   amp = params[1..3]                                            */
+ *                   amp = params[1..3]
+ *   TENSOR_NURBS:   a general tensor-product NURBS map (Sec. 2.3-2.4) given by the map_*
+ *                   fields of kl_desc: F(u) = sum_a w_a P_a prod_k N_{a_k}(u_k) / W(u),
+ *                   W(u) = sum_a w_a prod_k N_{a_k}(u_k), with its own degrees and open
+ *                   knot vectors on [0, 1] per direction; map_params is not read.   */
 typedef enum { KL_MAP_IDENTITY = 0, KL_MAP_BOX = 1, KL_MAP_ANNULUS_NURBS = 2,
-               KL_MAP_ANNULUS_POLAR = 3, KL_MAP_SINE_CUBE = 4 } kl_map_kind;
+               KL_MAP_ANNULUS_POLAR = 3, KL_MAP_SINE_CUBE = 4, KL_MAP_TENSOR_NURBS = 5 } kl_map_kind;
 
+/* Knot vectors (Sec. 2.3), when given explicitly: nondecreasing, open (the first and the
+ * last value repeated p + 1 times), from 0 to 1, every interior value repeated at most p
+ * times (continuity C^0 or smoother), at least 2 p + 2 entries; the space has nknots - p - 1
+ * functions.  Host arrays, read during kl_setup only. */
 typedef struct {
     int32_t dim;                 /* spatial dimension d, 1..3 */
     int32_t degree[3];           /* trial-space degree p_k >= 1 */
     int32_t nelem[3];            /* trial-space elements per direction >= 1; open uniform
-                                    knots with C^{p-1} continuity, n_k = nelem_k + p_k */
+                                    knots with C^{p-1} continuity, n_k = nelem_k + p_k.
+                                    Not read for a direction with explicit knots. */
+    const double *knots[3];      /* optional explicit trial knot vector of direction k
+                                    (NULL = open uniform from nelem) */
+    int32_t nknots[3];           /* its length */
     int32_t interp_degree[3];    /* interpolation space (Sec. 4.2); 0 = same as trial */
     int32_t interp_nelem[3];     /* 0 = same as trial */
-    int32_t map_kind;            /* kl_map_kind */
-    double  map_params[8];
-    int32_t cov_kind;            /* kl_cov_kind */
-    double  sigma2;              /* variance > 0 */
-    double  corr_len[3];         /* correlation length per physical direction > 0 */
-    int32_t max_block;           /* widest block per stage-5 pass; 0 = 32.  Wider
-                                    blocks given to kl_apply are processed in chunks. */
     int32_t interp_mult[3];      /* multiplicity m of every interior breakpoint of the
                                     interpolation knot vector, 1 <= m <= interp degree pt:
                                     continuity C^{pt-m}, nt_k = pt + 1 + (net_k - 1) m;
@@ -92,15 +97,35 @@ typedef struct {
                                     and Sec. 6 prefer for the exponential kernel.  0 = 1
                                     (C^{pt-1}).  m > pt (a discontinuous space, whose
                                     Greville points coincide) is KL_EINVAL. */
+    const double *interp_knots[3];   /* optional explicit interpolation knot vector
+                                    (NULL = from interp_nelem / interp_mult; with explicit
+                                    trial knots and interp_degree, interp_nelem and
+                                    interp_mult all 0 or equal to the trial ones, the trial
+                                    knot vector); its degree is interp_degree (0 = trial) */
+    int32_t interp_nknots[3];
+    int32_t map_kind;            /* kl_map_kind */
+    double  map_params[8];
+    int32_t map_degree[3];       /* TENSOR_NURBS: degree per direction >= 1 */
+    const double *map_knots[3];  /* TENSOR_NURBS: open knot vector per direction (host) */
+    int32_t map_nknots[3];
+    const double *map_ctrl;      /* TENSOR_NURBS: control points, prod_k m_k points of d
+                                    coordinates each (m_k = map_nknots[k] - map_degree[k] - 1),
+                                    in vec order (first index fastest), point-major (host) */
+    const double *map_weights;   /* TENSOR_NURBS: prod_k m_k weights > 0, or NULL (all 1) */
+    int32_t cov_kind;            /* kl_cov_kind */
+    double  sigma2;              /* variance > 0 */
+    double  corr_len[3];         /* correlation length per physical direction > 0 */
 } kl_desc;
 
 /* Builds the problem: knots, Greville points, Z_k and its Cholesky factor L_k, the
  * collocation matrices Bt_k and their LU factors, the mixed mass matrices M_k, the
  * composed factors C_k = Bt_k^{-T} M_k L_k^{-T}, mapped Greville points X = F(xhat)
  * and J = sqrt(det DF(xhat)) (Sec. 3.5, 4.1-4.3), in FP64 on the host; then uploads
- * them and allocates all workspaces.  Synchronous.  Errors: KL_EINVAL, KL_EDOMAIN,
+ * them on `stream` (a hipStream_t, NULL = default stream) and allocates all workspaces.
+ * Synchronous: returns after the uploads on `stream` have completed.  The setup time is
+ * kept with the handle (kl_eigs_report.t_setup).  Errors: KL_EINVAL, KL_EDOMAIN,
  * KL_ESINGULAR, KL_ENOMEM, KL_EHIP.  *out is written only on success. */
-kl_status kl_setup(const kl_desc *desc, kl_problem **out);
+kl_status kl_setup(const kl_desc *desc, void *stream, kl_problem **out);
 
 /* Host part of kl_setup only (no device work, usable without a GPU): the handle
  * supports kl_info, kl_get_points, kl_get_factor and kl_destroy; kl_apply, kl_stage5
@@ -190,6 +215,10 @@ typedef struct {
     double  lo_floor;       /* low-precision phase: relative residual (times theta_1) it
                                runs down to before the FP64 phase; 0 = default (FP32 2e-6,
                                BF16x3 5e-5, BF16 5e-3) */
+    int32_t coeffs;         /* 0: evecs receive the standard-form eigenvectors v' (unit
+                               2-norm); 1: the B-spline coefficients v = L^{-T} v' of the
+                               eigenfunctions phi_h = sum_j v_j B_j / sqrt(det DF) (Sec. 4.1,
+                               Sec. 3.4), which have unit L2 norm */
 } kl_eigs_opts;
 
 typedef struct {
@@ -197,6 +226,8 @@ typedef struct {
     int32_t n_block_applies[4];
     int32_t n_restarts;
     int32_t converged;      /* number of leading pairs meeting the criterion */
+    double  t_setup;        /* seconds spent in kl_setup for this handle (host setup and
+                               uploads), reported separately as the paper does (Sec. 6) */
     double  t_solve;        /* seconds, wall clock */
     double  t_host_eig;     /* seconds spent in host dense eigensolves (Rayleigh-Ritz) */
     double  max_rel_residual;   /* max_i ||A~' x_i - theta_i x_i|| / theta_i over i <= k */
@@ -207,13 +238,18 @@ typedef struct {
  *   ||A~' x_i - theta_i x_i||_2 <= max(tol * theta_i, abs_floor * theta_1),  ||x_i|| = 1.
  * x0: optional device FP64 start block (N x nvec0, ld N), or NULL for a seeded random
  * start.  evals: host, k values.  evecs: device FP64, N x k, leading dimension ldv;
- * unit 2-norm columns v' (so phi_h has unit L2 norm, Sec. 4.1).  rep may be NULL.
- * Synchronous.  On KL_ENOCONV evals/evecs hold the best Ritz pairs found.
+ * unit 2-norm columns v' (so phi_h has unit L2 norm, Sec. 4.1), or their B-spline
+ * coefficients with opts->coeffs = 1.  rep may be NULL.
+ * Ordering: the solver runs on its own stream, which first waits for the work queued on
+ * `stream` (a hipStream_t, NULL = default stream) at the time of the call, so x0 may be
+ * produced there; the call returns after evecs has been written (synchronous).
+ * On KL_ENOCONV evals/evecs hold the best Ritz pairs found.
  * The solver's device buffers and stream are created on the first call
  * and kept with the handle (grown when a later call needs more) until kl_destroy, so
- * calls on one handle must not overlap. */
+ * calls on one handle must not overlap with each other or with kl_apply / kl_stage5 /
+ * kl_kle_field on the same handle (they share its workspaces). */
 kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0, int32_t nvec0,
-                  double *evals, double *evecs, int64_t ldv, kl_eigs_report *rep);
+                  double *evals, double *evecs, int64_t ldv, kl_eigs_report *rep, void *stream);
 
 /* Stage-5 kernel timing for measurement tools: while enabled, every stage-5 launch of
  * this handle (from kl_apply, kl_stage5 and kl_eigs) is bracketed by two HIP events
@@ -277,9 +313,12 @@ kl_status kl_batch_config(kl_batch *B, int32_t precision, int32_t rb, int64_t lc
  * iteration applies the operators of all unfinished problems in one graph replay
  * (finished ones masked off).  evals: host, n x k (row i = problem i).  evecs: device
  * arena, problem i's N_i x k block at element k * row_offset_i, leading dimension N_i.
- * reps: host array of n reports, or NULL.  Returns KL_ENOCONV if any problem did not
- * converge (its report says how far it got), or the first error. */
-kl_status kl_eigs_batch(kl_batch *B, const kl_eigs_opts *opts, double *evals, double *evecs, kl_eigs_report *reps);
+ * reps: host array of n reports, or NULL.  Ordering as kl_eigs: the solver streams first
+ * wait for the work queued on `stream`; the call returns after evecs has been written.
+ * Returns KL_ENOCONV if any problem did not converge (its report says how far it got), or
+ * the first error. */
+kl_status kl_eigs_batch(kl_batch *B, const kl_eigs_opts *opts, double *evals, double *evecs, kl_eigs_report *reps,
+                        void *stream);
 kl_status kl_batch_destroy(kl_batch *B);
 
 /* ---- Warm-start network -----------------------------------------------------------

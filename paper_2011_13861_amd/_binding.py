@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "KL_OK", -1: "KL_EINVAL", -2: "KL_ENOMEM", -3: "KL_EHIP", -4:
                 -5: "KL_ESINGULAR", -6: "KL_ENUMERIC", -7: "KL_ENOCONV"}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 COV_KINDS = {"exp": 0, "sqexp": 1, "exp_l1": 2, "const": 3, "lin": 4}
-MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "sine_cube": 4}
+MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "sine_cube": 4,
+             "tensor_nurbs": 5}
 
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
@@ -38,13 +39,20 @@ class KLError(RuntimeError):
         self.status = status
 
 
+_DP3 = ctypes.POINTER(ctypes.c_double) * 3
+
+
 class KLDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32 * 3), ("nelem", ctypes.c_int32 * 3),
+                ("knots", _DP3), ("nknots", ctypes.c_int32 * 3),
                 ("interp_degree", ctypes.c_int32 * 3), ("interp_nelem", ctypes.c_int32 * 3),
+                ("interp_mult", ctypes.c_int32 * 3),
+                ("interp_knots", _DP3), ("interp_nknots", ctypes.c_int32 * 3),
                 ("map_kind", ctypes.c_int32), ("map_params", ctypes.c_double * 8),
+                ("map_degree", ctypes.c_int32 * 3), ("map_knots", _DP3), ("map_nknots", ctypes.c_int32 * 3),
+                ("map_ctrl", ctypes.POINTER(ctypes.c_double)), ("map_weights", ctypes.POINTER(ctypes.c_double)),
                 ("cov_kind", ctypes.c_int32), ("sigma2", ctypes.c_double),
-                ("corr_len", ctypes.c_double * 3), ("max_block", ctypes.c_int32),
-                ("interp_mult", ctypes.c_int32 * 3)]
+                ("corr_len", ctypes.c_double * 3)]
 
 
 class KLEigsOpts(ctypes.Structure):
@@ -52,13 +60,13 @@ class KLEigsOpts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("abs_floor", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("refine_fp64", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("guard", ctypes.c_int32), ("max_basis", ctypes.c_int32),
-                ("lo_floor", ctypes.c_double)]
+                ("lo_floor", ctypes.c_double), ("coeffs", ctypes.c_int32)]
 
 
 class KLEigsReport(ctypes.Structure):
     _fields_ = [("n_applies", ctypes.c_int32 * 4), ("n_block_applies", ctypes.c_int32 * 4),
                 ("n_restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("t_solve", ctypes.c_double), ("t_host_eig", ctypes.c_double),
+                ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double), ("t_host_eig", ctypes.c_double),
                 ("max_rel_residual", ctypes.c_double)]
 
 
@@ -72,7 +80,7 @@ def lib():
             raise ImportError("libklmf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
-        L.kl_setup.argtypes = [ctypes.POINTER(KLDesc), ctypes.POINTER(P)]
+        L.kl_setup.argtypes = [ctypes.POINTER(KLDesc), P, ctypes.POINTER(P)]
         L.kl_setup_host.argtypes = [ctypes.POINTER(KLDesc), ctypes.POINTER(P)]
         L.kl_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -84,7 +92,7 @@ def lib():
         L.kl_kle_field.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, P,
                                    ctypes.c_int64, P, ctypes.c_int64, P, P]
         L.kl_eigs.argtypes = [P, ctypes.POINTER(KLEigsOpts), P, ctypes.c_int32, P, P,
-                              ctypes.c_int64, ctypes.POINTER(KLEigsReport)]
+                              ctypes.c_int64, ctypes.POINTER(KLEigsReport), P]
         L.kl_symeig.argtypes = [ctypes.c_int32, P, P, P]
         L.kl_symeig_partial.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
@@ -109,7 +117,7 @@ def lib():
         L.kl_apply_batch.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
         L.kl_batch_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
-        L.kl_eigs_batch.argtypes = [P, ctypes.POINTER(KLEigsOpts), P, P, P]
+        L.kl_eigs_batch.argtypes = [P, ctypes.POINTER(KLEigsOpts), P, P, P, P]
         L.kl_batch_destroy.argtypes = [P]
         L.kl_destroy.argtypes = [P]
         L.kl_last_error.restype = ctypes.c_char_p
@@ -126,22 +134,47 @@ def check(status):
     return status
 
 
-def make_desc(desc, max_block=0):
-    """Marshals a workload description dict into the C kl_desc struct."""
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def grid_to_vec_order(a, d):
+    """(m_1, ..., m_d, ...) array -> rows in vec order (first grid index fastest)."""
+    a = np.asarray(a, dtype=np.float64)
+    axes = list(range(d - 1, -1, -1)) + list(range(d, a.ndim))
+    return np.ascontiguousarray(np.transpose(a, axes).reshape((-1,) + a.shape[d:]))
+
+
+def make_desc(desc):
+    """Marshals a workload description dict into the C kl_desc struct.  The host arrays the
+    struct points to (knot vectors, control net) are kept alive on the struct (`_keep`)."""
     d = int(desc["dim"])
     c = KLDesc()
+    keep = []
     c.dim = d
     deg = list(desc["degree"])
-    ne = list(desc["nelem"])
+    ne = list(desc.get("nelem") or [0] * d)
     ideg = list(desc.get("interp_degree") or [0] * d)
     ine = list(desc.get("interp_nelem") or [0] * d)
     imu = list(desc.get("interp_mult") or [0] * d)
-    for k in range(min(d, 3, len(deg), len(ne))):
+    for k in range(min(d, 3, len(deg))):
         c.degree[k] = int(deg[k])
-        c.nelem[k] = int(ne[k])
+        c.nelem[k] = int(ne[k]) if k < len(ne) else 0
         c.interp_degree[k] = int(ideg[k]) if k < len(ideg) else 0
         c.interp_nelem[k] = int(ine[k]) if k < len(ine) else 0
         c.interp_mult[k] = int(imu[k]) if k < len(imu) else 0
+    for key, ptrs, lens in (("knots", c.knots, c.nknots), ("interp_knots", c.interp_knots, c.interp_nknots)):
+        for k, t in enumerate(desc.get(key) or []):
+            if t is None:
+                continue
+            a = _f64(t)
+            keep.append(a)
+            ptrs[k] = _dptr(a)
+            lens[k] = len(a)
     g = desc["map"]
     c.map_kind = MAP_KINDS[g["kind"]]
     if g["kind"] == "box":
@@ -156,13 +189,27 @@ def make_desc(desc, max_block=0):
         amp = list(g.get("amp", [1.0, 0.5, 0.25]))
         for k in range(3):
             c.map_params[1 + k] = float(amp[k]) if k < len(amp) else 0.0
+    elif g["kind"] == "tensor_nurbs":
+        for k in range(d):
+            c.map_degree[k] = int(g["degree"][k])
+            a = _f64(g["knots"][k])
+            keep.append(a)
+            c.map_knots[k] = _dptr(a)
+            c.map_nknots[k] = len(a)
+        ctrl = grid_to_vec_order(g["ctrl"], d)
+        keep.append(ctrl)
+        c.map_ctrl = _dptr(ctrl)
+        if g.get("weights") is not None:
+            w = grid_to_vec_order(g["weights"], d)
+            keep.append(w)
+            c.map_weights = _dptr(w)
     cov = desc["cov"]
     c.cov_kind = COV_KINDS[cov["kind"]]
     c.sigma2 = float(cov.get("sigma2", 1.0))
     ell = list(cov.get("corr_len", [1.0] * d))
     for k in range(min(d, 3, len(ell))):
         c.corr_len[k] = float(ell[k])
-    c.max_block = int(max_block)
+    c._keep = keep
     return c
 
 
@@ -182,11 +229,13 @@ def _stream(stream):
 class Problem:
     """Owns one kl_problem handle (kl_setup / kl_destroy)."""
 
-    def __init__(self, desc, host_only=False, max_block=0):
+    def __init__(self, desc, host_only=False, stream=None):
         self._h = ctypes.c_void_p()
-        c = make_desc(desc, max_block)
-        fn = lib().kl_setup_host if host_only else lib().kl_setup
-        check(fn(ctypes.byref(c), ctypes.byref(self._h)))
+        c = make_desc(desc)
+        if host_only:
+            check(lib().kl_setup_host(ctypes.byref(c), ctypes.byref(self._h)))
+        else:
+            check(lib().kl_setup(ctypes.byref(c), _stream(stream), ctypes.byref(self._h)))
         N = ctypes.c_int64()
         Nt = ctypes.c_int64()
         n = (ctypes.c_int32 * 3)()
@@ -290,19 +339,24 @@ class Problem:
         return {names[p]: (int(cnt[p]), float(ms[p])) for p in range(4)}
 
     def eigs(self, k, precision="f64", block=32, tol=1e-6, abs_floor=1e-12, refine_fp64=True,
-             seed=0, x0=None, max_applies=0, guard=0, max_basis=0, lo_floor=0.0, ldv=None):
+             seed=0, x0=None, max_applies=0, guard=0, max_basis=0, lo_floor=0.0, coeffs=False,
+             stream=None):
         """k leading eigenpairs; returns (evals numpy, evecs device tensor (N, k) column-major,
-        report dict).  Raises KLError except for KL_ENOCONV, which is reported."""
+        report dict).  coeffs=True returns the B-spline coefficients v = L^{-T} v' instead of
+        the standard-form vectors.  The solve is ordered after the work queued on `stream`
+        (default: the current stream).  Raises KLError except for KL_ENOCONV, which is
+        reported."""
         import torch
         o = KLEigsOpts(k=k, block=block, max_applies=max_applies, tol=tol, abs_floor=abs_floor,
                        precision=PRECISIONS[precision], refine_fp64=int(bool(refine_fp64)),
-                       seed=seed, guard=guard, max_basis=max_basis, lo_floor=lo_floor)
+                       seed=seed, guard=guard, max_basis=max_basis, lo_floor=lo_floor,
+                       coeffs=int(bool(coeffs)))
         ev = np.zeros(k)
         V = torch.zeros((k, self.N), dtype=torch.float64, device="cuda").T
         rep = KLEigsReport()
         x0p, n0 = (ctypes.c_void_p(0), 0) if x0 is None else (_ptr(x0), _colmajor(x0, self.N))
         st = lib().kl_eigs(self._h, ctypes.byref(o), x0p, n0, ctypes.c_void_p(ev.ctypes.data),
-                           _ptr(V), self.N, ctypes.byref(rep))
+                           _ptr(V), self.N, ctypes.byref(rep), _stream(stream))
         if st not in (KL_OK, KL_ENOCONV):
             check(st)
         return ev, V, report_dict(rep, st)
@@ -315,7 +369,8 @@ class Batch:
 
     def __init__(self, descs):
         self._h = ctypes.c_void_p()
-        arr = (KLDesc * len(descs))(*[make_desc(d) for d in descs])
+        structs = [make_desc(d) for d in descs]       # they keep the host arrays alive
+        arr = (KLDesc * len(descs))(*structs)
         check(lib().kl_setup_batch(len(descs), arr, ctypes.byref(self._h)))
         self.n = len(descs)
         self.N, self.Nt, self.rowoff = [], [], []
@@ -359,15 +414,17 @@ class Batch:
         return g.value, it.value
 
     def eigs(self, k, precision="f64", block=32, tol=1e-6, abs_floor=1e-12, refine_fp64=True, seed=0,
-             max_applies=0, guard=0, max_basis=0, lo_floor=0.0):
+             max_applies=0, guard=0, max_basis=0, lo_floor=0.0, coeffs=False, stream=None):
         """Returns (evals (n, k) numpy, evecs arena (device), [report dict per problem])."""
         o = KLEigsOpts(k=k, block=block, max_applies=max_applies, tol=tol, abs_floor=abs_floor,
                        precision=PRECISIONS[precision], refine_fp64=int(bool(refine_fp64)),
-                       seed=seed, guard=guard, max_basis=max_basis, lo_floor=lo_floor)
+                       seed=seed, guard=guard, max_basis=max_basis, lo_floor=lo_floor,
+                       coeffs=int(bool(coeffs)))
         ev = np.zeros((self.n, k))
         V = self.arena(k)
         reps = (KLEigsReport * self.n)()
-        st = lib().kl_eigs_batch(self._h, ctypes.byref(o), ctypes.c_void_p(ev.ctypes.data), _ptr(V), reps)
+        st = lib().kl_eigs_batch(self._h, ctypes.byref(o), ctypes.c_void_p(ev.ctypes.data), _ptr(V), reps,
+                                 _stream(stream))
         if st not in (KL_OK, KL_ENOCONV):
             check(st)
         return ev, V, [report_dict(reps[i], st) for i in range(self.n)]
@@ -474,7 +531,8 @@ def symeig_partial(A, nv):
 def report_dict(rep, status=0):
     return {"status": STATUS_NAMES.get(status, status), "n_applies": list(rep.n_applies),
             "n_block_applies": list(rep.n_block_applies), "n_restarts": rep.n_restarts,
-            "converged": rep.converged, "t_solve": rep.t_solve, "t_host_eig": rep.t_host_eig,
+            "converged": rep.converged, "t_setup": rep.t_setup, "t_solve": rep.t_solve,
+            "t_host_eig": rep.t_host_eig,
             "max_rel_residual": rep.max_rel_residual}
 
 

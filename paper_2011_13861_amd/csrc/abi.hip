@@ -1,4 +1,5 @@
 // C ABI: problem setup, the matrix-free apply (Algorithm 1) and accessors.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -43,6 +44,8 @@ void free_problem(kl_problem *P) {
         hipFree(P->dCT[k]);
         hipFree(P->dE[k]);
         hipFree(P->dET[k]);
+        hipFree(P->dLT[k]);
+        hipFree(P->dL1[k]);
     }
     hipFree(P->ws.T0);
     hipFree(P->ws.T1);
@@ -72,7 +75,7 @@ bool valid_precision(int precision) { return precision >= KL_F64 && precision <=
 // Scaled Greville points for the stage-5 kernels (Sec. 4.3): X / ell per direction for
 // the FP64 kernel, with log2(e) absorbed for the exp2-based FP32 / BF16 kernels.  The
 // padding points stay zero (their rows and columns carry zero weight).
-kl_status upload_points(kl_problem *P) {
+kl_status upload_points(kl_problem *P, hipStream_t s) {
     const HostSetup &hs = P->hs;
     const int d = hs.d;
     const int64_t Np = P->Ntpad;
@@ -87,16 +90,20 @@ kl_status upload_points(kl_problem *P) {
             x32[size_t(k) * Np + p] = float(v * s32);
         }
     }
-    kl_status st = hip_check(hipMemcpy(P->dX64, x64.data(), x64.size() * 8, hipMemcpyHostToDevice), "copy X64");
+    kl_status st = hip_check(hipMemcpyAsync(P->dX64, x64.data(), x64.size() * 8, hipMemcpyHostToDevice, s),
+                             "copy X64");
     if (st != KL_OK) return st;
-    return hip_check(hipMemcpy(P->dX32, x32.data(), x32.size() * 4, hipMemcpyHostToDevice), "copy X32");
+    st = hip_check(hipMemcpyAsync(P->dX32, x32.data(), x32.size() * 4, hipMemcpyHostToDevice, s), "copy X32");
+    if (st != KL_OK) return st;
+    // the host staging vectors go out of scope here
+    return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
-void *stage5_input(kl_problem *P, int precision) {
+void *stage5_input(const Workspace &ws, int precision) {
     switch (precision) {
-    case KL_F64: return P->ws.Y5d;
-    case KL_F32: return P->ws.Y5f;
-    default: return P->ws.Y5b;
+    case KL_F64: return ws.Y5d;
+    case KL_F32: return ws.Y5f;
+    default: return ws.Y5b;
     }
 }
 
@@ -117,12 +124,12 @@ int64_t max_intermediate(const HostSetup &hs) {
 
 // Stage-5 launch; while profiling is on, a pair of HIP events (without the system-scope
 // fence, which would add a cache writeback to the interval) brackets the covariance kernel.
-int timed_stage5(kl_problem *P, int precision, const void *Y5, const double *wrow, double scale,
-                 hipStream_t s, bool defer_reduce = false) {
+int timed_stage5(kl_problem *P, const Workspace &ws, int precision, const void *Y5, const double *wrow,
+                 double scale, hipStream_t s, bool defer_reduce = false) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
-    const int nsplit = launch_stage5(P, precision, Y5, P->ws.Z5, P->ws.Zf, wrow, scale, s,
+    const int nsplit = launch_stage5(P, precision, Y5, ws.Z5, ws.Zf, wrow, scale, s,
                                      rec ? P->prof_ev[P->prof_used] : nullptr,
-                                     rec ? P->prof_ev[P->prof_used + 1] : nullptr, defer_reduce);
+                                     rec ? P->prof_ev[P->prof_used + 1] : nullptr, defer_reduce, ws.max_split);
     if (rec) {
         P->prof_prec.push_back(precision);
         P->prof_used += 2;
@@ -147,12 +154,13 @@ bool fused_directions(const kl_problem *P, int nb) {
 // backward one also adds the stage-5 split partials and applies sigma^2 J): 2d - 1
 // launches for d >= 2, otherwise one per direction, stage 5 and its split sums.
 kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx,
-                      double *y, int64_t ldy, hipStream_t s) {
+                      double *y, int64_t ldy, hipStream_t s, const Workspace *wsp) {
     const HostSetup &hs = P->hs;
+    const Workspace &ws = wsp ? *wsp : P->ws;
     const int d = hs.d;
-    double *T0 = P->ws.T0, *T1 = P->ws.T1;
+    double *T0 = ws.T0, *T1 = ws.T1;
     const bool lo = precision != KL_F64;
-    void *Y5 = stage5_input(P, precision);
+    void *Y5 = stage5_input(ws, precision);
     void *Y5lo = precision == KL_BF16X3 ? static_cast<void *>(static_cast<__bf16 *>(Y5) + P->Ntpad * kBW) : nullptr;
     const int y5_kind = precision == KL_F32 ? 1 : (precision == KL_BF16 || precision == KL_BF16X3) ? 2 : 0;
     const bool fuse = fused_directions(P, nb);
@@ -211,9 +219,9 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
         cur_ld = m.out_ldj;
     }
     // ---- stage 5, its output scaled by sigma^2 J (or left as split partials) ------------
-    const int nsplit = timed_stage5(P, precision, Y5, P->dJ, P->sigma2, s, fuse);
+    const int nsplit = timed_stage5(P, ws, precision, Y5, P->dJ, P->sigma2, s, fuse);
     // ---- stages 6-9 ---------------------------------------------------------------------
-    cur = P->ws.Zf;
+    cur = ws.Zf;
     cur_ld = P->Ntpad;
     A = 1;
     k0 = 0;
@@ -226,10 +234,10 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
         a.nvec = nb;
         a.in_ldj = P->Ntpad;
         if (nsplit > 1) {
-            a.in = P->ws.Z5; a.nsplit = nsplit; a.in_split = P->Ntpad * kBW;
+            a.in = ws.Z5; a.nsplit = nsplit; a.in_split = P->Ntpad * kBW;
             a.in_w = P->dJ; a.in_scale = P->sigma2;
         } else {
-            a.in = P->ws.Zf; a.nsplit = 1; a.in_split = 0; a.in_w = nullptr; a.in_scale = 1.0;
+            a.in = ws.Zf; a.nsplit = 1; a.in_split = 0; a.in_w = nullptr; a.in_scale = 1.0;
         }
         a.out_lo = nullptr; a.out_w = nullptr;
         if (d == 2) {
@@ -271,6 +279,41 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
+// v = L^{-T} v' one direction at a time (mode products with the upper triangular
+// factors L_k^{-T}); the result lands back in x.
+void launch_to_coefficients(const kl_problem *P, double *x, int64_t ldx, int nvec, double *tmp, hipStream_t s) {
+    const HostSetup &hs = P->hs;
+    const int d = hs.d;
+    const int64_t N = hs.N;
+    for (int c0 = 0; c0 < nvec; c0 += kBW) {
+        const int nb = std::min(kBW, nvec - c0);
+        double *cur = x + int64_t(c0) * ldx;
+        int64_t cur_ld = ldx;
+        int64_t A = 1;
+        for (int k = 0; k < d; ++k) {
+            ModeSpec m;
+            m.D = P->dLT[k];
+            m.DT = P->dL1[k];
+            m.in = cur;
+            m.in_ldj = cur_ld;
+            m.A = A;
+            m.nin = m.nout = hs.n[k];
+            m.Clo = 1;
+            for (int j = k + 1; j < d; ++j) m.Clo *= hs.n[j];
+            m.nvec = nb;
+            // x -> tmp -> x -> ... (never in place); an odd d ends in tmp and is copied back
+            const bool to_tmp = (k % 2) == 0;
+            m.out = to_tmp ? tmp : x + int64_t(c0) * ldx;
+            m.out_ldj = to_tmp ? N : ldx;
+            launch_mode(m, s);
+            A *= hs.n[k];
+            cur = static_cast<double *>(m.out);
+            cur_ld = m.out_ldj;
+        }
+        if (cur != x + int64_t(c0) * ldx) launch_copy_cols(cur, cur_ld, x + int64_t(c0) * ldx, ldx, N, nb, s);
+    }
+}
+
 }  // namespace kl
 
 using namespace kl;
@@ -288,13 +331,16 @@ kl_status kl_setup_host(const kl_desc *desc, kl_problem **out) {
     return KL_OK;
 }
 
-kl_status kl_setup(const kl_desc *desc, kl_problem **out) { return kl::setup_problem(desc, true, out); }
+kl_status kl_setup(const kl_desc *desc, void *stream, kl_problem **out) {
+    return kl::setup_problem(desc, true, static_cast<hipStream_t>(stream), out);
+}
 
 }  // extern "C"
 
 namespace kl {
 
-kl_status setup_problem(const kl_desc *desc, bool workspace, kl_problem **out) {
+kl_status setup_problem(const kl_desc *desc, bool workspace, hipStream_t s, kl_problem **out) {
+    const auto t0 = std::chrono::steady_clock::now();
     if (!desc || !out) { set_error("kl_setup: NULL argument"); return KL_EINVAL; }
     kl_problem *P = new (std::nothrow) kl_problem();
     if (!P) { set_error("kl_setup: host allocation failed"); return KL_ENOMEM; }
@@ -334,34 +380,44 @@ kl_status setup_problem(const kl_desc *desc, bool workspace, kl_problem **out) {
     do {                                               \
         if ((st = (expr)) != KL_OK) { free_problem(P); return st; } \
     } while (0)
-    {
-        std::vector<double> jpad(size_t(Np), 0.0);
-        for (int64_t p = 0; p < hs.Nt; ++p) jpad[p] = hs.J[p];
-        KL_TRY(dev_alloc(&P->dX64, size_t(d) * Np, "hipMalloc X64"));
-        KL_TRY(dev_alloc(&P->dX32, size_t(d) * Np, "hipMalloc X32"));
-        KL_TRY(dev_alloc(&P->dJ, jpad.size(), "hipMalloc J"));
-        KL_TRY(upload_points(P));
-        KL_TRY(hip_check(hipMemcpy(P->dJ, jpad.data(), jpad.size() * 8, hipMemcpyHostToDevice), "copy J"));
-    }
+    // host copies of everything that is uploaded; they stay alive until the stream has
+    // been synchronised at the end of the setup
+    std::vector<double> jpad(size_t(Np), 0.0);
+    for (int64_t p = 0; p < hs.Nt; ++p) jpad[p] = hs.J[p];
+    KL_TRY(dev_alloc(&P->dX64, size_t(d) * Np, "hipMalloc X64"));
+    KL_TRY(dev_alloc(&P->dX32, size_t(d) * Np, "hipMalloc X32"));
+    KL_TRY(dev_alloc(&P->dJ, jpad.size(), "hipMalloc J"));
+    KL_TRY(upload_points(P, s));
+    KL_TRY(hip_check(hipMemcpyAsync(P->dJ, jpad.data(), jpad.size() * 8, hipMemcpyHostToDevice, s), "copy J"));
+    std::vector<double> CT[3], ET[3], L1[3];
+    auto upload = [&](double **dst, const std::vector<double> &src, const char *what) -> kl_status {
+        kl_status st2 = dev_alloc(dst, src.size(), what);
+        if (st2 != KL_OK) return st2;
+        return hip_check(hipMemcpyAsync(*dst, src.data(), src.size() * 8, hipMemcpyHostToDevice, s), what);
+    };
     for (int k = 0; k < d; ++k) {
         const int n = hs.n[k], nt = hs.nt[k];
-        std::vector<double> CT(size_t(n) * nt);
+        CT[k].resize(size_t(n) * nt);
+        ET[k].resize(size_t(n) * nt);
         for (int i = 0; i < nt; ++i)
-            for (int j = 0; j < n; ++j) CT[size_t(j) * nt + i] = hs.C[k][size_t(i) * n + j];
-        KL_TRY(dev_alloc(&P->dC[k], hs.C[k].size(), "hipMalloc C"));
-        KL_TRY(dev_alloc(&P->dCT[k], CT.size(), "hipMalloc CT"));
-        KL_TRY(hip_check(hipMemcpy(P->dC[k], hs.C[k].data(), CT.size() * 8, hipMemcpyHostToDevice), "copy C"));
-        KL_TRY(hip_check(hipMemcpy(P->dCT[k], CT.data(), CT.size() * 8, hipMemcpyHostToDevice), "copy CT"));
-        // evaluation factor of the truncated expansion (kl_kle_field)
-        std::vector<double> ET(size_t(n) * nt);
-        for (int i = 0; i < nt; ++i)
-            for (int j = 0; j < n; ++j) ET[size_t(j) * nt + i] = hs.E[k][size_t(i) * n + j];
-        KL_TRY(dev_alloc(&P->dE[k], hs.E[k].size(), "hipMalloc E"));
-        KL_TRY(dev_alloc(&P->dET[k], ET.size(), "hipMalloc ET"));
-        KL_TRY(hip_check(hipMemcpy(P->dE[k], hs.E[k].data(), ET.size() * 8, hipMemcpyHostToDevice), "copy E"));
-        KL_TRY(hip_check(hipMemcpy(P->dET[k], ET.data(), ET.size() * 8, hipMemcpyHostToDevice), "copy ET"));
+            for (int j = 0; j < n; ++j) {
+                CT[k][size_t(j) * nt + i] = hs.C[k][size_t(i) * n + j];
+                // evaluation factor of the truncated expansion (kl_kle_field)
+                ET[k][size_t(j) * nt + i] = hs.E[k][size_t(i) * n + j];
+            }
+        L1[k].resize(size_t(n) * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) L1[k][size_t(j) * n + i] = hs.LT[k][size_t(i) * n + j];
+        KL_TRY(upload(&P->dC[k], hs.C[k], "C"));
+        KL_TRY(upload(&P->dCT[k], CT[k], "CT"));
+        KL_TRY(upload(&P->dE[k], hs.E[k], "E"));
+        KL_TRY(upload(&P->dET[k], ET[k], "ET"));
+        KL_TRY(upload(&P->dLT[k], hs.LT[k], "LT"));
+        KL_TRY(upload(&P->dL1[k], L1[k], "L1"));
     }
     if (!workspace) {
+        KL_TRY(hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"));
+        P->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         *out = P;
         return KL_OK;
     }
@@ -370,13 +426,15 @@ kl_status setup_problem(const kl_desc *desc, bool workspace, kl_problem **out) {
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5d), P->ws.y5_bytes, "hipMalloc Y5"));
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5f), P->ws.y5_bytes / 2, "hipMalloc Y5"));
     // the padding rows of the stage-5 input are never written and must stay zero
-    KL_TRY(hip_check(hipMemset(P->ws.Y5d, 0, P->ws.y5_bytes), "memset Y5"));
-    KL_TRY(hip_check(hipMemset(P->ws.Y5f, 0, P->ws.y5_bytes / 2), "memset Y5"));
+    KL_TRY(hip_check(hipMemsetAsync(P->ws.Y5d, 0, P->ws.y5_bytes, s), "memset Y5"));
+    KL_TRY(hip_check(hipMemsetAsync(P->ws.Y5f, 0, P->ws.y5_bytes / 2, s), "memset Y5"));
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Y5b), P->ws.y5_bytes / 2, "hipMalloc Y5"));
-    KL_TRY(hip_check(hipMemset(P->ws.Y5b, 0, P->ws.y5_bytes / 2), "memset Y5"));
+    KL_TRY(hip_check(hipMemsetAsync(P->ws.Y5b, 0, P->ws.y5_bytes / 2, s), "memset Y5"));
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Z5), P->ws.z5_bytes, "hipMalloc Z5"));
     KL_TRY(dev_alloc(reinterpret_cast<char **>(&P->ws.Zf), size_t(Np) * kBW * sizeof(double), "hipMalloc Zf"));
+    KL_TRY(hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"));
 #undef KL_TRY
+    P->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = P;
     return KL_OK;
 }
@@ -414,7 +472,7 @@ kl_status kl_set_cov(kl_problem *P, int32_t cov_kind, double sigma2, const doubl
     P->cov_kind = cov_kind;
     P->sigma2 = sigma2;
     for (int k = 0; k < 3; ++k) P->ell[k] = k < P->hs.d ? corr_len[k] : 1.0;
-    return upload_points(P);
+    return upload_points(P, nullptr);
 }
 
 kl_status kl_apply(kl_problem *P, int32_t precision, int32_t nvec, const double *x, int64_t ldx,
@@ -450,9 +508,9 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec, const double
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int c0 = 0; c0 < nvec; c0 += kBW) {
         const int nb = std::min(kBW, nvec - c0);
-        void *Y5 = stage5_input(P, precision);
+        void *Y5 = stage5_input(P->ws, precision);
         launch_pack_stage5(precision, y + int64_t(c0) * ldy, ldy, P->hs.Nt, nb, P->Ntpad, Y5, s);
-        const int nsplit = timed_stage5(P, precision, Y5, nullptr, 1.0, s);
+        const int nsplit = timed_stage5(P, P->ws, precision, Y5, nullptr, 1.0, s);
         (void)nsplit;
         launch_unpack_stage5(precision, P->ws.Zf, 1, P->Ntpad, P->hs.Nt, nb, P->sigma2,
                              z + int64_t(c0) * ldz, ldz, s);

@@ -408,7 +408,7 @@ kl_status kl_setup_batch(int32_t n, const kl_desc *descs, kl_batch **out) {
             return KL_EINVAL;
         }
         kl_problem *P = nullptr;
-        st = setup_problem(&descs[i], false, &P);
+        st = setup_problem(&descs[i], false, nullptr, &P);
         if (st != KL_OK) {
             const std::string msg = std::string(kl_last_error());
             free_batch(B);

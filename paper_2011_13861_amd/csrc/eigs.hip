@@ -31,9 +31,6 @@
 
 namespace kl {
 
-kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx,
-                      double *y, int64_t ldy, hipStream_t s);
-
 namespace {
 
 constexpr int kT = 256;
@@ -332,20 +329,33 @@ struct Solver {
     }
 };
 
-// Grows the problem's solver cache to hold an N x mmax basis (and N x cmax work block).
-kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
+// The problem's solver cache and its stream (created on first use).
+kl_status ensure_solver_stream(kl_problem *P) {
     if (!P->solver) {
         P->solver = new (std::nothrow) SolverCache();
         if (!P->solver) { set_error("kl_eigs: host allocation failed"); return KL_ENOMEM; }
     }
+    if (!P->solver->s) {
+        const hipError_t e = hipStreamCreate(&P->solver->s);
+        if (e != hipSuccess) {
+            P->solver->s = nullptr;
+            set_error(std::string("kl_eigs: stream: ") + hipGetErrorString(e));
+            return KL_EHIP;
+        }
+    }
+    return KL_OK;
+}
+
+// Grows the problem's solver cache to hold an N x mmax basis (and N x cmax work block).
+kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
+    kl_status st = ensure_solver_stream(P);
+    if (st != KL_OK) return st;
     SolverCache &c = *P->solver;
     auto hip = [](hipError_t e, const char *what) -> kl_status {
         if (e == hipSuccess) return KL_OK;
         set_error(std::string("kl_eigs: ") + what + ": " + hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? KL_ENOMEM : KL_EHIP;
     };
-    kl_status st;
-    if (!c.s && (st = hip(hipStreamCreate(&c.s), "stream")) != KL_OK) return st;
     if (c.N == N && c.mcap >= mmax && c.ccap >= cmax) return KL_OK;
     release_buffers(c);
     const int mc = std::max(mmax, c.N == N ? c.mcap : 0), cc = std::max(cmax, c.N == N ? c.ccap : 0);
@@ -387,6 +397,7 @@ struct EigRun {
     Solver S;
     double tol = 1e-6, floor_rel = 1e-12, lo_floor = 0.0;
     bool refine = false;
+    bool coeffs = false;                    // return B-spline coefficients v = L^{-T} v'
     int max_applies = 0;
     int precision = KL_F64;                 // precision of the current phase
     std::mt19937_64 rng;
@@ -427,6 +438,27 @@ void free_solver_cache(SolverCache *c) {
     delete c;
 }
 
+// The solver stream of P (created on first use) waits for the work queued on `caller`
+// so far: a start block or an apply the caller issued there is complete before the
+// solver reads or overwrites the shared buffers.
+kl_status order_after(kl_problem *P, hipStream_t caller) {
+    kl_status st = ensure_solver_stream(P);
+    if (st != KL_OK) return st;
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        set_error("kl_eigs: hipEventCreate failed");
+        return KL_EHIP;
+    }
+    hipError_t err = hipEventRecord(e, caller);
+    if (err == hipSuccess) err = hipStreamWaitEvent(P->solver->s, e, 0);
+    (void)hipEventDestroy(e);
+    if (err != hipSuccess) {
+        set_error(std::string("kl_eigs: ordering after the caller's stream: ") + hipGetErrorString(err));
+        return KL_EHIP;
+    }
+    return KL_OK;
+}
+
 // ---- one eigensolve as a resumable run ----------------------------------------------
 // The run stops at every operator application (pending_*); the caller applies A~' in
 // the pending precision to the pending columns (alone, or together with other runs in
@@ -463,6 +495,8 @@ kl_status EigRun::configure(kl_problem *P_, const kl_eigs_opts *opts) {
     // low-precision floor: relative accuracy the low-precision apply can certify
     lo_floor = opts->lo_floor > 0 ? opts->lo_floor
                : precision == KL_F32 ? 2e-6 : precision == KL_BF16X3 ? 5e-5 : precision == KL_BF16 ? 5e-3 : 0.0;
+    if (opts->coeffs != 0 && opts->coeffs != 1) { set_error("kl_eigs: coeffs must be 0 or 1"); return KL_EINVAL; }
+    coeffs = opts->coeffs == 1;
     rng.seed(opts->seed);
     return KL_OK;
 }
@@ -702,18 +736,21 @@ kl_status EigRun::rr_step() {
     const int add = int(std::min<int64_t>(S.b, N - (must_restart ? kk : S.m)));
     if (must_restart) {
         // ---- thick restart -------------------------------------------------------
+        const int newest = S.last;
         std::swap(S.V, S.Vt);
         std::swap(S.AV, S.AVt);
         S.m = kk;
         std::fill(S.H.begin(), S.H.end(), 0.0);
         for (int i = 0; i < kk; ++i) S.H[size_t(i) * S.mmax + i] = theta[i];
         S.restarts += 1;
-        // residuals of the kept vectors are in W (residual_kernel above); the restarted
-        // basis keeps the Arnoldi relation if the old one had it (the residuals then
-        // span at most one block)
+        // residuals of the kept vectors are in W (residual_kernel above).  If the old
+        // basis had the Arnoldi relation they span at most as many directions as its
+        // newest block had columns, and the restarted basis keeps the relation when all
+        // of them are kept; a newest block wider than `add` (the one that follows the
+        // switch to FP64 holds every residual direction of the kept vectors) loses it
         if (add <= 0) { done = true; return KL_OK; }
         if ((st = S.orth_into_basis(S.W, kk, add, rng)) != KL_OK) return st;
-        pending_keeps_krylov = true;
+        pending_keeps_krylov = newest <= add && !S.last_refilled;
     } else {
         // ---- block Krylov expansion from the newest block of AV --------------------
         if (add <= 0) { done = true; return KL_OK; }
@@ -733,8 +770,11 @@ kl_status EigRun::finish(double *evals, double *evecs, int64_t ldv, kl_eigs_repo
     const int kout = std::min<int>(S.k, int(theta.size()));
     for (int i = 0; i < S.k; ++i) evals[i] = i < kout ? theta[i] : 0.0;
     launch_copy_cols(S.Vt, N, evecs, ldv, N, kout, S.s);
-    kl_status st = S.check(hipStreamSynchronize(S.s), "sync");
+    // B-spline coefficients v = L^{-T} v' (Sec. 4.1); W (N x cmax >= k columns) is free now
+    if (coeffs && kout > 0) launch_to_coefficients(P, evecs, ldv, kout, S.W, S.s);
+    kl_status st = S.check(hipGetLastError(), "coefficient transform");
     if (st != KL_OK) return st;
+    if ((st = S.check(hipStreamSynchronize(S.s), "sync")) != KL_OK) return st;
     if (rep) {
         for (int p = 0; p < 4; ++p) {
             rep->n_applies[p] = S.applies[p];
@@ -742,6 +782,7 @@ kl_status EigRun::finish(double *evals, double *evecs, int64_t ldv, kl_eigs_repo
         }
         rep->n_restarts = S.restarts;
         rep->converged = converged;
+        rep->t_setup = P->t_setup;
         rep->t_solve = t_solve;
         rep->t_host_eig = t_host_eig;
         rep->max_rel_residual = max_rel;
@@ -761,7 +802,7 @@ using namespace kl;
 
 extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const double *x0,
                              int32_t nvec0, double *evals, double *evecs, int64_t ldv,
-                             kl_eigs_report *rep) {
+                             kl_eigs_report *rep, void *stream) {
     using clock = std::chrono::steady_clock;
     const auto t0 = clock::now();
     if (!P || P->host_only) { set_error("kl_eigs: NULL or host-only handle"); return KL_EINVAL; }
@@ -771,6 +812,7 @@ extern "C" kl_status kl_eigs(kl_problem *P, const kl_eigs_opts *opts, const doub
     EigRun run;
     kl_status st = run.configure(P, opts);
     if (st != KL_OK) return st;
+    if ((st = order_after(P, static_cast<hipStream_t>(stream))) != KL_OK) return st;
     if ((st = run.begin(x0, nvec0)) != KL_OK) return st;
     while (!run.done) {
         if (!run.pending_done &&
@@ -816,7 +858,7 @@ void parallel_for(int n, F fn) {
 // step (orthogonalisation, Rayleigh-Ritz, restarts) proceeds on host threads, each run
 // on its own stream.
 extern "C" kl_status kl_eigs_batch(kl_batch *B, const kl_eigs_opts *opts, double *evals, double *evecs,
-                                   kl_eigs_report *reps) {
+                                   kl_eigs_report *reps, void *stream) {
     using clock = std::chrono::steady_clock;
     const auto t0 = clock::now();
     if (!B || !opts || !evals || !evecs) { set_error("kl_eigs_batch: NULL argument"); return KL_EINVAL; }
@@ -849,6 +891,10 @@ extern "C" kl_status kl_eigs_batch(kl_batch *B, const kl_eigs_opts *opts, double
         stv[i] = st;
         if (st != KL_OK) msg[i] = kl_last_error();
     };
+    for (int i = 0; i < n; ++i) {
+        kl_status st0 = order_after(batch_problem(B, i), static_cast<hipStream_t>(stream));
+        if (st0 != KL_OK) return st0;
+    }
     parallel_for(n, [&](int i) { record(i, runs[i].begin(nullptr, 0)); });
     kl_status st = first_error();
     if (st != KL_OK) return st;

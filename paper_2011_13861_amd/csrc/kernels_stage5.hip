@@ -733,12 +733,12 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
                   const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop,
-                  bool defer_reduce) {
+                  bool defer_reduce, int max_split) {
     const int rbs = P->s5_rb[precision];
     const int rb = (rbs == 1 || rbs == 4 || (rbs == 8 && precision == KL_F32)) ? rbs : 2;
     int64_t lchunk;
     const int nsplit = stage5_splits(P->Ntpad, stage5_rows_per_wg(precision, rb), P->n_cu,
-                                     P->ws.max_split, P->s5_split[precision], &lchunk);
+                                     max_split > 0 ? max_split : P->ws.max_split, P->s5_split[precision], &lchunk);
     if (ev_start) (void)hipEventRecord(ev_start, s);
     switch (P->hs.d) {
     case 1: launch_dim<1>(precision, P, Y5, Z5, Zf, nsplit, lchunk, rb, wrow, scale, s); break;

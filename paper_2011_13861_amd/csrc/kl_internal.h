@@ -26,6 +26,7 @@ struct HostSetup {
     int64_t N = 0, Nt = 0;
     std::vector<double> C[3];   // composed factor C_k (nt_k x n_k, row-major)
     std::vector<double> E[3];   // B_k(Greville points of the interpolation space) L_k^{-T} (nt_k x n_k)
+    std::vector<double> LT[3];  // L_k^{-T} (n_k x n_k, row-major, upper triangular)
     std::vector<double> X;      // Nt x d, physical Greville points, vec order
     std::vector<double> J;      // Nt, sqrt(det DF)
 };
@@ -77,6 +78,9 @@ struct kl_problem {
     double *dCT[3] = {nullptr, nullptr, nullptr};   // C_k^T, n_k x nt_k row-major
     double *dE[3] = {nullptr, nullptr, nullptr};    // E_k, nt_k x n_k row-major (kl_kle_field)
     double *dET[3] = {nullptr, nullptr, nullptr};   // E_k^T
+    double *dLT[3] = {nullptr, nullptr, nullptr};   // L_k^{-T}, n_k x n_k row-major (coefficients)
+    double *dL1[3] = {nullptr, nullptr, nullptr};   // L_k^{-1} (its transpose)
+    double t_setup = 0.0;                           // seconds spent in kl_setup
     kl::Workspace ws;
     kl::SolverCache *solver = nullptr;
     int n_cu = 256;
@@ -203,18 +207,24 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 // kernel (the split sums that follow are outside).  With defer_reduce and more than one
 // split, the split sums are left to the consumer: Z5 then holds the unscaled partials
 // (split q of column j at Z5 + (q kBW + j) Ntpad) and Zf is not written.
+// max_split caps the split count (the partials buffer Z5 holds that many; 0 = the
+// problem's own workspace cap).
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
                   const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start = nullptr,
-                  hipEvent_t ev_stop = nullptr, bool defer_reduce = false);
+                  hipEvent_t ev_stop = nullptr, bool defer_reduce = false, int max_split = 0);
 
 // kl_setup with or without the single-problem apply workspace (T0/T1, stage-5 buffers);
-// problems of a batch use the batch's arenas instead.
-kl_status setup_problem(const kl_desc *desc, bool workspace, kl_problem **out);
+// problems of a batch use the batch's arenas instead.  Uploads on `s`, then waits for it.
+kl_status setup_problem(const kl_desc *desc, bool workspace, hipStream_t s, kl_problem **out);
+// Standard-form vectors to B-spline coefficients, v = L^{-T} v' (Sec. 4.1), in place on
+// nvec columns of x (ld >= N), using `tmp` (N x nvec, ld N) as the ping-pong buffer.
+void launch_to_coefficients(const kl_problem *P, double *x, int64_t ldx, int nvec, double *tmp, hipStream_t s);
 void destroy_problem(kl_problem *P);
 int64_t max_intermediate(const HostSetup &hs);
-// One chunk (<= kBW columns) of the single-problem apply.
+// One chunk (<= kBW columns) of the single-problem apply, on the problem's workspace or
+// on `ws` (same layout; its padding rows of the stage-5 inputs must be zero).
 kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx, double *y,
-                      int64_t ldy, hipStream_t s);
+                      int64_t ldy, hipStream_t s, const Workspace *ws = nullptr);
 
 // ---- batches of problems (batch.hip) ---------------------------------------------------
 int batch_size(const kl_batch *B);

@@ -1,7 +1,8 @@
 // Host setup of the KL operator in FP64 (runs once per problem, Sec. 3.5 and 4.1-4.3).
 //
 // Per direction k:
-//   knots (open uniform, C^{p-1}), B-spline evaluation by the triangular Cox-de Boor
+//   knots (open uniform, C^{p-1}, or an explicit open knot vector), B-spline evaluation
+//   by the triangular Cox-de Boor
 //   scheme restricted to the p+1 non-zero functions, Greville abscissae (knot averages),
 //   Z_k = int B_i B_j (Gauss-Legendre, p+1 points per element; Remark massmatrix),
 //   L_k = chol(Z_k) (eq. cholesky), Bt_k[i][j] = Bt_j(xhat_i) (eq. interpolation_matrix)
@@ -13,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <sstream>
+#include <string>
 
 #include "kl_internal.h"
 
@@ -58,6 +60,46 @@ void nonzero_basis(const std::vector<double> &t, int p, int s, double x, double 
         }
         out[j] = carry;
     }
+}
+
+// Values and first derivatives of the p+1 non-zero B-splines at x: the derivative of
+// B_{i,p} is p B_{i,p-1} / (t_{i+p} - t_i) - p B_{i+1,p-1} / (t_{i+p+1} - t_{i+1}) (Sec. 2.3).
+void nonzero_basis_ders(const std::vector<double> &t, int p, int s, double x, double *val, double *der) {
+    double lower[32];
+    nonzero_basis(t, p - 1, s, x, lower);      // B_{s-p+1..s, p-1}
+    for (int a = 0; a <= p; ++a) {
+        const int i = s - p + a;
+        double d = 0.0;
+        if (a >= 1) {
+            const double den = t[i + p] - t[i];
+            if (den > 0.0) d += p * lower[a - 1] / den;
+        }
+        if (a <= p - 1) {
+            const double den = t[i + p + 1] - t[i + 1];
+            if (den > 0.0) d -= p * lower[a] / den;
+        }
+        der[a] = d;
+    }
+    nonzero_basis(t, p, s, x, val);
+}
+
+// An explicit knot vector: finite, nondecreasing, open (first and last value repeated
+// p + 1 times), from 0 to 1, interior values repeated at most max_mult times.
+bool valid_knots(const double *t, int len, int p, int max_mult, std::string &why) {
+    if (!t || len < p + 2 + p) { why = "needs at least 2 p + 2 entries"; return false; }
+    for (int i = 0; i < len; ++i)
+        if (!std::isfinite(t[i]) || (i > 0 && t[i] < t[i - 1])) { why = "must be finite and nondecreasing"; return false; }
+    if (t[0] != 0.0 || t[len - 1] != 1.0) { why = "must run from 0 to 1"; return false; }
+    for (int i = 0; i <= p; ++i)
+        if (t[i] != 0.0 || t[len - 1 - i] != 1.0) { why = "must be open (end values repeated p + 1 times)"; return false; }
+    if (t[p + 1] == 0.0 || t[len - p - 2] == 1.0) { why = "must be open (end values repeated p + 1 times)"; return false; }
+    for (int i = p + 1; i < len - p - 1;) {
+        int j = i;
+        while (j < len - p - 1 && t[j] == t[i]) ++j;
+        if (j - i > max_mult) { why = "interior values may repeat at most p times (C^0)"; return false; }
+        i = j;
+    }
+    return true;
 }
 
 std::vector<double> greville(const std::vector<double> &t, int p, int n) {
@@ -177,14 +219,15 @@ void lu_solve_transposed(const std::vector<double> &LU, const std::vector<int> &
 }
 
 struct Dir {
-    int p, ne, pt, net, n, nt;
+    int p, pt, n, nt;
     std::vector<double> t, tt;
 };
 
 // C_k = Bt^{-T} M L^{-T} for one direction; also E_k = B(g) L^{-T}, the trial B-splines at
 // the interpolation Greville abscissae g applied to standard-form coefficients (Sec. 3.4,
 // 4.1), which evaluates eigenfunctions there.
-kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &E, std::vector<double> &g) {
+kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &E, std::vector<double> &LT,
+                          std::vector<double> &g) {
     const int n = D.n, nt = D.nt;
     // Z_k by Gauss-Legendre with p+1 points per element
     std::vector<double> xs, ws;
@@ -259,6 +302,15 @@ kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &E
             double s = e[i];
             for (int k = 0; k < i; ++k) s -= Z[size_t(i) * n + k] * e[k];
             e[i] = s / Z[size_t(i) * n + i];
+        }
+    }
+    // L^{-T} (upper triangular): column j solves L^T x = e_j by back substitution
+    LT.assign(size_t(n) * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        for (int i = j; i >= 0; --i) {
+            double s = i == j ? 1.0 : 0.0;
+            for (int k = i + 1; k <= j; ++k) s -= Z[size_t(k) * n + i] * LT[size_t(k) * n + j];
+            LT[size_t(i) * n + j] = s / Z[size_t(i) * n + i];
         }
     }
     // C = Bt^{-T} W, column by column
@@ -339,9 +391,83 @@ bool map_point(const kl_desc &desc, int d, const double *u, double *x, double &d
         det = 1.0 + eps * dots;
         return true;
     }
+    case KL_MAP_TENSOR_NURBS: {
+        // F(u) = A(u) / W(u), A = sum_a w_a P_a N_a(u), W = sum_a w_a N_a(u) over the
+        // (p_k + 1)^d non-zero tensor functions; dF/du_k = (dA/du_k - F dW/du_k) / W
+        double val[3][32], der[3][32];
+        int span[3], m[3];
+        for (int k = 0; k < d; ++k) {
+            const int pk = desc.map_degree[k];
+            m[k] = desc.map_nknots[k] - pk - 1;
+            const std::vector<double> t(desc.map_knots[k], desc.map_knots[k] + desc.map_nknots[k]);
+            span[k] = find_span(t, pk, m[k], u[k]);
+            nonzero_basis_ders(t, pk, span[k], u[k], val[k], der[k]);
+        }
+        double A[3] = {0, 0, 0}, dA[3][3] = {{0}}, W = 0.0, dW[3] = {0, 0, 0};
+        const int q0 = desc.map_degree[0] + 1, q1 = d > 1 ? desc.map_degree[1] + 1 : 1,
+                  q2 = d > 2 ? desc.map_degree[2] + 1 : 1;
+        for (int c = 0; c < q2; ++c)
+            for (int b = 0; b < q1; ++b)
+                for (int a = 0; a < q0; ++a) {
+                    const int ia[3] = {a, b, c};
+                    int64_t idx = 0, stride = 1;
+                    double Nv = 1.0, dN[3] = {1.0, 1.0, 1.0};
+                    for (int k = 0; k < d; ++k) {
+                        const int i = span[k] - desc.map_degree[k] + ia[k];
+                        idx += stride * i;
+                        stride *= m[k];
+                        Nv *= val[k][ia[k]];
+                        for (int j = 0; j < d; ++j) dN[j] *= (j == k ? der[k][ia[k]] : val[k][ia[k]]);
+                    }
+                    const double w = desc.map_weights ? desc.map_weights[idx] : 1.0;
+                    const double *P = desc.map_ctrl + size_t(idx) * d;
+                    W += w * Nv;
+                    for (int j = 0; j < d; ++j) dW[j] += w * dN[j];
+                    for (int i = 0; i < d; ++i) {
+                        A[i] += w * Nv * P[i];
+                        for (int j = 0; j < d; ++j) dA[i][j] += w * dN[j] * P[i];
+                    }
+                }
+        double D[3][3];
+        for (int i = 0; i < d; ++i) x[i] = A[i] / W;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) D[i][j] = (dA[i][j] - x[i] * dW[j]) / W;
+        if (d == 1) det = D[0][0];
+        else if (d == 2) det = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+        else
+            det = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) -
+                  D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+                  D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+        return true;
+    }
     default:
         return false;
     }
+}
+
+// Validates the TENSOR_NURBS fields of the description.
+kl_status check_nurbs_map(const kl_desc &desc, int d) {
+    int64_t npts = 1;
+    for (int k = 0; k < d; ++k) {
+        const int pk = desc.map_degree[k];
+        std::string why;
+        if (pk < 1 || pk > 20) { set_error("map_degree must be in 1..20"); return KL_EINVAL; }
+        if (!valid_knots(desc.map_knots[k], desc.map_nknots[k], pk, pk, why)) {
+            set_error("map knot vector " + std::to_string(k) + ": " + why);
+            return KL_EINVAL;
+        }
+        npts *= desc.map_nknots[k] - pk - 1;
+    }
+    if (!desc.map_ctrl) { set_error("TENSOR_NURBS needs map_ctrl"); return KL_EINVAL; }
+    for (int64_t i = 0; i < npts * d; ++i)
+        if (!std::isfinite(desc.map_ctrl[i])) { set_error("map_ctrl must be finite"); return KL_EINVAL; }
+    if (desc.map_weights)
+        for (int64_t i = 0; i < npts; ++i)
+            if (!(desc.map_weights[i] > 0.0) || !std::isfinite(desc.map_weights[i])) {
+                set_error("map_weights must be positive");
+                return KL_EINVAL;
+            }
+    return KL_OK;
 }
 
 }  // namespace
@@ -349,8 +475,12 @@ bool map_point(const kl_desc &desc, int d, const double *u, double *x, double &d
 kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
     const int d = desc.dim;
     if (d < 1 || d > 3) { set_error("dim must be 1, 2 or 3"); return KL_EINVAL; }
-    if (desc.map_kind < KL_MAP_IDENTITY || desc.map_kind > KL_MAP_SINE_CUBE) {
+    if (desc.map_kind < KL_MAP_IDENTITY || desc.map_kind > KL_MAP_TENSOR_NURBS) {
         set_error("unknown map_kind"); return KL_EINVAL;
+    }
+    if (desc.map_kind == KL_MAP_TENSOR_NURBS) {
+        kl_status st = check_nurbs_map(desc, d);
+        if (st != KL_OK) return st;
     }
     if ((desc.map_kind == KL_MAP_ANNULUS_NURBS || desc.map_kind == KL_MAP_ANNULUS_POLAR) && d != 2) {
         set_error("annulus maps are two-dimensional"); return KL_EINVAL;
@@ -374,24 +504,44 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
     for (int k = 0; k < d; ++k) {
         Dir &r = D[k];
         r.p = desc.degree[k];
-        r.ne = desc.nelem[k];
         r.pt = desc.interp_degree[k] > 0 ? desc.interp_degree[k] : r.p;
-        r.net = desc.interp_nelem[k] > 0 ? desc.interp_nelem[k] : r.ne;
-        if (r.p < 1 || r.p > 20 || r.pt < 1 || r.pt > 20 || r.ne < 1 || r.net < 1 ||
-            r.ne > 100000 || r.net > 100000) {
-            set_error("degrees must be in 1..20 and element counts >= 1"); return KL_EINVAL;
+        if (r.p < 1 || r.p > 20 || r.pt < 1 || r.pt > 20) { set_error("degrees must be in 1..20"); return KL_EINVAL; }
+        std::string why;
+        if (desc.knots[k]) {
+            if (!valid_knots(desc.knots[k], desc.nknots[k], r.p, r.p, why)) {
+                set_error("trial knot vector " + std::to_string(k) + ": " + why);
+                return KL_EINVAL;
+            }
+            r.t.assign(desc.knots[k], desc.knots[k] + desc.nknots[k]);
+        } else {
+            if (desc.nelem[k] < 1 || desc.nelem[k] > 100000) { set_error("element counts must be >= 1"); return KL_EINVAL; }
+            r.t = uniform_knots(r.p, desc.nelem[k]);
         }
-        const int mult = desc.interp_mult[k] > 0 ? desc.interp_mult[k] : 1;
-        if (desc.interp_mult[k] < 0 || mult > r.pt) {
-            set_error("interp_mult must be in 1..interp degree (0 = 1); discontinuous "
-                      "interpolation spaces are not supported");
-            return KL_EINVAL;
+        if (desc.interp_knots[k]) {
+            if (!valid_knots(desc.interp_knots[k], desc.interp_nknots[k], r.pt, r.pt, why)) {
+                set_error("interpolation knot vector " + std::to_string(k) + ": " + why);
+                return KL_EINVAL;
+            }
+            r.tt.assign(desc.interp_knots[k], desc.interp_knots[k] + desc.interp_nknots[k]);
+        } else if (desc.knots[k] && r.pt == r.p && desc.interp_nelem[k] == 0 && desc.interp_mult[k] == 0) {
+            r.tt = r.t;                      // the interpolation space is the trial space
+        } else {
+            const int net = desc.interp_nelem[k] > 0 ? desc.interp_nelem[k]
+                            : desc.knots[k] ? int(breakpoints(r.t).size()) - 1 : desc.nelem[k];
+            const int mult = desc.interp_mult[k] > 0 ? desc.interp_mult[k] : 1;
+            if (net < 1 || net > 100000) { set_error("element counts must be >= 1"); return KL_EINVAL; }
+            if (desc.interp_mult[k] < 0 || mult > r.pt) {
+                set_error("interp_mult must be in 1..interp degree (0 = 1); discontinuous "
+                          "interpolation spaces are not supported");
+                return KL_EINVAL;
+            }
+            r.tt = uniform_knots(r.pt, net, mult);
         }
-        r.n = r.ne + r.p;
-        r.nt = r.pt + 1 + (r.net - 1) * mult;
-        r.t = uniform_knots(r.p, r.ne);
-        r.tt = uniform_knots(r.pt, r.net, mult);
-        hs.p[k] = r.p; hs.ne[k] = r.ne; hs.pt[k] = r.pt; hs.net[k] = r.net;
+        r.n = int(r.t.size()) - r.p - 1;
+        r.nt = int(r.tt.size()) - r.pt - 1;
+        hs.p[k] = r.p; hs.pt[k] = r.pt;
+        hs.ne[k] = int(breakpoints(r.t).size()) - 1;
+        hs.net[k] = int(breakpoints(r.tt).size()) - 1;
         hs.n[k] = r.n; hs.nt[k] = r.nt;
         N *= r.n;
         Nt *= r.nt;
@@ -401,7 +551,7 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
     hs.Nt = Nt;
     std::vector<double> g[3];
     for (int k = 0; k < d; ++k) {
-        kl_status st = build_direction(D[k], hs.C[k], hs.E[k], g[k]);
+        kl_status st = build_direction(D[k], hs.C[k], hs.E[k], hs.LT[k], g[k]);
         if (st != KL_OK) return st;
     }
     hs.X.assign(size_t(Nt) * d, 0.0);

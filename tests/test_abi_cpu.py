@@ -44,8 +44,22 @@ def _oracle_factor(P, k):
     return np.linalg.solve(P.Bt[k].T, W)              # Bt^{-T} (M L^{-T})
 
 
+from test_oracle_nurbs import quarter_annulus, quarter_cylinder_shell, insert_knot  # noqa: E402
+
+NONUNIFORM = {"dim": 2, "degree": [2, 3],
+              "knots": [[0, 0, 0, 0.1, 0.35, 0.35, 0.6, 1, 1, 1], [0, 0, 0, 0, 0.5, 0.8, 1, 1, 1, 1]],
+              "interp_degree": [2, 2], "interp_knots": [None, [0, 0, 0, 0.2, 0.4, 0.6, 0.8, 1, 1, 1]],
+              "map": {"kind": "box", "lo": [0.0, 0.0], "hi": [1.5, 1.0]},
+              "cov": {"kind": "exp", "corr_len": [0.4, 0.6]}}
+CYLINDER = {"dim": 3, "degree": [1, 2, 2], "nelem": [3, 6, 5], "map": insert_knot(quarter_cylinder_shell(), 1, 0.5),
+            "cov": {"kind": "exp", "corr_len": [0.5, 0.5, 0.5]}}
+
 CASES = [
     workloads.unit_square(16, 2, "exp", 1.0),
+    NONUNIFORM,
+    CYLINDER,
+    {"dim": 2, "degree": [3, 2], "nelem": [7, 9], "map": quarter_annulus(1.0, 2.0),
+     "cov": {"kind": "sqexp", "corr_len": [0.5, 0.5]}},
     workloads.quarter_annulus(12, 3, "sqexp", (0.5, 0.7)),
     workloads.sine_cube(5, 2, "exp", 0.5),
     {"dim": 1, "degree": [3], "nelem": [9], "interp_degree": [2], "interp_nelem": [14],
@@ -64,6 +78,9 @@ CASES = [
 
 @pytest.mark.parametrize("desc", CASES)
 def test_host_setup_matches_oracle(desc):
+    """Sizes, mapped Greville points, J and the composed factors against the oracle (uniform
+    and explicit nonuniform knots with a C^0 interior knot, interpolation spaces of their
+    own, every map kind including the general tensor NURBS map in 2D and 3D)."""
     P = operator.Problem(desc)
     H = kl.Problem(desc, host_only=True)
     assert H.N == P.N and H.Nt == P.Nt and H.n == P.n and H.nt == P.nt
@@ -124,3 +141,45 @@ def test_host_only_handle_rejects_device_calls():
     assert st == -1
     assert b"host-only" in kl.lib().kl_last_error()
     H.close()
+
+
+def test_explicit_knots_and_nurbs_map_equal_builtin_forms():
+    """Explicit open uniform knots give the element-count problem; the quarter annulus as a
+    general NURBS map gives the built-in exact annulus; both to rounding."""
+    base = {"dim": 2, "degree": [2, 3], "nelem": [4, 3], "map": {"kind": "annulus_nurbs", "r0": 1.0, "r1": 2.0},
+            "cov": {"kind": "exp", "corr_len": [0.5, 0.5]}}
+    other = dict(base, knots=[[0, 0, 0, .25, .5, .75, 1, 1, 1], [0, 0, 0, 0, 1 / 3, 2 / 3, 1, 1, 1, 1]],
+                 map=quarter_annulus(1.0, 2.0))
+    other.pop("nelem")
+    A, B = kl.Problem(base, host_only=True), kl.Problem(other, host_only=True)
+    assert A.N == B.N and A.Nt == B.Nt
+    Xa, Ja = A.points()
+    Xb, Jb = B.points()
+    assert np.max(np.abs(Xa - Xb)) < 1e-14 and np.max(np.abs(Ja - Jb)) < 1e-14
+    for k in range(2):
+        assert np.max(np.abs(A.factor(k) - B.factor(k))) < 1e-13
+
+
+def test_knot_and_nurbs_errors():
+    good = {"dim": 2, "degree": [2, 2], "knots": [[0, 0, 0, 0.5, 1, 1, 1], None], "nelem": [0, 3],
+            "map": {"kind": "identity"}, "cov": {"kind": "exp", "corr_len": [1.0, 1.0]}}
+    assert _status_of(good) == 0
+    for bad in ([0, 0, 0.5, 1, 1, 1],            # not open at 0
+                [0, 0, 0, 0.5, 1, 1],            # not open at 1
+                [0, 0, 0, 0.6, 0.5, 1, 1, 1],    # decreasing
+                [0, 0, 0, 0.5, 0.5, 0.5, 1, 1, 1],   # interior multiplicity p + 1
+                [0, 0, 0, 0.5, 1, 1, 1.5, 1.5, 1.5],  # beyond 1
+                [0, 0, 0, float("nan"), 1, 1, 1],
+                [0, 0, 1, 1]):                   # too short for p = 2
+        assert _status_of(dict(good, knots=[bad, None])) == -1, bad
+    assert _status_of(dict(good, interp_knots=[[0, 0, 0, 0.5, 0.5, 0.5, 1, 1, 1], None])) == -1
+    g = quarter_annulus()
+    ann = {"dim": 2, "degree": [2, 2], "nelem": [3, 3], "map": g, "cov": {"kind": "exp", "corr_len": [1.0, 1.0]}}
+    assert _status_of(ann) == 0
+    w = np.array(g["weights"]); w[1, 1] = 0.0
+    assert _status_of(dict(ann, map=dict(g, weights=w))) == -1
+    assert _status_of(dict(ann, map=dict(g, knots=[[0, 0, 1], g["knots"][1]]))) == -1
+    assert _status_of(dict(ann, map=dict(g, degree=[0, 2]))) == -1
+    # a control net folded over itself: det DF changes sign -> KL_EDOMAIN
+    c = np.array(g["ctrl"]); c[0], c[1] = g["ctrl"][1], g["ctrl"][0]
+    assert _status_of(dict(ann, map=dict(g, ctrl=c))) == -4
