@@ -11,17 +11,22 @@
  * kind: 0 exp, 1 sqexp, 2 exp_l1, 3 const, 4 lin.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 
-int oracle_stage5(int d, int64_t n, const double *X, int b, const double *Y,
-                  int kind, double sigma2, const double *ell, double *Z)
+/* Rows [r0, r1) of Z' only (Z holds r1 - r0 rows), on `nthreads` threads (0 = the
+ * OpenMP default): a bounded sample of the same work for timing on host cores. */
+int oracle_stage5_rows(int d, int64_t n, const double *X, int b, const double *Y,
+                       int kind, double sigma2, const double *ell, int64_t r0, int64_t r1,
+                       int nthreads, double *Z)
 {
-    if (d < 1 || d > 3 || n < 0 || b < 1) return -1;
+    if (d < 1 || d > 3 || n < 0 || b < 1 || r0 < 0 || r1 > n || r0 > r1) return -1;
     double inv[3] = {1.0, 1.0, 1.0};
     for (int k = 0; k < d; ++k) inv[k] = 1.0 / ell[k];
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t i = 0; i < n; ++i) {
-        double *zi = Z + i * b;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t i = r0; i < r1; ++i) {
+        double *zi = Z + (i - r0) * b;
         for (int j = 0; j < b; ++j) zi[j] = 0.0;
         for (int64_t l = 0; l < n; ++l) {
             double g;
@@ -48,4 +53,10 @@ int oracle_stage5(int d, int64_t n, const double *X, int b, const double *Y,
         }
     }
     return 0;
+}
+
+int oracle_stage5(int d, int64_t n, const double *X, int b, const double *Y,
+                  int kind, double sigma2, const double *ell, double *Z)
+{
+    return oracle_stage5_rows(d, n, X, b, Y, kind, sigma2, ell, 0, n, 0, Z);
 }

@@ -28,26 +28,30 @@ def _load():
         if not os.path.exists(_SO):
             build_cstage5()
         lib = ctypes.CDLL(_SO)
-        lib.oracle_stage5.restype = ctypes.c_int
-        lib.oracle_stage5.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
-                                      ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
-                                      ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_stage5_rows.restype = ctypes.c_int
+        lib.oracle_stage5_rows.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                           ctypes.c_void_p]
         _lib = lib
     return _lib
 
 
-def stage5(prob, Yp):
-    """Z' = Gamma Y' for the oracle Problem `prob`, computed by the C/OpenMP loop."""
+def stage5(prob, Yp, rows=None, threads=0):
+    """Z' = Gamma Y' for the oracle Problem `prob`, computed by the C/OpenMP loop.
+    rows = (r0, r1) computes only those rows of Z' (a bounded timing sample); threads > 0
+    fixes the number of OpenMP threads."""
     lib = _load()
     X = np.ascontiguousarray(prob.X, dtype=np.float64)
     one = Yp.ndim == 1
     Y = np.ascontiguousarray(Yp.reshape(len(Yp), -1), dtype=np.float64)
-    Z = np.empty_like(Y)
+    r0, r1 = (0, X.shape[0]) if rows is None else (int(rows[0]), int(rows[1]))
+    Z = np.empty((r1 - r0, Y.shape[1]), dtype=np.float64)
     d = X.shape[1]
     ell = np.ascontiguousarray(np.asarray(prob.cov.get("corr_len", [1.0] * d), dtype=np.float64)[:d])
-    rc = lib.oracle_stage5(d, X.shape[0], X.ctypes.data, Y.shape[1], Y.ctypes.data,
-                           _KINDS[prob.cov["kind"]], float(prob.cov.get("sigma2", 1.0)),
-                           ell.ctypes.data, Z.ctypes.data)
+    rc = lib.oracle_stage5_rows(d, X.shape[0], X.ctypes.data, Y.shape[1], Y.ctypes.data,
+                                _KINDS[prob.cov["kind"]], float(prob.cov.get("sigma2", 1.0)),
+                                ell.ctypes.data, r0, r1, int(threads), Z.ctypes.data)
     if rc != 0:
         raise RuntimeError("oracle_stage5 failed")
     return Z.reshape(-1) if one else Z

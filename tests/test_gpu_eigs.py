@@ -22,23 +22,47 @@ from oracle import operator
 pytestmark = pytest.mark.gpu
 
 
-def check_pairs(w, V, w_ref, V_ref, k, vec_tol=1e-5):
+def check_pairs(w, V, w_ref, V_ref, k, vec_tol=1e-5, tol=1e-10, floor=1e-12):
+    """Eigenvalues within 1e-6 relative (+ 1e-12 lambda_1); eigenvectors within vec_tol
+    (isolated) or by the largest principal angle (clusters).  A pair is compared only when
+    the stopping criterion the solve ran at determines its vector to well within vec_tol:
+    the vector error is at most residual / gap, and the residual bound max(tol theta_i,
+    floor theta_1) divided by the absolute gap to the nearest eigenvalue outside its
+    cluster must stay below vec_tol / 10 (the absolute floor leaves the vectors of
+    eigenvalues near 1e-12 lambda_1 undetermined)."""
     w_all = np.asarray(w_ref)
     lam1 = w_all[0]
     assert np.all(np.abs(w[:k] - w_all[:k]) <= 1e-6 * np.abs(w_all[:k]) + 1e-12 * lam1), (w[:k] - w_all[:k])
+    compared = 0
     for g in oeigs.clusters(w_all, rel_gap=1e-3):
         if g[0] >= k:
             break
         if g[-1] >= k:
             continue                     # straddles index k
+        gaps = [abs(w_all[g[0] - 1] - w_all[g[0]])] if g[0] > 0 else []
+        if g[-1] + 1 < len(w_all):
+            gaps.append(abs(w_all[g[-1]] - w_all[g[-1] + 1]))
+        res = max(tol * abs(w_all[g[0]]), floor * lam1)
+        if not gaps or res / min(gaps) > 0.1 * vec_tol:
+            continue                     # not determined to the bar by the criterion
+        compared += len(g)
         if len(g) == 1:
             i = g[0]
             s = np.sign(V[:, i] @ V_ref[:, i])
             assert np.linalg.norm(V[:, i] - s * V_ref[:, i]) <= vec_tol, i
         else:
-            sv = np.linalg.svd(V_ref[:, g].T @ V[:, g], compute_uv=False)
-            sin = np.sqrt(max(0.0, 1.0 - sv.min() ** 2))
-            assert sin <= vec_tol, (g, sin)
+            assert subspace_sin(V[:, g], V_ref[:, g]) <= vec_tol, (g, subspace_sin(V[:, g], V_ref[:, g]))
+    return compared
+
+
+def subspace_sin(A, B):
+    """Sine of the largest principal angle between span A and span B, as the spectral norm
+    of the part of an orthonormal basis of A outside span B.  (Taking it as sqrt(1 -
+    sigma_min^2) from the singular values of B^T A would turn a departure from
+    orthonormality of 1e-9, e.g. vectors stored in FP32, into an angle of 4e-5.)"""
+    Qa = np.linalg.qr(A)[0]
+    Qb = np.linalg.qr(B)[0]
+    return np.linalg.norm(Qa - Qb @ (Qb.T @ Qa), 2)
 
 
 def _solve(desc, k, precision, tol=1e-10, **kw):
@@ -63,17 +87,65 @@ def test_config1_matches_dense_oracle(precision):
     assert np.all(r <= 1e-10 * w + 1e-12 * w[0] + 1e-14)
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+FORMS = ["f64", "f32", "bf16x3", "bf16"]
+_ARPACK = {}
+
+
+def _arpack(name, desc, kref):
+    if name not in _ARPACK:
+        P = operator.Problem(desc)
+        s5 = lambda Y: cstage5.stage5(P, Y)   # noqa: E731
+        _ARPACK[name] = oeigs.iterative_eigs(P, kref, tol=1e-13, stage5=s5)
+    return _ARPACK[name]
+
+
+@pytest.mark.parametrize("precision", FORMS)
 def test_config2_matches_arpack_oracle(precision):
+    """Config 2 (64x64 cubic quarter annulus, sqexp L = 0.5, k = 40) in every form: FP64,
+    and FP32 / BF16x3 / BF16 stage 5 with the FP64 refinement phase (Sec. 4.4.2 eigenproblem,
+    solved to 1e-10 under the FP64 operator)."""
     desc, k, _ = workloads.config("c2")
-    P = operator.Problem(desc)
-    s5 = lambda Y: cstage5.stage5(P, Y)   # noqa: E731
-    w_ref, V_ref = oeigs.iterative_eigs(P, k + 8, tol=1e-13, stage5=s5)
+    w_ref, V_ref = _arpack("c2", desc, k + 8)
     G, w, V, rep = _solve(desc, k, precision)
     assert rep["status"] == "KL_OK", rep
-    check_pairs(w, V, w_ref, V_ref, k)
-    if precision == "f32":
-        assert rep["n_applies"][1] > 0 and rep["n_applies"][0] > 0
+    assert check_pairs(w, V, w_ref, V_ref, k) >= k // 2
+    p = kl.PRECISIONS[precision]
+    assert rep["n_applies"][p] > 0
+    if precision != "f64":
+        assert rep["n_applies"][0] > 0
+
+
+@pytest.mark.parametrize("precision", FORMS)
+def test_cube_mid_size_matches_arpack_oracle(precision):
+    """A 3D problem of middle size (12^3 quadratic sine-perturbed cube, exp L = 0.4, 2,744
+    dofs, k = 30) in every form against ARPACK on the oracle."""
+    desc = workloads.sine_cube(12, 2, "exp", 0.4)
+    k = 30
+    w_ref, V_ref = _arpack("cube12", desc, k + 8)
+    G, w, V, rep = _solve(desc, k, precision)
+    assert rep["status"] == "KL_OK", rep
+    assert check_pairs(w, V, w_ref, V_ref, k) >= k // 2
+
+
+@pytest.fixture(scope="module")
+def c3_golden():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_eigs.npz")
+    z = np.load(path)
+    return z["evals"], z["evecs"].astype(np.float64)
+
+
+@pytest.mark.parametrize("precision", FORMS)
+def test_config3_matches_oracle_eigenpairs(c3_golden, precision):
+    """Config 3 (24^3 perturbed cube, exp L = 0.5, k = 50, block 32) in every form against
+    the oracle's ARPACK eigenpairs (tests/golden/c3_eigs.npz, written by
+    tests/golden/make_c3_eigs.py from the oracle alone)."""
+    w_ref, V_ref = c3_golden
+    desc, k, b = workloads.config("c3")
+    G, w, V, rep = _solve(desc, k, precision, block=b)
+    assert rep["status"] == "KL_OK" and rep["converged"] == k, rep
+    assert np.max(np.abs(V.T @ V - np.eye(k))) < 1e-8
+    assert check_pairs(w, V, w_ref, V_ref, k) >= k // 2
 
 
 def test_default_tolerance_meets_criterion_under_fp64():
@@ -138,13 +210,13 @@ def test_eigs_errors():
 
 
 def test_config3_residuals_under_fp64_apply():
-    """Config 3 (3-D, 24^3 quadratic, k = 50): both forms meet the criterion at 1e-6 under
-    the FP64 apply (itself checked against the oracle elsewhere), the basis is
-    orthonormal, and the two forms agree on the eigenvalues."""
+    """Config 3 (3-D, 24^3 quadratic, k = 50) at the metric's tolerance: every form meets
+    the criterion at 1e-6 under the FP64 apply (itself checked against the oracle
+    elsewhere), the basis is orthonormal, and the forms agree on the eigenvalues."""
     desc, k, b = workloads.config("c3")
     G = kl.Problem(desc)
     ws = {}
-    for prec in ("f64", "f32"):
+    for prec in FORMS:
         w, V, rep = G.eigs(k, precision=prec, block=b, tol=1e-6)
         assert rep["status"] == "KL_OK" and rep["converged"] == k, (prec, rep)
         Y = kl.new_block(G.N, k)
@@ -155,4 +227,45 @@ def test_config3_residuals_under_fp64_apply():
         assert np.all(r <= np.maximum(1e-6 * w, 1e-12 * w[0]) * 1.01), (prec, np.max(r / w))
         assert np.max(np.abs(Vh.T @ Vh - np.eye(k))) < 1e-8, prec
         ws[prec] = w
-    assert np.all(np.abs(ws["f32"] - ws["f64"]) <= 2e-6 * np.abs(ws["f64"])), np.max(np.abs(ws["f32"] / ws["f64"] - 1))
+    for prec in FORMS[1:]:
+        assert np.all(np.abs(ws[prec] - ws["f64"]) <= 2e-6 * np.abs(ws["f64"])), (prec, np.max(np.abs(ws[prec] / ws["f64"] - 1)))
+
+
+def test_coefficients_output_matches_oracle():
+    """coeffs = 1 returns v = L^{-T} v' (Sec. 4.1): the same solve (same seed) with coeffs =
+    0, transformed by the oracle's stage 1, gives it; the eigenfunctions have unit L2 norm
+    (v^T Z v = 1 with the oracle's mass matrix)."""
+    for desc in (workloads.config("c1")[0], workloads.sine_cube(5, 2, "exp", 0.5)):
+        P = operator.Problem(desc)
+        G = kl.Problem(desc)
+        k = 12
+        w0, V0, _ = G.eigs(k, tol=1e-8, seed=3)
+        w1, V1, rep = G.eigs(k, tol=1e-8, seed=3, coeffs=True)
+        V0, V1 = V0.cpu().numpy(), V1.cpu().numpy()
+        assert np.array_equal(w0, w1)
+        ref = P.to_coefficients(V0)
+        assert np.max(np.abs(V1 - ref)) <= 1e-12 * np.max(np.abs(ref))
+        Z = P.mass_dense()
+        assert np.max(np.abs(np.diag(V1.T @ Z @ V1) - 1.0)) < 1e-10
+        assert rep["t_setup"] > 0.0
+
+
+def test_solve_is_ordered_after_the_callers_stream():
+    """A start block produced on a non-default stream (behind a long queue of work there) is
+    complete before the solver reads it: exact eigenvectors as x0 converge at once."""
+    desc, k, _ = workloads.config("c1")
+    P = operator.Problem(desc)
+    w_ref, V_ref = oeigs.dense_eigs(P, 32)
+    G = kl.Problem(desc)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        big = torch.randn(4096, 4096, dtype=torch.float64, device="cuda")
+        for _ in range(6):
+            big = big @ big * 1e-3
+        x0 = (torch.from_numpy(np.ascontiguousarray(V_ref.T)).cuda() + 0.0 * big[0, 0]).T
+        y = kl.new_block(G.N, 32)
+        G.apply(x0, y, "f64", stream=s)
+        w, V, rep = G.eigs(k, precision="f64", tol=1e-8, x0=x0, stream=s)
+    assert rep["status"] == "KL_OK"
+    assert sum(rep["n_block_applies"]) <= 3
+    assert np.all(np.abs(w - w_ref[:k]) <= 1e-10 * w_ref[0])
