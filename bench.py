@@ -1,14 +1,16 @@
 """Benchmark of the covariance apply and of time-to-k eigenpairs on one MI355X.
 
 A step is one covariance apply (Algorithm 1) of a 32-vector block: forward Kronecker
-stages, the stage-5 covariance-times-block kernel in the workload's precision, backward
-Kronecker stages.  value = pair evaluations per second = Ntilde^2 per step / step time.
-The same run also times the eigensolve to k pairs at relative residual 1e-6 (FP32 form
-with FP64 refinement, and the plain FP64 form), reports the stage-5 kernel against its
-roofline (HIP events around every stage-5 launch in the timed region), and times the
-CPU oracle on a bounded sample of the same workload.
+stages, the stage-5 covariance-times-block kernel, backward Kronecker stages.  The
+headline is the 3D workload (24^3 quadratic sine-perturbed cube, 17,576 dofs, exponential
+kernel) with stage 5 in FP64, the paper's arithmetic.  value = pair evaluations per second
+= Ntilde^2 per step / step time.  The same run reports the stage-5 kernel against its
+roofline (HIP events around every stage-5 launch in the timed region), times the FP32,
+BF16x3 and BF16 stage-5 kernels on the same block, times the eigensolve to k pairs at
+relative residual 1e-6 in every form, and times the CPU oracle on the same workload (all
+host cores, and one core on a bounded sample).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5|c1]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c5|c1]
 """
 
 import argparse
@@ -21,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+# vector-ALU lane operations per second: 256 compute units x 64 lanes x 2.4 GHz
+VALU_LANE_OPS = 256 * 64 * 2.4e9
 # HBM bytes per stage-5 launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a
 # plain 256 MiB copy), keyed by (workload, precision, rb, nsplit); see
 # profiles/stage5_f32_c2_hbm_traffic.md.  Only reported for the setting it was measured on.
@@ -37,8 +41,9 @@ WORKLOADS = {
 
 
 def cpu_baseline(desc, b, budget_s=12.0):
-    """Oracle (literal Algorithm 1 with the C/OpenMP stage 5, FP64) applied to 32-vector
-    blocks of the same workload until about budget_s seconds have passed."""
+    """Oracle (literal Algorithm 1 with the C/OpenMP FP64 stage 5) applied to 32-vector
+    blocks of the same workload on every host core until about budget_s seconds have passed
+    (at least one whole apply)."""
     import numpy as np
 
     import workloads
@@ -57,8 +62,89 @@ def cpu_baseline(desc, b, budget_s=12.0):
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     return {"value": P.Nt ** 2 * n / dt, "unit": "pair evals/s", "cores": threads, "kind": "oracle",
-            "sample": "%d oracle applies (FP64, %d-vector block) of the same workload in %.1f s"
+            "sample": "%d whole oracle applies (FP64, %d-vector block) of the same workload in %.1f s"
                       % (n, b, dt)}, float(np.float64(dt / n))
+
+
+def cpu_baseline_one_core(desc, b, budget_s=8.0):
+    """The same oracle apply on one core (one OpenMP thread, one BLAS thread), for the
+    like-for-like comparison with the paper's single-core runs: the Kronecker stages on the
+    whole block, stage 5 on a bounded sample of rows (all columns, all vectors), its time
+    scaled to all rows."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads
+    from oracle import cstage5, operator
+    P = operator.Problem(desc)
+    V = workloads.random_block(P.N, b, seed=0)
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        Y = P.forward(V)
+        P.backward(Y)
+        t_kron = time.perf_counter() - t
+        rows = 64
+        while True:
+            t = time.perf_counter()
+            cstage5.stage5(P, Y, rows=(0, rows), threads=1)
+            dt = time.perf_counter() - t
+            if dt > budget_s / 4 or rows >= P.Nt:
+                break
+            rows = min(P.Nt, rows * 4)
+    t_apply = t_kron + dt * P.Nt / rows
+    return {"value": P.Nt ** 2 / t_apply, "unit": "pair evals/s", "cores": 1, "kind": "oracle",
+            "sample": "one oracle apply (FP64, %d-vector block): Kronecker stages in full (%.2f s), stage 5 "
+                      "on %d of %d rows (%.1f s), scaled to all rows" % (b, t_kron, rows, P.Nt, dt)}
+
+
+def oracle_time_to_k(desc, k):
+    """The oracle's eigenpairs by ARPACK (the paper's implicitly restarted Lanczos family,
+    one vector per apply, C/OpenMP stage 5 on every host core) to relative accuracy 1e-6."""
+    from oracle import cstage5, operator
+    from oracle import eigs as oeigs
+    P = operator.Problem(desc)
+    count = [0]
+
+    def s5(Y):
+        count[0] += 1 if Y.ndim == 1 else Y.shape[1]
+        return cstage5.stage5(P, Y)
+    t = time.perf_counter()
+    oeigs.iterative_eigs(P, k, tol=1e-6, stage5=s5)
+    return {"seconds": time.perf_counter() - t, "applies": count[0], "k": k,
+            "cores": int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()}
+
+
+def measured_rates():
+    """Issue rates measured by the library's rate microbenchmark (lib/klrates), or None."""
+    exe = os.path.join(ROOT, "paper_2011_13861_amd", "lib", "klrates")
+    if not os.path.exists(exe):
+        return None
+    import subprocess
+    r = subprocess.run([exe, "2048"], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return None
+    out = {}
+    for line in r.stdout.splitlines():
+        rec = json.loads(line)
+        out[rec.pop("test")] = rec
+    return out
+
+
+def valu_slots_per_pair(kind, d, precision, rates):
+    """Algorithmic vector-ALU issue slots per pair of the exp2-based kernels (FP32 kernel
+    evaluation): d subtractions and d multiply-adds for the squared distance (d for the L1
+    form), a square root for the exponential kernel, one base-2 exponential, and the
+    rounding of the value to the matrix operand (BF16: one conversion; BF16x3: the hi part,
+    the remainder and its conversion).  The square root and exponential cost their measured
+    issue time relative to an FMA."""
+    fma_ns = rates["fma_f32"]["ns_per_wave_instr_per_simd"]
+    c_exp = rates["exp_f32"]["ns_per_wave_instr_per_simd"] / fma_ns
+    c_sqrt = rates["sqrt_f32"]["ns_per_wave_instr_per_simd"] / fma_ns
+    s = 2 * d + c_exp
+    if kind == "exp":
+        s += c_sqrt
+    s += {"f32": 0, "bf16": 1, "bf16x3": 3}[precision]
+    return s, c_exp, c_sqrt
 
 
 def warm_start_section(n_train, epochs, n_eval, solves=3):
@@ -198,15 +284,49 @@ def batch_section(reps=20):
     return out
 
 
+def stage5_runs(G, kind, prec, x, y, steps, warmup, tune, objective, tiles=None):
+    """Times `steps` applies of the 32-vector block in one precision (stage-5 tiles tuned or
+    forced); returns (ms per apply, stage-5 launches, stage-5 ms in total, tiles)."""
+    import torch
+    if tiles:
+        G.stage5_config(prec, rb=tiles[0], nsplit=tiles[1])
+    elif tune:
+        from paper_2011_13861_amd import autotune
+        autotune.tune_problem(G, kind, precisions=(prec,), reps=10, objective=objective)
+    for _ in range(warmup):
+        G.apply(x, y, prec)
+    torch.cuda.synchronize()
+    G.profile_enable(True)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        G.apply(x, y, prec)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    cnt, kms = G.profile_read()[prec]
+    G.profile_enable(False)
+    return ev0.elapsed_time(ev1) / steps, cnt, kms, G.stage5_config(prec)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default=None, choices=["f32", "f64"])
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3", "bf16"],
+                    help="stage-5 precision of the headline (default FP64, the paper's arithmetic)")
+    ap.add_argument("--other-precisions", default="f32,bf16x3,bf16",
+                    help="stage-5 precisions timed beside the headline ('' = none)")
+    ap.add_argument("--eig-precisions", default="f64,f32,bf16x3,bf16",
+                    help="forms timed to k eigenpairs at 1e-6 (low precisions with FP64 refinement)")
     ap.add_argument("--solves", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--oracle-eigs", action="store_true",
+                    help="also time the oracle's ARPACK eigenpairs on the host cores (about a minute at c3)")
     ap.add_argument("--mlp-train", type=int, default=2000,
                     help="training solves for the warm-start section (0 = skip the section)")
     ap.add_argument("--mlp-epochs", type=int, default=1000)
@@ -216,7 +336,7 @@ def main():
     ap.add_argument("--tune-objective", default="apply", choices=["apply", "stage5"],
                     help="what the stage-5 tile search minimises: the whole apply (default) or the kernel alone")
     ap.add_argument("--tiles", default=None, metavar="RB,NSPLIT",
-                    help="force the stage-5 tiles instead of tuning (e.g. 2,6), for profiler runs")
+                    help="force the headline's stage-5 tiles instead of tuning (e.g. 2,6), for profiler runs")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="also run one plain device-to-device copy of MB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -240,73 +360,86 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     desc, k, b = workloads.config(args.workload)
-    prec = args.precision or "f32"
+    kind = desc["cov"]["kind"]
+    prec = args.precision
     G = kl.Problem(desc)
-    if args.tiles:
-        rb_, ns_ = (int(v) for v in args.tiles.split(","))
-        G.stage5_config(prec, rb=rb_, nsplit=ns_)
-    elif not args.no_tune:
-        from paper_2011_13861_amd import autotune
-        autotune.tune_problem(G, desc["cov"]["kind"], precisions=(prec,), reps=10, objective=args.tune_objective)
     x = kl.to_device_block(workloads.random_block(G.N, b, seed=1))
     y = kl.new_block(G.N, b)
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        G.apply(x, y, prec)
-    torch.cuda.synchronize()
-    G.profile_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    tiles = tuple(int(v) for v in args.tiles.split(",")) if args.tiles else None
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        G.apply(x, y, prec)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ms_per_step, cnt, kms, tiles = stage5_runs(G, kind, prec, x, y, args.steps, args.warmup,
+                                               not args.no_tune, args.tune_objective, tiles)
     wall = time.perf_counter() - t0
-    prof = G.profile_read()
-    G.profile_enable(False)
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
     pairs = float(G.Nt) ** 2
     value = pairs / (ms_per_step * 1e-3)
-    cnt, kms = prof[prec]
     k_avg_s = kms / max(cnt, 1) * 1e-3
-    flops = 2.0 * b * pairs                    # MFMA contraction flops per stage-5 launch
-    achieved = flops / k_avg_s / 1e12
-    tiles = G.stage5_config(prec)
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+    flops = 2.0 * b * pairs                    # matrix-core contraction flops per stage-5 launch
+    if prec == "f64":
+        # FP64: the kernel evaluation (vector ALU) and the contraction (matrix cores) share
+        # the FP64 arithmetic rate (they were measured not to overlap on this chip), so the
+        # bound is FP64 arithmetic with the paper-style flops of a pair: per coordinate a
+        # subtraction and a square (3d - 1 with the sum), the scaling, one exponential, one
+        # square root for the exponential kernel, and 2b for the contraction
+        d = desc["dim"]
+        per_pair = (3 * d - 1) + 1 + 1 + (1 if kind == "exp" else 0) + 2 * b
+        achieved = per_pair * pairs / k_avg_s / 1e12
+        bound = "alu"
+    else:
+        per_pair = 2 * b
+        achieved = flops / k_avg_s / 1e12
+        bound = "mfma"
+    roofline = {"bound": bound, "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[prec],
                 "traffic": MEASURED_TRAFFIC.get((args.workload, prec) + tuple(tiles)),
+                "flops_per_pair": per_pair,
+                "contraction_only_frac": flops / k_avg_s / 1e12 / PEAK_TFLOPS[prec],
                 "kernel": "stage5_%s_kernel" % prec, "kernel_avg_us": k_avg_s * 1e6,
                 "kernel_pairs_per_s": pairs / k_avg_s, "launches": cnt,
                 "stage5_tiles": {"rb": tiles[0], "nsplit": tiles[1]}}
+    rates = measured_rates()
+
+    # the other stage-5 precisions on the same block (matrix-core and vector-ALU bounds)
+    others = {}
+    for p in [q for q in args.other_precisions.split(",") if q and q != prec]:
+        ms_p, cnt_p, kms_p, tiles_p = stage5_runs(G, kind, p, x, y, args.steps, args.warmup,
+                                                  not args.no_tune, args.tune_objective)
+        ks = kms_p / max(cnt_p, 1) * 1e-3
+        ach = flops / ks / 1e12
+        rec = {"apply_ms": ms_p, "apply_pair_evals_per_s": pairs / (ms_p * 1e-3), "kernel_avg_us": ks * 1e6,
+               "kernel_pairs_per_s": pairs / ks, "mfma_achieved_TFLOPs": ach,
+               "mfma_frac": ach / PEAK_TFLOPS[p], "stage5_tiles": {"rb": tiles_p[0], "nsplit": tiles_p[1]}}
+        if rates is not None:
+            slots, c_exp, c_sqrt = valu_slots_per_pair(kind, desc["dim"], p, rates)
+            rec["valu_bound"] = {"slots_per_pair": slots, "exp_cost_fma": c_exp, "sqrt_cost_fma": c_sqrt,
+                                 "peak_pairs_per_s": VALU_LANE_OPS / slots,
+                                 "frac": (pairs / ks) / (VALU_LANE_OPS / slots)}
+        others[p] = rec
 
     # time to k eigenpairs at relative residual 1e-6 (criterion under the FP64 operator)
     def solve(p):
-        G.eigs(k, precision=p, tol=1e-6)          # warm (allocations, handles)
+        G.eigs(k, precision=p, block=b, tol=1e-6)          # warm (allocations, handles)
         times, reps = [], []
         for _ in range(args.solves):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            w, V, rep = G.eigs(k, precision=p, tol=1e-6)
+            w, V, rep = G.eigs(k, precision=p, block=b, tol=1e-6)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
             reps.append(rep)
         i = int(np.argsort(times)[len(times) // 2])
         return times[i], reps[i]
+    time_to_k = {}
     if args.solves > 0:
-        t_lo, rep_lo = solve("f32")
-        t_64, rep_64 = solve("f64")
-    else:
-        t_lo = t_64 = float("nan")
-        rep_lo = rep_64 = None
+        for p in [q for q in args.eig_precisions.split(",") if q]:
+            t_p, rep_p = solve(p)
+            time_to_k[p + ("_refined_fp64" if p != "f64" else "") + "_ms"] = t_p * 1e3
+            time_to_k[p + "_report"] = rep_p
 
     # truncated KL expansion from the k eigenpairs: m field samples and the variance at the
     # Greville points (kl_kle_field); inputs resident, HIP events on the default stream
     kle_out = None
     if args.solves > 0:
-        w, V, _ = G.eigs(k, precision="f64", tol=1e-6)
+        w, V, _ = G.eigs(k, precision="f64", block=b, tol=1e-6)
         m = 1024
         xi = kl.to_device_block(np.random.default_rng(5).standard_normal((k, m)))
         for _ in range(3):
@@ -333,8 +466,9 @@ def main():
         "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
                    "block": b, "k": k, "stage5_precision": prec},
         "roofline": roofline,
-        "time_to_k": {"f32_refined_fp64_ms": t_lo * 1e3, "f64_ms": t_64 * 1e3,
-                      "f32_report": rep_lo, "f64_report": rep_64},
+        "stage5_other_precisions": others,
+        "measured_rates": rates,
+        "time_to_k": time_to_k,
         "wall_s_timed_region": wall,
         "kle_field": kle_out,
     }
@@ -345,6 +479,9 @@ def main():
     if not args.no_cpu:
         cb, _ = cpu_baseline(desc, b)
         out["cpu_baseline"] = cb
+        out["cpu_baseline_1core"] = cpu_baseline_one_core(desc, b)
+        if args.oracle_eigs:
+            out["oracle_time_to_k"] = oracle_time_to_k(desc, k)
     print(json.dumps(out))
 
 

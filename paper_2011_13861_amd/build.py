@@ -3,7 +3,8 @@
 Every source with device code is compiled by hipcc (device code for gfx950 only) with
 packed FP32 instructions disabled; the host-only sources (setup, dense eigensolver) are
 compiled as plain C++; everything is linked into one shared library exposing the C ABI of
-include/kl.h.
+include/kl.h.  The issue-rate microbenchmark ubench/rates.hip is built next to it as
+lib/klrates.
 """
 
 import concurrent.futures
@@ -58,8 +59,15 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])
     os.replace(tmp, LIB)
+    # the issue-rate microbenchmark that prices the covariance kernel's roofline
+    rates = os.path.join(OUT_DIR, "klrates")
+    cmd = [HIPCC] + COMMON + ["-o", rates + ".tmp", os.path.join(HERE, "ubench", "rates.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for ubench/rates.hip:\n%s" % r.stderr[-4000:])
+    os.replace(rates + ".tmp", rates)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", rates)
     return LIB
 
 
