@@ -152,6 +152,20 @@ kl_status kl_set_cov(kl_problem *P, int32_t cov_kind, double sigma2, const doubl
 kl_status kl_apply(kl_problem *P, int32_t precision, int32_t nvec,
                    const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
 
+/* kl_apply for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same y = A~' x, with every
+ * intermediate (Kronecker buffers, stage-5 input, split partials and output) taken from a
+ * static device array of the library (64 MiB on each device, held until the process ends)
+ * instead of the problem's workspace; it calls no allocating routine.  All calls on one
+ * device share that array, so calls that overlap on one device (other streams, other
+ * threads) race and must be ordered by the caller; the array keeps the last call's
+ * contents, and the call clears what must start at zero itself.  Arguments and errors as
+ * kl_apply; a problem whose intermediates exceed the array is KL_EINVAL (the message gives
+ * the size needed); with fewer stage-5 split partials fitting than kl_apply would use, the
+ * split count is lowered (results agree with kl_apply to rounding). */
+kl_status kl_apply_noalloc(kl_problem *P, int32_t precision, int32_t nvec,
+                           const double *x, int64_t ldx, double *y, int64_t ldy, void *stream);
+
 /* Stage 5 alone (Algorithm 1, stage 5): z = Gamma y on the Greville grid, for
  * nvec columns of y (device, FP64, column-major, ld >= Ntilde).  z receives FP64.
  * sigma2 is applied; J is not.  Used to test the kernel in isolation. */

@@ -23,7 +23,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
              "tensor_nurbs": 5}
 
 # exported symbols declared in include/kl.h
-EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_stage5", "kl_get_points",
+EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_apply_noalloc", "kl_stage5", "kl_get_points",
            "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_profile_enable", "kl_profile_read",
            "kl_stage5_config", "kl_apply_config", "kl_set_cov",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
@@ -87,6 +87,7 @@ def lib():
         L.kl_apply.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, P,
                                ctypes.c_int64, P]
         L.kl_stage5.argtypes = L.kl_apply.argtypes
+        L.kl_apply_noalloc.argtypes = L.kl_apply.argtypes
         L.kl_get_points.argtypes = [P, P, P]
         L.kl_get_factor.argtypes = [P, ctypes.c_int32, P]
         L.kl_kle_field.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, P,
