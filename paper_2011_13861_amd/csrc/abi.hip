@@ -57,14 +57,14 @@ void free_problem(kl_problem *P) {
     delete P;
 }
 
-// Coordinate scale for stage 5: the FP64 kernels evaluate exp(-rho) / exp(-rho^2) from
-// coordinates divided by ell; the FP32 kernels use exp2 and absorb log2(e).
-double coord_scale(int cov_kind, double ell, bool base2) {
+// Coordinate scale for stage 5: every kernel evaluates a base-2 exponential, so the
+// coordinates absorb log2(e) / ell (exp, exp-L1) or sqrt(log2 e) / ell (sqexp).
+double coord_scale(int cov_kind, double ell) {
     const double log2e = 1.4426950408889634;
     switch (cov_kind) {
     case KL_COV_EXP:
-    case KL_COV_EXP_L1: return (base2 ? log2e : 1.0) / ell;
-    case KL_COV_SQEXP: return (base2 ? std::sqrt(log2e) : 1.0) / ell;
+    case KL_COV_EXP_L1: return log2e / ell;
+    case KL_COV_SQEXP: return std::sqrt(log2e) / ell;
     default: return 1.0;
     }
 }
@@ -72,9 +72,9 @@ double coord_scale(int cov_kind, double ell, bool base2) {
 
 bool valid_precision(int precision) { return precision >= KL_F64 && precision <= KL_BF16X3; }
 
-// Scaled Greville points for the stage-5 kernels (Sec. 4.3): X / ell per direction for
-// the FP64 kernel, with log2(e) absorbed for the exp2-based FP32 / BF16 kernels.  The
-// padding points stay zero (their rows and columns carry zero weight).
+// Scaled Greville points for the stage-5 kernels (Sec. 4.3): X log2(e) / ell (or with
+// sqrt(log2 e) for the squared exponential) per direction, in FP64 and rounded to FP32.
+// The padding points stay zero (their rows and columns carry zero weight).
 kl_status upload_points(kl_problem *P, hipStream_t s) {
     const HostSetup &hs = P->hs;
     const int d = hs.d;
@@ -82,12 +82,11 @@ kl_status upload_points(kl_problem *P, hipStream_t s) {
     std::vector<double> x64(size_t(d) * Np, 0.0);
     std::vector<float> x32(size_t(d) * Np, 0.f);
     for (int k = 0; k < d; ++k) {
-        const double s64 = coord_scale(P->cov_kind, P->ell[k], false);
-        const double s32 = coord_scale(P->cov_kind, P->ell[k], true);
+        const double sc = coord_scale(P->cov_kind, P->ell[k]);
         for (int64_t p = 0; p < hs.Nt; ++p) {
-            const double v = hs.X[size_t(p) * d + k];
-            x64[size_t(k) * Np + p] = v * s64;
-            x32[size_t(k) * Np + p] = float(v * s32);
+            const double v = hs.X[size_t(p) * d + k] * sc;
+            x64[size_t(k) * Np + p] = v;
+            x32[size_t(k) * Np + p] = float(v);
         }
     }
     kl_status st = hip_check(hipMemcpyAsync(P->dX64, x64.data(), x64.size() * 8, hipMemcpyHostToDevice, s),

@@ -1,10 +1,16 @@
-"""Coefficients of the FP64 exponential used by the stage-5 kernels (`exp_nonpos` in
-kernels_stage5.hip): the degree-11 polynomial that interpolates e^r at the 12 Chebyshev
-nodes of [-ln2/2, ln2/2] (the range left by a Cody-Waite reduction), and the split of ln2
-into a 32-significant-bit high part and the rounded remainder.  Standard library only:
-e^r at the nodes from 80-digit decimal arithmetic, the Vandermonde system solved in exact
-rational arithmetic, the result rounded to double.  Prints the constants and the largest
-relative error of the rounded polynomial (Horner, double) on a fine grid.
+"""Coefficients of the FP64 exponentials used by the stage-5 kernels (kernels_stage5.hip):
+
+* `exp2_nonpos`: the degree-11 polynomial that interpolates 2^f at the 12 Chebyshev nodes
+  of [-1/2, 1/2], the range left by the exact reduction f = x - rint(x) of a base-2
+  exponent (the kernels' coordinates absorb log2(e));
+* `exp_nonpos` (kept for reference): the degree-11 interpolant of e^r on [-ln2/2, ln2/2]
+  after a Cody-Waite reduction, and the split of ln2 into a 32-significant-bit high part
+  and the rounded remainder.
+
+Standard library only: the function values at the nodes from 80-digit decimal arithmetic,
+the Vandermonde system solved in exact rational arithmetic, the result rounded to double.
+Prints the constants and the largest relative error of the rounded polynomials (Horner,
+double) on a fine grid.
 
     python paper_2011_13861_amd/csrc/exp_poly.py
 """
@@ -27,12 +33,14 @@ def dcos(x):
         s += t
 
 
-def coefficients(degree=11, widen=Decimal("1.000001")):
-    a = LN2 / 2 * widen
+def coefficients(degree=11, widen=Decimal("1.000001"), base2=False):
+    """Interpolant of e^r on [-a, a], a = ln2 / 2 (base2=False), or of 2^f on [-a, a],
+    a = 1/2 (base2=True), at the Chebyshev nodes; coefficients of degree 0 first."""
+    a = (Decimal(1) / 2 if base2 else LN2 / 2) * widen
     n = degree + 1
     nodes = [a * dcos((2 * Decimal(i) + 1) * PI / (2 * n)) for i in range(n)]
     A = [[Fraction(x) ** j for j in range(n)] for x in nodes]
-    b = [Fraction(x.exp()) for x in nodes]
+    b = [Fraction((x * LN2).exp() if base2 else x.exp()) for x in nodes]
     for c in range(n):                                   # Gaussian elimination, exact
         p = max(range(c, n), key=lambda r: abs(A[r][c]))
         A[c], A[p], b[c], b[p] = A[p], A[c], b[p], b[c]
@@ -53,6 +61,17 @@ def ln2_split():
 
 
 if __name__ == "__main__":
+    cs2, a2 = coefficients(base2=True)
+    print("base-2 coefficients (degree 0 first):", [repr(c) for c in cs2])
+    worst = 0.0
+    for i in range(4001):
+        f = -a2 + 2 * a2 * i / 4000
+        p = cs2[-1]
+        for c in reversed(cs2[:-1]):
+            p = p * f + c
+        ref = (Decimal(f) * LN2).exp()
+        worst = max(worst, float(abs((Decimal(p) - ref) / ref)))
+    print("largest relative error of the rounded base-2 polynomial:", worst)
     cs, a = coefficients()
     hi, lo = ln2_split()
     print("ln2_hi", hi.hex(), "ln2_lo", lo.hex())

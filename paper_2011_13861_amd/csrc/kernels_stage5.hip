@@ -9,9 +9,9 @@
 // split over row tiles (grid.x) and, for small problems, over ranges of l (grid.y);
 // the split partial sums are added by the backward prologue.
 //
-// Coordinates are pre-scaled on the host: by 1/ell for the FP64 kernels (Gamma =
-// exp(-rho) or exp(-rho^2)) and by log2(e)/ell or sqrt(log2 e)/ell for the FP32 kernels,
-// which then use the hardware base-2 exponential.  sigma^2 is applied after the split
+// Coordinates are pre-scaled on the host by log2(e)/ell (exponential kernels) or
+// sqrt(log2 e)/ell (squared exponential), so that every kernel evaluates a base-2
+// exponential: the hardware one in the FP32 kernels, a polynomial one in FP64.  sigma^2 is applied after the split
 // reduction.  Grids are padded with zero points and zero vectors, which add nothing.
 #include <algorithm>
 
@@ -50,72 +50,68 @@ __device__ __forceinline__ float gamma_f32(const float *xk, const float *xl) {
     }
 }
 
-// FP64 exponential and square root for the arguments of the covariance kernels only
-// (exp of a finite x <= 0, sqrt of a finite a >= 0 that is zero or a normal number),
-// without the range and special-value handling of the general library functions.
-//  * exp: Cody-Waite reduction x = n ln2 + r, |r| <= ln2 / 2, with ln2 split into a high
-//    part of 32 significant bits (n ln2_hi is exact for |n| < 2^21; below that the result
-//    underflows to zero anyway) and the rounded remainder; e^r by a polynomial of degree
-//    11 (below); scaling by 2^n.
-//  * sqrt: Goldschmidt iteration from the hardware reciprocal square root (two coupled
-//    steps for s -> sqrt(a), h -> 1 / (2 sqrt(a))), then one Newton correction of s;
-//    sqrt(0) = 0 is selected explicitly (the reciprocal square root of 0 is infinite).
-__device__ __forceinline__ double exp_nonpos(double x) {
-    constexpr double kLog2e = 1.4426950408889634;
-    constexpr double kLn2Hi = 0x1.62e42fee00000p-1, kLn2Lo = 0x1.a39ef35793c76p-33;
-    const double n = __builtin_rint(x * kLog2e);
-    double r = fma(-n, kLn2Hi, x);
-    r = fma(-n, kLn2Lo, r);
-    // degree-11 interpolant of e^r at the 12 Chebyshev nodes of [-ln2/2, ln2/2]
-    // (coefficients solved in exact rational arithmetic from 80-digit values of e^r, then
-    // rounded; interpolation error below 5e-18, Horner evaluation below one ulp);
-    // exp_poly.py beside this file regenerates them and the ln2 split
-    double p = 2.5110037721946562e-08;
-    p = fma(p, r, 2.7632639789868395e-07);
-    p = fma(p, r, 2.7557240918265525e-06);
-    p = fma(p, r, 2.480148548192088e-05);
-    p = fma(p, r, 0.00019841269890047406);
-    p = fma(p, r, 0.0013888888952315155);
-    p = fma(p, r, 0.008333333333319601);
-    p = fma(p, r, 0.04166666666648809);
-    p = fma(p, r, 0.1666666666666668);
-    p = fma(p, r, 0.5000000000000019);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
+// FP64 base-2 exponential and square root for the arguments of the covariance kernels only
+// (2^x of a finite x <= 0, sqrt of a normal a > 0), without the range and special-value
+// handling of the general library functions.  The coordinates of the FP64 kernels are
+// scaled on the host by log2(e) / ell (sqrt(log2 e) / ell for the squared exponential), so
+// that Gamma = 2^(-rho') with rho' the scaled distance (squared distance).
+//  * exp2: x = n + f with n = rint(x) and f = x - n in [-1/2, 1/2] (exact); 2^f by a
+//    polynomial of degree 11 (below); scaling by 2^n.
+//  * sqrt: Goldschmidt iteration from the hardware reciprocal square root y: s = a y and
+//    h = y / 2 approximate sqrt(a) and 1 / (2 sqrt(a)); one coupled step squares their
+//    relative error (to about 2^-44), and a Newton correction s + h (a - s^2) squares it
+//    again, below the rounding of s.  The callers start the squared distance at 1e-300, so
+//    that a coincident pair gives sqrt(1e-300) = 1e-150 and 2^(-1e-150) = 1 without a
+//    special case (1e-300 is far below the rounding of any non-zero squared distance).
+__device__ __forceinline__ double exp2_nonpos(double x) {
+    const double n = __builtin_rint(x);
+    const double f = x - n;
+    // degree-11 interpolant of 2^f at the 12 Chebyshev nodes of [-1/2, 1/2] (coefficients
+    // solved in exact rational arithmetic from 80-digit values of 2^f, then rounded;
+    // interpolation error below 1e-17, Horner evaluation below 1.7e-16 relative);
+    // exp_poly.py beside this file regenerates them
+    double p = 4.455817928917402e-10;
+    p = fma(p, f, 7.074194335901629e-09);
+    p = fma(p, f, 1.0178057087618173e-07);
+    p = fma(p, f, 1.3215432535695181e-06);
+    p = fma(p, f, 1.5252733841556997e-05);
+    p = fma(p, f, 0.00015403530463724776);
+    p = fma(p, f, 0.001333355814640647);
+    p = fma(p, f, 0.009618129107587256);
+    p = fma(p, f, 0.055504108664821625);
+    p = fma(p, f, 0.24022650695910158);
+    p = fma(p, f, 0.6931471805599453);
+    p = fma(p, f, 1.0);
     return __builtin_ldexp(p, int(n));
 }
 
-__device__ __forceinline__ double sqrt_nonneg(double a) {
+__device__ __forceinline__ double sqrt_pos(double a) {
     const double y = __builtin_amdgcn_rsq(a);
     double s = a * y, h = 0.5 * y;
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-s, h, 0.5);
-        s = fma(s, e, s);
-        h = fma(h, e, h);
-    }
+    const double e = fma(-s, h, 0.5);
+    s = fma(s, e, s);
+    h = fma(h, e, h);
     const double d = fma(-s, s, a);
-    s = fma(d, h, s);
-    return a == 0.0 ? 0.0 : s;
+    return fma(d, h, s);
 }
 
 template <int KIND, int D>
 __device__ __forceinline__ double gamma_f64(const double *xk, const double *xl) {
     if constexpr (KIND == KL_COV_EXP) {
-        double r2 = 0.0;
+        double r2 = 1e-300;
 #pragma unroll
         for (int k = 0; k < D; ++k) { double t = xk[k] - xl[k]; r2 = fma(t, t, r2); }
-        return exp_nonpos(-sqrt_nonneg(r2));
+        return exp2_nonpos(-sqrt_pos(r2));
     } else if constexpr (KIND == KL_COV_SQEXP) {
         double r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) { double t = xk[k] - xl[k]; r2 = fma(t, t, r2); }
-        return exp_nonpos(-r2);
+        return exp2_nonpos(-r2);
     } else if constexpr (KIND == KL_COV_EXP_L1) {
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s += fabs(xk[k] - xl[k]);
-        return exp_nonpos(-s);
+        return exp2_nonpos(-s);
     } else if constexpr (KIND == KL_COV_CONST) {
         return 1.0;
     } else {

@@ -1,9 +1,8 @@
-"""The FP64 exponential of the stage-5 kernels: the constants written in
-kernels_stage5.hip are the ones exp_poly.py derives (Cody-Waite split of ln2, degree-11
-Chebyshev interpolant of e^r on [-ln2/2, ln2/2]), and the reduction + polynomial +
-scaling, replayed in double on the host, stays within a few ulp of exp on x <= 0."""
+"""The FP64 base-2 exponential of the stage-5 kernels: the constants written in
+kernels_stage5.hip are the ones exp_poly.py derives (degree-11 Chebyshev interpolant of 2^f
+on [-1/2, 1/2]), and the exact reduction + polynomial + scaling, replayed in double on the
+host, stays within a few ulp of 2^x on x <= 0."""
 import importlib.util
-import math
 import os
 import re
 
@@ -22,35 +21,28 @@ def _gen():
 
 def _kernel_constants():
     src = open(os.path.join(CSRC, "kernels_stage5.hip")).read()
-    body = src[src.index("double exp_nonpos(double x)"):src.index("double sqrt_nonneg(double a)")]
-    hi, lo = re.search(r"kLn2Hi = (0x[0-9a-fp.+-]+), kLn2Lo = (0x[0-9a-fp.+-]+);", body).groups()
+    body = src[src.index("double exp2_nonpos(double x)"):src.index("double sqrt_pos(double a)")]
     first = float(re.search(r"double p = ([0-9.e+-]+);", body).group(1))
-    rest = [float(v) for v in re.findall(r"p = fma\(p, r, ([0-9.e+-]+)\);", body)]
-    return float.fromhex(hi), float.fromhex(lo), [first] + rest   # highest degree first
+    rest = [float(v) for v in re.findall(r"p = fma\(p, f, ([0-9.e+-]+)\);", body)]
+    return [first] + rest   # highest degree first
 
 
 def test_kernel_constants_are_the_generated_ones():
-    gen = _gen()
-    coef, _ = gen.coefficients()
-    hi, lo = gen.ln2_split()
-    khi, klo, kc = _kernel_constants()
-    assert (khi, klo) == (hi, lo)
-    assert kc == list(reversed(coef))
-    # n * ln2_hi exact for |n| < 2^21: ln2_hi has at most 32 significant bits
-    m, _ = math.frexp(hi)
-    assert math.ldexp(m, 32) == int(math.ldexp(m, 32))
+    coef, half = _gen().coefficients(base2=True)
+    assert abs(half - 0.5) < 1e-5
+    assert _kernel_constants() == list(reversed(coef))
 
 
-def test_host_replay_matches_exp():
-    khi, klo, kc = _kernel_constants()
-    x = -np.concatenate([np.linspace(0.0, 40.0, 20001), np.geomspace(1e-12, 700.0, 5000)])
-    n = np.rint(x * 1.4426950408889634)
-    r = (x - n * khi) - n * klo                          # exact first product, as with fma
-    p = np.full_like(r, kc[0])
+def test_host_replay_matches_exp2():
+    kc = _kernel_constants()
+    x = -np.concatenate([np.linspace(0.0, 60.0, 30001), np.geomspace(1e-12, 1000.0, 5000)])
+    n = np.rint(x)
+    f = x - n                                            # exact
+    p = np.full_like(f, kc[0])
     for c in kc[1:]:
-        p = p * r + c
+        p = p * f + c
     y = np.ldexp(p, n.astype(np.int64))
-    ref = np.exp(x)
+    ref = np.exp2(x)
     rel = np.abs(y - ref) / ref
-    assert rel.max() < 1e-15, rel.max()
-    assert np.exp(0.0) == np.ldexp(kc[-1], 0)            # exp(0) = 1 exactly
+    assert rel.max() < 4e-16, rel.max()
+    assert np.ldexp(kc[-1], 0) == 1.0                    # 2^0 = 1 exactly

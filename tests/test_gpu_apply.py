@@ -329,3 +329,51 @@ def test_fused_directions_fallback_for_large_slabs():
     V = workloads.random_block(P.N, 2, seed=22)
     ref = P.apply(V, stage5=lambda Y: cstage5.stage5(P, Y))
     assert _rel_max(_gpu_apply(G, V, "f64"), ref) <= 1e-12
+
+
+ULP_CASES = [
+    ("exp3d", workloads.sine_cube(6, 2, "exp", 0.5)),
+    ("exp2d", workloads.quarter_annulus(14, 2, "exp", (0.5, 0.3))),
+    ("sqexp2d", workloads.quarter_annulus(14, 2, "sqexp", (0.5, 0.5))),
+    ("expl1", {"dim": 2, "degree": [2, 2], "nelem": [12, 12], "map": {"kind": "identity"},
+               "cov": {"kind": "exp_l1", "sigma2": 1.0, "corr_len": [0.3, 0.6]}}),
+    ("exp1d_short", {"dim": 1, "degree": [2], "nelem": [300], "map": {"kind": "identity"},
+                     "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.05]}}),
+]
+
+
+@pytest.mark.parametrize("name,desc", ULP_CASES, ids=[c[0] for c in ULP_CASES])
+def test_fp64_kernel_values_within_a_few_ulp(name, desc):
+    """FP64 stage 5 applied to unit vectors returns single kernel values Gamma(x_k, x_j)
+    (every other term of the contraction is an exact zero).  Against long-double values
+    from the same points: the error stays within a few ulp plus the rounding of the scaled
+    coordinates (absolute ~1e-16 |x| / ell in the exponent)."""
+    G = kl.Problem(desc)
+    X, _ = G.points()
+    rng = np.random.default_rng(17)
+    cols = rng.choice(G.Nt, 32, replace=False)
+    Y = np.zeros((G.Nt, 32))
+    Y[cols, np.arange(32)] = 1.0
+    y = kl.to_device_block(Y)
+    z = kl.new_block(G.Nt, 32)
+    G.stage5(y, z, "f64")
+    torch.cuda.synchronize()
+    out = z.cpu().numpy()
+    cov = desc["cov"]
+    ell = np.asarray(cov["corr_len"], dtype=np.longdouble)[:G.d]
+    Xl = X.astype(np.longdouble)
+    diff = (Xl[:, None, :] - Xl[None, cols, :]) / ell
+    if cov["kind"] == "exp":
+        ref = np.exp(-np.sqrt(np.sum(diff * diff, axis=2)))
+    elif cov["kind"] == "sqexp":
+        ref = np.exp(-np.sum(diff * diff, axis=2))
+    else:
+        ref = np.exp(-np.sum(np.abs(diff), axis=2))
+    mask = ref > 1e-12
+    rel = np.abs(out.astype(np.longdouble) - ref)[mask] / ref[mask]
+    scale = float(np.max(np.abs(X) / np.asarray(cov["corr_len"])[:G.d])) * 1.4427
+    if cov["kind"] == "sqexp":
+        scale = scale * scale
+    bar = 2.2e-16 * (4.0 + 2.0 * scale)
+    print("ULP", name, "max rel %.3e bar %.3e" % (float(rel.max()), bar))
+    assert float(rel.max()) <= bar, (name, float(rel.max()), bar)
