@@ -191,17 +191,30 @@ struct S5Tile {
     double scale;
 };
 
+// Workgroup -> (row tile, split).  Workgroups are dispatched to the 8 XCDs of the chip in
+// turn (linear id g, x fastest, goes to XCD g mod 8), each XCD with its own L2.  With a
+// split count that is a multiple of 8, the workgroups of split s are all placed on XCD
+// s mod 8 (slot q = g / 8 of that XCD covers split s = xcd + 8 (q / R), row tile q mod R),
+// so each XCD reads only its splits' columns of the stage-5 input instead of all of them.
 __device__ __forceinline__ S5Tile grid_tile(int64_t rows_wg, int64_t Ntpad, int64_t lchunk,
                                              const double *wrow, double scale) {
     S5Tile t;
     t.wrow = wrow;
     t.scale = scale;
     t.Ntpad = Ntpad;
-    t.row0 = int64_t(blockIdx.x) * rows_wg;
-    t.l0 = int64_t(blockIdx.y) * lchunk;
+    const int64_t R = gridDim.x, S = gridDim.y;
+    int64_t rowtile = blockIdx.x, split = blockIdx.y;
+    if ((S & 7) == 0) {
+        const int64_t g = int64_t(blockIdx.x) + R * int64_t(blockIdx.y);
+        const int64_t q = g >> 3;
+        rowtile = q % R;
+        split = (g & 7) + 8 * (q / R);
+    }
+    t.row0 = rowtile * rows_wg;
+    t.l0 = split * lchunk;
     t.l1 = min(t.l0 + lchunk, Ntpad);
-    t.split = int(blockIdx.y);
-    t.nsplit = int(gridDim.y);
+    t.split = int(split);
+    t.nsplit = int(S);
     return t;
 }
 
@@ -429,9 +442,8 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
     __shared__ float red[kWaves * 32 * (kBW + 1)];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 31, kh = lane >> 5;
-    const int64_t row0 = int64_t(blockIdx.x) * rows_wg;
-    const int64_t l0 = int64_t(blockIdx.y) * lchunk;
-    const int64_t l1 = min(l0 + lchunk, Ntpad);
+    const S5Tile tile = grid_tile(rows_wg, Ntpad, lchunk, wrow, scale);
+    const int64_t row0 = tile.row0, l0 = tile.l0, l1 = tile.l1;
     float xk[RB][D];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -517,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
             red[(wave * 32 + row) * (kBW + 1) + i] = acc[rb][r];
         }
         __syncthreads();
-        finish_block<float>(red, Z, Zf, int(blockIdx.y), int(gridDim.y), Ntpad, row0 + rb * 32, wrow, scale);
+        finish_block<float>(red, Z, Zf, tile.split, tile.nsplit, Ntpad, row0 + rb * 32, wrow, scale);
     }
 }
 

@@ -261,7 +261,10 @@ def test_long_direction():
 
 
 @pytest.mark.parametrize("prec,rb,ns", [("f32", 1, 0), ("f32", 2, 5), ("f32", 4, 0), ("f32", 8, 0), ("f32", 8, 9),
-                                        ("bf16x3", 1, 0), ("bf16x3", 4, 3), ("f64", 0, 7)])
+                                        ("bf16x3", 1, 0), ("bf16x3", 4, 3), ("f64", 0, 7),
+                                        # split counts that are multiples of 8: splits placed per XCD
+                                        ("f64", 0, 8), ("f64", 0, 16), ("f32", 2, 8), ("f32", 8, 16),
+                                        ("bf16x3", 2, 8), ("bf16", 1, 16)])
 def test_stage5_tile_settings(prec, rb, ns):
     """Every stage-5 tile setting (32-row blocks per wave, waves per workgroup, l-splits)
     against the oracle on a problem with several row tiles and splits."""
@@ -305,7 +308,7 @@ def test_fused_directions_match_oracle_and_per_direction_form(name, desc, precis
         _FUSE_REF[name] = (V, P.apply(V))
     V, ref = _FUSE_REF[name]
     tol = TOL[precision]
-    for ns in (1, 3, 9):
+    for ns in (1, 3, 8, 9):
         G.stage5_config(precision, nsplit=ns)
         G.apply_config(True)
         fused = _gpu_apply(G, V, precision)
