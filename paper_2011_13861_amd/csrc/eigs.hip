@@ -35,30 +35,6 @@ namespace {
 
 constexpr int kT = 256;
 
-// R[:, j] = AX[:, j] - theta_j X[:, j] for j < k; norms[j] = ||R[:, j]||_2.
-__global__ __launch_bounds__(kT) void residual_kernel(const double *__restrict__ X,
-                                                      const double *__restrict__ AX,
-                                                      const double *__restrict__ theta, int64_t N,
-                                                      int64_t ld, double *__restrict__ R,
-                                                      double *__restrict__ norms) {
-    const int j = blockIdx.x;
-    const double t = theta[j];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += kT) {
-        const double r = AX[i + ld * j] - t * X[i + ld * j];
-        if (R) R[i + ld * j] = r;
-        s += r * r;
-    }
-    __shared__ double red[kT];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kT / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) norms[j] = sqrt(red[0]);
-}
-
 // Checks a block for non-finite values: flag[0] = 1 if any.
 __global__ __launch_bounds__(kT) void finite_kernel(const double *__restrict__ X, int64_t n,
                                                     int *__restrict__ flag) {
@@ -70,26 +46,33 @@ __global__ __launch_bounds__(kT) void finite_kernel(const double *__restrict__ X
 
 struct SolverCache {
     hipStream_t s = nullptr;
+    // second stream of the Rayleigh-Ritz step: the Ritz vectors, their residuals and norms
+    // are formed there while the main stream applies the operator to the next block
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev = nullptr;    // orders s2 after the basis written on s
     int64_t N = 0;
     int mcap = 0, ccap = 0;
     double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
-    double *C = nullptr, *part = nullptr, *dtheta = nullptr, *dnorm = nullptr;
+    double *R = nullptr;        // residuals of the kept Ritz vectors (N x mcap)
+    double *C = nullptr, *C2 = nullptr, *part = nullptr, *dtheta = nullptr, *dnorm = nullptr;
+    double *rpart = nullptr;    // partial sums of the residual norms
     int *dflag = nullptr;
     // pinned host staging of the small transfers (hipHostMalloc): a device-to-host
     // region (Gram matrices, blocks of H, residual norms) and one host-to-device region
     // per source (orthonormalising transform, Ritz vectors, Ritz values); every region
     // is reused only after a stream synchronisation that follows its last transfer
     double *pin = nullptr;
-    size_t pin_region = 0;      // doubles per region (4 regions)
+    size_t pin_region = 0;      // doubles per region (5 regions: the fifth takes the norms)
 };
 
 namespace {
 
 void release_buffers(SolverCache &c) {
-    hipFree(c.V); hipFree(c.AV); hipFree(c.Vt); hipFree(c.AVt); hipFree(c.W);
-    hipFree(c.C); hipFree(c.part); hipFree(c.dtheta); hipFree(c.dnorm); hipFree(c.dflag);
+    hipFree(c.V); hipFree(c.AV); hipFree(c.Vt); hipFree(c.AVt); hipFree(c.W); hipFree(c.R);
+    hipFree(c.C); hipFree(c.C2); hipFree(c.part); hipFree(c.rpart); hipFree(c.dtheta); hipFree(c.dnorm);
+    hipFree(c.dflag);
     if (c.pin) hipHostFree(c.pin);
-    c.V = c.AV = c.Vt = c.AVt = c.W = c.C = c.part = c.dtheta = c.dnorm = nullptr;
+    c.V = c.AV = c.Vt = c.AVt = c.W = c.R = c.C = c.C2 = c.part = c.rpart = c.dtheta = c.dnorm = nullptr;
     c.pin = nullptr;
     c.pin_region = 0;
     c.dflag = nullptr;
@@ -123,13 +106,15 @@ void launch_normal_fill(double *X, int64_t n, uint64_t seed, hipStream_t s) {
 struct Solver {
     kl_problem *P;
     hipStream_t s = nullptr;
+    hipStream_t s2 = nullptr;   // Rayleigh-Ritz stream (NULL: everything on s)
+    hipEvent_t ev = nullptr;
     int64_t N = 0;
     int b = 32, k = 1, keep = 1, mmax = 1;
-    double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
-    double *C = nullptr, *dtheta = nullptr, *dnorm = nullptr, *part = nullptr;
+    double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr, *R = nullptr;
+    double *C = nullptr, *C2 = nullptr, *dtheta = nullptr, *dnorm = nullptr, *part = nullptr, *rpart = nullptr;
     int *dflag = nullptr;
     // pinned staging regions (see SolverCache)
-    double *pin_d2h = nullptr, *pin_T = nullptr, *pin_S = nullptr, *pin_theta = nullptr;
+    double *pin_d2h = nullptr, *pin_T = nullptr, *pin_S = nullptr, *pin_theta = nullptr, *pin_norm = nullptr;
     std::vector<double> H;      // mmax x mmax, row-major, host
     int m = 0;                  // current basis size
     int last = 0;               // columns [m - last, m) are the newest block
@@ -151,8 +136,8 @@ struct Solver {
     }
     // Out = alpha A S + beta Out   (A: N x ma, S: ma x nb with ld lds)
     kl_status gemm_nn(const double *A, int ma, const double *S, int lds, int nb, double alpha,
-                      double beta, double *Out) {
-        launch_gemm_nn(A, N, ma, S, lds, nb, N, alpha, beta, Out, N, s);
+                      double beta, double *Out, hipStream_t on = nullptr) {
+        launch_gemm_nn(A, N, ma, S, lds, nb, N, alpha, beta, Out, N, on ? on : s);
         return check(hipGetLastError(), "gemm kernel");
     }
 
@@ -335,13 +320,15 @@ kl_status ensure_solver_stream(kl_problem *P) {
         P->solver = new (std::nothrow) SolverCache();
         if (!P->solver) { set_error("kl_eigs: host allocation failed"); return KL_ENOMEM; }
     }
-    if (!P->solver->s) {
-        const hipError_t e = hipStreamCreate(&P->solver->s);
-        if (e != hipSuccess) {
-            P->solver->s = nullptr;
-            set_error(std::string("kl_eigs: stream: ") + hipGetErrorString(e));
-            return KL_EHIP;
-        }
+    SolverCache &c = *P->solver;
+    hipError_t e = hipSuccess;
+    if (!c.s && (e = hipStreamCreate(&c.s)) != hipSuccess) c.s = nullptr;
+    if (e == hipSuccess && !c.s2 && (e = hipStreamCreate(&c.s2)) != hipSuccess) c.s2 = nullptr;
+    if (e == hipSuccess && !c.ev && (e = hipEventCreateWithFlags(&c.ev, hipEventDisableTiming)) != hipSuccess)
+        c.ev = nullptr;
+    if (e != hipSuccess) {
+        set_error(std::string("kl_eigs: stream: ") + hipGetErrorString(e));
+        return KL_EHIP;
     }
     return KL_OK;
 }
@@ -365,10 +352,14 @@ kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
         (st = hip(hipMalloc(&c.Vt, nb), "alloc Vt")) != KL_OK ||
         (st = hip(hipMalloc(&c.AVt, nb), "alloc AVt")) != KL_OK ||
         (st = hip(hipMalloc(&c.W, size_t(N) * cc * sizeof(double)), "alloc W")) != KL_OK ||
+        (st = hip(hipMalloc(&c.R, nb), "alloc R")) != KL_OK ||
         (st = hip(hipMalloc(&c.C, size_t(cc) * cc * sizeof(double)), "alloc C")) != KL_OK ||
+        (st = hip(hipMalloc(&c.C2, size_t(cc) * cc * sizeof(double)), "alloc C2")) != KL_OK ||
         // split partials of the Gram kernel: its row ranges times a cmax x cmax product
-        (st = hip(hipMalloc(&c.part, size_t(gram_splits(N, cc, cc, 0)) * cc * cc * sizeof(double)),
+        (st = hip(hipMalloc(&c.part, size_t(gram_part_elems(N, std::max(mc, cc), std::max(mc, cc))) * sizeof(double)),
                   "alloc gram partials")) != KL_OK ||
+        (st = hip(hipMalloc(&c.rpart, size_t(residual_chunks(N)) * mc * sizeof(double)),
+                  "alloc residual partials")) != KL_OK ||
         (st = hip(hipMalloc(&c.dtheta, size_t(mc) * 8), "alloc theta")) != KL_OK ||
         (st = hip(hipMalloc(&c.dnorm, size_t(mc) * 8), "alloc norms")) != KL_OK ||
         (st = hip(hipMalloc(&c.dflag, sizeof(int)), "alloc flag")) != KL_OK) {
@@ -376,7 +367,7 @@ kl_status acquire_cache(kl_problem *P, int64_t N, int mmax, int cmax) {
         return st;
     }
     c.pin_region = size_t(std::max(mc, cc)) * size_t(std::max(mc, cc));
-    if ((st = hip(hipHostMalloc(reinterpret_cast<void **>(&c.pin), 4 * c.pin_region * sizeof(double),
+    if ((st = hip(hipHostMalloc(reinterpret_cast<void **>(&c.pin), 5 * c.pin_region * sizeof(double),
                                 hipHostMallocDefault), "alloc pinned staging")) != KL_OK) {
         c.pin = nullptr;
         release_buffers(c);
@@ -433,8 +424,11 @@ struct EigRun {
 void free_solver_cache(SolverCache *c) {
     if (!c) return;
     if (c->s) hipStreamSynchronize(c->s);
+    if (c->s2) hipStreamSynchronize(c->s2);
     release_buffers(*c);
     if (c->s) hipStreamDestroy(c->s);
+    if (c->s2) hipStreamDestroy(c->s2);
+    if (c->ev) hipEventDestroy(c->ev);
     delete c;
 }
 
@@ -511,12 +505,16 @@ kl_status EigRun::begin(const double *x0, int nvec0) {
     {
         SolverCache &c = *P->solver;
         S.s = c.s;
-        S.V = c.V; S.AV = c.AV; S.Vt = c.Vt; S.AVt = c.AVt; S.W = c.W;
-        S.C = c.C; S.part = c.part; S.dtheta = c.dtheta; S.dnorm = c.dnorm; S.dflag = c.dflag;
+        S.V = c.V; S.AV = c.AV; S.Vt = c.Vt; S.AVt = c.AVt; S.W = c.W; S.R = c.R;
+        S.C = c.C; S.C2 = c.C2; S.part = c.part; S.rpart = c.rpart; S.dtheta = c.dtheta; S.dnorm = c.dnorm;
+        S.dflag = c.dflag;
+        S.s2 = overlap ? c.s2 : nullptr;
+        S.ev = c.ev;
         S.pin_d2h = c.pin;
         S.pin_T = c.pin + c.pin_region;
         S.pin_S = c.pin + 2 * c.pin_region;
         S.pin_theta = c.pin + 3 * c.pin_region;
+        S.pin_norm = c.pin + 4 * c.pin_region;
     }
     S.H.assign(size_t(S.mmax) * S.mmax, 0.0);
     const int b0 = S.b;
@@ -574,7 +572,7 @@ kl_status EigRun::after_apply() {
         // expand with every residual direction of the FP64 operator: the kept vectors are
         // Ritz vectors of the low-precision operator, so (unlike after a restart within
         // one precision) their residuals are not confined to one block
-        hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.V, S.AV, S.dtheta, N, N, S.W, S.dnorm);
+        launch_residual(S.V, S.AV, S.dtheta, N, N, kk, S.W, S.rpart, S.dnorm, S.s);
         const int add = int(std::min<int64_t>(std::min(kk, S.mmax - S.m), N - S.m));
         krylov_ok = false;                  // low-precision Ritz vectors under the FP64 operator
         if (add > 0) {
@@ -625,6 +623,13 @@ kl_status EigRun::rr_step() {
     // orthonormalised residuals (otherwise the residuals are used).
     const int add_next = int(std::min<int64_t>(S.b, N - S.m));
     const bool speculate = overlap && add_next > 0;
+    // the Ritz vectors are formed on the second stream from V, AV[:, :m] as they stand now
+    // (the next block written below only touches columns >= m)
+    const hipStream_t rs = S.s2 ? S.s2 : S.s;
+    if (rs != S.s) {
+        if ((st = S.check(hipEventRecord(S.ev, S.s), "event")) != KL_OK) return st;
+        if ((st = S.check(hipStreamWaitEvent(rs, S.ev, 0), "event wait")) != KL_OK) return st;
+    }
     const bool spec_apply = speculate && max_rel > 10.0 * tol;
     bool blk_full = false;                  // the speculative block kept every direction
     bool eig_ok = false;
@@ -656,22 +661,25 @@ kl_status EigRun::rr_step() {
     if (!eig_ok) { set_error("kl_eigs: projected eigenproblem did not converge"); return KL_ENUMERIC; }
     for (double t : theta)
         if (!std::isfinite(t)) { set_error("kl_eigs: non-finite Ritz value"); return KL_ENUMERIC; }
-    // X = V S[:, :kk] -> Vt,  AX = AV S[:, :kk] -> AVt
+    // X = V S[:, :kk] -> Vt,  AX = AV S[:, :kk] -> AVt, residuals R = AX - X Theta and their
+    // norms, on the Rayleigh-Ritz stream: the check below need not wait for the operator
+    // application of the next block queued on the main stream
     std::copy(Sm.begin(), Sm.begin() + size_t(m) * kk, S.pin_S);
-    if ((st = S.check(hipMemcpyAsync(S.C, S.pin_S, size_t(m) * kk * 8, hipMemcpyHostToDevice, S.s), "copy S")) != KL_OK)
+    if ((st = S.check(hipMemcpyAsync(S.C2, S.pin_S, size_t(m) * kk * 8, hipMemcpyHostToDevice, rs), "copy S")) != KL_OK)
         return st;
-    if ((st = S.gemm_nn(S.V, m, S.C, m, kk, 1.0, 0.0, S.Vt)) != KL_OK) return st;
-    if ((st = S.gemm_nn(S.AV, m, S.C, m, kk, 1.0, 0.0, S.AVt)) != KL_OK) return st;
+    if ((st = S.gemm_nn(S.V, m, S.C2, m, kk, 1.0, 0.0, S.Vt, rs)) != KL_OK) return st;
+    if ((st = S.gemm_nn(S.AV, m, S.C2, m, kk, 1.0, 0.0, S.AVt, rs)) != KL_OK) return st;
     std::copy(theta.begin(), theta.begin() + kk, S.pin_theta);
-    if ((st = S.check(hipMemcpyAsync(S.dtheta, S.pin_theta, size_t(kk) * 8, hipMemcpyHostToDevice, S.s),
+    if ((st = S.check(hipMemcpyAsync(S.dtheta, S.pin_theta, size_t(kk) * 8, hipMemcpyHostToDevice, rs),
                       "copy theta")) != KL_OK)
         return st;
-    hipLaunchKernelGGL(residual_kernel, dim3(kk), dim3(kT), 0, S.s, S.Vt, S.AVt, S.dtheta, N, N, S.W, S.dnorm);
-    if ((st = S.check(hipMemcpyAsync(S.pin_d2h, S.dnorm, size_t(kk) * 8, hipMemcpyDeviceToHost, S.s),
+    launch_residual(S.Vt, S.AVt, S.dtheta, N, N, kk, S.R, S.rpart, S.dnorm, rs);
+    if ((st = S.check(hipMemcpyAsync(S.pin_norm, S.dnorm, size_t(kk) * 8, hipMemcpyDeviceToHost, rs),
                       "copy norms")) != KL_OK)
         return st;
-    if ((st = S.check(hipStreamSynchronize(S.s), "sync")) != KL_OK) return st;
-    norms.assign(S.pin_d2h, S.pin_d2h + kk);
+    // every later use of Vt, AVt, R and dtheta is queued after this host synchronisation
+    if ((st = S.check(hipStreamSynchronize(rs), "sync")) != KL_OK) return st;
+    norms.assign(S.pin_norm, S.pin_norm + kk);
     const double t1 = std::fabs(theta[0]);
     converged = 0;
     max_rel = 0.0;
@@ -743,13 +751,13 @@ kl_status EigRun::rr_step() {
         std::fill(S.H.begin(), S.H.end(), 0.0);
         for (int i = 0; i < kk; ++i) S.H[size_t(i) * S.mmax + i] = theta[i];
         S.restarts += 1;
-        // residuals of the kept vectors are in W (residual_kernel above).  If the old
+        // residuals of the kept vectors are in R (residual_kernel above).  If the old
         // basis had the Arnoldi relation they span at most as many directions as its
         // newest block had columns, and the restarted basis keeps the relation when all
         // of them are kept; a newest block wider than `add` (the one that follows the
         // switch to FP64 holds every residual direction of the kept vectors) loses it
         if (add <= 0) { done = true; return KL_OK; }
-        if ((st = S.orth_into_basis(S.W, kk, add, rng)) != KL_OK) return st;
+        if ((st = S.orth_into_basis(S.R, kk, add, rng)) != KL_OK) return st;
         pending_keeps_krylov = newest <= add && !S.last_refilled;
     } else {
         // ---- block Krylov expansion from the newest block of AV --------------------

@@ -1,15 +1,18 @@
 // FP64 block kernels of the eigensolver: C = A^T B for tall-skinny A (N x m) and
 // B (N x c), N >> m, c (the Gram matrices of the Rayleigh-Ritz projection and of the
 // Gram-Schmidt reorthogonalisation), and Out = alpha A S + beta Out for a tall-skinny A
-// and a small S (Ritz vectors, projections).
+// and a small S (Ritz vectors, projections).  Both read A once from HBM and are bound by
+// it; both run on v_mfma_f64_16x16x4_f64 (accumulator r of lane L holds
+// D[(L >> 4) + 4 r][L & 15]; A operand X[i][k] and B operand Y[k][j] in lane (i or j) + 16 k).
 //
-// Gram products: the N rows are split into G <= 256 ranges of at least two slabs, so that short
-// products still spread over the chip.  A workgroup owns one (64 x 64 tile of C, row
-// range) pair: it stages 32-row slabs of the 64 columns of A and of B in LDS (loads
-// coalesced along the rows, the next slab prefetched into registers while the current
-// one is used) and accumulates 16 entries per thread with FP64 FMAs.  The partials are
-// stored output-major, part[e][g], so that the reduction is one wave per output entry:
-// coalesced loads of G values and a cross-lane sum, in a fixed order.
+// Gram products: the N rows are split into G <= 256 ranges of at least 128 rows.  A
+// workgroup owns one (64 rows of C, row range) pair and all c <= 128 columns of C: per
+// 32-row slab it stages the slab of its 64 columns of A and of all columns of B in LDS
+// (loads coalesced along the rows, the next slab in registers while the current one is
+// used), and wave w accumulates the 16 rows 16 w.. of C against every 16-column tile.
+// Each workgroup stores its accumulators as they sit in the registers (contiguous,
+// coalesced); a second kernel adds the G partials of every slot in a fixed order and
+// writes the entry of C the slot holds.
 #include <algorithm>
 
 #include "kl_internal.h"
@@ -17,227 +20,336 @@
 namespace kl {
 namespace {
 
-constexpr int kT = 64;         // C tile edge
-constexpr int kSlab = 32;      // rows per LDS slab
-constexpr int kThreads = 256;  // 16 x 16 threads, 4 x 4 entries each
-constexpr int kG = 256;        // maximum number of row ranges
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kThreads) void gram_partial_kernel(
+constexpr int kThreads = 256;
+constexpr int kG = 256;          // maximum number of row ranges
+constexpr int kSlab = 32;        // rows per LDS slab
+constexpr int kGramRows = 64;    // rows of C per workgroup (4 waves x 16)
+constexpr int kMaxCT = 8;        // 16-column tiles of C per workgroup (c <= 128)
+constexpr int kRangeRows = 128;  // minimum rows per range
+
+template <int CT>
+__global__ __launch_bounds__(kThreads) void gram_mfma_kernel(
     const double *__restrict__ A, int64_t lda, int m, const double *__restrict__ B, int64_t ldb,
     int c, int64_t N, int64_t rows_per_range, double *__restrict__ part) {
-    __shared__ double sA[kSlab][kT + 1];
-    __shared__ double sB[kSlab][kT + 1];
-    const int i0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
-    const int g = blockIdx.z;
+    __shared__ double sA[kSlab][kGramRows + 2];
+    __shared__ double sB[kSlab][16 * CT + 2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int i0 = blockIdx.x * kGramRows;
+    const int g = blockIdx.y;
     const int64_t n0 = int64_t(g) * rows_per_range;
     const int64_t n1 = min(N, n0 + rows_per_range);
-    const int ti = threadIdx.x % 16, tj = threadIdx.x / 16;
-    double acc[4][4];
+    doublex4 acc[CT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-    constexpr int kPer = (kSlab * kT) / kThreads;       // 8 elements of A and of B per thread
-    double pa[kPer], pb[kPer];
+    for (int t = 0; t < CT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    // slab loads: element e of a slab is (row r = e % 32, column e / 32): 32 consecutive
+    // rows of one column per 32 threads
+    constexpr int kPA = (kSlab * kGramRows) / kThreads;       // 8 elements of A per thread
+    constexpr int kPB = (kSlab * 16 * CT + kThreads - 1) / kThreads;
+    double pa[kPA], pb[kPB];
     auto load = [&](int64_t ns) {
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < kPA; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int r = e % kSlab, col = i0 + e / kSlab;
+            const int64_t n = ns + r;
+            const bool ok = n < n1 && col < m;
+            const double v = A[int64_t(ok ? col : 0) * lda + (ok ? n : 0)];
+            pa[q] = ok ? v : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kPB; ++q) {
             const int e = threadIdx.x + q * kThreads;
             const int r = e % kSlab, col = e / kSlab;
             const int64_t n = ns + r;
-            pa[q] = (n < n1 && i0 + col < m) ? A[(i0 + col) * lda + n] : 0.0;
-            pb[q] = (n < n1 && j0 + col < c) ? B[(j0 + col) * ldb + n] : 0.0;
+            const bool ok = n < n1 && col < c && e < kSlab * 16 * CT;
+            const double v = B[int64_t(ok ? col : 0) * ldb + (ok ? n : 0)];
+            pb[q] = ok ? v : 0.0;
         }
     };
     if (n0 < n1) load(n0);
     for (int64_t ns = n0; ns < n1; ns += kSlab) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < kPA; ++q) {
             const int e = threadIdx.x + q * kThreads;
-            const int r = e % kSlab, col = e / kSlab;
-            sA[r][col] = pa[q];
-            sB[r][col] = pb[q];
+            sA[e % kSlab][e / kSlab] = pa[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kPB; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            if (e < kSlab * 16 * CT) sB[e % kSlab][e / kSlab] = pb[q];
         }
         __syncthreads();
         if (ns + kSlab < n1) load(ns + kSlab);
-#pragma unroll 4
-        for (int r = 0; r < kSlab; ++r) {
-            double a[4], b[4];
+        // C[16 w + i][16 t + j] += sum_n A[n][16 w + i] B[n][16 t + j]: A operand = A^T
+        // (lane i + 16 k: sA[4 s + k][16 w + i]), B operand = B (lane j + 16 k)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = sA[r][ti + 16 * u];
+        for (int st = 0; st < kSlab / 4; ++st) {
+            const double a = sA[4 * st + lk][16 * w + li];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) b[v] = sB[r][tj + 16 * v];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+            for (int t = 0; t < CT; ++t) {
+                const double b = sB[4 * st + lk][16 * t + li];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
         }
     }
+    // slot (t, r, thread) of workgroup (row block, range g) at
+    // part[((g nblk + blockIdx.x) 4 CT + 4 t + r) 256 + thread]
+    double *dst = part + (int64_t(g) * gridDim.x + blockIdx.x) * (4 * CT * kThreads);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int t = 0; t < CT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = i0 + ti + 16 * u, j = j0 + tj + 16 * v;
-            if (i < m && j < c) part[(int64_t(j) * m + i) * gridDim.z + g] = acc[u][v];
-        }
+        for (int r = 0; r < 4; ++r) dst[(4 * t + r) * kThreads + threadIdx.x] = acc[t][r];
 }
 
-// One wave per entry of C: sums part[e][0..G-1] across lanes.
-__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__restrict__ part,
-                                                               int G, int64_t mc,
-                                                               double *__restrict__ C) {
-    const int lane = threadIdx.x & 63;
-    const int64_t e = int64_t(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6);
-    if (e >= mc) return;
+// Sum of the G range partials of every accumulator slot.  A workgroup takes 64 slots;
+// wave w adds the ranges [w G / 4, (w + 1) G / 4) of its lane's slot in range order (four
+// loads in flight), and the four wave sums are added in wave order, so the result does
+// not depend on scheduling.  The slot's entry of C (column-major, ld m) is stored.
+template <int CT>
+__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__restrict__ part, int G, int nblk,
+                                                               int m, int c, double *__restrict__ C) {
+    constexpr int kSlots = 4 * CT * kThreads;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t e = int64_t(blockIdx.x) * 64 + lane;     // slot over all row blocks
+    const int64_t total = int64_t(nblk) * kSlots;
+    __shared__ double red[4][64];
     double v = 0.0;
-    for (int g = lane; g < G; g += 64) v += part[e * G + g];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) C[e] = v;
+    if (e < total) {
+        const int g0 = int(int64_t(G) * wv / 4), g1 = int(int64_t(G) * (wv + 1) / 4);
+        const double *p = part + e;
+        int g = g0;
+        for (; g + 4 <= g1; g += 4) {
+            const double a0 = p[int64_t(g) * total], a1 = p[int64_t(g + 1) * total];
+            const double a2 = p[int64_t(g + 2) * total], a3 = p[int64_t(g + 3) * total];
+            v += a0; v += a1; v += a2; v += a3;
+        }
+        for (; g < g1; ++g) v += p[int64_t(g) * total];
+    }
+    red[wv][lane] = v;
+    __syncthreads();
+    if (wv != 0 || e >= total) return;
+    const int blk = int(e / kSlots), rem = int(e % kSlots);
+    const int tr = rem / kThreads, th = rem % kThreads;
+    const int t = tr >> 2, r = tr & 3;
+    const int w = th >> 6, ln = th & 63;
+    const int i = blk * kGramRows + 16 * w + (ln >> 4) + 4 * r, j = 16 * t + (ln & 15);
+    if (i >= m || j >= c) return;
+    C[int64_t(j) * m + i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// Out (N x c) = alpha A (N x m) S (m x c) + beta Out, column-major, on
-// v_mfma_f64_16x16x4_f64 in the transposed form Out^T = S^T A^T: A operand S^T[j][k] in
-// lane j + 16 k, B operand A^T[k][i] = A[i + lda k] in lane i + 16 k (16 consecutive
-// rows of one column: coalesced), accumulator r of lane L = Out^T[(L >> 4) + 4 r][L & 15].
-// A workgroup owns 16 rows of Out and NT tiles of 16 columns (all of c up to 128, so
-// that A is read once); its 4 waves split the contraction (wave w takes the 4-wide
-// k-steps s = w mod 4), with the operands of the next batch of steps in flight while the
-// current one runs on the matrix cores.  The four partial tiles are added in LDS in
-// wave order and stored with alpha and beta (beta = 0 does not read Out).
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-constexpr int kNNBatch = 2;      // k-steps per wave per batch of loads
-constexpr int kNNMaxTiles = 8;   // column tiles per workgroup
+// Out (N x c) = alpha A (N x m) S (m x c) + beta Out, column-major, in the transposed form
+// Out^T = S^T A^T: A operand S^T[j][k] (lane j + 16 k) from S staged in LDS, B operand
+// A^T[k][i] = A[i + lda k] (lane i + 16 k: 16 consecutive rows of one column, coalesced)
+// straight from memory, the next chunk in flight while the current one runs.  A workgroup
+// owns 32 rows of Out; wave w takes rows 16 (w & 1).. and the 16-column tiles of group
+// w >> 1 (at most 4 tiles per wave), so no partial tiles are added across waves.  S is
+// staged 32 rows (k) at a time with loads coalesced along k.  beta = 0 does not read Out.
+constexpr int kNNChunk = 32;     // k per LDS chunk of S
+constexpr int kNNMaxTiles = 8;   // column tiles per workgroup (c <= 128)
 
-template <int NT>
-__global__ __launch_bounds__(kThreads) void gemm_nn_kernel(const double *__restrict__ A, int64_t lda, int m,
+template <int TPW, int NG>
+__global__ __launch_bounds__(128 * NG) void gemm_nn_kernel(const double *__restrict__ A, int64_t lda, int m,
                                                            const double *__restrict__ S, int64_t lds, int c,
                                                            int64_t N, double alpha, double beta,
                                                            double *__restrict__ Out, int64_t ldo) {
-    extern __shared__ double red_nn[];                     // [4][16][16 NT + 1]
-    constexpr int ldr = 16 * NT + 1;
+    // NG tile groups of TPW tiles; 2 NG waves
+    constexpr int kW = 2 * NG, kT = 64 * kW;
+    constexpr int kC = 16 * TPW * NG;                     // columns covered
+    __shared__ double sS[kNNChunk][kC + 2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t row0 = int64_t(blockIdx.x) * 16;
-    const int j0 = blockIdx.y * 16 * NT;
+    const int64_t row0 = int64_t(blockIdx.x) * 32 + 16 * (w & 1);
+    const int tg = w >> 1;
     const int64_t rowc = min(row0 + li, N - 1);            // clamped: rows past N are not stored
-    const int steps = (m + 3) / 4;
-    doublex4 acc[NT];
+    doublex4 acc[TPW];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-    // batch q of this wave: steps w + 4 (kNNBatch q + u), u < kNNBatch
-    auto load = [&](int q, double (&a)[kNNBatch], double (&b)[kNNBatch][NT]) {
+    for (int t = 0; t < TPW; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    constexpr int kPS = (kNNChunk * kC + kT - 1) / kT;    // S elements per thread per chunk
+    double ps[kPS], pa[kNNChunk / 4];
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < kNNBatch; ++u) {
-            const int k = 4 * (w + 4 * (kNNBatch * q + u)) + lk;
-            const bool kok = k < m;
-            const int kc = kok ? k : m - 1;
-            const double va = A[rowc + lda * kc];
-            a[u] = kok ? va : 0.0;
+        for (int q = 0; q < kPS; ++q) {
+            const int e = threadIdx.x + q * kT;
+            const int kk = e % kNNChunk, j = e / kNNChunk;
+            const bool ok = e < kNNChunk * kC && k0 + kk < m && j < c;
+            const double v = S[(ok ? k0 + kk : 0) + lds * (ok ? j : 0)];
+            ps[q] = ok ? v : 0.0;
+        }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int j = j0 + 16 * t + li;
-                const double vs = S[kc + lds * min(j, c - 1)];
-                b[u][t] = (kok && j < c) ? vs : 0.0;
+        for (int st = 0; st < kNNChunk / 4; ++st) {
+            const int k = k0 + 4 * st + lk;
+            const bool ok = k < m;
+            const double v = A[rowc + lda * (ok ? k : 0)];
+            pa[st] = ok ? v : 0.0;
+        }
+    };
+    if (m > 0) load(0);
+    for (int k0 = 0; k0 < m; k0 += kNNChunk) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPS; ++q) {
+            const int e = threadIdx.x + q * kT;
+            if (e < kNNChunk * kC) sS[e % kNNChunk][e / kNNChunk] = ps[q];
+        }
+        __syncthreads();
+        double a[kNNChunk / 4];
+#pragma unroll
+        for (int st = 0; st < kNNChunk / 4; ++st) a[st] = pa[st];
+        if (k0 + kNNChunk < m) load(k0 + kNNChunk);
+#pragma unroll
+        for (int st = 0; st < kNNChunk / 4; ++st)
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const double sv = sS[4 * st + lk][16 * (TPW * tg + t) + li];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, a[st], acc[t], 0, 0, 0);
             }
-        }
-    };
-    auto mma = [&](const double (&a)[kNNBatch], const double (&b)[kNNBatch][NT]) {
-#pragma unroll
-        for (int u = 0; u < kNNBatch; ++u)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[u][t], a[u], acc[t], 0, 0, 0);
-    };
-    const int nbatch = (steps + 4 * kNNBatch - 1) / (4 * kNNBatch);
-    double a0[kNNBatch], b0[kNNBatch][NT], a1[kNNBatch], b1[kNNBatch][NT];
-    if (nbatch > 0) load(0, a0, b0);                       // m = 0: no loads, Out = beta Out
-    for (int q = 0; q < nbatch; q += 2) {
-        if (q + 1 < nbatch) load(q + 1, a1, b1);
-        mma(a0, b0);
-        if (q + 1 >= nbatch) break;
-        if (q + 2 < nbatch) load(q + 2, a0, b0);
-        mma(a1, b1);
     }
-    // partial tiles -> LDS: acc[t][r] of lane L = Out[row0 + (L & 15)][j0 + 16 t + (L >> 4) + 4 r]
+    // acc[t][r] of lane L = Out[row0 + (L & 15)][16 (TPW tg + t) + (L >> 4) + 4 r]
+    const int64_t row = row0 + li;
+    if (row < N)
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red_nn[(w * 16 + li) * ldr + 16 * t + lk + 4 * r] = acc[t][r];
-    __syncthreads();
-    for (int e = threadIdx.x; e < 16 * 16 * NT; e += kThreads) {
-        const int i = e & 15, jj = e >> 4;
-        const int64_t row = row0 + i;
-        const int j = j0 + jj;
-        if (row < N && j < c) {
-            double v = red_nn[i * ldr + jj];
-#pragma unroll
-            for (int ww = 1; ww < 4; ++ww) v += red_nn[(ww * 16 + i) * ldr + jj];
-            double *o = Out + row + ldo * j;
-            *o = beta == 0.0 ? alpha * v : alpha * v + beta * *o;
-        }
-    }
+            for (int r = 0; r < 4; ++r) {
+                const int j = 16 * (TPW * tg + t) + lk + 4 * r;
+                if (j < c) {
+                    double *o = Out + row + ldo * j;
+                    *o = beta == 0.0 ? alpha * acc[t][r] : alpha * acc[t][r] + beta * *o;
+                }
+            }
 }
 
-template <int NT>
+template <int TPW, int NG>
 void launch_gemm_nn_t(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
                       double alpha, double beta, double *Out, int64_t ldo, hipStream_t s) {
-    const size_t lds_bytes = size_t(4) * 16 * (16 * NT + 1) * sizeof(double);
-    // once per process (thread-safe initialisation of a function-local static)
-    static const bool attr = [lds_bytes] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&gemm_nn_kernel<NT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
-        return true;
-    }();
-    (void)attr;
-    const dim3 grid(unsigned((N + 15) / 16), unsigned((c + 16 * NT - 1) / (16 * NT)));
-    hipLaunchKernelGGL((gemm_nn_kernel<NT>), grid, dim3(kThreads), lds_bytes, s, A, lda, m, S, lds, c, N, alpha,
+    const dim3 grid(unsigned((N + 31) / 32));
+    hipLaunchKernelGGL((gemm_nn_kernel<TPW, NG>), grid, dim3(128 * NG), 0, s, A, lda, m, S, lds, c, N, alpha,
                        beta, Out, ldo);
+}
+
+// R[:, j] = AX[:, j] - theta_j X[:, j] (if R) and the partial sums of r^2 over the row
+// chunk g (blockIdx.y): part[g kk + j].  One workgroup per (column, row chunk).
+__global__ __launch_bounds__(kThreads) void residual_partial_kernel(
+    const double *__restrict__ X, const double *__restrict__ AX, const double *__restrict__ theta, int64_t N,
+    int64_t ld, int64_t rows_per_chunk, int kk, double *__restrict__ R, double *__restrict__ part) {
+    const int j = blockIdx.x, g = blockIdx.y;
+    const double t = theta[j];
+    const int64_t r0 = int64_t(g) * rows_per_chunk, r1 = min(N, r0 + rows_per_chunk);
+    double s = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kThreads) {
+        const double r = AX[i + ld * j] - t * X[i + ld * j];
+        if (R) R[i + ld * j] = r;
+        s = fma(r, r, s);
+    }
+    __shared__ double red[kThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[int64_t(g) * kk + j] = red[0] + red[1] + red[2] + red[3];
+}
+
+// norms[j] = sqrt(sum_g part[g kk + j]) in chunk order.
+__global__ __launch_bounds__(kThreads) void residual_norm_kernel(const double *__restrict__ part, int G, int kk,
+                                                                 double *__restrict__ norms) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= kk) return;
+    double v = 0.0;
+    for (int g = 0; g < G; ++g) v += part[int64_t(g) * kk + j];
+    norms[j] = sqrt(v);
 }
 
 }  // namespace
 
 int gram_splits(int64_t N, int m, int c, int n_cu) {
     (void)m; (void)c; (void)n_cu;
-    int64_t g = (N + 2 * kSlab - 1) / (2 * kSlab);     // at least two slabs per range
+    int64_t g = (N + kRangeRows - 1) / kRangeRows;       // at least 128 rows per range
     if (g > kG) g = kG;
     if (g < 1) g = 1;
     return int(g);
 }
 
-// C (m x c, column-major, ld m) = A^T B with A: N x m (ld lda), B: N x c (ld ldb).
-// `part` needs gram_splits(N, ...) * m * c doubles (at most 256 m c).
+int64_t gram_part_elems(int64_t N, int m, int c) {
+    const int64_t nblk = (m + kGramRows - 1) / kGramRows;
+    const int64_t tiles = std::min<int64_t>(kMaxCT, (c + 15) / 16);
+    return int64_t(gram_splits(N, m, c, 0)) * nblk * 4 * tiles * kThreads;
+}
+
+// C (m x c, column-major, ld m) = A^T B with A: N x m (ld lda), B: N x c (ld ldb), c <= 128
+// per launch (wider products are done in column blocks of 128).
+// `part` needs gram_part_elems(N, m, c) doubles.
 void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int c,
                  int64_t N, double *part, double *C, int n_cu, hipStream_t s) {
+    if (m < 1 || c < 1) return;
     const int G0 = gram_splits(N, m, c, n_cu);
     int64_t rows = (N + G0 - 1) / G0;
     rows = (rows + kSlab - 1) / kSlab * kSlab;
-    const int G = int((N + rows - 1) / rows);
-    dim3 grid((m + kT - 1) / kT, (c + kT - 1) / kT, G);
-    hipLaunchKernelGGL(gram_partial_kernel, grid, dim3(kThreads), 0, s, A, lda, m, B, ldb, c, N, rows,
-                       part);
-    const int64_t mc = int64_t(m) * c;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(unsigned((mc + 3) / 4)), dim3(kThreads), 0, s, part,
-                       G, mc, C);
+    const int G = int(std::max<int64_t>(1, (N + rows - 1) / rows));
+    for (int j0 = 0; j0 < c; j0 += 16 * kMaxCT) {
+        const int cb = std::min(16 * kMaxCT, c - j0);
+        const int nblk = (m + kGramRows - 1) / kGramRows;
+        const dim3 grid{unsigned(nblk), unsigned(G), 1u};
+        const double *Bj = B + int64_t(j0) * ldb;
+        double *Cj = C + int64_t(j0) * m;
+#define KL_GRAM(CT)                                                                                        \
+    do {                                                                                                   \
+        hipLaunchKernelGGL((gram_mfma_kernel<CT>), grid, dim3(kThreads), 0, s, A, lda, m, Bj, ldb, cb, N,     \
+                           rows, part);                                                                    \
+        const int64_t slots = int64_t(nblk) * 4 * CT * kThreads;                                           \
+        hipLaunchKernelGGL((gram_reduce_kernel<CT>), dim3(unsigned((slots + 63) / 64)),                      \
+                           dim3(kThreads), 0, s, part, G, nblk, m, cb, Cj);                                \
+    } while (0)
+        switch ((cb + 15) / 16) {
+        case 1: KL_GRAM(1); break;
+        case 2: KL_GRAM(2); break;
+        case 3: KL_GRAM(3); break;
+        case 4: KL_GRAM(4); break;
+        case 5: KL_GRAM(5); break;
+        case 6: KL_GRAM(6); break;
+        case 7: KL_GRAM(7); break;
+        default: KL_GRAM(8); break;
+        }
+#undef KL_GRAM
+    }
 }
 
 void launch_gemm_nn(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
                     double alpha, double beta, double *Out, int64_t ldo, hipStream_t s) {
     if (N < 1 || c < 1) return;
-    if (m < 1) {                        // empty contraction: Out = beta Out
-        if (beta != 1.0) launch_gemm_nn_t<1>(A, lda, 0, S, lds, c, N, alpha, beta, Out, ldo, s);
-        return;
+    const int mm = std::max(m, 0);       // m = 0: empty contraction, Out = beta Out
+    for (int j0 = 0; j0 < c; j0 += 16 * kNNMaxTiles) {
+        const int cb = std::min(16 * kNNMaxTiles, c - j0);
+        const double *Sj = S + int64_t(j0) * lds;
+        double *Oj = Out + int64_t(j0) * ldo;
+        switch ((cb + 15) / 16) {
+        case 1: launch_gemm_nn_t<1, 1>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+        case 2: launch_gemm_nn_t<1, 2>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+        case 3: launch_gemm_nn_t<1, 3>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+        case 4: launch_gemm_nn_t<2, 2>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+        case 5:
+        case 6: launch_gemm_nn_t<2, 3>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+        default: launch_gemm_nn_t<2, 4>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+        }
     }
-    switch (std::min(kNNMaxTiles, (c + 15) / 16)) {
-    case 1: launch_gemm_nn_t<1>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
-    case 2: launch_gemm_nn_t<2>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
-    case 3: launch_gemm_nn_t<3>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
-    case 4: launch_gemm_nn_t<4>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
-    case 5: launch_gemm_nn_t<5>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
-    case 6: launch_gemm_nn_t<6>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
-    case 7: launch_gemm_nn_t<7>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
-    default: launch_gemm_nn_t<8>(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, s); break;
-    }
+}
+
+int residual_chunks(int64_t N) {
+    return int(std::max<int64_t>(1, std::min<int64_t>(64, (N + 2047) / 2048)));
+}
+
+void launch_residual(const double *X, const double *AX, const double *theta, int64_t N, int64_t ld, int kk,
+                     double *R, double *part, double *norms, hipStream_t s) {
+    if (kk < 1) return;
+    const int G = residual_chunks(N);
+    const int64_t rows = (N + G - 1) / G;
+    hipLaunchKernelGGL(residual_partial_kernel, dim3(unsigned(kk), unsigned(G)), dim3(kThreads), 0, s, X, AX, theta,
+                       N, ld, rows, kk, R, part);
+    hipLaunchKernelGGL(residual_norm_kernel, dim3(unsigned((kk + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       part, G, kk, norms);
 }
 
 }  // namespace kl

@@ -186,8 +186,9 @@ void launch_pack_stage5(int precision, const double *y, int64_t ldy, int64_t Nt,
 void launch_unpack_stage5(int precision, const void *Z5, int nsplit, int64_t Ntpad, int64_t Nt,
                           int nvec, double scale, double *z, int64_t ldz, hipStream_t s);
 // C (m x c, column-major, ld m) = A^T B for tall-skinny FP64 blocks; `part` holds
-// gram_splits(N, m, c) * m * c doubles of row-range partials (at most 256 m c).
+// gram_part_elems(N, m, c) doubles of row-range partials (it grows with m and c).
 int gram_splits(int64_t N, int m, int c, int n_cu);
+int64_t gram_part_elems(int64_t N, int m, int c);
 void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t ldb, int c,
                  int64_t N, double *part, double *C, int n_cu, hipStream_t s);
 
@@ -195,6 +196,11 @@ void launch_gram(const double *A, int64_t lda, int m, const double *B, int64_t l
 // not read).
 void launch_gemm_nn(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
                     double alpha, double beta, double *Out, int64_t ldo, hipStream_t s);
+// R[:, j] = AX[:, j] - theta_j X[:, j] (R may be NULL) and norms[j] = ||R[:, j]||_2 for
+// j < kk (device arrays, ld ld); `part` holds residual_chunks(N) * kk doubles.
+int residual_chunks(int64_t N);
+void launch_residual(const double *X, const double *AX, const double *theta, int64_t N, int64_t ld, int kk,
+                     double *R, double *part, double *norms, hipStream_t s);
 
 // Stage-5 launch geometry: rows per workgroup, and the number of l-splits (forced > 0
 // overrides the automatic choice); *lchunk receives the l-range length of one split.
