@@ -10,7 +10,7 @@ BF16x3 and BF16 stage-5 kernels on the same block, times the eigensolve to k pai
 relative residual 1e-6 in every form, and times the CPU oracle on the same workload (all
 host cores, and one core on a bounded sample).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c5|c1]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube24|annulus64|annulus48|square16]
 """
 
 import argparse
@@ -27,16 +27,18 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 # HBM bytes per stage-5 launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a
 # plain 256 MiB copy), keyed by (workload, precision, rb, nsplit); see
-# profiles/stage5_f32_c2_hbm_traffic.md.  Only reported for the setting it was measured on.
-MEASURED_TRAFFIC = {("c2", "f32", 2, 6): 8453 * 1024, ("c2", "f32", 2, 7): 9029 * 1024,
-                    ("c2", "f32", 8, 6): 8428 * 1024, ("c2", "f32", 8, 7): 9003 * 1024}
+# profiles/stage5_f64_cube24_hbm_traffic.md and profiles/stage5_f32_annulus64_hbm_traffic.md.  Only
+# reported for the setting it was measured on.
+MEASURED_TRAFFIC = {("cube24", "f64", 4, 10): 82959 * 1024,
+                    ("annulus64", "f32", 2, 6): 8453 * 1024, ("annulus64", "f32", 2, 7): 9029 * 1024,
+                    ("annulus64", "f32", 8, 6): 8428 * 1024, ("annulus64", "f32", 8, 7): 9003 * 1024}
 WORKLOADS = {
-    "c2": ("2D quarter annulus (r in [1,2], NURBS map) 64x64 cubic, Ntilde = N = 4489, "
-           "squared exponential L = 0.5, k = 40"),
-    "c3": ("3D sine-perturbed unit cube 24^3 quadratic, Ntilde = N = 17576, exponential L = 0.5, "
-           "k = 50"),
-    "c5": "2D quarter annulus 48x48 cubic, Ntilde = N = 2601, squared exponential L = 0.5, k = 16",
-    "c1": "2D unit square 16x16 quadratic, Ntilde = N = 324, exponential L = 1, k = 20",
+    "annulus64": ("2D quarter annulus (r in [1,2], NURBS map) 64x64 cubic, Ntilde = N = 4489, "
+                  "squared exponential L = 0.5, k = 40"),
+    "cube24": ("3D sine-perturbed unit cube 24^3 quadratic, Ntilde = N = 17576, exponential L = 0.5, "
+               "k = 50"),
+    "annulus48": "2D quarter annulus 48x48 cubic, Ntilde = N = 2601, squared exponential L = 0.5, k = 16",
+    "square16": "2D unit square 16x16 quadratic, Ntilde = N = 324, exponential L = 1, k = 20",
 }
 
 
@@ -148,7 +150,7 @@ def valu_slots_per_pair(kind, d, precision, rates):
 
 
 def warm_start_section(n_train, epochs, n_eval, solves=3):
-    """Config 5: the network is trained on n_train method-generated FP64 solves (tol 1e-10)
+    """Warm-start section: the network is trained on n_train method-generated FP64 solves (tol 1e-10)
     of the 48x48 cubic quarter annulus (training draws seed 2000), then the held-out draws
     (seed 2001) are solved to 1e-6 four ways: plain FP64 from a random block, FP32 with
     FP64 refinement from a random block, the same from the predicted block, and plain FP64
@@ -201,7 +203,7 @@ def warm_start_section(n_train, epochs, n_eval, solves=3):
             rec[name].append(best)
             app[name].append(sum(rep["n_applies"]))
     med = {k: float(np.median(v)) * 1e3 for k, v in rec.items()}
-    return {"workload": "c5: 2D quarter annulus 48x48 cubic, N = 2601, k = 16, block 16; "
+    return {"workload": "annulus48: 2D quarter annulus 48x48 cubic, N = 2601, k = 16, block 16; "
                         "L ~ logU[0.1,2], a ~ logU[0.5,2], flag ~ B(1/2)",
             "n_train": n_train, "epochs": epochs, "generate_s": gen_s, "train_s": train_s,
             "loss_first_last": [float(losses[0]), float(losses[-1])], "n_eval": n_eval,
@@ -211,7 +213,7 @@ def warm_start_section(n_train, epochs, n_eval, solves=3):
 
 
 def batch_section(reps=20):
-    """Config 4: 64 uneven 2D problems (seed 1127).  The batched apply (one graph replay
+    """Batch section: 64 uneven 2D problems (seed 1127).  The batched apply (one graph replay
     of 32 columns per problem, autotuned tiles) against the same 64 applies issued one
     problem after the other; then 20 eigenpairs of every problem at 1e-6, batched
     (FP32 with FP64 refinement, median of three runs: the solve is bound by host threads
@@ -226,7 +228,7 @@ def batch_section(reps=20):
     kinds = [d["cov"]["kind"] for d in descs]
     B = kl.Batch(descs)
     pairs = float(sum(nt * nt for nt in B.Nt))
-    out = {"workload": "c4: 64 unit-square problems, nelem ~ U{16..96}^2, p ~ U{2,3,4}, exp/sqexp, "
+    out = {"workload": "batch64: 64 unit-square problems, nelem ~ U{16..96}^2, p ~ U{2,3,4}, exp/sqexp, "
                        "L ~ logU[0.1,2] (seed 1127), 32 vectors each",
            "pairs_per_apply": pairs}
     x = torch.randn(B.Ntot * 32, dtype=torch.float64, device="cuda")
@@ -316,7 +318,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cube24", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3", "bf16"],
                     help="stage-5 precision of the headline (default FP64, the paper's arithmetic)")
     ap.add_argument("--other-precisions", default="f32,bf16x3,bf16",
@@ -326,12 +328,12 @@ def main():
     ap.add_argument("--solves", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--oracle-eigs", action="store_true",
-                    help="also time the oracle's ARPACK eigenpairs on the host cores (about a minute at c3)")
+                    help="also time the oracle's ARPACK eigenpairs on the host cores (about a minute on the 24^3 cube)")
     ap.add_argument("--mlp-train", type=int, default=2000,
                     help="training solves for the warm-start section (0 = skip the section)")
     ap.add_argument("--mlp-epochs", type=int, default=1000)
     ap.add_argument("--mlp-eval", type=int, default=20)
-    ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batch section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch section")
     ap.add_argument("--no-tune", action="store_true", help="keep the automatic stage-5 split")
     ap.add_argument("--tune-objective", default="apply", choices=["apply", "stage5"],
                     help="what the stage-5 tile search minimises: the whole apply (default) or the kernel alone")

@@ -64,7 +64,7 @@ def _gpu_apply(G, V, precision):
 
 
 SMALL = [
-    ("c1", workloads.config("c1")[0]),
+    ("square16", workloads.config("square16")[0]),
     ("annulus_ragged", workloads.quarter_annulus(13, 3, "sqexp", (0.5, 0.8))),
     ("cube", workloads.sine_cube(6, 2, "exp", 0.5)),
     ("interp_ne_trial", {"dim": 2, "degree": [2, 3], "nelem": [9, 5], "interp_degree": [3, 1],
@@ -132,9 +132,9 @@ def test_block_widths_and_strides(nvec):
     assert torch.all(ys[:, P.N:] == 7.0)          # padding of the output untouched
 
 
-def test_full_size_config2_apply():
-    """Config 2 (64x64 cubic quarter annulus, sqexp L = 0.5) at full size, 32 vectors."""
-    desc = workloads.config("c2")[0]
+def test_full_size_annulus64_apply():
+    """The 64x64 cubic quarter annulus, sqexp L = 0.5) at full size, 32 vectors."""
+    desc = workloads.config("annulus64")[0]
     P = operator.Problem(desc)
     G = kl.Problem(desc)
     V = workloads.random_block(P.N, 32, seed=5)
@@ -144,10 +144,10 @@ def test_full_size_config2_apply():
         _check(out, ref, prec, "full")
 
 
-def test_full_size_config5_apply():
-    """Config 5 (48x48 cubic quarter annulus, sqexp L = 0.5, the warm-start workload) at
+def test_full_size_annulus48_apply():
+    """The 48x48 cubic quarter annulus, sqexp L = 0.5, the warm-start workload) at
     full size, 32 vectors, every precision."""
-    desc = workloads.config("c5")[0]
+    desc = workloads.config("annulus48")[0]
     P = operator.Problem(desc)
     G = kl.Problem(desc)
     V = workloads.random_block(P.N, 32, seed=6)
@@ -183,12 +183,12 @@ def test_extreme_correlation_lengths(name, desc):
         _check(out, ref, prec, name)
 
 
-def test_full_size_config3_apply():
-    """Config 3 (24^3 perturbed cube, exp L = 0.5) at full size: the whole apply (fused
+def test_full_size_cube24_apply():
+    """The 24^3 perturbed cube, exp L = 0.5) at full size: the whole apply (fused
     first two directions, third direction, stage 5, backward) on the 32 columns the
     eigensolver applies at a time, and on a ragged 35-column call, against the oracle's
     Algorithm 1 with its C stage 5."""
-    desc = workloads.config("c3")[0]
+    desc = workloads.config("cube24")[0]
     P = operator.Problem(desc)
     G = kl.Problem(desc)
     assert G.apply_config(True)
@@ -196,15 +196,15 @@ def test_full_size_config3_apply():
     ref = P.apply(V, stage5=lambda Y: cstage5.stage5(P, Y))
     for prec in PRECS:
         out = _gpu_apply(G, V[:, :32], prec)
-        _check(out, ref[:, :32], prec, "c3 32")
-    _check(_gpu_apply(G, V, "f64"), ref, "f64", "c3 35")
+        _check(out, ref[:, :32], prec, "cube24 32")
+    _check(_gpu_apply(G, V, "f64"), ref, "f64", "cube24 35")
 
 
-def test_full_size_config3_stage5_sampled_rows():
-    """Config 3 (24^3 perturbed cube, exp L = 0.5): stage 5 on 32 vectors, sampled rows
+def test_full_size_cube24_stage5_sampled_rows():
+    """The 24^3 perturbed cube, exp L = 0.5): stage 5 on 32 vectors, sampled rows
     recomputed one by one by the oracle's kernel definition."""
     from oracle import covariance
-    desc = workloads.config("c3")[0]
+    desc = workloads.config("cube24")[0]
     G = kl.Problem(desc)
     X, _ = G.points()
     Y = workloads.random_block(G.Nt, 32, seed=6)
@@ -217,11 +217,11 @@ def test_full_size_config3_stage5_sampled_rows():
         rows = np.random.default_rng(0).choice(G.Nt, 64, replace=False)
         rows = np.concatenate([rows, [0, G.Nt - 1]])
         ref = covariance.gamma(desc["cov"], X[rows], X) @ Y
-        _check(out[rows], ref, prec, "c3 stage5 rows")
+        _check(out[rows], ref, prec, "cube24 stage5 rows")
 
 
 def test_apply_is_symmetric_on_gpu():
-    desc = workloads.config("c3")[0]
+    desc = workloads.config("cube24")[0]
     G = kl.Problem(desc)
     rng = np.random.default_rng(7)
     U = rng.standard_normal((G.N, 2))

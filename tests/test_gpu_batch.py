@@ -112,16 +112,16 @@ def test_batch_eigs_small_matches_dense_oracle(small):
 
 
 @pytest.fixture(scope="module")
-def c4():
+def batch64():
     descs = workloads.batch_problems(1127)
     return descs, kl.Batch(descs)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_c4_batch_apply_matches_single_problem_path(c4, prec):
+def test_batch64_batch_apply_matches_single_problem_path(batch64, prec):
     """All 64 problems of the uneven batch against the single-problem apply, and three of
     them (the largest, the smallest and one squared-exponential) against the oracle."""
-    descs, B = c4
+    descs, B = batch64
     nvec = 32
     x, host = _fill(B, nvec, 100)
     y = B.arena(nvec)
@@ -143,10 +143,10 @@ def test_c4_batch_apply_matches_single_problem_path(c4, prec):
             assert _err(outs[i], ref, "f64") <= 1e-12, i
 
 
-def test_c4_batch_eigs_fp32_refined(c4):
-    """Config 4: 20 eigenpairs of each of the 64 problems, FP32 applies with FP64
+def test_batch64_batch_eigs_fp32_refined(batch64):
+    """The 64-problem batch: 20 eigenpairs of each of the 64 problems, FP32 applies with FP64
     refinement, against per-problem FP64 solves."""
-    descs, B = c4
+    descs, B = batch64
     k = 20
     ev, V, reps = B.eigs(k, precision="f32", block=32, tol=1e-6)
     assert all(r["converged"] == k for r in reps)
@@ -156,14 +156,14 @@ def test_c4_batch_eigs_fp32_refined(c4):
         assert np.all(np.abs(ev[i] - w) <= 1e-6 * np.abs(w) + 1e-12 * w[0]), (i, ev[i], w)
 
 
-def test_c4_batch_eigs_match_oracle(c4):
-    """Config 4 batched (FP32 applies with FP64 refinement, tol 1e-10), sampled problems
+def test_batch64_batch_eigs_match_oracle(batch64):
+    """The 64-problem batch (FP32 applies with FP64 refinement, tol 1e-10), sampled problems
     against the oracle's eigenpairs: the smallest (sqexp), an exponential with L near 1.8, a
     fast-decaying squared exponential (L near 1.5, eigenvalues down to the 1e-12 floor), a
     short exponential (L near 0.11), all by dense LAPACK, and the largest problem (8,624
     dofs, sqexp) by ARPACK on the literal Algorithm 1."""
     from test_gpu_eigs import check_pairs
-    descs, B = c4
+    descs, B = batch64
     k = 20
     ev, V, reps = B.eigs(k, precision="f32", block=32, tol=1e-10)
     assert all(r["converged"] == k for r in reps), [r["converged"] for r in reps]
@@ -175,5 +175,5 @@ def test_c4_batch_eigs_match_oracle(c4):
             w_ref, V_ref = oeigs.iterative_eigs(P, k + 8, tol=1e-13, stage5=lambda Y: cstage5.stage5(P, Y))
         X = B.block(V, i, k).cpu().numpy()
         n = check_pairs(ev[i], X, w_ref, V_ref, k)
-        print("C4 problem", i, "N", P.N, "vectors compared", n)
+        print("batch problem", i, "N", P.N, "vectors compared", n)
         assert n >= 4, (i, n)

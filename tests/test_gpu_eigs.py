@@ -73,8 +73,8 @@ def _solve(desc, k, precision, tol=1e-10, **kw):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_config1_matches_dense_oracle(precision):
-    desc, k, _ = workloads.config("c1")
+def test_square16_matches_dense_oracle(precision):
+    desc, k, _ = workloads.config("square16")
     P = operator.Problem(desc)
     w_ref, V_ref = oeigs.dense_eigs(P, k + 10)
     G, w, V, rep = _solve(desc, k, precision)
@@ -100,12 +100,12 @@ def _arpack(name, desc, kref):
 
 
 @pytest.mark.parametrize("precision", FORMS)
-def test_config2_matches_arpack_oracle(precision):
-    """Config 2 (64x64 cubic quarter annulus, sqexp L = 0.5, k = 40) in every form: FP64,
+def test_annulus64_matches_arpack_oracle(precision):
+    """The 64x64 cubic quarter annulus, sqexp L = 0.5, k = 40) in every form: FP64,
     and FP32 / BF16x3 / BF16 stage 5 with the FP64 refinement phase (Sec. 4.4.2 eigenproblem,
     solved to 1e-10 under the FP64 operator)."""
-    desc, k, _ = workloads.config("c2")
-    w_ref, V_ref = _arpack("c2", desc, k + 8)
+    desc, k, _ = workloads.config("annulus64")
+    w_ref, V_ref = _arpack("annulus64", desc, k + 8)
     G, w, V, rep = _solve(desc, k, precision)
     assert rep["status"] == "KL_OK", rep
     assert check_pairs(w, V, w_ref, V_ref, k) >= k // 2
@@ -128,20 +128,20 @@ def test_cube_mid_size_matches_arpack_oracle(precision):
 
 
 @pytest.fixture(scope="module")
-def c3_golden():
+def cube24_golden():
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_eigs.npz")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cube24_eigs.npz")
     z = np.load(path)
     return z["evals"], z["evecs"].astype(np.float64)
 
 
 @pytest.mark.parametrize("precision", FORMS)
-def test_config3_matches_oracle_eigenpairs(c3_golden, precision):
-    """Config 3 (24^3 perturbed cube, exp L = 0.5, k = 50, block 32) in every form against
-    the oracle's ARPACK eigenpairs (tests/golden/c3_eigs.npz, written by
-    tests/golden/make_c3_eigs.py from the oracle alone)."""
-    w_ref, V_ref = c3_golden
-    desc, k, b = workloads.config("c3")
+def test_cube24_matches_oracle_eigenpairs(cube24_golden, precision):
+    """The 24^3 perturbed cube, exp L = 0.5, k = 50, block 32) in every form against
+    the oracle's ARPACK eigenpairs (tests/golden/cube24_eigs.npz, written by
+    tests/golden/make_cube24_eigs.py from the oracle alone)."""
+    w_ref, V_ref = cube24_golden
+    desc, k, b = workloads.config("cube24")
     G, w, V, rep = _solve(desc, k, precision, block=b)
     assert rep["status"] == "KL_OK" and rep["converged"] == k, rep
     assert np.max(np.abs(V.T @ V - np.eye(k))) < 1e-8
@@ -151,7 +151,7 @@ def test_config3_matches_oracle_eigenpairs(c3_golden, precision):
 def test_default_tolerance_meets_criterion_under_fp64():
     """At the metric's tolerance (1e-6) the FP32 form's pairs satisfy the criterion when
     re-checked with the oracle's FP64 operator."""
-    desc, k, _ = workloads.config("c2")
+    desc, k, _ = workloads.config("annulus64")
     P = operator.Problem(desc)
     G, w, V, rep = _solve(desc, k, "f32", tol=1e-6)
     r = np.linalg.norm(P.apply(V, stage5=lambda Y: cstage5.stage5(P, Y)) - V * w[None, :], axis=0)
@@ -159,7 +159,7 @@ def test_default_tolerance_meets_criterion_under_fp64():
 
 
 def test_warm_start_with_exact_vectors_converges_fast():
-    desc, k, _ = workloads.config("c1")
+    desc, k, _ = workloads.config("square16")
     P = operator.Problem(desc)
     w_ref, V_ref = oeigs.dense_eigs(P, 32)
     G = kl.Problem(desc)
@@ -183,7 +183,7 @@ def test_tiny_problem_full_space():
 
 
 def test_nonconvergence_returns_best_pairs():
-    desc, k, _ = workloads.config("c2")
+    desc, k, _ = workloads.config("annulus64")
     G = kl.Problem(desc)
     w, V, rep = G.eigs(k, precision="f64", tol=1e-14, abs_floor=1e-30, max_applies=64)
     assert rep["status"] == "KL_ENOCONV"
@@ -194,7 +194,7 @@ def test_nonconvergence_returns_best_pairs():
 
 
 def test_eigs_errors():
-    desc, k, _ = workloads.config("c1")
+    desc, k, _ = workloads.config("square16")
     G = kl.Problem(desc)
     with pytest.raises(kl.KLError) as e:
         G.eigs(G.N + 1)
@@ -209,11 +209,11 @@ def test_eigs_errors():
     assert e.value.status == -1
 
 
-def test_config3_residuals_under_fp64_apply():
-    """Config 3 (3-D, 24^3 quadratic, k = 50) at the metric's tolerance: every form meets
+def test_cube24_residuals_under_fp64_apply():
+    """The 3-D 24^3 cube ( quadratic, k = 50) at the metric's tolerance: every form meets
     the criterion at 1e-6 under the FP64 apply (itself checked against the oracle
     elsewhere), the basis is orthonormal, and the forms agree on the eigenvalues."""
-    desc, k, b = workloads.config("c3")
+    desc, k, b = workloads.config("cube24")
     G = kl.Problem(desc)
     ws = {}
     for prec in FORMS:
@@ -235,7 +235,7 @@ def test_coefficients_output_matches_oracle():
     """coeffs = 1 returns v = L^{-T} v' (Sec. 4.1): the same solve (same seed) with coeffs =
     0, transformed by the oracle's stage 1, gives it; the eigenfunctions have unit L2 norm
     (v^T Z v = 1 with the oracle's mass matrix)."""
-    for desc in (workloads.config("c1")[0], workloads.sine_cube(5, 2, "exp", 0.5)):
+    for desc in (workloads.config("square16")[0], workloads.sine_cube(5, 2, "exp", 0.5)):
         P = operator.Problem(desc)
         G = kl.Problem(desc)
         k = 12
@@ -253,7 +253,7 @@ def test_coefficients_output_matches_oracle():
 def test_solve_is_ordered_after_the_callers_stream():
     """A start block produced on a non-default stream (behind a long queue of work there) is
     complete before the solver reads it: exact eigenvectors as x0 converge at once."""
-    desc, k, _ = workloads.config("c1")
+    desc, k, _ = workloads.config("square16")
     P = operator.Problem(desc)
     w_ref, V_ref = oeigs.dense_eigs(P, 32)
     G = kl.Problem(desc)

@@ -241,7 +241,7 @@ def test_full_galerkin_linear_kernel_matches_ibq():
 
 
 def test_iterative_equals_dense_eigs():
-    desc, k, _ = workloads.config("c1")
+    desc, k, _ = workloads.config("square16")
     P = operator.Problem(desc)
     w, V = eigs.dense_eigs(P, k)
     wi, Vi = eigs.iterative_eigs(P, k, tol=1e-12)

@@ -27,7 +27,7 @@ def _noalloc(G, x, y, precision):
 
 @pytest.mark.parametrize("precision", ["f64", "f32", "bf16x3", "bf16"])
 def test_noalloc_matches_apply_on_two_calls(precision):
-    cases = [(workloads.config("c3")[0], 35), (workloads.config("c1")[0], 7)]
+    cases = [(workloads.config("cube24")[0], 35), (workloads.config("square16")[0], 7)]
     for desc, nvec in cases:
         G = kl.Problem(desc)
         x = kl.to_device_block(workloads.random_block(G.N, nvec, seed=nvec))

@@ -41,15 +41,15 @@ def sine_cube(nelem=24, p=2, kind="exp", ell=0.5):
             "cov": {"kind": kind, "sigma2": 1.0, "corr_len": [ell] * 3}}
 
 
-# The five named configurations: (description, number of eigenpairs, block size)
+# The named workloads: (description, number of eigenpairs, block size)
 def config(name):
-    if name == "c1":      # unit square 16x16, quadratic, exponential L = 1, 20 pairs
+    if name == "square16":      # unit square 16x16, quadratic, exponential L = 1, 20 pairs
         return unit_square(16, 2, "exp", 1.0), 20, 32
-    if name == "c2":      # quarter annulus 64x64, cubic, squared exponential L = 0.5, 40 pairs
+    if name == "annulus64":      # quarter annulus 64x64, cubic, squared exponential L = 0.5, 40 pairs
         return quarter_annulus(64, 3, "sqexp", (0.5, 0.5)), 40, 32
-    if name == "c3":      # perturbed cube 24^3, quadratic, exponential L = 0.5, 50 pairs
+    if name == "cube24":      # perturbed cube 24^3, quadratic, exponential L = 0.5, 50 pairs
         return sine_cube(24, 2, "exp", 0.5), 50, 32
-    if name == "c5":      # quarter annulus 48x48, cubic (MLP warm-start problem family)
+    if name == "annulus48":      # quarter annulus 48x48, cubic (MLP warm-start problem family)
         return quarter_annulus(48, 3, "sqexp", (0.5, 0.5)), 16, 16
     raise KeyError(name)
 
