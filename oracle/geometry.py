@@ -35,13 +35,14 @@ import numpy as np
 from . import splines
 
 
-def _bspline_derivative_matrix(knots, p, x):
-    """d/dx B_{i,p}(x) = p/(xi_{i+p}-xi_i) B_{i,p-1} - p/(xi_{i+p+1}-xi_{i+1}) B_{i+1,p-1}."""
+def _bspline_derivative_matrix(knots, p, x, side=None):
+    """d/dx B_{i,p}(x) = p/(xi_{i+p}-xi_i) B_{i,p-1} - p/(xi_{i+p+1}-xi_{i+1}) B_{i+1,p-1}
+    (one-sided at a knot where the map is only C^0: side -1 from the left, else from the right)."""
     n = splines.dimension(knots, p)
     out = np.zeros((len(x), n))
     if p == 0:
         return out
-    lower = splines.basis_matrix(knots, p - 1, x)  # n + 1 functions
+    lower = splines.basis_matrix(knots, p - 1, x, side)  # n + 1 functions
     for i in range(n):
         d1 = knots[i + p] - knots[i]
         d2 = knots[i + p + 1] - knots[i + 1]
@@ -97,18 +98,21 @@ def _quarter_annulus_nurbs(r0, r1):
     return ku, 1, kv, 2, ctrl, weights
 
 
-def tensor_nurbs(degree, knots, ctrl, weights, u):
+def tensor_nurbs(degree, knots, ctrl, weights, u, side=None):
     """F(u) and DF(u) (shape (npts, d, d), D[r, i, j] = dF_i / du_j) of a d-variate NURBS map.
     Sums over the control net are written as tensor contractions of the per-direction basis
     matrices N_k (npts x m_k) and their derivatives, with the weights folded into the
-    homogeneous control points (w P, w)."""
+    homogeneous control points (w P, w).  side (npts, d) of +-1: the side from which each
+    coordinate is approached (it matters for DF on the C^0 lines of the map only)."""
     u = np.atleast_2d(np.asarray(u, dtype=np.float64))
     npts, d = u.shape
+    sd = np.ones((npts, d)) if side is None else np.asarray(side, dtype=np.float64).reshape(npts, d)
     ctrl = np.asarray(ctrl, dtype=np.float64)
     w = np.ones(ctrl.shape[:d]) if weights is None else np.asarray(weights, dtype=np.float64)
     Pw = np.concatenate([ctrl * w[..., None], w[..., None]], axis=-1)   # homogeneous (m_1..m_d, d + 1)
-    N = [splines.basis_matrix(np.asarray(knots[k], dtype=np.float64), degree[k], u[:, k]) for k in range(d)]
-    dN = [_bspline_derivative_matrix(np.asarray(knots[k], dtype=np.float64), degree[k], u[:, k])
+    N = [splines.basis_matrix(np.asarray(knots[k], dtype=np.float64), degree[k], u[:, k], sd[:, k])
+         for k in range(d)]
+    dN = [_bspline_derivative_matrix(np.asarray(knots[k], dtype=np.float64), degree[k], u[:, k], sd[:, k])
           for k in range(d)]
     letters = "abc"[:d]
     spec = ",".join("r" + letters[k] for k in range(d)) + "," + letters + "h->rh"
@@ -125,8 +129,10 @@ def tensor_nurbs(degree, knots, ctrl, weights, u):
     return X, D
 
 
-def map_points(geom, u):
-    """Physical points F(u) and det DF(u) for parametric points u of shape (npts, d)."""
+def map_points(geom, u, side=None):
+    """Physical points F(u) and det DF(u) for parametric points u of shape (npts, d); side
+    (npts, d) of +-1 selects one-sided derivatives on the C^0 lines of a tensor NURBS map
+    (the other maps are smooth)."""
     u = np.atleast_2d(np.asarray(u, dtype=np.float64))
     npts, d = u.shape
     kind = geom["kind"]
@@ -172,7 +178,7 @@ def map_points(geom, u):
         D = np.broadcast_to(np.eye(d), (npts, d, d)).copy()
         D += eps * amp[None, :, None] * grad[:, None, :]
     elif kind == "tensor_nurbs":
-        X, D = tensor_nurbs(geom["degree"], geom["knots"], geom["ctrl"], geom.get("weights"), u)
+        X, D = tensor_nurbs(geom["degree"], geom["knots"], geom["ctrl"], geom.get("weights"), u, side)
     else:
         raise ValueError("unknown map kind %r" % kind)
     if "rotation" in geom:

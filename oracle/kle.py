@@ -20,7 +20,8 @@ from . import kron, splines
 def greville_evaluation(P):
     """Values of the trial B-splines at the interpolation Greville grid: the Kronecker product
     of the univariate nt_k x n_k matrices B_j(g_i) (dense, small problems only)."""
-    mats = [splines.basis_matrix(P.knots[k], P.p[k], splines.greville(P.knots_t[k], P.pt[k]))
+    mats = [splines.basis_matrix(P.knots[k], P.p[k], splines.greville(P.knots_t[k], P.pt[k]),
+                                 splines.greville_sides(P.knots_t[k], P.pt[k]))
             for k in range(P.d)]
     return kron.kron_dense(mats)
 

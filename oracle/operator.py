@@ -36,8 +36,10 @@ class Problem:
     vectors on [0, 1]; None entries fall back to nelem), optional interp_degree[d],
     interp_nelem[d] (default: the trial space) and interp_mult[d] (multiplicity of the
     interpolation space's interior breakpoints, default (or 0) 1; interp_mult =
-    interp_degree gives the C^0 interpolation of Sec. 4.2) or interp_knots[d], map
-    (geometry dict), cov (covariance dict).
+    interp_degree gives the C^0 interpolation of Sec. 4.2, interp_degree + 1 a C^-1 one)
+    or interp_knots[d], map (geometry dict), cov (covariance dict).  Interior knots may
+    be repeated up to p + 1 times (C^-1): the Greville points at such a knot coincide and
+    are evaluated from their own sides (splines.greville_sides), J included.
     """
 
     def __init__(self, desc):
@@ -65,8 +67,8 @@ class Problem:
             else:
                 nek = net[k] or ne[k]
                 mk = int(mult[k]) or 1                            # 0 means the default, 1
-                if mk < 1 or mk > pt[k]:
-                    raise ValueError("interp_mult must lie in 1..interp degree")
+                if mk < 1 or mk > pt[k] + 1:
+                    raise ValueError("interp_mult must lie in 1..interp degree + 1")
                 self.knots_t.append(splines.knots_with_multiplicity(pt[k], [j / nek for j in range(1, nek)], mk))
         net = [len(np.unique(self.knots_t[k])) - 1 for k in range(d)]
         self.p, self.ne, self.pt, self.net = p, ne, pt, net
@@ -83,9 +85,12 @@ class Problem:
                   for k in range(d)]
         # Greville grid in vec order (first index fastest), mapped points, J
         g1 = [splines.greville(self.knots_t[k], pt[k]) for k in range(d)]
+        s1 = [splines.greville_sides(self.knots_t[k], pt[k]) for k in range(d)]
         grids = np.meshgrid(*g1, indexing="ij")
         self.xhat = np.stack([g.reshape(-1, order="F") for g in grids], axis=1)
-        self.X, det = geometry.map_points(desc["map"], self.xhat)
+        sgrids = np.meshgrid(*s1, indexing="ij")
+        self.xhat_side = np.stack([g.reshape(-1, order="F") for g in sgrids], axis=1)
+        self.X, det = geometry.map_points(desc["map"], self.xhat, self.xhat_side)
         if np.any(det <= 0):
             raise ValueError("det DF <= 0 at a Greville point")
         self.J = np.sqrt(det)

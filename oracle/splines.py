@@ -18,6 +18,13 @@ Readings where the paper is silent:
   * For M_k the union of both breakpoint sets is used with ceil((p + pt + 1) / 2)
     Gauss points per span, which is exact for the degree p + pt integrand.
   * At x = 1 the basis is taken as the left limit (the last function equals 1).
+  * Sec. 6 uses interpolation spaces that are discontinuous (C^-1) across a C^0 line of
+    the geometry: an interior knot repeated p + 1 times.  The space then splits into the
+    functions left and right of the knot, and the last function on the left and the
+    first on the right have the same Greville abscissa (the knot).  Each such point is
+    evaluated as a limit from the side of its own function: from the left when the
+    abscissa is the right end of its function's support (which also covers x = 1), from
+    the right otherwise.  With that the collocation matrix stays invertible.
 """
 
 import math
@@ -41,7 +48,8 @@ def knots_with_multiplicity(p, breakpoints, mult):
     """Open knot vector with given interior breakpoints repeated `mult` times each.
 
     mult = p gives C^0 continuity at every breakpoint (reduced-continuity
-    interpolation spaces discussed in Sec. 4.2 remark on smoothness).
+    interpolation spaces discussed in Sec. 4.2 remark on smoothness); mult = p + 1 a
+    discontinuous (C^-1) space.
     """
     interior = []
     for b in breakpoints:
@@ -62,16 +70,19 @@ def _span_of_right_end(knots):
     raise ValueError("degenerate knot vector")
 
 
-def basis_matrix(knots, p, x):
+def basis_matrix(knots, p, x, side=None):
     """All B-splines B_{i,p}(x_r) by the Cox-de Boor recursion from its definition.
 
     B_{i,0}(x) = 1 on [xi_i, xi_{i+1}) and 0 otherwise;
     B_{i,q}(x) = (x - xi_i)/(xi_{i+q} - xi_i) B_{i,q-1}(x)
                + (xi_{i+q+1} - x)/(xi_{i+q+1} - xi_{i+1}) B_{i+1,q-1}(x),  0/0 := 0.
+    side[r] = -1 takes the limit from the left at x_r instead: B_{i,0} = 1 on
+    (xi_i, xi_{i+1}]; None or +1 the definition above (with the left limit at x = 1).
     Returns an array of shape (len(x), n).
     """
     knots = np.asarray(knots, dtype=np.float64)
     x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    sides = np.ones(len(x)) if side is None else np.broadcast_to(np.asarray(side), (len(x),))
     m = len(knots) - 1
     n = m - p
     last = _span_of_right_end(knots)
@@ -80,9 +91,12 @@ def basis_matrix(knots, p, x):
         # degree-0 functions, one per knot span
         b = np.zeros(m)
         for i in range(m):
-            if knots[i] <= xv < knots[i + 1]:
+            if sides[r] < 0:
+                if knots[i] < xv <= knots[i + 1]:
+                    b[i] = 1.0
+            elif knots[i] <= xv < knots[i + 1]:
                 b[i] = 1.0
-        if xv == knots[-1]:
+        if sides[r] >= 0 and xv == knots[-1]:
             b[last] = 1.0
         for q in range(1, p + 1):
             nb = np.zeros(m - q)
@@ -101,17 +115,30 @@ def basis_matrix(knots, p, x):
 
 
 def greville(knots, p):
-    """Greville abscissae xhat_i = mean(xi_{i+1}, ..., xi_{i+p})  (Sec. 4.2, cited)."""
+    """Greville abscissae xhat_i = mean(xi_{i+1}, ..., xi_{i+p})  (Sec. 4.2, cited); the
+    knot itself where those p knots coincide (so that the two abscissae at a C^-1 knot are
+    equal)."""
     knots = np.asarray(knots, dtype=np.float64)
     n = dimension(knots, p)
     if p == 0:
         return 0.5 * (knots[:-1] + knots[1:])[:n]
-    return np.array([knots[i + 1:i + p + 1].sum() / p for i in range(n)])
+    return np.array([knots[i + 1] if knots[i + 1] == knots[i + p] else knots[i + 1:i + p + 1].sum() / p
+                     for i in range(n)])
+
+
+def greville_sides(knots, p):
+    """-1 where the abscissa of B_i is the right end of its support [xi_i, xi_{i+p+1}] (the
+    knots xi_{i+1} .. xi_{i+p+1} coincide: the left function at a C^-1 knot, and the last
+    function at x = 1), else +1: the side from which the basis is evaluated there."""
+    knots = np.asarray(knots, dtype=np.float64)
+    n = dimension(knots, p)
+    return np.array([-1.0 if p > 0 and knots[i + 1] == knots[i + p + 1] else 1.0 for i in range(n)])
 
 
 def collocation_matrix(knots, p):
-    """Bt_k[i, j] = Bt_j(xhat_i) at the Greville abscissae (eq. interpolation_matrix)."""
-    return basis_matrix(knots, p, greville(knots, p))
+    """Bt_k[i, j] = Bt_j(xhat_i) at the Greville abscissae (eq. interpolation_matrix), each
+    abscissa evaluated from its own side (greville_sides)."""
+    return basis_matrix(knots, p, greville(knots, p), greville_sides(knots, p))
 
 
 def gauss_legendre(q):
