@@ -76,9 +76,15 @@ typedef enum { KL_MAP_IDENTITY = 0, KL_MAP_BOX = 1, KL_MAP_ANNULUS_NURBS = 2,
                KL_MAP_ANNULUS_POLAR = 3, KL_MAP_SINE_CUBE = 4, KL_MAP_TENSOR_NURBS = 5 } kl_map_kind;
 
 /* Knot vectors (Sec. 2.3), when given explicitly: nondecreasing, open (the first and the
- * last value repeated p + 1 times), from 0 to 1, every interior value repeated at most p
- * times (continuity C^0 or smoother), at least 2 p + 2 entries; the space has nknots - p - 1
- * functions.  Host arrays, read during kl_setup only. */
+ * last value repeated p + 1 times), from 0 to 1, at least 2 p + 2 entries; the space has
+ * nknots - p - 1 functions.  Trial and interpolation knot vectors may repeat an interior
+ * value up to p + 1 times: a discontinuous (C^-1) space, as Sec. 6 uses for the
+ * interpolation space across a C^0 line of the geometry, and, in the trial space, the
+ * non-conforming coupling of two patches (Sec. 3.6).  The last function left of such a
+ * knot and the first one right of it have the same Greville abscissa (the knot); each of
+ * these points is evaluated as the limit from the side of its own function, the basis
+ * functions and det DF alike.  Map knot vectors repeat interior values at most p times
+ * (the map is continuous).  Host arrays, read during kl_setup only. */
 typedef struct {
     int32_t dim;                 /* spatial dimension d, 1..3 */
     int32_t degree[3];           /* trial-space degree p_k >= 1 */
@@ -91,12 +97,11 @@ typedef struct {
     int32_t interp_degree[3];    /* interpolation space (Sec. 4.2); 0 = same as trial */
     int32_t interp_nelem[3];     /* 0 = same as trial */
     int32_t interp_mult[3];      /* multiplicity m of every interior breakpoint of the
-                                    interpolation knot vector, 1 <= m <= interp degree pt:
-                                    continuity C^{pt-m}, nt_k = pt + 1 + (net_k - 1) m;
+                                    interpolation knot vector, 1 <= m <= interp degree pt
+                                    + 1: continuity C^{pt-m}, nt_k = pt + 1 + (net_k - 1) m;
                                     m = pt gives the C^0 interpolation spaces that Sec. 4.2
-                                    and Sec. 6 prefer for the exponential kernel.  0 = 1
-                                    (C^{pt-1}).  m > pt (a discontinuous space, whose
-                                    Greville points coincide) is KL_EINVAL. */
+                                    and Sec. 6 prefer for the exponential kernel, m = pt + 1
+                                    a discontinuous one.  0 = 1 (C^{pt-1}). */
     const double *interp_knots[3];   /* optional explicit interpolation knot vector
                                     (NULL = from interp_nelem / interp_mult; with explicit
                                     trial knots and interp_degree, interp_nelem and

@@ -44,6 +44,15 @@ int find_span(const std::vector<double> &t, int p, int n, double x) {
     return lo;
 }
 
+// The span for the limit from one side: side >= 0 as find_span; side < 0 the span with
+// t[s] < x <= t[s+1] (the non-empty span that ends at x when x is a knot).
+int find_span_side(const std::vector<double> &t, int p, int n, double x, int side) {
+    int s = find_span(t, p, n, x);
+    if (side < 0)
+        while (s > p && t[s] == x) --s;
+    return s;
+}
+
 // The p+1 non-zero B-splines B_{s-p..s}(x) via the triangular recurrence.
 void nonzero_basis(const std::vector<double> &t, int p, int s, double x, double *out) {
     double left[32], right[32];
@@ -84,7 +93,8 @@ void nonzero_basis_ders(const std::vector<double> &t, int p, int s, double x, do
 }
 
 // An explicit knot vector: finite, nondecreasing, open (first and last value repeated
-// p + 1 times), from 0 to 1, interior values repeated at most max_mult times.
+// p + 1 times), from 0 to 1, interior values repeated at most max_mult times (p + 1 for
+// the spline spaces: C^-1; p for maps: C^0).
 bool valid_knots(const double *t, int len, int p, int max_mult, std::string &why) {
     if (!t || len < p + 2 + p) { why = "needs at least 2 p + 2 entries"; return false; }
     for (int i = 0; i < len; ++i)
@@ -96,18 +106,36 @@ bool valid_knots(const double *t, int len, int p, int max_mult, std::string &why
     for (int i = p + 1; i < len - p - 1;) {
         int j = i;
         while (j < len - p - 1 && t[j] == t[i]) ++j;
-        if (j - i > max_mult) { why = "interior values may repeat at most p times (C^0)"; return false; }
+        if (j - i > max_mult) {
+            why = max_mult > p ? "interior values may repeat at most p + 1 times (C^-1)"
+                               : "interior values may repeat at most p times (C^0)";
+            return false;
+        }
         i = j;
     }
     return true;
 }
 
-std::vector<double> greville(const std::vector<double> &t, int p, int n) {
+// Greville abscissae (knot averages); the knot itself where the p knots coincide, so that
+// the two abscissae at a knot repeated p + 1 times are equal.  side[i] = -1 where the
+// abscissa is the right end of the support [t_i, t_{i+p+1}] of function i (the knots
+// t_{i+1} .. t_{i+p+1} coincide: the left function at a C^-1 knot, and the last function at
+// x = 1): there the basis is evaluated as the limit from the left; +1 elsewhere.
+std::vector<double> greville(const std::vector<double> &t, int p, int n, std::vector<int> *side = nullptr) {
     std::vector<double> g(n);
     for (int i = 0; i < n; ++i) {
-        double s = 0.0;
-        for (int j = 1; j <= p; ++j) s += t[i + j];
-        g[i] = s / p;
+        if (t[i + 1] == t[i + p]) {
+            g[i] = t[i + 1];
+        } else {
+            double s = 0.0;
+            for (int j = 1; j <= p; ++j) s += t[i + j];
+            g[i] = s / p;
+        }
+    }
+    if (side) {
+        side->assign(n, 1);
+        for (int i = 0; i < n; ++i)
+            if (t[i + 1] == t[i + p + 1]) (*side)[i] = -1;
     }
     return g;
 }
@@ -227,7 +255,7 @@ struct Dir {
 // the interpolation Greville abscissae g applied to standard-form coefficients (Sec. 3.4,
 // 4.1), which evaluates eigenfunctions there.
 kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &E, std::vector<double> &LT,
-                          std::vector<double> &g) {
+                          std::vector<double> &g, std::vector<int> &gside) {
     const int n = D.n, nt = D.nt;
     // Z_k by Gauss-Legendre with p+1 points per element
     std::vector<double> xs, ws;
@@ -268,11 +296,12 @@ kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &E
             for (int b = 0; b <= D.p; ++b)
                 M[size_t(st - D.pt + a) * n + (s - D.p + b)] += ws[q] * Bt[a] * B[b];
     }
-    // collocation matrix at the Greville abscissae of the interpolation space
-    g = greville(D.tt, D.pt, nt);
+    // collocation matrix at the Greville abscissae of the interpolation space, each
+    // abscissa evaluated from the side of its own function
+    g = greville(D.tt, D.pt, nt, &gside);
     std::vector<double> Bc(size_t(nt) * nt, 0.0);
     for (int i = 0; i < nt; ++i) {
-        int st = find_span(D.tt, D.pt, nt, g[i]);
+        int st = find_span_side(D.tt, D.pt, nt, g[i], gside[i]);
         nonzero_basis(D.tt, D.pt, st, g[i], Bt);
         for (int a = 0; a <= D.pt; ++a) Bc[size_t(i) * nt + (st - D.pt + a)] = Bt[a];
     }
@@ -294,7 +323,7 @@ kl_status build_direction(Dir &D, std::vector<double> &C, std::vector<double> &E
     // E = B(g) L^{-T}: row r solves L e^T = b(g_r)^T (forward substitution)
     E.assign(size_t(nt) * n, 0.0);
     for (int r = 0; r < nt; ++r) {
-        const int s0 = find_span(D.t, D.p, n, g[r]);
+        const int s0 = find_span_side(D.t, D.p, n, g[r], gside[r]);
         nonzero_basis(D.t, D.p, s0, g[r], B);
         double *e = &E[size_t(r) * n];
         for (int a = 0; a <= D.p; ++a) e[s0 - D.p + a] = B[a];
@@ -337,8 +366,9 @@ void arc(double v, double &cx, double &cy, double &dx, double &dy) {
     dy = (dPy * W - Py * dW) / (W * W);
 }
 
-// F(u) and det DF(u) for one parametric point.
-bool map_point(const kl_desc &desc, int d, const double *u, double *x, double &det) {
+// F(u) and det DF(u) for one parametric point; side[k] < 0 takes the derivative along u_k
+// from the left (it differs from the right one only on a C^0 line of a NURBS map).
+bool map_point(const kl_desc &desc, int d, const double *u, const int *side, double *x, double &det) {
     const double *mp = desc.map_params;
     switch (desc.map_kind) {
     case KL_MAP_IDENTITY:
@@ -400,7 +430,7 @@ bool map_point(const kl_desc &desc, int d, const double *u, double *x, double &d
             const int pk = desc.map_degree[k];
             m[k] = desc.map_nknots[k] - pk - 1;
             const std::vector<double> t(desc.map_knots[k], desc.map_knots[k] + desc.map_nknots[k]);
-            span[k] = find_span(t, pk, m[k], u[k]);
+            span[k] = find_span_side(t, pk, m[k], u[k], side[k]);
             nonzero_basis_ders(t, pk, span[k], u[k], val[k], der[k]);
         }
         double A[3] = {0, 0, 0}, dA[3][3] = {{0}}, W = 0.0, dW[3] = {0, 0, 0};
@@ -508,7 +538,7 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
         if (r.p < 1 || r.p > 20 || r.pt < 1 || r.pt > 20) { set_error("degrees must be in 1..20"); return KL_EINVAL; }
         std::string why;
         if (desc.knots[k]) {
-            if (!valid_knots(desc.knots[k], desc.nknots[k], r.p, r.p, why)) {
+            if (!valid_knots(desc.knots[k], desc.nknots[k], r.p, r.p + 1, why)) {
                 set_error("trial knot vector " + std::to_string(k) + ": " + why);
                 return KL_EINVAL;
             }
@@ -518,7 +548,7 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
             r.t = uniform_knots(r.p, desc.nelem[k]);
         }
         if (desc.interp_knots[k]) {
-            if (!valid_knots(desc.interp_knots[k], desc.interp_nknots[k], r.pt, r.pt, why)) {
+            if (!valid_knots(desc.interp_knots[k], desc.interp_nknots[k], r.pt, r.pt + 1, why)) {
                 set_error("interpolation knot vector " + std::to_string(k) + ": " + why);
                 return KL_EINVAL;
             }
@@ -530,9 +560,8 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
                             : desc.knots[k] ? int(breakpoints(r.t).size()) - 1 : desc.nelem[k];
             const int mult = desc.interp_mult[k] > 0 ? desc.interp_mult[k] : 1;
             if (net < 1 || net > 100000) { set_error("element counts must be >= 1"); return KL_EINVAL; }
-            if (desc.interp_mult[k] < 0 || mult > r.pt) {
-                set_error("interp_mult must be in 1..interp degree (0 = 1); discontinuous "
-                          "interpolation spaces are not supported");
+            if (desc.interp_mult[k] < 0 || mult > r.pt + 1) {
+                set_error("interp_mult must be in 1..interp degree + 1 (0 = 1)");
                 return KL_EINVAL;
             }
             r.tt = uniform_knots(r.pt, net, mult);
@@ -550,8 +579,9 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
     hs.N = N;
     hs.Nt = Nt;
     std::vector<double> g[3];
+    std::vector<int> gside[3];
     for (int k = 0; k < d; ++k) {
-        kl_status st = build_direction(D[k], hs.C[k], hs.E[k], hs.LT[k], g[k]);
+        kl_status st = build_direction(D[k], hs.C[k], hs.E[k], hs.LT[k], g[k], gside[k]);
         if (st != KL_OK) return st;
     }
     hs.X.assign(size_t(Nt) * d, 0.0);
@@ -559,11 +589,13 @@ kl_status build_host_setup(const kl_desc &desc, HostSetup &hs) {
     for (int64_t p = 0; p < Nt; ++p) {
         int64_t r = p;
         double u[3], x[3], det;
+        int side[3] = {1, 1, 1};
         for (int k = 0; k < d; ++k) {
             u[k] = g[k][r % hs.nt[k]];
+            side[k] = gside[k][r % hs.nt[k]];
             r /= hs.nt[k];
         }
-        map_point(desc, d, u, x, det);
+        map_point(desc, d, u, side, x, det);
         if (!(det > 0.0) || !std::isfinite(det)) {
             std::ostringstream os;
             os << "det DF = " << det << " <= 0 at Greville point " << p;

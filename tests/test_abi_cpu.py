@@ -54,6 +54,24 @@ NONUNIFORM = {"dim": 2, "degree": [2, 3],
 CYLINDER = {"dim": 3, "degree": [1, 2, 2], "nelem": [3, 6, 5], "map": insert_knot(quarter_cylinder_shell(), 1, 0.5),
             "cov": {"kind": "exp", "corr_len": [0.5, 0.5, 0.5]}}
 
+def kinked_square(a=0.3, tau=0.5):
+    """The unit square through a map with a C^0 line (a kink) along u_1 = tau."""
+    ctrl = np.zeros((3, 2, 2))
+    for i, x in enumerate((0.0, a, 1.0)):
+        for j, y in enumerate((0.0, 1.0)):
+            ctrl[i, j] = (x, y)
+    return {"kind": "tensor_nurbs", "degree": [1, 1], "knots": [[0, 0, tau, 1, 1], [0, 0, 1, 1]], "ctrl": ctrl}
+
+
+# two patches along u_1 that meet at the kink: trial space C^-1 there (non-conforming),
+# interpolation space C^-1 there and C^0 elsewhere, a C^1 cubic trial space along u_2
+KINKED_2D = {"dim": 2, "degree": [2, 3], "nelem": [0, 5],
+             "knots": [[0, 0, 0, 0.25, 0.5, 0.5, 0.5, 0.75, 1, 1, 1], None],
+             "interp_degree": [2, 3], "interp_nelem": [0, 6],
+             "interp_knots": [[0, 0, 0, 0.125, 0.125, 0.25, 0.25, 0.375, 0.375, 0.5, 0.5, 0.5,
+                               0.625, 0.625, 0.75, 0.75, 0.875, 0.875, 1, 1, 1], None],
+             "map": kinked_square(), "cov": {"kind": "exp", "corr_len": [0.4, 0.6]}}
+
 CASES = [
     workloads.unit_square(16, 2, "exp", 1.0),
     NONUNIFORM,
@@ -72,6 +90,11 @@ CASES = [
      "cov": {"kind": "exp", "corr_len": [0.5, 0.5]}},
     {"dim": 3, "degree": [2, 2, 1], "nelem": [4, 3, 5], "interp_degree": [3, 2, 1], "interp_nelem": [4, 3, 5],
      "interp_mult": [2, 0, 1], "map": {"kind": "sine_cube", "eps": 0.05, "amp": [1.0, 0.5, 0.3]},
+     "cov": {"kind": "exp", "corr_len": [0.6, 0.6, 0.6]}},
+    # discontinuous spaces: coincident Greville points evaluated from their own sides
+    KINKED_2D,
+    {"dim": 3, "degree": [2, 2, 2], "nelem": [3, 4, 3], "interp_degree": [2, 3, 2], "interp_nelem": [4, 3, 3],
+     "interp_mult": [3, 4, 1], "map": {"kind": "sine_cube", "eps": 0.05, "amp": [1.0, 0.5, 0.3]},
      "cov": {"kind": "exp", "corr_len": [0.6, 0.6, 0.6]}},
 ]
 
@@ -113,10 +136,12 @@ def test_error_codes():
     assert _status_of(bad_ell) == -1
     bad_s2 = dict(good, cov={"kind": "exp", "sigma2": -1.0, "corr_len": [1.0, 1.0]})
     assert _status_of(bad_s2) == -1
-    # interpolation breakpoint multiplicity beyond the degree (discontinuous) or negative
-    assert _status_of(dict(good, interp_degree=[2, 2], interp_mult=[3, 1])) == -1
+    # interpolation breakpoint multiplicity beyond degree + 1, or negative; degree + 1 (C^-1)
+    # is a valid discontinuous space
+    assert _status_of(dict(good, interp_degree=[2, 2], interp_mult=[4, 1])) == -1
     assert _status_of(dict(good, interp_mult=[-1, 1])) == -1
     assert _status_of(dict(good, interp_mult=[2, 2])) == 0
+    assert _status_of(dict(good, interp_degree=[2, 2], interp_mult=[3, 1])) == 0
     annulus_3d = {"dim": 3, "degree": [2] * 3, "nelem": [2] * 3, "map": {"kind": "annulus_nurbs"},
                   "cov": {"kind": "exp", "corr_len": [1.0] * 3}}
     assert _status_of(annulus_3d) == -1
@@ -167,12 +192,15 @@ def test_knot_and_nurbs_errors():
     for bad in ([0, 0, 0.5, 1, 1, 1],            # not open at 0
                 [0, 0, 0, 0.5, 1, 1],            # not open at 1
                 [0, 0, 0, 0.6, 0.5, 1, 1, 1],    # decreasing
-                [0, 0, 0, 0.5, 0.5, 0.5, 1, 1, 1],   # interior multiplicity p + 1
+                [0, 0, 0, 0.5, 0.5, 0.5, 0.5, 1, 1, 1],   # interior multiplicity p + 2
                 [0, 0, 0, 0.5, 1, 1, 1.5, 1.5, 1.5],  # beyond 1
                 [0, 0, 0, float("nan"), 1, 1, 1],
                 [0, 0, 1, 1]):                   # too short for p = 2
         assert _status_of(dict(good, knots=[bad, None])) == -1, bad
-    assert _status_of(dict(good, interp_knots=[[0, 0, 0, 0.5, 0.5, 0.5, 1, 1, 1], None])) == -1
+    assert _status_of(dict(good, interp_knots=[[0, 0, 0, 0.5, 0.5, 0.5, 0.5, 1, 1, 1], None])) == -1
+    # multiplicity p + 1 (C^-1) is valid in the trial and interpolation spaces
+    assert _status_of(dict(good, knots=[[0, 0, 0, 0.5, 0.5, 0.5, 1, 1, 1], None])) == 0
+    assert _status_of(dict(good, interp_knots=[[0, 0, 0, 0.5, 0.5, 0.5, 1, 1, 1], None])) == 0
     g = quarter_annulus()
     ann = {"dim": 2, "degree": [2, 2], "nelem": [3, 3], "map": g, "cov": {"kind": "exp", "corr_len": [1.0, 1.0]}}
     assert _status_of(ann) == 0
@@ -180,6 +208,12 @@ def test_knot_and_nurbs_errors():
     assert _status_of(dict(ann, map=dict(g, weights=w))) == -1
     assert _status_of(dict(ann, map=dict(g, knots=[[0, 0, 1], g["knots"][1]]))) == -1
     assert _status_of(dict(ann, map=dict(g, degree=[0, 2]))) == -1
+    # a map must be continuous: its interior knots repeat at most p times
+    k = kinked_square()
+    sq = {"dim": 2, "degree": [2, 2], "nelem": [3, 3], "map": k, "cov": {"kind": "exp", "corr_len": [1.0, 1.0]}}
+    assert _status_of(sq) == 0
+    assert _status_of(dict(sq, map=dict(k, knots=[[0, 0, 0.5, 0.5, 1, 1], [0, 0, 1, 1]],
+                                        ctrl=np.concatenate([k["ctrl"][:2], k["ctrl"][1:]])))) == -1
     # a control net folded over itself: det DF changes sign -> KL_EDOMAIN
     c = np.array(g["ctrl"]); c[0], c[1] = g["ctrl"][1], g["ctrl"][0]
     assert _status_of(dict(ann, map=dict(g, ctrl=c))) == -4

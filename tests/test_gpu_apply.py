@@ -84,6 +84,10 @@ SMALL = [
              "cov": {"kind": "lin", "sigma2": 1.0, "corr_len": [1.0] * 3}}),
     ("nonuniform_knots", test_abi_cpu.NONUNIFORM),
     ("nurbs_cylinder_shell", test_abi_cpu.CYLINDER),
+    # discontinuous spaces: two patches meeting at a kink of the map, and C^-1 interpolation
+    # spaces in 3D (coincident Greville points, coincident kernel arguments)
+    ("kinked_two_patch", test_abi_cpu.KINKED_2D),
+    ("cube_interp_cminus1", test_abi_cpu.CASES[-1]),
 ]
 
 
@@ -133,7 +137,7 @@ def test_block_widths_and_strides(nvec):
 
 
 def test_full_size_annulus64_apply():
-    """The 64x64 cubic quarter annulus, sqexp L = 0.5) at full size, 32 vectors."""
+    """The 64x64 cubic quarter annulus (sqexp L = 0.5) at full size, 32 vectors."""
     desc = workloads.config("annulus64")[0]
     P = operator.Problem(desc)
     G = kl.Problem(desc)
@@ -145,7 +149,7 @@ def test_full_size_annulus64_apply():
 
 
 def test_full_size_annulus48_apply():
-    """The 48x48 cubic quarter annulus, sqexp L = 0.5, the warm-start workload) at
+    """The 48x48 cubic quarter annulus (sqexp L = 0.5, the warm-start workload) at
     full size, 32 vectors, every precision."""
     desc = workloads.config("annulus48")[0]
     P = operator.Problem(desc)
@@ -184,7 +188,7 @@ def test_extreme_correlation_lengths(name, desc):
 
 
 def test_full_size_cube24_apply():
-    """The 24^3 perturbed cube, exp L = 0.5) at full size: the whole apply (fused
+    """The 24^3 perturbed cube (exp L = 0.5) at full size: the whole apply (fused
     first two directions, third direction, stage 5, backward) on the 32 columns the
     eigensolver applies at a time, and on a ragged 35-column call, against the oracle's
     Algorithm 1 with its C stage 5."""
@@ -201,7 +205,7 @@ def test_full_size_cube24_apply():
 
 
 def test_full_size_cube24_stage5_sampled_rows():
-    """The 24^3 perturbed cube, exp L = 0.5): stage 5 on 32 vectors, sampled rows
+    """The 24^3 perturbed cube (exp L = 0.5): stage 5 on 32 vectors, sampled rows
     recomputed one by one by the oracle's kernel definition."""
     from oracle import covariance
     desc = workloads.config("cube24")[0]

@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import paper_2011_13861_amd as kl
+import test_abi_cpu
 import workloads
 from oracle import cstage5
 from oracle import eigs as oeigs
@@ -101,7 +102,7 @@ def _arpack(name, desc, kref):
 
 @pytest.mark.parametrize("precision", FORMS)
 def test_annulus64_matches_arpack_oracle(precision):
-    """The 64x64 cubic quarter annulus, sqexp L = 0.5, k = 40) in every form: FP64,
+    """The 64x64 cubic quarter annulus (sqexp L = 0.5, k = 40) in every form: FP64,
     and FP32 / BF16x3 / BF16 stage 5 with the FP64 refinement phase (Sec. 4.4.2 eigenproblem,
     solved to 1e-10 under the FP64 operator)."""
     desc, k, _ = workloads.config("annulus64")
@@ -137,7 +138,7 @@ def cube24_golden():
 
 @pytest.mark.parametrize("precision", FORMS)
 def test_cube24_matches_oracle_eigenpairs(cube24_golden, precision):
-    """The 24^3 perturbed cube, exp L = 0.5, k = 50, block 32) in every form against
+    """The 24^3 perturbed cube (exp L = 0.5, k = 50, block 32) in every form against
     the oracle's ARPACK eigenpairs (tests/golden/cube24_eigs.npz, written by
     tests/golden/make_cube24_eigs.py from the oracle alone)."""
     w_ref, V_ref = cube24_golden
@@ -210,7 +211,7 @@ def test_eigs_errors():
 
 
 def test_cube24_residuals_under_fp64_apply():
-    """The 3-D 24^3 cube ( quadratic, k = 50) at the metric's tolerance: every form meets
+    """The 24^3 quadratic perturbed cube (k = 50) at the metric's tolerance: every form meets
     the criterion at 1e-6 under the FP64 apply (itself checked against the oracle
     elsewhere), the basis is orthonormal, and the forms agree on the eigenvalues."""
     desc, k, b = workloads.config("cube24")
@@ -269,3 +270,17 @@ def test_solve_is_ordered_after_the_callers_stream():
     assert rep["status"] == "KL_OK"
     assert sum(rep["n_block_applies"]) <= 3
     assert np.all(np.abs(w - w_ref[:k]) <= 1e-10 * w_ref[0])
+
+
+@pytest.mark.parametrize("precision", ["f64", "bf16x3"])
+def test_linear_kernel_spectrum_through_a_kinked_two_patch_map(precision):
+    """1 + x . x' on the unit square through a map with a kink along u_1 = 1/2, the trial
+    space discontinuous there (two non-conforming patches) and the interpolation space too:
+    the interpolation-based operator is exact for this kernel only when the coincident
+    Greville points and det DF are taken from their own sides, and the solve returns the
+    closed-form eigenvalues (19 +- sqrt 313) / 24 and 1 / 12 (rank three)."""
+    desc = dict(test_abi_cpu.KINKED_2D, cov={"kind": "lin", "sigma2": 1.0, "corr_len": [1.0, 1.0]})
+    G, w, V, rep = _solve(desc, 3, precision)
+    assert rep["status"] == "KL_OK" and rep["converged"] == 3, rep
+    ref = np.array([(19 + np.sqrt(313)) / 24, 1 / 12, (19 - np.sqrt(313)) / 24])
+    assert np.max(np.abs(w - ref) / ref) < 1e-10, w - ref

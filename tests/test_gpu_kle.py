@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import paper_2011_13861_amd as kl
+import test_abi_cpu
 import workloads
 from oracle import eigs as oeigs
 from oracle import kle, operator
@@ -26,6 +27,9 @@ CASES = [
                    "cov": {"kind": "exp", "sigma2": 1.3, "corr_len": [0.5, 0.5]}}),
     ("line", {"dim": 1, "degree": [2], "nelem": [60], "map": {"kind": "box", "lo": [0.0], "hi": [3.0]},
               "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.4]}}),
+    # two patches meeting at a kink: the trial functions and 1 / sqrt(det DF) at the
+    # coincident Greville points are taken from their own sides
+    ("kinked_two_patch", test_abi_cpu.KINKED_2D),
 ]
 
 _REF = {}
