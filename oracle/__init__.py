@@ -20,6 +20,9 @@ covariance  covariance kernels Gamma(x, x') (Sec. 3.1, eq. (kernel), Fig. kernel
 kron        mode-k tensor contraction (Sec. 2.2)
 operator    Algorithm 1 (matrix-free apply), literal stages 1-9, and the dense
             standard-form operator assembled column by column (Sec. 4.4)
+multipatch  several patches with their own spaces and maps, coupled by stage 5 only
+            (Sec. 3.6, non-conforming multipatch domains)
+kle         truncated KL expansion at the Greville points (Sec. 3.2)
 eigs        eigenpairs of the standard-form problem (Sec. 4.1, Sec. 4.4.2)
 analytic    closed-form eigenpairs of the 1D exponential kernel (Sec. 6.1 remark)
 galerkin    brute-force full Galerkin matrix A (eq. (GalA_mat)) on tiny meshes
