@@ -137,8 +137,33 @@ kl_status kl_setup(const kl_desc *desc, void *stream, kl_problem **out);
  * and kl_eigs reject it with KL_EINVAL.  Same errors as kl_setup otherwise. */
 kl_status kl_setup_host(const kl_desc *desc, kl_problem **out);
 
-/* Sizes: N = prod n_k trial dofs, Ntilde = prod nt_k interpolation dofs; n and nt
- * (host arrays of 3) receive the per-direction sizes (1 beyond dim).  Any pointer may
+/* A domain made of several patches (Sec. 3.6, non-conforming multipatch): every patch
+ * has its own description (trial and interpolation spaces, map); they must share dim and
+ * the covariance (kind, sigma2, corr_len), else KL_EINVAL.  The trial space is the direct
+ * sum of the patch spaces (C^-1 between patches); the patches are coupled by the
+ * covariance alone: stage 5 runs over the Greville points of all patches, the Kronecker
+ * stages patch by patch.  Vectors hold patch 0's N_0 standard-form coefficients (in vec
+ * order), then patch 1's, and so on; points and J likewise (kl_patch_info gives the
+ * offsets).  The handle works with every single-problem entry point (kl_apply,
+ * kl_apply_noalloc, kl_stage5, kl_eigs with coeffs, kl_kle_field, kl_set_cov, the
+ * configuration and profiling calls) except kl_get_factor (KL_EINVAL: one factor per
+ * patch).  patches: host array of npatch descriptions, read during the call.  Same
+ * stream semantics and errors as kl_setup; a patch's own error is reported with its
+ * index. */
+kl_status kl_setup_patches(int32_t npatch, const kl_desc *patches, void *stream, kl_problem **out);
+
+/* Number of patches of a problem (1 for kl_setup), 0 for NULL. */
+int32_t kl_patch_count(const kl_problem *P);
+
+/* Patch i: its trial dofs N_i and interpolation points Ntilde_i, and the offsets of its
+ * dofs and points in the problem's vectors.  Any output pointer may be NULL.  KL_EINVAL
+ * for a NULL handle or i outside 0 .. kl_patch_count - 1. */
+kl_status kl_patch_info(const kl_problem *P, int32_t i, int64_t *N, int64_t *Ntilde, int64_t *dof_offset,
+                        int64_t *point_offset);
+
+/* Sizes: N = prod n_k trial dofs, Ntilde = prod nt_k interpolation dofs (the sums over
+ * the patches for kl_setup_patches); n and nt (host arrays of 3) receive the
+ * per-direction sizes (patch 0's for several patches; 1 beyond dim).  Any pointer may
  * be NULL. */
 kl_status kl_info(const kl_problem *P, int64_t *N, int64_t *Ntilde, int32_t *n, int32_t *nt);
 

@@ -25,7 +25,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_apply_noalloc", "kl_stage5", "kl_get_points",
            "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_profile_enable", "kl_profile_read",
-           "kl_stage5_config", "kl_apply_config", "kl_set_cov",
+           "kl_stage5_config", "kl_apply_config", "kl_set_cov", "kl_setup_patches", "kl_patch_count", "kl_patch_info",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
            "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_destroy",
            "kl_setup_batch", "kl_batch_info", "kl_apply_batch", "kl_batch_config", "kl_eigs_batch",
@@ -112,6 +112,9 @@ def lib():
         L.kl_mlp_train.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P, P]
         L.kl_mlp_destroy.argtypes = [P]
+        L.kl_setup_patches.argtypes = [ctypes.c_int32, ctypes.POINTER(KLDesc), P, ctypes.POINTER(P)]
+        L.kl_patch_count.argtypes = [P]
+        L.kl_patch_info.argtypes = [P, ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int64)] * 4
         L.kl_setup_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(KLDesc), ctypes.POINTER(P)]
         L.kl_batch_info.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -228,15 +231,24 @@ def _stream(stream):
 
 
 class Problem:
-    """Owns one kl_problem handle (kl_setup / kl_destroy)."""
+    """Owns one kl_problem handle (kl_setup / kl_destroy).  `desc` is one description, or
+    a list of patch descriptions of one domain (kl_setup_patches)."""
 
     def __init__(self, desc, host_only=False, stream=None):
         self._h = ctypes.c_void_p()
-        c = make_desc(desc)
-        if host_only:
-            check(lib().kl_setup_host(ctypes.byref(c), ctypes.byref(self._h)))
+        if isinstance(desc, (list, tuple)):
+            if host_only:
+                raise ValueError("several patches need a GPU (no host-only form)")
+            structs = [make_desc(d) for d in desc]     # they keep the host arrays alive
+            arr = (KLDesc * len(desc))(*structs)
+            check(lib().kl_setup_patches(len(desc), arr, _stream(stream), ctypes.byref(self._h)))
+            desc = desc[0]
         else:
-            check(lib().kl_setup(ctypes.byref(c), _stream(stream), ctypes.byref(self._h)))
+            c = make_desc(desc)
+            if host_only:
+                check(lib().kl_setup_host(ctypes.byref(c), ctypes.byref(self._h)))
+            else:
+                check(lib().kl_setup(ctypes.byref(c), _stream(stream), ctypes.byref(self._h)))
         N = ctypes.c_int64()
         Nt = ctypes.c_int64()
         n = (ctypes.c_int32 * 3)()
@@ -246,6 +258,15 @@ class Problem:
         self.N, self.Nt = N.value, Nt.value
         self.n = list(n)[:self.d]
         self.nt = list(nt)[:self.d]
+
+    def patches(self):
+        """[(N_i, Ntilde_i, dof offset, point offset)] per patch (kl_patch_info)."""
+        out = []
+        for i in range(int(lib().kl_patch_count(self._h))):
+            v = [ctypes.c_int64() for _ in range(4)]
+            check(lib().kl_patch_info(self._h, i, *[ctypes.byref(x) for x in v]))
+            out.append(tuple(x.value for x in v))
+        return out
 
     def close(self):
         if self._h:

@@ -97,6 +97,11 @@ struct kl_problem {
     size_t prof_used = 0;
     int64_t prof_count[4] = {0, 0, 0, 0};
     double prof_ms[4] = {0, 0, 0, 0};
+    // Several patches (kl_setup_patches): one kl_problem per patch holds that patch's
+    // factors (no workspace); this problem holds the points, J, stage-5 buffers and the
+    // workspace of the union, and hs carries the totals.  Empty for a single patch.
+    std::vector<kl_problem *> patches;
+    std::vector<int64_t> noff, toff;      // offsets of each patch's dofs and points
 };
 
 namespace kl {
@@ -222,11 +227,21 @@ int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, 
 // kl_setup with or without the single-problem apply workspace (T0/T1, stage-5 buffers);
 // problems of a batch use the batch's arenas instead.  Uploads on `s`, then waits for it.
 kl_status setup_problem(const kl_desc *desc, bool workspace, hipStream_t s, kl_problem **out);
+// kl_setup_patches: one factor-only problem per patch and the union's buffers.
+kl_status setup_patches(int npatch, const kl_desc *descs, hipStream_t s, kl_problem **out);
 // Standard-form vectors to B-spline coefficients, v = L^{-T} v' (Sec. 4.1), in place on
 // nvec columns of x (ld >= N), using `tmp` (N x nvec, ld N) as the ping-pong buffer.
 void launch_to_coefficients(const kl_problem *P, double *x, int64_t ldx, int nvec, double *tmp, hipStream_t s);
 void destroy_problem(kl_problem *P);
 int64_t max_intermediate(const HostSetup &hs);
+// Patch i of a problem (the problem itself when it has a single patch), with the offsets
+// of its dofs and points in the problem's vectors; the largest Kronecker intermediate
+// over the patches.
+inline int patch_count(const kl_problem *P) { return P->patches.empty() ? 1 : int(P->patches.size()); }
+inline const kl_problem *patch_of(const kl_problem *P, int i) { return P->patches.empty() ? P : P->patches[i]; }
+inline int64_t patch_noff(const kl_problem *P, int i) { return P->patches.empty() ? 0 : P->noff[i]; }
+inline int64_t patch_toff(const kl_problem *P, int i) { return P->patches.empty() ? 0 : P->toff[i]; }
+int64_t problem_max_intermediate(const kl_problem *P);
 // One chunk (<= kBW columns) of the single-problem apply, on the problem's workspace or
 // on `ws` (same layout; its padding rows of the stage-5 inputs must be zero).
 kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx, double *y,

@@ -103,31 +103,36 @@ extern "C" kl_status kl_kle_field(kl_problem *P, int32_t M, const double *lam, c
     double *Phi = static_cast<double *>(P->ws.Zf);        // Ntpad x kBW, column-major
     for (int c0 = 0; c0 < M; c0 += kBW) {
         const int nb = std::min(kBW, M - c0);
-        const void *cur = evecs + int64_t(c0) * ldv;
-        int64_t cur_ld = ldv, A = 1;
-        for (int k = 0; k < d; ++k) {
-            ModeSpec ms;
-            ms.D = P->dE[k];
-            ms.DT = P->dET[k];
-            ms.in = cur;
-            ms.in_ldj = cur_ld;
-            ms.A = A;
-            ms.nin = hs.n[k];
-            ms.nout = hs.nt[k];
-            ms.Clo = 1;
-            for (int j = k + 1; j < d; ++j) ms.Clo *= hs.n[j];
-            ms.nvec = nb;
-            if (k == d - 1) {
-                ms.out = Phi;
-                ms.out_ldj = P->Ntpad;
-            } else {
-                ms.out = (cur == P->ws.T0) ? P->ws.T1 : P->ws.T0;
-                ms.out_ldj = A * hs.nt[k] * ms.Clo;
+        // the trial functions at the Greville points, patch by patch on the patch's rows
+        for (int pi = 0; pi < patch_count(P); ++pi) {
+            const kl_problem *Q = patch_of(P, pi);
+            const HostSetup &qs = Q->hs;
+            const void *cur = evecs + int64_t(c0) * ldv + patch_noff(P, pi);
+            int64_t cur_ld = ldv, A = 1;
+            for (int k = 0; k < d; ++k) {
+                ModeSpec ms;
+                ms.D = Q->dE[k];
+                ms.DT = Q->dET[k];
+                ms.in = cur;
+                ms.in_ldj = cur_ld;
+                ms.A = A;
+                ms.nin = qs.n[k];
+                ms.nout = qs.nt[k];
+                ms.Clo = 1;
+                for (int j = k + 1; j < d; ++j) ms.Clo *= qs.n[j];
+                ms.nvec = nb;
+                if (k == d - 1) {
+                    ms.out = Phi + patch_toff(P, pi);
+                    ms.out_ldj = P->Ntpad;
+                } else {
+                    ms.out = (cur == P->ws.T0) ? P->ws.T1 : P->ws.T0;
+                    ms.out_ldj = A * qs.nt[k] * ms.Clo;
+                }
+                launch_mode(ms, s);
+                A *= qs.nt[k];
+                cur = ms.out;
+                cur_ld = ms.out_ldj;
             }
-            launch_mode(ms, s);
-            A *= hs.nt[k];
-            cur = ms.out;
-            cur_ld = ms.out_ldj;
         }
         ColScale cs{};
         for (int i = 0; i < nb; ++i) cs.v[i] = std::sqrt(lam[c0 + i]);

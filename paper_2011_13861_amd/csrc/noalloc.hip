@@ -78,7 +78,7 @@ extern "C" kl_status kl_apply_noalloc(kl_problem *P, int32_t precision, int32_t 
     // in the stage-5 precision (BF16: high then low parts), the stage-5 output and as many
     // split partials as fit (at least one)
     const int64_t Np = P->Ntpad;
-    const size_t t_bytes = round256(size_t(max_intermediate(P->hs)) * kBW * sizeof(double));
+    const size_t t_bytes = round256(size_t(problem_max_intermediate(P)) * kBW * sizeof(double));
     const int y5_elem = precision == KL_F64 ? 8 : precision == KL_F32 ? 4 : 2;
     const int y5_cols = precision == KL_BF16X3 ? 2 * kBW : kBW;   // BF16x3: high then low parts
     const size_t y5_bytes = round256(size_t(Np) * y5_cols * y5_elem);

@@ -217,3 +217,27 @@ def test_knot_and_nurbs_errors():
     # a control net folded over itself: det DF changes sign -> KL_EDOMAIN
     c = np.array(g["ctrl"]); c[0], c[1] = g["ctrl"][1], g["ctrl"][0]
     assert _status_of(dict(ann, map=dict(g, ctrl=c))) == -4
+
+
+def test_patch_entry_points_without_a_gpu():
+    """kl_setup_patches checks that the patches share dim and the covariance before any
+    device work; kl_patch_count / kl_patch_info on a single-patch handle."""
+    import ctypes
+    from paper_2011_13861_amd import _binding as b
+    sq = workloads.unit_square(4, 2, "exp", 1.0)
+    cube = workloads.sine_cube(3, 2, "exp", 1.0)
+    other_cov = dict(sq, cov={"kind": "exp", "sigma2": 1.0, "corr_len": [0.5, 1.0]})
+    h = ctypes.c_void_p()
+    for descs in ([sq, cube], [sq, other_cov]):
+        structs = [b.make_desc(d) for d in descs]
+        arr = (b.KLDesc * len(descs))(*structs)
+        assert b.lib().kl_setup_patches(len(descs), arr, None, ctypes.byref(h)) == -1
+        assert "share dim and the covariance" in b.lib().kl_last_error().decode()
+    arr = (b.KLDesc * 1)(b.make_desc(sq))
+    assert b.lib().kl_setup_patches(0, arr, None, ctypes.byref(h)) == -1
+    assert b.lib().kl_patch_count(None) == 0
+    H = kl.Problem(sq, host_only=True)
+    assert H.patches() == [(H.N, H.Nt, 0, 0)]
+    n = ctypes.c_int64()
+    assert b.lib().kl_patch_info(H.handle, 1, ctypes.byref(n), None, None, None) == -1
+    H.close()
