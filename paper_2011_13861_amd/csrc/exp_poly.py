@@ -1,8 +1,8 @@
 """Coefficients of the FP64 exponentials used by the stage-5 kernels (kernels_stage5.hip):
 
-* `exp2_nonpos`: the degree-11 polynomial that interpolates 2^f at the 12 Chebyshev nodes
-  of [-1/2, 1/2], the range left by the exact reduction f = x - rint(x) of a base-2
-  exponent (the kernels' coordinates absorb log2(e));
+* `exp2_nonpos`: the degree-9 polynomial in f that interpolates 2^(f/2) at the 10 Chebyshev
+  nodes of [-1/2, 1/2] (f the range left by the exact reduction f = x - rint(x) of a base-2
+  exponent; the kernels' coordinates absorb log2(e)); the kernel squares it to get 2^f;
 * `exp_nonpos` (kept for reference): the degree-11 interpolant of e^r on [-ln2/2, ln2/2]
   after a Cody-Waite reduction, and the split of ln2 into a 32-significant-bit high part
   and the rounded remainder.
@@ -33,14 +33,16 @@ def dcos(x):
         s += t
 
 
-def coefficients(degree=11, widen=Decimal("1.000001"), base2=False):
-    """Interpolant of e^r on [-a, a], a = ln2 / 2 (base2=False), or of 2^f on [-a, a],
-    a = 1/2 (base2=True), at the Chebyshev nodes; coefficients of degree 0 first."""
+def coefficients(degree=11, widen=Decimal("1.000001"), base2=False, half=False):
+    """Interpolant of e^r on [-a, a], a = ln2 / 2 (base2=False), of 2^f on [-a, a], a = 1/2
+    (base2=True), or of 2^(f/2) there (base2=True, half=True), at the Chebyshev nodes;
+    coefficients of degree 0 first."""
     a = (Decimal(1) / 2 if base2 else LN2 / 2) * widen
     n = degree + 1
     nodes = [a * dcos((2 * Decimal(i) + 1) * PI / (2 * n)) for i in range(n)]
     A = [[Fraction(x) ** j for j in range(n)] for x in nodes]
-    b = [Fraction((x * LN2).exp() if base2 else x.exp()) for x in nodes]
+    scale = LN2 / 2 if half else LN2
+    b = [Fraction((x * scale).exp() if base2 else x.exp()) for x in nodes]
     for c in range(n):                                   # Gaussian elimination, exact
         p = max(range(c, n), key=lambda r: abs(A[r][c]))
         A[c], A[p], b[c], b[p] = A[p], A[c], b[p], b[c]
@@ -61,8 +63,8 @@ def ln2_split():
 
 
 if __name__ == "__main__":
-    cs2, a2 = coefficients(base2=True)
-    print("base-2 coefficients (degree 0 first):", [repr(c) for c in cs2])
+    cs2, a2 = coefficients(degree=9, base2=True, half=True)
+    print("base-2 half-argument coefficients (degree 0 first):", [repr(c) for c in cs2])
     worst = 0.0
     for i in range(4001):
         f = -a2 + 2 * a2 * i / 4000
@@ -70,8 +72,8 @@ if __name__ == "__main__":
         for c in reversed(cs2[:-1]):
             p = p * f + c
         ref = (Decimal(f) * LN2).exp()
-        worst = max(worst, float(abs((Decimal(p) - ref) / ref)))
-    print("largest relative error of the rounded base-2 polynomial:", worst)
+        worst = max(worst, float(abs((Decimal(p * p) - ref) / ref)))
+    print("largest relative error of the squared rounded polynomial:", worst)
     cs, a = coefficients()
     hi, lo = ln2_split()
     print("ln2_hi", hi.hex(), "ln2_lo", lo.hex())

@@ -55,42 +55,43 @@ __device__ __forceinline__ float gamma_f32(const float *xk, const float *xl) {
 // handling of the general library functions.  The coordinates of the FP64 kernels are
 // scaled on the host by log2(e) / ell (sqrt(log2 e) / ell for the squared exponential), so
 // that Gamma = 2^(-rho') with rho' the scaled distance (squared distance).
-//  * exp2: x = n + f with n = rint(x) and f = x - n in [-1/2, 1/2] (exact); 2^f by a
-//    polynomial of degree 11 (below); scaling by 2^n.
+//  * exp2: x = n + f with n = rint(x) and f = x - n in [-1/2, 1/2] (exact); 2^f as the
+//    square of 2^(f/2), which a polynomial of degree 9 in f gives (below; one FMA fewer
+//    than a degree-11 polynomial for 2^f itself, at about 1.6 ulp); scaling by 2^n.
 //  * sqrt: Goldschmidt iteration from the hardware reciprocal square root y: s = a y and
-//    h = y / 2 approximate sqrt(a) and 1 / (2 sqrt(a)); one coupled step squares their
-//    relative error (to about 2^-44), and a Newton correction s + h (a - s^2) squares it
-//    again, below the rounding of s.  The callers start the squared distance at 1e-300, so
-//    that a coincident pair gives sqrt(1e-300) = 1e-150 and 2^(-1e-150) = 1 without a
-//    special case (1e-300 is far below the rounding of any non-zero squared distance).
+//    h = y / 2 approximate sqrt(a) and 1 / (2 sqrt(a)); one step s (1 + e), e = 1/2 - s h,
+//    squares the relative error of s (to about 2^-44), and a Newton correction
+//    s + h (a - s^2) squares it again, below the rounding of s: the correction term is
+//    already of relative size 2^-44, so h needs no refinement of its own.  The callers
+//    start the squared distance at 1e-300, so that a coincident pair gives
+//    sqrt(1e-300) = 1e-150 and 2^(-1e-150) = 1 without a special case (1e-300 is far below
+//    the rounding of any non-zero squared distance).
 __device__ __forceinline__ double exp2_nonpos(double x) {
     const double n = __builtin_rint(x);
     const double f = x - n;
-    // degree-11 interpolant of 2^f at the 12 Chebyshev nodes of [-1/2, 1/2] (coefficients
-    // solved in exact rational arithmetic from 80-digit values of 2^f, then rounded;
-    // interpolation error below 1e-17, Horner evaluation below 1.7e-16 relative);
-    // exp_poly.py beside this file regenerates them
-    double p = 4.455817928917402e-10;
-    p = fma(p, f, 7.074194335901629e-09);
-    p = fma(p, f, 1.0178057087618173e-07);
-    p = fma(p, f, 1.3215432535695181e-06);
-    p = fma(p, f, 1.5252733841556997e-05);
-    p = fma(p, f, 0.00015403530463724776);
-    p = fma(p, f, 0.001333355814640647);
-    p = fma(p, f, 0.009618129107587256);
-    p = fma(p, f, 0.055504108664821625);
-    p = fma(p, f, 0.24022650695910158);
-    p = fma(p, f, 0.6931471805599453);
+    // degree-9 interpolant of 2^(f/2) at the 10 Chebyshev nodes of [-1/2, 1/2]
+    // (coefficients solved in exact rational arithmetic from 80-digit values, then
+    // rounded; interpolation error below 1e-17; squared, the Horner evaluation stays below
+    // 3.6e-16 relative); exp_poly.py beside this file regenerates them
+    double p = 1.9892645214512514e-10;
+    p = fma(p, f, 5.166607104479313e-09);
+    p = fma(p, f, 1.1916195315468524e-07);
+    p = fma(p, f, 2.4068006815705036e-06);
+    p = fma(p, f, 4.166736921023986e-05);
+    p = fma(p, f, 0.0006011330693109269);
+    p = fma(p, f, 0.006938013583102615);
+    p = fma(p, f, 0.06005662673977255);
+    p = fma(p, f, 0.34657359027997264);
     p = fma(p, f, 1.0);
-    return __builtin_ldexp(p, int(n));
+    return __builtin_ldexp(p * p, int(n));
 }
 
 __device__ __forceinline__ double sqrt_pos(double a) {
     const double y = __builtin_amdgcn_rsq(a);
-    double s = a * y, h = 0.5 * y;
+    double s = a * y;
+    const double h = 0.5 * y;
     const double e = fma(-s, h, 0.5);
     s = fma(s, e, s);
-    h = fma(h, e, h);
     const double d = fma(-s, s, a);
     return fma(d, h, s);
 }

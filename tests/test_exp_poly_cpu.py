@@ -1,7 +1,8 @@
 """The FP64 base-2 exponential of the stage-5 kernels: the constants written in
-kernels_stage5.hip are the ones exp_poly.py derives (degree-11 Chebyshev interpolant of 2^f
-on [-1/2, 1/2]), and the exact reduction + polynomial + scaling, replayed in double on the
-host, stays within a few ulp of 2^x on x <= 0."""
+kernels_stage5.hip are the ones exp_poly.py derives (degree-9 Chebyshev interpolant of
+2^(f/2) on [-1/2, 1/2], squared by the kernel), and the exact reduction + polynomial +
+squaring + scaling, replayed in double on the host, stays within a few ulp of 2^x on
+x <= 0."""
 import importlib.util
 import os
 import re
@@ -28,9 +29,11 @@ def _kernel_constants():
 
 
 def test_kernel_constants_are_the_generated_ones():
-    coef, half = _gen().coefficients(base2=True)
+    coef, half = _gen().coefficients(degree=9, base2=True, half=True)
     assert abs(half - 0.5) < 1e-5
     assert _kernel_constants() == list(reversed(coef))
+    src = open(os.path.join(CSRC, "kernels_stage5.hip")).read()
+    assert "__builtin_ldexp(p * p, int(n))" in src
 
 
 def test_host_replay_matches_exp2():
@@ -41,8 +44,8 @@ def test_host_replay_matches_exp2():
     p = np.full_like(f, kc[0])
     for c in kc[1:]:
         p = p * f + c
-    y = np.ldexp(p, n.astype(np.int64))
-    ref = np.exp2(x)
-    rel = np.abs(y - ref) / ref
-    assert rel.max() < 4e-16, rel.max()
+    y = np.ldexp(p * p, n.astype(np.int64))
+    ref = np.exp2(x.astype(np.longdouble))
+    rel = np.abs(y.astype(np.longdouble) - ref) / ref
+    assert rel.max() < 5e-16, rel.max()
     assert np.ldexp(kc[-1], 0) == 1.0                    # 2^0 = 1 exactly
