@@ -8,7 +8,13 @@ This module is the gradient oracle for the GPU training kernels:
             with `group` = g, each output row is split into consecutive groups of g values
             (one eigenvector each) and every group is compared with the sign of its target
             that fits best: 0.5 / B * sum_groups min_{s = +-1} ||y_g - s t_g||^2, where
-            s = +1 when <y_g, t_g> >= 0 (eigenvectors are defined up to sign)
+            s = +1 when <y_g, t_g> >= 0 (eigenvectors are defined up to sign);
+            with a subspace weight mu > 0 also mu * 0.5 / B * sum_groups ||(I - P) y_g||^2,
+            P = sum_j t_j t_j^T / <t_j, t_j> over the row's target groups: the part of each
+            output group outside the span of the targets, unchanged when the targets are
+            rotated within their span (eigenvectors of a cluster are defined up to a
+            rotation); P is the orthogonal projector onto that span when the target groups
+            are mutually orthogonal, as eigenvectors are
   backward  the chain rule written out layer by layer
   adam      Kingma and Ba (2015) with bias correction.
 Pinned by central differences (tests/test_oracle_mlp.py), which do not use the backward code.
@@ -54,12 +60,29 @@ def signed_target(y, T, group):
     return (T.reshape(B, n // group, group) * s[:, :, None]).reshape(B, n)
 
 
-def loss(params, x, T, group=None):
+def outside_span(y, T, group):
+    """(I - P) y_g for every output group g of every row, P = sum_j t_j t_j^T / <t_j, t_j>
+    over that row's target groups (shape of y)."""
+    B, n = y.shape
+    Y = y.reshape(B, n // group, group)
+    Tg = T.reshape(B, n // group, group)
+    out = np.empty_like(Y)
+    for b in range(B):
+        P = sum(np.outer(t, t) / (t @ t) for t in Tg[b])
+        out[b] = Y[b] - Y[b] @ P.T
+    return out.reshape(B, n), Tg
+
+
+def loss(params, x, T, group=None, sub_w=0.0):
     y, _ = forward(params, x)
-    return 0.5 * np.sum((y - signed_target(y, T, group)) ** 2) / x.shape[0]
+    val = 0.5 * np.sum((y - signed_target(y, T, group)) ** 2) / x.shape[0]
+    if sub_w > 0.0 and group is not None:
+        r, _ = outside_span(y, T, group)
+        val += sub_w * 0.5 * np.sum(r ** 2) / x.shape[0]
+    return val
 
 
-def backward(params, x, T, group=None):
+def backward(params, x, T, group=None, sub_w=0.0):
     """Gradients [(dW_l, db_l)] of `loss` by the chain rule (the group signs are
     piecewise constant, so they are held fixed in the derivative)."""
     y, hs = forward(params, x)
@@ -67,6 +90,14 @@ def backward(params, x, T, group=None):
     L = len(params)
     grads = [None] * L
     delta = (y - signed_target(y, T, group)) / B      # dloss / dz_L
+    if sub_w > 0.0 and group is not None:
+        # d/dy 0.5 ||(I - P) y||^2 = (I - P)^T (I - P) y per group
+        r, Tg = outside_span(y, T, group)
+        R = r.reshape(Tg.shape)
+        for b in range(B):
+            P = sum(np.outer(t, t) / (t @ t) for t in Tg[b])
+            R[b] = R[b] - R[b] @ P
+        delta = delta + sub_w * R.reshape(B, -1) / B
     for l in range(L - 1, -1, -1):
         W, _ = params[l]
         grads[l] = [hs[l].T @ delta, delta.sum(axis=0)]

@@ -83,3 +83,60 @@ def test_signed_loss_central_differences_and_sign_invariance():
     # all signs aligned with the output: the signed loss is the plain loss of the aligned targets
     Ta = (T.reshape(5, 2, 4) * signs[:, :, None]).reshape(5, 8)
     assert abs(mlp.loss(params, x, Ta) - base) < 1e-14
+
+
+def _orthogonal_targets(rng, B, ng, g, scale):
+    T = np.empty((B, ng * g))
+    for b in range(B):
+        Q, _ = np.linalg.qr(rng.standard_normal((g, ng)))
+        T[b] = (Q.T * scale).reshape(-1)
+    return T
+
+
+def test_subspace_loss_central_differences():
+    """Sign-invariant plus subspace loss: gradients by central differences (targets far
+    from the sign switching surface)."""
+    rng = np.random.default_rng(5)
+    sizes = [3, 6, 12]
+    params = mlp.init_params(sizes, seed=6)
+    x = rng.standard_normal((4, 3))
+    y, _ = mlp.forward(params, x)
+    T = y + 0.3 * rng.standard_normal(y.shape)        # <y_g, t_g> far from zero
+    grads = mlp.backward(params, x, T, group=4, sub_w=0.7)
+    h = 1e-6
+    for l in range(len(params)):
+        for q in range(2):
+            P = params[l][q]
+            it = np.nditer(P, flags=["multi_index"])
+            for _ in it:
+                idx = it.multi_index
+                old = P[idx]
+                P[idx] = old + h
+                fp = mlp.loss(params, x, T, group=4, sub_w=0.7)
+                P[idx] = old - h
+                fm = mlp.loss(params, x, T, group=4, sub_w=0.7)
+                P[idx] = old
+                assert abs((fp - fm) / (2 * h) - grads[l][q][idx]) < 1e-7
+
+
+def test_subspace_term_is_rotation_invariant_and_vanishes_in_the_span():
+    """Rotating each row's orthogonal target groups by an orthogonal matrix (a rotation
+    inside an eigenvector cluster) leaves the subspace term unchanged while the per-group
+    term changes; an output inside the span of its targets has no subspace term."""
+    rng = np.random.default_rng(7)
+    B, ng, g = 3, 4, 9
+    sizes = [2, 5, ng * g]
+    params = mlp.init_params(sizes, seed=8)
+    x = rng.standard_normal((B, 2))
+    T = _orthogonal_targets(rng, B, ng, g, 3.0)
+    Q, _ = np.linalg.qr(rng.standard_normal((ng, ng)))
+    Tr = np.einsum("ij,bjk->bik", Q, T.reshape(B, ng, g)).reshape(B, -1)
+    sub = lambda TT: mlp.loss(params, x, TT, group=g, sub_w=1.0) - mlp.loss(params, x, TT, group=g)   # noqa: E731
+    assert abs(sub(T) - sub(Tr)) < 1e-12 * abs(sub(T))
+    assert abs(mlp.loss(params, x, T, group=g) - mlp.loss(params, x, Tr, group=g)) > 1e-3
+    # inside the span: y = combination of the row's targets
+    y, _ = mlp.forward(params, x)
+    C = rng.standard_normal((B, ng, ng))
+    Ys = np.einsum("bij,bjk->bik", C, T.reshape(B, ng, g)).reshape(B, -1)
+    r, _ = mlp.outside_span(Ys, T, g)
+    assert np.max(np.abs(r)) < 1e-12 * np.max(np.abs(Ys))
