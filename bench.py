@@ -147,7 +147,7 @@ def valu_slots_per_pair(kind, d, precision, rates):
     return s, c_exp, c_sqrt
 
 
-def warm_start_section(n_train, epochs, n_eval, solves=3):
+def warm_start_section(n_train, epochs, n_eval, solves=3, subspace=3.0):
     """Warm-start section: the network is trained on n_train method-generated FP64 solves (tol 1e-10)
     of the 48x48 cubic quarter annulus (training draws seed 2000), then the held-out draws
     (seed 2001) are solved to 1e-6 four ways: plain FP64 from a random block, FP32 with
@@ -176,7 +176,8 @@ def warm_start_section(n_train, epochs, n_eval, solves=3):
     gen_s = time.perf_counter() - t
     ws = warmstart.WarmStart(G.N, K, seed=0)
     t = time.perf_counter()
-    losses = ws.fit(warmstart.features(L, a, flag), T, epochs=epochs, batch=64, lr0=1e-3, lr1=3e-5)
+    losses = ws.fit(warmstart.features(L, a, flag), T, epochs=epochs, batch=64, lr0=1e-3, lr1=3e-5,
+                    subspace=subspace)
     train_s = time.perf_counter() - t
     del T
     Le, ae, fe = workloads.mlp_parameters(2001, n_eval)
@@ -203,7 +204,7 @@ def warm_start_section(n_train, epochs, n_eval, solves=3):
     med = {k: float(np.median(v)) * 1e3 for k, v in rec.items()}
     return {"workload": "annulus48: 2D quarter annulus 48x48 cubic, N = 2601, k = 16, block 16; "
                         "L ~ logU[0.1,2], a ~ logU[0.5,2], flag ~ B(1/2)",
-            "n_train": n_train, "epochs": epochs, "generate_s": gen_s, "train_s": train_s,
+            "n_train": n_train, "epochs": epochs, "subspace_weight": subspace, "generate_s": gen_s, "train_s": train_s,
             "loss_first_last": [float(losses[0]), float(losses[-1])], "n_eval": n_eval,
             "median_ms": med, "mean_applies": {k: float(np.mean(v)) for k, v in app.items()},
             "f32_warm_speedup_vs_f64": med["f64"] / med["f32_warm"],
@@ -330,6 +331,8 @@ def main():
     ap.add_argument("--mlp-train", type=int, default=2000,
                     help="training solves for the warm-start section (0 = skip the section)")
     ap.add_argument("--mlp-epochs", type=int, default=1000)
+    ap.add_argument("--mlp-subspace", type=float, default=3.0,
+                    help="weight of the subspace term of the warm-start loss (0 = per-eigenvector term only)")
     ap.add_argument("--mlp-eval", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch section")
     ap.add_argument("--no-tune", action="store_true", help="keep the automatic stage-5 split")
@@ -475,7 +478,8 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_section()
     if args.mlp_train > 0:
-        out["warm_start"] = warm_start_section(args.mlp_train, args.mlp_epochs, args.mlp_eval)
+        out["warm_start"] = warm_start_section(args.mlp_train, args.mlp_epochs, args.mlp_eval,
+                                               subspace=args.mlp_subspace)
     if not args.no_cpu:
         cb, _ = cpu_baseline(desc, b)
         out["cpu_baseline"] = cb

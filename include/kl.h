@@ -408,6 +408,15 @@ kl_status kl_mlp_adam(kl_mlp *M, float lr, float beta1, float beta2, float eps, 
  * Errors: KL_EINVAL, KL_ENOMEM, KL_EHIP, KL_ENUMERIC (non-finite loss). */
 kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int32_t group, int32_t epochs,
                        int32_t batch, float lr0, float lr1, uint64_t seed, double *epoch_loss, void *stream);
+/* Weight mu >= 0 of the subspace term of the grouped loss (0, the default, leaves it
+ * out).  With group > 0, kl_mlp_gradients and kl_mlp_train then add, per row and output
+ * group y_g, mu * 0.5 / batch * ||(I - P) y_g||^2 with P = sum_j t_j t_j^T / <t_j, t_j>
+ * over the row's target groups: the part of the prediction outside the span of the
+ * targets, which does not change when eigenvectors of a cluster are rotated among
+ * themselves (the targets must be mutually orthogonal, as eigenvectors are, for P to be
+ * the projector).  At most 32 groups per row (KL_EINVAL at the call otherwise).  Errors:
+ * KL_EINVAL (NULL handle, negative or non-finite weight). */
+kl_status kl_mlp_set_subspace(kl_mlp *M, float weight);
 kl_status kl_mlp_destroy(kl_mlp *M);
 
 /* Releases the handle and every device buffer it owns.  NULL is accepted. */

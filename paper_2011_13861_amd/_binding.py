@@ -27,7 +27,8 @@ EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_apply_noalloc
            "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_profile_enable", "kl_profile_read",
            "kl_stage5_config", "kl_apply_config", "kl_set_cov", "kl_setup_patches", "kl_patch_count", "kl_patch_info",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
-           "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_destroy",
+           "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_set_subspace",
+           "kl_mlp_destroy",
            "kl_setup_batch", "kl_batch_info", "kl_apply_batch", "kl_batch_config", "kl_eigs_batch",
            "kl_batch_destroy",
            "kl_destroy", "kl_last_error"]
@@ -111,6 +112,7 @@ def lib():
         L.kl_mlp_adam.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
         L.kl_mlp_train.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P, P]
+        L.kl_mlp_set_subspace.argtypes = [P, ctypes.c_float]
         L.kl_mlp_destroy.argtypes = [P]
         L.kl_setup_patches.argtypes = [ctypes.c_int32, ctypes.POINTER(KLDesc), P, ctypes.POINTER(P)]
         L.kl_patch_count.argtypes = [P]
@@ -507,6 +509,10 @@ class MLP:
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         check(lib().kl_mlp_adam(self._h, lr, beta1, beta2, eps, _stream(stream)))
+
+    def set_subspace(self, weight):
+        """Weight of the subspace term of the grouped loss (kl_mlp_set_subspace)."""
+        check(lib().kl_mlp_set_subspace(self._h, float(weight)))
 
     def train(self, x, t, group=0, epochs=100, batch=64, lr0=1e-3, lr1=1e-4, seed=0, stream=None):
         """Minibatch Adam training; returns the per-epoch mean loss (numpy)."""

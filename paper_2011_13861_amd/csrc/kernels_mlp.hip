@@ -166,6 +166,71 @@ __global__ __launch_bounds__(kThreads) void loss_kernel(const float *__restrict_
     if (threadIdx.x == 0) loss_part[int64_t(s) * gridDim.x + gi] = 0.5 * red[0];
 }
 
+// Sum of a double over the workgroup in a fixed order (lanes by butterfly within each
+// wave, then the waves in order); every thread gets the result.  `red` holds kThreads / 64.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+    return t;
+}
+
+// Subspace term of the loss, one workgroup per (group, sample), after loss_kernel on the
+// same stream: with y the group's output and t_j the sample's ng target groups,
+// c_j = <t_j, y>, n_j = <t_j, t_j> (FP64), r = y - sum_j t_j c_j / n_j (the part of y
+// outside the span of orthogonal targets); dy += w inv_b r and loss_part += 0.5 w ||r||^2.
+__global__ __launch_bounds__(kThreads) void subspace_kernel(const float *__restrict__ y, int64_t ldy,
+                                                            const float *__restrict__ tgt, int64_t ldt,
+                                                            const int *__restrict__ rows, int group, int ng, float w,
+                                                            float inv_b, float *__restrict__ dy, int64_t lddy,
+                                                            double *__restrict__ loss_part) {
+    const int gi = blockIdx.x, s = blockIdx.y;
+    const float *yr = y + int64_t(s) * ldy + int64_t(gi) * group;
+    const int trow = rows ? rows[s] : s;
+    const float *tr = tgt + int64_t(trow) * ldt;
+    __shared__ double red[kThreads / 64];
+    __shared__ double coef[kMaxSubGroups];
+    for (int j0 = 0; j0 < ng; j0 += 8) {
+        double c[8], n[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = n[q] = 0.0;
+        for (int i = threadIdx.x; i < group; i += kThreads) {
+            const double yv = yr[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (j0 + q < ng) {
+                    const double t = tr[int64_t(j0 + q) * group + i];
+                    c[q] += t * yv;
+                    n[q] += t * t;
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (j0 + q >= ng) break;
+            const double cs = block_sum(c[q], red);
+            const double ns = block_sum(n[q], red);
+            if (threadIdx.x == 0) coef[j0 + q] = ns > 0.0 ? cs / ns : 0.0;
+        }
+    }
+    __syncthreads();
+    float *dr = dy + int64_t(s) * lddy + int64_t(gi) * group;
+    const float sc = w * inv_b;
+    double l2 = 0.0;
+    for (int i = threadIdx.x; i < group; i += kThreads) {
+        double r = yr[i];
+        for (int j = 0; j < ng; ++j) r -= double(tr[int64_t(j) * group + i]) * coef[j];
+        dr[i] += sc * float(r);
+        l2 += r * r;
+    }
+    const double tot = block_sum(l2, red);
+    if (threadIdx.x == 0) loss_part[int64_t(s) * gridDim.x + gi] += 0.5 * double(w) * tot;
+}
+
 // db[j] = sum_i D[i][j] over M rows (one thread per column, fixed row order).
 __global__ __launch_bounds__(kThreads) void colsum_kernel(const float *__restrict__ D, int64_t ldd, int M,
                                                           int N, float *__restrict__ out) {
@@ -236,6 +301,13 @@ void launch_loss(const float *y, int64_t ldy, const float *t, int64_t ldt, const
     const int ng = n_out / group;
     hipLaunchKernelGGL(loss_kernel, dim3(ng, batch), dim3(kThreads), 0, s, y, ldy, t, ldt, rows, group, signed_,
                        1.0f / float(batch), dy, lddy, loss_part);
+}
+
+void launch_subspace(const float *y, int64_t ldy, const float *t, int64_t ldt, const int *rows, int batch,
+                     int n_out, int group, float weight, float *dy, int64_t lddy, double *loss_part, hipStream_t s) {
+    const int ng = n_out / group;
+    hipLaunchKernelGGL(subspace_kernel, dim3(ng, batch), dim3(kThreads), 0, s, y, ldy, t, ldt, rows, group, ng,
+                       weight, 1.0f / float(batch), dy, lddy, loss_part);
 }
 
 void launch_colsum(const float *D, int64_t ldd, int M, int N, float *out, hipStream_t s) {

@@ -32,6 +32,7 @@ struct kl_mlp {
     int64_t loss_cap = 0;
     int *rows = nullptr;             // shuffled row indices (training)
     int64_t rows_cap = 0;
+    float sub_w = 0.0f;              // weight of the subspace term of the grouped loss
 };
 
 namespace kl {
@@ -152,6 +153,17 @@ kl_status check_batch_args(const kl_mlp *M, int batch, const void *x, const char
     return KL_OK;
 }
 
+// Whether the grouped loss carries the subspace term; KL_EINVAL when it would need more
+// target groups per row than the kernel holds.
+kl_status check_subspace(const kl_mlp *M, int group, const char *fn, bool &on) {
+    on = group > 0 && M->sub_w > 0.0f;
+    if (on && M->sizes[M->L] / group > kMaxSubGroups) {
+        set_error(std::string(fn) + ": the subspace term takes at most 32 groups per row");
+        return KL_EINVAL;
+    }
+    return KL_OK;
+}
+
 kl_status check_group(const kl_mlp *M, int group, const char *fn) {
     const int n_out = M->sizes[M->L];
     if (group < 0 || (group > 0 && n_out % group != 0)) {
@@ -252,6 +264,8 @@ kl_status kl_mlp_gradients(kl_mlp *M, int32_t batch, const float *x, const float
     if (st != KL_OK) return st;
     if (batch < 1 || !t) { set_error("kl_mlp_gradients: need batch >= 1 and targets"); return KL_EINVAL; }
     if ((st = check_group(M, group, "kl_mlp_gradients")) != KL_OK) return st;
+    bool sub = false;
+    if ((st = check_subspace(M, group, "kl_mlp_gradients", sub)) != KL_OK) return st;
     const int n_out = M->sizes[M->L];
     const int gsz = group > 0 ? group : n_out;
     const int ng = n_out / gsz;
@@ -260,6 +274,7 @@ kl_status kl_mlp_gradients(kl_mlp *M, int32_t batch, const float *x, const float
     hipStream_t s = static_cast<hipStream_t>(stream);
     forward(M, batch, x, M->Y, s);
     launch_loss(M->Y, n_out, t, n_out, nullptr, batch, n_out, gsz, group > 0, M->D0, n_out, M->loss_part, s);
+    if (sub) launch_subspace(M->Y, n_out, t, n_out, nullptr, batch, n_out, gsz, M->sub_w, M->D0, n_out, M->loss_part, s);
     backward(M, batch, x, s);
     if ((st = hipc(hipGetLastError(), "kernel launch")) != KL_OK) return st;
     if (grads &&
@@ -304,6 +319,8 @@ kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int
     if (!(lr0 > 0.0f) || !(lr1 > 0.0f)) { set_error("kl_mlp_train: learning rates must be positive"); return KL_EINVAL; }
     kl_status st = check_group(M, group, "kl_mlp_train");
     if (st != KL_OK) return st;
+    bool sub = false;
+    if ((st = check_subspace(M, group, "kl_mlp_train", sub)) != KL_OK) return st;
     const int n_in = M->sizes[0], n_out = M->sizes[M->L];
     const int gsz = group > 0 ? group : n_out;
     const int ng = n_out / gsz;
@@ -337,6 +354,9 @@ kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int
             forward(M, nb, M->xb, M->Y, s);
             launch_loss(M->Y, n_out, t, n_out, rows, nb, n_out, gsz, group > 0, M->D0, n_out,
                         M->loss_part + b0 * ng, s);
+            if (sub)
+                launch_subspace(M->Y, n_out, t, n_out, rows, nb, n_out, gsz, M->sub_w, M->D0, n_out,
+                                M->loss_part + b0 * ng, s);
             backward(M, nb, M->xb, s);
             if ((st = kl_mlp_adam(M, lr, 0.9f, 0.999f, 1e-8f, s)) != KL_OK) return st;
         }
@@ -349,6 +369,16 @@ kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int
         if (epoch_loss) epoch_loss[e] = sum / double(n);
         if (!std::isfinite(sum)) { set_error("kl_mlp_train: non-finite loss"); return KL_ENUMERIC; }
     }
+    return KL_OK;
+}
+
+kl_status kl_mlp_set_subspace(kl_mlp *M, float weight) {
+    if (!M) { set_error("kl_mlp_set_subspace: NULL handle"); return KL_EINVAL; }
+    if (!(weight >= 0.0f) || !std::isfinite(weight)) {
+        set_error("kl_mlp_set_subspace: the weight must be finite and >= 0");
+        return KL_EINVAL;
+    }
+    M->sub_w = weight;
     return KL_OK;
 }
 

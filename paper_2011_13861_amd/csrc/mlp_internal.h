@@ -42,6 +42,12 @@ void launch_gemm(bool ta, bool tb, GemmArgs g, int splits, hipStream_t s);
 void launch_loss(const float *y, int64_t ldy, const float *t, int64_t ldt, const int *rows, int batch,
                  int n_out, int group, int signed_, float *dy, int64_t lddy, double *loss_part,
                  hipStream_t s);
+// Subspace term of the warm-start loss (after launch_loss on the same stream): adds
+// weight inv_b (I - P) y_g to dy and 0.5 weight ||(I - P) y_g||^2 to loss_part, P the
+// projector onto the sample's target groups; n_out / group <= kMaxSubGroups.
+constexpr int kMaxSubGroups = 32;
+void launch_subspace(const float *y, int64_t ldy, const float *t, int64_t ldt, const int *rows, int batch,
+                     int n_out, int group, float weight, float *dy, int64_t lddy, double *loss_part, hipStream_t s);
 void launch_colsum(const float *D, int64_t ldd, int M, int N, float *out, hipStream_t s);
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, const AdamArgs &a, hipStream_t s);
 void launch_gather(const float *src, int64_t lds, const int *rows, int nrows, int ncols, float *dst,

@@ -10,7 +10,11 @@ random start stays the fallback: a prediction that is not finite is not used.
 
 Network input: (log L, log a, 2 flag - 1).  Output: k N values, eigenvector i at
 [i N, (i + 1) N), scaled by sqrt(N) so that the entries are of order one.  Loss: the
-sign-invariant squared error per eigenvector (kl_mlp_gradients with group = N).
+sign-invariant squared error per eigenvector (kl_mlp_gradients with group = N) plus, with
+weight `subspace`, the part of each predicted eigenvector outside the span of the k
+target eigenvectors (kl_mlp_set_subspace), which does not care how eigenvectors of a
+cluster are rotated among themselves: near eigenvalue crossings over the parameters the
+per-eigenvector targets jump, the span does not.
 """
 
 import math
@@ -55,10 +59,11 @@ class WarmStart:
         self.N, self.k = int(N), int(k)
         self.net = MLP([3, *hidden, self.k * self.N], seed=seed)
 
-    def fit(self, feats, targets, epochs=200, batch=64, lr0=1e-3, lr1=3e-5, seed=0):
+    def fit(self, feats, targets, epochs=200, batch=64, lr0=1e-3, lr1=3e-5, seed=0, subspace=3.0):
         """Trains on (n, 3) inputs and (n, k N) targets; returns the per-epoch loss."""
         import torch
         x = torch.as_tensor(np.ascontiguousarray(feats, dtype=np.float32)).cuda()
+        self.net.set_subspace(subspace)
         return self.net.train(x, targets, group=self.N, epochs=epochs, batch=batch, lr0=lr0, lr1=lr1, seed=seed)
 
     def predict(self, feats):

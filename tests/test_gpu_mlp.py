@@ -124,3 +124,58 @@ def test_mlp_errors():
         net.gradients(x, t, group=4)           # 4 does not divide 6
     with pytest.raises(ValueError):
         net.forward(torch.zeros((2, 5), dtype=torch.float32, device="cuda"))
+
+
+def _orthogonal_targets_near(y, B, ng, group, rng):
+    """Per row, the output groups plus noise, orthogonalised (QR) and scaled to the output
+    groups' norms, with random signs: orthogonal targets whose sign choice is unambiguous."""
+    t = np.empty_like(y)
+    for b in range(B):
+        Yg = y[b].reshape(ng, group)
+        Q, _ = np.linalg.qr((Yg + 0.2 * np.abs(Yg).mean() * rng.standard_normal(Yg.shape)).T)
+        Tg = Q.T * np.linalg.norm(Yg, axis=1)[:, None]
+        Tg *= np.sign(np.sum(Tg * Yg, axis=1))[:, None] * rng.choice([-1.0, 1.0], size=(ng, 1))
+        t[b] = Tg.reshape(-1)
+    return t
+
+
+@pytest.mark.parametrize("sizes,B,group", CASES[1:], ids=["small_signed", "ragged", "warmstart_size"])
+def test_subspace_loss_gradients_match_oracle(sizes, B, group):
+    """The grouped loss with its subspace term (weight 0.8) against the oracle, on
+    mutually orthogonal target groups per row."""
+    flat, params, x, _ = _setup(sizes, B, 12, group)
+    y, _ = mlp.forward(params, x.astype(np.float64))
+    ng = sizes[-1] // group
+    t = _orthogonal_targets_near(y, B, ng, group, np.random.default_rng(13)).astype(np.float32)
+    net = kl.MLP(sizes)
+    net.set_params(flat)
+    net.set_subspace(0.8)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    loss, g = net.gradients(xd, td, group=group)
+    t64 = t.astype(np.float64)
+    loss_ref = mlp.loss(params, x.astype(np.float64), t64, group=group, sub_w=0.8)
+    assert abs(loss - loss_ref) <= 1e-4 * loss_ref, (loss, loss_ref)
+    assert loss_ref > mlp.loss(params, x.astype(np.float64), t64, group=group) * 1.01   # the term is present
+    g_ref = mlp.backward(params, x.astype(np.float64), t64, group=group, sub_w=0.8)
+    gl = _unflat(g.cpu().numpy(), sizes)
+    for l, ((dW, db), (rW, rb)) in enumerate(zip(gl, g_ref)):
+        assert _rel(dW, rW) <= 1e-4, (l, "W", _rel(dW, rW))
+        assert _rel(db, rb) <= 1e-4, (l, "b", _rel(db, rb))
+    # weight 0 is the plain grouped loss again
+    net.set_subspace(0.0)
+    loss0, _ = net.gradients(xd, td, group=group)
+    assert abs(loss0 - mlp.loss(params, x.astype(np.float64), t64, group=group)) <= 1e-4 * loss0
+
+
+def test_subspace_weight_errors():
+    net = kl.MLP([3, 4, 66])
+    with pytest.raises(kl.KLError):
+        net.set_subspace(-1.0)
+    with pytest.raises(kl.KLError):
+        net.set_subspace(float("nan"))
+    net.set_subspace(1.0)
+    x = torch.zeros((2, 3), dtype=torch.float32, device="cuda")
+    t = torch.ones((2, 66), dtype=torch.float32, device="cuda")
+    with pytest.raises(kl.KLError):
+        net.gradients(x, t, group=2)           # 33 groups per row: more than 32
+    net.gradients(x, t, group=3)                # 22 groups
