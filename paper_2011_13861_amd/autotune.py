@@ -14,8 +14,14 @@ for single problems (plus the objective when it is the whole apply), and by
 single problem is the stage-5 kernel alone (`objective="stage5"`, the default) or the whole
 apply of a 32-column block (`objective="apply"`): the fused backward Kronecker launch adds
 the stage-5 split partials, so fewer splits can make the apply faster even when the kernel
-alone is not.  Cached settings are applied with `apply_cached`.  The cache file is
-$KL_TUNE_CACHE, else ~/.cache/paper_2011_13861_amd/stage5_tune.json.
+alone is not.  With the whole apply as the objective the tuner also chooses between the
+fused Kronecker launches (first two directions of each side in one launch, the backward
+one adding the split partials) and one launch per direction (split partials added by their
+own pass), re-scanning the split count for the latter.  Cached settings are applied with
+`apply_cached`; a problem without an entry of its own takes the entry of the nearest
+tuned padded size within 25 % (same architecture, dimension, kind, precision, objective):
+the size buckets of the cache.  The cache file is $KL_TUNE_CACHE, else
+~/.cache/paper_2011_13861_amd/stage5_tune.json.
 """
 
 import hashlib
@@ -54,11 +60,30 @@ def _padded(nt):
     return (nt + 255) // 256 * 256
 
 
-def problem_key(G, kind, precision, objective="stage5"):
-    parts = [arch(), "d%d" % G.d, kind, precision, "Np%d" % _padded(G.Nt)]
+def problem_key(G, kind, precision, objective="stage5", arch_name=None):
+    parts = [arch_name or arch(), "d%d" % G.d, kind, precision, "Np%d" % _padded(G.Nt)]
     if objective != "stage5":
         parts.append(objective)
     return "|".join(parts)
+
+
+def lookup(data, key, bucket=0.25):
+    """The cache entry of `key`, else the one whose padded size is nearest to the key's
+    among entries that differ from it in the size only, if within `bucket` (relative)."""
+    if key in data:
+        return data[key]
+    parts = key.split("|")
+    i = next(j for j, p in enumerate(parts) if p.startswith("Np"))
+    np0 = int(parts[i][2:])
+    best = None
+    for k, e in data.items():
+        q = k.split("|")
+        if len(q) != len(parts) or q[:i] + q[i + 1:] != parts[:i] + parts[i + 1:] or not q[i].startswith("Np"):
+            continue
+        d = abs(int(q[i][2:]) - np0) / np0
+        if d <= bucket and (best is None or d < best[0]):
+            best = (d, e)
+    return best[1] if best else None
 
 
 def batch_key(B, kinds, precision):
@@ -120,8 +145,8 @@ def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None,
     path = path or cache_path()
     data = _load(path)
     out = {}
-    for prec in precisions:
-        rbs = [2] if prec == "f64" else ([1, 2, 4, 8] if prec == "f32" else [1, 2, 4])
+
+    def scan(prec, rbs):
         timed = []
         for rb in rbs:
             _, auto = G.stage5_config(prec, rb=rb, nsplit=0)
@@ -134,9 +159,23 @@ def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None,
                 if verbose:
                     print("tune", prec, rbe, nse, "%.1f us" % us)
                 timed.append((rbe, nse, us))
-        best = pick(timed)
+        return pick(timed)
+
+    for prec in precisions:
+        rbs = [2] if prec == "f64" else ([1, 2, 4, 8] if prec == "f32" else [1, 2, 4])
+        fused = G.apply_config(True)
+        best = scan(prec, rbs)
+        fuse = fused
+        if objective == "apply" and fused:
+            # one launch per direction, with the tile height found above
+            G.apply_config(False)
+            alt = scan(prec, [best[0]])
+            if alt[2] < best[2] * (1.0 - 0.015):
+                best, fuse = alt, False
+            G.apply_config(fuse)
         G.stage5_config(prec, rb=best[0], nsplit=best[1])
-        data[problem_key(G, kind, prec, objective)] = {"rb": best[0], "nsplit": best[1], "us": best[2]}
+        data[problem_key(G, kind, prec, objective)] = {"rb": best[0], "nsplit": best[1], "us": best[2],
+                                                        "fuse": bool(fuse)}
         out[prec] = best
     _store(path, data)
     return out
@@ -176,10 +215,13 @@ def tune_batch(B, kinds, precision="f32", reps=10, path=None, verbose=False):
 
 
 def apply_cached(G, kind, precision, path=None, objective="stage5"):
-    """Sets the cached setting for G, if any; returns it (or None)."""
-    e = _load(path or cache_path()).get(problem_key(G, kind, precision, objective))
+    """Sets the cached setting for G (its own, else its size bucket's), if any; returns it
+    (or None)."""
+    e = lookup(_load(path or cache_path()), problem_key(G, kind, precision, objective))
     if e:
         G.stage5_config(precision, rb=e["rb"], nsplit=e["nsplit"])
+        if "fuse" in e:
+            G.apply_config(e["fuse"])
     return e
 
 

@@ -53,6 +53,7 @@ def test_tune_problem_apply_objective(tmp_path):
     assert autotune.problem_key(G, "sqexp", "f32") not in data
     e = data[autotune.problem_key(G, "sqexp", "f32", "apply")]
     assert (e["rb"], e["nsplit"]) == (rb, ns) and us > 0
+    assert isinstance(e["fuse"], bool)            # fused or per-direction Kronecker launches
     F = kl.Problem(desc)
     assert autotune.apply_cached(F, "sqexp", "f32", path=path) is None
     assert autotune.apply_cached(F, "sqexp", "f32", path=path, objective="apply") is not None
