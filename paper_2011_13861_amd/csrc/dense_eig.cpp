@@ -362,7 +362,8 @@ bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv) {
 // triangular).  Returns false, leaving T unspecified, when a pivot r_jj^2 falls to
 // rel_tol max_i G_ii or below (numerical rank deficiency: the caller uses the
 // eigen-decomposition instead).
-bool chol_orth_transform(int n, const double *G, double *T, double rel_tol) {
+bool chol_orth_transform(int n, const double *G, double *T, double rel_tol, double *min_sine) {
+    if (min_sine) *min_sine = 0.0;
     if (n <= 0) return true;
     double dmax = 0.0;
     for (int i = 0; i < n; ++i) dmax = std::max(dmax, G[size_t(i) * n + i]);
@@ -375,6 +376,9 @@ bool chol_orth_transform(int n, const double *G, double *T, double rel_tol) {
         if (!(d > floor_)) return false;
         const double rjj = std::sqrt(d);
         R[size_t(j) * n + j] = rjj;
+        // sine of the angle between column j and the span of the columns before it
+        const double sj = rjj / std::sqrt(G[size_t(j) * n + j]);
+        if (min_sine && (j == 0 || sj < *min_sine)) *min_sine = sj;
         const double inv = 1.0 / rjj;
         for (int c = j + 1; c < n; ++c) {
             double v = G[size_t(j) * n + c];

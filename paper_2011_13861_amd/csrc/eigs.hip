@@ -235,6 +235,11 @@ struct Solver {
     // directions of W; rank deficiency is filled with seeded random directions.  With
     // c_holds_vtw the device buffer C already holds V[:, :m]^T W (m x ncols, as the
     // last update_H left it) and the first Gram product is not recomputed.
+    // One Cholesky pass leaves the columns orthonormal to about eps kappa^2 and orthogonal
+    // to V (after the two Gram-Schmidt rounds) to about eps kappa, kappa the condition of
+    // the block after Gram-Schmidt; when no column lies within asin(0.1) of the span of the
+    // columns before it, kappa is at most about 10 sqrt(ncols) and the second pass is
+    // skipped.
     kl_status orth_into_basis(double *Wb, int ncols, int want, std::mt19937_64 &rng, bool c_holds_vtw = false) {
         kl_status st;
         std::vector<double> G, w, Z;
@@ -242,8 +247,9 @@ struct Solver {
         last_refilled = false;
         // pass 0 selects the `want` dominant directions; later passes re-orthonormalise
         // them (twice is enough unless a direction had to be replaced by a random one)
-        bool refilled = true;
+        bool refilled = true, well_conditioned = false;
         for (int pass = 0; pass < 4 && (pass < 2 || refilled); ++pass) {
+            if (pass > 0 && !refilled && well_conditioned) break;
             if (pass > 0 && !refilled) {
                 // the block is orthonormal and orthogonal to V up to rounding: one pass of
                 // the short form (falls through to the full one if it meets rank deficiency)
@@ -278,8 +284,10 @@ struct Solver {
             const int out_cols = pass == 0 ? want : ncols;
             double *T = pin_T;
             int good = 0;
-            if (out_cols == ncols && chol_orth_transform(ncols, G.data(), T, 1e-24)) {
+            double min_sine = 0.0;
+            if (out_cols == ncols && chol_orth_transform(ncols, G.data(), T, 1e-24, &min_sine)) {
                 good = ncols;
+                well_conditioned = pass == 0 && min_sine >= 0.1;
             } else {
                 w.assign(ncols, 0.0);
                 Z.assign(size_t(ncols) * ncols, 0.0);

@@ -36,8 +36,10 @@ struct HostSetup {
 bool sym_eig(int n, const double *A, double *w, double *Z);
 // All eigenvalues (descending) and the eigenvectors of the nv largest (Z: n x nv).
 bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv);
-// T = R^{-1} with G = R^T R (host; false on a pivot <= rel_tol max diag(G)).
-bool chol_orth_transform(int n, const double *G, double *T, double rel_tol);
+// T = R^{-1} with G = R^T R (host; false on a pivot <= rel_tol max diag(G)).  min_sine
+// (optional) receives min_j R_jj / sqrt(G_jj): the smallest sine of the angle between a
+// column and the span of the columns before it (1 for orthogonal columns).
+bool chol_orth_transform(int n, const double *G, double *T, double rel_tol, double *min_sine = nullptr);
 
 // Fills `hs` from the description; returns KL_OK or an error (message set).
 kl_status build_host_setup(const kl_desc &desc, HostSetup &hs);
