@@ -29,7 +29,7 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 # plain 256 MiB copy), keyed by (workload, precision, rb, nsplit); see
 # profiles/stage5_f64_cube24_hbm_traffic.md and profiles/stage5_f32_annulus64_hbm_traffic.md.  Only
 # reported for the setting it was measured on.
-MEASURED_TRAFFIC = {("annulus64", "f32", 8, 6): 8438 * 1024}
+MEASURED_TRAFFIC = {("cube24", "f64", 4, 10): 82957 * 1024, ("annulus64", "f32", 8, 6): 8438 * 1024}
 WORKLOADS = {
     "annulus64": ("2D quarter annulus (r in [1,2], NURBS map) 64x64 cubic, Ntilde = N = 4489, "
                   "squared exponential L = 0.5, k = 40"),
