@@ -180,55 +180,140 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return t;
 }
 
-// Subspace term of the loss, one workgroup per (group, sample), after loss_kernel on the
-// same stream: with y the group's output and t_j the sample's ng target groups,
-// c_j = <t_j, y>, n_j = <t_j, t_j> (FP64), r = y - sum_j t_j c_j / n_j (the part of y
-// outside the span of orthogonal targets); dy += w inv_b r and loss_part += 0.5 w ||r||^2.
-__global__ __launch_bounds__(kThreads) void subspace_kernel(const float *__restrict__ y, int64_t ldy,
-                                                            const float *__restrict__ tgt, int64_t ldt,
-                                                            const int *__restrict__ rows, int group, int ng, float w,
-                                                            float inv_b, float *__restrict__ dy, int64_t lddy,
-                                                            double *__restrict__ loss_part) {
-    const int gi = blockIdx.x, s = blockIdx.y;
-    const float *yr = y + int64_t(s) * ldy + int64_t(gi) * group;
-    const int trow = rows ? rows[s] : s;
-    const float *tr = tgt + int64_t(trow) * ldt;
-    __shared__ double red[kThreads / 64];
-    __shared__ double coef[kMaxSubGroups];
-    for (int j0 = 0; j0 < ng; j0 += 8) {
-        double c[8], n[8];
+// Subspace term of the loss in three passes (after loss_kernel on the same stream).  With
+// y_a the sample's output groups and t_b its target groups (a, b < ng):
+//   gram:     per slice of the group index, the FP64 sums <y_a, t_b> and <t_b, t_b>;
+//   coef:     per sample, the slices summed in order, c_ab = <y_a, t_b> / <t_b, t_b>;
+//   residual: r_a = y_a - sum_b c_ab t_b (the part of y_a outside the span of orthogonal
+//             targets), dy += w inv_b r_a and loss_part += 0.5 w ||r_a||^2.
+// Every output and target element is read once per pass.
+constexpr int kSubChunk = 128;    // group elements staged in LDS per step of the gram pass
+constexpr int kSubSlices = 16;    // at most this many gram workgroups per sample
+constexpr int kSubPairs = (kMaxSubGroups * (kMaxSubGroups + 1) + kThreads - 1) / kThreads;
+
+int sub_slices(int group) { return std::min(kSubSlices, (group + kSubChunk - 1) / kSubChunk); }
+
+// part[(s ns + sl) P + q], P = ng^2 + ng: q < ng^2 holds <y_a, t_b> (a = q / ng, b = q % ng),
+// q = ng^2 + b holds <t_b, t_b>; workgroup sl sums the chunks sl, sl + ns, ... of the group.
+__global__ __launch_bounds__(kThreads) void subspace_gram_kernel(const float *__restrict__ y, int64_t ldy,
+                                                                 const float *__restrict__ tgt, int64_t ldt,
+                                                                 const int *__restrict__ rows, int group, int ng,
+                                                                 double *__restrict__ part) {
+    const int sl = blockIdx.x, ns = gridDim.x, s = blockIdx.y;
+    const float *yr = y + int64_t(s) * ldy;
+    const float *tr = tgt + int64_t(rows ? rows[s] : s) * ldt;
+    // rows 0..ng-1: the output groups, rows kMaxSubGroups + b: the target groups
+    __shared__ float sb[2 * kMaxSubGroups][kSubChunk + 1];
+    const int nn = ng * ng, P = nn + ng;
+    int ru[kSubPairs], rv[kSubPairs];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c[q] = n[q] = 0.0;
-        for (int i = threadIdx.x; i < group; i += kThreads) {
-            const double yv = yr[i];
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (j0 + q < ng) {
-                    const double t = tr[int64_t(j0 + q) * group + i];
-                    c[q] += t * yv;
-                    n[q] += t * t;
-                }
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (j0 + q >= ng) break;
-            const double cs = block_sum(c[q], red);
-            const double ns = block_sum(n[q], red);
-            if (threadIdx.x == 0) coef[j0 + q] = ns > 0.0 ? cs / ns : 0.0;
-        }
+    for (int k = 0; k < kSubPairs; ++k) {
+        const int q = threadIdx.x + k * kThreads;
+        ru[k] = q < nn ? q / ng : kMaxSubGroups + (q - nn);
+        rv[k] = kMaxSubGroups + (q < nn ? q % ng : q - nn);
     }
+    double acc[kSubPairs];
+#pragma unroll
+    for (int k = 0; k < kSubPairs; ++k) acc[k] = 0.0;
+    for (int c0 = sl * kSubChunk; c0 < group; c0 += ns * kSubChunk) {
+        const int len = min(kSubChunk, group - c0);
+        // all loads of the chunk are issued before the LDS stores
+        constexpr int kRowsPer = kThreads / kSubChunk;
+        const int a0 = threadIdx.x / kSubChunk, i = threadIdx.x % kSubChunk;
+        float vy[kMaxSubGroups / kRowsPer], vt[kMaxSubGroups / kRowsPer];
+#pragma unroll
+        for (int k = 0; k < kMaxSubGroups / kRowsPer; ++k) {
+            const int a = a0 + k * kRowsPer;
+            const bool in = a < ng && i < len;
+            const int64_t g = int64_t(a) * group + c0 + i;
+            vy[k] = in ? yr[g] : 0.0f;
+            vt[k] = in ? tr[g] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxSubGroups / kRowsPer; ++k) {
+            const int a = a0 + k * kRowsPer;
+            if (a < ng) {
+                sb[a][i] = vy[k];
+                sb[kMaxSubGroups + a][i] = vt[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSubPairs; ++k)
+            if (threadIdx.x + k * kThreads < P) {
+                double d = 0.0;
+#pragma unroll 8
+                for (int i = 0; i < kSubChunk; ++i) d += double(sb[ru[k]][i]) * double(sb[rv[k]][i]);
+                acc[k] += d;
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < kSubPairs; ++k) {
+        const int q = threadIdx.x + k * kThreads;
+        if (q < P) part[(int64_t(s) * ns + sl) * P + q] = acc[k];
+    }
+}
+
+// coef[s ng^2 + a ng + b] = c_ab from the ns slices of the gram pass (0 for a zero target).
+__global__ __launch_bounds__(kThreads) void subspace_coef_kernel(const double *__restrict__ part, int ns, int ng,
+                                                                 double *__restrict__ coef) {
+    const int s = blockIdx.x, nn = ng * ng, P = nn + ng;
+    for (int q = threadIdx.x; q < nn; q += kThreads) {
+        const int b = q % ng;
+        double c = 0.0, n = 0.0;
+        for (int sl = 0; sl < ns; ++sl) {
+            const double *p = part + (int64_t(s) * ns + sl) * P;
+            c += p[q];
+            n += p[nn + b];
+        }
+        coef[int64_t(s) * nn + q] = n > 0.0 ? c / n : 0.0;
+    }
+}
+
+// One workgroup per (slice of the group index, sample), gridDim.x = ng slices; each thread
+// loads the ng outputs, targets and deltas of its element first and keeps the ng residuals in
+// registers (MG >= ng).
+template <int MG>
+__global__ __launch_bounds__(kThreads) void subspace_residual_kernel(const float *__restrict__ y, int64_t ldy,
+                                                                     const float *__restrict__ tgt, int64_t ldt,
+                                                                     const int *__restrict__ rows, int group, int ng,
+                                                                     const double *__restrict__ coef, float w,
+                                                                     float inv_b, float *__restrict__ dy,
+                                                                     int64_t lddy, double *__restrict__ loss_part) {
+    const int sl = blockIdx.x, s = blockIdx.y;
+    const float *yr = y + int64_t(s) * ldy;
+    const float *tr = tgt + int64_t(rows ? rows[s] : s) * ldt;
+    float *dr = dy + int64_t(s) * lddy;
+    __shared__ double cf[MG][MG];
+    __shared__ double red[kThreads / 64];
+    for (int q = threadIdx.x; q < ng * ng; q += kThreads) cf[q / ng][q % ng] = coef[int64_t(s) * ng * ng + q];
     __syncthreads();
-    float *dr = dy + int64_t(s) * lddy + int64_t(gi) * group;
+    const int len = (group + ng - 1) / ng;
+    const int i0 = sl * len, i1 = min(group, i0 + len);
     const float sc = w * inv_b;
     double l2 = 0.0;
-    for (int i = threadIdx.x; i < group; i += kThreads) {
-        double r = yr[i];
-        for (int j = 0; j < ng; ++j) r -= double(tr[int64_t(j) * group + i]) * coef[j];
-        dr[i] += sc * float(r);
-        l2 += r * r;
+    for (int i = i0 + int(threadIdx.x); i < i1; i += kThreads) {
+        float yv[MG], tv[MG], dv[MG];
+#pragma unroll
+        for (int a = 0; a < MG; ++a) {
+            yv[a] = a < ng ? yr[int64_t(a) * group + i] : 0.0f;
+            tv[a] = a < ng ? tr[int64_t(a) * group + i] : 0.0f;
+            dv[a] = a < ng ? dr[int64_t(a) * group + i] : 0.0f;
+        }
+#pragma unroll
+        for (int a = 0; a < MG; ++a) {
+            if (a >= ng) break;
+            double r = yv[a];
+#pragma unroll
+            for (int b = 0; b < MG; ++b)
+                if (b < ng) r -= double(tv[b]) * cf[a][b];
+            dr[int64_t(a) * group + i] = dv[a] + sc * float(r);
+            l2 += r * r;
+        }
     }
     const double tot = block_sum(l2, red);
-    if (threadIdx.x == 0) loss_part[int64_t(s) * gridDim.x + gi] += 0.5 * double(w) * tot;
+    if (threadIdx.x == 0) loss_part[int64_t(s) * gridDim.x + sl] += 0.5 * double(w) * tot;
 }
 
 // db[j] = sum_i D[i][j] over M rows (one thread per column, fixed row order).
@@ -303,11 +388,33 @@ void launch_loss(const float *y, int64_t ldy, const float *t, int64_t ldt, const
                        1.0f / float(batch), dy, lddy, loss_part);
 }
 
-void launch_subspace(const float *y, int64_t ldy, const float *t, int64_t ldt, const int *rows, int batch,
-                     int n_out, int group, float weight, float *dy, int64_t lddy, double *loss_part, hipStream_t s) {
+int64_t subspace_scratch(int batch, int n_out, int group) {
     const int ng = n_out / group;
-    hipLaunchKernelGGL(subspace_kernel, dim3(ng, batch), dim3(kThreads), 0, s, y, ldy, t, ldt, rows, group, ng,
-                       weight, 1.0f / float(batch), dy, lddy, loss_part);
+    return int64_t(batch) * (int64_t(sub_slices(group)) * (ng * ng + ng) + ng * ng);
+}
+
+void launch_subspace(const float *y, int64_t ldy, const float *t, int64_t ldt, const int *rows, int batch,
+                     int n_out, int group, float weight, float *dy, int64_t lddy, double *loss_part,
+                     double *scratch, hipStream_t s) {
+    const int ng = n_out / group, ns = sub_slices(group);
+    double *part = scratch, *coef = scratch + int64_t(batch) * ns * (ng * ng + ng);
+    hipLaunchKernelGGL(subspace_gram_kernel, dim3(ns, batch), dim3(kThreads), 0, s, y, ldy, t, ldt, rows, group, ng,
+                       part);
+    hipLaunchKernelGGL(subspace_coef_kernel, dim3(batch), dim3(kThreads), 0, s, part, ns, ng, coef);
+    const dim3 grid(ng, batch);
+    const float inv_b = 1.0f / float(batch);
+    if (ng <= 4)
+        hipLaunchKernelGGL(subspace_residual_kernel<4>, grid, dim3(kThreads), 0, s, y, ldy, t, ldt, rows, group, ng,
+                           coef, weight, inv_b, dy, lddy, loss_part);
+    else if (ng <= 8)
+        hipLaunchKernelGGL(subspace_residual_kernel<8>, grid, dim3(kThreads), 0, s, y, ldy, t, ldt, rows, group, ng,
+                           coef, weight, inv_b, dy, lddy, loss_part);
+    else if (ng <= 16)
+        hipLaunchKernelGGL(subspace_residual_kernel<16>, grid, dim3(kThreads), 0, s, y, ldy, t, ldt, rows, group,
+                           ng, coef, weight, inv_b, dy, lddy, loss_part);
+    else
+        hipLaunchKernelGGL(subspace_residual_kernel<32>, grid, dim3(kThreads), 0, s, y, ldy, t, ldt, rows, group,
+                           ng, coef, weight, inv_b, dy, lddy, loss_part);
 }
 
 void launch_colsum(const float *D, int64_t ldd, int M, int N, float *out, hipStream_t s) {

@@ -33,6 +33,8 @@ struct kl_mlp {
     int *rows = nullptr;             // shuffled row indices (training)
     int64_t rows_cap = 0;
     float sub_w = 0.0f;              // weight of the subspace term of the grouped loss
+    double *sub_buf = nullptr;       // partial sums and coefficients of the subspace term
+    int64_t sub_cap = 0;
 };
 
 namespace kl {
@@ -83,6 +85,14 @@ kl_status ensure_loss(kl_mlp *M, int64_t n) {
     if (n <= M->loss_cap) return KL_OK;
     kl_status st = alloc(&M->loss_part, n, "alloc loss");
     if (st == KL_OK) M->loss_cap = n;
+    return st;
+}
+
+kl_status ensure_subspace(kl_mlp *M, int B, int group) {
+    const int64_t n = subspace_scratch(B, M->sizes[M->L], group);
+    if (n <= M->sub_cap) return KL_OK;
+    kl_status st = alloc(&M->sub_buf, n, "alloc subspace scratch");
+    if (st == KL_OK) M->sub_cap = n;
     return st;
 }
 
@@ -142,7 +152,7 @@ void free_mlp(kl_mlp *M) {
     hipFree(M->p); hipFree(M->g); hipFree(M->m); hipFree(M->v);
     for (float *h : M->H) hipFree(h);
     hipFree(M->Y); hipFree(M->D0); hipFree(M->D1); hipFree(M->xb); hipFree(M->part);
-    hipFree(M->loss_part); hipFree(M->rows);
+    hipFree(M->loss_part); hipFree(M->rows); hipFree(M->sub_buf);
     delete M;
 }
 
@@ -271,10 +281,13 @@ kl_status kl_mlp_gradients(kl_mlp *M, int32_t batch, const float *x, const float
     const int ng = n_out / gsz;
     if ((st = ensure_batch(M, batch)) != KL_OK) return st;
     if ((st = ensure_loss(M, int64_t(batch) * ng)) != KL_OK) return st;
+    if (sub && (st = ensure_subspace(M, batch, gsz)) != KL_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     forward(M, batch, x, M->Y, s);
     launch_loss(M->Y, n_out, t, n_out, nullptr, batch, n_out, gsz, group > 0, M->D0, n_out, M->loss_part, s);
-    if (sub) launch_subspace(M->Y, n_out, t, n_out, nullptr, batch, n_out, gsz, M->sub_w, M->D0, n_out, M->loss_part, s);
+    if (sub)
+        launch_subspace(M->Y, n_out, t, n_out, nullptr, batch, n_out, gsz, M->sub_w, M->D0, n_out, M->loss_part,
+                        M->sub_buf, s);
     backward(M, batch, x, s);
     if ((st = hipc(hipGetLastError(), "kernel launch")) != KL_OK) return st;
     if (grads &&
@@ -327,6 +340,7 @@ kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int
     const int B = int(std::min<int64_t>(batch, n));
     if ((st = ensure_batch(M, B)) != KL_OK) return st;
     if ((st = ensure_loss(M, n * ng)) != KL_OK) return st;
+    if (sub && (st = ensure_subspace(M, B, gsz)) != KL_OK) return st;
     if (n > M->rows_cap) {
         if ((st = alloc(&M->rows, n, "alloc rows")) != KL_OK) return st;
         M->rows_cap = n;
@@ -356,7 +370,7 @@ kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int
                         M->loss_part + b0 * ng, s);
             if (sub)
                 launch_subspace(M->Y, n_out, t, n_out, rows, nb, n_out, gsz, M->sub_w, M->D0, n_out,
-                                M->loss_part + b0 * ng, s);
+                                M->loss_part + b0 * ng, M->sub_buf, s);
             backward(M, nb, M->xb, s);
             if ((st = kl_mlp_adam(M, lr, 0.9f, 0.999f, 1e-8f, s)) != KL_OK) return st;
         }

@@ -44,10 +44,13 @@ void launch_loss(const float *y, int64_t ldy, const float *t, int64_t ldt, const
                  hipStream_t s);
 // Subspace term of the warm-start loss (after launch_loss on the same stream): adds
 // weight inv_b (I - P) y_g to dy and 0.5 weight ||(I - P) y_g||^2 to loss_part, P the
-// projector onto the sample's target groups; n_out / group <= kMaxSubGroups.
+// projector onto the sample's target groups; n_out / group <= kMaxSubGroups.  `scratch`
+// holds subspace_scratch(batch, n_out, group) doubles (partial sums and coefficients).
 constexpr int kMaxSubGroups = 32;
+int64_t subspace_scratch(int batch, int n_out, int group);
 void launch_subspace(const float *y, int64_t ldy, const float *t, int64_t ldt, const int *rows, int batch,
-                     int n_out, int group, float weight, float *dy, int64_t lddy, double *loss_part, hipStream_t s);
+                     int n_out, int group, float weight, float *dy, int64_t lddy, double *loss_part,
+                     double *scratch, hipStream_t s);
 void launch_colsum(const float *D, int64_t ldd, int M, int N, float *out, hipStream_t s);
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, const AdamArgs &a, hipStream_t s);
 void launch_gather(const float *src, int64_t lds, const int *rows, int nrows, int ncols, float *dst,

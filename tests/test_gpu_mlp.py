@@ -139,10 +139,17 @@ def _orthogonal_targets_near(y, B, ng, group, rng):
     return t
 
 
-@pytest.mark.parametrize("sizes,B,group", CASES[1:], ids=["small_signed", "ragged", "warmstart_size"])
+# 7 groups of 300 (several LDS chunks per slice, ragged tail); 32 groups of 150; 32 groups
+# of 48 (residual slices of 2 elements: slices 24 to 31 are empty)
+SUB_CASES = CASES[1:] + [([3, 16, 16, 2100], 5, 300), ([3, 16, 16, 4800], 3, 150), ([3, 8, 8, 1536], 4, 48)]
+
+
+@pytest.mark.parametrize("sizes,B,group", SUB_CASES,
+                         ids=["small_signed", "ragged", "warmstart_size", "g7", "g32", "g32_short"])
 def test_subspace_loss_gradients_match_oracle(sizes, B, group):
     """The grouped loss with its subspace term (weight 0.8) against the oracle, on
-    mutually orthogonal target groups per row."""
+    mutually orthogonal target groups per row (2 to 32 groups: every register bucket of
+    the residual pass)."""
     flat, params, x, _ = _setup(sizes, B, 12, group)
     y, _ = mlp.forward(params, x.astype(np.float64))
     ng = sizes[-1] // group
