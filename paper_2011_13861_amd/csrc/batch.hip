@@ -147,7 +147,7 @@ kl_status build_plan(kl_batch *B, int precision) {
     const int64_t rows_wg = stage5_rows_per_wg(precision, pl.rb);
     pl.grid = stage5_batch_grid(precision, d, pl.rb, B->n_cu);
     pl.lchunk = B->cfg_lchunk[pi] > 0 ? B->cfg_lchunk[pi] : auto_lchunk(B, rows_wg, pl.grid);
-    pl.lchunk = std::max<int64_t>(64, (pl.lchunk + 63) / 64 * 64);
+    pl.lchunk = std::max<int64_t>(64, (pl.lchunk + 63) / 64 * 64);   // 64-point granule of the stage-5 staging
     // ---- Kronecker directions -----------------------------------------------------------
     for (int k = 0; k < d; ++k) {
         pl.fwd_base[k].resize(n);

@@ -252,7 +252,11 @@ __device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, con
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
-    // prefetch registers: the next step's Y rows (16-byte loads) and points
+    // prefetch registers: the next step's Y rows (16-byte loads) and points.  l1 - l0 is a
+    // multiple of 64 (Ntpad and lchunk are), so a wave whose first point is below l1 has all
+    // kSubW of its points below l1 and the other waves skip the step: staged points at or
+    // past l1 are never read, and their loads are clamped into the split (no zero fill).
+    static_assert(64 % kSubW == 0, "a wave sub-tile divides the 64-point granule of the splits");
     float4 py[kLd4];
     float px[D];
     auto prefetch = [&](int64_t lt) {
@@ -260,15 +264,12 @@ __device__ __forceinline__ void stage5_f32_body(const float *__restrict__ X, con
         for (int q = 0; q < kLd4; ++q) {
             const int e = threadIdx.x + q * kNT;
             const int l4 = e % (kStep / 4), j = e / (kStep / 4);
-            const int64_t lg = lt + 4 * l4;
-            py[q] = lg < l1 ? *reinterpret_cast<const float4 *>(Y + int64_t(j) * Ntpad + lg)
-                            : float4{0.f, 0.f, 0.f, 0.f};
+            const int64_t lg = min(lt + 4 * l4, l1 - 4);
+            py[q] = *reinterpret_cast<const float4 *>(Y + int64_t(j) * Ntpad + lg);
         }
+        const int64_t lg = min(lt + int64_t(threadIdx.x), l1 - 1);
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int64_t lg = lt + threadIdx.x;
-            px[k] = (threadIdx.x < kStep && lg < l1) ? X[k * Ntpad + lg] : 0.f;
-        }
+        for (int k = 0; k < D; ++k) px[k] = threadIdx.x < kStep ? X[k * Ntpad + lg] : 0.f;
     };
     prefetch(l0);
     for (int64_t lt = l0; lt < l1; lt += kStep) {
@@ -352,17 +353,21 @@ __device__ __forceinline__ void stage5_f64_body(const double *__restrict__ X, co
         for (int r = 0; r < 4; ++r) { acc[rb][0][r] = 0.0; acc[rb][1][r] = 0.0; }
     for (int64_t lt = l0; lt < l1; lt += kStep) {
         __syncthreads();
+        // l1 - l0 is a multiple of kSub (Ntpad and lchunk are), so a wave whose first point
+        // is below l1 has all kSub of its points below l1 and the other waves skip the step:
+        // staged points at or past l1 are never read.  Their loads are clamped into the split
+        // (no zero fill, no branch).  Every load of a thread is at l = 2 (tid mod kStep/2).
+        static_assert(kThreads % (kStep / 2) == 0, "one l per thread in the Y staging");
+        static_assert(64 % kSub == 0, "a wave sub-tile divides the 64-point granule of the splits");
+        const int64_t lgy = min(lt + 2 * (threadIdx.x % (kStep / 2)), l1 - 2);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             // 16-byte loads (2 consecutive l of one column), 8 in flight per thread
             double2 v[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int e = threadIdx.x + (h * 8 + q) * kThreads;
-                const int l2 = e % (kStep / 2), j = e / (kStep / 2);
-                const int64_t lg = lt + 2 * l2;
-                v[q] = lg < l1 ? *reinterpret_cast<const double2 *>(Y + int64_t(j) * Ntpad + lg)
-                               : double2{0.0, 0.0};
+                const int j = (threadIdx.x + (h * 8 + q) * kThreads) / (kStep / 2);
+                v[q] = *reinterpret_cast<const double2 *>(Y + int64_t(j) * Ntpad + lgy);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -372,11 +377,9 @@ __device__ __forceinline__ void stage5_f64_body(const double *__restrict__ X, co
                 sY[(2 * l2 + 1) * (kBW + 1) + j] = v[q].y;
             }
         }
+        const int64_t lgx = min(lt + int64_t(threadIdx.x), l1 - 1);
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int64_t lg = lt + threadIdx.x;
-            sX[k * kStep + threadIdx.x] = lg < l1 ? X[k * Ntpad + lg] : 0.0;
-        }
+        for (int k = 0; k < D; ++k) sX[k * kStep + threadIdx.x] = X[k * Ntpad + lgx];
         __syncthreads();
         if (lt + wave * kSub < l1) {
             const int base = wave * kSub;
@@ -457,7 +460,22 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
         for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
     int4 ph[kLd], pl[kLd];
     float px[D];
+    // Steps wholly inside [l0, l1) load without bounds checks; the last one zero-fills the
+    // points past l1 (zero Y rows, so those products add exact zeros).
     auto prefetch = [&](int64_t lt) {
+        if (lt + kStep <= l1) {
+#pragma unroll
+            for (int q = 0; q < kLd; ++q) {
+                const int e = threadIdx.x + q * kThreads;
+                const int j = e / (kStep / 8), seg = e % (kStep / 8);
+                const int64_t lg = lt + 8 * seg;
+                ph[q] = *reinterpret_cast<const int4 *>(Yh + int64_t(j) * Ntpad + lg);
+                if constexpr (X3) pl[q] = *reinterpret_cast<const int4 *>(Yl + int64_t(j) * Ntpad + lg);
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k) px[k] = X[k * Ntpad + lt + threadIdx.x];
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < kLd; ++q) {
             const int e = threadIdx.x + q * kThreads;
@@ -490,7 +508,9 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
         for (int k = 0; k < D; ++k) sX[k][threadIdx.x] = px[k];
         __syncthreads();
         if (lt + kStep < l1) prefetch(lt + kStep);
-        if (lt + wave * kSub < l1) {
+        // every wave runs the whole step: a wave past l1 multiplies zero Y rows, and without
+        // a branch around the loop the accumulators stay in place across steps
+        {
             const int base = wave * kSub;
 #pragma unroll
             for (int ll = 0; ll < kSub; ll += 16) {
@@ -734,6 +754,9 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
             if (cost < best_cost - 1e-12) { best_cost = cost; best = S; }
         }
     }
+    // the split length is a multiple of kSub = 64 and Ntpad one of kPad: every split covers a
+    // multiple of 64 points, which the staging of the stage-5 bodies relies on
+    static_assert(kSub == 64 && kPad % 64 == 0, "64-point split granule");
     int64_t lchunk = ((Ntpad + best - 1) / best + kSub - 1) / kSub * kSub;
     const int64_t nsplit = (Ntpad + lchunk - 1) / lchunk;
     if (lchunk_out) *lchunk_out = lchunk;
