@@ -25,7 +25,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_apply_noalloc", "kl_stage5", "kl_get_points",
            "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_profile_enable", "kl_profile_read",
-           "kl_stage5_config", "kl_apply_config", "kl_set_cov", "kl_setup_patches", "kl_patch_count", "kl_patch_info",
+           "kl_stage5_config", "kl_stage5_symmetric", "kl_apply_config", "kl_set_cov", "kl_setup_patches", "kl_patch_count", "kl_patch_info",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
            "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_set_subspace",
            "kl_mlp_destroy",
@@ -99,6 +99,7 @@ def lib():
         L.kl_symeig_partial.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
         L.kl_stage5_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
+        L.kl_stage5_symmetric.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
         L.kl_apply_config.argtypes = [P, ctypes.c_int32, P]
         L.kl_profile_read.argtypes = [P, P, P]
         L.kl_set_cov.argtypes = [P, ctypes.c_int32, ctypes.c_double, P]
@@ -343,6 +344,13 @@ class Problem:
         check(lib().kl_stage5_config(self._h, PRECISIONS[precision], int(rb), int(nsplit),
                                      ctypes.byref(rbo), ctypes.byref(nso)))
         return rbo.value, nso.value
+
+    def stage5_symmetric(self, on=True, chunk=0):
+        """Symmetric FP64 stage 5 on (True) or off; chunk = row tiles per work item (0 =
+        automatic).  Returns the number of work items (0 when off)."""
+        out = ctypes.c_int32()
+        check(lib().kl_stage5_symmetric(self._h, int(bool(on)), int(chunk), ctypes.byref(out)))
+        return out.value
 
     def apply_config(self, fuse_directions=True):
         """Fused (True) or per-direction (False) Kronecker launches; returns whether a

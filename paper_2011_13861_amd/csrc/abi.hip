@@ -55,6 +55,9 @@ void free_problem(kl_problem *P) {
     hipFree(P->ws.Y5b);
     hipFree(P->ws.Z5);
     hipFree(P->ws.Zf);
+    hipFree(P->ws.symF);
+    hipFree(P->ws.symO);
+    hipFree(P->ws.symTab);
     delete P;
 }
 
@@ -127,6 +130,15 @@ int64_t max_intermediate(const HostSetup &hs) {
 int timed_stage5(kl_problem *P, const Workspace &ws, int precision, const void *Y5, const double *wrow,
                  double scale, hipStream_t s, bool defer_reduce = false) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
+    if (precision == KL_F64 && P->s5_sym && ws.symF) {
+        launch_stage5_sym(P, ws, Y5, wrow, scale, s, rec ? P->prof_ev[P->prof_used] : nullptr,
+                          rec ? P->prof_ev[P->prof_used + 1] : nullptr);
+        if (rec) {
+            P->prof_prec.push_back(precision);
+            P->prof_used += 2;
+        }
+        return 1;
+    }
     const int nsplit = launch_stage5(P, precision, Y5, ws.Z5, ws.Zf, wrow, scale, s,
                                      rec ? P->prof_ev[P->prof_used] : nullptr,
                                      rec ? P->prof_ev[P->prof_used + 1] : nullptr, defer_reduce, ws.max_split);
@@ -701,6 +713,57 @@ kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t
                                  P->s5_split[precision], &lchunk);
     if (rb_out) *rb_out = precision == KL_F64 ? 4 : rbe;
     if (nsplit_out) *nsplit_out = ns;
+    return KL_OK;
+}
+
+kl_status kl_stage5_symmetric(kl_problem *P, int32_t on, int32_t chunk, int32_t *items_out) {
+    if (!P || P->host_only) { set_error("kl_stage5_symmetric: NULL or host-only handle"); return KL_EINVAL; }
+    if (on != 0 && on != 1) { set_error("kl_stage5_symmetric: on must be 0 or 1"); return KL_EINVAL; }
+    if (chunk < 0 || chunk > (1 << 20)) { set_error("kl_stage5_symmetric: chunk must be >= 0"); return KL_EINVAL; }
+    if (!on) {
+        P->s5_sym = false;
+        if (items_out) *items_out = 0;
+        return KL_OK;
+    }
+    Workspace &ws = P->ws;
+    const SymPlan pl = sym_plan(P->Ntpad, P->n_cu, chunk);
+    if (!ws.symF || pl.chunk != ws.sym_chunk) {
+        hipStream_t s = nullptr;
+        kl_status st = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");   // no launch still reads them
+        if (st != KL_OK) return st;
+        hipFree(ws.symF);
+        hipFree(ws.symO);
+        hipFree(ws.symTab);
+        ws.symF = ws.symO = nullptr;
+        ws.symTab = nullptr;
+        ws.sym_chunk = 0;
+        const size_t tab = pl.items.size() * sizeof(SymItem) + pl.o_first.size() * sizeof(int);
+        std::vector<char> host(tab);
+        std::memcpy(host.data(), pl.items.data(), pl.items.size() * sizeof(SymItem));
+        std::memcpy(host.data() + pl.items.size() * sizeof(SymItem), pl.o_first.data(), pl.o_first.size() * sizeof(int));
+        if ((st = dev_alloc(reinterpret_cast<char **>(&ws.symF), sym_f_bytes(pl), "hipMalloc symmetric partials")) !=
+                KL_OK ||
+            (st = dev_alloc(reinterpret_cast<char **>(&ws.symO), sym_o_bytes(pl), "hipMalloc symmetric partials")) !=
+                KL_OK ||
+            (st = dev_alloc(reinterpret_cast<char **>(&ws.symTab), tab, "hipMalloc symmetric plan")) != KL_OK ||
+            (st = hip_check(hipMemcpyAsync(ws.symTab, host.data(), tab, hipMemcpyHostToDevice, s), "copy plan")) !=
+                KL_OK ||
+            (st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")) != KL_OK) {
+            hipFree(ws.symF);
+            hipFree(ws.symO);
+            hipFree(ws.symTab);
+            ws.symF = ws.symO = nullptr;
+            ws.symTab = nullptr;
+            P->s5_sym = false;
+            return st;
+        }
+        ws.sym_items = pl.n_items;
+        ws.sym_NB = pl.NB;
+        ws.sym_chunk = pl.chunk;
+        ws.sym_grid = std::min(pl.n_items, P->n_cu);
+    }
+    P->s5_sym = true;
+    if (items_out) *items_out = ws.sym_items;
     return KL_OK;
 }
 

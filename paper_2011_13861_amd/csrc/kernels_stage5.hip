@@ -555,6 +555,235 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
 }
 
 
+// ---- symmetric FP64 stage 5 ---------------------------------------------------------------
+// Gamma is symmetric, so one kernel value serves two products: z_r += Gamma(x_r, x_c) y_c and
+// z_c += Gamma(x_r, x_c) y_r.  The points are cut into 256-point column blocks J and 64-point
+// row tiles t; a work item is column block J with a run [t0, t1) of the row tiles t < 4 J + 4
+// (the tiles of the blocks at or below J).  Wave w of the workgroup owns the 64 columns
+// 256 J + 64 w + [0, 64): for every row tile it evaluates the 64 x 64 kernel values once and
+// contracts them twice on the FP64 matrix cores:
+//   * transposed: O += G^T Y_t into the wave's own accumulators (64 columns x kBW), kept
+//     over the whole item and stored once as the item's owned partial;
+//   * forward (tiles below the diagonal block only): F = G Y_J (64 rows x kBW), added over
+//     the four waves in LDS (wave order) and stored as the partial of slot (t, J).
+// The diagonal block (t >= 4 J) takes the transposed product only: over its four row tiles
+// it adds every l of block J to the owned columns.  sym_reduce_kernel then adds, per row, the
+// owned partials of its block (item order) and the forward partials of the blocks above it
+// (block order): every sum is taken in a fixed order.
+//
+// Lane layouts (v_mfma_f64_16x16x4f64, A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+// D[(lane >> 4) + 4 r][lane & 15]): lane (i, k) evaluates G[row 16 p + 4 m + k][col 16 q + i]
+// for m < 4, which is the A operand of the transposed product as it stands; the forward
+// product needs G[row 16 p + i][col 16 q + 4 m + k], which the wave reads back from a
+// 16 x 16 tile it has just written to LDS.
+constexpr int kSymCols = 256;                         // columns of a block (4 waves x 64)
+constexpr int kSymTile = 64;                          // rows of a row tile
+constexpr int kSymYt = kSymTile * (kBW + 1);          // LDS: Y of the row tile [row][kBW + 1]
+constexpr int kSymTr = 16 * 17;                       // LDS: a wave's transposition tile
+constexpr int kSymRed = kWaves * kSymTile * (kBW + 1);    // LDS: forward partials [wave][row][kBW + 1]
+constexpr int kSymStage = 3 * kSymTile + kSymYt + kWaves * kSymTr;   // points, block rows, transposition
+constexpr size_t kLdsSym = size_t(kSymRed + kSymStage) * sizeof(double);
+
+template <int KIND, int D>
+__global__ __launch_bounds__(kThreads) void stage5_f64_sym_kernel(
+    const double *__restrict__ X, const double *__restrict__ Y, int64_t Ntpad,
+    const SymItem *__restrict__ items, int n_items, double *__restrict__ Fp, double *__restrict__ Op) {
+    extern __shared__ double sm64[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = lane & 15, k = lane >> 4;
+    double *sXt = sm64;                                   // [D][64]
+    double *sYt = sm64 + D * kSymTile;                    // [64 rows][kBW + 1]
+    double *tr = sYt + kSymYt + wave * kSymTr;            // this wave's [16][17]
+    double *red = sm64 + kSymStage;                       // [wave][64 rows][kBW + 1]
+    const int G = gridDim.x, g = blockIdx.x;
+    // items longest first, dealt to the workgroups in snake order
+    for (int round = 0;; ++round) {
+        const int idx = round * G + ((round & 1) ? G - 1 - g : g);
+        if (idx >= n_items) break;
+        const SymItem I = items[idx];
+        const int64_t c0 = int64_t(I.J) * kSymCols + wave * 64;     // this wave's first column
+        // owned columns: the lane's column 16 q + i, and the forward B operands
+        // Y[vec 16 h + i][col 16 q + 4 m + k]
+        double xc[4][D];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int d = 0; d < D; ++d) xc[q][d] = X[d * Ntpad + c0 + 16 * q + i];
+        double yb[4][4][2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) yb[q][m][h] = Y[int64_t(16 * h + i) * Ntpad + c0 + 16 * q + 4 * m + k];
+        doublex4 O[4][2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { O[q][0][r] = 0.0; O[q][1][r] = 0.0; }
+        // the row tile's points and block rows, prefetched one tile ahead into registers:
+        // thread e < 64 holds the point 64 t + e, and every thread 4 pairs of rows of the
+        // block (e = tid + 256 u: vector e >> 5, rows 2 (e & 31) and the next)
+        double px[D];
+        double2 py[4];
+        auto prefetch = [&](int tt) {
+            const int64_t rr0 = int64_t(tt) * kSymTile;
+#pragma unroll
+            for (int d = 0; d < D; ++d) px[d] = threadIdx.x < kSymTile ? X[d * Ntpad + rr0 + threadIdx.x] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = threadIdx.x + u * kThreads;
+                py[u] = *reinterpret_cast<const double2 *>(Y + int64_t(e >> 5) * Ntpad + rr0 + 2 * (e & 31));
+            }
+        };
+        prefetch(I.t0);
+        for (int t = I.t0; t < I.t1; ++t) {
+            const bool diag = t >= 4 * I.J;
+            // after an off-diagonal tile the barrier before its reduction already ordered
+            // every read of the staging area before these writes
+            if (t == I.t0 || t - 1 >= 4 * I.J) __syncthreads();
+            if (threadIdx.x < kSymTile)
+#pragma unroll
+                for (int d = 0; d < D; ++d) sXt[d * kSymTile + threadIdx.x] = px[d];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = threadIdx.x + u * kThreads;
+                const int vec = e >> 5, rr = 2 * (e & 31);
+                sYt[rr * (kBW + 1) + vec] = py[u].x;
+                sYt[(rr + 1) * (kBW + 1) + vec] = py[u].y;
+            }
+            __syncthreads();
+            if (t + 1 < I.t1) prefetch(t + 1);               // lands while this tile computes
+            doublex4 F[4][2];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { F[p][0][r] = 0.0; F[p][1][r] = 0.0; }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                double xr[4][D], yr[4][2];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) xr[m][d] = sXt[d * kSymTile + 16 * p + 4 * m + k];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) yr[m][h] = sYt[(16 * p + 4 * m + k) * (kBW + 1) + 16 * h + i];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double gv[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) gv[m] = gamma_f64<KIND, D>(xr[m], xc[q]);
+                    if (!diag) {
+                        // transpose through LDS first, so that the round trip overlaps the
+                        // transposed products; then both products interleaved (four chains)
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) tr[(4 * m + k) * 17 + i] = gv[m];
+                        __builtin_amdgcn_wave_barrier();
+                        double gt[4];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) gt[m] = tr[i * 17 + 4 * m + k];
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            O[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[m], yr[m][0], O[q][0], 0, 0, 0);
+                            F[p][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(gt[m], yb[q][m][0], F[p][0], 0, 0, 0);
+                            O[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[m], yr[m][1], O[q][1], 0, 0, 0);
+                            F[p][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(gt[m], yb[q][m][1], F[p][1], 0, 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            O[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[m], yr[m][0], O[q][0], 0, 0, 0);
+                            O[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[m], yr[m][1], O[q][1], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            if (!diag) {
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            red[(wave * kSymTile + 16 * p + k + 4 * r) * (kBW + 1) + 16 * h + i] = F[p][h][r];
+                __syncthreads();
+                double *dst = Fp + (int64_t(2) * I.J * (I.J - 1) + t) * (kSymTile * kBW);
+#pragma unroll
+                for (int u = 0; u < (kSymTile * kBW) / kThreads; ++u) {
+                    const int e = threadIdx.x + u * kThreads;
+                    const int row = e >> 5, vec = e & 31;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) acc += red[(w * kSymTile + row) * (kBW + 1) + vec];
+                    dst[e] = acc;                             // [row][vec]
+                }
+            }
+        }
+        // the owned partial of the item, [column of the block][vec]
+        double *dst = Op + int64_t(I.oslot) * (kSymCols * kBW);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    dst[(wave * 64 + 16 * q + k + 4 * r) * kBW + 16 * h + i] = O[q][h][r];
+    }
+}
+
+// Row tile t of block J = t / 4: z = sum of the owned partials of J's items (item slots
+// o_first[J] .. o_first[J + 1] - 1, in order) and of the forward partials (t, J') for
+// J' = J + 1 .. NB - 1 (in order); Zf[vec][row] = z scale wrow[row] (z without wrow).
+__global__ __launch_bounds__(kThreads) void sym_reduce_kernel(const double *__restrict__ Fp,
+                                                              const double *__restrict__ Op,
+                                                              const int *__restrict__ o_first, int NB,
+                                                              int64_t Ntpad, const double *__restrict__ wrow,
+                                                              double scale, double *__restrict__ Zf) {
+    constexpr int kPer = (kSymTile * kBW) / kThreads;
+    __shared__ double sm[kBW][kSymTile + 1];
+    const int t = blockIdx.x, J = t >> 2, rt = t & 3;
+    double acc[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) acc[u] = 0.0;
+    for (int o = o_first[J]; o < o_first[J + 1]; ++o) {
+        const double *src = Op + int64_t(o) * (kSymCols * kBW) + rt * (kSymTile * kBW);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) acc[u] += src[threadIdx.x + u * kThreads];
+    }
+    int J2 = J + 1;
+    for (; J2 + 1 < NB; J2 += 2) {                       // two slots' loads in flight
+        const double *a = Fp + (int64_t(2) * J2 * (J2 - 1) + t) * (kSymTile * kBW);
+        const double *b = Fp + (int64_t(2) * (J2 + 1) * J2 + t) * (kSymTile * kBW);
+        double va[kPer], vb[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) { va[u] = a[threadIdx.x + u * kThreads]; vb[u] = b[threadIdx.x + u * kThreads]; }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) acc[u] = (acc[u] + va[u]) + vb[u];
+    }
+    if (J2 < NB) {
+        const double *a = Fp + (int64_t(2) * J2 * (J2 - 1) + t) * (kSymTile * kBW);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) acc[u] += a[threadIdx.x + u * kThreads];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        sm[e & 31][e >> 5] = acc[u];
+    }
+    __syncthreads();
+    const int64_t row0 = int64_t(t) * kSymTile;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        const int vec = e >> 6, row = e & 63;
+        double v = sm[vec][row];
+        if (wrow) v = v * scale * wrow[row0 + row];
+        Zf[int64_t(vec) * Ntpad + row0 + row] = v;
+    }
+}
+
 // ---- batched form: many problems, one persistent launch ------------------------------
 // The grid holds as many workgroups as fit on the chip at once; each repeatedly takes
 // the next (problem, row tile, split) item from a queue (a device counter) and runs the
@@ -791,6 +1020,71 @@ int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, 
                                P->Ntpad * kBW, P->Ntpad, wrow, scale);
     }
     return nsplit;
+}
+
+// ---- symmetric FP64 stage 5: plan and launch ---------------------------------------------
+SymPlan sym_plan(int64_t Ntpad, int n_cu, int chunk) {
+    SymPlan pl;
+    pl.NB = int(Ntpad / kSymCols);
+    const int64_t tiles = int64_t(2) * pl.NB * (pl.NB + 1);      // sum over J of 4 (J + 1)
+    // about three items per compute unit unless forced
+    pl.chunk = chunk > 0 ? chunk : int(std::max<int64_t>(1, (tiles + 3 * n_cu - 1) / (3 * int64_t(n_cu))));
+    pl.o_first.assign(size_t(pl.NB) + 1, 0);
+    int oslot = 0;
+    for (int J = 0; J < pl.NB; ++J) {
+        pl.o_first[J] = oslot;
+        const int nt = 4 * (J + 1);
+        for (int t0 = 0; t0 < nt; t0 += pl.chunk) pl.items.push_back(SymItem{J, t0, std::min(nt, t0 + pl.chunk), oslot++});
+    }
+    pl.o_first[pl.NB] = oslot;
+    pl.n_oslots = oslot;
+    pl.n_items = int(pl.items.size());
+    pl.f_slots = int64_t(2) * pl.NB * (pl.NB - 1);
+    std::stable_sort(pl.items.begin(), pl.items.end(),
+                     [](const SymItem &a, const SymItem &b) { return a.t1 - a.t0 > b.t1 - b.t0; });
+    return pl;
+}
+
+size_t sym_f_bytes(const SymPlan &pl) { return size_t(std::max<int64_t>(1, pl.f_slots)) * kSymTile * kBW * sizeof(double); }
+size_t sym_o_bytes(const SymPlan &pl) { return size_t(pl.n_oslots) * kSymCols * kBW * sizeof(double); }
+
+void launch_stage5_sym(const kl_problem *P, const Workspace &ws, const void *Y5, const double *wrow, double scale,
+                       hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+    const SymItem *items = static_cast<const SymItem *>(ws.symTab);
+    const int *o_first = reinterpret_cast<const int *>(items + ws.sym_items);
+    const double *Y = static_cast<const double *>(Y5);
+    double *Zf = static_cast<double *>(ws.Zf);
+    const dim3 grid(unsigned(ws.sym_grid));
+    if (ev_start) (void)hipEventRecord(ev_start, s);
+#define KL_SYM(KIND_, D_)                                                                                    \
+    do {                                                                                                     \
+        static const bool attr_set = [] {                                                                    \
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&stage5_f64_sym_kernel<KIND_, D_>),      \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsSym));             \
+            return true;                                                                                     \
+        }();                                                                                                 \
+        (void)attr_set;                                                                                      \
+        hipLaunchKernelGGL((stage5_f64_sym_kernel<KIND_, D_>), grid, dim3(kThreads), kLdsSym, s, P->dX64, Y, \
+                           P->Ntpad, items, ws.sym_items, ws.symF, ws.symO);                                 \
+    } while (0)
+#define KL_SYM_D(KIND_)                        \
+    switch (P->hs.d) {                         \
+    case 1: KL_SYM(KIND_, 1); break;           \
+    case 2: KL_SYM(KIND_, 2); break;           \
+    default: KL_SYM(KIND_, 3); break;          \
+    }
+    switch (P->cov_kind) {
+    case KL_COV_EXP: KL_SYM_D(KL_COV_EXP); break;
+    case KL_COV_SQEXP: KL_SYM_D(KL_COV_SQEXP); break;
+    case KL_COV_EXP_L1: KL_SYM_D(KL_COV_EXP_L1); break;
+    case KL_COV_CONST: KL_SYM_D(KL_COV_CONST); break;
+    default: KL_SYM_D(KL_COV_LIN); break;
+    }
+#undef KL_SYM_D
+#undef KL_SYM
+    hipLaunchKernelGGL(sym_reduce_kernel, dim3(unsigned(P->Ntpad / kSymTile)), dim3(kThreads), 0, s, ws.symF,
+                       ws.symO, o_first, ws.sym_NB, P->Ntpad, wrow, scale, Zf);
+    if (ev_stop) (void)hipEventRecord(ev_stop, s);
 }
 
 int stage5_batch_grid(int precision, int d, int rb, int n_cu) {

@@ -55,6 +55,24 @@ struct Workspace {
     size_t z5_bytes = 0;
     void *Zf = nullptr;                    // stage-5 output (column-major, ld Ntpad)
     int max_split = 1;
+    // symmetric FP64 stage 5 (allocated by kl_stage5_symmetric): forward partials per (row
+    // tile, column block), owned partials per work item, and the plan on the device
+    // (SymItem[sym_items] followed by int o_first[sym_NB + 1])
+    double *symF = nullptr, *symO = nullptr;
+    void *symTab = nullptr;
+    int sym_items = 0, sym_NB = 0, sym_grid = 0, sym_chunk = 0;
+};
+
+// Work item of the symmetric FP64 stage 5: column block J (256 points) against row tiles
+// [t0, t1) (64 points each, t1 <= 4 J + 4); its owned partial goes to slot oslot.
+struct SymItem {
+    int J, t0, t1, oslot;
+};
+struct SymPlan {
+    int NB = 0, chunk = 0, n_items = 0, n_oslots = 0;
+    int64_t f_slots = 0;               // forward partial slots: (t, J) for t < 4 J
+    std::vector<SymItem> items;        // longest first
+    std::vector<int> o_first;          // NB + 1: the owned slots of block J are o_first[J] ..
 };
 
 // Device buffers and stream of the block eigensolver, kept with the
@@ -92,6 +110,7 @@ struct kl_problem {
     int s5_rb[4] = {2, 2, 2, 2};
     bool fuse_dirs = true;                 // first two directions of each side in one launch
     int s5_split[4] = {0, 0, 0, 0};
+    bool s5_sym = false;                   // FP64 stage 5 in its symmetric form (kl_stage5_symmetric)
     // optional stage-5 timing with HIP events (kl_profile_enable / kl_profile_read)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;      // pool: 2 events per timed launch
@@ -225,6 +244,14 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
                   const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start = nullptr,
                   hipEvent_t ev_stop = nullptr, bool defer_reduce = false, int max_split = 0);
+// Symmetric FP64 stage 5 into ws.Zf (same result as launch_stage5 with one split): the plan
+// of a padded grid (chunk = row tiles per item, 0 = automatic), the sizes of its partial
+// buffers, and the launch (covariance kernel and ordered reduction, both inside the events).
+SymPlan sym_plan(int64_t Ntpad, int n_cu, int chunk);
+size_t sym_f_bytes(const SymPlan &pl);
+size_t sym_o_bytes(const SymPlan &pl);
+void launch_stage5_sym(const kl_problem *P, const Workspace &ws, const void *Y5, const double *wrow, double scale,
+                       hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // kl_setup with or without the single-problem apply workspace (T0/T1, stage-5 buffers);
 // problems of a batch use the batch's arenas instead.  Uploads on `s`, then waits for it.
