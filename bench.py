@@ -285,15 +285,18 @@ def batch_section(reps=20):
     return out
 
 
-def stage5_runs(G, kind, prec, x, y, steps, warmup, tune, objective, tiles=None):
+def stage5_runs(G, kind, prec, x, y, steps, warmup, tune, objective, tiles=None, symmetric="auto"):
     """Times `steps` applies of the 32-vector block in one precision (stage-5 tiles tuned or
-    forced); returns (ms per apply, stage-5 launches, stage-5 ms in total, tiles)."""
+    forced; FP64 stage 5 in its symmetric form as tuned, or forced on / off); returns (ms
+    per apply, stage-5 launches, stage-5 ms in total, tiles)."""
     import torch
     if tiles:
         G.stage5_config(prec, rb=tiles[0], nsplit=tiles[1])
     elif tune:
         from paper_2011_13861_amd import autotune
         autotune.tune_problem(G, kind, precisions=(prec,), reps=10, objective=objective)
+    if prec == "f64" and symmetric != "auto":
+        G.stage5_symmetric(symmetric == "on")
     for _ in range(warmup):
         G.apply(x, y, prec)
     torch.cuda.synchronize()
@@ -328,6 +331,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--oracle-eigs", action="store_true",
                     help="also time the oracle's ARPACK eigenpairs on the host cores (about a minute on the 24^3 cube)")
+    ap.add_argument("--symmetric", choices=("auto", "on", "off"), default="auto",
+                    help="FP64 stage 5 in its symmetric form: as the tuner finds faster (auto), or forced")
     ap.add_argument("--mlp-train", type=int, default=2000,
                     help="training solves for the warm-start section (0 = skip the section)")
     ap.add_argument("--mlp-epochs", type=int, default=1000)
@@ -371,7 +376,8 @@ def main():
     tiles = tuple(int(v) for v in args.tiles.split(",")) if args.tiles else None
     t0 = time.perf_counter()
     ms_per_step, cnt, kms, tiles = stage5_runs(G, kind, prec, x, y, args.steps, args.warmup,
-                                               not args.no_tune, args.tune_objective, tiles)
+                                               not args.no_tune, args.tune_objective, tiles, args.symmetric)
+    sym = prec == "f64" and getattr(G, "symmetric", False)
     wall = time.perf_counter() - t0
     pairs = float(G.Nt) ** 2
     value = pairs / (ms_per_step * 1e-3)
@@ -387,6 +393,13 @@ def main():
         per_pair = (3 * d - 1) + 1 + 1 + (1 if kind == "exp" else 0) + 2 * b
         achieved = per_pair * pairs / k_avg_s / 1e12
         bound = "alu"
+        if sym:
+            # symmetric form: every evaluated kernel value serves two pairs; the algorithmic
+            # flops are the evaluations of the 2 NB (NB + 1) 64 x 256 tiles it computes (NB
+            # 256-point blocks of the padded grid) plus the full contraction
+            nb = (G.Nt + 255) // 256
+            evaluated = 2.0 * nb * (nb + 1) * 64 * 256
+            achieved = ((per_pair - 2 * b) * evaluated + 2 * b * pairs) / k_avg_s / 1e12
     else:
         per_pair = 2 * b
         achieved = flops / k_avg_s / 1e12
@@ -398,7 +411,13 @@ def main():
                 "contraction_only_frac": flops / k_avg_s / 1e12 / PEAK_TFLOPS[prec],
                 "kernel": "stage5_%s_kernel" % prec, "kernel_avg_us": k_avg_s * 1e6,
                 "kernel_pairs_per_s": pairs / k_avg_s, "launches": cnt,
-                "stage5_tiles": {"rb": tiles[0], "nsplit": tiles[1]}}
+                "stage5_tiles": {"rb": tiles[0], "nsplit": tiles[1]},
+                "stage5_form": "symmetric" if sym else "plain"}
+    if sym:
+        roofline["kernel"] = "stage5_f64_sym_kernel + sym_reduce_kernel"
+        roofline["evaluated_pairs"] = evaluated
+        roofline["logical_pairs"] = pairs
+        roofline["traffic"] = None
     rates = measured_rates()
 
     # the other stage-5 precisions on the same block (matrix-core and vector-ALU bounds)

@@ -239,6 +239,7 @@ class Problem:
 
     def __init__(self, desc, host_only=False, stream=None):
         self._h = ctypes.c_void_p()
+        self.symmetric = False          # FP64 stage 5 in its symmetric form (stage5_symmetric)
         if isinstance(desc, (list, tuple)):
             if host_only:
                 raise ValueError("several patches need a GPU (no host-only form)")
@@ -350,6 +351,7 @@ class Problem:
         automatic).  Returns the number of work items (0 when off)."""
         out = ctypes.c_int32()
         check(lib().kl_stage5_symmetric(self._h, int(bool(on)), int(chunk), ctypes.byref(out)))
+        self.symmetric = bool(on)
         return out.value
 
     def apply_config(self, fuse_directions=True):

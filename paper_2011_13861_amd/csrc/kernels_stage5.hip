@@ -559,13 +559,15 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
 // Gamma is symmetric, so one kernel value serves two products: z_r += Gamma(x_r, x_c) y_c and
 // z_c += Gamma(x_r, x_c) y_r.  The points are cut into 256-point column blocks J and 64-point
 // row tiles t; a work item is column block J with a run [t0, t1) of the row tiles t < 4 J + 4
-// (the tiles of the blocks at or below J).  Wave w of the workgroup owns the 64 columns
-// 256 J + 64 w + [0, 64): for every row tile it evaluates the 64 x 64 kernel values once and
-// contracts them twice on the FP64 matrix cores:
-//   * transposed: O += G^T Y_t into the wave's own accumulators (64 columns x kBW), kept
-//     over the whole item and stored once as the item's owned partial;
-//   * forward (tiles below the diagonal block only): F = G Y_J (64 rows x kBW), added over
-//     the four waves in LDS (wave order) and stored as the partial of slot (t, J).
+// (the tiles of the blocks at or below J).  The workgroup has 8 waves (two per SIMD): wave
+// (cs, rh) owns the 64 columns 256 J + 64 cs + [0, 64) and rows 32 rh + [0, 32) of every row
+// tile.  It evaluates its 32 x 64 kernel values once and contracts them twice on the FP64
+// matrix cores:
+//   * transposed: O += G^T Y_t into the wave's accumulators (64 columns x kBW), kept over
+//     the item; at its end the two row halves are added (rh order) and stored as the item's
+//     owned partial;
+//   * forward (tiles below the diagonal block only): F = G Y_J (32 rows x kBW), added over
+//     the four column slabs in LDS (slab order) and stored as the partial of slot (t, J).
 // The diagonal block (t >= 4 J) takes the transposed product only: over its four row tiles
 // it adds every l of block J to the owned columns.  sym_reduce_kernel then adds, per row, the
 // owned partials of its block (item order) and the forward partials of the blocks above it
@@ -576,120 +578,140 @@ __global__ __launch_bounds__(kThreads) void stage5_bf16_kernel(
 // for m < 4, which is the A operand of the transposed product as it stands; the forward
 // product needs G[row 16 p + i][col 16 q + 4 m + k], which the wave reads back from a
 // 16 x 16 tile it has just written to LDS.
-constexpr int kSymCols = 256;                         // columns of a block (4 waves x 64)
-constexpr int kSymTile = 64;                          // rows of a row tile
-constexpr int kSymYt = kSymTile * (kBW + 1);          // LDS: Y of the row tile [row][kBW + 1]
-constexpr int kSymTr = 16 * 17;                       // LDS: a wave's transposition tile
-constexpr int kSymRed = kWaves * kSymTile * (kBW + 1);    // LDS: forward partials [wave][row][kBW + 1]
-constexpr int kSymStage = 3 * kSymTile + kSymYt + kWaves * kSymTr;   // points, block rows, transposition
-constexpr size_t kLdsSym = size_t(kSymRed + kSymStage) * sizeof(double);
+constexpr int kSymWaves = 8;
+constexpr int kSymThreads = 64 * kSymWaves;
+constexpr int kSymCols = 256;                         // columns of a block (4 slabs x 64)
+constexpr int kSymTile = 64;                          // rows of a row tile (2 halves x 32)
+constexpr int kSymLd = kBW + 1;                       // LDS row length of the [point][vec] arrays
+constexpr int kSymYJ = kSymCols * kSymLd;             // LDS: Y of the owned block [col][vec]
+constexpr int kSymXt = 3 * kSymTile;                  // LDS: points of the row tile [d][row]
+constexpr int kSymYt = kSymTile * kSymLd;             // LDS: Y of the row tile [row][vec]
+constexpr int kSymRed = 4 * kSymTile * kSymLd;        // LDS: [slab][64][vec] partials; holds the
+constexpr int kSymTr = 16 * 17;                       //      waves' transposition tiles meanwhile
+static_assert(kSymWaves * kSymTr <= kSymRed, "transposition tiles inside the reduction area");
+constexpr int kSymXJ = 3 * kSymCols;                 // LDS: points of the owned block [d][col]
+constexpr size_t kLdsSym = size_t(kSymYJ + kSymXJ + kSymXt + kSymYt + kSymRed) * sizeof(double);
+static_assert(kLdsSym <= 160 * 1024, "LDS of one gfx950 workgroup");
 
 template <int KIND, int D>
-__global__ __launch_bounds__(kThreads) void stage5_f64_sym_kernel(
+__global__ __launch_bounds__(kSymThreads) void stage5_f64_sym_kernel(
     const double *__restrict__ X, const double *__restrict__ Y, int64_t Ntpad,
     const SymItem *__restrict__ items, int n_items, double *__restrict__ Fp, double *__restrict__ Op) {
     extern __shared__ double sm64[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = lane & 15, k = lane >> 4;
-    double *sXt = sm64;                                   // [D][64]
-    double *sYt = sm64 + D * kSymTile;                    // [64 rows][kBW + 1]
-    double *tr = sYt + kSymYt + wave * kSymTr;            // this wave's [16][17]
-    double *red = sm64 + kSymStage;                       // [wave][64 rows][kBW + 1]
+    const int cs = wave & 3, rh = wave >> 2;
+    double *sYJ = sm64;                                   // [256 cols][kSymLd]
+    double *sXJ = sYJ + kSymYJ;                           // [D][256]
+    double *sXt = sXJ + kSymXJ;                           // [D][64]
+    double *sYt = sXt + kSymXt;                           // [64 rows][kSymLd]
+    double *red = sYt + kSymYt;                           // [slab][64][kSymLd]
+    double *tr = red + wave * kSymTr;                     // this wave's [16][17], while computing
     const int G = gridDim.x, g = blockIdx.x;
     // items longest first, dealt to the workgroups in snake order
     for (int round = 0;; ++round) {
         const int idx = round * G + ((round & 1) ? G - 1 - g : g);
         if (idx >= n_items) break;
         const SymItem I = items[idx];
-        const int64_t c0 = int64_t(I.J) * kSymCols + wave * 64;     // this wave's first column
-        // owned columns: the lane's column 16 q + i, and the forward B operands
-        // Y[vec 16 h + i][col 16 q + 4 m + k]
-        double xc[4][D];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int d = 0; d < D; ++d) xc[q][d] = X[d * Ntpad + c0 + 16 * q + i];
-        double yb[4][4][2];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) yb[q][m][h] = Y[int64_t(16 * h + i) * Ntpad + c0 + 16 * q + 4 * m + k];
-        doublex4 O[4][2];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) { O[q][0][r] = 0.0; O[q][1][r] = 0.0; }
-        // the row tile's points and block rows, prefetched one tile ahead into registers:
-        // thread e < 64 holds the point 64 t + e, and every thread 4 pairs of rows of the
-        // block (e = tid + 256 u: vector e >> 5, rows 2 (e & 31) and the next)
+        const int64_t cb = int64_t(I.J) * kSymCols;                  // the block's first column
+        // the row tile's points and block rows, prefetched one tile ahead: thread e < 64
+        // holds the point 64 t + e, every thread 2 pairs of rows (e = tid + 512 u: vector
+        // e >> 5, rows 2 (e & 31) and the next)
         double px[D];
-        double2 py[4];
+        double2 py[2];
         auto prefetch = [&](int tt) {
             const int64_t rr0 = int64_t(tt) * kSymTile;
 #pragma unroll
             for (int d = 0; d < D; ++d) px[d] = threadIdx.x < kSymTile ? X[d * Ntpad + rr0 + threadIdx.x] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = threadIdx.x + u * kThreads;
+            for (int u = 0; u < 2; ++u) {
+                const int e = threadIdx.x + u * kSymThreads;
                 py[u] = *reinterpret_cast<const double2 *>(Y + int64_t(e >> 5) * Ntpad + rr0 + 2 * (e & 31));
             }
         };
         prefetch(I.t0);
+        // the owned block's rows of Y, [col][vec] (e = tid + 512 u: vector e >> 7, columns
+        // 2 (e & 127) and the next); every wave is past the previous item's last reads
+        __syncthreads();
+        if (threadIdx.x < kSymCols)
+#pragma unroll
+            for (int d = 0; d < D; ++d) sXJ[d * kSymCols + threadIdx.x] = X[d * Ntpad + cb + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = threadIdx.x + u * kSymThreads;
+            const int vec = e >> 7, cc = 2 * (e & 127);
+            const double2 v = *reinterpret_cast<const double2 *>(Y + int64_t(vec) * Ntpad + cb + cc);
+            sYJ[cc * kSymLd + vec] = v.x;
+            sYJ[(cc + 1) * kSymLd + vec] = v.y;
+        }
+        doublex4 O[4][2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { O[q][0][r] = 0.0; O[q][1][r] = 0.0; }
         for (int t = I.t0; t < I.t1; ++t) {
             const bool diag = t >= 4 * I.J;
-            // after an off-diagonal tile the barrier before its reduction already ordered
+            // after an off-diagonal tile the barriers around its reduction already ordered
             // every read of the staging area before these writes
-            if (t == I.t0 || t - 1 >= 4 * I.J) __syncthreads();
+            if (t > I.t0 && t - 1 >= 4 * I.J) __syncthreads();
             if (threadIdx.x < kSymTile)
 #pragma unroll
                 for (int d = 0; d < D; ++d) sXt[d * kSymTile + threadIdx.x] = px[d];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = threadIdx.x + u * kThreads;
+            for (int u = 0; u < 2; ++u) {
+                const int e = threadIdx.x + u * kSymThreads;
                 const int vec = e >> 5, rr = 2 * (e & 31);
-                sYt[rr * (kBW + 1) + vec] = py[u].x;
-                sYt[(rr + 1) * (kBW + 1) + vec] = py[u].y;
+                sYt[rr * kSymLd + vec] = py[u].x;
+                sYt[(rr + 1) * kSymLd + vec] = py[u].y;
             }
             __syncthreads();
             if (t + 1 < I.t1) prefetch(t + 1);               // lands while this tile computes
-            doublex4 F[4][2];
+            doublex4 F[2][2];
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+            for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) { F[p][0][r] = 0.0; F[p][1][r] = 0.0; }
+                for (int r = 0; r < 4; ++r) { F[pp][0][r] = 0.0; F[pp][1][r] = 0.0; }
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                double xr[4][D], yr[4][2];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d) xr[m][d] = sXt[d * kSymTile + 16 * p + 4 * m + k];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) yr[m][h] = sYt[(16 * p + 4 * m + k) * (kBW + 1) + 16 * h + i];
-                }
+            for (int pp = 0; pp < 2; ++pp) {
+                const int p = 2 * rh + pp;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    double gv[4];
+                    // operands read from LDS per (p, q): few registers stay live across it
+                    double xr[4][D], yr[4][2], xc[D], gv[4];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) gv[m] = gamma_f64<KIND, D>(xr[m], xc[q]);
+                    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+                        for (int d = 0; d < D; ++d) xr[m][d] = sXt[d * kSymTile + 16 * p + 4 * m + k];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) yr[m][h] = sYt[(16 * p + 4 * m + k) * kSymLd + 16 * h + i];
+                    }
+#pragma unroll
+                    for (int d = 0; d < D; ++d) xc[d] = sXJ[d * kSymCols + 64 * cs + 16 * q + i];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) gv[m] = gamma_f64<KIND, D>(xr[m], xc);
                     if (!diag) {
                         // transpose through LDS first, so that the round trip overlaps the
-                        // transposed products; then both products interleaved (four chains)
+                        // transposed products
 #pragma unroll
                         for (int m = 0; m < 4; ++m) tr[(4 * m + k) * 17 + i] = gv[m];
                         __builtin_amdgcn_wave_barrier();
-                        double gt[4];
+                        double gt[4], yb[4][2];
 #pragma unroll
-                        for (int m = 0; m < 4; ++m) gt[m] = tr[i * 17 + 4 * m + k];
+                        for (int m = 0; m < 4; ++m) {
+                            gt[m] = tr[i * 17 + 4 * m + k];
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) yb[m][h] = sYJ[(64 * cs + 16 * q + 4 * m + k) * kSymLd + 16 * h + i];
+                        }
                         __builtin_amdgcn_wave_barrier();
 #pragma unroll
                         for (int m = 0; m < 4; ++m) {
                             O[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[m], yr[m][0], O[q][0], 0, 0, 0);
-                            F[p][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(gt[m], yb[q][m][0], F[p][0], 0, 0, 0);
                             O[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[m], yr[m][1], O[q][1], 0, 0, 0);
-                            F[p][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(gt[m], yb[q][m][1], F[p][1], 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            F[pp][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(gt[m], yb[m][0], F[pp][0], 0, 0, 0);
+                            F[pp][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(gt[m], yb[m][1], F[pp][1], 0, 0, 0);
                         }
                     } else {
 #pragma unroll
@@ -701,35 +723,50 @@ __global__ __launch_bounds__(kThreads) void stage5_f64_sym_kernel(
                 }
             }
             if (!diag) {
+                __syncthreads();                              // every wave done with its tile
 #pragma unroll
-                for (int p = 0; p < 4; ++p)
+                for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
                     for (int h = 0; h < 2; ++h)
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            red[(wave * kSymTile + 16 * p + k + 4 * r) * (kBW + 1) + 16 * h + i] = F[p][h][r];
+                            red[(cs * kSymTile + 16 * (2 * rh + pp) + k + 4 * r) * kSymLd + 16 * h + i] = F[pp][h][r];
                 __syncthreads();
                 double *dst = Fp + (int64_t(2) * I.J * (I.J - 1) + t) * (kSymTile * kBW);
 #pragma unroll
-                for (int u = 0; u < (kSymTile * kBW) / kThreads; ++u) {
-                    const int e = threadIdx.x + u * kThreads;
+                for (int u = 0; u < (kSymTile * kBW) / kSymThreads; ++u) {
+                    const int e = threadIdx.x + u * kSymThreads;
                     const int row = e >> 5, vec = e & 31;
                     double acc = 0.0;
 #pragma unroll
-                    for (int w = 0; w < kWaves; ++w) acc += red[(w * kSymTile + row) * (kBW + 1) + vec];
+                    for (int w = 0; w < 4; ++w) acc += red[(w * kSymTile + row) * kSymLd + vec];
                     dst[e] = acc;                             // [row][vec]
                 }
             }
         }
-        // the owned partial of the item, [column of the block][vec]
-        double *dst = Op + int64_t(I.oslot) * (kSymCols * kBW);
+        // the owned partial of the item, [column of the block][vec]: row half 0 plus row half 1
+        __syncthreads();
+        if (rh == 1)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    dst[(wave * 64 + 16 * q + k + 4 * r) * kBW + 16 * h + i] = O[q][h][r];
+                    for (int r = 0; r < 4; ++r)
+                        red[(cs * 64 + 16 * q + k + 4 * r) * kSymLd + 16 * h + i] = O[q][h][r];
+        __syncthreads();
+        if (rh == 0) {
+            double *dst = Op + int64_t(I.oslot) * (kSymCols * kBW);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int col = 16 * q + k + 4 * r;
+                        dst[(cs * 64 + col) * kBW + 16 * h + i] = O[q][h][r] + red[(cs * 64 + col) * kSymLd + 16 * h + i];
+                    }
+        }
     }
 }
 
@@ -1064,7 +1101,7 @@ void launch_stage5_sym(const kl_problem *P, const Workspace &ws, const void *Y5,
             return true;                                                                                     \
         }();                                                                                                 \
         (void)attr_set;                                                                                      \
-        hipLaunchKernelGGL((stage5_f64_sym_kernel<KIND_, D_>), grid, dim3(kThreads), kLdsSym, s, P->dX64, Y, \
+        hipLaunchKernelGGL((stage5_f64_sym_kernel<KIND_, D_>), grid, dim3(kSymThreads), kLdsSym, s, P->dX64, Y, \
                            P->Ntpad, items, ws.sym_items, ws.symF, ws.symO);                                 \
     } while (0)
 #define KL_SYM_D(KIND_)                        \
