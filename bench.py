@@ -26,10 +26,13 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 # vector-ALU lane operations per second: 256 compute units x 64 lanes x 2.4 GHz
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 # HBM bytes per stage-5 launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a
-# plain 256 MiB copy), keyed by (workload, precision, rb, nsplit); see
-# profiles/stage5_f64_cube24_hbm_traffic.md and profiles/stage5_f32_annulus64_hbm_traffic.md.  Only
-# reported for the setting it was measured on.
-MEASURED_TRAFFIC = {("cube24", "f64", 4, 10): 82957 * 1024, ("annulus64", "f32", 8, 6): 8438 * 1024}
+# plain 256 MiB copy), keyed by (workload, precision, rb, nsplit), or (workload, "f64",
+# "symmetric") for the symmetric FP64 form with its automatic work split (covariance kernel
+# and ordered reduction); see profiles/stage5_f64_cube24_hbm_traffic.md,
+# profiles/stage5_f64sym_cube24_hbm_traffic.md and profiles/stage5_f32_annulus64_hbm_traffic.md.
+# Only reported for the setting it was measured on.
+MEASURED_TRAFFIC = {("cube24", "f64", 4, 10): 82960 * 1024, ("annulus64", "f32", 8, 6): 8434 * 1024,
+                    ("cube24", "f64", "symmetric"): 517741 * 1024}
 WORKLOADS = {
     "annulus64": ("2D quarter annulus (r in [1,2], NURBS map) 64x64 cubic, Ntilde = N = 4489, "
                   "squared exponential L = 0.5, k = 40"),
@@ -211,7 +214,7 @@ def warm_start_section(n_train, epochs, n_eval, solves=3, subspace=3.0):
             "f64_warm_speedup_vs_f64": med["f64"] / med["f64_warm"]}
 
 
-def batch_section(reps=20):
+def batch_section(reps=20, eigs=True):
     """Batch section: 64 uneven 2D problems (seed 1127).  The batched apply (one graph replay
     of 32 columns per problem, autotuned tiles) against the same 64 applies issued one
     problem after the other; then 20 eigenpairs of every problem at 1e-6, batched
@@ -259,6 +262,8 @@ def batch_section(reps=20):
         t_s = e0.elapsed_time(e1) / max(1, reps // 4) * 1e-3
         out["apply_" + prec] = {"batched_ms": t_b * 1e3, "pair_evals_per_s": pairs / t_b, "rb": rb, "lchunk": lc,
                                 "sequential_ms": t_s * 1e3, "speedup": t_s / t_b}
+    if not eigs:
+        return out
     B.eigs(20, precision="f32", block=32, tol=1e-6)          # warm (solver buffers, handles)
     t_ebs = []                                               # host-thread bound: median of three
     for _ in range(3):
@@ -340,6 +345,8 @@ def main():
                     help="weight of the subspace term of the warm-start loss (0 = per-eigenvector term only)")
     ap.add_argument("--mlp-eval", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch section")
+    ap.add_argument("--no-batch-eigs", action="store_true",
+                    help="in the batch section, time the batched applies only (no eigensolves)")
     ap.add_argument("--no-tune", action="store_true", help="keep the automatic stage-5 split")
     ap.add_argument("--tune-objective", default="apply", choices=["apply", "stage5"],
                     help="what the stage-5 tile search minimises: the whole apply (default) or the kernel alone")
@@ -417,7 +424,7 @@ def main():
         roofline["kernel"] = "stage5_f64_sym_kernel + sym_reduce_kernel"
         roofline["evaluated_pairs"] = evaluated
         roofline["logical_pairs"] = pairs
-        roofline["traffic"] = None
+        roofline["traffic"] = MEASURED_TRAFFIC.get((args.workload, "f64", "symmetric"))
     rates = measured_rates()
 
     # the other stage-5 precisions on the same block (matrix-core and vector-ALU bounds)
@@ -495,7 +502,7 @@ def main():
         "kle_field": kle_out,
     }
     if not args.no_batch:
-        out["batch"] = batch_section()
+        out["batch"] = batch_section(eigs=not args.no_batch_eigs)
     if args.mlp_train > 0:
         out["warm_start"] = warm_start_section(args.mlp_train, args.mlp_epochs, args.mlp_eval,
                                                subspace=args.mlp_subspace)
