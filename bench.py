@@ -27,7 +27,7 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 # HBM bytes per stage-5 launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a
 # plain 256 MiB copy), keyed by (workload, precision, rb, nsplit), or (workload, "f64",
-# "symmetric") for the symmetric FP64 form with its automatic work split (covariance kernel
+# "symmetric") for the symmetric form with its automatic work split (covariance kernel
 # and ordered reduction); see profiles/stage5_f64_cube24_hbm_traffic.md,
 # profiles/stage5_f64sym_cube24_hbm_traffic.md and profiles/stage5_f32_annulus64_hbm_traffic.md.
 # Only reported for the setting it was measured on.
@@ -300,8 +300,8 @@ def stage5_runs(G, kind, prec, x, y, steps, warmup, tune, objective, tiles=None,
     elif tune:
         from paper_2011_13861_amd import autotune
         autotune.tune_problem(G, kind, precisions=(prec,), reps=10, objective=objective)
-    if prec == "f64" and symmetric != "auto":
-        G.stage5_symmetric(symmetric == "on")
+    if prec in ("f64", "bf16", "bf16x3") and symmetric != "auto":
+        G.stage5_symmetric(symmetric == "on", precision=prec)
     for _ in range(warmup):
         G.apply(x, y, prec)
     torch.cuda.synchronize()
@@ -337,7 +337,8 @@ def main():
     ap.add_argument("--oracle-eigs", action="store_true",
                     help="also time the oracle's ARPACK eigenpairs on the host cores (about a minute on the 24^3 cube)")
     ap.add_argument("--symmetric", choices=("auto", "on", "off"), default="auto",
-                    help="FP64 stage 5 in its symmetric form: as the tuner finds faster (auto), or forced")
+                    help="stage 5 of the headline precision (FP64, BF16, BF16x3) in its symmetric form: "
+                         "as the tuner finds faster (auto), or forced")
     ap.add_argument("--mlp-train", type=int, default=2000,
                     help="training solves for the warm-start section (0 = skip the section)")
     ap.add_argument("--mlp-epochs", type=int, default=1000)
@@ -384,7 +385,11 @@ def main():
     t0 = time.perf_counter()
     ms_per_step, cnt, kms, tiles = stage5_runs(G, kind, prec, x, y, args.steps, args.warmup,
                                                not args.no_tune, args.tune_objective, tiles, args.symmetric)
-    sym = prec == "f64" and getattr(G, "symmetric", False)
+    sym = prec in G.symmetric
+    # kernel values the symmetric form evaluates per launch: the 2 NB (NB + 1) tiles of 64 x
+    # 256 (NB 256-point blocks of the padded grid) at or below the diagonal blocks
+    nb = (G.Nt + 255) // 256
+    evaluated = 2.0 * nb * (nb + 1) * 64 * 256
     wall = time.perf_counter() - t0
     pairs = float(G.Nt) ** 2
     value = pairs / (ms_per_step * 1e-3)
@@ -402,10 +407,7 @@ def main():
         bound = "alu"
         if sym:
             # symmetric form: every evaluated kernel value serves two pairs; the algorithmic
-            # flops are the evaluations of the 2 NB (NB + 1) 64 x 256 tiles it computes (NB
-            # 256-point blocks of the padded grid) plus the full contraction
-            nb = (G.Nt + 255) // 256
-            evaluated = 2.0 * nb * (nb + 1) * 64 * 256
+            # flops are those of the evaluated values plus the full contraction
             achieved = ((per_pair - 2 * b) * evaluated + 2 * b * pairs) / k_avg_s / 1e12
     else:
         per_pair = 2 * b
@@ -421,10 +423,10 @@ def main():
                 "stage5_tiles": {"rb": tiles[0], "nsplit": tiles[1]},
                 "stage5_form": "symmetric" if sym else "plain"}
     if sym:
-        roofline["kernel"] = "stage5_f64_sym_kernel + sym_reduce_kernel"
+        roofline["kernel"] = "stage5_%s_sym_kernel + sym_reduce_kernel" % ("f64" if prec == "f64" else "bf16")
         roofline["evaluated_pairs"] = evaluated
         roofline["logical_pairs"] = pairs
-        roofline["traffic"] = MEASURED_TRAFFIC.get((args.workload, "f64", "symmetric"))
+        roofline["traffic"] = MEASURED_TRAFFIC.get((args.workload, prec, "symmetric"))
     rates = measured_rates()
 
     # the other stage-5 precisions on the same block (matrix-core and vector-ALU bounds)
@@ -436,12 +438,15 @@ def main():
         ach = flops / ks / 1e12
         rec = {"apply_ms": ms_p, "apply_pair_evals_per_s": pairs / (ms_p * 1e-3), "kernel_avg_us": ks * 1e6,
                "kernel_pairs_per_s": pairs / ks, "mfma_achieved_TFLOPs": ach,
-               "mfma_frac": ach / PEAK_TFLOPS[p], "stage5_tiles": {"rb": tiles_p[0], "nsplit": tiles_p[1]}}
+               "mfma_frac": ach / PEAK_TFLOPS[p], "stage5_tiles": {"rb": tiles_p[0], "nsplit": tiles_p[1]},
+               "stage5_form": "symmetric" if p in G.symmetric else "plain"}
         if rates is not None:
+            # the vector-ALU bound counts the kernel values the form evaluates
             slots, c_exp, c_sqrt = valu_slots_per_pair(kind, desc["dim"], p, rates)
-            rec["valu_bound"] = {"slots_per_pair": slots, "exp_cost_fma": c_exp, "sqrt_cost_fma": c_sqrt,
-                                 "peak_pairs_per_s": VALU_LANE_OPS / slots,
-                                 "frac": (pairs / ks) / (VALU_LANE_OPS / slots)}
+            values = evaluated if p in G.symmetric else pairs
+            rec["valu_bound"] = {"slots_per_value": slots, "exp_cost_fma": c_exp, "sqrt_cost_fma": c_sqrt,
+                                 "evaluated_values": values, "peak_values_per_s": VALU_LANE_OPS / slots,
+                                 "frac": (values / ks) / (VALU_LANE_OPS / slots)}
         others[p] = rec
 
     # time to k eigenpairs at relative residual 1e-6 (criterion under the FP64 operator)

@@ -221,20 +221,21 @@ kl_status kl_apply_config(kl_problem *P, int32_t fuse_directions, int32_t *fused
 kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t nsplit,
                            int32_t *rb_out, int32_t *nsplit_out);
 
-/* Symmetric FP64 stage 5 (Sec. 7 names exploiting the symmetry of the covariance as
- * further work).  Gamma(x, x') = Gamma(x', x), so each kernel value of a pair of point
- * blocks below the diagonal serves both products z_r += Gamma y_c and z_c += Gamma y_r:
- * about half the kernel evaluations of the plain kernel for the same matrix products.
- * The partial sums of the two sides are added in a fixed order (deterministic results;
- * rounding differs from the plain kernel's).  on = 1 selects the form for the FP64 applies
- * of this handle (kl_apply, kl_stage5, kl_eigs) and allocates its buffers (about
- * Ntpad^2 / 16 doubles of partial sums, Ntpad = Ntilde rounded up to 256; this call
- * synchronises the device when it (re)allocates); on = 0 returns to the plain kernel and
- * keeps the buffers until kl_destroy.  chunk = 64-point row tiles per work item (0 =
- * automatic, about three items per compute unit); items_out (may be NULL) receives the
- * number of work items.  kl_apply_noalloc always uses the plain kernel.
- * Errors: KL_EINVAL, KL_ENOMEM. */
-kl_status kl_stage5_symmetric(kl_problem *P, int32_t on, int32_t chunk, int32_t *items_out);
+/* Symmetric stage 5 (Sec. 7 names exploiting the symmetry of the covariance as further
+ * work).  Gamma(x, x') = Gamma(x', x), so each kernel value of a pair of point blocks below
+ * the diagonal serves both products z_r += Gamma y_c and z_c += Gamma y_r: about half the
+ * kernel evaluations of the plain kernel for the same matrix products.  The partial sums of
+ * the two sides (FP64 for KL_F64, FP32 for KL_BF16 / KL_BF16X3) are added in a fixed order
+ * (deterministic results; rounding differs from the plain kernel's).  precision = KL_F64,
+ * KL_BF16 or KL_BF16X3 (KL_EINVAL otherwise); on = 1 selects the form for that precision's
+ * applies of this handle (kl_apply, kl_stage5, kl_eigs) and allocates the buffers, shared
+ * by the precisions (about Ntpad^2 / 16 doubles of partial sums, Ntpad = Ntilde rounded up to
+ * 256; this call synchronises the device when it (re)allocates); on = 0 returns that
+ * precision to the plain kernel and keeps the buffers until kl_destroy.  chunk = 64-point
+ * row tiles per work item (0 = automatic, about three items per compute unit; a new chunk
+ * re-plans for every precision); items_out (may be NULL) receives the number of work items.
+ * kl_apply_noalloc always uses the plain kernels.  Errors: KL_EINVAL, KL_ENOMEM. */
+kl_status kl_stage5_symmetric(kl_problem *P, int32_t precision, int32_t on, int32_t chunk, int32_t *items_out);
 
 /* Copies of the setup data (host arrays, caller-owned):  X: Ntilde x dim row-major
  * physical Greville points; J: Ntilde weights sqrt(det DF); C: the nt_k x n_k

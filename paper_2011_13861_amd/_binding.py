@@ -99,7 +99,7 @@ def lib():
         L.kl_symeig_partial.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
         L.kl_stage5_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
-        L.kl_stage5_symmetric.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
+        L.kl_stage5_symmetric.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]
         L.kl_apply_config.argtypes = [P, ctypes.c_int32, P]
         L.kl_profile_read.argtypes = [P, P, P]
         L.kl_set_cov.argtypes = [P, ctypes.c_int32, ctypes.c_double, P]
@@ -239,7 +239,7 @@ class Problem:
 
     def __init__(self, desc, host_only=False, stream=None):
         self._h = ctypes.c_void_p()
-        self.symmetric = False          # FP64 stage 5 in its symmetric form (stage5_symmetric)
+        self.symmetric = set()          # precisions whose stage 5 is in its symmetric form
         if isinstance(desc, (list, tuple)):
             if host_only:
                 raise ValueError("several patches need a GPU (no host-only form)")
@@ -346,12 +346,17 @@ class Problem:
                                      ctypes.byref(rbo), ctypes.byref(nso)))
         return rbo.value, nso.value
 
-    def stage5_symmetric(self, on=True, chunk=0):
-        """Symmetric FP64 stage 5 on (True) or off; chunk = row tiles per work item (0 =
-        automatic).  Returns the number of work items (0 when off)."""
+    def stage5_symmetric(self, on=True, chunk=0, precision="f64"):
+        """Symmetric stage 5 on (True) or off for one precision ("f64", "bf16", "bf16x3");
+        chunk = row tiles per work item (0 = automatic).  Returns the number of work items
+        (0 when off)."""
         out = ctypes.c_int32()
-        check(lib().kl_stage5_symmetric(self._h, int(bool(on)), int(chunk), ctypes.byref(out)))
-        self.symmetric = bool(on)
+        check(lib().kl_stage5_symmetric(self._h, PRECISIONS[precision], int(bool(on)), int(chunk),
+                                        ctypes.byref(out)))
+        if on:
+            self.symmetric.add(precision)
+        else:
+            self.symmetric.discard(precision)
         return out.value
 
     def apply_config(self, fuse_directions=True):

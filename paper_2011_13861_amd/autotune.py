@@ -17,9 +17,9 @@ the stage-5 split partials, so fewer splits can make the apply faster even when 
 alone is not.  With the whole apply as the objective the tuner also chooses between the
 fused Kronecker launches (first two directions of each side in one launch, the backward
 one adding the split partials) and one launch per direction (split partials added by their
-own pass), re-scanning the split count for the latter.  For FP64 it then times the
-symmetric form of stage 5 (kl_stage5_symmetric) on the same objective and keeps it when it
-is faster.  Cached settings are applied with
+own pass), re-scanning the split count for the latter.  For FP64, BF16 and BF16x3 it then
+times the symmetric form of stage 5 (kl_stage5_symmetric) on the same objective and keeps it
+when it is faster.  Cached settings are applied with
 `apply_cached`; a problem without an entry of its own takes the entry of the nearest
 tuned padded size within 25 % (same architecture, dimension, kind, precision, objective):
 the size buckets of the cache.  The cache file is $KL_TUNE_CACHE, else
@@ -29,6 +29,9 @@ the size buckets of the cache.  The cache file is $KL_TUNE_CACHE, else
 import hashlib
 import json
 import os
+
+
+SYMMETRIC_PRECISIONS = ("f64", "bf16", "bf16x3")     # stage 5 has a symmetric form
 
 
 def cache_path():
@@ -177,10 +180,10 @@ def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None,
             G.apply_config(fuse)
         G.stage5_config(prec, rb=best[0], nsplit=best[1])
         sym = False
-        if prec == "f64":
-            # the symmetric FP64 form (half the kernel evaluations, partial sums in a fixed
-            # order) against the best plain setting, on the same objective
-            G.stage5_symmetric(True)
+        if prec in SYMMETRIC_PRECISIONS:
+            # the symmetric form (half the kernel evaluations, partial sums in a fixed order)
+            # against the best plain setting, on the same objective
+            G.stage5_symmetric(True, precision=prec)
             us = timer(G, prec, reps)
             if verbose:
                 print("tune", prec, "symmetric", "%.1f us" % us)
@@ -188,7 +191,7 @@ def tune_problem(G, kind, precisions=("f32",), reps=20, max_split=64, path=None,
             if sym:
                 best = (best[0], best[1], us)
             else:
-                G.stage5_symmetric(False)
+                G.stage5_symmetric(False, precision=prec)
         data[problem_key(G, kind, prec, objective)] = {"rb": best[0], "nsplit": best[1], "us": best[2],
                                                         "fuse": bool(fuse), "sym": bool(sym)}
         out[prec] = best
@@ -237,8 +240,8 @@ def apply_cached(G, kind, precision, path=None, objective="stage5"):
         G.stage5_config(precision, rb=e["rb"], nsplit=e["nsplit"])
         if "fuse" in e:
             G.apply_config(e["fuse"])
-        if precision == "f64" and "sym" in e:
-            G.stage5_symmetric(e["sym"])
+        if precision in SYMMETRIC_PRECISIONS and "sym" in e:
+            G.stage5_symmetric(e["sym"], precision=precision)
     return e
 
 

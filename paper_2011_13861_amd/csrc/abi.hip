@@ -130,8 +130,8 @@ int64_t max_intermediate(const HostSetup &hs) {
 int timed_stage5(kl_problem *P, const Workspace &ws, int precision, const void *Y5, const double *wrow,
                  double scale, hipStream_t s, bool defer_reduce = false) {
     const bool rec = P->prof_on && P->prof_used + 2 <= P->prof_ev.size();
-    if (precision == KL_F64 && P->s5_sym && ws.symF) {
-        launch_stage5_sym(P, ws, Y5, wrow, scale, s, rec ? P->prof_ev[P->prof_used] : nullptr,
+    if (P->s5_sym[precision] && ws.symF) {
+        launch_stage5_sym(P, precision, ws, Y5, wrow, scale, s, rec ? P->prof_ev[P->prof_used] : nullptr,
                           rec ? P->prof_ev[P->prof_used + 1] : nullptr);
         if (rec) {
             P->prof_prec.push_back(precision);
@@ -716,12 +716,16 @@ kl_status kl_stage5_config(kl_problem *P, int32_t precision, int32_t rb, int32_t
     return KL_OK;
 }
 
-kl_status kl_stage5_symmetric(kl_problem *P, int32_t on, int32_t chunk, int32_t *items_out) {
+kl_status kl_stage5_symmetric(kl_problem *P, int32_t precision, int32_t on, int32_t chunk, int32_t *items_out) {
     if (!P || P->host_only) { set_error("kl_stage5_symmetric: NULL or host-only handle"); return KL_EINVAL; }
+    if (precision != KL_F64 && precision != KL_BF16 && precision != KL_BF16X3) {
+        set_error("kl_stage5_symmetric: the symmetric form exists for KL_F64, KL_BF16 and KL_BF16X3");
+        return KL_EINVAL;
+    }
     if (on != 0 && on != 1) { set_error("kl_stage5_symmetric: on must be 0 or 1"); return KL_EINVAL; }
     if (chunk < 0 || chunk > (1 << 20)) { set_error("kl_stage5_symmetric: chunk must be >= 0"); return KL_EINVAL; }
     if (!on) {
-        P->s5_sym = false;
+        P->s5_sym[precision] = false;
         if (items_out) *items_out = 0;
         return KL_OK;
     }
@@ -754,7 +758,7 @@ kl_status kl_stage5_symmetric(kl_problem *P, int32_t on, int32_t chunk, int32_t 
             hipFree(ws.symTab);
             ws.symF = ws.symO = nullptr;
             ws.symTab = nullptr;
-            P->s5_sym = false;
+            for (bool &b : P->s5_sym) b = false;
             return st;
         }
         ws.sym_items = pl.n_items;
@@ -762,7 +766,7 @@ kl_status kl_stage5_symmetric(kl_problem *P, int32_t on, int32_t chunk, int32_t 
         ws.sym_chunk = pl.chunk;
         ws.sym_grid = std::min(pl.n_items, P->n_cu);
     }
-    P->s5_sym = true;
+    P->s5_sym[precision] = true;
     if (items_out) *items_out = ws.sym_items;
     return KL_OK;
 }

@@ -770,37 +770,216 @@ __global__ __launch_bounds__(kSymThreads) void stage5_f64_sym_kernel(
     }
 }
 
+// Symmetric BF16 / BF16x3 stage 5: the same work items and partial-sum slots as the FP64
+// form, with FP32 partial sums.  Wave w of the 8 owns the 32 columns 256 J + 32 w + [0, 32)
+// and takes both 32-row halves of every row tile.  Lane (c, kh) (c = lane & 31, kh = lane >>
+// 5) evaluates G[row 16 m + 8 kh + e][col c] for m < 2, e < 8 of a half: eight consecutive
+// rows of its own column, which is the A operand of the transposed product
+// (v_mfma_f32_32x32x16_bf16, A[i][k] = element k % 8 of lane i + 32 (k / 8)) as it stands;
+// the forward product needs G[row i][cols 16 m + 8 kh + e], read back (16-byte loads) from a
+// 32 x 32 tile the wave has just written to LDS.  With X3 the kernel values and both blocks
+// are split into BF16 hi + lo parts and hi hi + hi lo + lo hi are accumulated, in each product.
+constexpr int kSbLdJ = kSymCols + 8;                  // bf16 row of the owned block, [vec][col]
+constexpr int kSbLdT = kSymTile + 8;                  // bf16 row of the row tile, [vec][row]
+constexpr int kSbLdTr = 32 + 8;                       // bf16 row of a transposition tile
+constexpr int kSbRedLd = kBW + 1;                     // FP32 forward partials [wave][row][vec]
+
+template <bool X3>
+struct SymBf16Lds {
+    __bf16 yj[X3 ? 2 : 1][kBW * kSbLdJ];              // owned block of vectors (hi, lo)
+    __bf16 yt[X3 ? 2 : 1][kBW * kSbLdT];              // row tile of vectors (hi, lo)
+    __bf16 tr[kSymWaves][X3 ? 2 : 1][32 * kSbLdTr];   // the waves' transposition tiles
+    float xj[3][kSymCols];                            // points of the owned block [d][col]
+    float xt[3][kSymTile];                            // points of the row tile [d][row]
+    float red[kSymWaves * kSymTile * kSbRedLd];       // forward partials [wave][row][vec]
+};
+
+template <int KIND, int D, bool X3>
+__global__ __launch_bounds__(kSymThreads) void stage5_bf16_sym_kernel(
+    const float *__restrict__ X, const __bf16 *__restrict__ Yh, const __bf16 *__restrict__ Yl, int64_t Ntpad,
+    const SymItem *__restrict__ items, int n_items, float *__restrict__ Fp, float *__restrict__ Op) {
+    constexpr int NP = X3 ? 2 : 1;                    // parts of a BF16 operand
+    extern __shared__ __attribute__((aligned(16))) char smb[];
+    SymBf16Lds<X3> &L = *reinterpret_cast<SymBf16Lds<X3> *>(smb);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = lane & 31, kh = lane >> 5;
+    const __bf16 *Ysrc[2] = {Yh, Yl};
+    __bf16 *tr = L.tr[wave][0];
+    const int G = gridDim.x, g = blockIdx.x;
+    for (int round = 0;; ++round) {
+        const int idx = round * G + ((round & 1) ? G - 1 - g : g);
+        if (idx >= n_items) break;
+        const SymItem I = items[idx];
+        const int64_t cb = int64_t(I.J) * kSymCols;
+        // the row tile's points and vectors, prefetched one tile ahead: thread e < 64 holds
+        // the point 64 t + e; the vectors as 16-byte pieces (8 rows of one vector): 32 x 8
+        // pieces per part, thread e < 256 takes vector e >> 3, rows 8 (e & 7)
+        float px[D];
+        int4 pyh = int4{0, 0, 0, 0}, pyl = int4{0, 0, 0, 0};
+        auto prefetch = [&](int tt) {
+            const int64_t rr0 = int64_t(tt) * kSymTile;
+#pragma unroll
+            for (int d = 0; d < D; ++d) px[d] = threadIdx.x < kSymTile ? X[d * Ntpad + rr0 + threadIdx.x] : 0.f;
+            if (threadIdx.x < kBW * 8) {
+                const int64_t off = int64_t(threadIdx.x >> 3) * Ntpad + rr0 + 8 * (threadIdx.x & 7);
+                pyh = *reinterpret_cast<const int4 *>(Yh + off);
+                if constexpr (X3) pyl = *reinterpret_cast<const int4 *>(Yl + off);
+            }
+        };
+        prefetch(I.t0);
+        __syncthreads();                                  // every wave is past the last item
+        // owned block: points, and vectors [vec][col] (32 x 32 pieces of 8 columns per part)
+        if (threadIdx.x < kSymCols)
+#pragma unroll
+            for (int d = 0; d < D; ++d) L.xj[d][threadIdx.x] = X[d * Ntpad + cb + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = threadIdx.x + u * kSymThreads;      // 1024 pieces
+            const int vec = e >> 5, c8 = 8 * (e & 31);
+#pragma unroll
+            for (int pp = 0; pp < NP; ++pp)
+                *reinterpret_cast<int4 *>(&L.yj[pp][vec * kSbLdJ + c8]) =
+                    *reinterpret_cast<const int4 *>(Ysrc[pp] + int64_t(vec) * Ntpad + cb + c8);
+        }
+        __syncthreads();
+        // per item: the lane's column point and the forward B operands of its 32 columns,
+        // B[k = col 16 m + 8 kh + e][j = vec c]
+        float xc[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) xc[d] = L.xj[d][32 * wave + c];
+        bf16x8 bj[2][NP];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int pp = 0; pp < NP; ++pp)
+                bj[m][pp] = *reinterpret_cast<const bf16x8 *>(&L.yj[pp][c * kSbLdJ + 32 * wave + 16 * m + 8 * kh]);
+        floatx16 O;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) O[r] = 0.f;
+        for (int t = I.t0; t < I.t1; ++t) {
+            const bool diag = t >= 4 * I.J;
+            if (t > I.t0 && t - 1 >= 4 * I.J) __syncthreads();
+            if (threadIdx.x < kSymTile)
+#pragma unroll
+                for (int d = 0; d < D; ++d) L.xt[d][threadIdx.x] = px[d];
+            if (threadIdx.x < kBW * 8) {
+                const int o = (threadIdx.x >> 3) * kSbLdT + 8 * (threadIdx.x & 7);
+                *reinterpret_cast<int4 *>(&L.yt[0][o]) = pyh;
+                if constexpr (X3) *reinterpret_cast<int4 *>(&L.yt[NP - 1][o]) = pyl;
+            }
+            __syncthreads();
+            if (t + 1 < I.t1) prefetch(t + 1);
+            floatx16 F[2];
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) F[h2][r] = 0.f;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int rb = 32 * h2 + 16 * m + 8 * kh;     // the lane's 8 rows
+                    float xr[8][D];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+#pragma unroll
+                        for (int d = 0; d < D; ++d) xr[e][d] = L.xt[d][rb + e];
+                    bf16x8 ah, al;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float gv = gamma_f32<KIND, D>(xc, xr[e]);
+                        ah[e] = __bf16(gv);
+                        if constexpr (X3) al[e] = __bf16(gv - float(ah[e]));
+                    }
+                    const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&L.yt[0][c * kSbLdT + rb]);
+                    O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, O, 0, 0, 0);
+                    if constexpr (X3) {
+                        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&L.yt[1][c * kSbLdT + rb]);
+                        O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, O, 0, 0, 0);
+                        O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, O, 0, 0, 0);
+                    }
+                    if (!diag) {
+                        // G[row 16 m + 8 kh + e][col c] of the half into the tile
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            tr[(16 * m + 8 * kh + e) * kSbLdTr + c] = ah[e];
+                            if constexpr (X3) tr[32 * kSbLdTr + (16 * m + 8 * kh + e) * kSbLdTr + c] = al[e];
+                        }
+                    }
+                }
+                if (!diag) {
+                    __builtin_amdgcn_wave_barrier();
+                    // forward: A[i = row c][k = col 16 m + 8 kh + e] from the tile
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) {
+                        const bf16x8 fh = *reinterpret_cast<const bf16x8 *>(&tr[c * kSbLdTr + 16 * m + 8 * kh]);
+                        F[h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh, bj[m][0], F[h2], 0, 0, 0);
+                        if constexpr (X3) {
+                            const bf16x8 fl =
+                                *reinterpret_cast<const bf16x8 *>(&tr[32 * kSbLdTr + c * kSbLdTr + 16 * m + 8 * kh]);
+                            F[h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh, bj[m][NP - 1], F[h2], 0, 0, 0);
+                            F[h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl, bj[m][0], F[h2], 0, 0, 0);
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            if (!diag) {
+                // D[(r & 3) + 4 kh + 8 (r >> 2)][c]: row of the half, vector c
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        L.red[(wave * kSymTile + 32 * h2 + (r & 3) + 4 * kh + 8 * (r >> 2)) * kSbRedLd + c] = F[h2][r];
+                __syncthreads();
+                float *dst = Fp + (int64_t(2) * I.J * (I.J - 1) + t) * (kSymTile * kBW);
+#pragma unroll
+                for (int u = 0; u < (kSymTile * kBW) / kSymThreads; ++u) {
+                    const int e = threadIdx.x + u * kSymThreads;
+                    const int row = e >> 5, vec = e & 31;
+                    float acc = 0.f;
+#pragma unroll
+                    for (int w = 0; w < kSymWaves; ++w) acc += L.red[(w * kSymTile + row) * kSbRedLd + vec];
+                    dst[e] = acc;                             // [row][vec]
+                }
+            }
+        }
+        // the owned partial: D[(r & 3) + 4 kh + 8 (r >> 2)][c] = O[col of the wave][vector c]
+        float *dst = Op + int64_t(I.oslot) * (kSymCols * kBW);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[(32 * wave + (r & 3) + 4 * kh + 8 * (r >> 2)) * kBW + c] = O[r];
+    }
+}
+
 // Row tile t of block J = t / 4: z = sum of the owned partials of J's items (item slots
 // o_first[J] .. o_first[J + 1] - 1, in order) and of the forward partials (t, J') for
 // J' = J + 1 .. NB - 1 (in order); Zf[vec][row] = z scale wrow[row] (z without wrow).
-__global__ __launch_bounds__(kThreads) void sym_reduce_kernel(const double *__restrict__ Fp,
-                                                              const double *__restrict__ Op,
+template <typename T>
+__global__ __launch_bounds__(kThreads) void sym_reduce_kernel(const T *__restrict__ Fp, const T *__restrict__ Op,
                                                               const int *__restrict__ o_first, int NB,
                                                               int64_t Ntpad, const double *__restrict__ wrow,
-                                                              double scale, double *__restrict__ Zf) {
+                                                              double scale, T *__restrict__ Zf) {
     constexpr int kPer = (kSymTile * kBW) / kThreads;
-    __shared__ double sm[kBW][kSymTile + 1];
+    __shared__ T sm[kBW][kSymTile + 1];
     const int t = blockIdx.x, J = t >> 2, rt = t & 3;
-    double acc[kPer];
+    T acc[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) acc[u] = 0.0;
+    for (int u = 0; u < kPer; ++u) acc[u] = T(0);
     for (int o = o_first[J]; o < o_first[J + 1]; ++o) {
-        const double *src = Op + int64_t(o) * (kSymCols * kBW) + rt * (kSymTile * kBW);
+        const T *src = Op + int64_t(o) * (kSymCols * kBW) + rt * (kSymTile * kBW);
 #pragma unroll
         for (int u = 0; u < kPer; ++u) acc[u] += src[threadIdx.x + u * kThreads];
     }
     int J2 = J + 1;
     for (; J2 + 1 < NB; J2 += 2) {                       // two slots' loads in flight
-        const double *a = Fp + (int64_t(2) * J2 * (J2 - 1) + t) * (kSymTile * kBW);
-        const double *b = Fp + (int64_t(2) * (J2 + 1) * J2 + t) * (kSymTile * kBW);
-        double va[kPer], vb[kPer];
+        const T *a = Fp + (int64_t(2) * J2 * (J2 - 1) + t) * (kSymTile * kBW);
+        const T *b = Fp + (int64_t(2) * (J2 + 1) * J2 + t) * (kSymTile * kBW);
+        T va[kPer], vb[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) { va[u] = a[threadIdx.x + u * kThreads]; vb[u] = b[threadIdx.x + u * kThreads]; }
 #pragma unroll
         for (int u = 0; u < kPer; ++u) acc[u] = (acc[u] + va[u]) + vb[u];
     }
     if (J2 < NB) {
-        const double *a = Fp + (int64_t(2) * J2 * (J2 - 1) + t) * (kSymTile * kBW);
+        const T *a = Fp + (int64_t(2) * J2 * (J2 - 1) + t) * (kSymTile * kBW);
 #pragma unroll
         for (int u = 0; u < kPer; ++u) acc[u] += a[threadIdx.x + u * kThreads];
     }
@@ -815,9 +994,8 @@ __global__ __launch_bounds__(kThreads) void sym_reduce_kernel(const double *__re
     for (int u = 0; u < kPer; ++u) {
         const int e = threadIdx.x + u * kThreads;
         const int vec = e >> 6, row = e & 63;
-        double v = sm[vec][row];
-        if (wrow) v = v * scale * wrow[row0 + row];
-        Zf[int64_t(vec) * Ntpad + row0 + row] = v;
+        const T v = sm[vec][row];
+        Zf[int64_t(vec) * Ntpad + row0 + row] = wrow ? T(double(v) * scale * wrow[row0 + row]) : v;
     }
 }
 
@@ -1085,14 +1263,14 @@ SymPlan sym_plan(int64_t Ntpad, int n_cu, int chunk) {
 size_t sym_f_bytes(const SymPlan &pl) { return size_t(std::max<int64_t>(1, pl.f_slots)) * kSymTile * kBW * sizeof(double); }
 size_t sym_o_bytes(const SymPlan &pl) { return size_t(pl.n_oslots) * kSymCols * kBW * sizeof(double); }
 
-void launch_stage5_sym(const kl_problem *P, const Workspace &ws, const void *Y5, const double *wrow, double scale,
-                       hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+void launch_stage5_sym(const kl_problem *P, int precision, const Workspace &ws, const void *Y5,
+                       const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
     const SymItem *items = static_cast<const SymItem *>(ws.symTab);
     const int *o_first = reinterpret_cast<const int *>(items + ws.sym_items);
-    const double *Y = static_cast<const double *>(Y5);
-    double *Zf = static_cast<double *>(ws.Zf);
     const dim3 grid(unsigned(ws.sym_grid));
     if (ev_start) (void)hipEventRecord(ev_start, s);
+    if (precision == KL_F64) {
+        const double *Y = static_cast<const double *>(Y5);
 #define KL_SYM(KIND_, D_)                                                                                    \
     do {                                                                                                     \
         static const bool attr_set = [] {                                                                    \
@@ -1110,17 +1288,57 @@ void launch_stage5_sym(const kl_problem *P, const Workspace &ws, const void *Y5,
     case 2: KL_SYM(KIND_, 2); break;           \
     default: KL_SYM(KIND_, 3); break;          \
     }
-    switch (P->cov_kind) {
-    case KL_COV_EXP: KL_SYM_D(KL_COV_EXP); break;
-    case KL_COV_SQEXP: KL_SYM_D(KL_COV_SQEXP); break;
-    case KL_COV_EXP_L1: KL_SYM_D(KL_COV_EXP_L1); break;
-    case KL_COV_CONST: KL_SYM_D(KL_COV_CONST); break;
-    default: KL_SYM_D(KL_COV_LIN); break;
-    }
+        switch (P->cov_kind) {
+        case KL_COV_EXP: KL_SYM_D(KL_COV_EXP); break;
+        case KL_COV_SQEXP: KL_SYM_D(KL_COV_SQEXP); break;
+        case KL_COV_EXP_L1: KL_SYM_D(KL_COV_EXP_L1); break;
+        case KL_COV_CONST: KL_SYM_D(KL_COV_CONST); break;
+        default: KL_SYM_D(KL_COV_LIN); break;
+        }
 #undef KL_SYM_D
 #undef KL_SYM
-    hipLaunchKernelGGL(sym_reduce_kernel, dim3(unsigned(P->Ntpad / kSymTile)), dim3(kThreads), 0, s, ws.symF,
-                       ws.symO, o_first, ws.sym_NB, P->Ntpad, wrow, scale, Zf);
+        hipLaunchKernelGGL(sym_reduce_kernel<double>, dim3(unsigned(P->Ntpad / kSymTile)), dim3(kThreads), 0, s,
+                           ws.symF, ws.symO, o_first, ws.sym_NB, P->Ntpad, wrow, scale, static_cast<double *>(ws.Zf));
+    } else {
+        // BF16 operands: hi part at Y5, lo part right after it (Ntpad x kBW each); FP32
+        // partial sums in the same buffers
+        const __bf16 *yh = static_cast<const __bf16 *>(Y5);
+        const __bf16 *yl = yh + P->Ntpad * kBW;
+        float *Fp = reinterpret_cast<float *>(ws.symF), *Op = reinterpret_cast<float *>(ws.symO);
+#define KL_SYMB(KIND_, D_, X3_)                                                                              \
+    do {                                                                                                     \
+        constexpr size_t lds = sizeof(SymBf16Lds<X3_>);                                                       \
+        static const bool attr_set = [] {                                                                    \
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&stage5_bf16_sym_kernel<KIND_, D_, X3_>), \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));                 \
+            return true;                                                                                     \
+        }();                                                                                                 \
+        (void)attr_set;                                                                                      \
+        hipLaunchKernelGGL((stage5_bf16_sym_kernel<KIND_, D_, X3_>), grid, dim3(kSymThreads), lds, s, P->dX32, \
+                           yh, yl, P->Ntpad, items, ws.sym_items, Fp, Op);                                   \
+    } while (0)
+#define KL_SYMB_X(KIND_, D_)                                       \
+    if (precision == KL_BF16X3) KL_SYMB(KIND_, D_, true);          \
+    else KL_SYMB(KIND_, D_, false);
+#define KL_SYMB_D(KIND_)                       \
+    switch (P->hs.d) {                         \
+    case 1: KL_SYMB_X(KIND_, 1); break;        \
+    case 2: KL_SYMB_X(KIND_, 2); break;        \
+    default: KL_SYMB_X(KIND_, 3); break;       \
+    }
+        switch (P->cov_kind) {
+        case KL_COV_EXP: KL_SYMB_D(KL_COV_EXP); break;
+        case KL_COV_SQEXP: KL_SYMB_D(KL_COV_SQEXP); break;
+        case KL_COV_EXP_L1: KL_SYMB_D(KL_COV_EXP_L1); break;
+        case KL_COV_CONST: KL_SYMB_D(KL_COV_CONST); break;
+        default: KL_SYMB_D(KL_COV_LIN); break;
+        }
+#undef KL_SYMB_D
+#undef KL_SYMB_X
+#undef KL_SYMB
+        hipLaunchKernelGGL(sym_reduce_kernel<float>, dim3(unsigned(P->Ntpad / kSymTile)), dim3(kThreads), 0, s, Fp,
+                           Op, o_first, ws.sym_NB, P->Ntpad, wrow, scale, static_cast<float *>(ws.Zf));
+    }
     if (ev_stop) (void)hipEventRecord(ev_stop, s);
 }
 

@@ -110,7 +110,7 @@ struct kl_problem {
     int s5_rb[4] = {2, 2, 2, 2};
     bool fuse_dirs = true;                 // first two directions of each side in one launch
     int s5_split[4] = {0, 0, 0, 0};
-    bool s5_sym = false;                   // FP64 stage 5 in its symmetric form (kl_stage5_symmetric)
+    bool s5_sym[4] = {false, false, false, false};   // symmetric stage 5 per precision (kl_stage5_symmetric)
     // optional stage-5 timing with HIP events (kl_profile_enable / kl_profile_read)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;      // pool: 2 events per timed launch
@@ -244,14 +244,16 @@ int stage5_splits(int64_t Ntpad, int64_t rows_wg, int n_cu, int max_split, int f
 int launch_stage5(const kl_problem *P, int precision, const void *Y5, void *Z5, void *Zf,
                   const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start = nullptr,
                   hipEvent_t ev_stop = nullptr, bool defer_reduce = false, int max_split = 0);
-// Symmetric FP64 stage 5 into ws.Zf (same result as launch_stage5 with one split): the plan
-// of a padded grid (chunk = row tiles per item, 0 = automatic), the sizes of its partial
-// buffers, and the launch (covariance kernel and ordered reduction, both inside the events).
+// Symmetric stage 5 (KL_F64, KL_BF16, KL_BF16X3) into ws.Zf (same result as launch_stage5
+// with one split): the plan of a padded grid (chunk = row tiles per item, 0 = automatic),
+// the sizes of its partial buffers (FP64; the BF16 forms use them for FP32 partials), and
+// the launch (covariance kernel and ordered reduction, both inside the events).
 SymPlan sym_plan(int64_t Ntpad, int n_cu, int chunk);
 size_t sym_f_bytes(const SymPlan &pl);
 size_t sym_o_bytes(const SymPlan &pl);
-void launch_stage5_sym(const kl_problem *P, const Workspace &ws, const void *Y5, const double *wrow, double scale,
-                       hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+void launch_stage5_sym(const kl_problem *P, int precision, const Workspace &ws, const void *Y5,
+                       const double *wrow, double scale, hipStream_t s, hipEvent_t ev_start = nullptr,
+                       hipEvent_t ev_stop = nullptr);
 
 // kl_setup with or without the single-problem apply workspace (T0/T1, stage-5 buffers);
 // problems of a batch use the batch's arenas instead.  Uploads on `s`, then waits for it.

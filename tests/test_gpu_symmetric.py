@@ -1,10 +1,11 @@
-"""GPU parity of the symmetric FP64 stage 5 (kl_stage5_symmetric): each kernel value of a
-pair of point blocks below the diagonal serves both products, and the partial sums are
-added in a fixed order.
+"""GPU parity of the symmetric stage 5 (kl_stage5_symmetric; FP64, BF16x3, BF16): each
+kernel value of a pair of point blocks below the diagonal serves both products, and the
+partial sums are added in a fixed order.
 
-Same bar as the plain FP64 path: relative max-norm error <= 1e-12 against the oracle's
+Same bars as the plain kernels: FP64 relative max-norm error <= 1e-12 against the oracle's
 Algorithm 1 (its stage 5 is the dense product Gamma Y, which the symmetric form must
-reproduce up to rounding).  Work-item chunk sizes from 1 row tile to the automatic choice
+reproduce up to rounding); BF16x3 / BF16 relative Frobenius 5e-5 / 5e-3, every row within
+8x that.  Work-item chunk sizes from 1 row tile to the automatic choice
 cover items that stop inside, at and across the diagonal block; problem sizes from one
 256-point block (no forward partials) to the 24^3 cube (69 blocks).
 """
@@ -40,21 +41,35 @@ def test_symmetric_apply_matches_oracle(name, desc, chunk):
     tga._check(_apply(G, V), P.apply(V), "f64", name, "sym", chunk)
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("chunk", [0, 3])
+@pytest.mark.parametrize("name,desc", tga.SMALL, ids=[s[0] for s in tga.SMALL])
+def test_symmetric_low_precision_apply_matches_oracle(name, desc, chunk, precision):
+    """The symmetric BF16x3 and BF16 forms at the bars of the plain kernels (relative
+    Frobenius 5e-5 / 5e-3 and every row within 8x that)."""
+    P = operator.Problem(desc)
+    G = kl.Problem(desc)
+    assert G.stage5_symmetric(True, chunk, precision=precision) > 0
+    V = workloads.random_block(P.N, 7, seed=3)
+    tga._check(tga._gpu_apply(G, V, precision), P.apply(V), precision, name, "sym", chunk)
+
+
+@pytest.mark.parametrize("precision", ["f64", "bf16x3", "bf16"])
 @pytest.mark.parametrize("chunk", [0, 1, 2, 5, 7, 1000])
-def test_symmetric_stage5_alone_matches_oracle(chunk):
+def test_symmetric_stage5_alone_matches_oracle(chunk, precision):
     """Stage 5 alone (no sigma^2 J scaling inside) on 32 and on 3 vectors; 1000 row tiles
     per item puts every column block in one item."""
     desc = workloads.quarter_annulus(20, 2, "exp", (0.3, 0.6))
     P = operator.Problem(desc)
     G = kl.Problem(desc)
-    G.stage5_symmetric(True, chunk)
+    G.stage5_symmetric(True, chunk, precision=precision)
     for nv in (32, 3):
         Y = workloads.random_block(P.Nt, nv, seed=4 + nv)
         y = kl.to_device_block(Y)
         z = kl.new_block(G.Nt, nv)
-        G.stage5(y, z, "f64")
+        G.stage5(y, z, precision)
         torch.cuda.synchronize()
-        tga._check(z.cpu().numpy(), P.stage5(Y), "f64", "stage5 sym", chunk, nv)
+        tga._check(z.cpu().numpy(), P.stage5(Y), precision, "stage5 sym", chunk, nv)
 
 
 def test_symmetric_and_plain_kernels_agree_and_repeat():
@@ -87,6 +102,9 @@ def test_full_size_cube24_symmetric_apply():
     ref = P.apply(V, stage5=lambda Y: cstage5.stage5(P, Y))
     tga._check(_apply(G, V[:, :32]), ref[:, :32], "f64", "cube24 sym 32")
     tga._check(_apply(G, V), ref, "f64", "cube24 sym 35")
+    for prec in ("bf16x3", "bf16"):
+        G.stage5_symmetric(True, precision=prec)
+        tga._check(tga._gpu_apply(G, V[:, :32], prec), ref[:, :32], prec, "cube24 sym 32")
     X, _ = G.points()
     Y = workloads.random_block(G.Nt, 32, seed=6)
     z = kl.new_block(G.Nt, 32)
@@ -135,9 +153,10 @@ def test_symmetric_form_is_skipped_by_noalloc_and_errors():
     assert st == 0, kl.lib().kl_last_error()
     torch.cuda.synchronize()
     tga._check(out.cpu().numpy(), P.apply(V), "f64", "noalloc with sym on")
-    for on, chunk in ((2, 0), (1, -1)):
-        assert kl.lib().kl_stage5_symmetric(G.handle, on, chunk, None) == -1
+    for prec, on, chunk in ((0, 2, 0), (0, 1, -1), (1, 1, 0), (7, 1, 0)):
+        assert kl.lib().kl_stage5_symmetric(G.handle, prec, on, chunk, None) == -1
     assert G.stage5_symmetric(False) == 0
-    # the other precisions ignore the setting
+    # the setting is per precision: FP32 keeps its plain kernel
     G.stage5_symmetric(True)
+    G.stage5_symmetric(True, precision="bf16")
     tga._check(tga._gpu_apply(G, V, "f32"), P.apply(V), "f32", "f32 with sym on")
