@@ -207,7 +207,8 @@ kl_status kl_stage5(kl_problem *P, int32_t precision, int32_t nvec,
  * side run as one launch over 2-D slabs, and so do those of the backward side, which
  * also adds the stage-5 split partials and applies sigma^2 J (2d - 1 launches per
  * 32-column block); with 0, one launch per direction plus the split sums.  Sizes whose
- * slab does not fit the fused kernel's LDS take the per-direction form either way.
+ * slab does not fit the fused kernel's LDS take the per-direction form either way.  The
+ * setting also covers the evaluation of the eigenfunctions in kl_kle_field (its forward side).
  * fused_out (may be NULL) receives whether a 32-column apply would be fused.
  * Errors: KL_EINVAL. */
 kl_status kl_apply_config(kl_problem *P, int32_t fuse_directions, int32_t *fused_out);
@@ -248,9 +249,8 @@ kl_status kl_get_points(const kl_problem *P, double *X, double *J);
  * with phi_i = (sum_j v_j B_j) / sqrt(det DF) in the trial basis of Sec. 3.4 and v = L^{-T} v'
  * for the standard-form eigenvector v' (Sec. 4.1; column i of evecs, as kl_eigs returns it).
  * lam: host, M eigenvalues (finite, >= 0).  evecs: device, N x M column-major, ld ldv >= N.
- * xi: device, M x m column-major, ld ldxi >= M, m <= 1048560 (read only when F is
- * requested).  F: device,
- * Ntilde x m column-major, ld ldf >= Ntilde, or NULL.  var: device, Ntilde, or NULL (not
+ * xi: device, M x m column-major, ld ldxi >= M (read only when F is requested).  F: device,
+ * Ntilde x m column-major, ld ldf >= Ntilde, or NULL; ceil(Ntilde / 64) ceil(m / 64) < 2^31.  var: device, Ntilde, or NULL (not
  * both NULL).  Inputs and outputs must not overlap.  Asynchronous on `stream`; uses the
  * problem's workspaces, so calls on one problem must not run concurrently with each other or
  * with kl_apply.  Errors: KL_EINVAL (sizes, pointers, eigenvalues, host-only handle),

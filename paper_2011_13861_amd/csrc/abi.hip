@@ -170,12 +170,12 @@ bool fused_directions(const kl_problem *P, int nb) {
     return true;
 }
 
-namespace {
-
-// Stages 1-4 of one patch Q (its factors C_k): x (Q's N x nb, ld ldx) -> its rows of the
-// stage-5 input Y5 (ld ldy5; BF16x3 writes the low parts to Y5lo), times J (its rows).
-void forward_patch(const kl_problem *Q, bool fuse, int y5_kind, int nb, const double *x, int64_t ldx,
-                   void *Y5, void *Y5lo, int64_t ldy5, const double *J, double *T0, double *T1, hipStream_t s) {
+// Stages 1-4 of one patch Q with the factors D[k] (nt_k x n_k, row-major) and their
+// transposes DT[k]: x (Q's N x nb, ld ldx) -> its rows of Y5 (ld ldy5; BF16x3 writes the low
+// parts to Y5lo), times J (its rows) unless J is NULL.
+void forward_patch(const kl_problem *Q, const double *const *D, const double *const *DT, bool fuse, int y5_kind,
+                   int nb, const double *x, int64_t ldx, void *Y5, void *Y5lo, int64_t ldy5, const double *J,
+                   double *T0, double *T1, hipStream_t s) {
     const HostSetup &hs = Q->hs;
     const int d = hs.d;
     const void *cur = x;
@@ -184,7 +184,7 @@ void forward_patch(const kl_problem *Q, bool fuse, int y5_kind, int nb, const do
     int k0 = 0;
     if (fuse) {
         Mode2Args a{};
-        a.D1 = Q->dC[0]; a.D2 = Q->dC[1]; a.D1T = Q->dCT[0]; a.D2T = Q->dCT[1];
+        a.D1 = D[0]; a.D2 = D[1]; a.D1T = DT[0]; a.D2T = DT[1];
         a.in = x; a.in_ldj = ldx;
         a.nin1 = hs.n[0]; a.nin2 = hs.n[1]; a.nout1 = hs.nt[0]; a.nout2 = hs.nt[1];
         a.Clo = 1;
@@ -205,8 +205,8 @@ void forward_patch(const kl_problem *Q, bool fuse, int y5_kind, int nb, const do
     }
     for (int k = k0; k < d; ++k) {
         ModeSpec m;
-        m.D = Q->dC[k];
-        m.DT = Q->dCT[k];
+        m.D = D[k];
+        m.DT = DT[k];
         m.in = cur;
         m.in_ldj = cur_ld;
         m.A = A;
@@ -232,6 +232,8 @@ void forward_patch(const kl_problem *Q, bool fuse, int y5_kind, int nb, const do
         cur_ld = m.out_ldj;
     }
 }
+
+namespace {
 
 // Stages 6-9 of one patch Q: its rows of the stage-5 output -> y (Q's N x nb, ld ldy).
 // Fused: `in` holds nsplit partials `in_split` apart (or the finished rows when nsplit
@@ -317,7 +319,8 @@ kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int
     // ---- stages 1-4 ---------------------------------------------------------------------
     for (int i = 0; i < patch_count(P); ++i) {
         const int64_t toff = patch_toff(P, i);
-        forward_patch(patch_of(P, i), fuse, y5_kind, nb, x + patch_noff(P, i), ldx,
+        forward_patch(patch_of(P, i), patch_of(P, i)->dC, patch_of(P, i)->dCT, fuse, y5_kind, nb,
+                      x + patch_noff(P, i), ldx,
                       static_cast<char *>(Y5) + toff * y5_elem,
                       Y5lo ? static_cast<void *>(static_cast<char *>(Y5lo) + toff * y5_elem) : nullptr,
                       P->Ntpad, P->dJ + toff, ws.T0, ws.T1, s);

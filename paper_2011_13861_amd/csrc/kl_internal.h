@@ -273,6 +273,16 @@ inline const kl_problem *patch_of(const kl_problem *P, int i) { return P->patche
 inline int64_t patch_noff(const kl_problem *P, int i) { return P->patches.empty() ? 0 : P->noff[i]; }
 inline int64_t patch_toff(const kl_problem *P, int i) { return P->patches.empty() ? 0 : P->toff[i]; }
 int64_t problem_max_intermediate(const kl_problem *P);
+// Whether the first two directions of each side run as one launch (mode2_kernel) for nb
+// columns: for every patch or for none.
+bool fused_directions(const kl_problem *P, int nb);
+// Forward Kronecker stages of one patch Q with the factors D[k] (nt_k x n_k, row-major) and
+// their transposes DT[k]: x (Q's N x nb, ld ldx) -> out (Q's Ntilde rows, ld ldout), FP64
+// (y5_kind 0), FP32 (1), BF16 (2) or BF16 pairs (3, low parts to out_lo), times J unless J
+// is NULL; T0 and T1 hold the intermediates.
+void forward_patch(const kl_problem *Q, const double *const *D, const double *const *DT, bool fuse, int y5_kind,
+                   int nb, const double *x, int64_t ldx, void *out, void *out_lo, int64_t ldout, const double *J,
+                   double *T0, double *T1, hipStream_t s);
 // One chunk (<= kBW columns) of the single-problem apply, on the problem's workspace or
 // on `ws` (same layout; its padding rows of the stage-5 inputs must be zero).
 kl_status apply_chunk(kl_problem *P, int precision, int nb, const double *x, int64_t ldx, double *y,

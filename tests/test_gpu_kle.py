@@ -48,13 +48,17 @@ def _rel(a, b):
     return np.max(np.abs(a - b)) / np.max(np.abs(b))
 
 
+@pytest.mark.parametrize("fuse", [True, False], ids=["fused", "per_direction"])
 @pytest.mark.parametrize("M,m", [(7, 1), (32, 5), (45, 130)])
 @pytest.mark.parametrize("name,desc", CASES, ids=[c[0] for c in CASES])
-def test_kle_field_matches_oracle(name, desc, M, m):
+def test_kle_field_matches_oracle(name, desc, M, m, fuse):
+    """With the first two directions of the evaluation in one launch (where the operator's
+    forward stages fuse them) and one launch per direction."""
     P, lam, V = _eigpairs(name, desc, min(M, operator.Problem(desc).N))
     M = len(lam)
     xi = np.random.default_rng(M + m).standard_normal((M, m))
     G = kl.Problem(desc)
+    G.apply_config(fuse)
     F, var = G.kle_field(lam, kl.to_device_block(V), kl.to_device_block(xi))
     torch.cuda.synchronize()
     F_ref = kle.sample_field(P, lam, V, xi)
@@ -99,18 +103,44 @@ def test_linear_kernel_variance_through_gpu_eigensolver():
 
 
 def test_kle_field_many_chunks_same_problem():
-    """Same problem twice: 45 modes (two chunks), then 300 modes (ten chunks of 32, the last
-    ragged, each accumulating into F and var)."""
+    """Same problem three times: 45 modes (two chunks), then 300 modes (ten chunks of 32, the
+    last ragged; two passes of the product, the second accumulating into F and var) on 37
+    samples (edge tiles only) and on 150 (interior and edge tiles of the product)."""
     desc = {"dim": 2, "degree": [2, 2], "nelem": [20, 19], "map": {"kind": "annulus_polar", "r0": 1.0, "r1": 2.0},
             "cov": {"kind": "exp", "sigma2": 1.0, "corr_len": [0.3, 0.3]}}
     P = operator.Problem(desc)
     lam_all, V_all = oeigs.dense_eigs(P, 300)
     lam_all = np.maximum(lam_all, 0.0)
     G = kl.Problem(desc)
-    for M, m in [(45, 20), (300, 37)]:
+    for M, m in [(45, 20), (300, 37), (300, 150)]:
         lam, V = lam_all[:M], V_all[:, :M]
         xi = np.random.default_rng(M).standard_normal((M, m))
         F, var = G.kle_field(lam, kl.to_device_block(V), kl.to_device_block(xi))
         torch.cuda.synchronize()
         assert _rel(F.cpu().numpy(), kle.sample_field(P, lam, V, xi)) < 1e-12, M
         assert _rel(var.cpu().numpy(), kle.variance_field(P, lam, V)) < 1e-12, M
+
+
+def test_kle_field_wide_leading_dimensions():
+    """xi and F with leading dimensions above 2^26 (lane offsets of a tile no longer fit in
+    32 bits): the product takes per-lane 64-bit addresses.  About 1 GiB per buffer."""
+    import ctypes
+    name, desc = CASES[0]
+    P, lam, V = _eigpairs(name, desc, 40)
+    G = kl.Problem(desc)
+    m, M = 3, len(lam)
+    ld = (1 << 26) + 64
+    xi = np.random.default_rng(5).standard_normal((M, m))
+    xid = torch.zeros((m - 1) * ld + M, dtype=torch.float64, device="cuda")
+    xid.as_strided((m, M), (ld, 1)).copy_(torch.from_numpy(xi.T.copy()).cuda())
+    Fd = torch.full(((m - 1) * ld + G.Nt,), float("nan"), dtype=torch.float64, device="cuda")
+    Vd = kl.to_device_block(V)
+    st = kl.lib().kl_kle_field(G.handle, M, ctypes.c_void_p(lam.ctypes.data), ctypes.c_void_p(Vd.data_ptr()),
+                               ctypes.c_int64(G.N), m, ctypes.c_void_p(xid.data_ptr()), ctypes.c_int64(ld),
+                               ctypes.c_void_p(Fd.data_ptr()), ctypes.c_int64(ld), None, None)
+    assert st == 0, kl.lib().kl_last_error()
+    torch.cuda.synchronize()
+    F = Fd.as_strided((m, G.Nt), (ld, 1)).cpu().numpy().T
+    assert _rel(F, kle.sample_field(P, lam, V, xi)) < 1e-12
+    del xid, Fd
+    torch.cuda.empty_cache()
