@@ -3,8 +3,9 @@
 // phi_i = (sum_j v_j B_j) / sqrt(det DF) (Sec. 3.4) and v = L^{-T} v' (Sec. 4.1).
 //
 // The Kronecker product of the factors E_k = B_k(g) L_k^{-T} (the forward stages of the
-// operator with E_k in place of C_k, 32 eigenvectors at a time, the first two directions in one
-// launch where the operator fuses them) gives the unscaled values of all modes of a pass in
+// operator with E_k in place of C_k, all modes of a pass in one call where the buffer holds
+// their intermediates, else 32 at a time; the first two directions in one launch where the
+// operator fuses them) gives the unscaled values of all modes of a pass in
 // the split-partials buffer; one more launch forms
 // A[x][i] = Phi[x][i] sqrt(lambda_i) / J(x) while staging it, adds its squares to the
 // variance, and computes F = A xi on the FP64 matrix cores, each sample column of F written
@@ -230,21 +231,35 @@ extern "C" kl_status kl_kle_field(kl_problem *P, int32_t M, const double *lam, c
             set_error("kl_kle_field: eigenvalues must be finite and >= 0"); return KL_EINVAL;
         }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // the unscaled values of a pass's modes go to the split-partials buffer (Ntpad x cap)
+    // The unscaled values of a pass's modes go to the split-partials buffer (Ntpad x K).  A
+    // pass is evaluated in one forward call (every mode at once) when both Kronecker
+    // intermediates of its K modes fit behind them in that buffer and the mode kernels' row
+    // counts (intermediate x K) stay in 32 bits, and that takes no more passes than chunks of
+    // kBW modes through the workspace's intermediates would; otherwise it runs in such chunks.
     double *Phi = static_cast<double *>(P->ws.Z5);
-    const int64_t cap_cols = int64_t(P->ws.z5_bytes / (sizeof(double) * size_t(P->Ntpad))) / kBW * kBW;
-    const int per_pass = int(std::min<int64_t>(kKgMaxModes, std::max<int64_t>(kBW, cap_cols)));
+    const int64_t z5_elems = int64_t(P->ws.z5_bytes / sizeof(double));
+    const int64_t tmax = (problem_max_intermediate(P) + 31) / 32 * 32;
+    const int64_t rows_max = std::max<int64_t>(std::max<int64_t>(tmax, P->Ntpad), hs.N);
+    const int64_t wide = std::min<int64_t>(std::min<int64_t>(kKgMaxModes, z5_elems / (P->Ntpad + 2 * tmax)),
+                                           (int64_t(INT32_MAX) - 1) / rows_max);
+    const int chunked_pass =
+        int(std::min<int64_t>(kKgMaxModes, std::max<int64_t>(kBW, z5_elems / P->Ntpad / kBW * kBW)));
+    const bool one_call = wide >= std::min(M, chunked_pass);
+    const int per_pass = one_call ? int(wide) : chunked_pass;
+    const int chunk = one_call ? per_pass : kBW;
     for (int p0 = 0; p0 < M; p0 += per_pass) {
         const int K = std::min(per_pass, M - p0);
-        for (int c0 = 0; c0 < K; c0 += kBW) {
-            const int nb = std::min(kBW, K - c0);
+        double *T0 = one_call ? Phi + int64_t(per_pass) * P->Ntpad : P->ws.T0;
+        double *T1 = one_call ? T0 + int64_t(per_pass) * tmax : P->ws.T1;
+        for (int c0 = 0; c0 < K; c0 += chunk) {
+            const int nb = std::min(chunk, K - c0);
             // the trial functions at the Greville points, patch by patch on the patch's rows
             const bool fuse = fused_directions(P, nb);
             for (int pi = 0; pi < patch_count(P); ++pi) {
                 const kl_problem *Q = patch_of(P, pi);
                 forward_patch(Q, Q->dE, Q->dET, fuse, 0, nb, evecs + int64_t(p0 + c0) * ldv + patch_noff(P, pi), ldv,
-                              Phi + int64_t(c0) * P->Ntpad + patch_toff(P, pi), nullptr, P->Ntpad, nullptr,
-                              P->ws.T0, P->ws.T1, s);
+                              Phi + int64_t(c0) * P->Ntpad + patch_toff(P, pi), nullptr, P->Ntpad, nullptr, T0, T1,
+                              s);
             }
         }
         ModeScale sc{};
