@@ -53,6 +53,30 @@ struct KgLds {
     double V[4][kKgRows];          // variance partials of the four waves
 };
 
+// Staging loads of one chunk of kKgK modes from k0 (see kle_gemm_tile), into registers.
+template <bool WITH_F, bool INTERIOR, int UA, int UB>
+__device__ __forceinline__ void kg_load_chunk(double (&av)[UA], double (&bv)[UB], const double *__restrict__ Phi,
+                                              int64_t ldp, int64_t row0, uint32_t offA, int wave, int K, int k0,
+                                              const double *__restrict__ xi, int64_t ldxi, int m, int j0, int bs,
+                                              int bk) {
+    const int kc = min(kKgK, K - k0);
+#pragma unroll
+    for (int u = 0; u < UA; ++u) av[u] = *at_bytes(Phi + int64_t(k0 + min(wave + 4 * u, kc - 1)) * ldp + row0, offA);
+    if constexpr (WITH_F) {
+        if constexpr (INTERIOR) {
+            const uint32_t offB = (uint32_t(bs) * uint32_t(ldxi) + uint32_t(min(bk, kc - 1))) * 8u;
+#pragma unroll
+            for (int u = 0; u < UB; ++u) bv[u] = *at_bytes(xi + int64_t(j0 + 8 * u) * ldxi + k0, offB);
+        } else {
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int col = min(j0 + bs + 8 * u, m - 1);
+                bv[u] = xi[int64_t(col) * ldxi + k0 + min(bk, kc - 1)];
+            }
+        }
+    }
+}
+
 // One tile of kle_gemm_kernel.  INTERIOR: the tile's 64 rows and 64 samples lie inside F
 // and the leading dimensions are narrow, so xi and F are addressed by a scalar base per
 // sample column plus a fixed 32-bit lane offset; otherwise every lane clamps its own 64-bit
@@ -81,27 +105,13 @@ __device__ __forceinline__ void kle_gemm_tile(KgLds &L, const double *__restrict
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[t][r] = 0.0;
     constexpr int kUA = (kKgK * kKgRows) / 256, kUB = (kKgK * kKgCols) / 256;
+    // every load of a chunk is issued before the first wait; addresses are clamped into the
+    // arrays and the out-of-range values replaced by zeros in LDS.  The next chunk's loads are
+    // issued once this chunk is in LDS, so that they are in flight during its products.
+    double av[kUA], bv[WITH_F ? kUB : 1];
+    kg_load_chunk<WITH_F, INTERIOR>(av, bv, Phi, ldp, row0, offA, wave, K, 0, xi, ldxi, m, j0, bs, bk);
     for (int k0 = 0; k0 < K; k0 += kKgK) {
         const int kc = min(kKgK, K - k0);
-        // every load of a step is issued before the first wait; addresses are clamped into
-        // the arrays and the out-of-range values replaced by zeros afterwards
-        double av[kUA], bv[WITH_F ? kUB : 1];
-#pragma unroll
-        for (int u = 0; u < kUA; ++u)
-            av[u] = *at_bytes(Phi + int64_t(k0 + min(wave + 4 * u, kc - 1)) * ldp + row0, offA);
-        if constexpr (WITH_F) {
-            if constexpr (INTERIOR) {
-                const uint32_t offB = (uint32_t(bs) * uint32_t(ldxi) + uint32_t(min(bk, kc - 1))) * 8u;
-#pragma unroll
-                for (int u = 0; u < kUB; ++u) bv[u] = *at_bytes(xi + int64_t(j0 + 8 * u) * ldxi + k0, offB);
-            } else {
-#pragma unroll
-                for (int u = 0; u < kUB; ++u) {
-                    const int col = min(j0 + bs + 8 * u, m - 1);
-                    bv[u] = xi[int64_t(col) * ldxi + k0 + min(bk, kc - 1)];
-                }
-            }
-        }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kUA; ++u) {
@@ -120,6 +130,8 @@ __device__ __forceinline__ void kle_gemm_tile(KgLds &L, const double *__restrict
             }
         }
         __syncthreads();
+        if (k0 + kKgK < K)
+            kg_load_chunk<WITH_F, INTERIOR>(av, bv, Phi, ldp, row0, offA, wave, K, k0 + kKgK, xi, ldxi, m, j0, bs, bk);
         if constexpr (WITH_F) {
             const int nkq = (kc + 3) / 4;
 #pragma unroll
