@@ -334,9 +334,18 @@ kl_status kl_symeig(int32_t n, const double *A, double *w, double *Z);
  * column-major; all n eigenvalues in w): eigenvalues by QR on the tridiagonal form
  * without vectors, eigenvectors by inverse iteration on the tridiagonal form (vectors
  * of eigenvalues closer than 1e-3 ||T|| orthogonalised against each other), then the
- * Householder back-transformation.  Used by the Rayleigh-Ritz step of kl_eigs, which
- * needs only the kept Ritz vectors.  Errors: KL_EINVAL, KL_ENUMERIC, KL_ENOCONV. */
+ * Householder back-transformation.  Errors: KL_EINVAL, KL_ENUMERIC, KL_ENOCONV. */
 kl_status kl_symeig_partial(int32_t n, const double *A, double *w, double *Z, int32_t nv);
+
+/* The nv largest eigenvalues only (w: host, nv entries, descending) and their orthonormal
+ * eigenvectors (Z: host, n x nv column-major) of the n x n row-major symmetric A (host, read
+ * only): Householder tridiagonalisation, the eigenvalues by bisection on Sturm counts (to an
+ * interval of 2 eps |lambda|), eigenvectors by inverse iteration as in kl_symeig_partial, and
+ * the back-transformation; the bisection, the inverse iteration (in groups of whole clusters)
+ * and the back-transformation run on a persistent team of up to 8 host threads when it is
+ * free, with results independent of the team.  The solver used by the Rayleigh-Ritz step of
+ * kl_eigs.  Errors: KL_EINVAL, KL_ENUMERIC (non-finite input), KL_ENOCONV. */
+kl_status kl_symeig_top(int32_t n, const double *A, int32_t nv, double *w, double *Z);
 
 /* ---- Batches of problems -------------------------------------------------------------
  * Many problems of uneven size (same dimension) solved together: one apply of the whole

@@ -24,7 +24,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_apply_noalloc", "kl_stage5", "kl_get_points",
-           "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_profile_enable", "kl_profile_read",
+           "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_symeig_top", "kl_profile_enable", "kl_profile_read",
            "kl_stage5_config", "kl_stage5_symmetric", "kl_apply_config", "kl_set_cov", "kl_setup_patches", "kl_patch_count", "kl_patch_info",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
            "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_set_subspace",
@@ -97,6 +97,7 @@ def lib():
                               ctypes.c_int64, ctypes.POINTER(KLEigsReport), P]
         L.kl_symeig.argtypes = [ctypes.c_int32, P, P, P]
         L.kl_symeig_partial.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
+        L.kl_symeig_top.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, P]
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
         L.kl_stage5_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
         L.kl_stage5_symmetric.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]
@@ -569,6 +570,17 @@ def symeig_partial(A, nv):
     check(lib().kl_symeig_partial(n, ctypes.c_void_p(A.ctypes.data), ctypes.c_void_p(w.ctypes.data),
                                   ctypes.c_void_p(Z.ctypes.data), int(nv)))
     return w, Z[:nv].T.copy()
+
+
+def symeig_top(A, nv):
+    """The nv largest eigenvalues (descending) and their eigenvectors."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    w = np.zeros(max(nv, 1))
+    Z = np.zeros((max(nv, 1), n))
+    check(lib().kl_symeig_top(n, ctypes.c_void_p(A.ctypes.data), int(nv), ctypes.c_void_p(w.ctypes.data),
+                              ctypes.c_void_p(Z.ctypes.data)))
+    return w[:nv], Z[:nv].T.copy()
 
 
 def report_dict(rep, status=0):

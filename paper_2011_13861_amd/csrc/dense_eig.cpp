@@ -5,10 +5,18 @@
 // every reflection and rotation so that A = Z diag(w) Z^T.  Matrices are small (the
 // projected operator of the block eigensolver, n <= a few hundred).
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
 #include <limits>
+#include <mutex>
 #include <numeric>
+#include <thread>
 #include <vector>
+
+#include <unistd.h>
 
 #include "kl_internal.h"
 
@@ -275,32 +283,41 @@ inline void tri_lu_solve(int n, const double *rdd, const double *dl, const doubl
     for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) * rdd[i];
 }
 
-// Eigenvectors of the tridiagonal (d, e) for its nv largest eigenvalues w[0..nv-1]
-// (descending) by inverse iteration: two steps from a seeded random vector (the shifts are
-// eigenvalues accurate to rounding, so the second step already converges); eigenvalues
-// closer than 1e-3 ||T|| form a cluster whose vectors are orthogonalised against each
-// other at every step, and equal ones are separated by a tiny shift.  X: n x nv,
-// column-major.  work: 5 n doubles, piv: n chars.  Returns false on a breakdown.
-KL_HOST_CLONES
-bool tridiagonal_vectors_raw(int n, const double *d, const double *e, const double *w, int nv, double *X,
-                             double *work, char *piv) {
+// Tolerances of the inverse iteration below, from ||T||_1 of the tridiagonal (d, e).
+struct InvIterTol {
+    double ortol, pertol, tiny;
+};
+InvIterTol inv_iter_tol(int n, const double *d, const double *e) {
     const double eps = std::numeric_limits<double>::epsilon();
     double tnorm = 0.0;
     for (int i = 0; i < n; ++i)
         tnorm = std::max(tnorm, std::fabs(d[i]) + (i + 1 < n ? std::fabs(e[i]) : 0.0) + (i > 0 ? std::fabs(e[i - 1]) : 0.0));
     if (tnorm == 0.0) tnorm = 1.0;
-    const double ortol = 1e-3 * tnorm, pertol = 10.0 * eps * tnorm, tiny = eps * tnorm;
+    return {1e-3 * tnorm, 10.0 * eps * tnorm, eps * tnorm};
+}
+
+// Eigenvectors j0 .. j1 - 1 of the tridiagonal (d, e) for the eigenvalues w[j] (descending)
+// by inverse iteration: two steps from a seeded random vector (the shifts are eigenvalues
+// accurate to rounding, so the second step already converges); eigenvalues closer than
+// ortol form a cluster whose vectors are orthogonalised against each other at every step,
+// and equal ones are separated by a tiny shift.  j0 must start a cluster (j0 = 0, or
+// w[j0 - 1] - w[j0] > ortol).  The start of vector j is entries j n + 1 .. j n + n of one
+// splitmix64 stream, so that vectors can be computed in any order.  X: n x nv, column-major
+// (column j written).  work: 5 n doubles, piv: n chars.  Returns false on a breakdown.
+KL_HOST_CLONES
+bool tridiagonal_vectors_range(int n, const double *d, const double *e, const double *w, int j0, int j1,
+                               const InvIterTol &tol, double *X, double *work, char *piv) {
     double *rdd = work, *dl = work + n, *du = work + 2 * n, *du2 = work + 3 * n;
-    uint64_t state = 0x2545F4914F6CDD1Dull;
-    int cs = 0;                  // first index of the current cluster
+    int cs = j0;                 // first index of the current cluster
     double lam_prev = 0.0;
-    for (int j = 0; j < nv; ++j) {
+    for (int j = j0; j < j1; ++j) {
         double lam = w[j];
-        if (j > 0 && w[j - 1] - w[j] > ortol) cs = j;
-        if (j > cs && lam_prev - lam < pertol) lam = lam_prev - pertol;
+        if (j > j0 && w[j - 1] - w[j] > tol.ortol) cs = j;
+        if (j > cs && lam_prev - lam < tol.pertol) lam = lam_prev - tol.pertol;
         lam_prev = lam;
-        tri_lu_factor(n, d, e, lam, tiny, rdd, dl, du, du2, piv);
+        tri_lu_factor(n, d, e, lam, tol.tiny, rdd, dl, du, du2, piv);
         double *x = X + size_t(j) * n;
+        uint64_t state = 0x2545F4914F6CDD1Dull + uint64_t(j) * uint64_t(n) * 0x9E3779B97F4A7C15ull;
         for (int i = 0; i < n; ++i) {     // splitmix64 uniform on [-1, 1)
             uint64_t z = (state += 0x9E3779B97F4A7C15ull);
             z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -331,6 +348,137 @@ bool tridiagonal_vectors_raw(int n, const double *d, const double *e, const doub
     return true;
 }
 
+// All nv vectors in one sequence.
+bool tridiagonal_vectors_raw(int n, const double *d, const double *e, const double *w, int nv, double *X,
+                             double *work, char *piv) {
+    return tridiagonal_vectors_range(n, d, e, w, 0, nv, inv_iter_tol(n, d, e), X, work, piv);
+}
+
+// The largest nv eigenvalues of the symmetric tridiagonal (d, e2 = squared off-diagonals)
+// by bisection on the Sturm count (the number of negative pivots of the LDL^T factorisation
+// of T - x I is the number of eigenvalues below x; a pivot smaller than pivmin in magnitude
+// is replaced by -pivmin), from the Gershgorin interval [glo, ghi], until an interval is no
+// wider than 2 eps max(|lo|, |hi|) + pivmin.  Eigenvalues j0 .. j0 + kBisectChains - 1 (the
+// chains interleaved, so that their divisions overlap); w[j] for j < nv, descending.
+constexpr int kBisectChains = 16;
+KL_HOST_CLONES
+void bisect_top(int n, const double *d, const double *e2, double pivmin, double glo, double ghi, int j0, int nv,
+                double *w) {
+    constexpr int C = kBisectChains;
+    const double eps = std::numeric_limits<double>::epsilon();
+    double lo[C], hi[C];
+    int below[C];                                  // n - 1 - j: eigenvalues below the wanted one
+    for (int c = 0; c < C; ++c) {
+        lo[c] = glo;
+        hi[c] = ghi;
+        below[c] = n - 1 - std::min(j0 + c, nv - 1);
+    }
+    for (int it = 0; it < 128; ++it) {
+        double mid[C], q[C];
+        int cnt[C];
+        bool done = true;
+        for (int c = 0; c < C; ++c) {
+            mid[c] = 0.5 * (lo[c] + hi[c]);
+            if (hi[c] - lo[c] > 2.0 * eps * std::max(std::fabs(lo[c]), std::fabs(hi[c])) + pivmin) done = false;
+        }
+        if (done) break;
+        for (int c = 0; c < C; ++c) {
+            const double t = d[0] - mid[c];
+            q[c] = std::fabs(t) < pivmin ? -pivmin : t;
+            cnt[c] = q[c] < 0.0 ? 1 : 0;
+        }
+        for (int i = 1; i < n; ++i) {
+            const double di = d[i], ei = e2[i - 1];
+#pragma omp simd
+            for (int c = 0; c < C; ++c) {
+                double t = (di - mid[c]) - ei / q[c];
+                t = std::fabs(t) < pivmin ? -pivmin : t;
+                q[c] = t;
+                cnt[c] += t < 0.0 ? 1 : 0;
+            }
+        }
+        for (int c = 0; c < C; ++c) {
+            if (cnt[c] <= below[c]) lo[c] = mid[c];
+            else hi[c] = mid[c];
+        }
+    }
+    for (int c = 0; c < C && j0 + c < nv; ++c) w[j0 + c] = 0.5 * (lo[c] + hi[c]);
+}
+
+// A persistent team of host threads for the projected eigensolve: the tasks of a job are
+// taken in order from an atomic counter by the calling thread and the workers.  One job at a
+// time: a caller that finds the team busy (the batched solver resumes several problems on
+// host threads at once) runs its tasks alone.  Workers spin briefly after a job (the next one
+// of the same solve follows within a fraction of a millisecond), then sleep.
+class HostTeam {
+public:
+    static HostTeam &get() {
+        static HostTeam *team = new HostTeam();    // never destroyed: workers live as long as the process
+        return *team;
+    }
+    void run(int ntasks, const std::function<void(int)> &fn) {
+        std::unique_lock<std::mutex> job_lock(job_, std::try_to_lock);
+        // (a forked child has none of the workers)
+        if (!job_lock.owns_lock() || workers_.empty() || ntasks < 2 || getpid() != pid_) {
+            for (int t = 0; t < ntasks; ++t) fn(t);
+            return;
+        }
+        // a worker that is late for the previous job may take a task of this one as soon as
+        // next_ is reset: everything it reads is written before, done_ included
+        fn_ = &fn;
+        ntasks_ = ntasks;
+        done_.store(0);
+        next_.store(0);
+        {
+            std::lock_guard<std::mutex> g(m_);
+            gen_.fetch_add(1, std::memory_order_release);
+        }
+        cv_.notify_all();
+        take_tasks();
+        while (done_.load(std::memory_order_acquire) < ntasks) std::this_thread::yield();
+    }
+
+private:
+    HostTeam() : pid_(getpid()) {
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int nw = int(std::min(7u, hw > 1 ? hw - 1 : 0u));
+        for (int i = 0; i < nw; ++i) workers_.emplace_back([this] { loop(); });
+        for (auto &t : workers_) t.detach();
+    }
+    void take_tasks() {
+        for (;;) {
+            const int t = next_.fetch_add(1);
+            if (t >= ntasks_) return;
+            (*fn_)(t);
+            done_.fetch_add(1, std::memory_order_release);
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            // spin for about 0.3 ms on the job generation, then sleep until the next job
+            const auto t0 = std::chrono::steady_clock::now();
+            while (gen_.load(std::memory_order_acquire) == seen &&
+                   std::chrono::steady_clock::now() - t0 < std::chrono::microseconds(300))
+                std::this_thread::yield();
+            if (gen_.load(std::memory_order_acquire) == seen) {
+                std::unique_lock<std::mutex> l(m_);
+                cv_.wait(l, [&] { return gen_.load(std::memory_order_acquire) != seen; });
+            }
+            seen = gen_.load(std::memory_order_acquire);
+            take_tasks();
+        }
+    }
+    const pid_t pid_;
+    std::mutex job_, m_;
+    std::condition_variable cv_;
+    std::vector<std::thread> workers_;
+    std::atomic<uint64_t> gen_{0};
+    std::atomic<int> next_{0}, done_{0};
+    int ntasks_ = 0;
+    const std::function<void(int)> *fn_ = nullptr;
+};
+
 }  // namespace
 
 // All n eigenvalues (descending, w) and the eigenvectors of the nv largest (Z, n x nv
@@ -353,6 +501,70 @@ bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv) {
     // back-transformation: X <- H_0 H_1 ... H_{n-3} X
     apply_reflectors(n, nv, V, beta, X.data(), false);
     std::copy(X.begin(), X.end(), Z);
+    return true;
+}
+
+// The nv largest eigenvalues (descending, w[0..nv-1]) and their eigenvectors (Z, n x nv
+// column-major): tridiagonalisation, the eigenvalues by bisection (tasks of 16 on the host
+// team), eigenvectors of the tridiagonal by inverse iteration (tasks of whole clusters), and
+// the back-transformation (column chunks).  Results do not depend on how the tasks are
+// shared.
+bool sym_eig_top(int n, const double *A, int nv, double *w, double *Z) {
+    if (n <= 0 || nv <= 0) return true;
+    if (nv >= n || n <= 2) {
+        std::vector<double> wf(n), Zf(size_t(n) * n);
+        if (!sym_eig(n, A, wf.data(), Zf.data())) return false;
+        std::copy(wf.begin(), wf.begin() + std::min(nv, n), w);
+        std::copy(Zf.begin(), Zf.begin() + size_t(n) * std::min(nv, n), Z);
+        return true;
+    }
+    std::vector<double> d, e, V, beta;
+    tridiagonalise(n, A, d, e, V, beta);
+    // Gershgorin interval, widened by a few ulps of ||T||, and the pivot floor
+    std::vector<double> e2(n, 0.0);
+    double glo = std::numeric_limits<double>::infinity(), ghi = -glo, e2max = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+        glo = std::min(glo, d[i] - r);
+        ghi = std::max(ghi, d[i] + r);
+        if (i + 1 < n) {
+            e2[i] = e[i] * e[i];
+            e2max = std::max(e2max, e2[i]);
+        }
+    }
+    const double tn = std::max(std::fabs(glo), std::fabs(ghi));
+    const double eps = std::numeric_limits<double>::epsilon();
+    glo -= 4.0 * eps * tn + std::numeric_limits<double>::min();
+    ghi += 4.0 * eps * tn + std::numeric_limits<double>::min();
+    const double pivmin = std::numeric_limits<double>::min() * std::max(1.0, e2max);
+    HostTeam &team = HostTeam::get();
+    team.run((nv + kBisectChains - 1) / kBisectChains, [&](int t) {
+        bisect_top(n, d.data(), e2.data(), pivmin, glo, ghi, t * kBisectChains, nv, w);
+    });
+    for (int j = 0; j < nv; ++j)
+        if (!std::isfinite(w[j])) return false;
+    // inverse iteration in tasks of whole clusters (about 8 vectors each where clusters allow)
+    const InvIterTol tol = inv_iter_tol(n, d.data(), e.data());
+    std::vector<int> starts{0};
+    for (int j = 1; j < nv; ++j)
+        if (w[j - 1] - w[j] > tol.ortol && j - starts.back() >= 8) starts.push_back(j);
+    starts.push_back(nv);
+    const int ntask = int(starts.size()) - 1;
+    std::vector<double> work(size_t(5) * n * ntask);
+    std::vector<char> piv(size_t(n) * ntask);
+    std::vector<char> ok(ntask, 1);
+    team.run(ntask, [&](int t) {
+        ok[t] = tridiagonal_vectors_range(n, d.data(), e.data(), w, starts[t], starts[t + 1], tol, Z,
+                                          work.data() + size_t(5) * n * t, piv.data() + size_t(n) * t) ? 1 : 0;
+    });
+    for (int t = 0; t < ntask; ++t)
+        if (!ok[t]) return false;
+    // back-transformation Z <- H_0 H_1 ... H_{n-3} Z, in chunks of 8 columns
+    constexpr int kCols = 8;
+    team.run((nv + kCols - 1) / kCols, [&](int t) {
+        const int c0 = t * kCols, nc = std::min(kCols, nv - c0);
+        apply_reflectors_raw(n, nc, V.data(), beta.data(), Z + size_t(c0) * n, false);
+    });
     return true;
 }
 
@@ -424,5 +636,19 @@ extern "C" kl_status kl_symeig(int32_t n, const double *A, double *w, double *Z)
     for (int64_t i = 0; i < int64_t(n) * n; ++i)
         if (!std::isfinite(A[i])) { kl::set_error("kl_symeig: non-finite input"); return KL_ENUMERIC; }
     if (!kl::sym_eig(n, A, w, Z)) { kl::set_error("kl_symeig: QR iteration did not converge"); return KL_ENOCONV; }
+    return KL_OK;
+}
+
+extern "C" kl_status kl_symeig_top(int32_t n, const double *A, int32_t nv, double *w, double *Z) {
+    if (n < 0 || nv < 0 || nv > n || (nv > 0 && (!A || !w || !Z))) {
+        kl::set_error("kl_symeig_top: invalid arguments");
+        return KL_EINVAL;
+    }
+    for (int64_t i = 0; i < int64_t(n) * n; ++i)
+        if (!std::isfinite(A[i])) { kl::set_error("kl_symeig_top: non-finite input"); return KL_ENUMERIC; }
+    if (!kl::sym_eig_top(n, A, nv, w, Z)) {
+        kl::set_error("kl_symeig_top: eigensolve failed");
+        return KL_ENOCONV;
+    }
     return KL_OK;
 }

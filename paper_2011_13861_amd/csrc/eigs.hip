@@ -617,7 +617,7 @@ kl_status EigRun::rr_step() {
     std::vector<double> Hm(size_t(m) * m);
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < m; ++j) Hm[size_t(i) * m + j] = S.H[size_t(i) * S.mmax + j];
-    // all Ritz values, and the Ritz vectors of the kk kept ones (m x kk, column-major)
+    // the kk kept Ritz values (theta[0 .. kk - 1]) and their Ritz vectors (m x kk, column-major)
     const int kk = std::min(S.keep, m);
     theta.assign(m, 0.0);
     Sm.assign(size_t(m) * kk, 0.0);
@@ -644,7 +644,7 @@ kl_status EigRun::rr_step() {
     double eig_s = 0.0;
     auto solve_projected = [&]() {
         const auto te0 = clock::now();
-        eig_ok = sym_eig_partial(m, Hm.data(), theta.data(), Sm.data(), kk);
+        eig_ok = sym_eig_top(m, Hm.data(), kk, theta.data(), Sm.data());
         eig_s = std::chrono::duration<double>(clock::now() - te0).count();
     };
     if (speculate) {

@@ -1,4 +1,4 @@
-"""Host dense symmetric eigensolvers of the library (kl_symeig, kl_symeig_partial), used by
+"""Host dense symmetric eigensolvers of the library (kl_symeig, kl_symeig_partial, kl_symeig_top), used by
 the Rayleigh-Ritz step of the eigensolver, against numpy.linalg.eigh: eigenvalues,
 residuals ||A z - w z||, orthonormality, on random matrices, matrices with exactly
 repeated eigenvalues (the spectra of symmetric domains), graded spectra and tiny sizes."""
@@ -33,8 +33,8 @@ CASES = _cases()
 
 def _check(A, w, Z, nv):
     n = A.shape[0]
-    ref = np.sort(np.linalg.eigvalsh(A))[::-1]
-    scale = max(np.max(np.abs(ref)), 1e-300)
+    ref = np.sort(np.linalg.eigvalsh(A))[::-1][:len(w)]
+    scale = max(np.max(np.abs(ref)), 1e-300) if len(ref) else 1.0
     assert np.all(np.abs(w - ref) <= 1e-12 * scale * max(1.0, np.sqrt(n)))
     assert np.all(np.diff(w) <= 0)
     if nv:
@@ -57,8 +57,51 @@ def test_symeig_partial(name, A):
         _check(A, w, Z, nv)
 
 
+@pytest.mark.parametrize("name,A", CASES, ids=[c[0] for c in CASES])
+def test_symeig_top(name, A):
+    """Only the nv largest pairs (bisection, inverse iteration in cluster groups on host
+    threads): the same bars, and the same eigenvectors as the all-eigenvalue path up to sign
+    where the eigenvalues are simple."""
+    n = A.shape[0]
+    for nv in sorted({1, max(1, n // 3), min(n, 66), n}):
+        w, Z = B.symeig_top(A, nv)
+        assert w.shape == (nv,) and Z.shape == (n, nv)
+        _check(A, w, Z, nv)
+        wp, Zp = B.symeig_partial(A, nv)
+        gaps = np.abs(np.diff(np.sort(np.linalg.eigvalsh(A))[::-1]))
+        scale = max(np.max(np.abs(wp)), 1e-300)
+        for j in range(nv):
+            simple = (j == 0 or gaps[j - 1] > 1e-6 * scale) and (j == n - 1 or gaps[j] > 1e-6 * scale)
+            if simple:
+                assert abs(abs(Z[:, j] @ Zp[:, j]) - 1.0) <= 1e-9, (name, nv, j)
+
+
+def test_symeig_top_repeats_and_threads():
+    """Repeated calls, and calls from several host threads at once (the thread team serves one
+    call at a time, the others run alone), give identical results."""
+    import threading
+    name, A = CASES[5]
+    w0, Z0 = B.symeig_top(A, 40)
+    out = [None] * 6
+
+    def run(i):
+        out[i] = B.symeig_top(A, 40)
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(6)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for w, Z in out:
+        assert np.array_equal(w, w0) and np.array_equal(Z, Z0)
+
+
 def test_symeig_errors():
     with pytest.raises(B.KLError):
         B.symeig(np.array([[np.nan]]))
     with pytest.raises(B.KLError):
         B.symeig_partial(np.eye(3), 4)
+    with pytest.raises(B.KLError):
+        B.symeig_top(np.eye(3), 4)
+    with pytest.raises(B.KLError):
+        B.symeig_top(np.array([[1.0, np.inf], [np.inf, 1.0]]), 1)
