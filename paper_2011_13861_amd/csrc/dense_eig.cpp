@@ -507,9 +507,9 @@ bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv) {
 // The nv largest eigenvalues (descending, w[0..nv-1]) and their eigenvectors (Z, n x nv
 // column-major): tridiagonalisation, the eigenvalues by bisection (tasks of 16 on the host
 // team), eigenvectors of the tridiagonal by inverse iteration (tasks of whole clusters), and
-// the back-transformation (column chunks).  Results do not depend on how the tasks are
-// shared.
-bool sym_eig_top(int n, const double *A, int nv, double *w, double *Z) {
+// the back-transformation (column chunks); use_team = false runs the tasks on the calling
+// thread.  Results do not depend on how the tasks are shared.
+bool sym_eig_top(int n, const double *A, int nv, double *w, double *Z, bool use_team) {
     if (n <= 0 || nv <= 0) return true;
     if (nv >= n || n <= 2) {
         std::vector<double> wf(n), Zf(size_t(n) * n);
@@ -537,8 +537,13 @@ bool sym_eig_top(int n, const double *A, int nv, double *w, double *Z) {
     glo -= 4.0 * eps * tn + std::numeric_limits<double>::min();
     ghi += 4.0 * eps * tn + std::numeric_limits<double>::min();
     const double pivmin = std::numeric_limits<double>::min() * std::max(1.0, e2max);
-    HostTeam &team = HostTeam::get();
-    team.run((nv + kBisectChains - 1) / kBisectChains, [&](int t) {
+    // the tasks below on the host team, or one after another on this thread
+    auto run = [&](int ntasks, const std::function<void(int)> &fn) {
+        if (use_team) HostTeam::get().run(ntasks, fn);
+        else
+            for (int t = 0; t < ntasks; ++t) fn(t);
+    };
+    run((nv + kBisectChains - 1) / kBisectChains, [&](int t) {
         bisect_top(n, d.data(), e2.data(), pivmin, glo, ghi, t * kBisectChains, nv, w);
     });
     for (int j = 0; j < nv; ++j)
@@ -553,7 +558,7 @@ bool sym_eig_top(int n, const double *A, int nv, double *w, double *Z) {
     std::vector<double> work(size_t(5) * n * ntask);
     std::vector<char> piv(size_t(n) * ntask);
     std::vector<char> ok(ntask, 1);
-    team.run(ntask, [&](int t) {
+    run(ntask, [&](int t) {
         ok[t] = tridiagonal_vectors_range(n, d.data(), e.data(), w, starts[t], starts[t + 1], tol, Z,
                                           work.data() + size_t(5) * n * t, piv.data() + size_t(n) * t) ? 1 : 0;
     });
@@ -561,7 +566,7 @@ bool sym_eig_top(int n, const double *A, int nv, double *w, double *Z) {
         if (!ok[t]) return false;
     // back-transformation Z <- H_0 H_1 ... H_{n-3} Z, in chunks of 8 columns
     constexpr int kCols = 8;
-    team.run((nv + kCols - 1) / kCols, [&](int t) {
+    run((nv + kCols - 1) / kCols, [&](int t) {
         const int c0 = t * kCols, nc = std::min(kCols, nv - c0);
         apply_reflectors_raw(n, nc, V.data(), beta.data(), Z + size_t(c0) * n, false);
     });

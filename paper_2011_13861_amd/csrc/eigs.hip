@@ -644,7 +644,9 @@ kl_status EigRun::rr_step() {
     double eig_s = 0.0;
     auto solve_projected = [&]() {
         const auto te0 = clock::now();
-        eig_ok = sym_eig_top(m, Hm.data(), kk, theta.data(), Sm.data());
+        // (the batched solver's runs, which proceed in parallel on host threads, keep off the
+        // host team)
+        eig_ok = sym_eig_top(m, Hm.data(), kk, theta.data(), Sm.data(), overlap);
         eig_s = std::chrono::duration<double>(clock::now() - te0).count();
     };
     if (speculate) {

@@ -36,8 +36,9 @@ struct HostSetup {
 bool sym_eig(int n, const double *A, double *w, double *Z);
 // All eigenvalues (descending) and the eigenvectors of the nv largest (Z: n x nv).
 bool sym_eig_partial(int n, const double *A, double *w, double *Z, int nv);
-// The nv largest eigenvalues only (w[0..nv-1], descending) and their eigenvectors (Z, n x nv).
-bool sym_eig_top(int n, const double *A, int nv, double *w, double *Z);
+// The nv largest eigenvalues only (w[0..nv-1], descending) and their eigenvectors (Z, n x nv),
+// parts of the work on the host thread team when use_team is set (same results).
+bool sym_eig_top(int n, const double *A, int nv, double *w, double *Z, bool use_team = true);
 // T = R^{-1} with G = R^T R (host; false on a pivot <= rel_tol max diag(G)).  min_sine
 // (optional) receives min_j R_jj / sqrt(G_jj): the smallest sine of the angle between a
 // column and the span of the columns before it (1 for orthogonal columns).
