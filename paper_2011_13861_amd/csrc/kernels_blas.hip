@@ -223,6 +223,87 @@ __global__ __launch_bounds__(128 * NG) void gemm_nn_kernel(const double *__restr
             }
 }
 
+// The same product for wide S (c > 32) and tall A (N >= kNN2MinRows): a wave owns 16 rows of
+// Out and all TPW <= 8 column tiles, so that A is read once (the kernel above re-reads it in
+// each group of column tiles), and a workgroup of 4 waves owns 64 rows.  S is staged through
+// LDS in chunks of 64 k (the next chunk in registers while the current one is used) and the
+// A operands of a chunk (16 steps, one double per lane each) are loaded one chunk ahead.
+// The k steps of every tile run in the same order as in the kernel above (the same results).
+constexpr int kNN2Chunk = 64;
+constexpr int64_t kNN2MinRows = 16384;   // one 64-row workgroup per compute unit at least
+
+template <int TPW>
+__global__ __launch_bounds__(256) void gemm_nn_wide_kernel(const double *__restrict__ A, int64_t lda, int m,
+                                                           const double *__restrict__ S, int64_t lds, int c,
+                                                           int64_t N, double alpha, double beta,
+                                                           double *__restrict__ Out, int64_t ldo) {
+    constexpr int kC = 16 * TPW;
+    __shared__ double sS[kNN2Chunk][kC + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t row0 = int64_t(blockIdx.x) * 64 + 16 * w;
+    const int64_t rowc = min(row0 + li, N - 1);            // clamped: rows past N are not stored
+    doublex4 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    constexpr int kSteps = kNN2Chunk / 4;
+    constexpr int kPS = (kNN2Chunk * kC) / 256;              // S elements per thread per chunk
+    double ps[kPS], pa[kSteps];
+    // loads clamped into S and A (m >= 1 here); the values past m or c are zeroed in use
+    auto load = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < kPS; ++q) {
+            const int e = threadIdx.x + q * 256;
+            const int kk = e % kNN2Chunk, j = e / kNN2Chunk;
+            ps[q] = S[min(k0 + kk, m - 1) + lds * min(j, c - 1)];
+        }
+#pragma unroll
+        for (int st = 0; st < kSteps; ++st) pa[st] = A[rowc + lda * min(k0 + 4 * st + lk, m - 1)];
+    };
+    if (m > 0) load(0);
+    for (int k0 = 0; k0 < m; k0 += kNN2Chunk) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPS; ++q) {
+            const int e = threadIdx.x + q * 256;
+            const int kk = e % kNN2Chunk, j = e / kNN2Chunk;
+            sS[kk][j] = (k0 + kk < m && j < c) ? ps[q] : 0.0;
+        }
+        __syncthreads();
+        double a[kSteps];
+#pragma unroll
+        for (int st = 0; st < kSteps; ++st) a[st] = (k0 + 4 * st + lk < m) ? pa[st] : 0.0;
+        if (k0 + kNN2Chunk < m) load(k0 + kNN2Chunk);
+        const int nst = min(kSteps, (m - k0 + 3) / 4);
+#pragma unroll
+        for (int st = 0; st < kSteps; ++st)
+            if (st < nst)
+#pragma unroll
+                for (int t = 0; t < TPW; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sS[4 * st + lk][16 * t + li], a[st], acc[t], 0, 0, 0);
+    }
+    // acc[t][r] of lane L = Out[row0 + (L & 15)][16 t + (L >> 4) + 4 r]
+    const int64_t row = row0 + li;
+    if (row < N)
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = 16 * t + lk + 4 * r;
+                if (j < c) {
+                    double *o = Out + row + ldo * j;
+                    *o = beta == 0.0 ? alpha * acc[t][r] : alpha * acc[t][r] + beta * *o;
+                }
+            }
+}
+
+template <int TPW>
+void launch_gemm_nn_wide_t(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
+                           double alpha, double beta, double *Out, int64_t ldo, hipStream_t s) {
+    hipLaunchKernelGGL((gemm_nn_wide_kernel<TPW>), dim3(unsigned((N + 63) / 64)), dim3(256), 0, s, A, lda, m, S, lds,
+                       c, N, alpha, beta, Out, ldo);
+}
+
 template <int TPW, int NG>
 void launch_gemm_nn_t(const double *A, int64_t lda, int m, const double *S, int64_t lds, int c, int64_t N,
                       double alpha, double beta, double *Out, int64_t ldo, hipStream_t s) {
@@ -325,6 +406,17 @@ void launch_gemm_nn(const double *A, int64_t lda, int m, const double *S, int64_
         const int cb = std::min(16 * kNNMaxTiles, c - j0);
         const double *Sj = S + int64_t(j0) * lds;
         double *Oj = Out + int64_t(j0) * ldo;
+        if (cb > 32 && N >= kNN2MinRows) {
+            switch ((cb + 15) / 16) {
+            case 3: launch_gemm_nn_wide_t<3>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+            case 4: launch_gemm_nn_wide_t<4>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+            case 5: launch_gemm_nn_wide_t<5>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+            case 6: launch_gemm_nn_wide_t<6>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+            case 7: launch_gemm_nn_wide_t<7>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+            default: launch_gemm_nn_wide_t<8>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
+            }
+            continue;
+        }
         switch ((cb + 15) / 16) {
         case 1: launch_gemm_nn_t<1, 1>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
         case 2: launch_gemm_nn_t<1, 2>(A, lda, mm, Sj, lds, cb, N, alpha, beta, Oj, ldo, s); break;
