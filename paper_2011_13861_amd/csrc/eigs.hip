@@ -50,6 +50,7 @@ struct SolverCache {
     // are formed there while the main stream applies the operator to the next block
     hipStream_t s2 = nullptr;
     hipEvent_t ev = nullptr;    // orders s2 after the basis written on s
+    hipEvent_t ev_wait[2] = {nullptr, nullptr};   // host waits on s and on s2 (polled)
     int64_t N = 0;
     int mcap = 0, ccap = 0;
     double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr;
@@ -108,6 +109,7 @@ struct Solver {
     hipStream_t s = nullptr;
     hipStream_t s2 = nullptr;   // Rayleigh-Ritz stream (NULL: everything on s)
     hipEvent_t ev = nullptr;
+    hipEvent_t ev_wait[2] = {nullptr, nullptr};   // see wait()
     int64_t N = 0;
     int b = 32, k = 1, keep = 1, mmax = 1;
     double *V = nullptr, *AV = nullptr, *Vt = nullptr, *AVt = nullptr, *W = nullptr, *R = nullptr;
@@ -127,6 +129,22 @@ struct Solver {
         os << "kl_eigs: " << what << ": " << hipGetErrorString(e);
         set_error(os.str());
         return e == hipErrorOutOfMemory ? KL_ENOMEM : KL_EHIP;
+    }
+    // Waits on the host for the work queued on st (s or s2) so far.  The waits inside a step
+    // are short (a Gram product, the residual norms), so an event recorded on st is polled:
+    // a blocking stream synchronisation may sleep until an interrupt wakes the thread, which
+    // costs tens of microseconds per wait.  The batched solver's runs (no second stream),
+    // which share the host cores, keep the blocking form.
+    kl_status wait(hipStream_t st) {
+        hipEvent_t e = ev_wait[st == s2 && s2 ? 1 : 0];
+        if (!e || !s2) return check(hipStreamSynchronize(st), "sync");
+        kl_status r;
+        if ((r = check(hipEventRecord(e, st), "event")) != KL_OK) return r;
+        for (;;) {
+            const hipError_t q = hipEventQuery(e);
+            if (q == hipSuccess) return KL_OK;
+            if (q != hipErrorNotReady) return check(q, "event query");
+        }
     }
     // C = A^T B   (A: N x ma, B: N x nb, ld N) -> C (ma x nb, ld ma), device; split-N
     // Gram kernel (tall-skinny shapes)
@@ -160,7 +178,7 @@ struct Solver {
         const double *hc = pin_d2h;
         if ((st = check(hipMemcpyAsync(pin_d2h, C, size_t(c1) * nc * 8, hipMemcpyDeviceToHost, s), "copy H")) != KL_OK)
             return st;
-        if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+        if ((st = wait(s)) != KL_OK) return st;
         for (int j = 0; j < nc; ++j)
             for (int i = 0; i < c1; ++i) {
                 const double v = hc[size_t(j) * c1 + i];
@@ -195,7 +213,7 @@ struct Solver {
         if ((st = check(hipMemcpyAsync(pin_d2h, C, size_t(mt) * ncols * 8, hipMemcpyDeviceToHost, s),
                         "copy Gram")) != KL_OK)
             return st;
-        if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+        if ((st = wait(s)) != KL_OK) return st;
         std::vector<double> G(size_t(ncols) * ncols);
         for (int j = 0; j < ncols; ++j)
             for (int i = 0; i < ncols; ++i) G[size_t(i) * ncols + j] = pin_d2h[size_t(j) * mt + m + i];
@@ -269,7 +287,7 @@ struct Solver {
             if ((st = check(hipMemcpyAsync(pin_d2h, C, size_t(ncols) * ncols * 8, hipMemcpyDeviceToHost, s),
                             "copy G")) != KL_OK)
                 return st;
-            if ((st = check(hipStreamSynchronize(s), "sync")) != KL_OK) return st;
+            if ((st = wait(s)) != KL_OK) return st;
             G.assign(pin_d2h, pin_d2h + size_t(ncols) * ncols);
             for (int i = 0; i < ncols; ++i)
                 for (int j = i + 1; j < ncols; ++j) {
@@ -334,6 +352,9 @@ kl_status ensure_solver_stream(kl_problem *P) {
     if (e == hipSuccess && !c.s2 && (e = hipStreamCreate(&c.s2)) != hipSuccess) c.s2 = nullptr;
     if (e == hipSuccess && !c.ev && (e = hipEventCreateWithFlags(&c.ev, hipEventDisableTiming)) != hipSuccess)
         c.ev = nullptr;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        if (!c.ev_wait[i] && (e = hipEventCreateWithFlags(&c.ev_wait[i], hipEventDisableTiming)) != hipSuccess)
+            c.ev_wait[i] = nullptr;
     if (e != hipSuccess) {
         set_error(std::string("kl_eigs: stream: ") + hipGetErrorString(e));
         return KL_EHIP;
@@ -437,6 +458,8 @@ void free_solver_cache(SolverCache *c) {
     if (c->s) hipStreamDestroy(c->s);
     if (c->s2) hipStreamDestroy(c->s2);
     if (c->ev) hipEventDestroy(c->ev);
+    for (hipEvent_t e : c->ev_wait)
+        if (e) hipEventDestroy(e);
     delete c;
 }
 
@@ -518,6 +541,8 @@ kl_status EigRun::begin(const double *x0, int nvec0) {
         S.dflag = c.dflag;
         S.s2 = overlap ? c.s2 : nullptr;
         S.ev = c.ev;
+        S.ev_wait[0] = c.ev_wait[0];
+        S.ev_wait[1] = c.ev_wait[1];
         S.pin_d2h = c.pin;
         S.pin_T = c.pin + c.pin_region;
         S.pin_S = c.pin + 2 * c.pin_region;
@@ -688,7 +713,7 @@ kl_status EigRun::rr_step() {
                       "copy norms")) != KL_OK)
         return st;
     // every later use of Vt, AVt, R and dtheta is queued after this host synchronisation
-    if ((st = S.check(hipStreamSynchronize(rs), "sync")) != KL_OK) return st;
+    if ((st = S.wait(rs)) != KL_OK) return st;
     norms.assign(S.pin_norm, S.pin_norm + kk);
     const double t1 = std::fabs(theta[0]);
     converged = 0;
