@@ -347,6 +347,19 @@ kl_status kl_symeig_partial(int32_t n, const double *A, double *w, double *Z, in
  * kl_eigs.  Errors: KL_EINVAL, KL_ENUMERIC (non-finite input), KL_ENOCONV. */
 kl_status kl_symeig_top(int32_t n, const double *A, int32_t nv, double *w, double *Z);
 
+/* The eigensolver's tall-skinny FP64 product (Ritz vectors X = V S, projections):
+ * Out (N x c) = alpha A (N x m) S (m x c) + beta Out, device arrays, column-major with leading
+ * dimensions lda >= N, lds >= m, ldo >= N; beta = 0 does not read Out; m = 0 gives beta Out
+ * (A and S may then be NULL).  Out must not overlap A or S.  On the FP64 matrix cores: a
+ * workgroup owns 32 rows and up to 128 columns (S staged in LDS in chunks of the
+ * contraction, A read from memory with the next chunk in flight), or for more than 32
+ * columns and at least 16384 rows 64 rows with each wave owning 16 rows and every column
+ * tile; every output entry adds its m products in the order of k either way.  Asynchronous
+ * on `stream` (a hipStream_t, NULL = default stream); allocates nothing.  N <= 2^36.
+ * Errors: KL_EINVAL (sizes, leading dimensions, NULL pointers), KL_EHIP (launch failure). */
+kl_status kl_gemm_tall(int64_t N, int32_t m, int32_t c, const double *A, int64_t lda, const double *S,
+                       int64_t lds, double alpha, double beta, double *Out, int64_t ldo, void *stream);
+
 /* ---- Batches of problems -------------------------------------------------------------
  * Many problems of uneven size (same dimension) solved together: one apply of the whole
  * batch is one replay of a captured HIP graph of 2 dim + 3 launches (batched Kronecker

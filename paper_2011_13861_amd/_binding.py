@@ -24,7 +24,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_apply_noalloc", "kl_stage5", "kl_get_points",
-           "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_symeig_top", "kl_profile_enable", "kl_profile_read",
+           "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_symeig_top", "kl_gemm_tall", "kl_profile_enable", "kl_profile_read",
            "kl_stage5_config", "kl_stage5_symmetric", "kl_apply_config", "kl_set_cov", "kl_setup_patches", "kl_patch_count", "kl_patch_info",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
            "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_set_subspace",
@@ -98,6 +98,8 @@ def lib():
         L.kl_symeig.argtypes = [ctypes.c_int32, P, P, P]
         L.kl_symeig_partial.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
         L.kl_symeig_top.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, P]
+        L.kl_gemm_tall.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, P,
+                                   ctypes.c_int64, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64, P]
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
         L.kl_stage5_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
         L.kl_stage5_symmetric.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]
@@ -581,6 +583,18 @@ def symeig_top(A, nv):
     check(lib().kl_symeig_top(n, ctypes.c_void_p(A.ctypes.data), int(nv), ctypes.c_void_p(w.ctypes.data),
                               ctypes.c_void_p(Z.ctypes.data)))
     return w[:nv], Z[:nv].T.copy()
+
+
+def gemm_tall(A, S, out, alpha=1.0, beta=0.0, stream=None):
+    """out (N x c) = alpha A S + beta out on the device (kl_gemm_tall): FP64 column-major
+    blocks A (N x m), S (m x c) and out (N x c); m = 0 (S with no rows) gives beta out."""
+    N, c = int(out.shape[0]), int(out.shape[1])
+    m = int(S.shape[0])
+    if m and (A.shape[0] != N or A.shape[1] != m or S.shape[1] != c):
+        raise ValueError("shapes do not match")
+    check(lib().kl_gemm_tall(N, m, c, _ptr(A) if m else None, _ld(A) if m else N, _ptr(S) if m else None,
+                             _ld(S) if m else 1, float(alpha), float(beta), _ptr(out), _ld(out), _stream(stream)))
+    return out
 
 
 def report_dict(rep, status=0):

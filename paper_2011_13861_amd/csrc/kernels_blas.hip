@@ -14,6 +14,7 @@
 // coalesced); a second kernel adds the G partials of every slot in a fixed order and
 // writes the entry of C the slot holds.
 #include <algorithm>
+#include <string>
 
 #include "kl_internal.h"
 
@@ -445,3 +446,21 @@ void launch_residual(const double *X, const double *AX, const double *theta, int
 }
 
 }  // namespace kl
+
+// Tall-skinny product on the device through the C ABI (see include/kl.h).
+extern "C" kl_status kl_gemm_tall(int64_t N, int32_t m, int32_t c, const double *A, int64_t lda, const double *S,
+                                  int64_t lds, double alpha, double beta, double *Out, int64_t ldo, void *stream) {
+    using namespace kl;
+    if (N < 0 || m < 0 || c < 0) { set_error("kl_gemm_tall: negative size"); return KL_EINVAL; }
+    if (N == 0 || c == 0) return KL_OK;
+    if (N > (int64_t(1) << 36)) { set_error("kl_gemm_tall: more than 2^36 rows"); return KL_EINVAL; }
+    if (!Out || ldo < N || (m > 0 && (!A || !S || lda < N || lds < m))) {
+        set_error("kl_gemm_tall: NULL pointer or leading dimension too small");
+        return KL_EINVAL;
+    }
+    (void)hipGetLastError();
+    launch_gemm_nn(A, lda, m, S, lds, c, N, alpha, beta, Out, ldo, static_cast<hipStream_t>(stream));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error(std::string("kl_gemm_tall: ") + hipGetErrorString(e)); return KL_EHIP; }
+    return KL_OK;
+}

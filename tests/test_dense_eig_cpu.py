@@ -105,3 +105,20 @@ def test_symeig_errors():
         B.symeig_top(np.eye(3), 4)
     with pytest.raises(B.KLError):
         B.symeig_top(np.array([[1.0, np.inf], [np.inf, 1.0]]), 1)
+
+
+def test_gemm_tall_argument_errors():
+    """kl_gemm_tall rejects bad sizes, leading dimensions and pointers before any device work
+    (so on the host alone), and returns at once for an empty output."""
+    import ctypes
+    L = B.lib()
+    P = ctypes.c_void_p(16)          # never dereferenced: every call below fails its checks first
+    assert L.kl_gemm_tall(-1, 2, 2, P, 4, P, 2, 1.0, 0.0, P, 4, None) == -1
+    assert L.kl_gemm_tall(4, -2, 2, P, 4, P, 2, 1.0, 0.0, P, 4, None) == -1
+    assert L.kl_gemm_tall(4, 2, 2, P, 3, P, 2, 1.0, 0.0, P, 4, None) == -1        # lda < N
+    assert L.kl_gemm_tall(4, 2, 2, P, 4, P, 1, 1.0, 0.0, P, 4, None) == -1        # lds < m
+    assert L.kl_gemm_tall(4, 2, 2, P, 4, P, 2, 1.0, 0.0, P, 3, None) == -1        # ldo < N
+    assert L.kl_gemm_tall(4, 2, 2, None, 4, P, 2, 1.0, 0.0, P, 4, None) == -1     # A NULL
+    assert L.kl_gemm_tall(4, 2, 2, P, 4, P, 2, 1.0, 0.0, None, 4, None) == -1     # Out NULL
+    assert L.kl_gemm_tall(0, 2, 2, None, 0, None, 2, 1.0, 0.0, None, 0, None) == 0  # nothing to do
+    assert L.kl_gemm_tall(4, 2, 0, None, 4, None, 2, 1.0, 0.0, None, 4, None) == 0
