@@ -360,6 +360,19 @@ kl_status kl_symeig_top(int32_t n, const double *A, int32_t nv, double *w, doubl
 kl_status kl_gemm_tall(int64_t N, int32_t m, int32_t c, const double *A, int64_t lda, const double *S,
                        int64_t lds, double alpha, double beta, double *Out, int64_t ldo, void *stream);
 
+/* The eigensolver's Gram product on the device: C (m x c, column-major, leading dimension
+ * exactly m) = A^T B for tall A (N x m, ld lda >= N) and B (N x c, ld ldb >= N), FP64 device
+ * arrays.  The N rows are split into up to 256 ranges of at least 128 rows; each range's
+ * partial products (FP64 matrix cores, 64 rows of C by up to 128 columns per workgroup) go to
+ * `work` (device, kl_gram_tall_workspace(N, m, c) doubles, caller-owned) and are added in range
+ * order, so the result does not depend on scheduling.  m = 0 or c = 0: nothing is done; N = 0:
+ * C = 0.  C must not overlap A, B or work; calls sharing `work` must not overlap.
+ * Asynchronous on `stream`; allocates nothing.  N <= 2^36.  Errors: KL_EINVAL (sizes, leading
+ * dimensions, NULL pointers, workspace too small), KL_EHIP. */
+int64_t kl_gram_tall_workspace(int64_t N, int32_t m, int32_t c);
+kl_status kl_gram_tall(int64_t N, int32_t m, int32_t c, const double *A, int64_t lda, const double *B,
+                       int64_t ldb, double *C, double *work, int64_t work_elems, void *stream);
+
 /* ---- Batches of problems -------------------------------------------------------------
  * Many problems of uneven size (same dimension) solved together: one apply of the whole
  * batch is one replay of a captured HIP graph of 2 dim + 3 launches (batched Kronecker

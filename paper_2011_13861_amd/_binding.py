@@ -24,7 +24,7 @@ MAP_KINDS = {"identity": 0, "box": 1, "annulus_nurbs": 2, "annulus_polar": 3, "s
 
 # exported symbols declared in include/kl.h
 EXPORTS = ["kl_setup", "kl_setup_host", "kl_info", "kl_apply", "kl_apply_noalloc", "kl_stage5", "kl_get_points",
-           "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_symeig_top", "kl_gemm_tall", "kl_profile_enable", "kl_profile_read",
+           "kl_get_factor", "kl_kle_field", "kl_eigs", "kl_symeig", "kl_symeig_partial", "kl_symeig_top", "kl_gemm_tall", "kl_gram_tall_workspace", "kl_gram_tall", "kl_profile_enable", "kl_profile_read",
            "kl_stage5_config", "kl_stage5_symmetric", "kl_apply_config", "kl_set_cov", "kl_setup_patches", "kl_patch_count", "kl_patch_info",
            "kl_mlp_create", "kl_mlp_num_params", "kl_mlp_set_params", "kl_mlp_get_params",
            "kl_mlp_forward", "kl_mlp_gradients", "kl_mlp_adam", "kl_mlp_train", "kl_mlp_set_subspace",
@@ -100,6 +100,10 @@ def lib():
         L.kl_symeig_top.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, P]
         L.kl_gemm_tall.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, P,
                                    ctypes.c_int64, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64, P]
+        L.kl_gram_tall_workspace.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+        L.kl_gram_tall_workspace.restype = ctypes.c_int64
+        L.kl_gram_tall.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, P,
+                                   ctypes.c_int64, P, P, ctypes.c_int64, P]
         L.kl_profile_enable.argtypes = [P, ctypes.c_int32]
         L.kl_stage5_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
         L.kl_stage5_symmetric.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]
@@ -595,6 +599,23 @@ def gemm_tall(A, S, out, alpha=1.0, beta=0.0, stream=None):
     check(lib().kl_gemm_tall(N, m, c, _ptr(A) if m else None, _ld(A) if m else N, _ptr(S) if m else None,
                              _ld(S) if m else 1, float(alpha), float(beta), _ptr(out), _ld(out), _stream(stream)))
     return out
+
+
+def gram_tall(A, Bm, stream=None):
+    """C = A^T B on the device (kl_gram_tall) for column-major FP64 blocks A (N x m) and
+    B (N x c); returns C as a column-major (m, c) device tensor."""
+    import torch
+    N, m = int(A.shape[0]), int(A.shape[1])
+    c = int(Bm.shape[1])
+    if Bm.shape[0] != N:
+        raise ValueError("A and B need the same number of rows")
+    C = torch.empty((c, m), dtype=torch.float64, device=A.device).T
+    nw = int(lib().kl_gram_tall_workspace(N, m, c))
+    work = torch.empty(max(nw, 1), dtype=torch.float64, device=A.device)
+    check(lib().kl_gram_tall(N, m, c, _ptr(A) if m else None, _ld(A) if m else max(N, 1), _ptr(Bm) if c else None,
+                             _ld(Bm) if c else max(N, 1), _ptr(C) if m and c else None, _ptr(work), nw,
+                             _stream(stream)))
+    return C
 
 
 def report_dict(rep, status=0):

@@ -464,3 +464,42 @@ extern "C" kl_status kl_gemm_tall(int64_t N, int32_t m, int32_t c, const double 
     if (e != hipSuccess) { set_error(std::string("kl_gemm_tall: ") + hipGetErrorString(e)); return KL_EHIP; }
     return KL_OK;
 }
+
+// Gram product on the device through the C ABI (see include/kl.h).
+extern "C" int64_t kl_gram_tall_workspace(int64_t N, int32_t m, int32_t c) {
+    if (N < 1 || m < 1 || c < 1) return 0;
+    return kl::gram_part_elems(N, m, c);
+}
+
+extern "C" kl_status kl_gram_tall(int64_t N, int32_t m, int32_t c, const double *A, int64_t lda, const double *B,
+                                  int64_t ldb, double *C, double *work, int64_t work_elems, void *stream) {
+    using namespace kl;
+    if (N < 0 || m < 0 || c < 0) { set_error("kl_gram_tall: negative size"); return KL_EINVAL; }
+    if (m == 0 || c == 0) return KL_OK;
+    if (!C) { set_error("kl_gram_tall: NULL C"); return KL_EINVAL; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (N == 0) {                                        // empty sums: C = 0
+        if (hipMemsetAsync(C, 0, size_t(m) * size_t(c) * sizeof(double), s) != hipSuccess) {
+            set_error("kl_gram_tall: clearing C failed");
+            return KL_EHIP;
+        }
+        return KL_OK;
+    }
+    if (N > (int64_t(1) << 36)) { set_error("kl_gram_tall: more than 2^36 rows"); return KL_EINVAL; }
+    if (!A || !B || lda < N || ldb < N) {
+        set_error("kl_gram_tall: NULL pointer or leading dimension too small");
+        return KL_EINVAL;
+    }
+    if (!work || work_elems < gram_part_elems(N, m, c)) {
+        set_error("kl_gram_tall: workspace smaller than kl_gram_tall_workspace(N, m, c)");
+        return KL_EINVAL;
+    }
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetLastError();
+    launch_gram(A, lda, m, B, ldb, c, N, work, C, ncu, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error(std::string("kl_gram_tall: ") + hipGetErrorString(e)); return KL_EHIP; }
+    return KL_OK;
+}

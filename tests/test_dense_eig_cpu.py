@@ -122,3 +122,19 @@ def test_gemm_tall_argument_errors():
     assert L.kl_gemm_tall(4, 2, 2, P, 4, P, 2, 1.0, 0.0, None, 4, None) == -1     # Out NULL
     assert L.kl_gemm_tall(0, 2, 2, None, 0, None, 2, 1.0, 0.0, None, 0, None) == 0  # nothing to do
     assert L.kl_gemm_tall(4, 2, 0, None, 4, None, 2, 1.0, 0.0, None, 4, None) == 0
+
+
+def test_gram_tall_argument_errors():
+    """kl_gram_tall and its workspace query reject bad arguments on the host alone."""
+    import ctypes
+    L = B.lib()
+    P = ctypes.c_void_p(16)
+    assert L.kl_gram_tall_workspace(-1, 2, 2) == 0 and L.kl_gram_tall_workspace(100, 0, 2) == 0
+    assert L.kl_gram_tall_workspace(1000, 64, 32) > 0
+    assert L.kl_gram_tall(-1, 2, 2, P, 4, P, 4, P, P, 10 ** 6, None) == -1
+    assert L.kl_gram_tall(4, 2, 2, P, 3, P, 4, P, P, 10 ** 6, None) == -1        # lda < N
+    assert L.kl_gram_tall(4, 2, 2, P, 4, P, 3, P, P, 10 ** 6, None) == -1        # ldb < N
+    assert L.kl_gram_tall(4, 2, 2, P, 4, P, 4, None, P, 10 ** 6, None) == -1     # C NULL
+    assert L.kl_gram_tall(4, 2, 2, P, 4, P, 4, P, None, 10 ** 6, None) == -1     # no workspace
+    assert L.kl_gram_tall(4, 2, 2, P, 4, P, 4, P, P, 1, None) == -1              # workspace too small
+    assert L.kl_gram_tall(4, 0, 2, None, 4, None, 4, None, None, 0, None) == 0   # nothing to do
