@@ -109,15 +109,33 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
     }
 }
 
-// Sum of the K-range partials in a fixed order, then the epilogue.
-__global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(GemmArgs g, int splits) {
+// Sum of the K-range partials in a fixed order, then the epilogue: a workgroup takes 64
+// output elements, wave w adds the w-th quarter of the partials of its lane's element in
+// split order (loads issued eight at a time), and the quarter sums are added in wave order
+// through LDS.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int splits) {
+    __shared__ float qs[4][64];
     const int64_t total = int64_t(g.M) * g.N;
-    for (int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x; e < total;
-         e += int64_t(gridDim.x) * kThreads) {
-        float v = 0.0f;
-        for (int s = 0; s < splits; ++s) v += g.part[int64_t(s) * total + e];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t e = int64_t(blockIdx.x) * 64 + lane;
+    const int64_t ec = min(e, total - 1);               // lanes past the end read the last element
+    const int s0 = (splits * w) / 4, s1 = (splits * (w + 1)) / 4;
+    float v = 0.0f;
+    int sp = s0;
+    for (; sp + 8 <= s1; sp += 8) {
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = g.part[int64_t(sp + u) * total + ec];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t[u];
+    }
+    for (; sp < s1; ++sp) v += g.part[int64_t(sp) * total + ec];
+    qs[w][lane] = v;
+    __syncthreads();
+    if (w == 0 && e < total) {
+        const float sum = ((qs[0][lane] + qs[1][lane]) + qs[2][lane]) + qs[3][lane];
         const int row = int(e / g.N), col = int(e % g.N);
-        g.C[int64_t(row) * g.ldc + col] = epilogue(g, row, col, v);
+        g.C[int64_t(row) * g.ldc + col] = epilogue(g, row, col, sum);
     }
 }
 
@@ -316,14 +334,29 @@ __global__ __launch_bounds__(kThreads) void subspace_residual_kernel(const float
     if (threadIdx.x == 0) loss_part[int64_t(s) * gridDim.x + sl] += 0.5 * double(w) * tot;
 }
 
-// db[j] = sum_i D[i][j] over M rows (one thread per column, fixed row order).
-__global__ __launch_bounds__(kThreads) void colsum_kernel(const float *__restrict__ D, int64_t ldd, int M,
-                                                          int N, float *__restrict__ out) {
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    if (j >= N) return;
+// db[j] = sum_i D[i][j] over M rows: a workgroup takes 64 columns, wave w adds the w-th
+// quarter of the rows for its lane's column (loads issued eight at a time), and the four
+// quarter sums are added in wave order through LDS (a fixed order: the same bits every call).
+__global__ __launch_bounds__(256) void colsum_kernel(const float *__restrict__ D, int64_t ldd, int M, int N,
+                                                     float *__restrict__ out) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = int(blockIdx.x) * 64 + lane;
+    const int jc = min(j, N - 1);                        // lanes past N read column N - 1, store nothing
+    const int r0 = (M * w) / 4, r1 = (M * (w + 1)) / 4;
     float s = 0.0f;
-    for (int i = 0; i < M; ++i) s += D[int64_t(i) * ldd + j];
-    out[j] = s;
+    int i = r0;
+    for (; i + 8 <= r1; i += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = D[int64_t(i + u) * ldd + jc];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; i < r1; ++i) s += D[int64_t(i) * ldd + jc];
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < N) out[j] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // Adam with bias correction: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
@@ -376,7 +409,7 @@ void launch_gemm(bool ta, bool tb, GemmArgs g, int splits, hipStream_t s) {
     else if (tb) hipLaunchKernelGGL((gemm_f32_kernel<false, true>), grid, dim3(kThreads), 0, s, g);
     else hipLaunchKernelGGL((gemm_f32_kernel<false, false>), grid, dim3(kThreads), 0, s, g);
     if (splits > 1)
-        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(int64_t(g.M) * g.N, 2048)), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(unsigned((int64_t(g.M) * g.N + 63) / 64)), dim3(256), 0, s,
                            g, splits);
 }
 
@@ -418,7 +451,8 @@ void launch_subspace(const float *y, int64_t ldy, const float *t, int64_t ldt, c
 }
 
 void launch_colsum(const float *D, int64_t ldd, int M, int N, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0, s, D, ldd, M, N, out);
+    if (N < 1) return;
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 63) / 64), dim3(256), 0, s, D, ldd, M, N, out);
 }
 
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, const AdamArgs &a, hipStream_t s) {
