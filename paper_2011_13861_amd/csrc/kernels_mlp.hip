@@ -109,6 +109,105 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
     }
 }
 
+// The same product for operands whose contiguous index runs in whole float4s (16-byte
+// aligned bases, leading dimensions and contiguous extents multiples of 4; gemm_vec_ok).
+// 64 x 64 tiles with 64-deep K chunks, staged in LDS with k contiguous (sA[i][k], sB[j][k];
+// rows padded to 68 floats, so the 16 lanes served together by a 128-bit LDS read fall on
+// distinct banks).  Within a chunk, MFMA step s takes k = s from the lower half-wave and
+// k = 32 + s from the upper one, so a lane reads its 32 operands of the chunk as eight
+// 128-bit LDS loads; every term is added as in gemm_f32_kernel, in another order.  Global
+// loads are one float4 per thread and operand row, eight per thread and chunk, with the
+// next chunk prefetched into registers while the current one is consumed.
+constexpr int kVK = 64, kVS = kVK + 4;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
+    __shared__ float4 sA[kTM * kVS / 4];
+    __shared__ float4 sB[kTN * kVS / 4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int i0 = blockIdx.y * kTM, j0 = blockIdx.x * kTN;
+    const int kb = blockIdx.z * g.kchunk;
+    const int ke = min(g.K, kb + g.kchunk);
+    const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
+    // float4 number r * 256 + t of a 64 x 64 operand tile: c4 = t & 15 counts float4s along
+    // the contiguous index, o + 16 r (o = t >> 4) is the other index.
+    const int c4 = t & 15, o = t >> 4;
+    // Per-thread bases at k = 0 and row / column o; A(r) and B(r) add 16 r rows, the chunk
+    // start adds kc along k.
+    const float *baseA = TA ? g.A + int64_t(o) * g.lda + i0 + 4 * c4 : g.A + int64_t(i0 + o) * g.lda + 4 * c4;
+    const float *baseB = TB ? g.B + int64_t(j0 + o) * g.ldb + 4 * c4 : g.B + int64_t(o) * g.ldb + j0 + 4 * c4;
+    const int64_t rowA = 16 * g.lda, rowB = 16 * g.ldb;
+    const bool colA = !TA || i0 + 4 * c4 < g.M;   // contiguous index in range (i for TA)
+    const bool colB = TB || j0 + 4 * c4 < g.N;    // contiguous index in range (j unless TB)
+    floatx16 acc;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    float4 ra[4], rb[4];
+    auto load = [&](int kc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int other = o + 16 * r;
+            const bool va = TA ? (colA && kc + other < ke) : (i0 + other < g.M && kc + 4 * c4 < ke);
+            const bool vb = TB ? (j0 + other < g.N && kc + 4 * c4 < ke) : (colB && kc + other < ke);
+            const float *pa = baseA + r * rowA + (TA ? int64_t(kc) * g.lda : int64_t(kc));
+            const float *pb = baseB + r * rowB + (TB ? int64_t(kc) : int64_t(kc) * g.ldb);
+            ra[r] = va ? *reinterpret_cast<const float4 *>(pa) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            rb[r] = vb ? *reinterpret_cast<const float4 *>(pb) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    };
+    auto store = [&]() {
+        float *fa = reinterpret_cast<float *>(sA);
+        float *fb = reinterpret_cast<float *>(sB);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int other = o + 16 * r;
+            if (TA) {   // ra[r] = A(4 c4 .. 4 c4 + 3, other)
+                fa[(4 * c4 + 0) * kVS + other] = ra[r].x;
+                fa[(4 * c4 + 1) * kVS + other] = ra[r].y;
+                fa[(4 * c4 + 2) * kVS + other] = ra[r].z;
+                fa[(4 * c4 + 3) * kVS + other] = ra[r].w;
+            } else {    // ra[r] = A(other, 4 c4 .. 4 c4 + 3)
+                sA[other * (kVS / 4) + c4] = ra[r];
+            }
+            if (TB) {   // rb[r] = B(4 c4 .. 4 c4 + 3, other)
+                sB[other * (kVS / 4) + c4] = rb[r];
+            } else {    // rb[r] = B(other, 4 c4 .. 4 c4 + 3)
+                fb[(4 * c4 + 0) * kVS + other] = rb[r].x;
+                fb[(4 * c4 + 1) * kVS + other] = rb[r].y;
+                fb[(4 * c4 + 2) * kVS + other] = rb[r].z;
+                fb[(4 * c4 + 3) * kVS + other] = rb[r].w;
+            }
+        }
+    };
+    const float4 *la = sA + (wi + (lane & 31)) * (kVS / 4) + 8 * (lane >> 5);
+    const float4 *lb = sB + (wj + (lane & 31)) * (kVS / 4) + 8 * (lane >> 5);
+    if (kb < ke) load(kb);
+    for (int kc = kb; kc < ke; kc += kVK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (kc + kVK < ke) load(kc + kVK);
+#pragma unroll
+        for (int s4 = 0; s4 < 8; ++s4) {
+            const float4 a = la[s4], b = lb[s4];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+        }
+    }
+    const int col = j0 + wj + (lane & 31);
+    if (col >= g.N) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = i0 + wi + (r & 3) + 4 * (lane >> 5) + 8 * (r >> 2);
+        if (row >= g.M) continue;
+        if (gridDim.z > 1)
+            g.part[(int64_t(blockIdx.z) * g.M + row) * g.N + col] = acc[r];
+        else
+            g.C[int64_t(row) * g.ldc + col] = epilogue(g, row, col, acc[r]);
+    }
+}
+
 // Sum of the K-range partials in a fixed order, then the epilogue: a workgroup takes 64
 // output elements, wave w adds the w-th quarter of the partials of its lane's element in
 // split order (loads issued eight at a time), and the quarter sums are added in wave order
@@ -390,21 +489,33 @@ int grid_for(int64_t n, int cap) { return int(std::max<int64_t>(1, std::min<int6
 
 }  // namespace
 
-int gemm_splits(int M, int N, int K, int n_cu, int64_t part_cap, int *kchunk) {
+bool gemm_vec_ok(bool ta, bool tb, const GemmArgs &g) {
+    auto aligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    if (!aligned(g.A) || !aligned(g.B) || (g.lda & 3) || (g.ldb & 3)) return false;
+    return ((ta ? g.M : g.K) & 3) == 0 && ((tb ? g.K : g.N) & 3) == 0;
+}
+
+int gemm_splits(int M, int N, int K, int n_cu, int64_t part_cap, bool vec, int *kchunk) {
+    const int kstep = vec ? kVK : kTK;
     const int64_t tiles = int64_t((M + kTM - 1) / kTM) * ((N + kTN - 1) / kTN);
-    const int ksteps = std::max(1, (K + kTK - 1) / kTK);
+    const int ksteps = std::max(1, (K + kstep - 1) / kstep);
     int splits = 1;
     const int64_t want = 2 * int64_t(n_cu);
     if (tiles < want) splits = int(std::min<int64_t>(ksteps, (want + tiles - 1) / tiles));
     while (splits > 1 && int64_t(splits) * M * N > part_cap) --splits;
     const int steps_per = (ksteps + splits - 1) / splits;
-    *kchunk = steps_per * kTK;
+    *kchunk = steps_per * kstep;
     return (ksteps + steps_per - 1) / steps_per;
 }
 
-void launch_gemm(bool ta, bool tb, GemmArgs g, int splits, hipStream_t s) {
+void launch_gemm(bool ta, bool tb, bool vec, GemmArgs g, int splits, hipStream_t s) {
     const dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM, splits);
-    if (ta && tb) hipLaunchKernelGGL((gemm_f32_kernel<true, true>), grid, dim3(kThreads), 0, s, g);
+    if (vec) {
+        if (ta && tb) hipLaunchKernelGGL((gemm_f32_vec_kernel<true, true>), grid, dim3(kThreads), 0, s, g);
+        else if (ta) hipLaunchKernelGGL((gemm_f32_vec_kernel<true, false>), grid, dim3(kThreads), 0, s, g);
+        else if (tb) hipLaunchKernelGGL((gemm_f32_vec_kernel<false, true>), grid, dim3(kThreads), 0, s, g);
+        else hipLaunchKernelGGL((gemm_f32_vec_kernel<false, false>), grid, dim3(kThreads), 0, s, g);
+    } else if (ta && tb) hipLaunchKernelGGL((gemm_f32_kernel<true, true>), grid, dim3(kThreads), 0, s, g);
     else if (ta) hipLaunchKernelGGL((gemm_f32_kernel<true, false>), grid, dim3(kThreads), 0, s, g);
     else if (tb) hipLaunchKernelGGL((gemm_f32_kernel<false, true>), grid, dim3(kThreads), 0, s, g);
     else hipLaunchKernelGGL((gemm_f32_kernel<false, false>), grid, dim3(kThreads), 0, s, g);

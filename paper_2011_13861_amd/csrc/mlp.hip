@@ -104,8 +104,9 @@ void gemm(kl_mlp *M, bool ta, bool tb, const float *A, int64_t lda, const float 
     g.M = m; g.N = n; g.K = k;
     g.epi = epi; g.bias = bias; g.aux = aux; g.ldaux = ldaux;
     g.part = M->part;
-    const int splits = gemm_splits(m, n, k, M->n_cu, M->part_cap, &g.kchunk);
-    launch_gemm(ta, tb, g, splits, s);
+    const bool vec = gemm_vec_ok(ta, tb, g);
+    const int splits = gemm_splits(m, n, k, M->n_cu, M->part_cap, vec, &g.kchunk);
+    launch_gemm(ta, tb, vec, g, splits, s);
 }
 
 // Forward pass of B rows of x (B x sizes[0]); the output goes to `out` (B x sizes[L]).

@@ -23,7 +23,7 @@ struct GemmArgs {
     float *C = nullptr;
     int64_t ldc = 0;
     int M = 0, N = 0, K = 0;
-    int kchunk = 0;                 // K range of one split (multiple of 32)
+    int kchunk = 0;                 // K range of one split (multiple of the K chunk)
     const float *bias = nullptr;
     const float *aux = nullptr;
     int64_t ldaux = 0;
@@ -35,10 +35,15 @@ struct AdamArgs {
     float lr, b1, b2, eps, c1, c2;
 };
 
+// Whether the float4 form of the product applies: A and B 16-byte aligned, lda and ldb
+// multiples of 4, and the contiguous extent of each operand (K or M for A, N or K for B)
+// a multiple of 4.
+bool gemm_vec_ok(bool ta, bool tb, const GemmArgs &g);
 // Number of K splits for a launch (partials limited to part_cap floats); *kchunk
-// receives the K range of one split.
-int gemm_splits(int M, int N, int K, int n_cu, int64_t part_cap, int *kchunk);
-void launch_gemm(bool ta, bool tb, GemmArgs g, int splits, hipStream_t s);
+// receives the K range of one split (a multiple of the form's K chunk: 64 for the float4
+// form, 32 otherwise).
+int gemm_splits(int M, int N, int K, int n_cu, int64_t part_cap, bool vec, int *kchunk);
+void launch_gemm(bool ta, bool tb, bool vec, GemmArgs g, int splits, hipStream_t s);
 void launch_loss(const float *y, int64_t ldy, const float *t, int64_t ldt, const int *rows, int batch,
                  int n_out, int group, int signed_, float *dy, int64_t lddy, double *loss_part,
                  hipStream_t s);

@@ -57,11 +57,22 @@ def _setup(sizes, B, seed, group):
     return flat, params, x, t.astype(np.float32)
 
 
+# Widths that are multiples of 4 (with 16-byte aligned weight blocks) take the float4 form
+# of the product: "aligned_ragged" on ragged tiles and split K ranges, "aligned_odd_batch"
+# with 19 rows, "aligned_tiles" on exact 64-multiples, "warmstart_b64" at the training
+# minibatch of the warm-start network (every layer but the first in the float4 form).
 CASES = [([3, 16, 16, 10], 7, 0), ([3, 16, 16, 10], 7, 5), ([5, 70, 33, 130], 67, 13),
-         ([3, 256, 256, 41616], 8, 2601)]
+         ([3, 256, 256, 41616], 8, 2601), ([4, 36, 68, 1300], 20, 13), ([4, 36, 68, 1300], 19, 13),
+         ([8, 64, 128, 4160], 64, 0), ([3, 256, 256, 41616], 64, 2601)]
+CASE_IDS = ["small_mse", "small_signed", "ragged", "warmstart_size", "aligned_ragged",
+            "aligned_odd_batch", "aligned_tiles", "warmstart_b64"]
 
 
-@pytest.mark.parametrize("sizes,B,group", CASES, ids=["small_mse", "small_signed", "ragged", "warmstart_size"])
+def _max_rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("sizes,B,group", CASES, ids=CASE_IDS)
 def test_forward_and_gradients_match_oracle(sizes, B, group):
     flat, params, x, t = _setup(sizes, B, 11, group)
     net = kl.MLP(sizes)
@@ -72,6 +83,7 @@ def test_forward_and_gradients_match_oracle(sizes, B, group):
     y = net.forward(xd).cpu().numpy()
     y_ref, _ = mlp.forward(params, x.astype(np.float64))
     assert _rel(y, y_ref) <= 1e-5
+    assert _max_rel(y, y_ref) <= 1e-5     # every element, so that one wrong tile shows
     loss, g = net.gradients(xd, td, group=group)
     loss_ref = mlp.loss(params, x.astype(np.float64), t.astype(np.float64), group=group or None)
     assert abs(loss - loss_ref) <= 1e-4 * loss_ref
@@ -80,6 +92,7 @@ def test_forward_and_gradients_match_oracle(sizes, B, group):
     for l, ((dW, db), (rW, rb)) in enumerate(zip(gl, g_ref)):
         assert _rel(dW, rW) <= 1e-4, (l, "W", _rel(dW, rW))
         assert _rel(db, rb) <= 1e-4, (l, "b", _rel(db, rb))
+        assert _max_rel(dW, rW) <= 1e-4, (l, "W", _max_rel(dW, rW))
 
 
 def test_adam_step_matches_oracle():
@@ -141,11 +154,13 @@ def _orthogonal_targets_near(y, B, ng, group, rng):
 
 # 7 groups of 300 (several LDS chunks per slice, ragged tail); 32 groups of 150; 32 groups
 # of 48 (residual slices of 2 elements: slices 24 to 31 are empty)
-SUB_CASES = CASES[1:] + [([3, 16, 16, 2100], 5, 300), ([3, 16, 16, 4800], 3, 150), ([3, 8, 8, 1536], 4, 48)]
+SUB_CASES = CASES[1:4] + [CASES[7]] + [([3, 16, 16, 2100], 5, 300), ([3, 16, 16, 4800], 3, 150),
+                            ([3, 8, 8, 1536], 4, 48)]
 
 
 @pytest.mark.parametrize("sizes,B,group", SUB_CASES,
-                         ids=["small_signed", "ragged", "warmstart_size", "g7", "g32", "g32_short"])
+                         ids=["small_signed", "ragged", "warmstart_size", "warmstart_b64", "g7", "g32",
+                              "g32_short"])
 def test_subspace_loss_gradients_match_oracle(sizes, B, group):
     """The grouped loss with its subspace term (weight 0.8) against the oracle, on
     mutually orthogonal target groups per row (2 to 32 groups: every register bucket of
