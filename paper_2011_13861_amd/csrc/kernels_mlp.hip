@@ -109,6 +109,56 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
     }
 }
 
+// Stores of a wave's 32 x 32 accumulator block: acc[r] of a lane is row
+// rl + (r & 3) + 8 (r >> 2) of the column its pointer addresses (base at row rl); rows past
+// M are skipped unless the tile is interior.  The epilogue kind is a template argument, so
+// that the stores carry no per-element branching.
+template <int EPI, bool INTERIOR>
+__device__ __forceinline__ void store_block(float *base, int64_t ld, const float *aux, int64_t ldaux, float bj,
+                                            int rl, int M, const floatx16 &acc) {
+    const int64_t l2 = 2 * ld, l3 = 3 * ld, l8 = 8 * ld;
+    const int64_t a2 = 2 * ldaux, a3 = 3 * ldaux, a8 = 8 * ldaux;
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            if (!INTERIOR && rl + rr + 8 * rg >= M) continue;
+            const int64_t off = rr == 0 ? 0 : rr == 1 ? ld : rr == 2 ? l2 : l3;
+            float v = acc[4 * rg + rr];
+            if (EPI == EPI_BIAS) v += bj;
+            if (EPI == EPI_BIAS_TANH) v = tanhf(v + bj);
+            if (EPI == EPI_DTANH) {
+                const float h = aux[rr == 0 ? 0 : rr == 1 ? ldaux : rr == 2 ? a2 : a3];
+                v *= 1.0f - h * h;
+            }
+            base[off] = v;
+        }
+        base += l8;
+        if (EPI == EPI_DTANH) aux += a8;
+    }
+}
+
+template <bool INTERIOR>
+__device__ __forceinline__ void store_tile(const GemmArgs &g, int rl, int col, const floatx16 &acc) {
+    if (gridDim.z > 1) {
+        store_block<EPI_NONE, INTERIOR>(g.part + (int64_t(blockIdx.z) * g.M + rl) * g.N + col, g.N, nullptr, 0,
+                                        0.0f, rl, g.M, acc);
+        return;
+    }
+    float *c = g.C + int64_t(rl) * g.ldc + col;
+    switch (g.epi) {
+    case EPI_BIAS: store_block<EPI_BIAS, INTERIOR>(c, g.ldc, nullptr, 0, g.bias[col], rl, g.M, acc); break;
+    case EPI_BIAS_TANH:
+        store_block<EPI_BIAS_TANH, INTERIOR>(c, g.ldc, nullptr, 0, g.bias[col], rl, g.M, acc);
+        break;
+    case EPI_DTANH:
+        store_block<EPI_DTANH, INTERIOR>(c, g.ldc, g.aux + int64_t(rl) * g.ldaux + col, g.ldaux, 0.0f, rl, g.M,
+                                         acc);
+        break;
+    default: store_block<EPI_NONE, INTERIOR>(c, g.ldc, nullptr, 0, 0.0f, rl, g.M, acc); break;
+    }
+}
+
 // The same product for operands whose contiguous index runs in whole float4s (16-byte
 // aligned bases, leading dimensions and contiguous extents multiples of 4; gemm_vec_ok).
 // 64 x 64 tiles with 64-deep K chunks, staged in LDS with k contiguous (sA[i][k], sB[j][k];
@@ -118,6 +168,10 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
 // 128-bit LDS loads; every term is added as in gemm_f32_kernel, in another order.  Global
 // loads are one float4 per thread and operand row, eight per thread and chunk, with the
 // next chunk prefetched into registers while the current one is consumed.
+// An operand whose contiguous index is not k (A when TA, B unless TB) reaches LDS as four
+// scalar writes per float4; in its rows the float4 group k/4 is stored at
+// (k/4) ^ ((row/16) & 3), which spreads a wave's scalar writes over all 64 banks (four-way
+// conflicts otherwise) and leaves the 128-bit reads conflict-free.
 constexpr int kVK = 64, kVS = kVK + 4;
 
 template <bool TA, bool TB>
@@ -154,32 +208,33 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
             rb[r] = vb ? *reinterpret_cast<const float4 *>(pb) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
     };
+    // scalar writes of float4 rows 4 c4 .. 4 c4 + 3 at k = other (swizzle (4 c4 / 16) & 3)
+    auto put_t = [&](float *f, const float4 &v, int other) {
+        const int at = 4 * ((other >> 2) ^ (c4 >> 2)) + (other & 3);
+        f[(4 * c4 + 0) * kVS + at] = v.x;
+        f[(4 * c4 + 1) * kVS + at] = v.y;
+        f[(4 * c4 + 2) * kVS + at] = v.z;
+        f[(4 * c4 + 3) * kVS + at] = v.w;
+    };
     auto store = [&]() {
-        float *fa = reinterpret_cast<float *>(sA);
-        float *fb = reinterpret_cast<float *>(sB);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int other = o + 16 * r;
-            if (TA) {   // ra[r] = A(4 c4 .. 4 c4 + 3, other)
-                fa[(4 * c4 + 0) * kVS + other] = ra[r].x;
-                fa[(4 * c4 + 1) * kVS + other] = ra[r].y;
-                fa[(4 * c4 + 2) * kVS + other] = ra[r].z;
-                fa[(4 * c4 + 3) * kVS + other] = ra[r].w;
-            } else {    // ra[r] = A(other, 4 c4 .. 4 c4 + 3)
-                sA[other * (kVS / 4) + c4] = ra[r];
-            }
-            if (TB) {   // rb[r] = B(4 c4 .. 4 c4 + 3, other)
-                sB[other * (kVS / 4) + c4] = rb[r];
-            } else {    // rb[r] = B(other, 4 c4 .. 4 c4 + 3)
-                fb[(4 * c4 + 0) * kVS + other] = rb[r].x;
-                fb[(4 * c4 + 1) * kVS + other] = rb[r].y;
-                fb[(4 * c4 + 2) * kVS + other] = rb[r].z;
-                fb[(4 * c4 + 3) * kVS + other] = rb[r].w;
-            }
+            if (TA) put_t(reinterpret_cast<float *>(sA), ra[r], other);   // ra[r] = A(4 c4.., other)
+            else sA[other * (kVS / 4) + c4] = ra[r];                     // ra[r] = A(other, 4 c4..)
+            if (TB) sB[other * (kVS / 4) + c4] = rb[r];                  // rb[r] = B(4 c4.., other)
+            else put_t(reinterpret_cast<float *>(sB), rb[r], other);     // rb[r] = B(other, 4 c4..)
         }
     };
-    const float4 *la = sA + (wi + (lane & 31)) * (kVS / 4) + 8 * (lane >> 5);
-    const float4 *lb = sB + (wj + (lane & 31)) * (kVS / 4) + 8 * (lane >> 5);
+    // LDS read pointers: group s4 = 4 q + p of the lane's half sits at p ^ sw in a swizzled row
+    const int ra_row = wi + (lane & 31), rb_row = wj + (lane & 31);
+    const int swa = TA ? (ra_row >> 4) & 3 : 0, swb = TB ? 0 : (rb_row >> 4) & 3;
+    const float4 *la[4], *lb[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        la[p] = sA + ra_row * (kVS / 4) + 8 * (lane >> 5) + (p ^ swa);
+        lb[p] = sB + rb_row * (kVS / 4) + 8 * (lane >> 5) + (p ^ swb);
+    }
     if (kb < ke) load(kb);
     for (int kc = kb; kc < ke; kc += kVK) {
         __syncthreads();
@@ -187,25 +242,22 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
         __syncthreads();
         if (kc + kVK < ke) load(kc + kVK);
 #pragma unroll
-        for (int s4 = 0; s4 < 8; ++s4) {
-            const float4 a = la[s4], b = lb[s4];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const float4 a = la[p][4 * q], b = lb[p][4 * q];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+            }
         }
     }
     const int col = j0 + wj + (lane & 31);
     if (col >= g.N) return;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int row = i0 + wi + (r & 3) + 4 * (lane >> 5) + 8 * (r >> 2);
-        if (row >= g.M) continue;
-        if (gridDim.z > 1)
-            g.part[(int64_t(blockIdx.z) * g.M + row) * g.N + col] = acc[r];
-        else
-            g.C[int64_t(row) * g.ldc + col] = epilogue(g, row, col, acc[r]);
-    }
+    const int rl = i0 + wi + 4 * (lane >> 5);
+    if (i0 + kTM <= g.M) store_tile<true>(g, rl, col, acc);
+    else store_tile<false>(g, rl, col, acc);
 }
 
 // Sum of the K-range partials in a fixed order, then the epilogue: a workgroup takes 64
