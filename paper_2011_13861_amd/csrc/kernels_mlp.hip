@@ -33,6 +33,18 @@ __device__ __forceinline__ float epilogue(const GemmArgs &g, int row, int col, f
     }
 }
 
+// Adam update of one parameter from its gradient g (every Adam path of the network goes
+// through it, so fused and separate steps give the same bits: with contraction off, each
+// product and sum rounds on its own wherever the function is inlined).
+__device__ __forceinline__ void adam_update(float &p, float &m, float &v, float g, const AdamArgs &a) {
+#pragma clang fp contract(off)
+    const float mi = a.b1 * m + (1.0f - a.b1) * g;
+    const float vi = a.b2 * v + (1.0f - a.b2) * g * g;
+    m = mi;
+    v = vi;
+    p -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+}
+
 // C (M x N) = op(A) (M x K) * op(B) (K x N), one 64 x 64 tile per workgroup, four waves
 // of 32 x 32 on v_mfma_f32_32x32x2f32.  blockIdx.z selects a K range; with more than one
 // range the raw sums go to part[z][M][N] and splitk_reduce applies the epilogue.
@@ -172,9 +184,13 @@ __device__ __forceinline__ void store_tile(const GemmArgs &g, int rl, int col, c
 // scalar writes per float4; in its rows the float4 group k/4 is stored at
 // (k/4) ^ ((row/16) & 3), which spreads a wave's scalar writes over all 64 banks (four-way
 // conflicts otherwise) and leaves the 128-bit reads conflict-free.
+// ADAM (EPI_ADAM, one K range): the accumulators are gradients of the parameters at C
+// (moments at am, av, same layout); the lane's 16 parameters and their moments are loaded
+// right after the first operand chunk, so that they arrive during the products, and the
+// updated values are stored in place of the tile.
 constexpr int kVK = 64, kVS = kVK + 4;
 
-template <bool TA, bool TB>
+template <bool TA, bool TB, bool ADAM = false>
 __global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
     __shared__ float4 sA[kTM * kVS / 4];
     __shared__ float4 sB[kTN * kVS / 4];
@@ -236,6 +252,21 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
         lb[p] = sB + rb_row * (kVS / 4) + 8 * (lane >> 5) + (p ^ swb);
     }
     if (kb < ke) load(kb);
+    // ADAM: acc[r] of the lane belongs to row rl + (r & 3) + 8 (r >> 2) of column col
+    const int col = j0 + wj + (lane & 31);
+    const int rl = i0 + wi + 4 * (lane >> 5);
+    float pp[ADAM ? 16 : 1], mm[ADAM ? 16 : 1], vv[ADAM ? 16 : 1];
+    if constexpr (ADAM) {
+        const int64_t o = int64_t(rl) * g.ldc + min(col, g.N - 1);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int dr = (r & 3) + 8 * (r >> 2);
+            const int64_t off = o + int64_t(min(dr, g.M - 1 - rl)) * g.ldc;   // clamped: rows past M
+            pp[r] = g.C[off];
+            mm[r] = g.am[off];
+            vv[r] = g.av[off];
+        }
+    }
     for (int kc = kb; kc < ke; kc += kVK) {
         __syncthreads();
         store();
@@ -253,9 +284,21 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
             }
         }
     }
-    const int col = j0 + wj + (lane & 31);
     if (col >= g.N) return;
-    const int rl = i0 + wi + 4 * (lane >> 5);
+    if constexpr (ADAM) {
+        const int64_t o = int64_t(rl) * g.ldc + col;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int dr = (r & 3) + 8 * (r >> 2);
+            if (rl + dr >= g.M) continue;
+            adam_update(pp[r], mm[r], vv[r], acc[r], g.adam);
+            const int64_t off = o + int64_t(dr) * g.ldc;
+            g.C[off] = pp[r];
+            g.am[off] = mm[r];
+            g.av[off] = vv[r];
+        }
+        return;
+    }
     if (i0 + kTM <= g.M) store_tile<true>(g, rl, col, acc);
     else store_tile<false>(g, rl, col, acc);
 }
@@ -516,12 +559,30 @@ __global__ __launch_bounds__(kThreads) void adam_kernel(float *__restrict__ p, c
                                                         float *__restrict__ m, float *__restrict__ v,
                                                         int64_t n, AdamArgs a) {
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += int64_t(gridDim.x) * kThreads) {
-        const float gi = g[i];
-        const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
-        const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+        float pi = p[i], mi = m[i], vi = v[i];
+        adam_update(pi, mi, vi, g[i], a);
+        p[i] = pi;
         m[i] = mi;
         v[i] = vi;
-        p[i] -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    }
+}
+
+// The same step on the parameter ranges of r (the parameters whose update did not run in
+// a product's epilogue): element e of the concatenated ranges is parameter
+// off[k] + e - end[k - 1] for the first k with e < end[k].
+__global__ __launch_bounds__(kThreads) void adam_ranges_kernel(float *__restrict__ p, const float *__restrict__ g,
+                                                               float *__restrict__ m, float *__restrict__ v,
+                                                               AdamRanges r, AdamArgs a) {
+    const int64_t total = r.end[r.n - 1];
+    for (int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x; e < total; e += int64_t(gridDim.x) * kThreads) {
+        int k = 0;
+        while (e >= r.end[k]) ++k;
+        const int64_t i = r.off[k] + (e - (k ? r.end[k - 1] : 0));
+        float pi = p[i], mi = m[i], vi = v[i];
+        adam_update(pi, mi, vi, g[i], a);
+        p[i] = pi;
+        m[i] = mi;
+        v[i] = vi;
     }
 }
 
@@ -562,6 +623,10 @@ int gemm_splits(int M, int N, int K, int n_cu, int64_t part_cap, bool vec, int *
 
 void launch_gemm(bool ta, bool tb, bool vec, GemmArgs g, int splits, hipStream_t s) {
     const dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM, splits);
+    if (vec && g.epi == EPI_ADAM) {   // the weight gradient h^T D (TA, not TB), one K range
+        hipLaunchKernelGGL((gemm_f32_vec_kernel<true, false, true>), grid, dim3(kThreads), 0, s, g);
+        return;
+    }
     if (vec) {
         if (ta && tb) hipLaunchKernelGGL((gemm_f32_vec_kernel<true, true>), grid, dim3(kThreads), 0, s, g);
         else if (ta) hipLaunchKernelGGL((gemm_f32_vec_kernel<true, false>), grid, dim3(kThreads), 0, s, g);
@@ -620,6 +685,13 @@ void launch_colsum(const float *D, int64_t ldd, int M, int N, float *out, hipStr
 
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, const AdamArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, p, g, m, v, n, a);
+}
+
+void launch_adam_ranges(float *p, const float *g, float *m, float *v, const AdamRanges &r, const AdamArgs &a,
+                        hipStream_t s) {
+    if (r.n < 1 || r.end[r.n - 1] < 1) return;
+    hipLaunchKernelGGL(adam_ranges_kernel, dim3(grid_for(r.end[r.n - 1], 4096)), dim3(kThreads), 0, s, p, g, m, v,
+                       r, a);
 }
 
 void launch_gather(const float *src, int64_t lds, const int *rows, int nrows, int ncols, float *dst,

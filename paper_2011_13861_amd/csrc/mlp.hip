@@ -109,6 +109,29 @@ void gemm(kl_mlp *M, bool ta, bool tb, const float *A, int64_t lda, const float 
     launch_gemm(ta, tb, vec, g, splits, s);
 }
 
+// Whether the weight gradient h^T D (h: B x fi, D: B x fo) runs in the float4 form in one
+// K range, so that the Adam step of its parameters can run in the product's epilogue.
+bool adam_fusable(const kl_mlp *M, const float *h, const float *D, int fi, int fo, int B) {
+    GemmArgs g;
+    g.A = h; g.lda = fi; g.B = D; g.ldb = fo;
+    g.M = fi; g.N = fo; g.K = B;
+    if (!gemm_vec_ok(true, false, g)) return false;
+    int kchunk = 0;
+    return gemm_splits(fi, fo, B, M->n_cu, M->part_cap, true, &kchunk) == 1;
+}
+
+// W (fi x fo) -= Adam step of the gradient h^T D, moments at mw / vw (adam_fusable holds).
+void gemm_adam(kl_mlp *M, const float *h, const float *D, float *W, float *mw, float *vw, int fi, int fo, int B,
+               const AdamArgs &a, hipStream_t s) {
+    GemmArgs g;
+    g.A = h; g.lda = fi; g.B = D; g.ldb = fo; g.C = W; g.ldc = fo;
+    g.M = fi; g.N = fo; g.K = B;
+    g.epi = EPI_ADAM; g.am = mw; g.av = vw; g.adam = a;
+    g.part = M->part;
+    gemm_splits(fi, fo, B, M->n_cu, M->part_cap, true, &g.kchunk);
+    launch_gemm(true, false, true, g, 1, s);
+}
+
 // Forward pass of B rows of x (B x sizes[0]); the output goes to `out` (B x sizes[L]).
 void forward(kl_mlp *M, int B, const float *x, float *out, hipStream_t s) {
     const float *h = x;
@@ -123,19 +146,29 @@ void forward(kl_mlp *M, int B, const float *x, float *out, hipStream_t s) {
 }
 
 // Backpropagation from the output delta in M->D0 (B x sizes[L]); gradients into M->g.
-void backward(kl_mlp *M, int B, const float *x, hipStream_t s) {
+// With `fuse` set (training), every weight block whose gradient product adam_fusable
+// accepts takes its Adam step in that product's epilogue (its gradient is not stored), and
+// the ranges of all other parameters are added to *rest for one Adam launch afterwards.
+// The delta through W_l is formed before W_l's product, which may update W_l.
+void backward(kl_mlp *M, int B, const float *x, hipStream_t s, const AdamArgs *fuse = nullptr,
+              AdamRanges *rest = nullptr) {
     float *D = M->D0, *Dn = M->D1;
     for (int l = M->L - 1; l >= 0; --l) {
         const int fi = M->sizes[l], fo = M->sizes[l + 1];
         const float *h = l == 0 ? x : M->H[l];
-        // dW_l = h_l^T D,  db_l = column sums of D
-        gemm(M, true, false, h, fi, D, fo, M->g + M->offW[l], fo, fi, fo, B, EPI_NONE, nullptr, nullptr, 0, s);
-        launch_colsum(D, fo, B, fo, M->g + M->offb[l], s);
-        if (l > 0) {
-            // delta of layer l: (D W_l^T) * (1 - h_l^2)
+        // delta of layer l: (D W_l^T) * (1 - h_l^2)
+        if (l > 0)
             gemm(M, false, true, D, fo, M->p + M->offW[l], fo, Dn, fi, B, fi, fo, EPI_DTANH, nullptr, h, fi, s);
-            std::swap(D, Dn);
+        // dW_l = h_l^T D,  db_l = column sums of D
+        if (fuse && adam_fusable(M, h, D, fi, fo, B)) {
+            gemm_adam(M, h, D, M->p + M->offW[l], M->m + M->offW[l], M->v + M->offW[l], fi, fo, B, *fuse, s);
+        } else {
+            gemm(M, true, false, h, fi, D, fo, M->g + M->offW[l], fo, fi, fo, B, EPI_NONE, nullptr, nullptr, 0, s);
+            if (fuse) rest->add(M->offW[l], int64_t(fi) * fo);
         }
+        launch_colsum(D, fo, B, fo, M->g + M->offb[l], s);
+        if (fuse) rest->add(M->offb[l], fo);
+        if (l > 0) std::swap(D, Dn);
     }
 }
 
@@ -182,6 +215,16 @@ kl_status check_group(const kl_mlp *M, int group, const char *fn) {
         return KL_EINVAL;
     }
     return KL_OK;
+}
+
+// Arguments of the next Adam step (advances the step count t).
+AdamArgs next_adam(kl_mlp *M, float lr, float beta1, float beta2, float eps) {
+    M->adam_t += 1;
+    AdamArgs a;
+    a.lr = lr; a.b1 = beta1; a.b2 = beta2; a.eps = eps;
+    a.c1 = float(1.0 - std::pow(double(beta1), double(M->adam_t)));
+    a.c2 = float(1.0 - std::pow(double(beta2), double(M->adam_t)));
+    return a;
 }
 
 }  // namespace
@@ -314,11 +357,7 @@ kl_status kl_mlp_adam(kl_mlp *M, float lr, float beta1, float beta2, float eps, 
         set_error("kl_mlp_adam: bad hyper-parameters");
         return KL_EINVAL;
     }
-    M->adam_t += 1;
-    AdamArgs a;
-    a.lr = lr; a.b1 = beta1; a.b2 = beta2; a.eps = eps;
-    a.c1 = float(1.0 - std::pow(double(beta1), double(M->adam_t)));
-    a.c2 = float(1.0 - std::pow(double(beta2), double(M->adam_t)));
+    const AdamArgs a = next_adam(M, lr, beta1, beta2, eps);
     launch_adam(M->p, M->g, M->m, M->v, M->n_params, a, static_cast<hipStream_t>(stream));
     return hipc(hipGetLastError(), "kernel launch");
 }
@@ -372,8 +411,13 @@ kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int
             if (sub)
                 launch_subspace(M->Y, n_out, t, n_out, rows, nb, n_out, gsz, M->sub_w, M->D0, n_out,
                                 M->loss_part + b0 * ng, M->sub_buf, s);
-            backward(M, nb, M->xb, s);
-            if ((st = kl_mlp_adam(M, lr, 0.9f, 0.999f, 1e-8f, s)) != KL_OK) return st;
+            // the Adam step: in the epilogues of the weight products that allow it, then
+            // one launch over the remaining parameters (the same bits as backward + kl_mlp_adam)
+            const AdamArgs a = next_adam(M, lr, 0.9f, 0.999f, 1e-8f);
+            AdamRanges rest;
+            backward(M, nb, M->xb, s, &a, &rest);
+            launch_adam_ranges(M->p, M->g, M->m, M->v, rest, a, s);
+            if ((st = hipc(hipGetLastError(), "kernel launch")) != KL_OK) return st;
         }
         if ((st = hipc(hipMemcpyAsync(lp.data(), M->loss_part, lp.size() * sizeof(double), hipMemcpyDeviceToHost, s),
                        "copy loss")) != KL_OK)

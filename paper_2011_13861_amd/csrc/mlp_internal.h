@@ -9,12 +9,21 @@
 namespace kl {
 namespace mlp {
 
-enum Epilogue { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_TANH = 2, EPI_DTANH = 3 };
+enum Epilogue { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_TANH = 2, EPI_DTANH = 3, EPI_ADAM = 4 };
+
+// Adam step with bias correction c1 = 1 - b1^t, c2 = 1 - b2^t.
+struct AdamArgs {
+    float lr, b1, b2, eps, c1, c2;
+};
 
 // C = op(A) op(B) with an epilogue; logical A is M x K, logical B is K x N:
 //   A(i, k) = TA ? A[k lda + i] : A[i lda + k],  B(k, j) = TB ? B[j ldb + k] : B[k ldb + j].
 // Epilogues: EPI_BIAS  C = AB + bias[j];  EPI_BIAS_TANH  C = tanh(AB + bias[j]);
 // EPI_DTANH  C = AB * (1 - aux[i][j]^2).
+// EPI_ADAM (float4 form with one K range only, see adam_fusable in the network code): AB
+// is the gradient of the parameters at C, whose Adam moments sit at am and av with the
+// same layout (leading dimension ldc); the three are updated in place and no gradient is
+// stored.
 struct GemmArgs {
     const float *A = nullptr;
     int64_t lda = 0;
@@ -29,10 +38,22 @@ struct GemmArgs {
     int64_t ldaux = 0;
     int epi = EPI_NONE;
     float *part = nullptr;          // splits x M x N partials when split over K
+    float *am = nullptr, *av = nullptr;   // Adam moments (EPI_ADAM)
+    AdamArgs adam{};
 };
 
-struct AdamArgs {
-    float lr, b1, b2, eps, c1, c2;
+// Parameter ranges [off[r], off[r] + len) of one Adam launch, given as off[] and the
+// running ends end[r] = len_0 + ... + len_r.
+constexpr int kAdamRanges = 16;
+struct AdamRanges {
+    int n = 0;
+    int64_t off[kAdamRanges] = {};
+    int64_t end[kAdamRanges] = {};
+    void add(int64_t o, int64_t len) {
+        off[n] = o;
+        end[n] = (n ? end[n - 1] : 0) + len;
+        ++n;
+    }
 };
 
 // Whether the float4 form of the product applies: A and B 16-byte aligned, lda and ldb
@@ -58,6 +79,8 @@ void launch_subspace(const float *y, int64_t ldy, const float *t, int64_t ldt, c
                      double *scratch, hipStream_t s);
 void launch_colsum(const float *D, int64_t ldd, int M, int N, float *out, hipStream_t s);
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, const AdamArgs &a, hipStream_t s);
+void launch_adam_ranges(float *p, const float *g, float *m, float *v, const AdamRanges &r, const AdamArgs &a,
+                        hipStream_t s);
 void launch_gather(const float *src, int64_t lds, const int *rows, int nrows, int ncols, float *dst,
                    hipStream_t s);
 

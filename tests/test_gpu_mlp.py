@@ -95,6 +95,59 @@ def test_forward_and_gradients_match_oracle(sizes, B, group):
         assert _max_rel(dW, rW) <= 1e-4, (l, "W", _max_rel(dW, rW))
 
 
+def _epoch_perm(n, state):
+    """Minibatch order of one epoch of kl_mlp_train: a Fisher-Yates shuffle whose draws are
+    splitmix64 of the running state (the published generator: add 0x9E3779B97F4A7C15, then
+    two xor-shift-multiply rounds and a final xor-shift)."""
+    mask = (1 << 64) - 1
+    perm = list(range(n))
+    for i in range(n - 1, 0, -1):
+        state = (state + 0x9E3779B97F4A7C15) & mask
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        z ^= z >> 31
+        j = z % (i + 1)
+        perm[i], perm[j] = perm[j], perm[i]
+    return perm, state
+
+
+# warm-start network (W2, W3 updated in their gradient products' epilogues, W1 and the
+# biases in the ranged step), all weights fused, none fused (split K ranges: batch 256),
+# none in the float4 form
+TRAIN_CASES = [([3, 256, 256, 41616], 64, 2601, 3.0), ([8, 64, 128, 4160], 64, 0, 0.0),
+               ([4, 36, 68, 1300], 256, 65, 0.5), ([5, 70, 33, 130], 67, 13, 0.0)]
+
+
+@pytest.mark.parametrize("sizes,B,group,sub", TRAIN_CASES,
+                         ids=["warmstart", "all_fused", "split_k", "scalar_form"])
+def test_training_step_matches_gradients_and_adam(sizes, B, group, sub):
+    """Two epochs of kl_mlp_train on one minibatch give the same bits as the same two steps
+    taken through kl_mlp_gradients and kl_mlp_adam on the rows in the training order: the
+    Adam step that runs in a weight product's epilogue (no stored gradient) equals the
+    separate one."""
+    flat, _, x, t = _setup(sizes, B, 21, group)
+    fused, ref = kl.MLP(sizes), kl.MLP(sizes)
+    fused.set_params(flat)
+    ref.set_params(flat)
+    if sub:
+        fused.set_subspace(sub)
+        ref.set_subspace(sub)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    seed, lr = 5, 1e-3
+    fused.train(xd, td, group=group, epochs=2, batch=B, lr0=lr, lr1=lr, seed=seed)
+    state = seed
+    for _ in range(2):
+        perm, state = _epoch_perm(B, state)
+        idx = torch.tensor(perm, device="cuda")
+        ref.gradients(xd[idx].contiguous(), td[idx].contiguous(), group=group)
+        ref.adam(lr)
+    a, b = fused.get_params(), ref.get_params()
+    assert not np.array_equal(a, flat)
+    diff = np.flatnonzero(a != b)
+    assert diff.size == 0, (diff.size, diff[:4], np.max(np.abs(a - b)))
+
+
 def test_adam_step_matches_oracle():
     """Three Adam steps on the GPU gradients, against the oracle's Adam fed the same
     gradients (the update rule alone, FP32 against FP64)."""
