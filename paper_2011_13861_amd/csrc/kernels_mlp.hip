@@ -35,14 +35,19 @@ __device__ __forceinline__ float epilogue(const GemmArgs &g, int row, int col, f
 
 // Adam update of one parameter from its gradient g (every Adam path of the network goes
 // through it, so fused and separate steps give the same bits: with contraction off, each
-// product and sum rounds on its own wherever the function is inlined).
+// product and sum rounds on its own wherever the function is inlined).  The bias
+// corrections are multiplications by their reciprocals, the square root and the final
+// reciprocal the hardware's (about 1 ulp each): a few vector instructions per parameter
+// instead of three correctly rounded divisions and a square root, which matters where the
+// update runs in a matrix product's epilogue.
 __device__ __forceinline__ void adam_update(float &p, float &m, float &v, float g, const AdamArgs &a) {
 #pragma clang fp contract(off)
     const float mi = a.b1 * m + (1.0f - a.b1) * g;
     const float vi = a.b2 * v + (1.0f - a.b2) * g * g;
     m = mi;
     v = vi;
-    p -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    const float den = __builtin_amdgcn_sqrtf(vi * a.ic2) + a.eps;
+    p -= a.lr * (mi * a.ic1) * __builtin_amdgcn_rcpf(den);
 }
 
 // C (M x N) = op(A) (M x K) * op(B) (K x N), one 64 x 64 tile per workgroup, four waves

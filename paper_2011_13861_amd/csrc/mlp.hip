@@ -222,8 +222,8 @@ AdamArgs next_adam(kl_mlp *M, float lr, float beta1, float beta2, float eps) {
     M->adam_t += 1;
     AdamArgs a;
     a.lr = lr; a.b1 = beta1; a.b2 = beta2; a.eps = eps;
-    a.c1 = float(1.0 - std::pow(double(beta1), double(M->adam_t)));
-    a.c2 = float(1.0 - std::pow(double(beta2), double(M->adam_t)));
+    a.ic1 = float(1.0 / (1.0 - std::pow(double(beta1), double(M->adam_t))));
+    a.ic2 = float(1.0 / (1.0 - std::pow(double(beta2), double(M->adam_t))));
     return a;
 }
 

@@ -11,9 +11,10 @@ namespace mlp {
 
 enum Epilogue { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_TANH = 2, EPI_DTANH = 3, EPI_ADAM = 4 };
 
-// Adam step with bias correction c1 = 1 - b1^t, c2 = 1 - b2^t.
+// Adam step with bias correction c1 = 1 - b1^t, c2 = 1 - b2^t, applied through their
+// reciprocals ic1 = 1 / c1, ic2 = 1 / c2 (rounded from FP64 on the host).
 struct AdamArgs {
-    float lr, b1, b2, eps, c1, c2;
+    float lr, b1, b2, eps, ic1, ic2;
 };
 
 // C = op(A) op(B) with an epilogue; logical A is M x K, logical B is K x N:
