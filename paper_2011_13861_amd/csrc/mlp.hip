@@ -104,18 +104,24 @@ void gemm(kl_mlp *M, bool ta, bool tb, const float *A, int64_t lda, const float 
     g.M = m; g.N = n; g.K = k;
     g.epi = epi; g.bias = bias; g.aux = aux; g.ldaux = ldaux;
     g.part = M->part;
+    if (gemm_direct_ok(g)) {
+        launch_gemm_direct(ta, tb, g, s);
+        return;
+    }
     const bool vec = gemm_vec_ok(ta, tb, g);
     const int splits = gemm_splits(m, n, k, M->n_cu, M->part_cap, vec, &g.kchunk);
     launch_gemm(ta, tb, vec, g, splits, s);
 }
 
 // Whether the weight gradient h^T D (h: B x fi, D: B x fo) runs in the float4 form in one
-// K range, so that the Adam step of its parameters can run in the product's epilogue.
+// K range, so that the Adam step of its parameters can run in the product's epilogue (a
+// product that gemm() sends to the one-thread-per-output kernel is not fused, so that the
+// gradient is the same sum either way).
 bool adam_fusable(const kl_mlp *M, const float *h, const float *D, int fi, int fo, int B) {
     GemmArgs g;
     g.A = h; g.lda = fi; g.B = D; g.ldb = fo;
     g.M = fi; g.N = fo; g.K = B;
-    if (!gemm_vec_ok(true, false, g)) return false;
+    if (gemm_direct_ok(g) || !gemm_vec_ok(true, false, g)) return false;
     int kchunk = 0;
     return gemm_splits(fi, fo, B, M->n_cu, M->part_cap, true, &kchunk) == 1;
 }

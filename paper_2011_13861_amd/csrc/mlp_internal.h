@@ -61,6 +61,12 @@ struct AdamRanges {
 // multiples of 4, and the contiguous extent of each operand (K or M for A, N or K for B)
 // a multiple of 4.
 bool gemm_vec_ok(bool ta, bool tb, const GemmArgs &g);
+// Whether a product goes to the one-thread-per-output kernel instead of matrix tiles: fan-in
+// K <= kDirectK and at most kDirectOut outputs (never for EPI_ADAM).
+constexpr int kDirectK = 8;
+constexpr int64_t kDirectOut = 65536;
+bool gemm_direct_ok(const GemmArgs &g);
+void launch_gemm_direct(bool ta, bool tb, const GemmArgs &g, hipStream_t s);
 // Number of K splits for a launch (partials limited to part_cap floats); *kchunk
 // receives the K range of one split (a multiple of the form's K chunk: 64 for the float4
 // form, 32 otherwise).

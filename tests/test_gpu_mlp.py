@@ -113,7 +113,8 @@ def _epoch_perm(n, state):
 
 
 # warm-start network (W2, W3 updated in their gradient products' epilogues, W1 and the
-# biases in the ranged step), all weights fused, none fused (split K ranges: batch 256),
+# biases in the ranged step; the first layer's forward product, fan-in 3, in the
+# one-thread-per-output kernel), all weights fused, none fused (split K ranges: batch 256),
 # none in the float4 form
 TRAIN_CASES = [([3, 256, 256, 41616], 64, 2601, 3.0), ([8, 64, 128, 4160], 64, 0, 0.0),
                ([4, 36, 68, 1300], 256, 65, 0.5), ([5, 70, 33, 130], 67, 13, 0.0)]
