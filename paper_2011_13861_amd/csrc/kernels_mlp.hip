@@ -1,6 +1,8 @@
-// Kernels of the warm-start network: FP32 GEMM on the matrix cores with fused
-// bias / tanh / tanh-derivative epilogues, the sign-invariant loss, column sums for the
-// bias gradients, Adam, and a row gather for minibatches.
+// Kernels of the warm-start network: FP32 GEMM on the matrix cores (a float4 form for
+// aligned operands, a scalar-load form otherwise, and one thread per output for products
+// of a few inputs) with fused bias / tanh / tanh-derivative / Adam epilogues, the
+// sign-invariant loss and its subspace term, column sums for the bias gradients, Adam on
+// the whole parameter vector or on parameter ranges, and a row gather for minibatches.
 //
 // The network maps covariance parameters to a block of leading eigenvector coefficients
 // (an addition to the method: the paper starts its Lanczos iteration from a generic
