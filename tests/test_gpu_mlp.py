@@ -61,11 +61,13 @@ def _setup(sizes, B, seed, group):
 # of the product: "aligned_ragged" on ragged tiles and split K ranges, "aligned_odd_batch"
 # with 19 rows, "aligned_tiles" on exact 64-multiples, "warmstart_b64" at the training
 # minibatch of the warm-start network (every layer but the first in the float4 form).
+# "direct_forms": fan-ins of at most 8 (3 inputs, 5 rows, 8 outputs) take the one-thread-
+# per-output kernel in its plain, transposed-A and transposed-B forms.
 CASES = [([3, 16, 16, 10], 7, 0), ([3, 16, 16, 10], 7, 5), ([5, 70, 33, 130], 67, 13),
          ([3, 256, 256, 41616], 8, 2601), ([4, 36, 68, 1300], 20, 13), ([4, 36, 68, 1300], 19, 13),
-         ([8, 64, 128, 4160], 64, 0), ([3, 256, 256, 41616], 64, 2601)]
+         ([8, 64, 128, 4160], 64, 0), ([3, 256, 256, 41616], 64, 2601), ([3, 16, 8], 5, 0)]
 CASE_IDS = ["small_mse", "small_signed", "ragged", "warmstart_size", "aligned_ragged",
-            "aligned_odd_batch", "aligned_tiles", "warmstart_b64"]
+            "aligned_odd_batch", "aligned_tiles", "warmstart_b64", "direct_forms"]
 
 
 def _max_rel(a, b):
