@@ -359,51 +359,6 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int spli
     }
 }
 
-// Sign-invariant loss, one workgroup per (group, sample): with y_g and t_g the group's
-// output and target, s = +1 if <y_g, t_g> >= 0 else -1 (dot accumulated in FP64);
-// dy_g = (y_g - s t_g) * inv_b and loss_part = 0.5 ||y_g - s t_g||^2 (FP64).
-// signed_ == 0 keeps s = +1 (plain squared error).
-__global__ __launch_bounds__(kThreads) void loss_kernel(const float *__restrict__ y, int64_t ldy,
-                                                        const float *__restrict__ tgt, int64_t ldt,
-                                                        const int *__restrict__ rows, int group,
-                                                        int signed_, float inv_b, float *__restrict__ dy,
-                                                        int64_t lddy, double *__restrict__ loss_part) {
-    const int gi = blockIdx.x, s = blockIdx.y;
-    const float *yr = y + int64_t(s) * ldy + int64_t(gi) * group;
-    const int trow = rows ? rows[s] : s;
-    const float *tr = tgt + int64_t(trow) * ldt + int64_t(gi) * group;
-    __shared__ double red[kThreads];
-    __shared__ double sgn_sh;
-    double dot = 0.0;
-    if (signed_) {
-        for (int i = threadIdx.x; i < group; i += kThreads) dot += double(yr[i]) * double(tr[i]);
-        red[threadIdx.x] = dot;
-        __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) sgn_sh = red[0] >= 0.0 ? 1.0 : -1.0;
-        __syncthreads();
-    }
-    const float sg = signed_ ? float(sgn_sh) : 1.0f;
-    float *dr = dy + int64_t(s) * lddy + int64_t(gi) * group;
-    double l2 = 0.0;
-    for (int i = threadIdx.x; i < group; i += kThreads) {
-        const float e = yr[i] - sg * tr[i];
-        dr[i] = e * inv_b;
-        l2 += double(e) * double(e);
-    }
-    __syncthreads();
-    red[threadIdx.x] = l2;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) loss_part[int64_t(s) * gridDim.x + gi] = 0.5 * red[0];
-}
-
 // Sum of a double over the workgroup in a fixed order (lanes by butterfly within each
 // wave, then the waves in order); every thread gets the result.  `red` holds kThreads / 64.
 __device__ __forceinline__ double block_sum(double v, double *red) {
@@ -416,6 +371,71 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) t += red[w];
     return t;
+}
+
+// Sign-invariant loss, one workgroup per (group, sample): with y_g and t_g the group's
+// output and target, s = +1 if <y_g, t_g> >= 0 else -1 (dot accumulated in FP64);
+// dy_g = (y_g - s t_g) * inv_b and loss_part = 0.5 ||y_g - s t_g||^2 (FP64).
+// signed_ == 0 keeps s = +1 (plain squared error).
+// Groups of up to kLossRegs * kThreads elements are read once into registers (all loads
+// issued together, clamped into the group and masked where used); longer groups are read
+// twice.  Both sums use block_sum.
+constexpr int kLossRegs = 16;
+
+__global__ __launch_bounds__(kThreads) void loss_kernel(const float *__restrict__ y, int64_t ldy,
+                                                        const float *__restrict__ tgt, int64_t ldt,
+                                                        const int *__restrict__ rows, int group,
+                                                        int signed_, float inv_b, float *__restrict__ dy,
+                                                        int64_t lddy, double *__restrict__ loss_part) {
+    const int gi = blockIdx.x, s = blockIdx.y;
+    const float *yr = y + int64_t(s) * ldy + int64_t(gi) * group;
+    const int trow = rows ? rows[s] : s;
+    const float *tr = tgt + int64_t(trow) * ldt + int64_t(gi) * group;
+    float *dr = dy + int64_t(s) * lddy + int64_t(gi) * group;
+    __shared__ double red[kThreads / 64];
+    const int t0 = threadIdx.x;
+    const bool cached = group <= kLossRegs * kThreads;
+    float yv[kLossRegs], tv[kLossRegs];
+    if (cached) {
+#pragma unroll
+        for (int u = 0; u < kLossRegs; ++u) {
+            const int i = min(t0 + u * kThreads, group - 1);
+            yv[u] = yr[i];
+            tv[u] = tr[i];
+        }
+    }
+    float sg = 1.0f;
+    if (signed_) {
+        double dot = 0.0;
+        if (cached) {
+#pragma unroll
+            for (int u = 0; u < kLossRegs; ++u)
+                if (t0 + u * kThreads < group) dot += double(yv[u]) * double(tv[u]);
+        } else {
+            for (int i = t0; i < group; i += kThreads) dot += double(yr[i]) * double(tr[i]);
+        }
+        sg = block_sum(dot, red) >= 0.0 ? 1.0f : -1.0f;
+    }
+    double l2 = 0.0;
+    if (cached) {
+#pragma unroll
+        for (int u = 0; u < kLossRegs; ++u) {
+            const int i = t0 + u * kThreads;
+            if (i < group) {
+                const float e = yv[u] - sg * tv[u];
+                dr[i] = e * inv_b;
+                l2 += double(e) * double(e);
+            }
+        }
+    } else {
+        for (int i = t0; i < group; i += kThreads) {
+            const float e = yr[i] - sg * tr[i];
+            dr[i] = e * inv_b;
+            l2 += double(e) * double(e);
+        }
+    }
+    l2 = block_sum(l2, red);
+    if (t0 == 0) loss_part[int64_t(s) * gridDim.x + gi] = 0.5 * l2;
 }
 
 // Subspace term of the loss in three passes (after loss_kernel on the same stream).  With
