@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kThreads) void loss_kernel(const float *__restrict_
 //             targets), dy += w inv_b r_a and loss_part += 0.5 w ||r_a||^2.
 // Every output and target element is read once per pass.
 constexpr int kSubChunk = 128;    // group elements staged in LDS per step of the gram pass
-constexpr int kSubSlices = 16;    // at most this many gram workgroups per sample
+constexpr int kSubSlices = 32;    // at most this many gram workgroups per sample
 constexpr int kSubPairs = (kMaxSubGroups * (kMaxSubGroups + 1) + kThreads - 1) / kThreads;
 
 int sub_slices(int group) { return std::min(kSubSlices, (group + kSubChunk - 1) / kSubChunk); }
@@ -520,6 +520,8 @@ __global__ __launch_bounds__(kThreads) void subspace_coef_kernel(const double *_
     for (int q = threadIdx.x; q < nn; q += kThreads) {
         const int b = q % ng;
         double c = 0.0, n = 0.0;
+        // the loads of eight slices are issued together; the sums stay in slice order
+#pragma unroll 8
         for (int sl = 0; sl < ns; ++sl) {
             const double *p = part + (int64_t(s) * ns + sl) * P;
             c += p[q];
