@@ -116,20 +116,21 @@ def _epoch_perm(n, state):
 
 # warm-start network (W2, W3 updated in their gradient products' epilogues, W1 and the
 # biases in the ranged step; the first layer's forward product, fan-in 3, in the
-# one-thread-per-output kernel), all weights fused, none fused (split K ranges: batch 256),
-# none in the float4 form
-TRAIN_CASES = [([3, 256, 256, 41616], 64, 2601, 3.0), ([8, 64, 128, 4160], 64, 0, 0.0),
-               ([4, 36, 68, 1300], 256, 65, 0.5), ([5, 70, 33, 130], 67, 13, 0.0)]
+# one-thread-per-output kernel), the same with 72 samples (minibatches of 64 and 8 rows),
+# all weights fused, none fused (split K ranges: batch 256), none in the float4 form
+TRAIN_CASES = [([3, 256, 256, 41616], 64, 64, 2601, 3.0), ([3, 256, 256, 41616], 72, 64, 2601, 3.0),
+               ([8, 64, 128, 4160], 64, 64, 0, 0.0), ([4, 36, 68, 1300], 256, 256, 65, 0.5),
+               ([5, 70, 33, 130], 67, 67, 13, 0.0)]
 
 
-@pytest.mark.parametrize("sizes,B,group,sub", TRAIN_CASES,
-                         ids=["warmstart", "all_fused", "split_k", "scalar_form"])
-def test_training_step_matches_gradients_and_adam(sizes, B, group, sub):
-    """Two epochs of kl_mlp_train on one minibatch give the same bits as the same two steps
-    taken through kl_mlp_gradients and kl_mlp_adam on the rows in the training order: the
-    Adam step that runs in a weight product's epilogue (no stored gradient) equals the
-    separate one."""
-    flat, _, x, t = _setup(sizes, B, 21, group)
+@pytest.mark.parametrize("sizes,n,B,group,sub", TRAIN_CASES,
+                         ids=["warmstart", "warmstart_ragged_batch", "all_fused", "split_k", "scalar_form"])
+def test_training_step_matches_gradients_and_adam(sizes, n, B, group, sub):
+    """Two epochs of kl_mlp_train give the same bits as the same steps taken through
+    kl_mlp_gradients and kl_mlp_adam on the minibatches in the training order: the Adam
+    step that runs in a weight product's epilogue (no stored gradient) equals the separate
+    one."""
+    flat, _, x, t = _setup(sizes, n, 21, group)
     fused, ref = kl.MLP(sizes), kl.MLP(sizes)
     fused.set_params(flat)
     ref.set_params(flat)
@@ -141,10 +142,11 @@ def test_training_step_matches_gradients_and_adam(sizes, B, group, sub):
     fused.train(xd, td, group=group, epochs=2, batch=B, lr0=lr, lr1=lr, seed=seed)
     state = seed
     for _ in range(2):
-        perm, state = _epoch_perm(B, state)
-        idx = torch.tensor(perm, device="cuda")
-        ref.gradients(xd[idx].contiguous(), td[idx].contiguous(), group=group)
-        ref.adam(lr)
+        perm, state = _epoch_perm(n, state)
+        for b0 in range(0, n, B):
+            idx = torch.tensor(perm[b0:b0 + B], device="cuda")
+            ref.gradients(xd[idx].contiguous(), td[idx].contiguous(), group=group)
+            ref.adam(lr)
     a, b = fused.get_params(), ref.get_params()
     assert not np.array_equal(a, flat)
     diff = np.flatnonzero(a != b)
