@@ -62,12 +62,14 @@ def _setup(sizes, B, seed, group):
 # with 19 rows, "aligned_tiles" on exact 64-multiples, "warmstart_b64" at the training
 # minibatch of the warm-start network (every layer but the first in the float4 form).
 # "direct_forms": fan-ins of at most 8 (3 inputs, 5 rows, 8 outputs) take the one-thread-
-# per-output kernel in its plain, transposed-A and transposed-B forms.
+# per-output kernel in its plain, transposed-A and transposed-B forms.  "ragged_split": the
+# delta back through 1030 unaligned outputs takes the scalar-load form over split K ranges.
 CASES = [([3, 16, 16, 10], 7, 0), ([3, 16, 16, 10], 7, 5), ([5, 70, 33, 130], 67, 13),
          ([3, 256, 256, 41616], 8, 2601), ([4, 36, 68, 1300], 20, 13), ([4, 36, 68, 1300], 19, 13),
-         ([8, 64, 128, 4160], 64, 0), ([3, 256, 256, 41616], 64, 2601), ([3, 16, 8], 5, 0)]
+         ([8, 64, 128, 4160], 64, 0), ([3, 256, 256, 41616], 64, 2601), ([3, 16, 8], 5, 0),
+         ([5, 70, 33, 1030], 9, 0)]
 CASE_IDS = ["small_mse", "small_signed", "ragged", "warmstart_size", "aligned_ragged",
-            "aligned_odd_batch", "aligned_tiles", "warmstart_b64", "direct_forms"]
+            "aligned_odd_batch", "aligned_tiles", "warmstart_b64", "direct_forms", "ragged_split"]
 
 
 def _max_rel(a, b):
@@ -117,9 +119,9 @@ def _epoch_perm(n, state):
 # warm-start network (W2, W3 updated in their gradient products' epilogues, W1 and the
 # biases in the ranged step; the first layer's forward product, fan-in 3, in the
 # one-thread-per-output kernel), the same with 72 samples (minibatches of 64 and 8 rows),
-# all weights fused, none fused (split K ranges: batch 256), none in the float4 form
+# all weights fused, none fused (split K ranges: batch 512), none in the float4 form
 TRAIN_CASES = [([3, 256, 256, 41616], 64, 64, 2601, 3.0), ([3, 256, 256, 41616], 72, 64, 2601, 3.0),
-               ([8, 64, 128, 4160], 64, 64, 0, 0.0), ([4, 36, 68, 1300], 256, 256, 65, 0.5),
+               ([8, 64, 128, 4160], 64, 64, 0, 0.0), ([4, 36, 68, 1300], 512, 512, 65, 0.5),
                ([5, 70, 33, 130], 67, 67, 13, 0.0)]
 
 
