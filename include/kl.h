@@ -448,7 +448,9 @@ kl_status kl_mlp_forward(kl_mlp *M, int32_t batch, const float *x, float *y, voi
 kl_status kl_mlp_gradients(kl_mlp *M, int32_t batch, const float *x, const float *t, int32_t group,
                            double *loss, float *grads, void *stream);
 
-/* One Adam step (Kingma and Ba, with bias correction) with the last gradients. */
+/* One Adam step (Kingma and Ba, with bias correction) with the gradients of the last
+ * kl_mlp_gradients call.  The bias corrections are applied through their reciprocals and
+ * the square root and final reciprocal are the hardware's (about 1 ulp each). */
 kl_status kl_mlp_adam(kl_mlp *M, float lr, float beta1, float beta2, float eps, void *stream);
 
 /* Minibatch training on n samples x (n x sizes[0]) and targets t (n x sizes[L]), both
@@ -456,6 +458,10 @@ kl_status kl_mlp_adam(kl_mlp *M, float lr, float beta1, float beta2, float eps, 
  * smaller), loss as in kl_mlp_gradients, Adam (0.9, 0.999, 1e-8) with a learning rate
  * going geometrically from lr0 (first epoch) to lr1 (last).  epoch_loss (host, epochs
  * values, may be NULL) receives the mean per-sample loss of each epoch.  Synchronous.
+ * Each step gives the bits of kl_mlp_gradients + kl_mlp_adam on the same rows, but the
+ * Adam step of a weight block runs inside its gradient product where the product allows
+ * it, so afterwards the kept gradients are not those of the last batch: call
+ * kl_mlp_gradients before a separate kl_mlp_adam.
  * Errors: KL_EINVAL, KL_ENOMEM, KL_EHIP, KL_ENUMERIC (non-finite loss). */
 kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int32_t group, int32_t epochs,
                        int32_t batch, float lr0, float lr1, uint64_t seed, double *epoch_loss, void *stream);
