@@ -44,13 +44,18 @@ struct GemmArgs {
 };
 
 // Parameter ranges [off[r], off[r] + len) of one Adam launch, given as off[] and the
-// running ends end[r] = len_0 + ... + len_r.
-constexpr int kAdamRanges = 16;
+// running ends end[r] = len_0 + ... + len_r.  A range that starts where the previous one
+// ends extends it.  Capacity: two ranges (weights and biases) for each of at most 16 layers.
+constexpr int kAdamRanges = 32;
 struct AdamRanges {
     int n = 0;
     int64_t off[kAdamRanges] = {};
     int64_t end[kAdamRanges] = {};
     void add(int64_t o, int64_t len) {
+        if (n > 0 && off[n - 1] + (end[n - 1] - (n > 1 ? end[n - 2] : 0)) == o) {
+            end[n - 1] += len;
+            return;
+        }
         off[n] = o;
         end[n] = (n ? end[n - 1] : 0) + len;
         ++n;

@@ -119,14 +119,16 @@ def _epoch_perm(n, state):
 # warm-start network (W2, W3 updated in their gradient products' epilogues, W1 and the
 # biases in the ranged step; the first layer's forward product, fan-in 3, in the
 # one-thread-per-output kernel), the same with 72 samples (minibatches of 64 and 8 rows),
-# all weights fused, none fused (split K ranges: batch 512), none in the float4 form
+# all weights fused, none fused (split K ranges: batch 512), none in the float4 form, and 11
+# layers none of which is fused (11 merged parameter ranges in the ranged Adam launch)
 TRAIN_CASES = [([3, 256, 256, 41616], 64, 64, 2601, 3.0), ([3, 256, 256, 41616], 72, 64, 2601, 3.0),
                ([8, 64, 128, 4160], 64, 64, 0, 0.0), ([4, 36, 68, 1300], 512, 512, 65, 0.5),
-               ([5, 70, 33, 130], 67, 67, 13, 0.0)]
+               ([5, 70, 33, 130], 67, 67, 13, 0.0), ([5] + [9] * 10 + [7], 20, 20, 0, 0.0)]
 
 
 @pytest.mark.parametrize("sizes,n,B,group,sub", TRAIN_CASES,
-                         ids=["warmstart", "warmstart_ragged_batch", "all_fused", "split_k", "scalar_form"])
+                         ids=["warmstart", "warmstart_ragged_batch", "all_fused", "split_k", "scalar_form",
+                              "deep_unfused"])
 def test_training_step_matches_gradients_and_adam(sizes, n, B, group, sub):
     """Two epochs of kl_mlp_train give the same bits as the same steps taken through
     kl_mlp_gradients and kl_mlp_adam on the minibatches in the training order: the Adam
