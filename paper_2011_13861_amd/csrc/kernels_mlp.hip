@@ -197,10 +197,15 @@ __device__ __forceinline__ void store_tile(const GemmArgs &g, int rl, int col, c
 // updated values are stored in place of the tile.
 constexpr int kVK = 64, kVS = kVK + 4;
 
+// Column sums (g.colsum, TA and not TB): the workgroups of the first row tile add the 64
+// entries of each column of every staged B chunk, wave q taking the chunk's physical
+// positions 16 q .. 16 q + 15 of the column's LDS row, and the four quarter sums in wave
+// order, chunk after chunk.
 template <bool TA, bool TB, bool ADAM = false>
 __global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
     __shared__ float4 sA[kTM * kVS / 4];
     __shared__ float4 sB[kTN * kVS / 4];
+    __shared__ float cs[TA && !TB ? 4 : 1][64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int i0 = blockIdx.y * kTM, j0 = blockIdx.x * kTN;
     const int kb = blockIdx.z * g.kchunk;
@@ -274,11 +279,24 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
             vv[r] = g.av[off];
         }
     }
+    const bool do_cs = TA && !TB && g.colsum != nullptr && blockIdx.y == 0;   // uniform
+    float csum = 0.0f;
     for (int kc = kb; kc < ke; kc += kVK) {
         __syncthreads();
         store();
         __syncthreads();
         if (kc + kVK < ke) load(kc + kVK);
+        if constexpr (TA && !TB) {
+            if (do_cs) {
+                const float *row = reinterpret_cast<const float *>(sB) + (t & 63) * kVS + 16 * w;
+                float part = 0.0f;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) part += row[u];
+                cs[w][t & 63] = part;
+                __syncthreads();
+                if (t < 64) csum += ((cs[0][t] + cs[1][t]) + cs[2][t]) + cs[3][t];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
 #pragma unroll
@@ -289,6 +307,18 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_vec_kernel(GemmArgs g) {
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
             }
+        }
+    }
+    if (do_cs && t < 64 && j0 + t < g.N) {
+        const int j = j0 + t;
+        if (g.epi == EPI_ADAM) {
+            float pb = g.colsum[j], mb = g.bm[j], vb = g.bv[j];
+            adam_update(pb, mb, vb, csum, g.adam);
+            g.colsum[j] = pb;
+            g.bm[j] = mb;
+            g.bv[j] = vb;
+        } else {
+            g.colsum[j] = csum;
         }
     }
     if (col >= g.N) return;

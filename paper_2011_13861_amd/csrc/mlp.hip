@@ -126,13 +126,22 @@ bool adam_fusable(const kl_mlp *M, const float *h, const float *D, int fi, int f
     return gemm_splits(fi, fo, B, M->n_cu, M->part_cap, true, &kchunk) == 1;
 }
 
-// W (fi x fo) -= Adam step of the gradient h^T D, moments at mw / vw (adam_fusable holds).
-void gemm_adam(kl_mlp *M, const float *h, const float *D, float *W, float *mw, float *vw, int fi, int fo, int B,
-               const AdamArgs &a, hipStream_t s) {
+// Layer l's weight gradient h^T D and bias gradient (column sums of D) in one product
+// (adam_fusable holds): with `a`, the Adam step of W_l and b_l in its epilogue (no gradient
+// stored), otherwise both gradients into M->g.
+void gemm_dw(kl_mlp *M, int l, const float *h, const float *D, int fi, int fo, int B, const AdamArgs *a,
+             hipStream_t s) {
     GemmArgs g;
-    g.A = h; g.lda = fi; g.B = D; g.ldb = fo; g.C = W; g.ldc = fo;
+    g.A = h; g.lda = fi; g.B = D; g.ldb = fo; g.ldc = fo;
     g.M = fi; g.N = fo; g.K = B;
-    g.epi = EPI_ADAM; g.am = mw; g.av = vw; g.adam = a;
+    if (a) {
+        g.C = M->p + M->offW[l];
+        g.epi = EPI_ADAM; g.am = M->m + M->offW[l]; g.av = M->v + M->offW[l]; g.adam = *a;
+        g.colsum = M->p + M->offb[l]; g.bm = M->m + M->offb[l]; g.bv = M->v + M->offb[l];
+    } else {
+        g.C = M->g + M->offW[l];
+        g.colsum = M->g + M->offb[l];
+    }
     g.part = M->part;
     gemm_splits(fi, fo, B, M->n_cu, M->part_cap, true, &g.kchunk);
     launch_gemm(true, false, true, g, 1, s);
@@ -152,9 +161,10 @@ void forward(kl_mlp *M, int B, const float *x, float *out, hipStream_t s) {
 }
 
 // Backpropagation from the output delta in M->D0 (B x sizes[L]); gradients into M->g.
-// With `fuse` set (training), every weight block whose gradient product adam_fusable
-// accepts takes its Adam step in that product's epilogue (its gradient is not stored), and
-// the ranges of all other parameters are added to *rest for one Adam launch afterwards.
+// Where adam_fusable accepts a layer's weight-gradient product, that product also forms the
+// bias gradient, and with `fuse` set (training) it takes the Adam step of the layer's
+// weights and biases in its epilogue (no gradient stored); the ranges of all other
+// parameters are added to *rest for one Adam launch afterwards.
 // The delta through W_l is formed before W_l's product, which may update W_l.
 void backward(kl_mlp *M, int B, const float *x, hipStream_t s, const AdamArgs *fuse = nullptr,
               AdamRanges *rest = nullptr) {
@@ -165,15 +175,18 @@ void backward(kl_mlp *M, int B, const float *x, hipStream_t s, const AdamArgs *f
         // delta of layer l: (D W_l^T) * (1 - h_l^2)
         if (l > 0)
             gemm(M, false, true, D, fo, M->p + M->offW[l], fo, Dn, fi, B, fi, fo, EPI_DTANH, nullptr, h, fi, s);
-        // dW_l = h_l^T D,  db_l = column sums of D
-        if (fuse && adam_fusable(M, h, D, fi, fo, B)) {
-            gemm_adam(M, h, D, M->p + M->offW[l], M->m + M->offW[l], M->v + M->offW[l], fi, fo, B, *fuse, s);
+        // dW_l = h_l^T D,  db_l = column sums of D: one product where it runs in one K range
+        // of the float4 form (with or without the Adam step), else a product and column sums
+        if (adam_fusable(M, h, D, fi, fo, B)) {
+            gemm_dw(M, l, h, D, fi, fo, B, fuse, s);
         } else {
             gemm(M, true, false, h, fi, D, fo, M->g + M->offW[l], fo, fi, fo, B, EPI_NONE, nullptr, nullptr, 0, s);
-            if (fuse) rest->add(M->offW[l], int64_t(fi) * fo);
+            launch_colsum(D, fo, B, fo, M->g + M->offb[l], s);
+            if (fuse) {
+                rest->add(M->offW[l], int64_t(fi) * fo);
+                rest->add(M->offb[l], fo);
+            }
         }
-        launch_colsum(D, fo, B, fo, M->g + M->offb[l], s);
-        if (fuse) rest->add(M->offb[l], fo);
         if (l > 0) std::swap(D, Dn);
     }
 }

@@ -41,6 +41,10 @@ struct GemmArgs {
     float *part = nullptr;          // splits x M x N partials when split over K
     float *am = nullptr, *av = nullptr;   // Adam moments (EPI_ADAM)
     AdamArgs adam{};
+    // float4 form with TA, not TB and one K range only: the column sums of B (the bias
+    // gradient of a weight-gradient product) go to colsum[N], or with EPI_ADAM take the Adam
+    // step of the parameters at colsum (moments bm, bv)
+    float *colsum = nullptr, *bm = nullptr, *bv = nullptr;
 };
 
 // Parameter ranges [off[r], off[r] + len) of one Adam launch, given as off[] and the
