@@ -459,9 +459,9 @@ kl_status kl_mlp_adam(kl_mlp *M, float lr, float beta1, float beta2, float eps, 
  * going geometrically from lr0 (first epoch) to lr1 (last).  epoch_loss (host, epochs
  * values, may be NULL) receives the mean per-sample loss of each epoch.  Synchronous.
  * Each step gives the bits of kl_mlp_gradients + kl_mlp_adam on the same rows, but the
- * Adam step of a weight block runs inside its gradient product where the product allows
- * it, so afterwards the kept gradients are not those of the last batch: call
- * kl_mlp_gradients before a separate kl_mlp_adam.
+ * Adam step of a layer's weights and biases runs inside its weight-gradient product where
+ * the product allows it, so afterwards the kept gradients are not those of the last batch:
+ * call kl_mlp_gradients before a separate kl_mlp_adam.
  * Errors: KL_EINVAL, KL_ENOMEM, KL_EHIP, KL_ENUMERIC (non-finite loss). */
 kl_status kl_mlp_train(kl_mlp *M, int64_t n, const float *x, const float *t, int32_t group, int32_t epochs,
                        int32_t batch, float lr0, float lr1, uint64_t seed, double *epoch_loss, void *stream);
